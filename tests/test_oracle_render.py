@@ -1,0 +1,398 @@
+"""Pins of the CPU oracle's rasterizer half against closed forms, library
+routines and brute force (no GPU).  Each test names the passage it pins."""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+from scipy.special import sph_harm_y
+
+import oracle
+from paper_2605_06876_amd import synth
+
+
+def one_gaussian(mu, log_s, q=(1, 0, 0, 0), logit=0.0, dc=(0.0, 0.0, 0.0), deg=0, rest=None):
+    nk = (deg + 1) ** 2
+    sh = np.zeros((nk, 3, 1), np.float32)
+    sh[0, :, 0] = dc
+    if rest is not None:
+        sh[1:, :, 0] = rest
+    return synth.Scene(np.array(mu, np.float32).reshape(3, 1), np.array(log_s, np.float32).reshape(3, 1),
+                       np.array(q, np.float32).reshape(4, 1), np.array([logit], np.float32), sh, deg)
+
+
+def axis_camera(W=64, H=64, f=80.0, z=-4.0):
+    return synth.Camera(np.eye(3), (0, 0, -z), f, f, W / 2, H / 2, W, H)
+
+
+C0 = 1.0 / (2.0 * math.sqrt(math.pi))
+
+
+# ---- Sec. 3: covariance from rotation and scale; EWA projection ---------------
+
+def test_isotropic_on_axis_closed_form():
+    """Isotropic s at (0,0,z) with identity camera rotation:
+    Sigma_2D = (f s / z)^2 I + 0.3 I."""
+    s, z, f = 0.05, 4.0, 80.0
+    sc = one_gaussian((0, 0, 0), [math.log(s)] * 3)
+    cam = axis_camera(f=f, z=-z)
+    pr = oracle.project(sc, cam)
+    ls = float(np.float32(math.log(s)))
+    s32 = math.exp(ls)
+    want = (f * s32 / z) ** 2 + 0.3
+    np.testing.assert_allclose(pr.cov2d[0], [want, 0.0, want], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(pr.mean2d[0], [32.0, 32.0], rtol=0, atol=1e-12)
+
+
+def test_rotation_convention_against_scipy():
+    """Quaternion (w,x,y,z) -> R matches scipy's Rotation (scalar-last), seen
+    through the projected covariance of an on-axis Gaussian."""
+    rng = np.random.default_rng(3)
+    f, z = 90.0, 5.0
+    cam = axis_camera(f=f, z=-z)
+    for _ in range(20):
+        q = rng.normal(size=4).astype(np.float32)
+        ls = rng.normal(-3, 0.4, size=3).astype(np.float32)
+        sc = one_gaussian((0, 0, 0), ls, q)
+        pr = oracle.project(sc, cam)
+        qd = q.astype(np.float64)
+        R = Rotation.from_quat([qd[1], qd[2], qd[3], qd[0]]).as_matrix()
+        S = R @ np.diag(np.exp(2 * ls.astype(np.float64))) @ R.T
+        want = (f / z) ** 2 * S[:2, :2] + 0.3 * np.eye(2)
+        np.testing.assert_allclose(pr.cov2d[0], [want[0, 0], want[0, 1], want[1, 1]], rtol=1e-10)
+
+
+def test_projection_jacobian_matches_finite_differences():
+    """Off-axis small Gaussian: Sigma_2D - 0.3 I = P Sigma P^T with P the
+    numerical Jacobian of the pinhole map (world -> pixel)."""
+    rng = np.random.default_rng(4)
+    cam = synth.look_at((1.0, -0.5, -4.0), (0.1, 0.2, 0.0), 96, 80, 55.0)
+    Rw = cam.R.astype(np.float64)
+    tw = cam.t.astype(np.float64)
+
+    def pix(p):
+        t = Rw @ p + tw
+        return np.array([cam.fx * t[0] / t[2] + cam.cx, cam.fy * t[1] / t[2] + cam.cy])
+
+    for _ in range(10):
+        mu = rng.uniform(-0.5, 0.5, size=3).astype(np.float32)
+        q = rng.normal(size=4).astype(np.float32)
+        ls = rng.normal(-3.5, 0.3, size=3).astype(np.float32)
+        sc = one_gaussian(mu, ls, q)
+        pr = oracle.project(sc, cam)
+        m = mu.astype(np.float64)
+        h = 1e-6
+        P = np.stack([(pix(m + h * e) - pix(m - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+        qd = q.astype(np.float64)
+        R = Rotation.from_quat([qd[1], qd[2], qd[3], qd[0]]).as_matrix()
+        S = R @ np.diag(np.exp(2 * ls.astype(np.float64))) @ R.T
+        want = P @ S @ P.T + 0.3 * np.eye(2)
+        np.testing.assert_allclose(pr.cov2d[0], [want[0, 0], want[0, 1], want[1, 1]], rtol=1e-6)
+        np.testing.assert_allclose(pr.mean2d[0], pix(m), rtol=1e-12)
+
+
+def test_near_plane_and_opacity_culling():
+    cam = axis_camera(z=-4.0)
+    behind = one_gaussian((0, 0, -3.9), [-3] * 3)          # t_z = 0.1 <= 0.2
+    faint = one_gaussian((0, 0, 0), [-3] * 3, logit=-6.0)  # o = 0.0025 < 1/255
+    assert oracle.project(behind, cam).valid[0] == 0
+    assert oracle.project(faint, cam).valid[0] == 0
+    assert oracle.project(one_gaussian((0, 0, 0), [-3] * 3), cam).valid[0] == 1
+
+
+# ---- colour: real spherical harmonics ------------------------------------------
+
+def _real_sh_scipy(l, m, x, y, z):
+    theta = math.acos(max(-1.0, min(1.0, z)))
+    phi = math.atan2(y, x)
+    if m == 0:
+        return sph_harm_y(l, 0, theta, phi).real
+    if m > 0:
+        return math.sqrt(2.0) * sph_harm_y(l, m, theta, phi).real
+    return math.sqrt(2.0) * sph_harm_y(l, -m, theta, phi).imag
+
+
+def test_sh_basis_matches_scipy_real_harmonics():
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        v = rng.normal(size=3)
+        v /= np.linalg.norm(v)
+        Y = oracle.sh_basis(*v)
+        k = 0
+        for l in range(4):
+            for m in range(-l, l + 1):
+                assert abs(Y[k] - _real_sh_scipy(l, m, *v)) < 1e-12, (l, m)
+                k += 1
+
+
+def test_sh_basis_orthonormal_by_quadrature():
+    xg, wg = np.polynomial.legendre.leggauss(24)
+    nphi = 48
+    G = np.zeros((16, 16))
+    for ct, w in zip(xg, wg):
+        st = math.sqrt(1 - ct * ct)
+        for j in range(nphi):
+            ph = 2 * math.pi * j / nphi
+            Y = oracle.sh_basis(st * math.cos(ph), st * math.sin(ph), ct)
+            G += np.outer(Y, Y) * w * (2 * math.pi / nphi)
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_degree0_colour_closed_form():
+    dc = (0.3, -0.7, 1.2)
+    pr = oracle.project(one_gaussian((0, 0, 0), [-3] * 3, dc=dc), axis_camera())
+    want = np.maximum(0.0, C0 * np.float32(dc).astype(np.float64) + 0.5)
+    np.testing.assert_allclose(pr.rgb[0], want, rtol=1e-14)
+
+
+# ---- Eq. (rendering): compositing closed forms and invariants -------------------
+
+def test_single_isotropic_gaussian_centre_pixel_is_opacity_times_colour():
+    """A Gaussian centred on a pixel centre: alpha = o there, so with a black
+    background the pixel is o * c."""
+    f, z = 80.0, 4.0
+    cam = axis_camera(W=64, H=64, f=f, z=-z)
+    # mean at pixel (32, 32)'s centre: world x = (32.5 - cx) z / f
+    mx = (32.5 - 32.0) * z / f
+    for logit in (-1.0, 0.0, 2.0, 4.0):
+        sc = one_gaussian((mx, mx, 0.0), [-3.0] * 3, logit=logit, dc=(0.5, -0.2, 1.0))
+        pr = oracle.project(sc, cam)
+        r = oracle.render_pixels(pr, np.array([[32, 32]]))
+        o = 1.0 / (1.0 + math.exp(-float(np.float32(logit))))
+        a = min(o, 0.99)
+        np.testing.assert_allclose(r["color"][0], a * pr.rgb[0], rtol=1e-6)
+        assert r["dom"][0] == 0 and r["ncontrib"][0] == 1
+
+
+def test_two_layers_closed_form_and_order():
+    """Two Gaussians covering a pixel: C = a1 c1 + (1 - a1) a2 c2, front first,
+    regardless of their index order."""
+    cam = axis_camera(W=32, H=32, f=60.0, z=-4.0)
+    # pixel (16,16)'s centre is 0.5 px off the principal point: world x = 0.5 t_z / f
+    mf, mb = 0.5 * 3.0 / 60.0, 0.5 * 5.0 / 60.0
+    front = one_gaussian((mf, mf, -1.0), [-2.0] * 3, logit=0.3, dc=(1.0, 0.0, 0.0))
+    back = one_gaussian((mb, mb, 1.0), [-2.0] * 3, logit=0.8, dc=(0.0, 1.0, 0.0))
+    for pair in ((front, back), (back, front)):
+        sc = synth.Scene(np.concatenate([p.means for p in pair], 1), np.concatenate([p.log_scales for p in pair], 1),
+                         np.concatenate([p.quats for p in pair], 1), np.concatenate([p.opacity_logits for p in pair]),
+                         np.concatenate([p.sh for p in pair], 2), 0)
+        pr = oracle.project(sc, cam)
+        px = np.array([[16, 16]])
+        r = oracle.render_pixels(pr, px)
+        np.testing.assert_allclose(pr.mean2d, 16.5, atol=1e-6)
+        d = pr.mean2d - 16.5
+        a = [min(0.99, pr.opacity[i] * math.exp(-0.5 * (pr.conic[i, 0] * d[i, 0] ** 2 + pr.conic[i, 2] * d[i, 1] ** 2)
+                                                   - pr.conic[i, 1] * d[i, 0] * d[i, 1])) for i in range(2)]
+        # pixel centre (16.5,16.5) coincides with both means
+        fi = 0 if pair[0] is front else 1
+        bi = 1 - fi
+        want = a[fi] * pr.rgb[fi] + (1 - a[fi]) * a[bi] * pr.rgb[bi]
+        np.testing.assert_allclose(r["color"][0], want, rtol=1e-12)
+        assert r["dom"][0] == (fi if a[fi] >= (1 - a[fi]) * a[bi] else bi)
+        assert r["ncontrib"][0] == 2
+        assert abs(r["T"][0] - (1 - a[0]) * (1 - a[1])) < 1e-14
+
+
+def test_transmittance_and_weight_invariants_c1():
+    scene, cam, _ = synth.c1_inputs()
+    pr = oracle.project(scene, cam)
+    img, maps = oracle.render_image(pr)
+    T = maps["T"]
+    assert (T > 0).all() and (T <= 1).all()
+    assert (T >= 1e-4 * (1 - 0.99) - 1e-18).all()
+    # with a black background the colour is sum w c with sum w = 1 - T <= 1
+    assert (img >= 0).all()
+    maxc = pr.rgb[pr.valid.astype(bool)].max()
+    assert (img.max(axis=0) <= (1 - T) * maxc + 1e-12).all()
+    # transmittance non-increasing along each pixel's contributor list:
+    # removing the last contributor can only raise T
+    assert ((maps["ncontrib"] == 0) == (T == 1.0)).all()
+
+
+def test_image_symmetric_for_mirrored_input():
+    """Mirroring the scene through the camera's x = 0 plane (with quaternion
+    and colour symmetric) mirrors the image."""
+    rng = np.random.default_rng(7)
+    n = 30
+    mu = rng.uniform(-0.6, 0.6, size=(3, n))
+    mu[0] = np.abs(mu[0]) + 0.01
+    ls = rng.normal(-2.7, 0.3, size=(3, n))
+    q = np.zeros((4, n))
+    q[0] = 1
+    logit = rng.normal(0, 1, n)
+    dc = rng.uniform(-1, 1, size=(1, 3, n))
+    mu2 = mu.copy()
+    mu2[0] = -mu[0]
+    both = synth.Scene(np.concatenate([mu, mu2], 1), np.concatenate([ls, ls], 1), np.concatenate([q, q], 1),
+                       np.concatenate([logit, logit]), np.concatenate([dc, dc], 2), 0)
+    W = 64
+    cam = synth.Camera(np.eye(3), (0, 0, 4), 70.0, 70.0, W / 2, W / 2, W, W)
+    img, maps = oracle.render_image(oracle.project(both, cam))
+    ok = maps["flag"] == 0
+    ok = ok & ok[:, ::-1]
+    np.testing.assert_allclose(img[:, ok], img[:, :, ::-1][:, ok], atol=1e-9)
+
+
+# ---- compact box [A4]: brute force --------------------------------------------
+
+def test_box_contains_every_pixel_with_alpha_above_threshold():
+    scene, cam, _ = synth.c1_inputs(seed=11)
+    pr = oracle.project(scene, cam)
+    W, H = cam.width, cam.height
+    ys, xs = np.mgrid[0:H, 0:W]
+    px, py = xs + 0.5, ys + 0.5
+    valid = np.nonzero(pr.valid)[0]
+    for i in valid[:300]:
+        dx = pr.mean2d[i, 0] - px
+        dy = pr.mean2d[i, 1] - py
+        a, b, c = pr.conic[i]
+        al = pr.opacity[i] * np.exp(-0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy)
+        x0, y0, x1, y1 = pr.box[i]
+        outside = (xs < x0) | (xs > x1) | (ys < y0) | (ys > y1)
+        assert not (al[outside] >= 1.0 / 255.0 * (1 + 1e-9)).any()
+
+
+def test_box_halfwidth_is_ellipse_extent():
+    """The continuous half-widths sqrt(k Sxx), sqrt(k Syy) equal the extent of
+    the ellipse d^T conic d = k found by sampling its boundary."""
+    rng = np.random.default_rng(12)
+    cam = axis_camera(W=256, H=256, f=200.0)
+    for _ in range(10):
+        sc = one_gaussian(rng.uniform(-0.2, 0.2, 3), rng.normal(-3, 0.5, 3), rng.normal(size=4), rng.normal())
+        pr = oracle.project(sc, cam)
+        if not pr.valid[0]:
+            continue
+        k = 2 * math.log(255 * pr.opacity[0])
+        A, B, C = pr.cov2d[0]
+        L = np.linalg.cholesky(np.array([[A, B], [B, C]]))
+        th = np.linspace(0, 2 * np.pi, 200001)
+        pts = math.sqrt(k) * (L @ np.stack([np.cos(th), np.sin(th)]))
+        assert abs(pts[0].max() - math.sqrt(k * A)) < 1e-8 * math.sqrt(k * A) + 1e-9
+        assert abs(pts[1].max() - math.sqrt(k * C)) < 1e-8 * math.sqrt(k * C) + 1e-9
+        # box edges: pixel centres x+1/2 inside [m - h, m + h]
+        x0, y0, x1, y1 = pr.box[0]
+        hx = math.sqrt(k * A)
+        m = pr.mean2d[0, 0]
+        assert x0 + 0.5 >= m - hx and (x0 == 0 or x0 - 0.5 < m - hx)
+        assert x1 + 0.5 <= m + hx and (x1 == 255 or x1 + 1.5 > m + hx)
+
+
+# ---- tile binning: brute force -------------------------------------------------
+
+@pytest.mark.parametrize("tw,th", [(16, 16), (8, 8), (32, 8)])
+def test_binning_matches_independent_enumeration(tw, th):
+    scene, cam, _ = synth.c1_inputs(seed=13)
+    pr = oracle.project(scene, cam)
+    keys, vals, ranges = oracle.bin_tiles(pr, tw, th)
+    ntx = (cam.width + tw - 1) // tw
+    kk, vv = [], []
+    for i in range(pr.n):
+        if not pr.valid[i]:
+            continue
+        x0, y0, x1, y1 = pr.box[i]
+        for ty in range(y0 // th, y1 // th + 1):
+            for tx in range(x0 // tw, x1 // tw + 1):
+                kk.append((ty * ntx + tx) << 32 | int(pr.depth_key[i]))
+                vv.append(i)
+    kk = np.array(kk, np.uint64)
+    vv = np.array(vv, np.uint32)
+    o = np.argsort(kk, kind="stable")
+    np.testing.assert_array_equal(keys, kk[o])
+    np.testing.assert_array_equal(vals, vv[o])
+    tiles = keys >> np.uint64(32)
+    for t in range(ranges.shape[0]):
+        idx = np.nonzero(tiles == t)[0]
+        if idx.size == 0:
+            assert tuple(ranges[t]) == (0, 0)
+        else:
+            assert tuple(ranges[t]) == (idx[0], idx[-1] + 1)
+    # depth bits are the float32 of the view depth
+    np.testing.assert_array_equal(pr.depth_key[pr.valid == 1],
+                                  pr.tview[pr.valid == 1, 2].astype(np.float32).view(np.uint32))
+
+
+# ---- gradients: central finite differences in FP64 ------------------------------
+
+def _loss_and_grad(scene, cam, G):
+    pr = oracle.project(scene, cam)
+    pix = oracle.all_pixels(cam.width, cam.height)
+    r = oracle.render_pixels(pr, pix)
+    L = float((r["color"] * G).sum())
+    g2d = oracle.render_backward_pixels(pr, pix, G)
+    return L, oracle.project_backward(scene, cam, g2d), r
+
+
+def _fd_scene(seed, deg):
+    rng = np.random.default_rng(seed)
+    n = 6
+    mu = rng.uniform(-0.35, 0.35, size=(3, n))
+    ls = rng.normal(-2.3, 0.25, size=(3, n))
+    q = rng.normal(size=(4, n))
+    logit = rng.normal(0.0, 0.8, size=n)
+    nk = (deg + 1) ** 2
+    sh = rng.normal(0.0, 0.3, size=(nk, 3, n))
+    sh[0] = rng.uniform(-0.5, 1.2, size=(3, n))
+    return synth.Scene(mu, ls, q, logit, sh, deg)
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_analytic_gradients_match_central_fd(deg):
+    """L = <G, I(theta)> for a fixed random G; FP64 central differences on the
+    FP32-stored parameters (the oracle widens them to double).  A parameter
+    whose perturbation changes a contributor set or stop point is skipped."""
+    scene = _fd_scene(20 + deg, deg)
+    cam = synth.Camera(np.eye(3), (0, 0, 4), 48.0, 48.0, 16, 14, 32, 28, bg=(0.2, 0.1, 0.3))
+    G = np.random.default_rng(99).normal(size=(cam.width * cam.height, 3))
+    L0, grads, r0 = _loss_and_grad(scene, cam, G)
+    checked = skipped = 0
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        arr = getattr(scene, name)
+        flat = arr.reshape(-1)
+        gan = grads[name].reshape(-1)
+        for j in range(flat.size):
+            x = float(flat[j])
+            h0 = 2.0 ** (round(math.log2(max(1.0, abs(x)))) - 12)
+
+            def fd_at(h):
+                Ls, same = [], True
+                hp = float(np.float32(x + h)) - x   # the representable steps
+                hm = x - float(np.float32(x - h))
+                for sgn in (1, -1):
+                    pert = flat.copy()
+                    pert[j] = np.float32(x + sgn * h)
+                    d = {k: getattr(scene, k).copy() for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+                    d[name] = pert.reshape(arr.shape)
+                    sc2 = synth.Scene(d["means"], d["log_scales"], d["quats"], d["opacity_logits"], d["sh"], deg)
+                    L, _, r = _loss_and_grad(sc2, cam, G)
+                    same = same and np.array_equal(r["ncontrib"], r0["ncontrib"]) and np.array_equal(r["last"], r0["last"])
+                    Ls.append(L)
+                return (Ls[0] - Ls[1]) / (hp + hm), same
+
+            f1, s1 = fd_at(h0)
+            f2, s2 = fd_at(h0 / 2)
+            if not (s1 and s2):
+                skipped += 1
+                continue
+            fd = (4.0 * f2 - f1) / 3.0   # Richardson: O(h^4)
+            an = gan[j]
+            scale = max(1e-6, abs(an), abs(fd))
+            assert abs(fd - an) <= 1e-6 * scale + 1e-10, (name, j, fd, an)
+            checked += 1
+    assert checked > 0.8 * (checked + skipped), (checked, skipped)
+
+
+def test_gradient_closed_forms_at_single_gaussian_centre():
+    """At the centre pixel of one Gaussian: dC/dc = o, dC/do = c and the
+    2D-mean gradient vanishes."""
+    f, z = 80.0, 4.0
+    cam = axis_camera(W=64, H=64, f=f, z=-z)
+    mx = (32.5 - 32.0) * z / f
+    sc = one_gaussian((mx, mx, 0.0), [-3.0] * 3, logit=0.4, dc=(0.5, -0.2, 1.0))
+    pr = oracle.project(sc, cam)
+    for ch in range(3):
+        G = np.zeros((1, 3))
+        G[0, ch] = 1.0
+        g = oracle.render_backward_pixels(pr, np.array([[32, 32]]), G)
+        np.testing.assert_allclose(g["rgb"][0, ch], pr.opacity[0], rtol=1e-12)
+        np.testing.assert_allclose(g["opacity"][0], pr.rgb[0, ch], rtol=1e-12)
+        np.testing.assert_allclose(g["mean2d"][0], [0.0, 0.0], atol=1e-7)  # mean is 1e-9 px off (float32)
