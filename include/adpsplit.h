@@ -1,0 +1,236 @@
+/*
+ * adpsplit.h - C-ABI of the MI355X (gfx950) differentiable Gaussian rasterizer
+ * and the AdpSplit error-driven adaptive split (arxiv 2605.06876).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named in the structs and arguments below are DEVICE pointers
+ *    (HIP global memory) owned by the caller unless stated otherwise; camera
+ *    structs and parameter structs are passed by host pointer and copied.
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*, NULL = the null stream) unless stated otherwise.
+ *  - Gaussians are stored struct-of-arrays, FP32, contiguous, n rows:
+ *      means [3][n], log_scales [3][n] (s = exp), quats [4][n] (w,x,y,z, not
+ *      necessarily unit; normalised inside), opacity_logits [n]
+ *      (o = 1/(1+exp(-x))), sh [(d+1)^2][3][n] (real spherical harmonics,
+ *      degree d <= 3; the colour is max(0, sum_k Y_k(dir) sh_k + 1/2)).
+ *    (Sec. 3 defines mean, rotation, scale, opacity and SH colour.)
+ *  - Camera: world->camera rotation R (row-major) and translation t with
+ *    x_cam = R x_world + t; camera axes x right, y down, z forward, so the
+ *    rows of R are the camera's right, down and forward directions (App. A
+ *    uses them for unprojection).  Intrinsics fx, fy, cx, cy in pixels; the
+ *    centre of pixel (x, y) is (x + 1/2, y + 1/2).
+ *  - Images are planar FP32 [3][H][W]; per-pixel maps are [H][W].
+ *  - Errors: every call returns an as_status.  AS_ERR_ARG comes from host-side
+ *    checks made before anything is enqueued; AS_ERR_HIP wraps a failing HIP
+ *    runtime call (text via as_last_error()).  Device-side capacity overflows
+ *    are reported through counters the caller reads after synchronising, as
+ *    described per call.  No C++ exception crosses this boundary.
+ *  - One as_ctx per stream and thread; contexts are not thread-safe.
+ */
+#ifndef ADPSPLIT_H
+#define ADPSPLIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AS_OK = 0,
+    AS_ERR_ARG = 1,       /* invalid argument (null pointer, bad size, bad degree) */
+    AS_ERR_CAPACITY = 2,  /* a host-visible capacity is too small */
+    AS_ERR_HIP = 3,       /* HIP runtime error */
+    AS_ERR_STATE = 4      /* call out of order (e.g. backward without a render) */
+} as_status;
+
+typedef struct as_ctx as_ctx;
+typedef struct as_frame as_frame;
+
+typedef struct {
+    float R[9];          /* world -> camera rotation, row-major */
+    float t[3];          /* world -> camera translation */
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float bg[3];         /* background colour added with the final transmittance */
+} as_camera;
+
+typedef struct {
+    const float *means, *log_scales, *quats, *opacity_logits, *sh;
+    int64_t n;
+    int32_t sh_degree;
+} as_gaussians;
+
+typedef struct {
+    float *means, *log_scales, *quats, *opacity_logits, *sh;
+    int64_t n;           /* row stride of every array (gradients: n; split output: capacity) */
+    int32_t sh_degree;
+} as_gaussians_mut;
+
+/* AdpSplit hyper-parameters (Sec. 5 "Implementation": tau_l1 0.1, r_erode 2,
+ * m_min 5, L 3, N_max 19, gamma_d 2.0, gamma_c 0.15); eps is the t*
+ * stabiliser of Eq. (tstar), eta the shrink factor of Eq. (vanilla_split_scale). */
+typedef struct {
+    double tau_l1;
+    int32_t r_erode, m_min, L, n_max;
+    double gamma_d, gamma_c, eps, eta;
+} as_split_params;
+
+/* One retained error region (Sec. 4.1 statistics).  Integer moments are over
+ * integer pixel indices; the centroid is in the continuous pixel frame; cov is
+ * the pixel covariance plus 1/12 per axis (the unit pixel's own variance); e1
+ * has a canonical sign (e1x > 0, or e1x == 0 and e1y > 0). */
+typedef struct {
+    int32_t cand, view, label, area;   /* dominant candidate id, view id, min linear pixel index, pixels */
+    int32_t band, pad0;
+    int64_t sx, sy, sxx, sxy, syy;
+    double cx, cy;
+    double cov[3];                     /* xx, xy, yy */
+    double e1[2];
+    double sigma1, sigma2;
+    float rgb[3];                      /* target colour of the pixel holding the centroid */
+    float pad1;
+} as_region;                           /* 152 bytes */
+
+typedef struct {
+    as_region *records;   /* device, capacity rows */
+    int64_t capacity;
+    int64_t *count;       /* device counter; the caller zeroes it before the first view.
+                             After synchronising, count > capacity means records were dropped. */
+} as_region_buf;
+
+/* Device views into a frame's state, for inspection by tests and tools. */
+typedef struct {
+    int32_t width, height, tile_w, tile_h, tiles_x, tiles_y;
+    int64_t n_cap, key_cap;
+    uint32_t *n_keys;         /* [1] number of (tile, Gaussian) pairs of the last render */
+    uint64_t *keys;           /* [key_cap] sorted keys: tile << 32 | float bits of view depth */
+    uint32_t *vals;           /* [key_cap] Gaussian id of each sorted key */
+    uint32_t *ranges;         /* [tiles][2] start, end into keys/vals */
+    uint32_t *depth_key;      /* [n] float bits of view-space depth */
+    int16_t *box;             /* [n][4] inclusive pixel box x0, y0, x1, y1 (valid if ntiles > 0) */
+    uint32_t *ntiles;         /* [n] tiles touched (0 = culled) */
+    float *rec;               /* [n][12] blend record: mean hi (2), mean lo (2), conic (3), opacity, rgb (3), pad */
+    float *t_final;           /* [H][W] final transmittance */
+    uint32_t *last;           /* [H][W] index into vals of the last contributor (valid if n_contrib > 0) */
+    uint32_t *n_contrib;      /* [H][W] number of contributors */
+    int32_t *dom;             /* [H][W] dominant Gaussian id, -1 if none */
+    double *err;              /* [H][W] L1 error (written when the render gets a target) */
+    uint64_t *err_minmax;     /* [2] bit patterns of the error map's min and max */
+    float *grad2d;            /* [9][n] per-Gaussian 2D gradients of the last backward */
+} as_frame_view;
+
+/* ---- context and state ------------------------------------------------------ */
+
+/* Create a context bound to HIP device `device`. */
+as_status as_ctx_create(int device, as_ctx **out);
+void as_ctx_destroy(as_ctx *ctx);
+/* Text of the last error raised on this thread (static storage). */
+const char *as_last_error(void);
+const char *as_version(void);
+
+/* Allocate the per-view state of the rasterizer: n_cap Gaussians, a width x
+ * height image, and key_cap (tile, Gaussian) pairs (<= 2^32 - 1).  The frame
+ * owns its device memory; as_frame_destroy frees it.  When `auto_grow` is
+ * nonzero, as_render synchronises once after binning to read the pair count
+ * and grows the key buffers if needed; when zero, the render never
+ * synchronises, and a pair count above key_cap leaves *n_keys > key_cap with
+ * the pairs beyond capacity dropped (the caller checks and re-renders). */
+as_status as_frame_create(as_ctx *ctx, int64_t n_cap, int32_t width, int32_t height, int64_t key_cap,
+                          int32_t auto_grow, as_frame **out);
+void as_frame_destroy(as_frame *f);
+as_status as_frame_get_view(const as_frame *f, as_frame_view *out);
+
+/* ---- the four calls of the path --------------------------------------------- */
+
+/* Forward render of one view (Eq. (rendering), Sec. 3) plus the dominant
+ * Gaussian map D_v (Eq. (dominant-map), Sec. 4.1) and, when `gt` is not NULL,
+ * the per-pixel L1 error against gt and its min and max over the view (the
+ * inputs of Eq. (l1map)), fused into the same per-tile traversal.
+ *   g      : Gaussians (n <= frame n_cap, sh_degree 0..3)
+ *   cam    : host pointer; width/height must equal the frame's
+ *   gt     : NULL or [3][H][W] target
+ *   image  : out [3][H][W]
+ * State needed by the backward pass and the error statistics stays in the
+ * frame until the next render into it. */
+as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as_frame *frame, const float *gt,
+                    float *image, void *stream);
+
+/* Reverse pass of the last as_render into `frame` (the differentiable
+ * rasterizer of Sec. 3): recomputes the blend per tile backwards from the
+ * stored final transmittance and last-contributor index.
+ *   dL_dimage : [3][H][W]
+ *   grads     : out, overwritten; same layout and degree as g, stride g->n
+ *   g2d_norm  : NULL or [n]; += |dL/d(mean2d)| (pixel units) for each Gaussian
+ *               visible in this view (the ADC statistic of Sec. 3)
+ *   vis_count : NULL or [n]; += 1 for each visible Gaussian */
+as_status as_render_backward(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as_frame *frame,
+                             const float *dL_dimage, as_gaussians_mut *grads, float *g2d_norm, int32_t *vis_count,
+                             void *stream);
+
+/* Per-pixel L1 error e = sum_c |image_c - gt_c| in FP64 and its min and max
+ * over the view (the inputs of Eq. (l1map)), for images not produced by
+ * as_render with a target.  err: out [H][W]; err_minmax: out [2]. */
+as_status as_error_map(as_ctx *ctx, int32_t width, int32_t height, const float *image, const float *gt, double *err,
+                       uint64_t *err_minmax, void *stream);
+
+/* Error region partitioning of one sampled view (Sec. 4.1): normalised error
+ * E (Eq. (l1map)), metric map M = [E > tau_l1], attribution count
+ * attr_count[D(u)] += 1 for high-error pixels dominated by a candidate
+ * (counted before erosion), erosion with a (2 r_erode + 1)^2 square (pixels
+ * outside the image count as set), L uniform bands over (tau_l1, 1], regions
+ * as 8-connected components with equal (D, B) (Eq. (error-region)), area
+ * filter (Eq. (min_region_area)) and region statistics.  Regions are appended
+ * to `regions` in ascending label order.
+ *   err, err_minmax : from as_render (frame view) or as_error_map
+ *   dom             : [H][W] dominant map (-1 = none)
+ *   gt              : [3][H][W] target (colour at the centroid)
+ *   is_candidate    : [n] 0/1 split-candidate mask
+ *   attr_count      : [n] accumulated */
+as_status as_accumulate_error_stats(as_ctx *ctx, int32_t width, int32_t height, const double *err,
+                                    const uint64_t *err_minmax, const int32_t *dom, const float *gt, int32_t view_id,
+                                    int64_t n, const uint8_t *is_candidate, const as_split_params *params,
+                                    as_region_buf *regions, int32_t *attr_count, void *stream);
+
+/* The adaptive split of every candidate (Sec. 4.2, 4.3, App. A and Sec. 5
+ * "Implementation"): one child proposal per region (centre on the centroid ray
+ * at t* of Eq. (tstar); shape from the unprojected, clipped PCA axes; colour
+ * from the target), transitive merging under Eq. (merge_conditions) with the
+ * merged parameters of Eq. (merge_cov), a cap of N_max children by covariance
+ * extent, and the mode: VANILLA (0, no attributed pixel: the fixed N = 2 split
+ * of Eq. (vanilla_split_sample)), RESET (1, attributed pixels but no
+ * surviving region: no rows, parent kept), ADAPTIVE (2: N_i children plus a
+ * parent copy with opacity o / (N_i + 1)).
+ *   cand       : [n_cand] candidate ids, strictly ascending
+ *   regions    : the regions of all sampled views (any order)
+ *   views      : host array [n_views]; a region's view id indexes it
+ *   attr_count : [n]
+ *   noise      : [n_cand][2][3] standard normals for the VANILLA children
+ *   out        : rows = capacity (>= n + n_cand * max(2, n_max + 1) always suffices)
+ *   mode, count: out [n_cand]; offset: out [n_cand] exclusive scan of count
+ *   n_out      : out [1] device; the new set is the non-removed Gaussians in
+ *                order, then one block per candidate in ascending id order
+ *                (children by descending extent, then the parent copy).
+ * Returns AS_ERR_CAPACITY when out->n is below the bound above. */
+as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *cand, int64_t n_cand,
+                            const as_region_buf *regions, const as_camera *views, int32_t n_views,
+                            const int32_t *attr_count, const as_split_params *params, const float *noise,
+                            as_gaussians_mut *out, uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out,
+                            void *stream);
+
+/* ---- test hooks --------------------------------------------------------------- */
+
+/* Stable LSD radix sort of n (key, value) pairs on the low key_bits bits, in
+ * place (the sorter the binning uses).  keys [n], vals [n]. */
+as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, int32_t key_bits, void *stream);
+
+/* Element-wise FP64 sqrt(a), a / b, exp(b) and log(a) on the device, used to
+ * check that the decision arithmetic rounds like the host's.  out[4][n]. */
+as_status as_debug_fp64_ops(as_ctx *ctx, const double *a, const double *b, int64_t n, double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADPSPLIT_H */

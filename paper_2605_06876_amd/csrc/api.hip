@@ -1,0 +1,397 @@
+// Host side of the C-ABI declared in include/adpsplit.h: argument checks,
+// frame lifetime and the launch order of each call.  No kernels live here.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "internal.h"
+
+namespace {
+thread_local char g_err[1024] = "";
+
+bool bad(hipError_t e, const char *what) {
+    if (e == hipSuccess) return false;
+    as_set_error("%s: %s", what, hipGetErrorString(e));
+    return true;
+}
+
+as_status launch_status(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        as_set_error("%s: kernel launch failed: %s", what, hipGetErrorString(e));
+        return AS_ERR_HIP;
+    }
+    return AS_OK;
+}
+
+int tile_bits(int64_t tiles) {
+    int b = 0;
+    while ((int64_t(1) << b) < tiles) b++;
+    return b;
+}
+
+bool check_gauss(const as_gaussians *g, const char *what) {
+    if (!g) { as_set_error("%s: null Gaussians", what); return false; }
+    if (g->n < 0 || g->n > 0xFFFFFFFFll) { as_set_error("%s: n = %lld out of range", what, (long long)g->n); return false; }
+    if (g->sh_degree < 0 || g->sh_degree > 3) { as_set_error("%s: sh_degree %d not in 0..3", what, g->sh_degree); return false; }
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh)) {
+        as_set_error("%s: null parameter pointer", what);
+        return false;
+    }
+    return true;
+}
+
+bool check_mut(const as_gaussians_mut *g, int64_t rows, int32_t deg, const char *what) {
+    if (!g) { as_set_error("%s: null output", what); return false; }
+    if (g->n < rows) { as_set_error("%s: output stride %lld < %lld rows", what, (long long)g->n, (long long)rows); return false; }
+    if (g->sh_degree != deg) { as_set_error("%s: output sh_degree %d != %d", what, g->sh_degree, deg); return false; }
+    if (rows > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh)) {
+        as_set_error("%s: null output pointer", what);
+        return false;
+    }
+    return true;
+}
+
+GaussPtrs gptrs(const as_gaussians *g) {
+    GaussPtrs p;
+    p.means = g->means; p.log_scales = g->log_scales; p.quats = g->quats; p.opac = g->opacity_logits; p.sh = g->sh;
+    p.n = g->n; p.deg = g->sh_degree;
+    return p;
+}
+
+GradPtrs mptrs(const as_gaussians_mut *g) {
+    GradPtrs p;
+    p.means = g->means; p.log_scales = g->log_scales; p.quats = g->quats; p.opac = g->opacity_logits; p.sh = g->sh;
+    p.stride = g->n;
+    return p;
+}
+
+bool check_params(const as_split_params *p, const char *what) {
+    if (!p) { as_set_error("%s: null params", what); return false; }
+    if (!(p->tau_l1 >= 0.0 && p->tau_l1 < 1.0) || p->r_erode < 0 || p->r_erode > 64 || p->m_min < 1 || p->L < 1 ||
+        p->L > 255 || p->n_max < 0 || !(p->gamma_d >= 0.0) || !(p->gamma_c >= 0.0) || !(p->eps >= 0.0) || !(p->eta > 0.0)) {
+        as_set_error("%s: parameter out of range", what);
+        return false;
+    }
+    return true;
+}
+
+template <typename T>
+hipError_t dmalloc(T **p, size_t count) {
+    return hipMalloc((void **)p, count * sizeof(T) + 256);
+}
+
+void free_keys(as_frame *f) {
+    for (int k = 0; k < 2; k++) {
+        if (f->keys[k]) (void)hipFree(f->keys[k]);
+        if (f->vals[k]) (void)hipFree(f->vals[k]);
+        f->keys[k] = nullptr;
+        f->vals[k] = nullptr;
+    }
+}
+
+hipError_t alloc_keys(as_frame *f, int64_t key_cap) {
+    hipError_t e;
+    for (int k = 0; k < 2; k++) {
+        if ((e = dmalloc(&f->keys[k], key_cap)) != hipSuccess) return e;
+        if ((e = dmalloc(&f->vals[k], key_cap)) != hipSuccess) return e;
+    }
+    f->key_cap = key_cap;
+    return devbuf_ensure(f->sort_hist, sort_hist_bytes(key_cap));
+}
+}  // namespace
+
+void as_set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+hipError_t devbuf_ensure(DevBuf &b, size_t bytes) {
+    if (b.p && b.bytes >= bytes) return hipSuccess;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t nb = bytes < 256 ? 256 : bytes;
+    nb = (nb + 255) & ~(size_t)255;
+    const hipError_t e = hipMalloc(&b.p, nb);
+    if (e == hipSuccess) b.bytes = nb;
+    return e;
+}
+
+void devbuf_free(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+extern "C" {
+
+const char *as_last_error(void) { return g_err; }
+const char *as_version(void) { return "adpsplit 0.1.0 (gfx950)"; }
+
+as_status as_ctx_create(int device, as_ctx **out) {
+    if (!out) { as_set_error("as_ctx_create: null out"); return AS_ERR_ARG; }
+    *out = nullptr;
+    if (bad(hipSetDevice(device), "hipSetDevice")) return AS_ERR_HIP;
+    hipDeviceProp_t prop;
+    if (bad(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties")) return AS_ERR_HIP;
+    if (prop.warpSize != 64) {
+        as_set_error("device %d has wavefront size %d; the kernels are written for wave64", device, prop.warpSize);
+        return AS_ERR_ARG;
+    }
+    as_ctx *c = new (std::nothrow) as_ctx();
+    if (!c) { as_set_error("as_ctx_create: out of host memory"); return AS_ERR_HIP; }
+    c->device = device;
+    *out = c;
+    return AS_OK;
+}
+
+void as_ctx_destroy(as_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (auto &b : ctx->es) devbuf_free(b);
+    for (auto &b : ctx->sp) devbuf_free(b);
+    for (auto &b : ctx->dbg) devbuf_free(b);
+    delete ctx;
+}
+
+void as_frame_destroy(as_frame *f) {
+    if (!f) return;
+    (void)hipSetDevice(f->ctx->device);
+    void *ptrs[] = {f->rec, f->depth_key, f->box, f->ntiles, f->offsets, f->grad2d, f->ranges, f->n_keys,
+                    f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    free_keys(f);
+    devbuf_free(f->scan_tmp);
+    devbuf_free(f->sort_hist);
+    if (f->h_nkeys) (void)hipHostFree(f->h_nkeys);
+    delete f;
+}
+
+as_status as_frame_create(as_ctx *ctx, int64_t n_cap, int32_t width, int32_t height, int64_t key_cap,
+                          int32_t auto_grow, as_frame **out) {
+    if (!ctx || !out) { as_set_error("as_frame_create: null argument"); return AS_ERR_ARG; }
+    *out = nullptr;
+    if (n_cap < 1 || n_cap > 0xFFFFFFFFll || width < 1 || height < 1 || width > 32767 || height > 32767 ||
+        key_cap < 1 || key_cap > 0xFFFFFFFFll) {
+        as_set_error("as_frame_create: size out of range (n_cap %lld, %dx%d, key_cap %lld)", (long long)n_cap, width,
+                     height, (long long)key_cap);
+        return AS_ERR_ARG;
+    }
+    if (bad(hipSetDevice(ctx->device), "hipSetDevice")) return AS_ERR_HIP;
+    as_frame *f = new (std::nothrow) as_frame();
+    if (!f) { as_set_error("as_frame_create: out of host memory"); return AS_ERR_HIP; }
+    f->ctx = ctx;
+    f->n_cap = n_cap;
+    f->W = width;
+    f->H = height;
+    f->tiles_x = (width + AS_TILE_W - 1) / AS_TILE_W;
+    f->tiles_y = (height + AS_TILE_H - 1) / AS_TILE_H;
+    f->auto_grow = auto_grow;
+    const int64_t P = (int64_t)width * height, tiles = (int64_t)f->tiles_x * f->tiles_y;
+    hipError_t e = hipSuccess;
+    if ((e = dmalloc(&f->rec, n_cap)) != hipSuccess || (e = dmalloc(&f->depth_key, n_cap)) != hipSuccess ||
+        (e = dmalloc(&f->box, n_cap * 4)) != hipSuccess || (e = dmalloc(&f->ntiles, n_cap)) != hipSuccess ||
+        (e = dmalloc(&f->offsets, n_cap)) != hipSuccess || (e = dmalloc(&f->grad2d, n_cap * 9)) != hipSuccess ||
+        (e = dmalloc(&f->ranges, tiles * 2)) != hipSuccess || (e = dmalloc(&f->n_keys, 4)) != hipSuccess ||
+        (e = dmalloc(&f->t_final, P)) != hipSuccess || (e = dmalloc(&f->last, P)) != hipSuccess ||
+        (e = dmalloc(&f->n_contrib, P)) != hipSuccess || (e = dmalloc(&f->dom, P)) != hipSuccess ||
+        (e = dmalloc(&f->err, P)) != hipSuccess || (e = dmalloc(&f->err_minmax, 2)) != hipSuccess ||
+        (e = alloc_keys(f, key_cap)) != hipSuccess || (e = devbuf_ensure(f->scan_tmp, scan_tmp_bytes(n_cap))) != hipSuccess ||
+        (e = hipHostMalloc((void **)&f->h_nkeys, 64, hipHostMallocDefault)) != hipSuccess) {
+        as_set_error("as_frame_create: allocation failed: %s", hipGetErrorString(e));
+        as_frame_destroy(f);
+        return AS_ERR_HIP;
+    }
+    *out = f;
+    return AS_OK;
+}
+
+as_status as_frame_get_view(const as_frame *f, as_frame_view *v) {
+    if (!f || !v) { as_set_error("as_frame_get_view: null argument"); return AS_ERR_ARG; }
+    v->width = f->W; v->height = f->H; v->tile_w = AS_TILE_W; v->tile_h = AS_TILE_H;
+    v->tiles_x = f->tiles_x; v->tiles_y = f->tiles_y;
+    v->n_cap = f->n_cap; v->key_cap = f->key_cap;
+    v->n_keys = f->n_keys;
+    v->keys = f->keys[f->sorted_sel];
+    v->vals = f->vals[f->sorted_sel];
+    v->ranges = f->ranges;
+    v->depth_key = f->depth_key;
+    v->box = f->box;
+    v->ntiles = f->ntiles;
+    v->rec = reinterpret_cast<float *>(f->rec);
+    v->t_final = f->t_final; v->last = f->last; v->n_contrib = f->n_contrib; v->dom = f->dom;
+    v->err = f->err; v->err_minmax = f->err_minmax; v->grad2d = f->grad2d;
+    return AS_OK;
+}
+
+as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as_frame *f, const float *gt,
+                    float *image, void *stream) {
+    if (!ctx || !cam || !f || !image) { as_set_error("as_render: null argument"); return AS_ERR_ARG; }
+    if (!check_gauss(g, "as_render")) return AS_ERR_ARG;
+    if (g->n > f->n_cap) {
+        as_set_error("as_render: %lld Gaussians exceed the frame capacity %lld", (long long)g->n, (long long)f->n_cap);
+        return AS_ERR_CAPACITY;
+    }
+    if (cam->width != f->W || cam->height != f->H) {
+        as_set_error("as_render: camera %dx%d does not match the frame %dx%d", cam->width, cam->height, f->W, f->H);
+        return AS_ERR_ARG;
+    }
+    if (!(cam->fx > 0.f) || !(cam->fy > 0.f)) { as_set_error("as_render: focal lengths must be positive"); return AS_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    const GaussPtrs gp = gptrs(g);
+    const DevCam dc = to_devcam(*cam);
+    const int64_t n = g->n, tiles = (int64_t)f->tiles_x * f->tiles_y;
+    f->has_render = 0;
+    launch_project(gp, dc, f->tiles_x, f->rec, f->depth_key, f->box, f->ntiles, s);
+    scan_u32(f->ntiles, f->offsets, n, f->n_keys, f->scan_tmp.p, s);
+    int64_t n_hint = f->key_cap;
+    if (f->auto_grow) {
+        if (bad(hipMemcpyAsync(f->h_nkeys, f->n_keys, 4, hipMemcpyDeviceToHost, s), "as_render: pair count readback") ||
+            bad(hipStreamSynchronize(s), "as_render: synchronise"))
+            return AS_ERR_HIP;
+        const int64_t K = *f->h_nkeys;
+        if (K > f->key_cap) {
+            free_keys(f);
+            int64_t cap = K + K / 4 + 1024;
+            if (cap > 0xFFFFFFFFll) cap = 0xFFFFFFFFll;
+            if (bad(alloc_keys(f, cap), "as_render: growing the key buffers")) return AS_ERR_HIP;
+        }
+        n_hint = K;
+    }
+    launch_emit_keys(n, f->depth_key, f->box, f->ntiles, f->offsets, f->tiles_x, f->key_cap, f->keys[0], f->vals[0], s);
+    const int sel = radix_sort_pairs(f->keys, f->vals, f->n_keys, f->key_cap, n_hint, 32 + tile_bits(tiles),
+                                     f->sort_hist.p, s);
+    f->sorted_sel = sel;
+    launch_ranges(f->keys[sel], f->n_keys, f->key_cap, tiles, f->ranges, s);
+    if (gt) {
+        launch_fill_u64(f->err_minmax, 0x7ff0000000000000ull, 1, s);
+        launch_fill_u64(f->err_minmax + 1, 0ull, 1, s);
+    }
+    launch_blend_fwd(f, f->vals[sel], dc, gt, image, s);
+    const as_status st = launch_status("as_render");
+    if (st != AS_OK) return st;
+    f->has_render = 1;
+    f->n_last = n;
+    f->deg_last = g->sh_degree;
+    f->has_gt = gt != nullptr;
+    return AS_OK;
+}
+
+as_status as_render_backward(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as_frame *f,
+                             const float *dL_dimage, as_gaussians_mut *grads, float *g2d_norm, int32_t *vis_count,
+                             void *stream) {
+    if (!ctx || !cam || !f || !dL_dimage) { as_set_error("as_render_backward: null argument"); return AS_ERR_ARG; }
+    if (!check_gauss(g, "as_render_backward")) return AS_ERR_ARG;
+    if (!f->has_render || f->n_last != g->n || f->deg_last != g->sh_degree) {
+        as_set_error("as_render_backward: the frame holds no render of these Gaussians");
+        return AS_ERR_STATE;
+    }
+    if (cam->width != f->W || cam->height != f->H) { as_set_error("as_render_backward: camera/frame size mismatch"); return AS_ERR_ARG; }
+    if (!check_mut(grads, g->n, g->sh_degree, "as_render_backward")) return AS_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = g->n;
+    const DevCam dc = to_devcam(*cam);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9 * n, s);
+    launch_blend_bwd(f, f->vals[f->sorted_sel], dc, dL_dimage, f->grad2d, n, s);
+    launch_project_bwd(gptrs(g), dc, f->ntiles, f->grad2d, n, mptrs(grads), g2d_norm, vis_count, s);
+    return launch_status("as_render_backward");
+}
+
+as_status as_error_map(as_ctx *ctx, int32_t width, int32_t height, const float *image, const float *gt, double *err,
+                       uint64_t *err_minmax, void *stream) {
+    if (!ctx || !image || !gt || !err || !err_minmax || width < 1 || height < 1) {
+        as_set_error("as_error_map: bad argument");
+        return AS_ERR_ARG;
+    }
+    launch_error_map(width, height, image, gt, err, err_minmax, (hipStream_t)stream);
+    return launch_status("as_error_map");
+}
+
+as_status as_accumulate_error_stats(as_ctx *ctx, int32_t width, int32_t height, const double *err,
+                                    const uint64_t *err_minmax, const int32_t *dom, const float *gt, int32_t view_id,
+                                    int64_t n, const uint8_t *is_candidate, const as_split_params *params,
+                                    as_region_buf *regions, int32_t *attr_count, void *stream) {
+    if (!ctx || !err || !err_minmax || !dom || !gt || !is_candidate || !regions || !regions->records ||
+        !regions->count || !attr_count || width < 1 || height < 1 || n < 1 || view_id < 0) {
+        as_set_error("as_accumulate_error_stats: bad argument");
+        return AS_ERR_ARG;
+    }
+    if ((int64_t)width * height > 0x7FFFFFFFll) { as_set_error("as_accumulate_error_stats: image too large"); return AS_ERR_ARG; }
+    if (!check_params(params, "as_accumulate_error_stats")) return AS_ERR_ARG;
+    const as_status st = run_error_stats(ctx, width, height, err, err_minmax, dom, gt, view_id, n, is_candidate,
+                                         *params, *regions, attr_count, (hipStream_t)stream);
+    if (st != AS_OK) return st;
+    return launch_status("as_accumulate_error_stats");
+}
+
+as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *cand, int64_t n_cand,
+                            const as_region_buf *regions, const as_camera *views, int32_t n_views,
+                            const int32_t *attr_count, const as_split_params *params, const float *noise,
+                            as_gaussians_mut *out, uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out,
+                            void *stream) {
+    if (!ctx || !regions || !regions->records || !regions->count || !attr_count || !n_out || n_cand < 0 ||
+        n_views < 0 || (n_views > 0 && !views)) {
+        as_set_error("as_adaptive_split: bad argument");
+        return AS_ERR_ARG;
+    }
+    if (n_cand > 0 && (!cand || !noise || !mode || !count || !offset)) {
+        as_set_error("as_adaptive_split: null per-candidate pointer");
+        return AS_ERR_ARG;
+    }
+    if (!check_gauss(g, "as_adaptive_split") || !check_params(params, "as_adaptive_split")) return AS_ERR_ARG;
+    const int64_t per = params->n_max + 1 > 2 ? params->n_max + 1 : 2;
+    const int64_t bound = g->n + n_cand * per;
+    if (!check_mut(out, 0, g->sh_degree, "as_adaptive_split")) return AS_ERR_ARG;
+    if (out->n < bound) {
+        as_set_error("as_adaptive_split: output capacity %lld below the bound %lld", (long long)out->n, (long long)bound);
+        return AS_ERR_CAPACITY;
+    }
+    for (int v = 0; v < n_views; v++)
+        if (!(views[v].fx > 0.f) || !(views[v].fy > 0.f) || views[v].width < 1 || views[v].height < 1) {
+            as_set_error("as_adaptive_split: view %d is invalid", v);
+            return AS_ERR_ARG;
+        }
+    const as_status st = run_adaptive_split(ctx, gptrs(g), cand, n_cand, *regions, views, n_views, attr_count, *params,
+                                            noise, mptrs(out), out->n, mode, count, offset, n_out, (hipStream_t)stream);
+    if (st != AS_OK) return st;
+    return launch_status("as_adaptive_split");
+}
+
+as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, int32_t key_bits, void *stream) {
+    if (!ctx || (n > 0 && (!keys || !vals)) || n < 0 || n > 0xFFFFFFFFll || key_bits < 0 || key_bits > 64) {
+        as_set_error("as_debug_sort_pairs: bad argument");
+        return AS_ERR_ARG;
+    }
+    if (n == 0) return AS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (bad(devbuf_ensure(ctx->dbg[0], n * 8), "sort scratch") || bad(devbuf_ensure(ctx->dbg[1], n * 4), "sort scratch") ||
+        bad(devbuf_ensure(ctx->dbg[2], sort_hist_bytes(n)), "sort scratch") || bad(devbuf_ensure(ctx->dbg[3], 64), "sort scratch"))
+        return AS_ERR_HIP;
+    uint64_t *kk[2] = {keys, (uint64_t *)ctx->dbg[0].p};
+    uint32_t *vv[2] = {vals, (uint32_t *)ctx->dbg[1].p};
+    uint32_t *n_dev = (uint32_t *)ctx->dbg[3].p;
+    launch_fill_u32(n_dev, (uint32_t)n, 1, s);
+    const int sel = radix_sort_pairs(kk, vv, n_dev, n, n, key_bits, ctx->dbg[2].p, s);
+    if (sel == 1) {
+        if (bad(hipMemcpyAsync(keys, kk[1], n * 8, hipMemcpyDeviceToDevice, s), "sort copy-back") ||
+            bad(hipMemcpyAsync(vals, vv[1], n * 4, hipMemcpyDeviceToDevice, s), "sort copy-back"))
+            return AS_ERR_HIP;
+    }
+    return launch_status("as_debug_sort_pairs");
+}
+
+as_status as_debug_fp64_ops(as_ctx *ctx, const double *a, const double *b, int64_t n, double *out, void *stream) {
+    if (!ctx || n < 0 || (n > 0 && (!a || !b || !out))) { as_set_error("as_debug_fp64_ops: bad argument"); return AS_ERR_ARG; }
+    launch_fp64_ops(a, b, n, out, (hipStream_t)stream);
+    return launch_status("as_debug_fp64_ops");
+}
+
+}  // extern "C"

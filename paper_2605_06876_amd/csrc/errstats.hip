@@ -1,0 +1,336 @@
+// Error region partitioning of one sampled view (Sec. 4.1): normalised L1 error
+// (Eq. (l1map)), metric map, attribution counts, erosion, error bands, 8-connected
+// regions of equal (dominant candidate, band) (Eq. (error-region)), the area
+// filter (Eq. (min_region_area)) and the region statistics.
+//
+// Decision quantities (E, M, B, the region set and its integer moments) are
+// computed in FP64 / exact integers; this file is compiled with
+// -ffp-contract=off.  Connected components use a lock-free union-find whose
+// roots are always the smallest pixel index of their component, so labels are
+// canonical and independent of thread scheduling.
+#include "internal.h"
+
+namespace {
+
+enum { ES_M, ES_B, ES_LABEL, ES_FLAG, ES_SLOT, ES_ROOT, ES_MOM, ES_KEEP, ES_KIDX, ES_SCAN, ES_TOT };
+
+__device__ __forceinline__ double dev_bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+__global__ void k_error_map(int W, int H, const float *__restrict__ img, const float *__restrict__ gt,
+                            double *__restrict__ err, unsigned long long *__restrict__ minmax) {
+    const int64_t P = (int64_t)W * H;
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    const bool in = u < P;
+    if (in) {
+        const double d0 = fabs((double)img[u] - (double)gt[u]);
+        const double d1 = fabs((double)img[P + u] - (double)gt[P + u]);
+        const double d2 = fabs((double)img[2 * P + u] - (double)gt[2 * P + u]);
+        e = (d0 + d1) + d2;
+        err[u] = e;
+    }
+    const double emin = wave_min_d(in ? e : __longlong_as_double(0x7ff0000000000000ll));
+    const double emax = wave_max_d(in ? e : 0.0);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&minmax[0], (unsigned long long)__double_as_longlong(emin));
+        atomicMax(&minmax[1], (unsigned long long)__double_as_longlong(emax));
+    }
+}
+
+// E, M, B and the pre-erosion attribution count.
+__global__ void k_classify(int64_t P, const double *__restrict__ err, const unsigned long long *__restrict__ minmax,
+                           const int32_t *__restrict__ dom, const uint8_t *__restrict__ is_cand, double tau, int L,
+                           uint8_t *__restrict__ M, uint8_t *__restrict__ B, int32_t *__restrict__ attr) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool hit = false;
+    int32_t d = -1;
+    if (u < P) {
+        const double emin = dev_bits_to_double(minmax[0]), emax = dev_bits_to_double(minmax[1]);
+        const double E = (emax == emin) ? 0.0 : (err[u] - emin) / (emax - emin);
+        const bool m = E > tau;
+        uint8_t b = 0;
+        if (m) {
+            double bb = floor(((E - tau) * (double)L) / (1.0 - tau));
+            if (bb > (double)(L - 1)) bb = (double)(L - 1);
+            b = (uint8_t)bb;
+        }
+        M[u] = m;
+        B[u] = b;
+        d = dom[u];
+        hit = m && d >= 0 && is_cand[d];
+    }
+    // attr[d] += 1 per hit; one atomic per wave when all hits share d
+    const uint64_t hits = __ballot(hit);
+    if (!hits) return;
+    const int leader = __ffsll((unsigned long long)hits) - 1;
+    const int32_t d0 = __shfl(d, leader, 64);
+    const uint64_t same = __ballot(hit && d == d0);
+    if (same == hits) {
+        if ((int)__lane_id() == leader) atomicAdd(&attr[d0], (int32_t)__popcll(hits));
+    } else if (hit) {
+        atomicAdd(&attr[d], 1);
+    }
+}
+
+// M' = erosion of M with a (2r+1)^2 square (outside counts as set); active
+// pixels start as their own component.
+__global__ void k_erode_init(int W, int H, int r, const uint8_t *__restrict__ M, const int32_t *__restrict__ dom,
+                             const uint8_t *__restrict__ is_cand, int32_t *__restrict__ label) {
+    const int64_t P = (int64_t)W * H;
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= P) return;
+    const int x = (int)(u % W), y = (int)(u / W);
+    bool keep = M[u] != 0;
+    for (int dy = -r; dy <= r && keep; dy++) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= H) continue;
+        for (int dx = -r; dx <= r; dx++) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= W) continue;
+            if (!M[(int64_t)yy * W + xx]) {
+                keep = false;
+                break;
+            }
+        }
+    }
+    const int32_t d = dom[u];
+    const bool active = keep && d >= 0 && is_cand[d];
+    label[u] = active ? (int32_t)u : -1;
+}
+
+__device__ __forceinline__ int32_t uf_load(const int32_t *L, int32_t x) {
+    return __hip_atomic_load(L + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t uf_find(const int32_t *L, int32_t x) {
+    int32_t p = uf_load(L, x);
+    while (p != x) {
+        x = p;
+        p = uf_load(L, x);
+    }
+    return x;
+}
+
+// Link the components of a and b; a root only ever points to a smaller index.
+__device__ __forceinline__ void uf_unite(int32_t *L, int32_t a, int32_t b) {
+    while (true) {
+        a = uf_find(L, a);
+        b = uf_find(L, b);
+        if (a == b) return;
+        if (a < b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        const int32_t old = atomicMin(L + a, b);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+__global__ void k_ccl_union(int W, int H, const int32_t *__restrict__ dom, const uint8_t *__restrict__ B,
+                            int32_t *label) {
+    const int64_t P = (int64_t)W * H;
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= P) return;
+    if (label[u] < 0) return;
+    const int x = (int)(u % W), y = (int)(u / W);
+    const int32_t d = dom[u];
+    const uint8_t b = B[u];
+    const int nx[4] = {-1, -1, 0, 1};
+    const int ny[4] = {0, -1, -1, -1};
+    for (int k = 0; k < 4; k++) {
+        const int xx = x + nx[k], yy = y + ny[k];
+        if (xx < 0 || yy < 0 || xx >= W) continue;
+        const int64_t q = (int64_t)yy * W + xx;
+        if (uf_load(label, (int32_t)q) < 0) continue;
+        if (dom[q] != d || B[q] != b) continue;
+        uf_unite(label, (int32_t)u, (int32_t)q);
+    }
+}
+
+__global__ void k_ccl_flatten(int64_t P, int32_t *label, uint8_t *__restrict__ root_flag) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= P) return;
+    const int32_t l = label[u];
+    if (l < 0) {
+        root_flag[u] = 0;
+        return;
+    }
+    const int32_t r = uf_find(label, (int32_t)u);
+    root_flag[u] = (r == (int32_t)u);
+    label[u] = r;
+}
+
+__global__ void k_slot_roots(int64_t P, const uint8_t *__restrict__ root_flag, const int64_t *__restrict__ slot,
+                             int32_t *__restrict__ slot_root) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= P) return;
+    if (root_flag[u]) slot_root[slot[u]] = (int32_t)u;
+}
+
+// Exact integer moments A, Sx, Sy, Sxx, Sxy, Syy per component.
+__global__ void k_moments(int W, int H, const int32_t *__restrict__ label, const int64_t *__restrict__ slot,
+                          unsigned long long *__restrict__ mom) {
+    const int64_t P = (int64_t)W * H;
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s = -1;
+    int64_t v[6] = {0, 0, 0, 0, 0, 0};
+    if (u < P) {
+        const int32_t l = label[u];
+        if (l >= 0) {
+            s = slot[l];
+            const int64_t x = u % W, y = u / W;
+            v[0] = 1; v[1] = x; v[2] = y; v[3] = x * x; v[4] = x * y; v[5] = y * y;
+        }
+    }
+    const bool act = s >= 0;
+    const uint64_t acts = __ballot(act);
+    if (!acts) return;
+    const int leader = __ffsll((unsigned long long)acts) - 1;
+    const int64_t s0 = __shfl(s, leader, 64);
+    if (__ballot(act && s == s0) == acts) {
+        for (int k = 0; k < 6; k++) {
+            int64_t t = v[k];
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+            v[k] = t;
+        }
+        if ((int)__lane_id() == leader)
+            for (int k = 0; k < 6; k++) atomicAdd(&mom[s0 * 6 + k], (unsigned long long)v[k]);
+    } else if (act) {
+        for (int k = 0; k < 6; k++) atomicAdd(&mom[s * 6 + k], (unsigned long long)v[k]);
+    }
+}
+
+__global__ void k_region_keep(const int64_t *__restrict__ n_slots, int64_t cap_slots,
+                              const unsigned long long *__restrict__ mom, int m_min, uint8_t *__restrict__ keep) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= cap_slots) return;
+    keep[s] = (s < *n_slots) && ((int64_t)mom[s * 6] >= (int64_t)m_min);
+}
+
+__device__ __forceinline__ double central_moment(int64_t A, int64_t sab, int64_t sa, int64_t sb) {
+    const __int128 num = (__int128)A * sab - (__int128)sa * sb;
+    double dnum;
+    if (num >= (__int128)INT64_MIN && num <= (__int128)INT64_MAX) dnum = (double)(int64_t)num;
+    else dnum = (double)num;
+    const double dA = (double)A;
+    return dnum / (dA * dA);
+}
+
+__global__ void k_region_emit(int W, int H, int view, const int64_t *__restrict__ n_slots, int64_t cap_slots,
+                              const unsigned long long *__restrict__ mom, const uint8_t *__restrict__ keep,
+                              const int64_t *__restrict__ kidx, const int32_t *__restrict__ slot_root,
+                              const int32_t *__restrict__ dom, const uint8_t *__restrict__ B,
+                              const float *__restrict__ gt, as_region *__restrict__ out, int64_t out_cap,
+                              const int64_t *__restrict__ count) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= cap_slots || s >= *n_slots || !keep[s]) return;
+    const int64_t pos = *count + kidx[s];
+    if (pos >= out_cap) return;
+    const int64_t P = (int64_t)W * H;
+    as_region r;
+    const int32_t root = slot_root[s];
+    r.cand = dom[root];
+    r.view = view;
+    r.label = root;
+    r.band = B[root];
+    r.pad0 = 0;
+    const int64_t A = (int64_t)mom[s * 6 + 0];
+    r.area = (int32_t)A;
+    r.sx = (int64_t)mom[s * 6 + 1];
+    r.sy = (int64_t)mom[s * 6 + 2];
+    r.sxx = (int64_t)mom[s * 6 + 3];
+    r.sxy = (int64_t)mom[s * 6 + 4];
+    r.syy = (int64_t)mom[s * 6 + 5];
+    const double dA = (double)A;
+    r.cx = (double)r.sx / dA + 0.5;
+    r.cy = (double)r.sy / dA + 0.5;
+    const double cxx = central_moment(A, r.sxx, r.sx, r.sx) + 1.0 / 12.0;
+    const double cxy = central_moment(A, r.sxy, r.sx, r.sy);
+    const double cyy = central_moment(A, r.syy, r.sy, r.sy) + 1.0 / 12.0;
+    r.cov[0] = cxx;
+    r.cov[1] = cxy;
+    r.cov[2] = cyy;
+    const double half_tr = 0.5 * (cxx + cyy);
+    const double half_dif = 0.5 * (cxx - cyy);
+    const double disc = sqrt(half_dif * half_dif + cxy * cxy);
+    const double l1 = half_tr + disc, l2 = half_tr - disc;
+    double ex, ey;
+    if (disc == 0.0) {
+        ex = 1.0; ey = 0.0;
+    } else if (half_dif >= 0.0) {
+        ex = half_dif + disc; ey = cxy;
+    } else {
+        ex = cxy; ey = -half_dif + disc;
+    }
+    const double en = sqrt(ex * ex + ey * ey);
+    ex = ex / en;
+    ey = ey / en;
+    if (ex < 0.0 || (ex == 0.0 && ey < 0.0)) {
+        ex = -ex;
+        ey = -ey;
+    }
+    r.e1[0] = ex;
+    r.e1[1] = ey;
+    r.sigma1 = sqrt(l1);
+    r.sigma2 = sqrt(l2 > 0.0 ? l2 : 0.0);
+    const int64_t gx = (int64_t)floor(r.cx), gy = (int64_t)floor(r.cy);
+    for (int ch = 0; ch < 3; ch++) r.rgb[ch] = gt[ch * P + gy * W + gx];
+    r.pad1 = 0.f;
+    out[pos] = r;
+}
+
+__global__ void k_count_add(int64_t *count, const int64_t *__restrict__ kept) { *count += *kept; }
+
+}  // namespace
+
+void launch_error_map(int W, int H, const float *image, const float *gt, double *err, uint64_t *minmax, hipStream_t s) {
+    const int64_t P = (int64_t)W * H;
+    launch_fill_u64(minmax, 0x7ff0000000000000ull, 1, s);
+    launch_fill_u64(minmax + 1, 0ull, 1, s);
+    if (P == 0) return;
+    hipLaunchKernelGGL(k_error_map, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, W, H, image, gt, err,
+                       reinterpret_cast<unsigned long long *>(minmax));
+}
+
+as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const uint64_t *minmax, const int32_t *dom,
+                          const float *gt, int view, int64_t n, const uint8_t *is_cand, const as_split_params &p,
+                          as_region_buf &rb, int32_t *attr, hipStream_t s) {
+    (void)n;
+    const int64_t P = (int64_t)W * H;
+    if (P == 0) return AS_OK;
+    hipError_t e = hipSuccess;
+    DevBuf *es = ctx->es;
+    if ((e = devbuf_ensure(es[ES_M], P)) != hipSuccess || (e = devbuf_ensure(es[ES_B], P)) != hipSuccess ||
+        (e = devbuf_ensure(es[ES_LABEL], P * 4)) != hipSuccess || (e = devbuf_ensure(es[ES_FLAG], P)) != hipSuccess ||
+        (e = devbuf_ensure(es[ES_SLOT], P * 8)) != hipSuccess || (e = devbuf_ensure(es[ES_ROOT], P * 4)) != hipSuccess ||
+        (e = devbuf_ensure(es[ES_MOM], P * 48)) != hipSuccess || (e = devbuf_ensure(es[ES_KEEP], P)) != hipSuccess ||
+        (e = devbuf_ensure(es[ES_KIDX], P * 8)) != hipSuccess ||
+        (e = devbuf_ensure(es[ES_SCAN], scan_tmp_bytes(P))) != hipSuccess ||
+        (e = devbuf_ensure(es[ES_TOT], 64)) != hipSuccess) {
+        as_set_error("error-stats scratch allocation failed: %s", hipGetErrorString(e));
+        return AS_ERR_HIP;
+    }
+    uint8_t *M = (uint8_t *)es[ES_M].p, *B = (uint8_t *)es[ES_B].p, *flag = (uint8_t *)es[ES_FLAG].p;
+    uint8_t *keep = (uint8_t *)es[ES_KEEP].p;
+    int32_t *label = (int32_t *)es[ES_LABEL].p, *root = (int32_t *)es[ES_ROOT].p;
+    int64_t *slot = (int64_t *)es[ES_SLOT].p, *kidx = (int64_t *)es[ES_KIDX].p, *tot = (int64_t *)es[ES_TOT].p;
+    unsigned long long *mom = (unsigned long long *)es[ES_MOM].p;
+    const unsigned grid = (unsigned)((P + 255) / 256);
+    hipLaunchKernelGGL(k_classify, dim3(grid), dim3(256), 0, s, P, err,
+                       reinterpret_cast<const unsigned long long *>(minmax), dom, is_cand, p.tau_l1, p.L, M, B, attr);
+    hipLaunchKernelGGL(k_erode_init, dim3(grid), dim3(256), 0, s, W, H, p.r_erode, M, dom, is_cand, label);
+    hipLaunchKernelGGL(k_ccl_union, dim3(grid), dim3(256), 0, s, W, H, dom, B, label);
+    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid), dim3(256), 0, s, P, label, flag);
+    scan_u8_to_i64(flag, slot, P, tot, es[ES_SCAN].p, s);
+    hipLaunchKernelGGL(k_slot_roots, dim3(grid), dim3(256), 0, s, P, flag, slot, root);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(mom), 0ull, P * 6, s);
+    hipLaunchKernelGGL(k_moments, dim3(grid), dim3(256), 0, s, W, H, label, slot, mom);
+    hipLaunchKernelGGL(k_region_keep, dim3(grid), dim3(256), 0, s, tot, P, mom, p.m_min, keep);
+    scan_u8_to_i64(keep, kidx, P, tot + 1, es[ES_SCAN].p, s);
+    hipLaunchKernelGGL(k_region_emit, dim3(grid), dim3(256), 0, s, W, H, view, tot, P, mom, keep, kidx, root, dom, B,
+                       gt, rb.records, rb.capacity, rb.count);
+    hipLaunchKernelGGL(k_count_add, dim3(1), dim3(1), 0, s, rb.count, tot + 1);
+    return AS_OK;
+}

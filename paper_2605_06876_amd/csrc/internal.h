@@ -1,0 +1,178 @@
+// Internal declarations shared by the HIP translation units of libadpsplit.
+// Not part of the C-ABI (include/adpsplit.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adpsplit.h"
+
+#define AS_TILE_W 16
+#define AS_TILE_H 16
+#define AS_BLOCK 256        // threads per tile block: one 16x16 tile, four wave64
+#define AS_NEAR 0.2
+#define AS_LOWPASS 0.3
+
+// Blend record of one projected Gaussian, 48 bytes (three float4):
+//   [0] mean_x hi, mean_y hi, mean_x lo, mean_y lo  (mean = hi + lo, continuous pixel frame)
+//   [1] conic xx, conic xy, conic yy, opacity
+//   [2] r, g, b, 0
+struct __align__(16) BlendRec {
+    float4 m, c, rgb;
+};
+
+// Camera in device-friendly form, passed by value to kernels.
+struct DevCam {
+    float R[9], t[3], fx, fy, cx, cy;
+    int32_t W, H;
+    float bg[3];
+};
+
+static inline DevCam to_devcam(const as_camera &c) {
+    DevCam d;
+    for (int k = 0; k < 9; k++) d.R[k] = c.R[k];
+    for (int k = 0; k < 3; k++) d.t[k] = c.t[k];
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    d.W = c.width; d.H = c.height;
+    for (int k = 0; k < 3; k++) d.bg[k] = c.bg[k];
+    return d;
+}
+
+struct GaussPtrs {
+    const float *means, *log_scales, *quats, *opac, *sh;
+    int64_t n;
+    int32_t deg;
+};
+
+struct GradPtrs {
+    float *means, *log_scales, *quats, *opac, *sh;
+    int64_t stride;
+};
+
+// A growable device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+hipError_t devbuf_ensure(DevBuf &b, size_t bytes);
+void devbuf_free(DevBuf &b);
+
+struct as_frame {
+    as_ctx *ctx;
+    int64_t n_cap, key_cap;
+    int32_t W, H, tiles_x, tiles_y;
+    int32_t auto_grow;
+    // per Gaussian
+    BlendRec *rec;
+    uint32_t *depth_key;
+    int16_t *box;          // [n][4]
+    uint32_t *ntiles;
+    uint32_t *offsets;
+    float *grad2d;         // [9][n]
+    // pairs
+    uint64_t *keys[2];
+    uint32_t *vals[2];
+    int sorted_sel;
+    uint32_t *ranges;      // [tiles][2]
+    uint32_t *n_keys;      // [1] device
+    uint32_t *h_nkeys;     // pinned host mirror
+    // per pixel
+    float *t_final;
+    uint32_t *last;
+    uint32_t *n_contrib;
+    int32_t *dom;
+    double *err;
+    uint64_t *err_minmax;
+    // scratch for scans and the sorter
+    DevBuf scan_tmp, sort_hist;
+    // state of the last render
+    int has_render;
+    int64_t n_last;
+    int32_t deg_last;
+    int32_t has_gt;
+};
+
+struct as_ctx {
+    int device;
+    DevBuf es[16];    // error-statistics scratch (errstats.hip names the slots)
+    DevBuf sp[24];    // adaptive-split scratch (split.hip names the slots)
+    DevBuf dbg[4];    // test hooks
+};
+
+// ---- launchers (each defined in the .hip file that holds the kernel) -------------
+
+// projection (project.hip)
+void launch_project(const GaussPtrs &g, const DevCam &cam, int tiles_x, BlendRec *rec, uint32_t *depth_key,
+                    int16_t *box, uint32_t *ntiles, hipStream_t s);
+// projection backward (project_bwd.hip)
+void launch_project_bwd(const GaussPtrs &g, const DevCam &cam, const uint32_t *ntiles, const float *grad2d,
+                        int64_t g2d_stride, GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s);
+
+// scans (binning.hip): exclusive scans with the total written to *total
+size_t scan_tmp_bytes(int64_t n);
+void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *tmp, hipStream_t s);
+void scan_u8_to_i64(const uint8_t *in, int64_t *out, int64_t n, int64_t *total, void *tmp, hipStream_t s);
+void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total, void *tmp, hipStream_t s);
+
+// binning (binning.hip)
+void launch_emit_keys(int64_t n, const uint32_t *depth_key, const int16_t *box, const uint32_t *ntiles,
+                      const uint32_t *offsets, int tiles_x, int64_t key_cap, uint64_t *keys, uint32_t *vals,
+                      hipStream_t s);
+size_t sort_hist_bytes(int64_t n_hint);
+// Sorts (keys[0], vals[0]) on the low key_bits bits, ping-ponging with
+// (keys[1], vals[1]); returns which buffer holds the result.  The element count
+// is read from the device (*n_dev, clamped to cap); n_hint sizes the grid.
+int radix_sort_pairs(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint,
+                     int key_bits, void *hist, hipStream_t s);
+void launch_ranges(const uint64_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
+                   hipStream_t s);
+void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+
+// blend (blend.hip)
+void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const DevCam &cam, const float *gt, float *image,
+                      hipStream_t s);
+void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const DevCam &cam, const float *dL_dimage,
+                      float *grad2d, int64_t g2d_stride, hipStream_t s);
+
+// error statistics (errstats.hip)
+void launch_error_map(int W, int H, const float *image, const float *gt, double *err, uint64_t *minmax,
+                      hipStream_t s);
+as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const uint64_t *minmax, const int32_t *dom,
+                          const float *gt, int view, int64_t n, const uint8_t *is_cand, const as_split_params &p,
+                          as_region_buf &rb, int32_t *attr, hipStream_t s);
+
+// adaptive split (split.hip)
+as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *cand, int64_t n_cand,
+                             const as_region_buf &rb, const as_camera *views, int n_views, const int32_t *attr,
+                             const as_split_params &p, const float *noise, GradPtrs out, int64_t out_cap,
+                             uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out, hipStream_t s);
+
+// debug (binning.hip)
+void launch_fp64_ops(const double *a, const double *b, int64_t n, double *out, hipStream_t s);
+
+// error reporting (api.cpp)
+void as_set_error(const char *fmt, ...);
+
+// ---- device helpers -----------------------------------------------------------------
+
+#ifdef __HIPCC__
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const unsigned lane = __lane_id();
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+#endif

@@ -1,0 +1,135 @@
+// EWA projection, spherical-harmonic colour, depth key and compact box of every
+// Gaussian (Sec. 3 of the paper: each Gaussian is projected to the image plane
+// and its view-dependent colour decoded from SH along the viewing direction).
+//
+// One thread per Gaussian, struct-of-arrays reads (coalesced).  All arithmetic
+// is FP64 and this file is compiled with -ffp-contract=off: the depth key and
+// the pixel box decide which (tile, Gaussian) pairs exist, so they are
+// computed with a fixed expression order and IEEE-rounded operations.
+#include "internal.h"
+#include "sh_device.h"
+
+namespace {
+
+__device__ __forceinline__ void quat_to_rot_d(double w, double x, double y, double z, double R[9]) {
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__global__ void __launch_bounds__(256) k_project(GaussPtrs g, DevCam cam, int tiles_x, BlendRec *__restrict__ rec,
+                                                 uint32_t *__restrict__ depth_key, short4 *__restrict__ box,
+                                                 uint32_t *__restrict__ ntiles) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const int64_t n = g.n;
+    double mu[3], s[3], q[4];
+    for (int k = 0; k < 3; k++) mu[k] = (double)g.means[k * n + i];
+    for (int k = 0; k < 3; k++) s[k] = exp((double)g.log_scales[k * n + i]);
+    for (int k = 0; k < 4; k++) q[k] = (double)g.quats[k * n + i];
+    const double ologit = (double)g.opac[i];
+
+    double Rc[9], tc[3];
+    for (int k = 0; k < 9; k++) Rc[k] = (double)cam.R[k];
+    for (int k = 0; k < 3; k++) tc[k] = (double)cam.t[k];
+    const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
+
+    double tv[3];
+    for (int r = 0; r < 3; r++) tv[r] = Rc[r * 3 + 0] * mu[0] + Rc[r * 3 + 1] * mu[1] + Rc[r * 3 + 2] * mu[2] + tc[r];
+    const double tx = tv[0], ty = tv[1], tz = tv[2];
+    depth_key[i] = __float_as_uint((float)tz);
+
+    BlendRec rr;
+    rr.m = make_float4(0.f, 0.f, 0.f, 0.f);
+    rr.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    rr.rgb = make_float4(0.f, 0.f, 0.f, 0.f);
+    short4 bx = make_short4(0, 0, -1, -1);
+    uint32_t nt = 0;
+
+    do {
+        if (!(tz > AS_NEAR)) break;
+        const double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+        const double qnorm = sqrt(qn2);
+        double Rg[9];
+        quat_to_rot_d(q[0] / qnorm, q[1] / qnorm, q[2] / qnorm, q[3] / qnorm, Rg);
+        // perspective Jacobian at the (clamped) centre
+        const double limx = 1.3 * ((double)cam.W / (2.0 * fx));
+        const double limy = 1.3 * ((double)cam.H / (2.0 * fy));
+        const double txtz = tx / tz, tytz = ty / tz;
+        const double cx_ = fmin(limx, fmax(-limx, txtz)) * tz;
+        const double cy_ = fmin(limy, fmax(-limy, tytz)) * tz;
+        const double J[6] = {fx / tz, 0.0, -(fx * cx_) / (tz * tz), 0.0, fy / tz, -(fy * cy_) / (tz * tz)};
+        double T[6];
+        for (int r = 0; r < 2; r++)
+            for (int k = 0; k < 3; k++)
+                T[r * 3 + k] = J[r * 3 + 0] * Rc[0 * 3 + k] + J[r * 3 + 1] * Rc[1 * 3 + k] + J[r * 3 + 2] * Rc[2 * 3 + k];
+        double S[9];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; k++) acc += Rg[a * 3 + k] * (s[k] * s[k]) * Rg[b * 3 + k];
+                S[a * 3 + b] = acc;
+            }
+        double C2[4];
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; k++)
+                    for (int l = 0; l < 3; l++) acc += T[a * 3 + k] * S[k * 3 + l] * T[b * 3 + l];
+                C2[a * 2 + b] = acc;
+            }
+        const double A = C2[0] + AS_LOWPASS, B = C2[1], Cc = C2[3] + AS_LOWPASS;
+        const double det = A * Cc - B * B;
+        if (!(det > 0.0)) break;
+        const double mx = fx * tx / tz + cx;
+        const double my = fy * ty / tz + cy;
+        const double o = 1.0 / (1.0 + exp(-ologit));
+        if (!(o >= (1.0 / 255.0))) break;
+        const double kk = 2.0 * log(255.0 * o);
+        const double hx = sqrt(kk * A), hy = sqrt(kk * Cc);
+        double x0 = ceil(mx - hx - 0.5), x1 = floor(mx + hx - 0.5);
+        double y0 = ceil(my - hy - 0.5), y1 = floor(my + hy - 0.5);
+        x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
+        x1 = fmin(x1, (double)(cam.W - 1)); y1 = fmin(y1, (double)(cam.H - 1));
+        if (!(x0 <= x1 && y0 <= y1)) break;
+
+        // colour along the unit view direction
+        double oc[3];
+        for (int j = 0; j < 3; j++) oc[j] = -(Rc[0 * 3 + j] * tc[0] + Rc[1 * 3 + j] * tc[1] + Rc[2 * 3 + j] * tc[2]);
+        const double v0 = mu[0] - oc[0], v1 = mu[1] - oc[1], v2 = mu[2] - oc[2];
+        const double vn = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+        double Y[16];
+        sh_eval_basis(v0 / vn, v1 / vn, v2 / vn, g.deg, Y);
+        const int nk = (g.deg + 1) * (g.deg + 1);
+        double col[3];
+        for (int ch = 0; ch < 3; ch++) {
+            double acc = 0.0;
+            for (int k = 0; k < nk; k++) acc += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
+            acc += 0.5;
+            col[ch] = acc < 0.0 ? 0.0 : acc;
+        }
+
+        const float mxh = (float)mx, myh = (float)my;
+        rr.m = make_float4(mxh, myh, (float)(mx - (double)mxh), (float)(my - (double)myh));
+        rr.c = make_float4((float)(Cc / det), (float)(-B / det), (float)(A / det), (float)o);
+        rr.rgb = make_float4((float)col[0], (float)col[1], (float)col[2], 0.f);
+        const int ix0 = (int)x0, iy0 = (int)y0, ix1 = (int)x1, iy1 = (int)y1;
+        bx = make_short4((short)ix0, (short)iy0, (short)ix1, (short)iy1);
+        nt = (uint32_t)((ix1 / AS_TILE_W - ix0 / AS_TILE_W + 1) * (iy1 / AS_TILE_H - iy0 / AS_TILE_H + 1));
+    } while (0);
+
+    rec[i] = rr;
+    box[i] = bx;
+    ntiles[i] = nt;
+    (void)tiles_x;
+}
+
+}  // namespace
+
+void launch_project(const GaussPtrs &g, const DevCam &cam, int tiles_x, BlendRec *rec, uint32_t *depth_key,
+                    int16_t *box, uint32_t *ntiles, hipStream_t s) {
+    if (g.n == 0) return;
+    const int64_t blocks = (g.n + 255) / 256;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key,
+                       reinterpret_cast<short4 *>(box), ntiles);
+}

@@ -1,0 +1,192 @@
+// Reverse pass of the projection (Sec. 3): from the per-Gaussian 2D gradients
+// (mean, conic, opacity, colour) accumulated by the blend back to the stored
+// parameters (means, log-scales, quaternions, opacity logits, SH).  One thread
+// per Gaussian, FP64, struct-of-arrays reads and writes.
+//
+// Chain: colour = max(0, sum_k Y_k(d) sh_k + 1/2) with d = (mu - o_v)/|mu - o_v|;
+// mean2d = (fx tx/tz + cx, fy ty/tz + cy); conic = inverse(J W Sigma W^T J^T
+// + 0.3 I) with J the perspective Jacobian at the clamped centre; Sigma =
+// R(q/|q|) diag(exp(2 log s)) R^T; o = sigmoid(logit).
+#include "internal.h"
+#include "sh_device.h"
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, const uint32_t *__restrict__ ntiles,
+                                                     const float *__restrict__ g2d, int64_t gs, GradPtrs out,
+                                                     float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const int64_t n = g.n, os = out.stride;
+    const int nk = (g.deg + 1) * (g.deg + 1);
+    if (ntiles[i] == 0) {
+        for (int k = 0; k < 3; k++) { out.means[k * os + i] = 0.f; out.log_scales[k * os + i] = 0.f; }
+        for (int k = 0; k < 4; k++) out.quats[k * os + i] = 0.f;
+        out.opac[i] = 0.f;
+        for (int k = 0; k < nk * 3; k++) out.sh[(int64_t)k * os + i] = 0.f;
+        return;
+    }
+    const double gm0 = g2d[0 * gs + i], gm1 = g2d[1 * gs + i];
+    const double gca = g2d[2 * gs + i], gcb = g2d[3 * gs + i], gcc = g2d[4 * gs + i];
+    const double gop = g2d[5 * gs + i];
+    const double grgb[3] = {g2d[6 * gs + i], g2d[7 * gs + i], g2d[8 * gs + i]};
+    if (g2d_norm) g2d_norm[i] += (float)sqrt(gm0 * gm0 + gm1 * gm1);
+    if (vis_count) vis_count[i] += 1;
+
+    double mu[3], s[3], q[4];
+    for (int k = 0; k < 3; k++) mu[k] = (double)g.means[k * n + i];
+    for (int k = 0; k < 3; k++) s[k] = exp((double)g.log_scales[k * n + i]);
+    for (int k = 0; k < 4; k++) q[k] = (double)g.quats[k * n + i];
+    const double o = 1.0 / (1.0 + exp(-(double)g.opac[i]));
+    double Rc[9], tc[3];
+    for (int k = 0; k < 9; k++) Rc[k] = (double)cam.R[k];
+    for (int k = 0; k < 3; k++) tc[k] = (double)cam.t[k];
+    const double fx = cam.fx, fy = cam.fy;
+    double tv[3];
+    for (int r = 0; r < 3; r++) tv[r] = Rc[r * 3 + 0] * mu[0] + Rc[r * 3 + 1] * mu[1] + Rc[r * 3 + 2] * mu[2] + tc[r];
+    const double tx = tv[0], ty = tv[1], tz = tv[2];
+    const double qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double w = q[0] / qnorm, x = q[1] / qnorm, y = q[2] / qnorm, z = q[3] / qnorm;
+    const double Rg[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                          2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                          2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+
+    double dmu[3] = {0.0, 0.0, 0.0};
+    // opacity
+    out.opac[i] = (float)(gop * o * (1.0 - o));
+    // colour and view direction
+    double oc[3];
+    for (int j = 0; j < 3; j++) oc[j] = -(Rc[0 * 3 + j] * tc[0] + Rc[1 * 3 + j] * tc[1] + Rc[2 * 3 + j] * tc[2]);
+    const double v[3] = {mu[0] - oc[0], mu[1] - oc[1], mu[2] - oc[2]};
+    const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double d[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
+    double Y[16], dY[16][3];
+    sh_eval_basis(d[0], d[1], d[2], g.deg, Y);
+    sh_eval_basis_grad(d[0], d[1], d[2], g.deg, dY);
+    double gd[3] = {0.0, 0.0, 0.0};
+    for (int ch = 0; ch < 3; ch++) {
+        double raw = 0.0;
+        for (int k = 0; k < nk; k++) raw += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
+        const bool clamped = raw + 0.5 < 0.0;
+        const double gc = clamped ? 0.0 : grgb[ch];
+        for (int k = 0; k < nk; k++) {
+            out.sh[((int64_t)k * 3 + ch) * os + i] = (float)(Y[k] * gc);
+            const double shv = (double)g.sh[((int64_t)k * 3 + ch) * n + i];
+            for (int a = 0; a < 3; a++) gd[a] += dY[k][a] * shv * gc;
+        }
+    }
+    const double ddot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+    for (int a = 0; a < 3; a++) dmu[a] += (gd[a] - d[a] * ddot) / vn;
+
+    // mean2d
+    double dt[3] = {0.0, 0.0, 0.0};
+    dt[0] += gm0 * fx / tz;
+    dt[1] += gm1 * fy / tz;
+    dt[2] += -gm0 * fx * tx / (tz * tz) - gm1 * fy * ty / (tz * tz);
+
+    // conic = inverse(cov): dL/dcov = -K G K
+    const double limx = 1.3 * ((double)cam.W / (2.0 * fx));
+    const double limy = 1.3 * ((double)cam.H / (2.0 * fy));
+    const double txtz = tx / tz, tytz = ty / tz;
+    const bool clx = txtz < -limx || txtz > limx, cly = tytz < -limy || tytz > limy;
+    const double cx_ = fmin(limx, fmax(-limx, txtz)) * tz;
+    const double cy_ = fmin(limy, fmax(-limy, tytz)) * tz;
+    const double J[6] = {fx / tz, 0.0, -(fx * cx_) / (tz * tz), 0.0, fy / tz, -(fy * cy_) / (tz * tz)};
+    double T[6];
+    for (int r = 0; r < 2; r++)
+        for (int k = 0; k < 3; k++)
+            T[r * 3 + k] = J[r * 3 + 0] * Rc[k] + J[r * 3 + 1] * Rc[3 + k] + J[r * 3 + 2] * Rc[6 + k];
+    double Sg[9];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; k++) acc += Rg[a * 3 + k] * (s[k] * s[k]) * Rg[b * 3 + k];
+            Sg[a * 3 + b] = acc;
+        }
+    double C2[4];
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; k++)
+                for (int l = 0; l < 3; l++) acc += T[a * 3 + k] * Sg[k * 3 + l] * T[b * 3 + l];
+            C2[a * 2 + b] = acc;
+        }
+    const double A = C2[0] + AS_LOWPASS, B = C2[1], Cc = C2[3] + AS_LOWPASS;
+    const double det = A * Cc - B * B;
+    const double K[4] = {Cc / det, -B / det, -B / det, A / det};
+    const double Gk[4] = {gca, 0.5 * gcb, 0.5 * gcb, gcc};
+    double KG[4], Gc[4];
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) KG[a * 2 + b] = K[a * 2] * Gk[b] + K[a * 2 + 1] * Gk[2 + b];
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) Gc[a * 2 + b] = -(KG[a * 2] * K[b] + KG[a * 2 + 1] * K[2 + b]);
+    double dS[9], dT[6];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            double acc = 0.0;
+            for (int r = 0; r < 2; r++)
+                for (int qq = 0; qq < 2; qq++) acc += T[r * 3 + a] * Gc[r * 2 + qq] * T[qq * 3 + b];
+            dS[a * 3 + b] = acc;
+        }
+    for (int r = 0; r < 2; r++)
+        for (int k = 0; k < 3; k++) {
+            double acc = 0.0;
+            for (int qq = 0; qq < 2; qq++)
+                for (int l = 0; l < 3; l++) acc += Gc[r * 2 + qq] * T[qq * 3 + l] * Sg[l * 3 + k];
+            dT[r * 3 + k] = 2.0 * acc;
+        }
+    double dJ[6];
+    for (int r = 0; r < 2; r++)
+        for (int k = 0; k < 3; k++)
+            dJ[r * 3 + k] = dT[r * 3 + 0] * Rc[k * 3 + 0] + dT[r * 3 + 1] * Rc[k * 3 + 1] + dT[r * 3 + 2] * Rc[k * 3 + 2];
+    dt[2] += dJ[0] * (-fx / (tz * tz)) + dJ[4] * (-fy / (tz * tz));
+    if (!clx) {
+        dt[0] += dJ[2] * (-fx / (tz * tz));
+        dt[2] += dJ[2] * (2.0 * fx * tx / (tz * tz * tz));
+    } else {
+        dt[2] += dJ[2] * (fx * (cx_ / tz) / (tz * tz));
+    }
+    if (!cly) {
+        dt[1] += dJ[5] * (-fy / (tz * tz));
+        dt[2] += dJ[5] * (2.0 * fy * ty / (tz * tz * tz));
+    } else {
+        dt[2] += dJ[5] * (fy * (cy_ / tz) / (tz * tz));
+    }
+    for (int a = 0; a < 3; a++) dmu[a] += Rc[0 * 3 + a] * dt[0] + Rc[1 * 3 + a] * dt[1] + Rc[2 * 3 + a] * dt[2];
+    for (int a = 0; a < 3; a++) out.means[a * os + i] = (float)dmu[a];
+    // scales
+    for (int k = 0; k < 3; k++) {
+        double acc = 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) acc += Rg[a * 3 + k] * dS[a * 3 + b] * Rg[b * 3 + k];
+        out.log_scales[k * os + i] = (float)(2.0 * s[k] * s[k] * acc);
+    }
+    // rotation -> quaternion
+    double dR[9];
+    for (int a = 0; a < 3; a++)
+        for (int k = 0; k < 3; k++) {
+            double acc = 0.0;
+            for (int b = 0; b < 3; b++) acc += dS[a * 3 + b] * Rg[b * 3 + k];
+            dR[a * 3 + k] = 2.0 * acc * s[k] * s[k];
+        }
+    double dq[4];
+    dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                   2.0 * x * dR[8]);
+    dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                   2.0 * y * dR[8]);
+    dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
+                   y * dR[7]);
+    const double qn[4] = {w, x, y, z};
+    const double qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+    for (int k = 0; k < 4; k++) out.quats[k * os + i] = (float)((dq[k] - qn[k] * qd) / qnorm);
+}
+
+}  // namespace
+
+void launch_project_bwd(const GaussPtrs &g, const DevCam &cam, const uint32_t *ntiles, const float *grad2d,
+                        int64_t g2d_stride, GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s) {
+    if (g.n == 0) return;
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g, cam, ntiles, grad2d,
+                       g2d_stride, out, g2d_norm, vis_count);
+}

@@ -1,0 +1,335 @@
+"""HIP rasterizer vs the CPU oracle, element by element, through the C-ABI.
+
+Bars: bit-exact depth keys, boxes, tile keys, sort order, ranges, contributor
+counts and dominant ids on pixels whose FP64 decisions are not within the
+FP32 margin of a threshold (flagged by the oracle); image max-abs <= 1e-4 on
+unflagged pixels; gradients: per tensor ||d||/||ref|| <= 1e-3."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_06876_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2605_06876_amd import api  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return api.Context(0)
+
+
+def gpu_render(ctx, scene, cam, gt=None, key_cap=None):
+    g = api.Gaussians.from_scene(scene)
+    frame = api.Frame(ctx, max(g.n, 1), cam.width, cam.height, key_cap=key_cap)
+    gtt = torch.from_numpy(gt).cuda() if gt is not None else None
+    img = api.render(ctx, g, cam, frame, gt=gtt)
+    torch.cuda.synchronize()
+    return g, frame, img.cpu().numpy()
+
+
+def check_projection(pr, st, n):
+    valid = pr.valid.astype(bool)
+    gvalid = st["ntiles"] > 0
+    np.testing.assert_array_equal(gvalid, valid)
+    np.testing.assert_array_equal(st["depth_key"][valid], pr.depth_key[valid])
+    np.testing.assert_array_equal(st["box"][valid].astype(np.int32), pr.box[valid])
+    rec = st["rec"][valid].astype(np.float64)
+    mean = rec[:, 0:2] + rec[:, 2:4]
+    np.testing.assert_allclose(mean, pr.mean2d[valid], rtol=0, atol=1e-4)
+    np.testing.assert_allclose(rec[:, 4:7], pr.conic[valid], rtol=2e-6, atol=1e-9)
+    np.testing.assert_allclose(rec[:, 7], pr.opacity[valid], rtol=2e-7)
+    np.testing.assert_allclose(rec[:, 8:11], pr.rgb[valid], rtol=2e-6, atol=1e-7)
+
+
+# ---- arithmetic the decisions rely on -------------------------------------------------
+
+def test_fp64_sqrt_and_division_round_like_the_host(ctx):
+    rng = np.random.default_rng(0)
+    n = 1 << 22
+    a = np.abs(rng.normal(size=n)) * 10.0 ** rng.uniform(-30, 30, n)
+    b = rng.normal(size=n) * 10.0 ** rng.uniform(-30, 30, n)
+    out = api.debug_fp64_ops(ctx, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(out[0], np.sqrt(a))
+    np.testing.assert_array_equal(out[1], a / b)
+    bb = rng.uniform(-700, 700, n)
+    out = api.debug_fp64_ops(ctx, torch.from_numpy(a).cuda(), torch.from_numpy(bb).cuda()).cpu().numpy()
+    ulp_e = np.abs(out[2] - np.exp(bb)) / np.spacing(np.exp(bb))
+    ulp_l = np.abs(out[3] - np.log(a)) / np.maximum(np.spacing(np.abs(np.log(a))), 1e-300)
+    say("exp: %.3g of results differ from the host, max %.2f ulp; log: %.3g, max %.2f ulp"
+        % ((ulp_e > 0).mean(), ulp_e.max(), (ulp_l > 0).mean(), ulp_l.max()))
+    assert ulp_e.max() <= 2 and ulp_l.max() <= 2
+
+
+@pytest.mark.parametrize("n,bits,dup", [(1, 8, 0), (1000, 45, 0), (300_000, 47, 1), (2_000_000, 64, 0),
+                                        (1_234_567, 20, 1)])
+def test_radix_sort_is_a_stable_sort(ctx, n, bits, dup):
+    rng = np.random.default_rng(n)
+    if dup:
+        keys = rng.integers(0, 1000, size=n, dtype=np.uint64) << np.uint64(max(bits - 10, 0))
+    else:
+        keys = rng.integers(0, 2 ** 63, size=n, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, size=n, dtype=np.uint64)
+    if bits < 64:
+        keys &= np.uint64((1 << bits) - 1)
+    vals = np.arange(n, dtype=np.uint32)
+    kt = torch.from_numpy(keys.view(np.int64)).cuda()
+    vt = torch.from_numpy(vals.view(np.int32)).cuda()
+    api.debug_sort_pairs(ctx, kt, vt, bits)
+    o = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(kt.cpu().numpy().view(np.uint64), keys[o])
+    np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[o])
+
+
+# ---- C1: 2,000 Gaussians, 128x128, SH 0 ----------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1(ctx):
+    scene, cam, gt = synth.c1_inputs()
+    say("c1: render on the GPU")
+    g, frame, img = gpu_render(ctx, scene, cam, gt)
+    st = frame.host_state(g.n)
+    pr = oracle.project(scene, cam)
+    ref, maps = oracle.render_image(pr)
+    return dict(scene=scene, cam=cam, gt=gt, g=g, frame=frame, img=img, st=st, pr=pr, ref=ref, maps=maps)
+
+
+def test_c1_projection(c1):
+    check_projection(c1["pr"], c1["st"], c1["g"].n)
+
+
+def test_c1_binning_bit_exact(c1):
+    keys, vals, ranges = oracle.bin_tiles(c1["pr"], 16, 16)
+    st = c1["st"]
+    assert st["n_keys"] == len(keys)
+    np.testing.assert_array_equal(st["keys"], keys)
+    np.testing.assert_array_equal(st["vals"], vals)
+    np.testing.assert_array_equal(st["ranges"], ranges)
+
+
+def test_c1_image_counts_dominant(c1):
+    ok = c1["maps"]["flag"] == 0
+    say("c1: flagged pixels %d of %d" % ((~ok).sum(), ok.size))
+    assert (~ok).mean() < 0.01
+    err = np.abs(c1["img"].astype(np.float64) - c1["ref"])
+    assert err[:, ok].max() <= 1e-4, err[:, ok].max()
+    np.testing.assert_array_equal(c1["st"]["n_contrib"][ok], c1["maps"]["ncontrib"][ok])
+    np.testing.assert_array_equal(c1["st"]["dom"][ok], c1["maps"]["dom"][ok])
+    np.testing.assert_allclose(c1["st"]["t_final"][ok], c1["maps"]["T"][ok], rtol=1e-4, atol=1e-6)
+    # the last contributor's id matches
+    st = c1["st"]
+    has = ok & (st["n_contrib"] > 0)
+    lastid = st["vals"][st["last"][has]]
+    np.testing.assert_array_equal(lastid, c1["maps"]["last"][has])
+
+
+def test_c1_error_map_fused_in_render(c1):
+    st = c1["st"]
+    e = np.abs(c1["img"].astype(np.float64) - c1["gt"].astype(np.float64))
+    want = (e[0] + e[1]) + e[2]
+    np.testing.assert_array_equal(st["err"], want)
+    assert st["err_minmax"][0] == want.min().view(np.uint64) and st["err_minmax"][1] == want.max().view(np.uint64)
+
+
+def _grad_compare(gr, gref, exclude=None, tol=1e-3):
+    out = {}
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        a = getattr(gr, name).cpu().numpy().astype(np.float64)
+        b = gref[name]
+        if exclude is not None:
+            a = a[..., ~exclude]
+            b = b[..., ~exclude]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        rms = np.sqrt((b ** 2).mean()) if b.size else 0.0
+        elem = np.abs(a - b) <= tol * (np.abs(b) + rms) + 1e-12
+        out[name] = (rel, elem.mean())
+        assert rel <= tol, (name, rel)
+        assert elem.mean() >= 0.999, (name, elem.mean())
+    return out
+
+
+def test_c1_backward_matches_oracle(ctx, c1):
+    rng = np.random.default_rng(5)
+    cam = c1["cam"]
+    G = rng.normal(size=(3, cam.height, cam.width)).astype(np.float32)
+    say("c1: backward on the GPU")
+    grads = api.render_backward(ctx, c1["g"], cam, c1["frame"], torch.from_numpy(G).cuda())
+    torch.cuda.synchronize()
+    pr = c1["pr"]
+    pix = oracle.all_pixels(cam.width, cam.height)
+    g2d = oracle.render_backward_pixels(pr, pix, G.transpose(1, 2, 0).reshape(-1, 3).astype(np.float64))
+    gref = oracle.project_backward(c1["scene"], cam, g2d)
+    # Gaussians that touch a flagged pixel can legitimately differ
+    flagged = np.zeros(pr.n, bool)
+    fy, fx = np.nonzero(c1["maps"]["flag"])
+    for x, y in zip(fx, fy):
+        b = pr.box
+        flagged |= (pr.valid == 1) & (b[:, 0] <= x) & (x <= b[:, 2]) & (b[:, 1] <= y) & (y <= b[:, 3])
+    say("c1: %d Gaussians touch flagged pixels" % flagged.sum())
+    res = _grad_compare(grads, gref, exclude=flagged)
+    say("c1 gradients: " + ", ".join("%s %.2e" % (k, v[0]) for k, v in res.items()))
+
+
+def test_backward_accumulates_adc_statistic(ctx, c1):
+    cam = c1["cam"]
+    G = np.random.default_rng(6).normal(size=(3, cam.height, cam.width)).astype(np.float32)
+    n = c1["g"].n
+    acc = torch.zeros(n, dtype=torch.float32, device="cuda")
+    cnt = torch.zeros(n, dtype=torch.int32, device="cuda")
+    api.render(ctx, c1["g"], cam, c1["frame"])
+    api.render_backward(ctx, c1["g"], cam, c1["frame"], torch.from_numpy(G).cuda(), g2d_norm=acc, vis_count=cnt)
+    api.render_backward(ctx, c1["g"], cam, c1["frame"], torch.from_numpy(G).cuda(), g2d_norm=acc, vis_count=cnt)
+    torch.cuda.synchronize()
+    st = c1["frame"].host_state(n)
+    v = st["ntiles"] > 0
+    np.testing.assert_array_equal(cnt.cpu().numpy(), 2 * v.astype(np.int32))
+    g2d = c1["frame"].view()
+    pr = c1["pr"]
+    pix = oracle.all_pixels(cam.width, cam.height)
+    ref = oracle.render_backward_pixels(pr, pix, G.transpose(1, 2, 0).reshape(-1, 3).astype(np.float64))
+    want = 2 * np.linalg.norm(ref["mean2d"], axis=1)
+    a = acc.cpu().numpy()
+    assert np.linalg.norm(a - want) <= 2e-3 * np.linalg.norm(want)
+    del g2d
+
+
+# ---- edge cases ---------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,H", [(1, 1), (17, 5), (33, 47), (130, 70)])
+def test_ragged_image_sizes(ctx, W, H):
+    scene = synth.scene_uniform_sh0(400, seed=W * 131 + H)
+    cam = synth.look_at((0.2, -0.1, -3.5), (0.0, 0.0, 0.0), W, H, 60.0, bg=(0.3, 0.2, 0.1))
+    g, frame, img = gpu_render(ctx, scene, cam)
+    pr = oracle.project(scene, cam)
+    ref, maps = oracle.render_image(pr)
+    ok = maps["flag"] == 0
+    assert np.abs(img.astype(np.float64) - ref)[:, ok].max() <= 1e-4
+    st = frame.host_state(g.n)
+    keys, vals, ranges = oracle.bin_tiles(pr, 16, 16)
+    np.testing.assert_array_equal(st["keys"], keys)
+    np.testing.assert_array_equal(st["vals"], vals)
+    np.testing.assert_array_equal(st["ranges"], ranges)
+
+
+def test_everything_culled_and_empty_tiles(ctx):
+    scene = synth.scene_uniform_sh0(50, seed=3)
+    scene.means[2] = -10.0          # all behind the camera
+    cam = synth.look_at((0.0, 0.0, -4.0), (0.0, 0.0, 0.0), 48, 32, 60.0, bg=(0.25, 0.5, 0.75))
+    g, frame, img = gpu_render(ctx, scene, cam)
+    st = frame.host_state(g.n)
+    assert st["n_keys"] == 0 and (st["ranges"] == 0).all()
+    np.testing.assert_array_equal(img, np.broadcast_to(cam.bg.reshape(3, 1, 1), img.shape))
+    assert (st["dom"] == -1).all() and (st["t_final"] == 1).all()
+
+
+def test_key_capacity_growth(ctx):
+    scene, cam, gt = synth.c1_inputs(seed=21)
+    g, frame, img = gpu_render(ctx, scene, cam, key_cap=16)   # far too small: the render grows it
+    pr = oracle.project(scene, cam)
+    keys, vals, ranges = oracle.bin_tiles(pr, 16, 16)
+    st = frame.host_state(g.n)
+    np.testing.assert_array_equal(st["keys"], keys)
+    assert frame.view().key_cap >= len(keys)
+
+
+def test_bad_arguments_are_rejected(ctx):
+    scene, cam, _ = synth.c1_inputs()
+    g = api.Gaussians.from_scene(scene)
+    frame = api.Frame(ctx, g.n, 64, 64)
+    with pytest.raises(api.AdpSplitError) as e:
+        api.render(ctx, g, cam, frame)          # camera is 128x128
+    assert e.value.status == api.AS_ERR_ARG
+    small = api.Frame(ctx, 10, cam.width, cam.height)
+    with pytest.raises(api.AdpSplitError) as e:
+        api.render(ctx, g, cam, small)
+    assert e.value.status == api.AS_ERR_CAPACITY
+    fresh = api.Frame(ctx, g.n, cam.width, cam.height)
+    with pytest.raises(api.AdpSplitError) as e:
+        api.render_backward(ctx, g, cam, fresh, torch.zeros(3, 128, 128, device="cuda"))
+    assert e.value.status == api.AS_ERR_STATE
+
+
+# ---- C2: 1,000,000 Gaussians, 1256x828, SH 3 (the benchmark's launch) ---------------------
+
+@pytest.fixture(scope="module")
+def c2(ctx):
+    scene, cam, gt = synth.c2_inputs()
+    say("c2: render on the GPU")
+    g, frame, img = gpu_render(ctx, scene, cam, gt)
+    st = frame.host_state(g.n)
+    say("c2: %d pairs; oracle projection" % st["n_keys"])
+    pr = oracle.project(scene, cam)
+    return dict(scene=scene, cam=cam, gt=gt, g=g, frame=frame, img=img, st=st, pr=pr)
+
+
+def test_c2_projection_decisions(c2):
+    check_projection(c2["pr"], c2["st"], c2["g"].n)
+
+
+def test_c2_binning_bit_exact(c2):
+    say("c2: oracle binning")
+    keys, vals, ranges = oracle.bin_tiles(c2["pr"], 16, 16)
+    st = c2["st"]
+    assert st["n_keys"] == len(keys)
+    np.testing.assert_array_equal(st["keys"], keys)
+    np.testing.assert_array_equal(st["vals"], vals)
+    np.testing.assert_array_equal(st["ranges"], ranges)
+
+
+def _sample_pixels(W, H, n, seed):
+    rng = np.random.default_rng(seed)
+    pix = np.stack([rng.integers(0, W, n), rng.integers(0, H, n)], 1)
+    # include the ragged last tile row/column and the corners
+    extra = np.array([[0, 0], [W - 1, H - 1], [W - 1, 0], [0, H - 1], [W - 5, H - 3]])
+    return np.concatenate([pix, extra]).astype(np.int32)
+
+
+def test_c2_sampled_pixels(c2):
+    cam = c2["cam"]
+    pix = _sample_pixels(cam.width, cam.height, 400, 1)
+    say("c2: oracle on %d sampled pixels" % len(pix))
+    r = oracle.render_pixels(c2["pr"], pix)
+    ok = r["flag"] == 0
+    got = c2["img"][:, pix[:, 1], pix[:, 0]].T.astype(np.float64)
+    assert np.abs(got - r["color"])[ok].max() <= 1e-4
+    st = c2["st"]
+    np.testing.assert_array_equal(st["n_contrib"][pix[:, 1], pix[:, 0]][ok], r["ncontrib"][ok])
+    np.testing.assert_array_equal(st["dom"][pix[:, 1], pix[:, 0]][ok], r["dom"][ok])
+    say("c2: flagged %d of %d; mean pairs per pixel %.1f" % ((~ok).sum(), len(ok), r["pairs"].mean()))
+
+
+def test_c2_backward_sparse_upstream(ctx, c2):
+    """Upstream gradient nonzero only at sampled pixels: every Gaussian's
+    gradient is then a sum the oracle can form pixel by pixel."""
+    cam = c2["cam"]
+    pix = _sample_pixels(cam.width, cam.height, 300, 2)
+    pix = np.unique(pix, axis=0)
+    rng = np.random.default_rng(3)
+    Gs = rng.normal(size=(len(pix), 3))
+    G = np.zeros((3, cam.height, cam.width), np.float32)
+    G[:, pix[:, 1], pix[:, 0]] = Gs.T.astype(np.float32)
+    grads = api.render_backward(ctx, c2["g"], cam, c2["frame"], torch.from_numpy(G).cuda())
+    torch.cuda.synchronize()
+    r = oracle.render_pixels(c2["pr"], pix)
+    keep = r["flag"] == 0
+    say("c2: oracle backward at %d pixels" % keep.sum())
+    g2d = oracle.render_backward_pixels(c2["pr"], pix[keep], G[:, pix[keep, 1], pix[keep, 0]].T.astype(np.float64))
+    gref = oracle.project_backward(c2["scene"], cam, g2d)
+    # flagged pixels' Gaussians are excluded from the comparison
+    flagged = np.zeros(c2["pr"].n, bool)
+    b = c2["pr"].box
+    for x, y in pix[~keep]:
+        flagged |= (c2["pr"].valid == 1) & (b[:, 0] <= x) & (x <= b[:, 2]) & (b[:, 1] <= y) & (y <= b[:, 3])
+    res = _grad_compare(grads, gref, exclude=flagged)
+    say("c2 gradients: " + ", ".join("%s %.2e" % (k, v[0]) for k, v in res.items()))

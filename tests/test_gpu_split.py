@@ -1,0 +1,261 @@
+"""HIP error statistics and adaptive split vs the CPU oracle through the C-ABI.
+
+Both sides get the same seeded inputs (synthetic error maps, scenes, cameras,
+standard normals); neither consumes the other's output.  Bars: region set,
+integer moments, attribution counts, modes, counts, offsets and output row
+order bit-exact; region statistics relative <= 1e-5; child parameters
+relative <= 1e-5 (covariances compared, quaternion sign free)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_06876_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2605_06876_amd import api  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return api.Context(0)
+
+
+def gpu_error_stats(ctx, img, gt, dom, is_cand, view, prm, regions, attr):
+    H, W = dom.shape
+    it = torch.from_numpy(img).cuda()
+    gtt = torch.from_numpy(gt).cuda()
+    err, mm = api.error_map(ctx, it, gtt)
+    api.accumulate_error_stats(ctx, W, H, err, mm, torch.from_numpy(dom).cuda(), gtt, view,
+                               torch.from_numpy(is_cand).cuda(), prm, regions, attr)
+    return err, mm
+
+
+def gparams(o):
+    return api.SplitParams(o.tau_l1, o.r_erode, o.m_min, o.L, o.n_max, o.gamma_d, o.gamma_c, o.eps, o.eta)
+
+
+def compare_regions(got, want):
+    assert len(got) == len(want), (len(got), len(want))
+    for f in ("cand", "view", "label", "area", "band", "sx", "sy", "sxx", "sxy", "syy"):
+        np.testing.assert_array_equal(got[f], want[f], err_msg=f)
+    for f in ("cx", "cy", "cov", "e1", "sigma1", "sigma2"):
+        np.testing.assert_array_equal(got[f], want[f], err_msg=f)   # same FP64 ops: identical bits
+    np.testing.assert_array_equal(got["rgb"].astype(np.float64), want["rgb"])
+
+
+@pytest.mark.parametrize("H,W,n,seed,r", [(96, 128, 40, 1, 2), (200, 333, 300, 2, 1), (64, 64, 5, 3, 0),
+                                          (828, 1256, 5000, 4, 2)])
+def test_error_stats_bit_exact(ctx, H, W, n, seed, r):
+    img, gt, dom, is_cand = synth.error_map_fixture(H, W, n, seed=seed, n_sites=max(50, H * W // 800),
+                                                    n_blobs=max(30, H * W // 2000))
+    prm = oracle.SplitParams(r_erode=r)
+    attr_o = np.zeros(n, np.int32)
+    want, maps = oracle.error_stats(img, gt, dom, is_cand, 3, prm, attr_o)
+    regions = api.RegionBuffer(max(16, H * W // 5))
+    attr_g = torch.zeros(n, dtype=torch.int32, device="cuda")
+    err, mm = gpu_error_stats(ctx, img, gt, dom, is_cand, 3, gparams(prm), regions, attr_g)
+    torch.cuda.synchronize()
+    got = regions.host()
+    say("%dx%d: %d regions, %d attributed pixels" % (W, H, len(want), attr_o.sum()))
+    compare_regions(got, want)
+    np.testing.assert_array_equal(attr_g.cpu().numpy(), attr_o)
+
+
+def test_error_stats_degenerate_maps(ctx):
+    # constant error: no high-error pixels at all
+    H, W, n = 40, 50, 3
+    dom = np.zeros((H, W), np.int32)
+    img = np.full((3, H, W), 0.5, np.float32)
+    gt = np.zeros_like(img)
+    regions = api.RegionBuffer(100)
+    attr = torch.zeros(n, dtype=torch.int32, device="cuda")
+    gpu_error_stats(ctx, img, gt, dom, np.ones(n, np.uint8), 0, api.SplitParams(), regions, attr)
+    torch.cuda.synchronize()
+    assert regions.host().shape[0] == 0 and attr.sum().item() == 0
+    # no candidates: attribution stays zero, no regions
+    img, gt, dom, _ = synth.error_map_fixture(H, W, n, seed=9)
+    regions.reset()
+    gpu_error_stats(ctx, img, gt, dom, np.zeros(n, np.uint8), 0, api.SplitParams(), regions, attr)
+    torch.cuda.synchronize()
+    assert regions.host().shape[0] == 0 and attr.sum().item() == 0
+
+
+def test_region_buffer_overflow_is_reported(ctx):
+    img, gt, dom, is_cand = synth.error_map_fixture(120, 160, 40, seed=8, n_blobs=120)
+    prm = oracle.SplitParams(m_min=1, r_erode=0)
+    want, _ = oracle.error_stats(img, gt, dom, is_cand, 0, prm, np.zeros(40, np.int32))
+    regions = api.RegionBuffer(3)
+    gpu_error_stats(ctx, img, gt, dom, is_cand, 0, gparams(prm), regions, torch.zeros(40, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    assert regions.count.item() == len(want) > 3
+    with pytest.raises(api.AdpSplitError):
+        regions.host()
+
+
+def views_for(k, W, H, seed):
+    return synth.sphere_cameras(k, 4.0, [(W, H)], seed=seed)
+
+
+def run_both_split(ctx, scene, views, maps_per_view, is_cand, prm, seed):
+    n = scene.n
+    attr_o = np.zeros(n, np.int32)
+    regs_o = []
+    regions = api.RegionBuffer(sum(m[2].size for m in maps_per_view) // 5 + 16)
+    attr_g = torch.zeros(n, dtype=torch.int32, device="cuda")
+    for v, (img, gt, dom) in enumerate(maps_per_view):
+        r, _ = oracle.error_stats(img, gt, dom, is_cand, v, prm, attr_o)
+        regs_o.append(r)
+        gpu_error_stats(ctx, img, gt, dom, is_cand, v, gparams(prm), regions, attr_g)
+    regs_o = np.concatenate(regs_o) if regs_o else np.zeros(0, oracle.REGION_DTYPE)
+    cand = np.nonzero(is_cand)[0].astype(np.int32)
+    noise = synth.vanilla_noise(len(cand), seed)
+    want = oracle.adaptive_split(scene, cand, regs_o, views, attr_o, prm, noise)
+    g = api.Gaussians.from_scene(scene)
+    out, mode, count, offset, n_out = api.adaptive_split(ctx, g, torch.from_numpy(cand).cuda(), regions, views, attr_g,
+                                                         gparams(prm), torch.from_numpy(noise).cuda())
+    torch.cuda.synchronize()
+    return want, (out, mode.cpu().numpy(), count.cpu().numpy(), offset.cpu().numpy(), int(n_out.item())), attr_o
+
+
+def cov_from(q, ls):
+    q = q / np.linalg.norm(q, axis=0, keepdims=True)
+    w, x, y, z = q
+    R = np.stack([np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)]),
+                  np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)]),
+                  np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)])])  # [3,3,n]
+    s2 = np.exp(2 * ls)
+    return np.einsum("ikn,kn,jkn->ijn", R, s2, R)
+
+
+def compare_split(want, got):
+    out, mode, count, offset, n_out = got
+    np.testing.assert_array_equal(mode, want["mode"])
+    np.testing.assert_array_equal(count, want["count"])
+    np.testing.assert_array_equal(offset, want["offset"])
+    assert n_out == want["n_out"]
+    m = out.means[:, :n_out].cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(m, want["means"], rtol=1e-5, atol=1e-6)
+    ls = out.log_scales[:, :n_out].cpu().numpy().astype(np.float64)
+    q = out.quats[:, :n_out].cpu().numpy().astype(np.float64)
+    Cg = cov_from(q, ls)
+    Co = cov_from(want["quats"].astype(np.float64), want["log_scales"].astype(np.float64))
+    scale = np.abs(Co).max(axis=(0, 1)) + 1e-30
+    assert (np.abs(Cg - Co).max(axis=(0, 1)) <= 1e-5 * scale).all()
+    np.testing.assert_allclose(out.opacity_logits[:n_out].cpu().numpy(), want["opacity_logits"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(out.sh[:, :, :n_out].cpu().numpy(), want["sh"], rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_split_on_synthetic_maps(ctx, seed):
+    H, W, n, V = 120, 160, 60, 4
+    scene = synth.scene_uniform_sh0(n, seed=seed)
+    views = views_for(V, W, H, seed)
+    maps = []
+    rng = np.random.default_rng(seed)
+    is_cand = (rng.uniform(size=n) < 0.5).astype(np.uint8)
+    for v in range(V):
+        img, gt, dom, _ = synth.error_map_fixture(H, W, n, seed=seed * 100 + v, n_sites=60, n_blobs=80)
+        maps.append((img, gt, dom))
+    want, got, attr = run_both_split(ctx, scene, views, maps, is_cand, oracle.SplitParams(), seed)
+    say("modes: vanilla %d reset %d adaptive %d; new rows %d" % ((want["mode"] == 0).sum(), (want["mode"] == 1).sum(),
+                                                               (want["mode"] == 2).sum(), want["count"].sum()))
+    assert (want["mode"] == 2).sum() > 0
+    compare_split(want, got)
+
+
+def test_split_merges_across_views_and_caps(ctx):
+    """Many views of the same dominant maps: proposals coincide across views and
+    merge; small N_max forces the cap; one candidate never dominates (vanilla)."""
+    H, W, n, V = 96, 128, 12, 6
+    scene = synth.scene_uniform_sh0(n, seed=5)
+    views = views_for(V, W, H, 5)
+    img, gt, dom, _ = synth.error_map_fixture(H, W, n - 1, seed=77, n_sites=40, n_blobs=120)
+    maps = [(img, gt, dom)] * V
+    is_cand = np.ones(n, np.uint8)
+    prm = oracle.SplitParams(n_max=3, gamma_d=4.0, gamma_c=0.3, r_erode=1)
+    want, got, attr = run_both_split(ctx, scene, views, maps, is_cand, prm, 5)
+    assert want["mode"][n - 1] == 0 and (want["count"] <= 4).all()
+    compare_split(want, got)
+
+
+def test_split_without_regions_or_candidates(ctx):
+    scene = synth.scene_uniform_sh0(20, seed=2)
+    g = api.Gaussians.from_scene(scene)
+    regions = api.RegionBuffer(8)
+    cand = np.array([1, 4, 9], np.int32)
+    attr = np.zeros(20, np.int32)
+    attr[4] = 7
+    noise = synth.vanilla_noise(3, 0)
+    prm = oracle.SplitParams()
+    want = oracle.adaptive_split(scene, cand, np.zeros(0, oracle.REGION_DTYPE), [], attr, prm, noise)
+    out = api.adaptive_split(ctx, g, torch.from_numpy(cand).cuda(), regions, [], torch.from_numpy(attr).cuda(),
+                             gparams(prm), torch.from_numpy(noise).cuda())
+    torch.cuda.synchronize()
+    compare_split(want, (out[0], out[1].cpu().numpy(), out[2].cpu().numpy(), out[3].cpu().numpy(), int(out[4].item())))
+    # no candidates at all: the set is copied unchanged
+    empty = np.zeros(0, np.int32)
+    want = oracle.adaptive_split(scene, empty, np.zeros(0, oracle.REGION_DTYPE), [], attr, prm, np.zeros((0, 2, 3), np.float32))
+    out = api.adaptive_split(ctx, g, torch.zeros(0, dtype=torch.int32, device="cuda"), regions, [],
+                             torch.from_numpy(attr).cuda(), gparams(prm), torch.zeros(0, device="cuda"))
+    torch.cuda.synchronize()
+    assert int(out[4].item()) == want["n_out"] == 20
+    np.testing.assert_array_equal(out[0].means[:, :20].cpu().numpy(), scene.means)
+
+
+def test_split_rejects_small_output(ctx):
+    scene = synth.scene_uniform_sh0(20, seed=2)
+    g = api.Gaussians.from_scene(scene)
+    small = api.Gaussians.empty(21, 0)
+    with pytest.raises(api.AdpSplitError) as e:
+        api.adaptive_split(ctx, g, torch.tensor([1], dtype=torch.int32, device="cuda"), api.RegionBuffer(4), [],
+                           torch.zeros(20, dtype=torch.int32, device="cuda"), api.SplitParams(),
+                           torch.zeros(1, 2, 3, device="cuda"), out=small)
+    assert e.value.status == api.AS_ERR_CAPACITY
+
+
+def test_densify_step_end_to_end_on_renders(ctx):
+    """Render -> fused error map -> error statistics -> split on the GPU, and the
+    oracle's own render -> error statistics -> split.  FP32 vs FP64 renders may
+    move pixels across the error threshold, so the comparison is statistical:
+    modes agree for nearly all candidates and the region counts are close."""
+    n, W, H, V = 3000, 160, 120, 3
+    scene = synth.scene_clusters(n, seed=31, sh_degree=1, log_scale_mu=-3.6, log_scale_sd=0.5)
+    views = views_for(V, W, H, 31)
+    gts = [synth.smooth_image(H, W, 40 + v) for v in range(V)]
+    is_cand = np.zeros(n, np.uint8)
+    is_cand[np.random.default_rng(1).permutation(n)[: n // 10]] = 1
+    prm = oracle.SplitParams()
+    g = api.Gaussians.from_scene(scene)
+    frame = api.Frame(ctx, n, W, H)
+    regions = api.RegionBuffer(V * W * H // 5)
+    attr_g = torch.zeros(n, dtype=torch.int32, device="cuda")
+    attr_o = np.zeros(n, np.int32)
+    regs_o = []
+    for v, (cam, gt) in enumerate(zip(views, gts)):
+        gtt = torch.from_numpy(gt).cuda()
+        api.render(ctx, g, cam, frame, gt=gtt)
+        dm = frame.device_maps()
+        api.accumulate_error_stats(ctx, W, H, dm["err"], dm["err_minmax"], dm["dom"], gtt, v,
+                                   torch.from_numpy(is_cand).cuda(), gparams(prm), regions, attr_g)
+        img_o, maps = oracle.render_image(oracle.project(scene, cam))
+        r, _ = oracle.error_stats(img_o.astype(np.float32), gt, maps["dom"].astype(np.int32), is_cand, v, prm, attr_o)
+        regs_o.append(r)
+    torch.cuda.synchronize()
+    regs_g = regions.host()
+    regs_o = np.concatenate(regs_o)
+    say("end to end: %d GPU regions, %d oracle regions" % (len(regs_g), len(regs_o)))
+    assert abs(len(regs_g) - len(regs_o)) <= max(2, 0.02 * len(regs_o))
+    ag = attr_g.cpu().numpy()
+    assert np.abs(ag - attr_o).sum() <= max(5, 0.01 * attr_o.sum())
