@@ -1,0 +1,335 @@
+#!/usr/bin/env python3
+"""Throughput of the HIP rasterizer + AdpSplit path on one MI355X.
+
+Workload (the metric's configuration): 1,000,000 clustered Gaussians, SH
+degree 3, FP32, one 1256x828 view.  One step = forward render with the fused
+L1 error map, the error-region statistics of the view (5% of the Gaussians
+are split candidates), and the backward pass for a fixed synthetic upstream
+gradient.  All inputs are seeded, synthetic and resident in HBM before the
+timed region.  Also reported: the densification step (500,000 Gaussians, 16
+views, top-5% candidates, adaptive split) and the CPU oracle on a bounded
+sample of the same workload.
+
+Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only),
+--no-cpu-baseline, --no-densify.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+# VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one
+# non-packed FP32 op per lane per clock; transcendentals at a quarter rate)
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# Algorithmic VALU lane-ops per (pixel, Gaussian) pair, counted from the
+# formulas (add/sub/mul/fma/min/compare/select = 1, exp = 4 at quarter rate):
+# forward: offset 2, exponent 9, exp 4, alpha 2, alpha test 1, transmittance 2,
+# stop test 1, weight 1, colour 3, dominant test+select 3  -> 28
+# backward: the forward's 17 up to the transmittance, restore T 1 (division
+# as reciprocal+mul: 4+1), colour grads 3, accumulators 9, dL/dalpha 6+1,
+# background term 3, opacity/exponent grads 2, mean grads 6, conic grads 6 -> 59
+OPS_FWD_PER_PAIR = 28
+OPS_BWD_PER_PAIR = 59
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-densify", action="store_true")
+    ap.add_argument("--json", default="", help="also write the JSON line to this file")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sh3_bytes():
+    return 4 * (3 + 3 + 4 + 1 + 48)
+
+
+def training_step_bench(args):
+    import numpy as np
+    import torch
+
+    from paper_2605_06876_amd import api, synth
+
+    api.lib()   # raises if the HIP library is missing: no fallback
+    torch.cuda.set_device(0)
+    log("bench: generating the 1M-Gaussian workload")
+    scene, cam, gt = synth.c2_inputs()
+    n, W, H = scene.n, cam.width, cam.height
+    ctx = api.Context(0)
+    g = api.Gaussians.from_scene(scene)
+    gtt = torch.from_numpy(gt).cuda()
+    G = torch.from_numpy(np.random.default_rng(7).normal(0.0, 1.0 / (3 * W * H), (3, H, W)).astype(np.float32)).cuda()
+    rng = np.random.default_rng(8)
+    is_cand = torch.from_numpy((rng.uniform(size=n) < 0.05).astype(np.uint8)).cuda()
+    params = api.SplitParams()
+    regions = api.RegionBuffer(W * H // params.m_min + 1)
+    attr = torch.zeros(n, dtype=torch.int32, device="cuda")
+    g2d = torch.zeros(n, dtype=torch.float32, device="cuda")
+    vis = torch.zeros(n, dtype=torch.int32, device="cuda")
+    frame = api.Frame(ctx, n, W, H, key_cap=16 * n)
+    image = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
+    grads = api.Gaussians.empty(n, scene.sh_degree)
+    dm = frame.device_maps()
+
+    def step():
+        regions.count.zero_()
+        api.render(ctx, g, cam, frame, gt=gtt, image=image)
+        api.accumulate_error_stats(ctx, W, H, dm["err"], dm["err_minmax"], dm["dom"], gtt, 0, is_cand, params,
+                                   regions, attr)
+        api.render_backward(ctx, g, cam, frame, G, grads=grads, g2d_norm=g2d, vis_count=vis)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    api.timing_enable(ctx, True)
+    api.timing_read(ctx)
+    log("bench: timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = api.timing_read(ctx)
+    api.timing_enable(ctx, False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    K = frame.n_keys()
+    n_regions = int(regions.count.item())
+    return dict(ms=ms, stages=stages, K=K, n=n, W=W, H=H, n_regions=n_regions, steps=args.steps, ctx=ctx)
+
+
+def densify_bench(ctx):
+    """500,000 Gaussians, 16 views of 1256x828, candidates = top 5% by the
+    view-averaged screen-space gradient norm (the split rule of Sec. 3 with
+    the gradient threshold set by rank), then AdpSplit."""
+    import numpy as np
+    import torch
+
+    from paper_2605_06876_amd import api, synth
+
+    n, W, H, V = 500_000, 1256, 828, 16
+    scene = synth.scene_clusters(n, 1003, 3)
+    views = synth.sphere_cameras(V, 4.0, [(W, H)], seed=1003)
+    gts = [torch.from_numpy(synth.smooth_image(H, W, 2000 + v)).cuda() for v in range(V)]
+    g = api.Gaussians.from_scene(scene)
+    frame = api.Frame(ctx, n, W, H, key_cap=16 * n)
+    image = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
+    g2d = torch.zeros(n, dtype=torch.float32, device="cuda")
+    vis = torch.zeros(n, dtype=torch.int32, device="cuda")
+    grads = api.Gaussians.empty(n, 3)
+    # ADC statistic from 16 backward passes of the L1 loss (untimed set-up)
+    for cam, gt in zip(views, gts):
+        api.render(ctx, g, cam, frame, gt=gt, image=image)
+        dL = torch.sign(image - gt) / (3 * W * H)
+        api.render_backward(ctx, g, cam, frame, dL.contiguous(), grads=grads, g2d_norm=g2d, vis_count=vis)
+    gi = (g2d / vis.clamp(min=1)).cpu().numpy()
+    order = np.lexsort((np.arange(n), -gi))
+    cand = np.sort(order[: n // 20]).astype(np.int32)
+    is_cand = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    is_cand[torch.from_numpy(cand.astype(np.int64)).cuda()] = 1
+    cand_t = torch.from_numpy(cand).cuda()
+    noise = torch.from_numpy(synth.vanilla_noise(len(cand), 5)).cuda()
+    params = api.SplitParams()
+    regions = api.RegionBuffer(V * W * H // params.m_min // 4)
+    attr = torch.zeros(n, dtype=torch.int32, device="cuda")
+    out = api.Gaussians.empty(n + len(cand) * (params.n_max + 1), 3)
+    dm = frame.device_maps()
+
+    def densify():
+        regions.count.zero_()
+        attr.zero_()
+        for v, (cam, gt) in enumerate(zip(views, gts)):
+            api.render(ctx, g, cam, frame, gt=gt, image=image)
+            api.accumulate_error_stats(ctx, W, H, dm["err"], dm["err_minmax"], dm["dom"], gt, v, is_cand, params,
+                                       regions, attr)
+        return api.adaptive_split(ctx, g, cand_t, regions, views, attr, params, noise, out=out)
+
+    densify()
+    torch.cuda.synchronize()
+    api.timing_enable(ctx, True)
+    api.timing_read(ctx)
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = densify()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = api.timing_read(ctx)
+    api.timing_enable(ctx, False)
+    mode = res[1].cpu().numpy()
+    return dict(ms=(t1 - t0) * 1e3 / reps, n=n, views=V, candidates=len(cand), regions=int(regions.count.item()),
+                new_rows=int(res[2].sum().item()), n_out=int(res[4].item()),
+                modes=dict(vanilla=int((mode == 0).sum()), reset=int((mode == 1).sum()), adaptive=int((mode == 2).sum())),
+                stage_ms={k: round(v[0] / reps, 4) for k, v in st.items() if v[1]})
+
+
+def cpu_baseline(W_rows=48):
+    """The CPU oracle on a bounded sample of the same workload: projection of all
+    1M Gaussians, forward + backward compositing of a band of W_rows image rows,
+    reverse projection of all Gaussians; the band's per-pixel cost is scaled to
+    the whole image.  Returns the figures and the total algorithmic pair count
+    of the band."""
+    import numpy as np
+
+    import oracle
+    from paper_2605_06876_amd import synth
+
+    scene, cam, gt = synth.c2_inputs()
+    W, H = cam.width, cam.height
+    y0 = H // 2 - W_rows // 2
+    t0 = time.perf_counter()
+    pr = oracle.project(scene, cam)
+    t1 = time.perf_counter()
+    Gb = np.random.default_rng(7).normal(0.0, 1.0 / (3 * W * H), (W_rows * W, 3))
+    r = oracle.render_rows(pr, y0, y0 + W_rows, dL_dcolor=Gb)
+    t2 = time.perf_counter()
+    oracle.project_backward(scene, cam, r["grad"])
+    t3 = time.perf_counter()
+    full = (t1 - t0) + (t2 - t1) * (H / W_rows) + (t3 - t2)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return dict(value=round(W * H / full / 1e6, 5), unit="Mpix/s", cores=threads, kind="oracle",
+                sample="rows %d-%d of the 1256x828 view (%d px, fwd+bwd compositing) + projection and reverse "
+                       "projection of all 1,000,000 Gaussians; band cost scaled by %d/%d rows; %.1f s measured"
+                       % (y0, y0 + W_rows, W_rows * W, H, W_rows, t3 - t0),
+                seconds_full_image_estimate=round(full, 2), band_pairs_per_px=round(float(r["pairs"].mean()), 2))
+
+
+def load_workload_constants():
+    path = os.path.join(ROOT, "tests", "golden", "c2_workload.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+KERNEL_SOURCES = {
+    "project": "project.hip", "scan": "binning.hip", "emit": "binning.hip", "sort": "binning.hip",
+    "ranges": "binning.hip", "blend_fwd": "blend.hip", "blend_bwd": "blend.hip", "project_bwd": "project_bwd.hip",
+    "error_stats": "errstats.hip",
+}
+
+
+def source_hash(stage):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2605_06876_amd", "csrc", KERNEL_SOURCES[stage])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's counters), or None
+    when there is none or the kernel's source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f).get(stage)
+    if not tr or tr.get("source_sha256_16") != source_hash(stage):
+        return None
+    return tr.get("bytes_per_launch")
+
+
+def main():
+    args = _args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'Sharding'). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    res = training_step_bench(args)
+    consts = load_workload_constants()
+    P_alg = consts["pairs"]
+    n, W, H, K = res["n"], res["W"], res["H"], res["K"]
+    st = {k: (v[0] / max(v[1], 1), v[1]) for k, v in res["stages"].items()}
+    per_step = {k: v[0] for k, v in st.items() if v[1]}
+    # algorithmic work per launch of each stage
+    work = {
+        "project": ("hbm", n * (sh3_bytes() + 64) / 1e9, "GB"),
+        "scan": ("hbm", n * 8 / 1e9, "GB"),
+        "emit": ("hbm", (n * 16 + K * 12) / 1e9, "GB"),
+        "sort": ("hbm", K * 24 / 1e9, "GB"),
+        "ranges": ("hbm", (K * 8 + 8 * ((W + 15) // 16) * ((H + 15) // 16)) / 1e9, "GB"),
+        "blend_fwd": ("alu", P_alg * OPS_FWD_PER_PAIR / 1e12, "TOP"),
+        "blend_bwd": ("alu", P_alg * OPS_BWD_PER_PAIR / 1e12, "TOP"),
+        "project_bwd": ("hbm", n * (2 * sh3_bytes() + 36 + 4 + 16) / 1e9, "GB"),
+        "error_stats": ("hbm", W * H * 30 / 1e9, "GB"),
+    }
+    dom_stage = max((k for k in per_step if k in work), key=lambda k: per_step[k])
+    bound, amount, u = work[dom_stage]
+    t = per_step[dom_stage] / 1e3
+    if bound == "hbm":
+        roof = dict(bound="hbm", achieved=round(amount / t, 1), peak=PEAK_HBM_GBS, unit="GB/s")
+    else:
+        roof = dict(bound="alu", achieved=round(amount / t, 3), peak=round(PEAK_VALU_TOPS, 2), unit="TOP/s")
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["kernel"] = dom_stage
+    roof["avg_ms"] = round(per_step[dom_stage], 4)
+    roof["traffic"] = measured_traffic(dom_stage)
+    all_roofs = {}
+    for k, (b, amt, unit) in work.items():
+        if k in per_step and per_step[k] > 0:
+            ach = amt / (per_step[k] / 1e3)
+            pk = PEAK_HBM_GBS if b == "hbm" else PEAK_VALU_TOPS
+            all_roofs[k] = dict(ms=round(per_step[k], 4), achieved=round(ach, 2),
+                                unit="GB/s" if b == "hbm" else "TOP/s", frac=round(ach / pk, 4))
+    mpix = W * H / 1e6
+    value = mpix / (res["ms"] / 1e3)
+    fb_ms = sum(per_step.get(k, 0.0) for k in ("project", "scan", "emit", "sort", "ranges", "blend_fwd", "blend_bwd",
+                                                "project_bwd"))
+    out = {
+        "metric": "fwd+bwd Mpix/s @1M Gaussians 1256x828",
+        "value": round(value, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded clustered scene, smooth synthetic target; the paper's datasets are unavailable)",
+        "config": {"workload": "training step: render + L1 error statistics (5% candidates) + backward, "
+                               "1,000,000 Gaussians SH3, one 1256x828 view",
+                   "gaussians": n, "width": W, "height": H, "sh_degree": 3, "pairs_tile": K, "pairs_alg": P_alg,
+                   "regions": res["n_regions"]},
+        "roofline": roof,
+        "stage_ms": {k: round(v, 4) for k, v in per_step.items()},
+        "stage_roofline": all_roofs,
+        "fwd_bwd_kernels_ms": round(fb_ms, 4),
+    }
+    if not args.no_densify:
+        log("bench: densification step (500k Gaussians, 16 views)")
+        out["densify"] = densify_bench(res["ctx"])
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"]["cpu_model"] = platform.processor() or platform.machine()
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.json:
+        with open(args.json, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -220,6 +220,34 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
                             as_gaussians_mut *out, uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out,
                             void *stream);
 
+/* ---- per-stage timing ------------------------------------------------------------ */
+
+/* Stages timed when timing is on (indices into as_timing_read's arrays). */
+enum {
+    AS_STAGE_PROJECT = 0,      /* projection, colour, depth key, box */
+    AS_STAGE_SCAN = 1,         /* exclusive scan of tiles per Gaussian */
+    AS_STAGE_EMIT = 2,         /* (tile | depth) key emission */
+    AS_STAGE_SORT = 3,         /* LSD radix sort of the keys */
+    AS_STAGE_RANGES = 4,       /* per-tile ranges */
+    AS_STAGE_BLEND_FWD = 5,    /* forward blend + dominant map + fused L1 error */
+    AS_STAGE_BLEND_BWD = 6,    /* reverse blend */
+    AS_STAGE_PROJECT_BWD = 7,  /* reverse projection */
+    AS_STAGE_ERROR_MAP = 8,    /* as_error_map */
+    AS_STAGE_ERROR_STATS = 9,  /* as_accumulate_error_stats */
+    AS_STAGE_SPLIT = 10,       /* as_adaptive_split */
+    AS_NUM_STAGES = 11
+};
+
+/* When `on` is nonzero, every stage above records a pair of hipEvents on the
+ * stream of the call that runs it, so its duration is measured on the stream
+ * its kernels use.  Costs one event pair per stage; off by default. */
+as_status as_timing_enable(as_ctx *ctx, int32_t on);
+
+/* Wait for the recorded events, add each stage's elapsed milliseconds to
+ * ms[AS_NUM_STAGES] and its number of runs to runs[AS_NUM_STAGES] (host
+ * arrays, zeroed by this call first), and forget the records. */
+as_status as_timing_read(as_ctx *ctx, double *ms, int64_t *runs);
+
 /* ---- test hooks --------------------------------------------------------------- */
 
 /* Stable LSD radix sort of n (key, value) pairs on the low key_bits bits, in

@@ -244,7 +244,7 @@ def adaptive_split(scene, cand, regions, cams, attr, params, noise, out_cap=None
     regions = np.ascontiguousarray(regions, dtype=REGION_DTYPE)
     camp = np.ascontiguousarray(np.stack([pack_camera(c) for c in cams]) if len(cams) else np.zeros((1, 21)))
     attr = _c(attr, np.int32)
-    noise = _c(noise, np.float32).reshape(max(nc, 1) * 6 if nc else 6)[: max(nc, 1) * 6]
+    noise = _c(noise, np.float32).reshape(nc * 6) if nc else np.zeros(6, np.float32)
     prm = np.array([params.gamma_d, params.gamma_c, params.eps, params.eta, params.n_max], np.float64)
     nk = (scene.sh_degree + 1) ** 2
     if out_cap is None:
@@ -293,3 +293,28 @@ def child_proposal(parent, region, cam, eps=1e-8):
     ok = lib().orc_child_proposal(_p(m), _p(s), _p(q), _p(o), _p(reg), _p(pack_camera(cam)), ctypes.c_double(eps),
                                   _p(mu), _p(R), _p(sc))
     return bool(ok), mu, R.reshape(3, 3), sc
+
+
+def render_rows(pr, y0=0, y1=None, dL_dcolor=None):
+    """Eq. (rendering) for every pixel of rows [y0, y1) (same arithmetic as
+    render_pixels, gathered per row).  With dL_dcolor [(y1-y0)*W, 3] the
+    reverse pass runs too and the 2D gradients are returned under "grad"."""
+    W = pr.width
+    y1 = pr.height if y1 is None else y1
+    npix = (y1 - y0) * W
+    out = dict(color=np.zeros((npix, 3)), T=np.zeros(npix), ncontrib=np.zeros(npix, np.int32),
+               dom=np.zeros(npix, np.int64), last=np.zeros(npix, np.int64), flag=np.zeros(npix, np.uint8),
+               pairs=np.zeros(npix, np.int64))
+    n = pr.n
+    gp = [None] * 4
+    gC = None
+    if dL_dcolor is not None:
+        gC = _c(dL_dcolor, np.float64).reshape(npix, 3)
+        out["grad"] = dict(mean2d=np.zeros((n, 2)), conic=np.zeros((n, 3)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
+        gp = [_p(out["grad"][k]) for k in ("mean2d", "conic", "opacity", "rgb")]
+    lib().orc_render_rows(ctypes.c_int64(n), _p(pr.valid), _p(pr.mean2d), _p(pr.conic), _p(pr.rgb), _p(pr.opacity),
+                          _p(pr.depth_key), _p(pr.box), _p(_c(pr.bg, np.float64)), ctypes.c_int(W), ctypes.c_int(y0),
+                          ctypes.c_int(y1), _p(out["color"]), _p(out["T"]), _p(out["ncontrib"]), _p(out["dom"]),
+                          _p(out["last"]), _p(out["flag"]), _p(out["pairs"]), _p(gC) if gC is not None else None,
+                          *gp)
+    return out

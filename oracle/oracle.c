@@ -1229,3 +1229,122 @@ int orc_child_proposal(const float *means, const float *log_scales, const float 
     memcpy(s, p.s, sizeof(p.s));
     return p.ok;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Eq. (rendering) for whole rows: for every pixel of rows [y0, y1), the      */
+/* Gaussians whose box holds the pixel, composited in ascending (depth key,   */
+/* id) order with exactly the arithmetic of render_pixel.  The set of         */
+/* candidates of a row is gathered once per row (Gaussians whose box spans   */
+/* it, kept in depth order), which is the same sequence render_pixel walks.   */
+/* When dL_dcolor is given, the reverse pass of each pixel follows, as in     */
+/* orc_render_backward_pixels, and is added into the 2D gradients.           */
+/* ------------------------------------------------------------------------ */
+void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, const double *conic, const double *rgb,
+                     const double *opacity, const uint32_t *depth_key, const int32_t *box, const double *bg, int W,
+                     int y0, int y1, double *color, double *Tfinal, int32_t *ncontrib, int64_t *dom, int64_t *last,
+                     uint8_t *flag, int64_t *pairs, const double *dL_dcolor, double *g_mean, double *g_conic,
+                     double *g_opac, double *g_rgb) {
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t m = depth_order(n, valid, depth_key, order);
+    if (dL_dcolor) {
+        memset(g_mean, 0, sizeof(double) * 2 * n);
+        memset(g_conic, 0, sizeof(double) * 3 * n);
+        memset(g_opac, 0, sizeof(double) * n);
+        memset(g_rgb, 0, sizeof(double) * 3 * n);
+    }
+#pragma omp parallel
+    {
+        int64_t *row = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+        /* per-pixel contributor lists for the reverse pass */
+        int64_t *cap = (int64_t *)calloc((size_t)W, sizeof(int64_t));
+        int64_t **lid = (int64_t **)calloc((size_t)W, sizeof(int64_t *));
+        double **lal = (double **)calloc((size_t)W, sizeof(double *));
+        double **lT = (double **)calloc((size_t)W, sizeof(double *));
+        double **lG = (double **)calloc((size_t)W, sizeof(double *));
+#pragma omp for schedule(dynamic, 1)
+        for (int y = y0; y < y1; y++) {
+            int64_t nr = 0;
+            for (int64_t k = 0; k < m; k++) {
+                const int32_t *b = box + order[k] * 4;
+                if (y >= b[1] && y <= b[3]) row[nr++] = order[k];
+            }
+            for (int x = 0; x < W; x++) {
+                const int64_t p = (int64_t)(y - y0) * W + x;
+                double px = x + 0.5, py = y + 0.5;
+                double T = 1.0, C[3] = {0, 0, 0}, wbest = -1.0, wsecond = -1.0;
+                int64_t dm = -1, ls = -1, pr = 0;
+                int nc = 0, fl = 0;
+                for (int64_t k = 0; k < nr; k++) {
+                    int64_t i = row[k];
+                    const int32_t *b = box + i * 4;
+                    if (x < b[0] || x > b[2]) continue;
+                    pr++;
+                    double G;
+                    double a = alpha_at(mean2d + i * 2, conic + i * 3, opacity[i], px, py, &G);
+                    double araw = opacity[i] * G;
+                    if (fabs(araw - ALPHA_MIN) <= FLAG_ALPHA_REL * ALPHA_MIN) fl = 1;
+                    if (a < ALPHA_MIN) continue;
+                    double testT = T * (1.0 - a);
+                    if (fabs(testT - T_STOP) <= FLAG_T_REL * T_STOP) fl = 1;
+                    if (testT < T_STOP) break;
+                    double w = a * T;
+                    for (int ch = 0; ch < 3; ch++) C[ch] += w * rgb[i * 3 + ch];
+                    if (w > wbest) { wsecond = wbest; wbest = w; dm = i; }
+                    else if (w > wsecond) wsecond = w;
+                    if (dL_dcolor) {
+                        if (nc == cap[x]) {
+                            cap[x] = cap[x] ? 2 * cap[x] : 64;
+                            lid[x] = (int64_t *)realloc(lid[x], sizeof(int64_t) * cap[x]);
+                            lal[x] = (double *)realloc(lal[x], sizeof(double) * cap[x]);
+                            lT[x] = (double *)realloc(lT[x], sizeof(double) * cap[x]);
+                            lG[x] = (double *)realloc(lG[x], sizeof(double) * cap[x]);
+                        }
+                        lid[x][nc] = i; lal[x][nc] = a; lT[x][nc] = T; lG[x][nc] = G;
+                    }
+                    T = testT;
+                    nc++;
+                    ls = i;
+                }
+                if (dm >= 0 && wsecond >= 0.0 && wbest - wsecond <= FLAG_DOM_REL * wbest) fl = 1;
+                for (int ch = 0; ch < 3; ch++) color[p * 3 + ch] = C[ch] + T * bg[ch];
+                Tfinal[p] = T; ncontrib[p] = nc; dom[p] = dm; last[p] = ls; flag[p] = (uint8_t)fl; pairs[p] = pr;
+                if (!dL_dcolor) continue;
+                const double *gC = dL_dcolor + p * 3;
+                double S[3];
+                for (int ch = 0; ch < 3; ch++) S[ch] = T * bg[ch];
+                for (int k = nc - 1; k >= 0; k--) {
+                    int64_t i = lid[x][k];
+                    double a = lal[x][k], Tk = lT[x][k], G = lG[x][k];
+                    double dLda = 0.0;
+                    for (int ch = 0; ch < 3; ch++) {
+#pragma omp atomic
+                        g_rgb[i * 3 + ch] += a * Tk * gC[ch];
+                        dLda += gC[ch] * (Tk * rgb[i * 3 + ch] - S[ch] / (1.0 - a));
+                    }
+                    for (int ch = 0; ch < 3; ch++) S[ch] += a * Tk * rgb[i * 3 + ch];
+                    double o = opacity[i];
+                    if (o * G < ALPHA_MAX) {
+                        double dLdpow = dLda * o * G;
+                        double dx = mean2d[i * 2] - px, dy = mean2d[i * 2 + 1] - py;
+                        const double *cn = conic + i * 3;
+#pragma omp atomic
+                        g_opac[i] += dLda * G;
+#pragma omp atomic
+                        g_mean[i * 2 + 0] += dLdpow * (-(cn[0] * dx + cn[1] * dy));
+#pragma omp atomic
+                        g_mean[i * 2 + 1] += dLdpow * (-(cn[2] * dy + cn[1] * dx));
+#pragma omp atomic
+                        g_conic[i * 3 + 0] += dLdpow * (-0.5 * dx * dx);
+#pragma omp atomic
+                        g_conic[i * 3 + 1] += dLdpow * (-dx * dy);
+#pragma omp atomic
+                        g_conic[i * 3 + 2] += dLdpow * (-0.5 * dy * dy);
+                    }
+                }
+            }
+        }
+        for (int x = 0; x < W; x++) { free(lid[x]); free(lal[x]); free(lT[x]); free(lG[x]); }
+        free(lid); free(lal); free(lT); free(lG); free(cap); free(row);
+    }
+    free(order);
+}

@@ -67,7 +67,10 @@ assert REGION_DTYPE.itemsize == 152
 
 EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "as_frame_create", "as_frame_destroy",
             "as_frame_get_view", "as_render", "as_render_backward", "as_error_map", "as_accumulate_error_stats",
-            "as_adaptive_split", "as_debug_sort_pairs", "as_debug_fp64_ops")
+            "as_adaptive_split", "as_timing_enable", "as_timing_read", "as_debug_sort_pairs", "as_debug_fp64_ops")
+
+STAGES = ("project", "scan", "emit", "sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd", "error_map",
+          "error_stats", "split")
 
 
 def lib():
@@ -380,6 +383,18 @@ def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=
                                    _ptr(count) if nc else None, _ptr(offset) if nc else None, _ptr(n_out),
                                    _stream(stream)))
     return out, mode[:nc], count[:nc], offset[:nc], n_out
+
+
+def timing_enable(ctx, on=True):
+    _check(lib().as_timing_enable(ctx.handle, ctypes.c_int32(1 if on else 0)))
+
+
+def timing_read(ctx):
+    """{stage: (total ms, runs)} since the last read."""
+    ms = (ctypes.c_double * len(STAGES))()
+    runs = (ctypes.c_int64 * len(STAGES))()
+    _check(lib().as_timing_read(ctx.handle, ms, runs))
+    return {name: (ms[k], runs[k]) for k, name in enumerate(STAGES)}
 
 
 def debug_sort_pairs(ctx, keys, vals, key_bits, stream=None):

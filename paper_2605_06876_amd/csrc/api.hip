@@ -2,6 +2,7 @@
 // frame lifetime and the launch order of each call.  No kernels live here.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -130,6 +131,46 @@ void devbuf_free(DevBuf &b) {
     b.bytes = 0;
 }
 
+static hipEvent_t pool_get(as_ctx *c) {
+    if (c->n_pool > 0) return c->pool[--c->n_pool];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void pool_put(as_ctx *c, hipEvent_t e) {
+    if (!e) return;
+    if (c->n_pool == c->cap_pool) {
+        const int nc = c->cap_pool ? 2 * c->cap_pool : 64;
+        hipEvent_t *p = (hipEvent_t *)realloc(c->pool, sizeof(hipEvent_t) * nc);
+        if (!p) { (void)hipEventDestroy(e); return; }
+        c->pool = p;
+        c->cap_pool = nc;
+    }
+    c->pool[c->n_pool++] = e;
+}
+
+StageTimer::StageTimer(as_ctx *c, int st, hipStream_t str) : ctx(c), stage(st), s(str) {
+    if (!ctx || !ctx->timing) return;
+    beg = pool_get(ctx);
+    if (beg) (void)hipEventRecord(beg, s);
+}
+
+StageTimer::~StageTimer() {
+    if (!beg) return;
+    hipEvent_t end = pool_get(ctx);
+    if (!end) { pool_put(ctx, beg); return; }
+    (void)hipEventRecord(end, s);
+    if (ctx->n_recs == ctx->cap_recs) {
+        const int nc = ctx->cap_recs ? 2 * ctx->cap_recs : 256;
+        StageRec *p = (StageRec *)realloc(ctx->recs, sizeof(StageRec) * nc);
+        if (!p) { pool_put(ctx, beg); pool_put(ctx, end); return; }
+        ctx->recs = p;
+        ctx->cap_recs = nc;
+    }
+    ctx->recs[ctx->n_recs++] = StageRec{stage, beg, end};
+}
+
 extern "C" {
 
 const char *as_last_error(void) { return g_err; }
@@ -158,6 +199,13 @@ void as_ctx_destroy(as_ctx *ctx) {
     for (auto &b : ctx->es) devbuf_free(b);
     for (auto &b : ctx->sp) devbuf_free(b);
     for (auto &b : ctx->dbg) devbuf_free(b);
+    for (int k = 0; k < ctx->n_recs; k++) {
+        (void)hipEventDestroy(ctx->recs[k].beg);
+        (void)hipEventDestroy(ctx->recs[k].end);
+    }
+    for (int k = 0; k < ctx->n_pool; k++) (void)hipEventDestroy(ctx->pool[k]);
+    free(ctx->recs);
+    free(ctx->pool);
     delete ctx;
 }
 
@@ -250,8 +298,14 @@ as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as
     const DevCam dc = to_devcam(*cam);
     const int64_t n = g->n, tiles = (int64_t)f->tiles_x * f->tiles_y;
     f->has_render = 0;
-    launch_project(gp, dc, f->tiles_x, f->rec, f->depth_key, f->box, f->ntiles, s);
-    scan_u32(f->ntiles, f->offsets, n, f->n_keys, f->scan_tmp.p, s);
+    {
+        StageTimer t(ctx, AS_STAGE_PROJECT, s);
+        launch_project(gp, dc, f->tiles_x, f->rec, f->depth_key, f->box, f->ntiles, s);
+    }
+    {
+        StageTimer t(ctx, AS_STAGE_SCAN, s);
+        scan_u32(f->ntiles, f->offsets, n, f->n_keys, f->scan_tmp.p, s);
+    }
     int64_t n_hint = f->key_cap;
     if (f->auto_grow) {
         if (bad(hipMemcpyAsync(f->h_nkeys, f->n_keys, 4, hipMemcpyDeviceToHost, s), "as_render: pair count readback") ||
@@ -266,16 +320,29 @@ as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as
         }
         n_hint = K;
     }
-    launch_emit_keys(n, f->depth_key, f->box, f->ntiles, f->offsets, f->tiles_x, f->key_cap, f->keys[0], f->vals[0], s);
-    const int sel = radix_sort_pairs(f->keys, f->vals, f->n_keys, f->key_cap, n_hint, 32 + tile_bits(tiles),
-                                     f->sort_hist.p, s);
+    {
+        StageTimer t(ctx, AS_STAGE_EMIT, s);
+        launch_emit_keys(n, f->depth_key, f->box, f->ntiles, f->offsets, f->tiles_x, f->key_cap, f->keys[0],
+                         f->vals[0], s);
+    }
+    int sel;
+    {
+        StageTimer t(ctx, AS_STAGE_SORT, s);
+        sel = radix_sort_pairs(f->keys, f->vals, f->n_keys, f->key_cap, n_hint, 32 + tile_bits(tiles), f->sort_hist.p, s);
+    }
     f->sorted_sel = sel;
-    launch_ranges(f->keys[sel], f->n_keys, f->key_cap, tiles, f->ranges, s);
+    {
+        StageTimer t(ctx, AS_STAGE_RANGES, s);
+        launch_ranges(f->keys[sel], f->n_keys, f->key_cap, tiles, f->ranges, s);
+    }
     if (gt) {
         launch_fill_u64(f->err_minmax, 0x7ff0000000000000ull, 1, s);
         launch_fill_u64(f->err_minmax + 1, 0ull, 1, s);
     }
-    launch_blend_fwd(f, f->vals[sel], dc, gt, image, s);
+    {
+        StageTimer t(ctx, AS_STAGE_BLEND_FWD, s);
+        launch_blend_fwd(f, f->vals[sel], dc, gt, image, s);
+    }
     const as_status st = launch_status("as_render");
     if (st != AS_OK) return st;
     f->has_render = 1;
@@ -299,9 +366,15 @@ as_status as_render_backward(as_ctx *ctx, const as_gaussians *g, const as_camera
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = g->n;
     const DevCam dc = to_devcam(*cam);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9 * n, s);
-    launch_blend_bwd(f, f->vals[f->sorted_sel], dc, dL_dimage, f->grad2d, n, s);
-    launch_project_bwd(gptrs(g), dc, f->ntiles, f->grad2d, n, mptrs(grads), g2d_norm, vis_count, s);
+    {
+        StageTimer t(ctx, AS_STAGE_BLEND_BWD, s);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9 * n, s);
+        launch_blend_bwd(f, f->vals[f->sorted_sel], dc, dL_dimage, f->grad2d, n, s);
+    }
+    {
+        StageTimer t(ctx, AS_STAGE_PROJECT_BWD, s);
+        launch_project_bwd(gptrs(g), dc, f->ntiles, f->grad2d, n, mptrs(grads), g2d_norm, vis_count, s);
+    }
     return launch_status("as_render_backward");
 }
 
@@ -311,7 +384,10 @@ as_status as_error_map(as_ctx *ctx, int32_t width, int32_t height, const float *
         as_set_error("as_error_map: bad argument");
         return AS_ERR_ARG;
     }
-    launch_error_map(width, height, image, gt, err, err_minmax, (hipStream_t)stream);
+    {
+        StageTimer t(ctx, AS_STAGE_ERROR_MAP, (hipStream_t)stream);
+        launch_error_map(width, height, image, gt, err, err_minmax, (hipStream_t)stream);
+    }
     return launch_status("as_error_map");
 }
 
@@ -326,8 +402,12 @@ as_status as_accumulate_error_stats(as_ctx *ctx, int32_t width, int32_t height, 
     }
     if ((int64_t)width * height > 0x7FFFFFFFll) { as_set_error("as_accumulate_error_stats: image too large"); return AS_ERR_ARG; }
     if (!check_params(params, "as_accumulate_error_stats")) return AS_ERR_ARG;
-    const as_status st = run_error_stats(ctx, width, height, err, err_minmax, dom, gt, view_id, n, is_candidate,
-                                         *params, *regions, attr_count, (hipStream_t)stream);
+    as_status st;
+    {
+        StageTimer t(ctx, AS_STAGE_ERROR_STATS, (hipStream_t)stream);
+        st = run_error_stats(ctx, width, height, err, err_minmax, dom, gt, view_id, n, is_candidate, *params, *regions,
+                             attr_count, (hipStream_t)stream);
+    }
     if (st != AS_OK) return st;
     return launch_status("as_accumulate_error_stats");
 }
@@ -359,10 +439,41 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
             as_set_error("as_adaptive_split: view %d is invalid", v);
             return AS_ERR_ARG;
         }
-    const as_status st = run_adaptive_split(ctx, gptrs(g), cand, n_cand, *regions, views, n_views, attr_count, *params,
-                                            noise, mptrs(out), out->n, mode, count, offset, n_out, (hipStream_t)stream);
+    as_status st;
+    {
+        StageTimer t(ctx, AS_STAGE_SPLIT, (hipStream_t)stream);
+        st = run_adaptive_split(ctx, gptrs(g), cand, n_cand, *regions, views, n_views, attr_count, *params, noise,
+                                mptrs(out), out->n, mode, count, offset, n_out, (hipStream_t)stream);
+    }
     if (st != AS_OK) return st;
     return launch_status("as_adaptive_split");
+}
+
+as_status as_timing_enable(as_ctx *ctx, int32_t on) {
+    if (!ctx) { as_set_error("as_timing_enable: null context"); return AS_ERR_ARG; }
+    ctx->timing = on != 0;
+    return AS_OK;
+}
+
+as_status as_timing_read(as_ctx *ctx, double *ms, int64_t *runs) {
+    if (!ctx || !ms || !runs) { as_set_error("as_timing_read: null argument"); return AS_ERR_ARG; }
+    for (int k = 0; k < AS_NUM_STAGES; k++) { ms[k] = 0.0; runs[k] = 0; }
+    as_status st = AS_OK;
+    for (int k = 0; k < ctx->n_recs; k++) {
+        StageRec &r = ctx->recs[k];
+        float e = 0.f;
+        if (st == AS_OK && (bad(hipEventSynchronize(r.end), "as_timing_read") ||
+                            bad(hipEventElapsedTime(&e, r.beg, r.end), "as_timing_read")))
+            st = AS_ERR_HIP;
+        if (st == AS_OK && r.stage >= 0 && r.stage < AS_NUM_STAGES) {
+            ms[r.stage] += e;
+            runs[r.stage] += 1;
+        }
+        pool_put(ctx, r.beg);
+        pool_put(ctx, r.end);
+    }
+    ctx->n_recs = 0;
+    return st;
 }
 
 as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, int32_t key_bits, void *stream) {

@@ -92,11 +92,31 @@ struct as_frame {
     int32_t has_gt;
 };
 
+struct StageRec {
+    int stage;
+    hipEvent_t beg, end;
+};
+
 struct as_ctx {
     int device;
     DevBuf es[16];    // error-statistics scratch (errstats.hip names the slots)
     DevBuf sp[24];    // adaptive-split scratch (split.hip names the slots)
     DevBuf dbg[4];    // test hooks
+    int timing = 0;
+    StageRec *recs = nullptr;     // recorded stage event pairs
+    int n_recs = 0, cap_recs = 0;
+    hipEvent_t *pool = nullptr;   // idle events
+    int n_pool = 0, cap_pool = 0;
+};
+
+// Records a hipEvent pair around one stage on stream s when timing is on.
+struct StageTimer {
+    as_ctx *ctx;
+    int stage;
+    hipStream_t s;
+    hipEvent_t beg = nullptr;
+    StageTimer(as_ctx *c, int st, hipStream_t str);
+    ~StageTimer();
 };
 
 // ---- launchers (each defined in the .hip file that holds the kernel) -------------

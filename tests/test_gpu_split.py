@@ -157,8 +157,8 @@ def compare_split(want, got):
     np.testing.assert_allclose(out.sh[:, :, :n_out].cpu().numpy(), want["sh"], rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("seed", [11, 12])
-def test_split_on_synthetic_maps(ctx, seed):
+@pytest.mark.parametrize("seed,m_min", [(11, 5), (12, 5), (13, 60)])
+def test_split_on_synthetic_maps(ctx, seed, m_min):
     H, W, n, V = 120, 160, 60, 4
     scene = synth.scene_uniform_sh0(n, seed=seed)
     views = views_for(V, W, H, seed)
@@ -168,10 +168,12 @@ def test_split_on_synthetic_maps(ctx, seed):
     for v in range(V):
         img, gt, dom, _ = synth.error_map_fixture(H, W, n, seed=seed * 100 + v, n_sites=60, n_blobs=80)
         maps.append((img, gt, dom))
-    want, got, attr = run_both_split(ctx, scene, views, maps, is_cand, oracle.SplitParams(), seed)
+    want, got, attr = run_both_split(ctx, scene, views, maps, is_cand, oracle.SplitParams(m_min=m_min), seed)
     say("modes: vanilla %d reset %d adaptive %d; new rows %d" % ((want["mode"] == 0).sum(), (want["mode"] == 1).sum(),
                                                                (want["mode"] == 2).sum(), want["count"].sum()))
     assert (want["mode"] == 2).sum() > 0
+    if m_min > 5:
+        assert (want["mode"] == 1).sum() > 0
     compare_split(want, got)
 
 
