@@ -213,12 +213,14 @@ void as_frame_destroy(as_frame *f) {
     if (!f) return;
     (void)hipSetDevice(f->ctx->device);
     void *ptrs[] = {f->rec, f->depth_key, f->box, f->ntiles, f->offsets, f->grad2d, f->ranges, f->n_keys,
-                    f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax};
+                    f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax, f->dkeys[0], f->dkeys[1],
+                    f->dvals[0], f->dvals[1], f->nt_sorted, f->n_gauss};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_keys(f);
     devbuf_free(f->scan_tmp);
     devbuf_free(f->sort_hist);
+    devbuf_free(f->dsort_hist);
     if (f->h_nkeys) (void)hipHostFree(f->h_nkeys);
     delete f;
 }
@@ -252,6 +254,10 @@ as_status as_frame_create(as_ctx *ctx, int64_t n_cap, int32_t width, int32_t hei
         (e = dmalloc(&f->t_final, P)) != hipSuccess || (e = dmalloc(&f->last, P)) != hipSuccess ||
         (e = dmalloc(&f->n_contrib, P)) != hipSuccess || (e = dmalloc(&f->dom, P)) != hipSuccess ||
         (e = dmalloc(&f->err, P)) != hipSuccess || (e = dmalloc(&f->err_minmax, 2)) != hipSuccess ||
+        (e = dmalloc(&f->dkeys[0], n_cap)) != hipSuccess || (e = dmalloc(&f->dkeys[1], n_cap)) != hipSuccess ||
+        (e = dmalloc(&f->dvals[0], n_cap)) != hipSuccess || (e = dmalloc(&f->dvals[1], n_cap)) != hipSuccess ||
+        (e = dmalloc(&f->nt_sorted, n_cap)) != hipSuccess || (e = dmalloc(&f->n_gauss, 4)) != hipSuccess ||
+        (e = devbuf_ensure(f->dsort_hist, sort_hist_bytes(n_cap))) != hipSuccess ||
         (e = alloc_keys(f, key_cap)) != hipSuccess || (e = devbuf_ensure(f->scan_tmp, scan_tmp_bytes(n_cap))) != hipSuccess ||
         (e = hipHostMalloc((void **)&f->h_nkeys, 64, hipHostMallocDefault)) != hipSuccess) {
         as_set_error("as_frame_create: allocation failed: %s", hipGetErrorString(e));
@@ -302,9 +308,20 @@ as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as
         StageTimer t(ctx, AS_STAGE_PROJECT, s);
         launch_project(gp, dc, f->tiles_x, f->rec, f->depth_key, f->box, f->ntiles, s);
     }
+    // Depth-first binning: a stable sort of the Gaussians by depth, keys
+    // emitted in that order, then a stable sort on the tile bits alone, gives
+    // the same order as sorting (tile | depth) keys emitted by id.
+    const uint32_t *order;
+    {
+        StageTimer t(ctx, AS_STAGE_SORT, s);
+        launch_depth_pairs(n, f->depth_key, f->dkeys[0], f->dvals[0], f->n_gauss, s);
+        const int dsel = radix_sort_pairs_range(f->dkeys, f->dvals, f->n_gauss, f->n_cap, n, 0, 32, f->dsort_hist.p, s);
+        order = f->dvals[dsel];
+    }
     {
         StageTimer t(ctx, AS_STAGE_SCAN, s);
-        scan_u32(f->ntiles, f->offsets, n, f->n_keys, f->scan_tmp.p, s);
+        launch_gather_u32(n, f->ntiles, order, f->nt_sorted, s);
+        scan_u32(f->nt_sorted, f->offsets, n, f->n_keys, f->scan_tmp.p, s);
     }
     int64_t n_hint = f->key_cap;
     if (f->auto_grow) {
@@ -322,13 +339,14 @@ as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as
     }
     {
         StageTimer t(ctx, AS_STAGE_EMIT, s);
-        launch_emit_keys(n, f->depth_key, f->box, f->ntiles, f->offsets, f->tiles_x, f->key_cap, f->keys[0],
-                         f->vals[0], s);
+        launch_emit_sorted(n, order, f->depth_key, f->box, f->ntiles, f->offsets, f->tiles_x, f->key_cap, f->keys[0],
+                           f->vals[0], s);
     }
     int sel;
     {
         StageTimer t(ctx, AS_STAGE_SORT, s);
-        sel = radix_sort_pairs(f->keys, f->vals, f->n_keys, f->key_cap, n_hint, 32 + tile_bits(tiles), f->sort_hist.p, s);
+        sel = radix_sort_pairs_range(f->keys, f->vals, f->n_keys, f->key_cap, n_hint, 32, 32 + tile_bits(tiles),
+                                     f->sort_hist.p, s);
     }
     f->sorted_sel = sel;
     {

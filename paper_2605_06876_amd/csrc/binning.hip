@@ -138,6 +138,49 @@ __global__ void __launch_bounds__(256) k_emit(int64_t n, const uint32_t *__restr
         }
 }
 
+// Keys of one Gaussian, emitted in depth order: rank r holds Gaussian order[r]
+// and writes its keys at offsets[r] (the scan of ntiles in that order).
+__global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *__restrict__ order,
+                                                     const uint32_t *__restrict__ depth_key,
+                                                     const short4 *__restrict__ box,
+                                                     const uint32_t *__restrict__ ntiles,
+                                                     const uint32_t *__restrict__ offsets, int tiles_x, int64_t key_cap,
+                                                     uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t i = order[r];
+    const uint32_t nt = ntiles[i];
+    if (nt == 0) return;
+    const uint64_t off = offsets[r];
+    if (off + nt > (uint64_t)key_cap) return;   // over capacity: the count tells the caller
+    const short4 b = box[i];
+    const uint64_t dk = depth_key[i];
+    const int tx0 = b.x / AS_TILE_W, tx1 = b.z / AS_TILE_W, ty0 = b.y / AS_TILE_H, ty1 = b.w / AS_TILE_H;
+    uint64_t k = off;
+    for (int ty = ty0; ty <= ty1; ty++)
+        for (int tx = tx0; tx <= tx1; tx++) {
+            keys[k] = ((uint64_t)(ty * tiles_x + tx) << 32) | dk;
+            vals[k] = i;
+            k++;
+        }
+}
+
+// (depth key, id) pairs of every Gaussian for the depth sort.
+__global__ void k_depth_pairs(int64_t n, const uint32_t *__restrict__ depth_key, uint64_t *__restrict__ keys,
+                              uint32_t *__restrict__ vals, uint32_t *__restrict__ n32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *n32 = (uint32_t)n;
+    if (i >= n) return;
+    keys[i] = depth_key[i];
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_gather_u32(int64_t n, const uint32_t *__restrict__ src, const uint32_t *__restrict__ idx,
+                             uint32_t *__restrict__ dst) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) dst[r] = src[idx[r]];
+}
+
 // ---- LSD radix sort --------------------------------------------------------------------
 
 constexpr int RS_THREADS = 256;
@@ -304,11 +347,16 @@ size_t sort_hist_bytes(int64_t n_hint) {
 
 int radix_sort_pairs(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint,
                      int key_bits, void *hist, hipStream_t s) {
+    return radix_sort_pairs_range(keys, vals, n_dev, cap, n_hint, 0, key_bits, hist, s);
+}
+
+int radix_sort_pairs_range(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint,
+                           int lo_bit, int hi_bit, void *hist, hipStream_t s) {
     const int G = rs_grid(n_hint);
     uint32_t *h = reinterpret_cast<uint32_t *>(hist);
     void *tmp = reinterpret_cast<char *>(hist) + (size_t)(256 * G) * 4;
     int sel = 0;
-    for (int shift = 0; shift < key_bits; shift += 8) {
+    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(RS_THREADS), 0, s, keys[sel], n_dev, cap, shift, h);
         scan_impl<uint32_t, uint32_t>(h, h, (int64_t)256 * G, (uint32_t *)nullptr, tmp, s);
         hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(RS_THREADS), 0, s, keys[sel], vals[sel], keys[sel ^ 1],
@@ -316,6 +364,25 @@ int radix_sort_pairs(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev
         sel ^= 1;
     }
     return sel;
+}
+
+void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint64_t *keys, uint32_t *vals, uint32_t *n32,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_depth_pairs, dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)), dim3(256), 0, s, n,
+                       depth_key, keys, vals, n32);
+}
+
+void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint32_t *dst, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, src, idx, dst);
+}
+
+void launch_emit_sorted(int64_t n, const uint32_t *order, const uint32_t *depth_key, const int16_t *box,
+                        const uint32_t *ntiles, const uint32_t *offsets, int tiles_x, int64_t key_cap, uint64_t *keys,
+                        uint32_t *vals, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_emit_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order, depth_key,
+                       reinterpret_cast<const short4 *>(box), ntiles, offsets, tiles_x, key_cap, keys, vals);
 }
 
 void launch_ranges(const uint64_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,

@@ -67,8 +67,14 @@ struct as_frame {
     uint32_t *depth_key;
     int16_t *box;          // [n][4]
     uint32_t *ntiles;
-    uint32_t *offsets;
+    uint32_t *offsets;     // [n] key offsets, in depth order
     float *grad2d;         // [9][n]
+    // depth-first binning: Gaussians sorted by depth, then keys by tile
+    uint64_t *dkeys[2];
+    uint32_t *dvals[2];
+    uint32_t *nt_sorted;   // [n] tiles touched, in depth order
+    uint32_t *n_gauss;     // [1] device copy of n for the depth sort
+    DevBuf dsort_hist;
     // pairs
     uint64_t *keys[2];
     uint32_t *vals[2];
@@ -144,6 +150,17 @@ size_t sort_hist_bytes(int64_t n_hint);
 // is read from the device (*n_dev, clamped to cap); n_hint sizes the grid.
 int radix_sort_pairs(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint,
                      int key_bits, void *hist, hipStream_t s);
+// The same on bits [lo_bit, hi_bit) only (8-bit digits from lo_bit upwards).
+int radix_sort_pairs_range(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint,
+                           int lo_bit, int hi_bit, void *hist, hipStream_t s);
+// Depth-first binning helpers: (depth, id) pairs, gathers, and key emission in
+// the depth order a stable depth sort produced.
+void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint64_t *keys, uint32_t *vals, uint32_t *n32,
+                        hipStream_t s);
+void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint32_t *dst, hipStream_t s);
+void launch_emit_sorted(int64_t n, const uint32_t *order, const uint32_t *depth_key, const int16_t *box,
+                        const uint32_t *ntiles, const uint32_t *offsets, int tiles_x, int64_t key_cap, uint64_t *keys,
+                        uint32_t *vals, hipStream_t s);
 void launch_ranges(const uint64_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
                    hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);

@@ -17,6 +17,7 @@ __device__ __forceinline__ void quat_to_rot_d(double w, double x, double y, doub
     R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+template <int DEG>
 __global__ void __launch_bounds__(256) k_project(GaussPtrs g, DevCam cam, int tiles_x, BlendRec *__restrict__ rec,
                                                  uint32_t *__restrict__ depth_key, short4 *__restrict__ box,
                                                  uint32_t *__restrict__ ntiles) {
@@ -99,11 +100,13 @@ __global__ void __launch_bounds__(256) k_project(GaussPtrs g, DevCam cam, int ti
         const double v0 = mu[0] - oc[0], v1 = mu[1] - oc[1], v2 = mu[2] - oc[2];
         const double vn = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
         double Y[16];
-        sh_eval_basis(v0 / vn, v1 / vn, v2 / vn, g.deg, Y);
-        const int nk = (g.deg + 1) * (g.deg + 1);
+        sh_eval_basis(v0 / vn, v1 / vn, v2 / vn, DEG, Y);
+        constexpr int nk = (DEG + 1) * (DEG + 1);
         double col[3];
+#pragma unroll
         for (int ch = 0; ch < 3; ch++) {
             double acc = 0.0;
+#pragma unroll
             for (int k = 0; k < nk; k++) acc += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
             acc += 0.5;
             col[ch] = acc < 0.0 ? 0.0 : acc;
@@ -130,6 +133,11 @@ void launch_project(const GaussPtrs &g, const DevCam &cam, int tiles_x, BlendRec
                     int16_t *box, uint32_t *ntiles, hipStream_t s) {
     if (g.n == 0) return;
     const int64_t blocks = (g.n + 255) / 256;
-    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key,
-                       reinterpret_cast<short4 *>(box), ntiles);
+    short4 *b4 = reinterpret_cast<short4 *>(box);
+    switch (g.deg) {
+    case 0: hipLaunchKernelGGL(k_project<0>, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key, b4, ntiles); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key, b4, ntiles); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key, b4, ntiles); break;
+    default: hipLaunchKernelGGL(k_project<3>, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key, b4, ntiles); break;
+    }
 }

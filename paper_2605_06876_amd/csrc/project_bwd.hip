@@ -12,17 +12,19 @@
 
 namespace {
 
+template <int DEG>
 __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, const uint32_t *__restrict__ ntiles,
                                                      const float *__restrict__ g2d, int64_t gs, GradPtrs out,
                                                      float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
     const int64_t n = g.n, os = out.stride;
-    const int nk = (g.deg + 1) * (g.deg + 1);
+    constexpr int nk = (DEG + 1) * (DEG + 1);
     if (ntiles[i] == 0) {
         for (int k = 0; k < 3; k++) { out.means[k * os + i] = 0.f; out.log_scales[k * os + i] = 0.f; }
         for (int k = 0; k < 4; k++) out.quats[k * os + i] = 0.f;
         out.opac[i] = 0.f;
+#pragma unroll
         for (int k = 0; k < nk * 3; k++) out.sh[(int64_t)k * os + i] = 0.f;
         return;
     }
@@ -61,14 +63,17 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, co
     const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     const double d[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
     double Y[16], dY[16][3];
-    sh_eval_basis(d[0], d[1], d[2], g.deg, Y);
-    sh_eval_basis_grad(d[0], d[1], d[2], g.deg, dY);
+    sh_eval_basis(d[0], d[1], d[2], DEG, Y);
+    sh_eval_basis_grad(d[0], d[1], d[2], DEG, dY);
     double gd[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int ch = 0; ch < 3; ch++) {
         double raw = 0.0;
+#pragma unroll
         for (int k = 0; k < nk; k++) raw += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
         const bool clamped = raw + 0.5 < 0.0;
         const double gc = clamped ? 0.0 : grgb[ch];
+#pragma unroll
         for (int k = 0; k < nk; k++) {
             out.sh[((int64_t)k * 3 + ch) * os + i] = (float)(Y[k] * gc);
             const double shv = (double)g.sh[((int64_t)k * 3 + ch) * n + i];
@@ -187,6 +192,11 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, co
 void launch_project_bwd(const GaussPtrs &g, const DevCam &cam, const uint32_t *ntiles, const float *grad2d,
                         int64_t g2d_stride, GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s) {
     if (g.n == 0) return;
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g, cam, ntiles, grad2d,
-                       g2d_stride, out, g2d_norm, vis_count);
+    const dim3 grid((unsigned)((g.n + 255) / 256));
+    switch (g.deg) {
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
+    }
 }

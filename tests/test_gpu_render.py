@@ -333,3 +333,35 @@ def test_c2_backward_sparse_upstream(ctx, c2):
         flagged |= (c2["pr"].valid == 1) & (b[:, 0] <= x) & (x <= b[:, 2]) & (b[:, 1] <= y) & (y <= b[:, 3])
     res = _grad_compare(grads, gref, exclude=flagged)
     say("c2 gradients: " + ", ".join("%s %.2e" % (k, v[0]) for k, v in res.items()))
+
+
+def test_autograd_function_matches_oracle_gradients(c1):
+    """loss = <G, render(theta)> through torch.autograd: the parameter
+    gradients equal the oracle's analytic FP64 gradients."""
+    from paper_2605_06876_amd.autograd import Rasterizer
+    scene, cam = c1["scene"], c1["cam"]
+    params = [torch.from_numpy(np.ascontiguousarray(getattr(scene, k))).cuda().requires_grad_(True)
+              for k in ("means", "log_scales", "quats", "opacity_logits", "sh")]
+    r = Rasterizer(scene.n, cam.width, cam.height, track_stats=True)
+    G = np.random.default_rng(12).normal(size=(3, cam.height, cam.width)).astype(np.float32)
+    img = r(*params, scene.sh_degree, cam)
+    loss = (img * torch.from_numpy(G).cuda()).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    pr = c1["pr"]
+    pix = oracle.all_pixels(cam.width, cam.height)
+    g2d = oracle.render_backward_pixels(pr, pix, G.transpose(1, 2, 0).reshape(-1, 3).astype(np.float64))
+    gref = oracle.project_backward(scene, cam, g2d)
+    flagged = np.zeros(pr.n, bool)
+    fy, fx = np.nonzero(c1["maps"]["flag"])
+    for x, y in zip(fx, fy):
+        b = pr.box
+        flagged |= (pr.valid == 1) & (b[:, 0] <= x) & (x <= b[:, 2]) & (b[:, 1] <= y) & (y <= b[:, 3])
+
+    class Grads:
+        pass
+    gg = Grads()
+    for k, p in zip(("means", "log_scales", "quats", "opacity_logits", "sh"), params):
+        setattr(gg, k, p.grad)
+    _grad_compare(gg, gref, exclude=flagged)
+    assert (r.vis_count.cpu().numpy() == (pr.valid == 1)).all()
