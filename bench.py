@@ -49,6 +49,9 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-densify", action="store_true")
     ap.add_argument("--json", default="", help="also write the JSON line to this file")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tuning)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 1 GiB device copy first (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -86,6 +89,12 @@ def training_step_bench(args):
     image = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
     grads = api.Gaussians.empty(n, scene.sh_degree)
     dm = frame.device_maps()
+    from paper_2605_06876_amd import autotune
+    if args.no_tune:
+        best, tune_ms = api.get_tuning(ctx), {}
+    else:
+        log("bench: autotuning the blend launch (untimed)")
+        best, tune_ms = autotune.autotune(ctx, g, cam, frame, gt=gtt, dL=G, reps=3, use_cache=False, cache_path=None)
 
     def step():
         regions.count.zero_()
@@ -111,7 +120,8 @@ def training_step_bench(args):
     ms = (t1 - t0) * 1e3 / args.steps
     K = frame.n_keys()
     n_regions = int(regions.count.item())
-    return dict(ms=ms, stages=stages, K=K, n=n, W=W, H=H, n_regions=n_regions, steps=args.steps, ctx=ctx)
+    return dict(ms=ms, stages=stages, K=K, n=n, W=W, H=H, n_regions=n_regions, steps=args.steps, ctx=ctx,
+                tuning=best, tuning_ms={k: round(v, 4) for k, v in tune_ms.items()})
 
 
 def densify_bench(ctx):
@@ -264,6 +274,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     res = training_step_bench(args)
     consts = load_workload_constants()
     P_alg = consts["pairs"]
@@ -320,7 +336,8 @@ def main():
         "config": {"workload": "training step: render + L1 error statistics (5% candidates) + backward, "
                                "1,000,000 Gaussians SH3, one 1256x828 view",
                    "gaussians": n, "width": W, "height": H, "sh_degree": 3, "pairs_tile": K, "pairs_alg": P_alg,
-                   "regions": res["n_regions"]},
+                   "regions": res["n_regions"], "tuning": res["tuning"]},
+        "tuning_candidates_ms": res["tuning_ms"],
         "roofline": roof,
         "stage_ms": {k: round(v, 4) for k, v in per_step.items()},
         "stage_roofline": all_roofs,

@@ -101,14 +101,19 @@ typedef struct {
                              After synchronising, count > capacity means records were dropped. */
 } as_region_buf;
 
-/* Device views into a frame's state, for inspection by tests and tools. */
+/* Device views into a frame's state for one of its views, for inspection by
+ * tests and tools.  Per-entry arrays are those of the view's own Gaussians
+ * (index = Gaussian id); keys, vals and the range values are global over the
+ * views of the last render (the pairs of every view sort together). */
 typedef struct {
     int32_t width, height, tile_w, tile_h, tiles_x, tiles_y;
     int64_t n_cap, key_cap;
-    uint32_t *n_keys;         /* [1] number of (tile, Gaussian) pairs of the last render */
-    uint64_t *keys;           /* [key_cap] sorted keys: tile << 32 | float bits of view depth */
-    uint32_t *vals;           /* [key_cap] Gaussian id of each sorted key */
-    uint32_t *ranges;         /* [tiles][2] start, end into keys/vals */
+    int32_t tile_base;        /* global id of the view's first tile */
+    uint32_t ent_base;        /* global entry id of the view's Gaussian 0 */
+    uint32_t *n_keys;         /* [1] number of (tile, entry) pairs of the last render, all views */
+    uint32_t *keys;           /* [key_cap] sorted global tile ids */
+    uint32_t *vals;           /* [key_cap] entry id of each sorted pair (entry = ent_base of its view + Gaussian id) */
+    uint32_t *ranges;         /* [tiles][2] start, end into keys/vals of the view's tiles */
     uint32_t *depth_key;      /* [n] float bits of view-space depth */
     int16_t *box;             /* [n][4] inclusive pixel box x0, y0, x1, y1 (valid if ntiles > 0) */
     uint32_t *ntiles;         /* [n] tiles touched (0 = culled) */
@@ -119,7 +124,8 @@ typedef struct {
     int32_t *dom;             /* [H][W] dominant Gaussian id, -1 if none */
     double *err;              /* [H][W] L1 error (written when the render gets a target) */
     uint64_t *err_minmax;     /* [2] bit patterns of the error map's min and max */
-    float *grad2d;            /* [9][n] per-Gaussian 2D gradients of the last backward */
+    float *grad2d;            /* [9][grad2d_stride] per-Gaussian 2D gradients of the last backward */
+    int64_t grad2d_stride;
 } as_frame_view;
 
 /* ---- context and state ------------------------------------------------------ */
@@ -140,8 +146,16 @@ const char *as_version(void);
  * the pairs beyond capacity dropped (the caller checks and re-renders). */
 as_status as_frame_create(as_ctx *ctx, int64_t n_cap, int32_t width, int32_t height, int64_t key_cap,
                           int32_t auto_grow, as_frame **out);
+/* A frame for batched renders of up to max_views (<= 16) views of any sizes:
+ * entry_cap bounds the sum over the views of their Gaussian counts,
+ * pixel_cap the sum of W x H, tile_cap the sum of 16 x 16 tiles (a W x H view
+ * has ceil(W/16) ceil(H/16)); key_cap and auto_grow as above. */
+as_status as_frame_create_batch(as_ctx *ctx, int32_t max_views, int64_t entry_cap, int64_t pixel_cap,
+                                int64_t tile_cap, int64_t key_cap, int32_t auto_grow, as_frame **out);
 void as_frame_destroy(as_frame *f);
+/* View 0 (as_frame_get_view) or view v of the last render. */
 as_status as_frame_get_view(const as_frame *f, as_frame_view *out);
+as_status as_frame_get_view_of(const as_frame *f, int32_t view, as_frame_view *out);
 
 /* ---- the four calls of the path --------------------------------------------- */
 
@@ -169,6 +183,30 @@ as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as
 as_status as_render_backward(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as_frame *frame,
                              const float *dL_dimage, as_gaussians_mut *grads, float *g2d_norm, int32_t *vis_count,
                              void *stream);
+
+/* Batched forward render: n_views (1..max_views) cameras of any sizes, view v
+ * rendering the Gaussian set scenes[v] (views may share a set; every set has
+ * the same sh_degree), in one pass of each stage: one projection launch over
+ * all (view, Gaussian) entries, one depth sort, one key sort over the global
+ * tile ids, and one blend launch over every tile of every view.  Each view's
+ * outputs are those as_render would give for it alone (the pairs of
+ * different views never share a tile).
+ *   scenes : host array [n_views]
+ *   cams   : host array [n_views]
+ *   gt     : NULL, or host array [n_views] of [3][H_v][W_v] targets
+ *   images : host array [n_views] of out [3][H_v][W_v]
+ * AS_ERR_CAPACITY when the views exceed the frame's entry, pixel or tile
+ * capacity; a frame created by as_frame_create takes one view of its size. */
+as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_camera *cams, int32_t n_views,
+                          as_frame *frame, const float *const *gt, float *const *images, void *stream);
+
+/* Reverse pass of the last as_render_batch, whose views all rendered the
+ * Gaussian set g: per-view 2D gradients from one blend launch, then the
+ * parameter gradients summed over the views in view order.
+ *   dL_dimages : host array [n_views] of [3][H_v][W_v]
+ *   grads, g2d_norm, vis_count : as as_render_backward (visibility counted per view) */
+as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame *frame, const float *const *dL_dimages,
+                                   as_gaussians_mut *grads, float *g2d_norm, int32_t *vis_count, void *stream);
 
 /* Per-pixel L1 error e = sum_c |image_c - gt_c| in FP64 and its min and max
  * over the view (the inputs of Eq. (l1map)), for images not produced by
@@ -220,6 +258,23 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
                             as_gaussians_mut *out, uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out,
                             void *stream);
 
+/* ---- launch tuning ---------------------------------------------------------------- */
+
+/* Launch choices that change speed but never results (the autotuner in the
+ * Python package measures them on the caller's workload). */
+typedef struct {
+    int32_t lds_batch;       /* Gaussian records staged per LDS batch by the blend kernels: 256, 512 or 1024 */
+    int32_t longest_first;   /* nonzero: tiles are dispatched in descending order of list length */
+    int32_t persistent;      /* nonzero: the blend kernels run as one resident grid pulling tiles from a queue */
+    int32_t radix_bits;      /* digit width of the radix sorts, 4..8 */
+} as_tuning;
+
+/* Set / read the context's tuning (defaults: lds_batch 256, longest_first 1,
+ * persistent 0, radix_bits 8).  AS_ERR_ARG for an lds_batch other than 256,
+ * 512 or 1024 or a radix_bits outside 4..8. */
+as_status as_set_tuning(as_ctx *ctx, const as_tuning *t);
+as_status as_get_tuning(const as_ctx *ctx, as_tuning *t);
+
 /* ---- per-stage timing ------------------------------------------------------------ */
 
 /* Stages timed when timing is on (indices into as_timing_read's arrays). */
@@ -248,10 +303,27 @@ as_status as_timing_enable(as_ctx *ctx, int32_t on);
  * arrays, zeroed by this call first), and forget the records. */
 as_status as_timing_read(as_ctx *ctx, double *ms, int64_t *runs);
 
+/* ---- graph capture ------------------------------------------------------------- */
+
+/* Record every call made on `stream` between as_graph_begin and as_graph_end
+ * into a HIP graph, replayed by as_graph_launch with the same arguments
+ * (the device buffers the calls named must stay allocated, and their
+ * contents at replay time are the inputs).  None of the calls of this
+ * library synchronise or allocate while a stream is capturing: frames must
+ * have auto_grow = 0 and every context buffer must already have its size,
+ * so each captured call is made once outside the capture first
+ * (AS_ERR_STATE otherwise).  Per-stage timing is suspended while capturing. */
+typedef struct as_graph as_graph;
+as_status as_graph_begin(as_ctx *ctx, void *stream);
+as_status as_graph_end(as_ctx *ctx, void *stream, as_graph **out);
+as_status as_graph_launch(as_graph *graph, void *stream);
+void as_graph_destroy(as_graph *graph);
+
 /* ---- test hooks --------------------------------------------------------------- */
 
 /* Stable LSD radix sort of n (key, value) pairs on the low key_bits bits, in
- * place (the sorter the binning uses).  keys [n], vals [n]. */
+ * place (the sorter the binning uses, with the context's radix_bits).
+ * keys [n], vals [n]; bits at and above key_bits are ignored. */
 as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, int32_t key_bits, void *stream);
 
 /* Element-wise FP64 sqrt(a), a / b, exp(b) and log(a) on the device, used to

@@ -53,9 +53,11 @@ class _RegionBuf(ctypes.Structure):
 class _FrameView(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
-                ("n_cap", ctypes.c_int64), ("key_cap", ctypes.c_int64)] + [
+                ("n_cap", ctypes.c_int64), ("key_cap", ctypes.c_int64), ("tile_base", ctypes.c_int32),
+                ("ent_base", ctypes.c_uint32)] + [
         (nm, ctypes.c_void_p) for nm in ("n_keys", "keys", "vals", "ranges", "depth_key", "box", "ntiles", "rec",
-                                         "t_final", "last", "n_contrib", "dom", "err", "err_minmax", "grad2d")]
+                                         "t_final", "last", "n_contrib", "dom", "err", "err_minmax", "grad2d")] + [
+        ("grad2d_stride", ctypes.c_int64)]
 
 
 REGION_DTYPE = np.dtype([
@@ -65,9 +67,13 @@ REGION_DTYPE = np.dtype([
     ("rgb", "<f4", (3,)), ("pad1", "<f4")])
 assert REGION_DTYPE.itemsize == 152
 
-EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "as_frame_create", "as_frame_destroy",
-            "as_frame_get_view", "as_render", "as_render_backward", "as_error_map", "as_accumulate_error_stats",
-            "as_adaptive_split", "as_timing_enable", "as_timing_read", "as_debug_sort_pairs", "as_debug_fp64_ops")
+EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "as_frame_create",
+            "as_frame_create_batch", "as_frame_destroy", "as_frame_get_view", "as_frame_get_view_of", "as_render",
+            "as_render_backward", "as_render_batch", "as_render_backward_batch", "as_error_map",
+            "as_accumulate_error_stats", "as_adaptive_split", "as_set_tuning", "as_get_tuning", "as_timing_enable",
+            "as_timing_read", "as_graph_begin", "as_graph_end", "as_graph_launch", "as_graph_destroy",
+            "as_debug_sort_pairs", "as_debug_fp64_ops")
+_NO_STATUS = ("as_last_error", "as_version", "as_ctx_destroy", "as_frame_destroy", "as_graph_destroy")
 
 STAGES = ("project", "scan", "emit", "sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd", "error_map",
           "error_stats", "split")
@@ -85,10 +91,11 @@ def lib():
         L.as_last_error.restype = ctypes.c_char_p
         L.as_version.restype = ctypes.c_char_p
         for name in EXPORTED:
-            if name not in ("as_last_error", "as_version", "as_ctx_destroy", "as_frame_destroy"):
+            if name not in _NO_STATUS:
                 getattr(L, name).restype = ctypes.c_int
         L.as_ctx_destroy.restype = None
         L.as_frame_destroy.restype = None
+        L.as_graph_destroy.restype = None
         _lib = L
     return _lib
 
@@ -200,7 +207,8 @@ class Context:
 
 
 class Frame:
-    """Per-view rasterizer state (as_frame)."""
+    """Rasterizer state (as_frame): one view of a fixed size, or (batch=True
+    through BatchFrame) up to 16 views of any sizes."""
 
     def __init__(self, ctx, n_cap, width, height, key_cap=None, auto_grow=True):
         if key_cap is None:
@@ -210,10 +218,10 @@ class Frame:
                                      ctypes.c_int64(key_cap), ctypes.c_int32(1 if auto_grow else 0), ctypes.byref(h)))
         self.ctx, self.handle, self.width, self.height, self.n_cap = ctx, h, width, height, n_cap
 
-    def view(self):
-        v = _FrameView()
-        _check(lib().as_frame_get_view(self.handle, ctypes.byref(v)))
-        return v
+    def view(self, v=0):
+        out = _FrameView()
+        _check(lib().as_frame_get_view_of(self.handle, ctypes.c_int32(v), ctypes.byref(out)))
+        return out
 
     def close(self):
         if self.handle:
@@ -239,29 +247,63 @@ class Frame:
         v = self.view()
         return int(self._dev(v.n_keys, 4).view(np.uint32)[0])
 
-    def host_state(self, n):
-        """Keys, values, ranges, per-Gaussian and per-pixel state as numpy arrays."""
-        v = self.view()
+    def host_state(self, n, view=0):
+        """Keys, values, ranges, per-Gaussian and per-pixel state of one view
+        as numpy arrays.  `tile_keys`/`vals` are the sorted pairs of all views
+        (global tile ids, entry ids); `keys` restates each pair as
+        (tile of the view) << 32 | depth bits, the form of a (tile | depth)
+        sort, and `gauss` its Gaussian id (meaningful for this view's pairs)."""
+        v = self.view(view)
         K = min(self.n_keys(), v.key_cap)
-        P = self.width * self.height
+        H, W = v.height, v.width
+        P = W * H
         T = v.tiles_x * v.tiles_y
+        tk = self._dev(v.keys, 4 * K).view(np.uint32)
+        vals = self._dev(v.vals, 4 * K).view(np.uint32)
+        ne = int(vals.max()) + 1 if K else 0
+        dk_all = self._dev(v.depth_key - 4 * v.ent_base, 4 * ne).view(np.uint32)
+        keys = ((tk.astype(np.int64) - v.tile_base).astype(np.uint64) << np.uint64(32)) | \
+            (dk_all[vals].astype(np.uint64) if K else np.zeros(0, np.uint64))
         return dict(
-            n_keys=self.n_keys(), keys=self._dev(v.keys, 8 * K).view(np.uint64), vals=self._dev(v.vals, 4 * K).view(np.uint32),
+            n_keys=self.n_keys(), tile_keys=tk, keys=keys, vals=vals,
+            gauss=(vals.astype(np.int64) - v.ent_base).astype(np.uint32),
             ranges=self._dev(v.ranges, 8 * T).view(np.uint32).reshape(T, 2),
             depth_key=self._dev(v.depth_key, 4 * n).view(np.uint32), box=self._dev(v.box, 8 * n).view(np.int16).reshape(n, 4),
             ntiles=self._dev(v.ntiles, 4 * n).view(np.uint32), rec=self._dev(v.rec, 48 * n).view(np.float32).reshape(n, 12),
-            t_final=self._dev(v.t_final, 4 * P).view(np.float32).reshape(self.height, self.width),
-            last=self._dev(v.last, 4 * P).view(np.uint32).reshape(self.height, self.width),
-            n_contrib=self._dev(v.n_contrib, 4 * P).view(np.uint32).reshape(self.height, self.width),
-            dom=self._dev(v.dom, 4 * P).view(np.int32).reshape(self.height, self.width),
-            err=self._dev(v.err, 8 * P).view(np.float64).reshape(self.height, self.width),
+            t_final=self._dev(v.t_final, 4 * P).view(np.float32).reshape(H, W),
+            last=self._dev(v.last, 4 * P).view(np.uint32).reshape(H, W),
+            n_contrib=self._dev(v.n_contrib, 4 * P).view(np.uint32).reshape(H, W),
+            dom=self._dev(v.dom, 4 * P).view(np.int32).reshape(H, W),
+            err=self._dev(v.err, 8 * P).view(np.float64).reshape(H, W),
             err_minmax=self._dev(v.err_minmax, 16).view(np.uint64),
-            tiles_x=v.tiles_x, tiles_y=v.tiles_y)
+            tiles_x=v.tiles_x, tiles_y=v.tiles_y, tile_base=v.tile_base, ent_base=v.ent_base)
 
-    def device_maps(self):
-        """Device addresses of the per-pixel maps (for accumulate_error_stats)."""
-        v = self.view()
-        return dict(err=v.err, err_minmax=v.err_minmax, dom=v.dom, t_final=v.t_final)
+    def device_maps(self, view=0):
+        """Device addresses of one view's per-pixel maps (for accumulate_error_stats)."""
+        v = self.view(view)
+        return dict(err=v.err, err_minmax=v.err_minmax, dom=v.dom, t_final=v.t_final, width=v.width,
+                    height=v.height)
+
+
+class BatchFrame(Frame):
+    """as_frame_create_batch: state for batched renders of up to max_views views."""
+
+    def __init__(self, ctx, max_views, entry_cap, pixel_cap, tile_cap, key_cap=None, auto_grow=True):
+        if key_cap is None:
+            key_cap = max(1 << 16, 8 * entry_cap)
+        h = ctypes.c_void_p()
+        _check(lib().as_frame_create_batch(ctx.handle, ctypes.c_int32(max_views), ctypes.c_int64(entry_cap),
+                                           ctypes.c_int64(pixel_cap), ctypes.c_int64(tile_cap),
+                                           ctypes.c_int64(key_cap), ctypes.c_int32(1 if auto_grow else 0),
+                                           ctypes.byref(h)))
+        self.ctx, self.handle, self.n_cap, self.max_views = ctx, h, entry_cap, max_views
+
+    @staticmethod
+    def for_views(ctx, n_per_view, cams, key_cap=None, auto_grow=True):
+        """A frame sized for exactly these views (n_per_view: int or list)."""
+        ns = n_per_view if isinstance(n_per_view, (list, tuple)) else [n_per_view] * len(cams)
+        tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+        return BatchFrame(ctx, len(cams), sum(ns), sum(c.width * c.height for c in cams), tiles, key_cap, auto_grow)
 
 
 _hiprt = None
@@ -303,6 +345,73 @@ def render_backward(ctx, g, cam, frame, dL_dimage, grads=None, g2d_norm=None, vi
     _check(lib().as_render_backward(ctx.handle, ctypes.byref(gs), ctypes.byref(c), frame.handle, _ptr(dL_dimage),
                                     ctypes.byref(gm), _ptr(g2d_norm), _ptr(vis_count), _stream(stream)))
     return grads
+
+
+def render_batch(ctx, scenes, cams, frame, gts=None, images=None, stream=None):
+    """as_render_batch: scenes is one Gaussians (shared by every view) or a
+    list with one per view; returns the list of images [3,H_v,W_v]."""
+    V = len(cams)
+    if not isinstance(scenes, (list, tuple)):
+        scenes = [scenes] * V
+    if images is None:
+        images = [torch.empty(3, c.height, c.width, dtype=torch.float32, device="cuda") for c in cams]
+    ss = (_Gaussians * V)(*[g.struct() for g in scenes])
+    cs = (_Camera * V)(*[camera_struct(c) for c in cams])
+    ims = (ctypes.c_void_p * V)(*[_ptr(t).value for t in images])
+    gp = (ctypes.c_void_p * V)(*[_ptr(t).value for t in gts]) if gts is not None else None
+    _check(lib().as_render_batch(ctx.handle, ss, cs, ctypes.c_int32(V), frame.handle, gp, ims, _stream(stream)))
+    return images
+
+
+def render_backward_batch(ctx, g, frame, dL_dimages, grads=None, g2d_norm=None, vis_count=None, stream=None):
+    """as_render_backward_batch: gradients summed over the views of the last
+    batched render of g."""
+    if grads is None:
+        grads = Gaussians.empty(g.n, g.sh_degree)
+    gs = g.struct()
+    gm = _GaussiansMut.of(grads)
+    V = len(dL_dimages)
+    dl = (ctypes.c_void_p * V)(*[_ptr(t).value for t in dL_dimages])
+    _check(lib().as_render_backward_batch(ctx.handle, ctypes.byref(gs), frame.handle, dl, ctypes.byref(gm),
+                                          _ptr(g2d_norm), _ptr(vis_count), _stream(stream)))
+    return grads
+
+
+class Graph:
+    """A HIP graph of library calls recorded on one stream (as_graph_*)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    @staticmethod
+    def capture(ctx, fn, stream):
+        """Record fn() on `stream` (a torch.cuda.Stream, not the null stream)."""
+        s = ctypes.c_void_p(stream.cuda_stream)
+        _check(lib().as_graph_begin(ctx.handle, s))
+        h = ctypes.c_void_p()
+        try:
+            with torch.cuda.stream(stream):
+                fn()
+        except BaseException:
+            if lib().as_graph_end(ctx.handle, s, ctypes.byref(h)) == AS_OK:
+                lib().as_graph_destroy(h)
+            raise
+        _check(lib().as_graph_end(ctx.handle, s, ctypes.byref(h)))
+        return Graph(h)
+
+    def launch(self, stream):
+        _check(lib().as_graph_launch(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if self.handle:
+            lib().as_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class _GaussiansMut(_Gaussians):
@@ -383,6 +492,23 @@ def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=
                                    _ptr(count) if nc else None, _ptr(offset) if nc else None, _ptr(n_out),
                                    _stream(stream)))
     return out, mode[:nc], count[:nc], offset[:nc], n_out
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("lds_batch", ctypes.c_int32), ("longest_first", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("radix_bits", ctypes.c_int32)]
+
+
+def set_tuning(ctx, lds_batch=256, longest_first=True, persistent=False, radix_bits=8):
+    t = _Tuning(lds_batch, 1 if longest_first else 0, 1 if persistent else 0, radix_bits)
+    _check(lib().as_set_tuning(ctx.handle, ctypes.byref(t)))
+
+
+def get_tuning(ctx):
+    t = _Tuning()
+    _check(lib().as_get_tuning(ctx.handle, ctypes.byref(t)))
+    return dict(lds_batch=t.lds_batch, longest_first=bool(t.longest_first), persistent=bool(t.persistent),
+                radix_bits=t.radix_bits)
 
 
 def timing_enable(ctx, on=True):

@@ -11,6 +11,7 @@
 
 namespace {
 thread_local char g_err[1024] = "";
+thread_local int g_capturing = 0;   // inside as_graph_begin / as_graph_end on this thread
 
 bool bad(hipError_t e, const char *what) {
     if (e == hipSuccess) return false;
@@ -113,6 +114,7 @@ void as_set_error(const char *fmt, ...) {
 
 hipError_t devbuf_ensure(DevBuf &b, size_t bytes) {
     if (b.p && b.bytes >= bytes) return hipSuccess;
+    if (g_capturing) return hipErrorStreamCaptureUnsupported;   // no allocation inside a capture
     if (b.p) {
         (void)hipFree(b.p);
         b.p = nullptr;
@@ -151,7 +153,7 @@ static void pool_put(as_ctx *c, hipEvent_t e) {
 }
 
 StageTimer::StageTimer(as_ctx *c, int st, hipStream_t str) : ctx(c), stage(st), s(str) {
-    if (!ctx || !ctx->timing) return;
+    if (!ctx || !ctx->timing || g_capturing) return;
     beg = pool_get(ctx);
     if (beg) (void)hipEventRecord(beg, s);
 }
@@ -189,6 +191,7 @@ as_status as_ctx_create(int device, as_ctx **out) {
     as_ctx *c = new (std::nothrow) as_ctx();
     if (!c) { as_set_error("as_ctx_create: out of host memory"); return AS_ERR_HIP; }
     c->device = device;
+    c->n_cu = prop.multiProcessorCount;
     *out = c;
     return AS_OK;
 }
@@ -214,7 +217,7 @@ void as_frame_destroy(as_frame *f) {
     (void)hipSetDevice(f->ctx->device);
     void *ptrs[] = {f->rec, f->depth_key, f->box, f->ntiles, f->offsets, f->grad2d, f->ranges, f->n_keys,
                     f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax, f->dkeys[0], f->dkeys[1],
-                    f->dvals[0], f->dvals[1], f->nt_sorted, f->n_gauss};
+                    f->dvals[0], f->dvals[1], f->nt_sorted, f->n_ent, f->tile_order, f->queue};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_keys(f);
@@ -223,6 +226,43 @@ void as_frame_destroy(as_frame *f) {
     devbuf_free(f->dsort_hist);
     if (f->h_nkeys) (void)hipHostFree(f->h_nkeys);
     delete f;
+}
+
+static as_status frame_alloc(as_ctx *ctx, int32_t max_views, int64_t ent_cap, int64_t pix_cap, int64_t tile_cap,
+                             int64_t key_cap, int32_t auto_grow, int32_t fixed_w, int32_t fixed_h, as_frame **out) {
+    if (bad(hipSetDevice(ctx->device), "hipSetDevice")) return AS_ERR_HIP;
+    as_frame *f = new (std::nothrow) as_frame();
+    if (!f) { as_set_error("as_frame_create: out of host memory"); return AS_ERR_HIP; }
+    f->ctx = ctx;
+    f->max_views = max_views;
+    f->fixed_w = fixed_w;
+    f->fixed_h = fixed_h;
+    f->auto_grow = auto_grow;
+    f->ent_cap = ent_cap;
+    f->pix_cap = pix_cap;
+    f->tile_cap = tile_cap;
+    hipError_t e = hipSuccess;
+    if ((e = dmalloc(&f->rec, ent_cap)) != hipSuccess || (e = dmalloc(&f->depth_key, ent_cap)) != hipSuccess ||
+        (e = dmalloc(&f->box, ent_cap * 4)) != hipSuccess || (e = dmalloc(&f->ntiles, ent_cap)) != hipSuccess ||
+        (e = dmalloc(&f->offsets, ent_cap)) != hipSuccess || (e = dmalloc(&f->grad2d, ent_cap * 9)) != hipSuccess ||
+        (e = dmalloc(&f->ranges, tile_cap * 2)) != hipSuccess || (e = dmalloc(&f->n_keys, 4)) != hipSuccess ||
+        (e = dmalloc(&f->tile_order, tile_cap)) != hipSuccess || (e = dmalloc(&f->queue, 2)) != hipSuccess ||
+        (e = dmalloc(&f->t_final, pix_cap)) != hipSuccess || (e = dmalloc(&f->last, pix_cap)) != hipSuccess ||
+        (e = dmalloc(&f->n_contrib, pix_cap)) != hipSuccess || (e = dmalloc(&f->dom, pix_cap)) != hipSuccess ||
+        (e = dmalloc(&f->err, pix_cap)) != hipSuccess || (e = dmalloc(&f->err_minmax, 2 * max_views)) != hipSuccess ||
+        (e = dmalloc(&f->dkeys[0], ent_cap)) != hipSuccess || (e = dmalloc(&f->dkeys[1], ent_cap)) != hipSuccess ||
+        (e = dmalloc(&f->dvals[0], ent_cap)) != hipSuccess || (e = dmalloc(&f->dvals[1], ent_cap)) != hipSuccess ||
+        (e = dmalloc(&f->nt_sorted, ent_cap)) != hipSuccess || (e = dmalloc(&f->n_ent, 4)) != hipSuccess ||
+        (e = devbuf_ensure(f->dsort_hist, sort_hist_bytes(ent_cap))) != hipSuccess ||
+        (e = alloc_keys(f, key_cap)) != hipSuccess ||
+        (e = devbuf_ensure(f->scan_tmp, scan_tmp_bytes(ent_cap))) != hipSuccess ||
+        (e = hipHostMalloc((void **)&f->h_nkeys, 64, hipHostMallocDefault)) != hipSuccess) {
+        as_set_error("as_frame_create: allocation failed: %s", hipGetErrorString(e));
+        as_frame_destroy(f);
+        return AS_ERR_HIP;
+    }
+    *out = f;
+    return AS_OK;
 }
 
 as_status as_frame_create(as_ctx *ctx, int64_t n_cap, int32_t width, int32_t height, int64_t key_cap,
@@ -235,87 +275,145 @@ as_status as_frame_create(as_ctx *ctx, int64_t n_cap, int32_t width, int32_t hei
                      height, (long long)key_cap);
         return AS_ERR_ARG;
     }
-    if (bad(hipSetDevice(ctx->device), "hipSetDevice")) return AS_ERR_HIP;
-    as_frame *f = new (std::nothrow) as_frame();
-    if (!f) { as_set_error("as_frame_create: out of host memory"); return AS_ERR_HIP; }
-    f->ctx = ctx;
-    f->n_cap = n_cap;
-    f->W = width;
-    f->H = height;
-    f->tiles_x = (width + AS_TILE_W - 1) / AS_TILE_W;
-    f->tiles_y = (height + AS_TILE_H - 1) / AS_TILE_H;
-    f->auto_grow = auto_grow;
-    const int64_t P = (int64_t)width * height, tiles = (int64_t)f->tiles_x * f->tiles_y;
-    hipError_t e = hipSuccess;
-    if ((e = dmalloc(&f->rec, n_cap)) != hipSuccess || (e = dmalloc(&f->depth_key, n_cap)) != hipSuccess ||
-        (e = dmalloc(&f->box, n_cap * 4)) != hipSuccess || (e = dmalloc(&f->ntiles, n_cap)) != hipSuccess ||
-        (e = dmalloc(&f->offsets, n_cap)) != hipSuccess || (e = dmalloc(&f->grad2d, n_cap * 9)) != hipSuccess ||
-        (e = dmalloc(&f->ranges, tiles * 2)) != hipSuccess || (e = dmalloc(&f->n_keys, 4)) != hipSuccess ||
-        (e = dmalloc(&f->t_final, P)) != hipSuccess || (e = dmalloc(&f->last, P)) != hipSuccess ||
-        (e = dmalloc(&f->n_contrib, P)) != hipSuccess || (e = dmalloc(&f->dom, P)) != hipSuccess ||
-        (e = dmalloc(&f->err, P)) != hipSuccess || (e = dmalloc(&f->err_minmax, 2)) != hipSuccess ||
-        (e = dmalloc(&f->dkeys[0], n_cap)) != hipSuccess || (e = dmalloc(&f->dkeys[1], n_cap)) != hipSuccess ||
-        (e = dmalloc(&f->dvals[0], n_cap)) != hipSuccess || (e = dmalloc(&f->dvals[1], n_cap)) != hipSuccess ||
-        (e = dmalloc(&f->nt_sorted, n_cap)) != hipSuccess || (e = dmalloc(&f->n_gauss, 4)) != hipSuccess ||
-        (e = devbuf_ensure(f->dsort_hist, sort_hist_bytes(n_cap))) != hipSuccess ||
-        (e = alloc_keys(f, key_cap)) != hipSuccess || (e = devbuf_ensure(f->scan_tmp, scan_tmp_bytes(n_cap))) != hipSuccess ||
-        (e = hipHostMalloc((void **)&f->h_nkeys, 64, hipHostMallocDefault)) != hipSuccess) {
-        as_set_error("as_frame_create: allocation failed: %s", hipGetErrorString(e));
-        as_frame_destroy(f);
-        return AS_ERR_HIP;
-    }
-    *out = f;
-    return AS_OK;
+    const int64_t tiles = (int64_t)((width + AS_TILE_W - 1) / AS_TILE_W) * ((height + AS_TILE_H - 1) / AS_TILE_H);
+    return frame_alloc(ctx, 1, n_cap, (int64_t)width * height, tiles, key_cap, auto_grow, width, height, out);
 }
 
-as_status as_frame_get_view(const as_frame *f, as_frame_view *v) {
+as_status as_frame_create_batch(as_ctx *ctx, int32_t max_views, int64_t entry_cap, int64_t pixel_cap,
+                                int64_t tile_cap, int64_t key_cap, int32_t auto_grow, as_frame **out) {
+    if (!ctx || !out) { as_set_error("as_frame_create_batch: null argument"); return AS_ERR_ARG; }
+    *out = nullptr;
+    if (max_views < 1 || max_views > AS_MAX_VIEWS || entry_cap < 1 || entry_cap > 0xFFFFFFFFll || pixel_cap < 1 ||
+        pixel_cap > 0x7FFFFFFFll || tile_cap < 1 || tile_cap > 0x7FFFFFFFll || key_cap < 1 || key_cap > 0xFFFFFFFFll) {
+        as_set_error("as_frame_create_batch: size out of range (views %d, entries %lld, pixels %lld, tiles %lld, "
+                     "keys %lld)", max_views, (long long)entry_cap, (long long)pixel_cap, (long long)tile_cap,
+                     (long long)key_cap);
+        return AS_ERR_ARG;
+    }
+    return frame_alloc(ctx, max_views, entry_cap, pixel_cap, tile_cap, key_cap, auto_grow, 0, 0, out);
+}
+
+as_status as_frame_get_view_of(const as_frame *f, int32_t view, as_frame_view *v) {
     if (!f || !v) { as_set_error("as_frame_get_view: null argument"); return AS_ERR_ARG; }
-    v->width = f->W; v->height = f->H; v->tile_w = AS_TILE_W; v->tile_h = AS_TILE_H;
-    v->tiles_x = f->tiles_x; v->tiles_y = f->tiles_y;
-    v->n_cap = f->n_cap; v->key_cap = f->key_cap;
+    const ViewTable &vt = f->vt;
+    if (!(view == 0 && !f->has_render) && (view < 0 || view >= vt.n_views)) {
+        as_set_error("as_frame_get_view: view %d not in the last render", view);
+        return AS_ERR_ARG;
+    }
+    const bool have = f->has_render && view < vt.n_views;
+    const int W = have ? vt.cam[view].W : f->fixed_w, H = have ? vt.cam[view].H : f->fixed_h;
+    const int64_t pb = have ? vt.pix_base[view] : 0;
+    const uint32_t eb = have ? vt.ent_base[view] : 0;
+    const int32_t tb = have ? vt.tile_base[view] : 0;
+    v->width = W; v->height = H; v->tile_w = AS_TILE_W; v->tile_h = AS_TILE_H;
+    v->tiles_x = (W + AS_TILE_W - 1) / AS_TILE_W;
+    v->tiles_y = (H + AS_TILE_H - 1) / AS_TILE_H;
+    v->n_cap = have ? (int64_t)(vt.ent_base[view + 1] - eb) : f->ent_cap;
+    v->key_cap = f->key_cap;
+    v->tile_base = tb;
+    v->ent_base = eb;
     v->n_keys = f->n_keys;
     v->keys = f->keys[f->sorted_sel];
     v->vals = f->vals[f->sorted_sel];
-    v->ranges = f->ranges;
-    v->depth_key = f->depth_key;
-    v->box = f->box;
-    v->ntiles = f->ntiles;
-    v->rec = reinterpret_cast<float *>(f->rec);
-    v->t_final = f->t_final; v->last = f->last; v->n_contrib = f->n_contrib; v->dom = f->dom;
-    v->err = f->err; v->err_minmax = f->err_minmax; v->grad2d = f->grad2d;
+    v->ranges = f->ranges + 2 * (int64_t)tb;
+    v->depth_key = f->depth_key + eb;
+    v->box = f->box + 4 * (int64_t)eb;
+    v->ntiles = f->ntiles + eb;
+    v->rec = reinterpret_cast<float *>(f->rec + eb);
+    v->t_final = f->t_final + pb; v->last = f->last + pb; v->n_contrib = f->n_contrib + pb; v->dom = f->dom + pb;
+    v->err = f->err + pb;
+    v->err_minmax = f->err_minmax + 2 * (have ? view : 0);
+    v->grad2d = f->grad2d + eb;
+    v->grad2d_stride = f->ent_cap;
     return AS_OK;
 }
 
-as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as_frame *f, const float *gt,
-                    float *image, void *stream) {
-    if (!ctx || !cam || !f || !image) { as_set_error("as_render: null argument"); return AS_ERR_ARG; }
-    if (!check_gauss(g, "as_render")) return AS_ERR_ARG;
-    if (g->n > f->n_cap) {
-        as_set_error("as_render: %lld Gaussians exceed the frame capacity %lld", (long long)g->n, (long long)f->n_cap);
-        return AS_ERR_CAPACITY;
-    }
-    if (cam->width != f->W || cam->height != f->H) {
-        as_set_error("as_render: camera %dx%d does not match the frame %dx%d", cam->width, cam->height, f->W, f->H);
+as_status as_frame_get_view(const as_frame *f, as_frame_view *v) { return as_frame_get_view_of(f, 0, v); }
+
+static bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+    return cs == hipStreamCaptureStatusActive;
+}
+
+as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_camera *cams, int32_t n_views,
+                          as_frame *f, const float *const *gt, float *const *images, void *stream) {
+    if (!ctx || !scenes || !cams || !f || !images) { as_set_error("as_render: null argument"); return AS_ERR_ARG; }
+    if (n_views < 1 || n_views > f->max_views) {
+        as_set_error("as_render: %d views for a frame of at most %d", n_views, f->max_views);
         return AS_ERR_ARG;
     }
-    if (!(cam->fx > 0.f) || !(cam->fy > 0.f)) { as_set_error("as_render: focal lengths must be positive"); return AS_ERR_ARG; }
     hipStream_t s = (hipStream_t)stream;
-    const GaussPtrs gp = gptrs(g);
-    const DevCam dc = to_devcam(*cam);
-    const int64_t n = g->n, tiles = (int64_t)f->tiles_x * f->tiles_y;
+    ViewTable vt;
+    memset(&vt, 0, sizeof(vt));
+    SceneTable sc;
+    memset(&sc, 0, sizeof(sc));
+    ViewImages im;
+    ViewImagesC gi;
+    memset(&im, 0, sizeof(im));
+    memset(&gi, 0, sizeof(gi));
+    vt.n_views = n_views;
+    int64_t ents = 0, pix = 0, tiles = 0, max_n = 0;
+    const int deg = scenes[0].sh_degree;
+    for (int v = 0; v < n_views; v++) {
+        const as_gaussians *g = &scenes[v];
+        const as_camera *c = &cams[v];
+        if (!check_gauss(g, "as_render")) return AS_ERR_ARG;
+        if (g->sh_degree != deg) { as_set_error("as_render: views mix SH degrees %d and %d", deg, g->sh_degree); return AS_ERR_ARG; }
+        if (!images[v] || (gt && !gt[v])) { as_set_error("as_render: null image or target of view %d", v); return AS_ERR_ARG; }
+        if (c->width < 1 || c->height < 1 || c->width > 32767 || c->height > 32767) {
+            as_set_error("as_render: view %d size %dx%d out of range", v, c->width, c->height);
+            return AS_ERR_ARG;
+        }
+        if (f->fixed_w && (c->width != f->fixed_w || c->height != f->fixed_h)) {
+            as_set_error("as_render: camera %dx%d does not match the frame %dx%d", c->width, c->height, f->fixed_w,
+                         f->fixed_h);
+            return AS_ERR_ARG;
+        }
+        if (!(c->fx > 0.f) || !(c->fy > 0.f)) { as_set_error("as_render: focal lengths must be positive"); return AS_ERR_ARG; }
+        const int tx = (c->width + AS_TILE_W - 1) / AS_TILE_W, ty = (c->height + AS_TILE_H - 1) / AS_TILE_H;
+        vt.tile_base[v] = (int32_t)tiles;
+        vt.tiles_x[v] = tx;
+        vt.ent_base[v] = (uint32_t)ents;
+        vt.pix_base[v] = pix;
+        vt.cam[v] = to_devcam(*c);
+        sc.g[v] = gptrs(g);
+        im.p[v] = images[v];
+        gi.p[v] = gt ? gt[v] : nullptr;
+        ents += g->n;
+        pix += (int64_t)c->width * c->height;
+        tiles += (int64_t)tx * ty;
+        if (g->n > max_n) max_n = g->n;
+        if (ents > f->ent_cap || pix > f->pix_cap || tiles > f->tile_cap) {
+            as_set_error("as_render: the views need %lld entries, %lld pixels, %lld tiles; the frame holds %lld, %lld, "
+                         "%lld", (long long)ents, (long long)pix, (long long)tiles, (long long)f->ent_cap,
+                         (long long)f->pix_cap, (long long)f->tile_cap);
+            return AS_ERR_CAPACITY;
+        }
+    }
+    vt.tile_base[n_views] = (int32_t)tiles;
+    vt.ent_base[n_views] = (uint32_t)ents;
+    vt.pix_base[n_views] = pix;
+    const bool cap = capturing(s);
+    if (cap && f->auto_grow) {
+        as_set_error("as_render: a frame with auto_grow synchronises and cannot be captured");
+        return AS_ERR_STATE;
+    }
+    const int64_t n = ents;
     f->has_render = 0;
     {
         StageTimer t(ctx, AS_STAGE_PROJECT, s);
-        launch_project(gp, dc, f->tiles_x, f->rec, f->depth_key, f->box, f->ntiles, s);
+        launch_project(sc, vt, max_n, deg, f->rec, f->depth_key, f->box, f->ntiles, s);
     }
-    // Depth-first binning: a stable sort of the Gaussians by depth, keys
-    // emitted in that order, then a stable sort on the tile bits alone, gives
-    // the same order as sorting (tile | depth) keys emitted by id.
+    // Depth-first binning: a stable sort of the entries by depth, keys
+    // emitted in that order, then a stable sort on the tile ids alone, gives
+    // every tile the order of a stable sort of (tile | depth) keys emitted by id.
     const uint32_t *order;
     {
         StageTimer t(ctx, AS_STAGE_SORT, s);
-        launch_depth_pairs(n, f->depth_key, f->dkeys[0], f->dvals[0], f->n_gauss, s);
-        const int dsel = radix_sort_pairs_range(f->dkeys, f->dvals, f->n_gauss, f->n_cap, n, 0, 32, f->dsort_hist.p, s);
+        launch_depth_pairs(n, f->depth_key, f->dkeys[0], f->dvals[0], f->n_ent, s);
+        const int dsel = radix_sort_u32(f->dkeys, f->dvals, f->n_ent, f->ent_cap, n, 0, 32, ctx->radix_bits,
+                                        f->dsort_hist.p, s);
         order = f->dvals[dsel];
     }
     {
@@ -331,69 +429,113 @@ as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as
         const int64_t K = *f->h_nkeys;
         if (K > f->key_cap) {
             free_keys(f);
-            int64_t cap = K + K / 4 + 1024;
-            if (cap > 0xFFFFFFFFll) cap = 0xFFFFFFFFll;
-            if (bad(alloc_keys(f, cap), "as_render: growing the key buffers")) return AS_ERR_HIP;
+            int64_t kc = K + K / 4 + 1024;
+            if (kc > 0xFFFFFFFFll) kc = 0xFFFFFFFFll;
+            if (bad(alloc_keys(f, kc), "as_render: growing the key buffers")) return AS_ERR_HIP;
         }
         n_hint = K;
     }
     {
         StageTimer t(ctx, AS_STAGE_EMIT, s);
-        launch_emit_sorted(n, order, f->depth_key, f->box, f->ntiles, f->offsets, f->tiles_x, f->key_cap, f->keys[0],
-                           f->vals[0], s);
+        launch_emit_sorted(n, order, vt, f->box, f->ntiles, f->offsets, f->key_cap, f->keys[0], f->vals[0], s);
     }
     int sel;
     {
         StageTimer t(ctx, AS_STAGE_SORT, s);
-        sel = radix_sort_pairs_range(f->keys, f->vals, f->n_keys, f->key_cap, n_hint, 32, 32 + tile_bits(tiles),
-                                     f->sort_hist.p, s);
+        sel = radix_sort_u32(f->keys, f->vals, f->n_keys, f->key_cap, n_hint, 0, tile_bits(tiles), ctx->radix_bits,
+                             f->sort_hist.p, s);
     }
     f->sorted_sel = sel;
     {
         StageTimer t(ctx, AS_STAGE_RANGES, s);
         launch_ranges(f->keys[sel], f->n_keys, f->key_cap, tiles, f->ranges, s);
+        f->use_order = ctx->longest_first;
+        if (f->use_order) launch_tile_order(f->ranges, (int)tiles, f->tile_order, s);
     }
     if (gt) {
-        launch_fill_u64(f->err_minmax, 0x7ff0000000000000ull, 1, s);
-        launch_fill_u64(f->err_minmax + 1, 0ull, 1, s);
+        for (int v = 0; v < n_views; v++) {
+            launch_fill_u64(f->err_minmax + 2 * v, 0x7ff0000000000000ull, 1, s);
+            launch_fill_u64(f->err_minmax + 2 * v + 1, 0ull, 1, s);
+        }
     }
+    const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
     {
         StageTimer t(ctx, AS_STAGE_BLEND_FWD, s);
-        launch_blend_fwd(f, f->vals[sel], dc, gt, image, s);
+        launch_blend_fwd(f, f->vals[sel], f->use_order ? f->tile_order : nullptr, bl, vt, gi, im, s);
     }
     const as_status st = launch_status("as_render");
     if (st != AS_OK) return st;
     f->has_render = 1;
-    f->n_last = n;
-    f->deg_last = g->sh_degree;
+    f->vt = vt;
+    f->scenes = sc;
     f->has_gt = gt != nullptr;
+    f->persistent_last = ctx->persistent;
     return AS_OK;
+}
+
+as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as_frame *f, const float *gt,
+                    float *image, void *stream) {
+    if (!ctx || !g || !cam || !f || !image) { as_set_error("as_render: null argument"); return AS_ERR_ARG; }
+    if (!f->fixed_w) { as_set_error("as_render: a batch frame takes as_render_batch"); return AS_ERR_ARG; }
+    const float *gts[1] = {gt};
+    float *ims[1] = {image};
+    return as_render_batch(ctx, g, cam, 1, f, gt ? gts : nullptr, ims, stream);
+}
+
+static bool same_set(const GaussPtrs &a, const as_gaussians *g) {
+    return a.means == g->means && a.log_scales == g->log_scales && a.quats == g->quats &&
+           a.opac == g->opacity_logits && a.sh == g->sh && a.n == g->n && a.deg == g->sh_degree;
+}
+
+as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame *f, const float *const *dL_dimages,
+                                   as_gaussians_mut *grads, float *g2d_norm, int32_t *vis_count, void *stream) {
+    if (!ctx || !f || !dL_dimages) { as_set_error("as_render_backward: null argument"); return AS_ERR_ARG; }
+    if (!check_gauss(g, "as_render_backward")) return AS_ERR_ARG;
+    if (!f->has_render) { as_set_error("as_render_backward: the frame holds no render"); return AS_ERR_STATE; }
+    const ViewTable &vt = f->vt;
+    for (int v = 0; v < vt.n_views; v++) {
+        if (!same_set(f->scenes.g[v], g)) {
+            as_set_error("as_render_backward: view %d of the last render used another Gaussian set", v);
+            return AS_ERR_STATE;
+        }
+        if (!dL_dimages[v]) { as_set_error("as_render_backward: null gradient image of view %d", v); return AS_ERR_ARG; }
+    }
+    if (!check_mut(grads, g->n, g->sh_degree, "as_render_backward")) return AS_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    ViewImagesC dl;
+    memset(&dl, 0, sizeof(dl));
+    for (int v = 0; v < vt.n_views; v++) dl.p[v] = dL_dimages[v];
+    const int64_t ents = vt.ent_base[vt.n_views];
+    const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
+    {
+        StageTimer t(ctx, AS_STAGE_BLEND_BWD, s);
+        for (int k = 0; k < 9; k++)
+            launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d + k * f->ent_cap), 0u, ents, s);
+        launch_blend_bwd(f, f->vals[f->sorted_sel], f->use_order ? f->tile_order : nullptr, bl, vt, dl, f->grad2d,
+                         f->ent_cap, s);
+    }
+    {
+        StageTimer t(ctx, AS_STAGE_PROJECT_BWD, s);
+        launch_project_bwd(gptrs(g), vt, f->ntiles, f->grad2d, f->ent_cap, mptrs(grads), g2d_norm, vis_count, s);
+    }
+    return launch_status("as_render_backward");
 }
 
 as_status as_render_backward(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as_frame *f,
                              const float *dL_dimage, as_gaussians_mut *grads, float *g2d_norm, int32_t *vis_count,
                              void *stream) {
     if (!ctx || !cam || !f || !dL_dimage) { as_set_error("as_render_backward: null argument"); return AS_ERR_ARG; }
-    if (!check_gauss(g, "as_render_backward")) return AS_ERR_ARG;
-    if (!f->has_render || f->n_last != g->n || f->deg_last != g->sh_degree) {
-        as_set_error("as_render_backward: the frame holds no render of these Gaussians");
+    if (f->has_render && f->vt.n_views == 1 &&
+        (cam->width != f->vt.cam[0].W || cam->height != f->vt.cam[0].H)) {
+        as_set_error("as_render_backward: camera/frame size mismatch");
+        return AS_ERR_ARG;
+    }
+    if (f->has_render && f->vt.n_views != 1) {
+        as_set_error("as_render_backward: the last render had %d views; use as_render_backward_batch", f->vt.n_views);
         return AS_ERR_STATE;
     }
-    if (cam->width != f->W || cam->height != f->H) { as_set_error("as_render_backward: camera/frame size mismatch"); return AS_ERR_ARG; }
-    if (!check_mut(grads, g->n, g->sh_degree, "as_render_backward")) return AS_ERR_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t n = g->n;
-    const DevCam dc = to_devcam(*cam);
-    {
-        StageTimer t(ctx, AS_STAGE_BLEND_BWD, s);
-        launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9 * n, s);
-        launch_blend_bwd(f, f->vals[f->sorted_sel], dc, dL_dimage, f->grad2d, n, s);
-    }
-    {
-        StageTimer t(ctx, AS_STAGE_PROJECT_BWD, s);
-        launch_project_bwd(gptrs(g), dc, f->ntiles, f->grad2d, n, mptrs(grads), g2d_norm, vis_count, s);
-    }
-    return launch_status("as_render_backward");
+    const float *dl[1] = {dL_dimage};
+    return as_render_backward_batch(ctx, g, f, dl, grads, g2d_norm, vis_count, stream);
 }
 
 as_status as_error_map(as_ctx *ctx, int32_t width, int32_t height, const float *image, const float *gt, double *err,
@@ -467,6 +609,32 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
     return launch_status("as_adaptive_split");
 }
 
+as_status as_set_tuning(as_ctx *ctx, const as_tuning *t) {
+    if (!ctx || !t) { as_set_error("as_set_tuning: null argument"); return AS_ERR_ARG; }
+    if (t->lds_batch != 256 && t->lds_batch != 512 && t->lds_batch != 1024) {
+        as_set_error("as_set_tuning: lds_batch %d not in {256, 512, 1024}", t->lds_batch);
+        return AS_ERR_ARG;
+    }
+    if (t->radix_bits < 4 || t->radix_bits > 8) {
+        as_set_error("as_set_tuning: radix_bits %d not in 4..8", t->radix_bits);
+        return AS_ERR_ARG;
+    }
+    ctx->lds_batch = t->lds_batch;
+    ctx->longest_first = t->longest_first != 0;
+    ctx->persistent = t->persistent != 0;
+    ctx->radix_bits = t->radix_bits;
+    return AS_OK;
+}
+
+as_status as_get_tuning(const as_ctx *ctx, as_tuning *t) {
+    if (!ctx || !t) { as_set_error("as_get_tuning: null argument"); return AS_ERR_ARG; }
+    t->lds_batch = ctx->lds_batch;
+    t->longest_first = ctx->longest_first;
+    t->persistent = ctx->persistent;
+    t->radix_bits = ctx->radix_bits;
+    return AS_OK;
+}
+
 as_status as_timing_enable(as_ctx *ctx, int32_t on) {
     if (!ctx) { as_set_error("as_timing_enable: null context"); return AS_ERR_ARG; }
     ctx->timing = on != 0;
@@ -494,6 +662,56 @@ as_status as_timing_read(as_ctx *ctx, double *ms, int64_t *runs) {
     return st;
 }
 
+struct as_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+as_status as_graph_begin(as_ctx *ctx, void *stream) {
+    if (!ctx || !stream) { as_set_error("as_graph_begin: needs a context and a non-null stream"); return AS_ERR_ARG; }
+    if (g_capturing) { as_set_error("as_graph_begin: a capture is already open on this thread"); return AS_ERR_STATE; }
+    if (bad(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal), "as_graph_begin"))
+        return AS_ERR_HIP;
+    g_capturing = 1;
+    return AS_OK;
+}
+
+as_status as_graph_end(as_ctx *ctx, void *stream, as_graph **out) {
+    if (!ctx || !stream || !out) { as_set_error("as_graph_end: null argument"); return AS_ERR_ARG; }
+    *out = nullptr;
+    if (!g_capturing) { as_set_error("as_graph_end: no capture open on this thread"); return AS_ERR_STATE; }
+    g_capturing = 0;
+    hipGraph_t g = nullptr;
+    if (bad(hipStreamEndCapture((hipStream_t)stream, &g), "as_graph_end")) return AS_ERR_HIP;
+    as_graph *gr = new (std::nothrow) as_graph();
+    if (!gr) {
+        (void)hipGraphDestroy(g);
+        as_set_error("as_graph_end: out of host memory");
+        return AS_ERR_HIP;
+    }
+    gr->graph = g;
+    if (bad(hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0), "as_graph_end: instantiate")) {
+        (void)hipGraphDestroy(g);
+        delete gr;
+        return AS_ERR_HIP;
+    }
+    *out = gr;
+    return AS_OK;
+}
+
+as_status as_graph_launch(as_graph *graph, void *stream) {
+    if (!graph) { as_set_error("as_graph_launch: null graph"); return AS_ERR_ARG; }
+    if (bad(hipGraphLaunch(graph->exec, (hipStream_t)stream), "as_graph_launch")) return AS_ERR_HIP;
+    return AS_OK;
+}
+
+void as_graph_destroy(as_graph *graph) {
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+}
+
 as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, int32_t key_bits, void *stream) {
     if (!ctx || (n > 0 && (!keys || !vals)) || n < 0 || n > 0xFFFFFFFFll || key_bits < 0 || key_bits > 64) {
         as_set_error("as_debug_sort_pairs: bad argument");
@@ -508,7 +726,7 @@ as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64
     uint32_t *vv[2] = {vals, (uint32_t *)ctx->dbg[1].p};
     uint32_t *n_dev = (uint32_t *)ctx->dbg[3].p;
     launch_fill_u32(n_dev, (uint32_t)n, 1, s);
-    const int sel = radix_sort_pairs(kk, vv, n_dev, n, n, key_bits, ctx->dbg[2].p, s);
+    const int sel = radix_sort_u64(kk, vv, n_dev, n, n, 0, key_bits, ctx->radix_bits, ctx->dbg[2].p, s);
     if (sel == 1) {
         if (bad(hipMemcpyAsync(keys, kk[1], n * 8, hipMemcpyDeviceToDevice, s), "sort copy-back") ||
             bad(hipMemcpyAsync(vals, vv[1], n * 4, hipMemcpyDeviceToDevice, s), "sort copy-back"))

@@ -1,10 +1,12 @@
-// Tile binning: exclusive scans, (tile | depth) key emission, a stable LSD radix
-// sort on 8-bit digits staged through LDS, and per-tile ranges.
+// Tile binning: exclusive scans, tile key emission, a stable LSD radix sort
+// staged through LDS, and per-tile ranges.
 //
 // The rasterizer composites each pixel over the Gaussians in ascending
-// (depth, id) order (Sec. 3, front-to-back blending); sorting the keys
-// tile << 32 | float_bits(depth) stably, after emitting them in ascending id
-// order, gives every tile its list in exactly that order.
+// (depth, id) order (Sec. 3, front-to-back blending).  The host sorts the
+// entries stably by the float bits of their depth (ids ascending on ties),
+// emits each entry's tile ids in that order, and sorts the (tile, entry) pairs
+// stably on the tile id alone: every tile's list then comes out in exactly
+// the order a stable sort of tile << 32 | depth keys emitted by id gives.
 #include "internal.h"
 
 namespace {
@@ -116,57 +118,68 @@ void scan_impl(const Tin *in, Tout *out, int64_t n, Tout *total, void *tmp, hipS
 
 // ---- key emission -------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_emit(int64_t n, const uint32_t *__restrict__ depth_key,
-                                              const short4 *__restrict__ box, const uint32_t *__restrict__ ntiles,
-                                              const uint32_t *__restrict__ offsets, int tiles_x, int64_t key_cap,
-                                              uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t nt = ntiles[i];
-    if (nt == 0) return;
-    const uint64_t off = offsets[i];
-    if (off + nt > (uint64_t)key_cap) return;   // over capacity: the count tells the caller
-    const short4 b = box[i];
-    const uint64_t dk = depth_key[i];
-    const int tx0 = b.x / AS_TILE_W, tx1 = b.z / AS_TILE_W, ty0 = b.y / AS_TILE_H, ty1 = b.w / AS_TILE_H;
-    uint64_t k = off;
-    for (int ty = ty0; ty <= ty1; ty++)
-        for (int tx = tx0; tx <= tx1; tx++) {
-            keys[k] = ((uint64_t)(ty * tiles_x + tx) << 32) | dk;
-            vals[k] = (uint32_t)i;
-            k++;
-        }
-}
-
-// Keys of one Gaussian, emitted in depth order: rank r holds Gaussian order[r]
-// and writes its keys at offsets[r] (the scan of ntiles in that order).
-__global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *__restrict__ order,
-                                                     const uint32_t *__restrict__ depth_key,
+// Tile keys in depth order: rank r holds entry order[r] and owns key positions
+// [offsets[r], offsets[r] + ntiles) (the scan of ntiles in that order), its
+// tiles row-major over its tile rectangle, as global tile ids of its view.
+// Consecutive ranks own consecutive positions, so a wave writes one contiguous
+// run of keys: each lane takes positions lane, lane + 64, ... of the run and
+// finds its owner among the wave's 64 ranks by binary search over their
+// offsets, which keeps the stores coalesced whatever the per-entry tile
+// counts are.
+__global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *__restrict__ order, const ViewTable vt,
                                                      const short4 *__restrict__ box,
                                                      const uint32_t *__restrict__ ntiles,
-                                                     const uint32_t *__restrict__ offsets, int tiles_x, int64_t key_cap,
-                                                     uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const uint32_t i = order[r];
-    const uint32_t nt = ntiles[i];
-    if (nt == 0) return;
-    const uint64_t off = offsets[r];
-    if (off + nt > (uint64_t)key_cap) return;   // over capacity: the count tells the caller
-    const short4 b = box[i];
-    const uint64_t dk = depth_key[i];
-    const int tx0 = b.x / AS_TILE_W, tx1 = b.z / AS_TILE_W, ty0 = b.y / AS_TILE_H, ty1 = b.w / AS_TILE_H;
-    uint64_t k = off;
-    for (int ty = ty0; ty <= ty1; ty++)
-        for (int tx = tx0; tx <= tx1; tx++) {
-            keys[k] = ((uint64_t)(ty * tiles_x + tx) << 32) | dk;
-            vals[k] = i;
-            k++;
+                                                     const uint32_t *__restrict__ offsets, int64_t key_cap,
+                                                     uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    __shared__ uint32_t s_off[4][64], s_id[4][64], s_nt[4][64];
+    __shared__ int32_t s_t0[4][64], s_bw[4][64], s_tx[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x + w * 64;
+    if (r0 >= n) return;   // wave-uniform
+    const int64_t r = r0 + lane;
+    uint32_t nt = 0, off = 0xFFFFFFFFu, e = 0;
+    uint64_t end = 0;
+    if (r < n) {
+        e = order[r];
+        nt = ntiles[e];
+        off = offsets[r];
+        end = (uint64_t)off + nt;
+        if (nt) {
+            const int v = view_of_entry(vt, e);
+            const short4 b = box[e];
+            const int tx0 = b.x / AS_TILE_W, ty0 = b.y / AS_TILE_H;
+            s_t0[w][lane] = vt.tile_base[v] + ty0 * vt.tiles_x[v] + tx0;
+            s_bw[w][lane] = b.z / AS_TILE_W - tx0 + 1;
+            s_tx[w][lane] = vt.tiles_x[v];
         }
+    }
+    s_off[w][lane] = off;   // non-decreasing over the valid ranks; the sentinel sorts last
+    s_id[w][lane] = e;
+    s_nt[w][lane] = nt;
+    for (int o = 32; o > 0; o >>= 1) end = max(end, (uint64_t)__shfl_xor((unsigned long long)end, o, 64));
+    const uint64_t beg = (uint32_t)__shfl((int)off, 0, 64);   // lane 0 is a valid rank
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t lim = end < (uint64_t)key_cap ? end : (uint64_t)key_cap;
+    for (uint64_t pos = beg + lane; pos < lim; pos += 64) {
+        // the last rank whose first position is <= pos owns pos (ranks with no
+        // tiles share their successor's offset and are passed over)
+        int lo = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)   // probes stay within 1..63
+            if ((uint64_t)s_off[w][lo + step] <= pos) lo += step;
+        const uint64_t o = s_off[w][lo];
+        if (o + s_nt[w][lo] > (uint64_t)key_cap) continue;   // an entry that does not fit is dropped whole
+        const uint32_t q = (uint32_t)(pos - o), bw = (uint32_t)s_bw[w][lo];
+        const uint32_t qy = q / bw, qx = q - qy * bw;
+        keys[pos] = (uint32_t)s_t0[w][lo] + qy * (uint32_t)s_tx[w][lo] + qx;
+        vals[pos] = s_id[w][lo];
+    }
 }
 
-// (depth key, id) pairs of every Gaussian for the depth sort.
-__global__ void k_depth_pairs(int64_t n, const uint32_t *__restrict__ depth_key, uint64_t *__restrict__ keys,
+// (depth key, entry) pairs of every entry for the depth sort.
+__global__ void k_depth_pairs(int64_t n, const uint32_t *__restrict__ depth_key, uint32_t *__restrict__ keys,
                               uint32_t *__restrict__ vals, uint32_t *__restrict__ n32) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *n32 = (uint32_t)n;
@@ -182,6 +195,12 @@ __global__ void k_gather_u32(int64_t n, const uint32_t *__restrict__ src, const 
 }
 
 // ---- LSD radix sort --------------------------------------------------------------------
+//
+// One pass per digit of RB bits: a per-block digit histogram (block-major
+// chunks of the input), an exclusive scan of the digit-major histogram, and a
+// stable scatter.  Inside a block, a wave ranks its 64 keys among equal digits
+// with RB ballots (lanes whose digit matches bit by bit), and per-wave digit
+// counters in LDS carry the running offsets across the wave's rounds.
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_TILE = 1024;   // keys per block iteration: 4 waves x 4 rounds x 64 lanes
@@ -193,55 +212,62 @@ __device__ __forceinline__ void rs_chunk(int64_t n, int G, int b, int64_t *beg, 
     *end = *beg + chunk < n ? *beg + chunk : n;
 }
 
-__global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *__restrict__ kin, const uint32_t *n_dev,
-                                                           int64_t cap, int shift, uint32_t *__restrict__ hist) {
-    __shared__ uint32_t s_h[4][256];
+template <typename K, int RB>
+__global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const K *__restrict__ kin, const uint32_t *n_dev,
+                                                           int64_t cap, int shift, uint32_t mask,
+                                                           uint32_t *__restrict__ hist) {
+    constexpr int NB = 1 << RB;
+    __shared__ uint32_t s_h[4][NB];
     const int tid = threadIdx.x, w = tid >> 6;
-    for (int k = 0; k < 4; k++) s_h[k][tid] = 0;
+    if (tid < NB)
+        for (int k = 0; k < 4; k++) s_h[k][tid] = 0;
     __syncthreads();
     int64_t n = *n_dev;
     if (n > cap) n = cap;
     int64_t beg, end;
     rs_chunk(n, gridDim.x, blockIdx.x, &beg, &end);
     for (int64_t idx = beg + tid; idx < end; idx += RS_THREADS) {
-        const uint32_t d = (uint32_t)(kin[idx] >> shift) & 255u;
+        const uint32_t d = (uint32_t)(kin[idx] >> shift) & mask;
         atomicAdd(&s_h[w][d], 1u);
     }
     __syncthreads();
-    hist[(int64_t)tid * gridDim.x + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
+    if (tid < NB) hist[(int64_t)tid * gridDim.x + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
 }
 
-__global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *__restrict__ kin,
-                                                              const uint32_t *__restrict__ vin,
-                                                              uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                              const uint32_t *n_dev, int64_t cap, int shift,
+template <typename K, int RB>
+__global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const K *__restrict__ kin,
+                                                              const uint32_t *__restrict__ vin, K *__restrict__ kout,
+                                                              uint32_t *__restrict__ vout, const uint32_t *n_dev,
+                                                              int64_t cap, int shift, uint32_t mask,
                                                               const uint32_t *__restrict__ hist) {
-    __shared__ uint32_t s_base[256];
-    __shared__ uint32_t s_cnt[4][256];
+    constexpr int NB = 1 << RB;
+    __shared__ uint32_t s_base[NB];
+    __shared__ uint32_t s_cnt[4][NB];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     int64_t n = *n_dev;
     if (n > cap) n = cap;
     int64_t beg, end;
     rs_chunk(n, gridDim.x, blockIdx.x, &beg, &end);
-    s_base[tid] = hist[(int64_t)tid * gridDim.x + blockIdx.x];
+    if (tid < NB) s_base[tid] = hist[(int64_t)tid * gridDim.x + blockIdx.x];
     const uint64_t lt = lanemask_lt();
     for (int64_t t0 = beg; t0 < end; t0 += RS_TILE) {
-        for (int k = 0; k < 4; k++) s_cnt[k][tid] = 0;
+        if (tid < NB)
+            for (int k = 0; k < 4; k++) s_cnt[k][tid] = 0;
         __syncthreads();
-        uint64_t key[4];
+        K key[4];
         uint32_t val[4], dig[4], loc[4];
         bool ok[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int64_t idx = t0 + w * 256 + j * 64 + lane;
             ok[j] = idx < end;
-            key[j] = ok[j] ? kin[idx] : 0ull;
+            key[j] = ok[j] ? kin[idx] : (K)0;
             val[j] = ok[j] ? vin[idx] : 0u;
-            const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
+            const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
             dig[j] = d;
             uint64_t peers = __ballot(ok[j]);
 #pragma unroll
-            for (int bit = 0; bit < 8; bit++) {
+            for (int bit = 0; bit < RB; bit++) {
                 const bool set = (d >> bit) & 1u;
                 const uint64_t m = __ballot(set);
                 peers &= set ? m : ~m;
@@ -254,7 +280,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *__
             loc[j] = before + rank;
         }
         __syncthreads();
-        {
+        if (tid < NB) {
             const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
             const uint32_t base = s_base[tid];
             s_cnt[0][tid] = base;
@@ -276,15 +302,17 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *__
     }
 }
 
-__global__ void k_ranges(const uint64_t *__restrict__ keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles,
+// [start, end) of every tile in the sorted tile keys (tiles without keys keep
+// the [0, 0) the caller filled).
+__global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles,
                          uint32_t *__restrict__ ranges) {
     int64_t n = *n_dev;
     if (n > cap) n = cap;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t t = keys[i] >> 32;
+        const uint32_t t = keys[i];
         if (t >= (uint64_t)n_tiles) continue;
-        if (i == 0 || (keys[i - 1] >> 32) != t) ranges[2 * t] = (uint32_t)i;
-        if (i == n - 1 || (keys[i + 1] >> 32) != t) ranges[2 * t + 1] = (uint32_t)(i + 1);
+        if (i == 0 || keys[i - 1] != t) ranges[2 * t] = (uint32_t)i;
+        if (i == n - 1 || keys[i + 1] != t) ranges[2 * t + 1] = (uint32_t)(i + 1);
     }
 }
 
@@ -311,6 +339,49 @@ void fill_impl(T *p, T v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
 }
 
+int rs_grid(int64_t n_hint) {
+    int64_t g = (n_hint + 8 * RS_TILE - 1) / (8 * RS_TILE);
+    if (g < 1) g = 1;
+    if (g > 2048) g = 2048;
+    return (int)g;
+}
+
+template <typename K, int RB>
+void radix_pass(K *kin, uint32_t *vin, K *kout, uint32_t *vout, const uint32_t *n_dev, int64_t cap, int G, int shift,
+                int width, uint32_t *h, void *tmp, hipStream_t s) {
+    const uint32_t mask = (1u << width) - 1u;   // width <= RB: digits above the range stay out
+    hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(G), dim3(RS_THREADS), 0, s, kin, n_dev, cap, shift, mask, h);
+    scan_impl<uint32_t, uint32_t>(h, h, (int64_t)(1 << RB) * G, (uint32_t *)nullptr, tmp, s);
+    hipLaunchKernelGGL((k_radix_scatter<K, RB>), dim3(G), dim3(RS_THREADS), 0, s, kin, vin, kout, vout, n_dev, cap,
+                       shift, mask, h);
+}
+
+template <typename K>
+int radix_sort_impl(K *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
+                    int hi_bit, int rb, void *hist, hipStream_t s) {
+    const int G = rs_grid(n_hint);
+    uint32_t *h = reinterpret_cast<uint32_t *>(hist);
+    void *tmp = reinterpret_cast<char *>(hist) + (size_t)(256 * G) * 4;
+    if (rb < 4) rb = 4;
+    if (rb > 8) rb = 8;
+    int sel = 0;
+    for (int shift = lo_bit; shift < hi_bit; shift += rb) {
+        // the last digit needs only the bits that are left
+        const int w = hi_bit - shift < rb ? hi_bit - shift : rb;
+        K *ki = keys[sel], *ko = keys[sel ^ 1];
+        uint32_t *vi = vals[sel], *vo = vals[sel ^ 1];
+        switch (w) {
+        case 1: case 2: case 3: case 4: radix_pass<K, 4>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
+        case 5: radix_pass<K, 5>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
+        case 6: radix_pass<K, 6>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
+        case 7: radix_pass<K, 7>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
+        default: radix_pass<K, 8>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
+        }
+        sel ^= 1;
+    }
+    return sel;
+}
+
 }  // namespace
 
 size_t scan_tmp_bytes(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE + 1) * 8 + 256; }
@@ -325,48 +396,22 @@ void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total,
     scan_impl<int32_t, int64_t>(in, out, n, total, tmp, s);
 }
 
-void launch_emit_keys(int64_t n, const uint32_t *depth_key, const int16_t *box, const uint32_t *ntiles,
-                      const uint32_t *offsets, int tiles_x, int64_t key_cap, uint64_t *keys, uint32_t *vals,
-                      hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, depth_key,
-                       reinterpret_cast<const short4 *>(box), ntiles, offsets, tiles_x, key_cap, keys, vals);
-}
-
-static int rs_grid(int64_t n_hint) {
-    int64_t g = (n_hint + 8 * RS_TILE - 1) / (8 * RS_TILE);
-    if (g < 1) g = 1;
-    if (g > 2048) g = 2048;
-    return (int)g;
-}
-
 size_t sort_hist_bytes(int64_t n_hint) {
     const int64_t G = rs_grid(n_hint);
     return (size_t)(256 * G) * 4 + scan_tmp_bytes(256 * G) + 64;
 }
 
-int radix_sort_pairs(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint,
-                     int key_bits, void *hist, hipStream_t s) {
-    return radix_sort_pairs_range(keys, vals, n_dev, cap, n_hint, 0, key_bits, hist, s);
+int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
+                   int hi_bit, int radix_bits, void *hist, hipStream_t s) {
+    return radix_sort_impl<uint32_t>(keys, vals, n_dev, cap, n_hint, lo_bit, hi_bit, radix_bits, hist, s);
 }
 
-int radix_sort_pairs_range(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint,
-                           int lo_bit, int hi_bit, void *hist, hipStream_t s) {
-    const int G = rs_grid(n_hint);
-    uint32_t *h = reinterpret_cast<uint32_t *>(hist);
-    void *tmp = reinterpret_cast<char *>(hist) + (size_t)(256 * G) * 4;
-    int sel = 0;
-    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(RS_THREADS), 0, s, keys[sel], n_dev, cap, shift, h);
-        scan_impl<uint32_t, uint32_t>(h, h, (int64_t)256 * G, (uint32_t *)nullptr, tmp, s);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(RS_THREADS), 0, s, keys[sel], vals[sel], keys[sel ^ 1],
-                           vals[sel ^ 1], n_dev, cap, shift, h);
-        sel ^= 1;
-    }
-    return sel;
+int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
+                   int hi_bit, int radix_bits, void *hist, hipStream_t s) {
+    return radix_sort_impl<uint64_t>(keys, vals, n_dev, cap, n_hint, lo_bit, hi_bit, radix_bits, hist, s);
 }
 
-void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint64_t *keys, uint32_t *vals, uint32_t *n32,
+void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals, uint32_t *n32,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_depth_pairs, dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)), dim3(256), 0, s, n,
                        depth_key, keys, vals, n32);
@@ -377,15 +422,15 @@ void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint
     hipLaunchKernelGGL(k_gather_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, src, idx, dst);
 }
 
-void launch_emit_sorted(int64_t n, const uint32_t *order, const uint32_t *depth_key, const int16_t *box,
-                        const uint32_t *ntiles, const uint32_t *offsets, int tiles_x, int64_t key_cap, uint64_t *keys,
+void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
+                        const uint32_t *ntiles, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
                         uint32_t *vals, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_emit_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order, depth_key,
-                       reinterpret_cast<const short4 *>(box), ntiles, offsets, tiles_x, key_cap, keys, vals);
+    hipLaunchKernelGGL(k_emit_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order, vt,
+                       reinterpret_cast<const short4 *>(box), ntiles, offsets, key_cap, keys, vals);
 }
 
-void launch_ranges(const uint64_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
+void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
                    hipStream_t s) {
     fill_impl<uint32_t>(ranges, 0u, 2 * n_tiles, s);
     hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, s, keys, n_dev, cap, n_tiles, ranges);

@@ -3,13 +3,24 @@
 // error of Eq. (l1map) fused into the same traversal, and the matching reverse
 // pass.
 //
-// One 16x16 tile per 256-thread block; each wave64 owns an 8x8 quadrant.
-// Gaussian records are staged through LDS in batches of 256.  A staged
-// record carries the Gaussian's pixel box as two 16-bit masks over the tile's
-// columns and rows: a wave skips a Gaussian whose box misses its quadrant
-// (wave-uniform branch), and a pixel outside the box never composites it, so
-// the contributor set is exactly {box holds the pixel, alpha >= 1/255}.  A
-// block stops fetching once all 256 pixels have saturated.
+// Work decomposition (gfx950, wave64): one 16x16 tile per 256-thread block;
+// the tile is cut into sixteen 4x4 pixel blocks and each 16-lane row of a
+// wave owns one of them.  Gaussian records are staged through LDS in batches
+// of BATCH records (the tunable "LDS depth"; each thread fetches BATCH/256
+// records one batch ahead, so the gather latency overlaps the previous batch's
+// blending).  A staged record carries the Gaussian's pixel box as two 16-bit
+// masks over the tile's columns and rows.  After staging, every row compacts
+// the indices of the records whose box meets its 4x4 block (ballots), so a
+// wave advances four rows through four different Gaussians per instruction,
+// and a pixel outside a box never composites it: the contributor set is
+// exactly {box holds the pixel, alpha >= 1/255}.  A block stops fetching once
+// all 256 pixels have saturated.
+//
+// One launch covers every tile of every view of a batch (global tile ids;
+// each view's size, camera, pixel and entry ranges come from the view table).
+// Tiles are visited in a given order (longest list first) and either one
+// block per tile, or by a persistent grid sized to the resident capacity of
+// the device whose blocks pull tile after tile from a global atomic queue.
 //
 // Alpha is evaluated as exp2(q) with q = a' dx^2 + b' dx dy + c' dy^2 + log2(o)
 // (conic pre-scaled by -log2(e)/2, opacity folded into the exponent); the
@@ -42,74 +53,182 @@ __device__ __forceinline__ uint32_t span_mask(int lo, int hi) {   // bits lo..hi
     return ((2u << hi) - 1u) & ~((1u << lo) - 1u);
 }
 
-// Stage Gaussian `id` for the tile at (ox, oy).
-__device__ __forceinline__ void stage_record(const BlendRec *__restrict__ rec, const short4 *__restrict__ box,
-                                             uint32_t id, int ox, int oy, StagedRec &s, float &blue,
-                                             uint32_t &mask) {
-#pragma clang fp contract(off)
-    const BlendRec r = rec[id];
-    const short4 b = box[id];
-    const float mx = (r.m.x - (float)ox) + r.m.z;
-    const float my = (r.m.y - (float)oy) + r.m.w;
-    const float k = -0.5f * LOG2E;
-    s.mc = make_float4(mx, my, k * r.c.x, -LOG2E * r.c.y);
-    s.cc = make_float4(k * r.c.z, __log2f(r.c.w), r.rgb.x, r.rgb.y);
-    blue = r.rgb.z;
-    mask = span_mask(b.x - ox, b.z - ox) | (span_mask(b.y - oy, b.w - oy) << 16);
+// Registers of one record fetched ahead of its batch.
+struct Fetched {
+    BlendRec r;
+    short4 b;
+    uint32_t id;
+};
+
+__device__ __forceinline__ void fetch(const uint32_t *__restrict__ vals, const BlendRec *__restrict__ rec,
+                                      const short4 *__restrict__ box, uint32_t idx, Fetched &f) {
+    f.id = vals[idx];
+    f.r = rec[f.id];
+    f.b = box[f.id];
 }
 
+__device__ __forceinline__ void stage(const Fetched &f, int ox, int oy, StagedRec *s_rec, float *s_blue,
+                                      int32_t *s_id, uint32_t *s_mask, int t) {
+#pragma clang fp contract(off)
+    const float mx = (f.r.m.x - (float)ox) + f.r.m.z;
+    const float my = (f.r.m.y - (float)oy) + f.r.m.w;
+    const float k = -0.5f * LOG2E;
+    StagedRec sr;
+    sr.mc = make_float4(mx, my, k * f.r.c.x, -LOG2E * f.r.c.y);
+    sr.cc = make_float4(k * f.r.c.z, __log2f(f.r.c.w), f.r.rgb.x, f.r.rgb.y);
+    s_rec[t] = sr;
+    s_blue[t] = f.r.rgb.z;
+    s_id[t] = (int32_t)f.id;
+    s_mask[t] = span_mask(f.b.x - ox, f.b.z - ox) | (span_mask(f.b.y - oy, f.b.w - oy) << 16);
+}
+
+// Pixel geometry of a lane: 16-lane row `row` of wave w owns 4x4 block
+// sb = 4 w + row of the tile (blocks in row-major order).
+struct LaneGeom {
+    int lx, ly, row;
+    uint32_t bx, by;   // the block's column / row bits in a record's box masks
+};
+
+__device__ __forceinline__ LaneGeom lane_geom(int tid) {
+    LaneGeom g;
+    const int w = tid >> 6, lane = tid & 63;
+    g.row = lane >> 4;
+    const int sb = w * 4 + g.row, c = lane & 15;
+    const int sbx = sb & 3, sby = sb >> 2;
+    g.lx = sbx * 4 + (c & 3);
+    g.ly = sby * 4 + (c >> 2);
+    g.bx = 0xFu << (sbx * 4);
+    g.by = (0xFu << (sby * 4)) << 16;
+    return g;
+}
+
+// For each row of this wave, the indices j < cnt (ascending) of the staged
+// records whose box meets the row's 4x4 block, into hits[row][..]; returns
+// this lane's row count.  `ok(j)` adds a condition that is the same for the
+// whole wave.
+template <int BATCH, typename Ok>
+__device__ __forceinline__ int compact_rows(const uint32_t *s_mask, int cnt, uint16_t (*hits)[BATCH], int w, int row,
+                                            Ok ok) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lanemask_lt();
+    // the four blocks of wave w: sb = 4w + r -> sbx = r (w even: blocks 0-3 of a block row)
+    const int sby = w;   // sb = 4 w + r -> sby = w, sbx = r
+    const uint32_t by = (0xFu << (sby * 4)) << 16;
+    int n[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < BATCH / 64; k++) {
+        const int j = k * 64 + lane;
+        const uint32_t m = j < cnt ? s_mask[j] : 0u;
+        const bool any = (m & by) && ok(j);
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const bool hit = any && (m & (0xFu << (r * 4)));
+            const uint64_t bal = __ballot(hit);
+            if (hit) hits[r][n[r] + __popcll(bal & lt)] = (uint16_t)j;
+            n[r] += __popcll(bal);
+        }
+    }
+    return row == 0 ? n[0] : row == 1 ? n[1] : row == 2 ? n[2] : n[3];
+}
+
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, true));
+}
+
+// Sum over the 16 lanes of each DPP row; the row's total lands in its lane 15
+// (every lane of the wave must be active).
+__device__ __forceinline__ float row_sum_to_lane15(float v0) {
+    float v = v0 + dpp_f<0x111, 0xf, 0xf>(v0);   // row_shr:1
+    v += dpp_f<0x112, 0xf, 0xf>(v0);              // row_shr:2
+    v += dpp_f<0x113, 0xf, 0xf>(v0);              // row_shr:3  -> lanes hold sums of 4
+    v += dpp_f<0x114, 0xf, 0xe>(v);               // row_shr:4 into banks 1-3
+    v += dpp_f<0x118, 0xf, 0xc>(v);               // row_shr:8 into banks 2-3
+    return v;
+}
+
+template <int BATCH>
+struct BlendShared {
+    StagedRec rec[BATCH];
+    float blue[BATCH];
+    int32_t id[BATCH];
+    uint32_t mask[BATCH];
+    uint16_t hits[AS_BLOCK / 64][4][BATCH];
+};
+
+// Next tile of this block: a queue slot (persistent grid) or the block index;
+// returns false when the block is done.
+template <bool PERSIST>
+__device__ __forceinline__ bool next_tile(uint32_t *queue, int n_tiles, int iter, uint32_t &idx, uint32_t *s_next) {
+    if (!PERSIST) {
+        idx = blockIdx.x;
+        return iter == 0 && idx < (uint32_t)n_tiles;
+    }
+    if (threadIdx.x == 0) *s_next = atomicAdd(queue, 1u);
+    __syncthreads();
+    idx = *s_next;
+    __syncthreads();   // all have read the slot before thread 0 takes the next one
+    return idx < (uint32_t)n_tiles;
+}
+
+template <int BATCH, bool PERSIST>
 __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restrict__ ranges,
+                                                        const uint32_t *__restrict__ tile_order,
                                                         const uint32_t *__restrict__ vals,
                                                         const BlendRec *__restrict__ rec,
-                                                        const short4 *__restrict__ box, DevCam cam, int tiles_x,
-                                                        const float *__restrict__ gt, float *__restrict__ image,
+                                                        const short4 *__restrict__ box, const ViewTable vt,
+                                                        const ViewImagesC gts, const ViewImages images,
                                                         float *__restrict__ t_final, uint32_t *__restrict__ last_out,
                                                         uint32_t *__restrict__ ncontrib_out,
                                                         int32_t *__restrict__ dom_out, double *__restrict__ err,
-                                                        unsigned long long *__restrict__ minmax) {
-    __shared__ StagedRec s_rec[AS_BLOCK];
-    __shared__ float s_blue[AS_BLOCK];
-    __shared__ int32_t s_id[AS_BLOCK];
-    __shared__ uint32_t s_mask[AS_BLOCK];
+                                                        unsigned long long *__restrict__ minmax, uint32_t *queue,
+                                                        int n_tiles) {
+    constexpr int R = BATCH / AS_BLOCK;
+    __shared__ BlendShared<BATCH> sh;
+    __shared__ uint32_t s_next;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int tile = blockIdx.x;
-    const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int qx = (w & 1) * 8, qy = (w >> 1) * 8;
-    const int lx = qx + (lane & 7), ly = qy + (lane >> 3);
-    const int ox = tx * AS_TILE_W, oy = ty * AS_TILE_H;
-    const int x = ox + lx, y = oy + ly;
-    const bool inside = x < cam.W && y < cam.H;
-    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
-    const uint32_t qmx = 0xFFu << qx, qmy = (0xFFu << qy) << 16;
-    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const LaneGeom lg = lane_geom(tid);
+    const uint16_t *hits = sh.hits[w][lg.row];
+    const float px = (float)lg.lx + 0.5f, py = (float)lg.ly + 0.5f;
+    uint32_t idx;
+    for (int iter = 0; next_tile<PERSIST>(queue, n_tiles, iter, idx, &s_next); iter++) {
+        const int tile = tile_order ? (int)tile_order[idx] : (int)idx;
+        const int v = view_of_tile(vt, tile);
+        const int lt = tile - vt.tile_base[v], tiles_x = vt.tiles_x[v];
+        const int W = vt.cam[v].W, H = vt.cam[v].H;
+        const int tx = lt % tiles_x, ty = lt / tiles_x;
+        const int ox = tx * AS_TILE_W, oy = ty * AS_TILE_H;
+        const int x = ox + lg.lx, y = oy + lg.ly;
+        const bool inside = x < W && y < H;
+        const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
 
-    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, wbest = 0.f;
-    int32_t dom = -1;
-    uint32_t last = 0, nc = 0;
-    int done = inside ? 0 : 1;
+        float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, wbest = 0.f;
+        int32_t dom = -1;
+        uint32_t last = 0, nc = 0;
+        int done = inside ? 0 : 1;
 
-    for (uint32_t b0 = start; b0 < end; b0 += AS_BLOCK) {
-        if (__syncthreads_count(done) == AS_BLOCK) break;
-        const uint32_t idx = b0 + tid;
-        if (idx < end) {
-            const uint32_t id = vals[idx];
-            StagedRec sr;
-            float blue;
-            uint32_t m;
-            stage_record(rec, box, id, ox, oy, sr, blue, m);
-            s_rec[tid] = sr;
-            s_blue[tid] = blue;
-            s_id[tid] = (int32_t)id;
-            s_mask[tid] = m;
-        }
-        __syncthreads();
-        if (!done) {
-            const int cnt = (int)min((uint32_t)AS_BLOCK, end - b0);
-            for (int j = 0; j < cnt; j++) {
-                const uint32_t m = s_mask[j];
-                if (!(m & qmx) || !(m & qmy)) continue;            // box misses this quadrant
-                if (!((m >> lx) & (m >> (16 + ly)) & 1u)) continue;  // box misses this pixel
-                const StagedRec r = s_rec[j];
+        Fetched nf[R];
+#pragma unroll
+        for (int k = 0; k < R; k++)
+            if (start + k * AS_BLOCK + tid < end) fetch(vals, rec, box, start + k * AS_BLOCK + tid, nf[k]);
+        for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
+            if (__syncthreads_count(done) == AS_BLOCK) break;   // also: the previous batch is consumed
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const int t = k * AS_BLOCK + tid;
+                if (b0 + t < end) stage(nf[k], ox, oy, sh.rec, sh.blue, sh.id, sh.mask, t);
+                if (b0 + BATCH + t < end) fetch(vals, rec, box, b0 + BATCH + t, nf[k]);
+            }
+            __syncthreads();
+            if (__ballot(!done) == 0) continue;                 // the whole wave has saturated
+            const int cnt = (int)min((uint32_t)BATCH, end - b0);
+            const int nh = compact_rows<BATCH>(sh.mask, cnt, sh.hits[w], w, lg.row, [](int) { return true; });
+            if (done) continue;
+            for (int h = 0; h < nh; h++) {
+                const int j = hits[h];
+                const uint32_t m = sh.mask[j];
+                if (!((m >> lg.lx) & (m >> (16 + lg.ly)) & 1u)) continue;   // box misses this pixel
+                const StagedRec r = sh.rec[j];
                 const float dx = r.mc.x - px, dy = r.mc.y - py;
                 const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, r));
                 const float alpha = fminf(ALPHA_MAX, araw);
@@ -122,47 +241,49 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                 const float wgt = alpha * T;
                 C0 += wgt * r.cc.z;
                 C1 += wgt * r.cc.w;
-                C2 += wgt * s_blue[j];
+                C2 += wgt * sh.blue[j];
                 if (wgt > wbest) {
                     wbest = wgt;
-                    dom = s_id[j];
+                    dom = sh.id[j];
                 }
                 T = testT;
                 last = b0 + (uint32_t)j;
                 nc++;
             }
         }
-    }
 
-    double e = 0.0;
-    if (inside) {
-        const int64_t P = (int64_t)cam.W * cam.H;
-        const int64_t pix = (int64_t)y * cam.W + x;
-        const float r0 = C0 + T * cam.bg[0];
-        const float r1 = C1 + T * cam.bg[1];
-        const float r2 = C2 + T * cam.bg[2];
-        image[pix] = r0;
-        image[P + pix] = r1;
-        image[2 * P + pix] = r2;
-        t_final[pix] = T;
-        last_out[pix] = last;
-        ncontrib_out[pix] = nc;
-        dom_out[pix] = dom;
-        if (gt) {
-            const double d0 = fabs((double)r0 - (double)gt[pix]);
-            const double d1 = fabs((double)r1 - (double)gt[P + pix]);
-            const double d2 = fabs((double)r2 - (double)gt[2 * P + pix]);
-            e = (d0 + d1) + d2;
-            err[pix] = e;
+        const float *gt = gts.p[v];
+        double e = 0.0;
+        if (inside) {
+            const int64_t P = (int64_t)W * H;
+            const int64_t pl = (int64_t)y * W + x, pix = vt.pix_base[v] + pl;
+            float *image = images.p[v];
+            const float r0 = C0 + T * vt.cam[v].bg[0];
+            const float r1 = C1 + T * vt.cam[v].bg[1];
+            const float r2 = C2 + T * vt.cam[v].bg[2];
+            image[pl] = r0;
+            image[P + pl] = r1;
+            image[2 * P + pl] = r2;
+            t_final[pix] = T;
+            last_out[pix] = last;
+            ncontrib_out[pix] = nc;
+            dom_out[pix] = dom < 0 ? -1 : dom - (int32_t)vt.ent_base[v];
+            if (gt) {
+                const double d0 = fabs((double)r0 - (double)gt[pl]);
+                const double d1 = fabs((double)r1 - (double)gt[P + pl]);
+                const double d2 = fabs((double)r2 - (double)gt[2 * P + pl]);
+                e = (d0 + d1) + d2;
+                err[pix] = e;
+            }
         }
-    }
-    if (gt) {
-        // e >= 0, so the IEEE bit patterns order like the values
-        const double emin = wave_min_d(inside ? e : __longlong_as_double(0x7ff0000000000000ll));
-        const double emax = wave_max_d(inside ? e : 0.0);
-        if (lane == 0) {
-            atomicMin(&minmax[0], (unsigned long long)__double_as_longlong(emin));
-            atomicMax(&minmax[1], (unsigned long long)__double_as_longlong(emax));
+        if (gt) {
+            // e >= 0, so the IEEE bit patterns order like the values
+            const double emin = wave_min_d(inside ? e : __longlong_as_double(0x7ff0000000000000ll));
+            const double emax = wave_max_d(inside ? e : 0.0);
+            if (lane == 0) {
+                atomicMin(&minmax[2 * v], (unsigned long long)__double_as_longlong(emin));
+                atomicMax(&minmax[2 * v + 1], (unsigned long long)__double_as_longlong(emax));
+            }
         }
     }
 }
@@ -173,150 +294,279 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
 // where A_k is the colour composited behind k normalised by T_{k+1}; walking
 // the list backwards from the last contributor restores T_k = T_{k+1}/(1-a_k)
 // and A_k incrementally.  Gradients reach (o, conic, mean) only where
-// alpha = o G is below the 0.99 clamp.  Each wave reduces its 64 pixels'
-// gradients of a Gaussian before one set of atomics.
+// alpha = o G is below the 0.99 clamp.  Each row sums its 16 pixels' nine
+// gradients of a Gaussian with DPP, lane 15 adds them into the batch slot of
+// that Gaussian in LDS, and after the batch one pass issues the global
+// atomics: one set per (Gaussian, tile).
+template <int BATCH, bool PERSIST>
 __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restrict__ ranges,
+                                                        const uint32_t *__restrict__ tile_order,
                                                         const uint32_t *__restrict__ vals,
                                                         const BlendRec *__restrict__ rec,
-                                                        const short4 *__restrict__ box, DevCam cam, int tiles_x,
+                                                        const short4 *__restrict__ box, const ViewTable vt,
                                                         const float *__restrict__ t_final,
                                                         const uint32_t *__restrict__ last_in,
                                                         const uint32_t *__restrict__ ncontrib_in,
-                                                        const float *__restrict__ dL_dimage, float *__restrict__ grad2d,
-                                                        int64_t stride) {
-    __shared__ StagedRec s_rec[AS_BLOCK];
-    __shared__ float s_blue[AS_BLOCK];
-    __shared__ int32_t s_id[AS_BLOCK];
-    __shared__ uint32_t s_mask[AS_BLOCK];
+                                                        const ViewImagesC dLs, float *__restrict__ grad2d,
+                                                        int64_t stride, uint32_t *queue, int n_tiles) {
+    constexpr int R = BATCH / AS_BLOCK;
+    __shared__ BlendShared<BATCH> sh;
+    __shared__ float s_gacc[9][BATCH];
+    __shared__ uint32_t s_gflag[BATCH];
     __shared__ uint32_t s_maxlast;
+    __shared__ uint32_t s_next;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int tile = blockIdx.x;
-    const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int qx = (w & 1) * 8, qy = (w >> 1) * 8;
-    const int lx = qx + (lane & 7), ly = qy + (lane >> 3);
-    const int ox = tx * AS_TILE_W, oy = ty * AS_TILE_H;
-    const int x = ox + lx, y = oy + ly;
-    const bool inside = x < cam.W && y < cam.H;
-    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
-    const uint32_t qmx = 0xFFu << qx, qmy = (0xFFu << qy) << 16;
-    const uint32_t start = ranges[2 * tile];
-
-    const int64_t P = (int64_t)cam.W * cam.H;
-    const int64_t pix = (int64_t)y * cam.W + x;
-    float T = 1.0f, Tfin = 1.0f, dL0 = 0.f, dL1 = 0.f, dL2 = 0.f;
-    uint32_t lastp = 0;
-    bool has = false;
-    if (inside) {
-        Tfin = t_final[pix];
-        T = Tfin;
-        has = ncontrib_in[pix] > 0;
-        lastp = last_in[pix];
-        dL0 = dL_dimage[pix];
-        dL1 = dL_dimage[P + pix];
-        dL2 = dL_dimage[2 * P + pix];
-    }
-    const float bgdot = cam.bg[0] * dL0 + cam.bg[1] * dL1 + cam.bg[2] * dL2;
-    if (tid == 0) s_maxlast = 0;
-    __syncthreads();
-    if (has) atomicMax(&s_maxlast, lastp + 1);
-    __syncthreads();
-    const uint32_t hi_end = s_maxlast > start ? s_maxlast : start;   // one past the block's last contributor
-    // one past the wave's last contributor (wave-uniform)
-    uint32_t wlast = has ? lastp + 1 : 0;
-    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
-
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, last_alpha = 0.f, lc0 = 0.f, lc1 = 0.f, lc2 = 0.f;
-
-    for (uint32_t b1 = hi_end; b1 > start;) {
-        const uint32_t b0 = b1 - start > (uint32_t)AS_BLOCK ? b1 - AS_BLOCK : start;
-        const uint32_t idx = b0 + tid;
-        if (idx < b1) {
-            const uint32_t id = vals[idx];
-            StagedRec sr;
-            float blue;
-            uint32_t m;
-            stage_record(rec, box, id, ox, oy, sr, blue, m);
-            s_rec[tid] = sr;
-            s_blue[tid] = blue;
-            s_id[tid] = (int32_t)id;
-            s_mask[tid] = m;
-        }
-        __syncthreads();
-        for (int j = (int)(b1 - b0) - 1; j >= 0; j--) {
-            const uint32_t gidx = b0 + (uint32_t)j;
-            if (gidx >= wlast) continue;                        // beyond every pixel of this wave
-            const uint32_t m = s_mask[j];
-            if (!(m & qmx) || !(m & qmy)) continue;             // box misses this quadrant
-            float g[9];
+    const LaneGeom lg = lane_geom(tid);
+    const uint16_t *hits = sh.hits[w][lg.row];
+    const float px = (float)lg.lx + 0.5f, py = (float)lg.ly + 0.5f;
+    for (int i = tid; i < BATCH; i += AS_BLOCK) {
+        s_gflag[i] = 0;
 #pragma unroll
-            for (int k = 0; k < 9; k++) g[k] = 0.f;
-            bool contrib = false;
-            if (has && gidx <= lastp && ((m >> lx) & (m >> (16 + ly)) & 1u)) {
-                const StagedRec r = s_rec[j];
-                const float dx = r.mc.x - px, dy = r.mc.y - py;
-                const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, r));
-                const float alpha = fminf(ALPHA_MAX, araw);
-                if (alpha >= ALPHA_MIN) {
-                    contrib = true;
-                    const float om = 1.0f - alpha;
-                    T = T / om;
-                    const float wgt = alpha * T;
-                    const float c0 = r.cc.z, c1 = r.cc.w, c2 = s_blue[j];
-                    acc0 = last_alpha * lc0 + (1.0f - last_alpha) * acc0;
-                    acc1 = last_alpha * lc1 + (1.0f - last_alpha) * acc1;
-                    acc2 = last_alpha * lc2 + (1.0f - last_alpha) * acc2;
-                    lc0 = c0; lc1 = c1; lc2 = c2;
-                    float dLda = (c0 - acc0) * dL0 + (c1 - acc1) * dL1 + (c2 - acc2) * dL2;
-                    dLda *= T;
-                    last_alpha = alpha;
-                    dLda += (-Tfin / om) * bgdot;
-                    g[6] = wgt * dL0;
-                    g[7] = wgt * dL1;
-                    g[8] = wgt * dL2;
-                    if (araw < ALPHA_MAX) {
-                        // alpha = o exp(p): dalpha/do = alpha/o, dalpha/dp = alpha;
-                        // p = -(a dx^2 + c dy^2)/2 - b dx dy with the unscaled conic
-                        const float o = exp2f(r.cc.y);
-                        g[5] = dLda * araw / o;
-                        const float dp = dLda * araw;
-                        const float a = -2.0f * LN2 * r.mc.z, b = -LN2 * r.mc.w, c = -2.0f * LN2 * r.cc.x;
-                        g[0] = dp * (-(a * dx + b * dy));
-                        g[1] = dp * (-(c * dy + b * dx));
-                        g[2] = dp * (-0.5f * dx * dx);
-                        g[3] = dp * (-dx * dy);
-                        g[4] = dp * (-0.5f * dy * dy);
+        for (int k = 0; k < 9; k++) s_gacc[k][i] = 0.f;
+    }
+    uint32_t idx;
+    for (int iter = 0; next_tile<PERSIST>(queue, n_tiles, iter, idx, &s_next); iter++) {
+        const int tile = tile_order ? (int)tile_order[idx] : (int)idx;
+        const int v = view_of_tile(vt, tile);
+        const int lt = tile - vt.tile_base[v], tiles_x = vt.tiles_x[v];
+        const int W = vt.cam[v].W, H = vt.cam[v].H;
+        const int tx = lt % tiles_x, ty = lt / tiles_x;
+        const int ox = tx * AS_TILE_W, oy = ty * AS_TILE_H;
+        const int x = ox + lg.lx, y = oy + lg.ly;
+        const bool inside = x < W && y < H;
+        const uint32_t start = ranges[2 * tile];
+
+        const int64_t P = (int64_t)W * H;
+        const int64_t pl = (int64_t)y * W + x, pix = vt.pix_base[v] + pl;
+        float T = 1.0f, Tfin = 1.0f, dL0 = 0.f, dL1 = 0.f, dL2 = 0.f;
+        uint32_t lastp = 0;
+        bool has = false;
+        if (inside) {
+            const float *dL_dimage = dLs.p[v];
+            Tfin = t_final[pix];
+            T = Tfin;
+            has = ncontrib_in[pix] > 0;
+            lastp = last_in[pix];
+            dL0 = dL_dimage[pl];
+            dL1 = dL_dimage[P + pl];
+            dL2 = dL_dimage[2 * P + pl];
+        }
+        const float bgdot = vt.cam[v].bg[0] * dL0 + vt.cam[v].bg[1] * dL1 + vt.cam[v].bg[2] * dL2;
+        if (tid == 0) s_maxlast = 0;
+        __syncthreads();
+        if (has) atomicMax(&s_maxlast, lastp + 1);
+        __syncthreads();
+        const uint32_t hi_end = s_maxlast > start ? s_maxlast : start;   // one past the block's last contributor
+        // one past the wave's last contributor (wave-uniform)
+        uint32_t wlast = has ? lastp + 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
+
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, last_alpha = 0.f, lc0 = 0.f, lc1 = 0.f, lc2 = 0.f;
+
+        // batches [b0, b1) walk the list backwards from hi_end
+        Fetched nf[R];
+        {
+            const uint32_t b0 = hi_end - start > (uint32_t)BATCH ? hi_end - BATCH : start;
+#pragma unroll
+            for (int k = 0; k < R; k++)
+                if (b0 + k * AS_BLOCK + tid < hi_end) fetch(vals, rec, box, b0 + k * AS_BLOCK + tid, nf[k]);
+        }
+        for (uint32_t b1 = hi_end; b1 > start;) {
+            const uint32_t b0 = b1 - start > (uint32_t)BATCH ? b1 - BATCH : start;
+            const uint32_t n1 = b0, n0 = n1 - start > (uint32_t)BATCH ? n1 - BATCH : start;
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const int t = k * AS_BLOCK + tid;
+                if (b0 + t < b1) stage(nf[k], ox, oy, sh.rec, sh.blue, sh.id, sh.mask, t);
+                if (n0 + t < n1) fetch(vals, rec, box, n0 + t, nf[k]);
+            }
+            __syncthreads();
+            const int nh = compact_rows<BATCH>(sh.mask, (int)(b1 - b0), sh.hits[w], w, lg.row,
+                                               [&](int j) { return b0 + (uint32_t)j < wlast; });
+            // the wave walks max over its rows of the row counts; rows past their
+            // own count idle
+            int nmax = nh;
+            for (int o = 16; o < 64; o <<= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
+            for (int h = nmax - 1; h >= 0; h--) {
+                const bool valid = h < nh;
+                const int j = valid ? hits[h] : 0;
+                const uint32_t gidx = b0 + (uint32_t)j;
+                const uint32_t m = sh.mask[j];
+                float g[9];
+#pragma unroll
+                for (int k = 0; k < 9; k++) g[k] = 0.f;
+                bool contrib = false;
+                if (valid && has && gidx <= lastp && ((m >> lg.lx) & (m >> (16 + lg.ly)) & 1u)) {
+                    const StagedRec r = sh.rec[j];
+                    const float dx = r.mc.x - px, dy = r.mc.y - py;
+                    const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, r));
+                    const float alpha = fminf(ALPHA_MAX, araw);
+                    if (alpha >= ALPHA_MIN) {
+                        contrib = true;
+                        const float om = 1.0f - alpha;
+                        T = T / om;
+                        const float wgt = alpha * T;
+                        const float c0 = r.cc.z, c1 = r.cc.w, c2 = sh.blue[j];
+                        acc0 = last_alpha * lc0 + (1.0f - last_alpha) * acc0;
+                        acc1 = last_alpha * lc1 + (1.0f - last_alpha) * acc1;
+                        acc2 = last_alpha * lc2 + (1.0f - last_alpha) * acc2;
+                        lc0 = c0; lc1 = c1; lc2 = c2;
+                        float dLda = (c0 - acc0) * dL0 + (c1 - acc1) * dL1 + (c2 - acc2) * dL2;
+                        dLda *= T;
+                        last_alpha = alpha;
+                        dLda += (-Tfin / om) * bgdot;
+                        g[6] = wgt * dL0;
+                        g[7] = wgt * dL1;
+                        g[8] = wgt * dL2;
+                        if (araw < ALPHA_MAX) {
+                            // alpha = o exp(p): dalpha/do = alpha/o, dalpha/dp = alpha;
+                            // p = -(a dx^2 + c dy^2)/2 - b dx dy with the unscaled conic
+                            const float o = exp2f(r.cc.y);
+                            g[5] = dLda * araw / o;
+                            const float dp = dLda * araw;
+                            const float a = -2.0f * LN2 * r.mc.z, b = -LN2 * r.mc.w, c = -2.0f * LN2 * r.cc.x;
+                            g[0] = dp * (-(a * dx + b * dy));
+                            g[1] = dp * (-(c * dy + b * dx));
+                            g[2] = dp * (-0.5f * dx * dx);
+                            g[3] = dp * (-dx * dy);
+                            g[4] = dp * (-0.5f * dy * dy);
+                        }
+                    }
+                }
+                const uint64_t cb = __ballot(contrib);
+                if (cb) {
+#pragma unroll
+                    for (int k = 0; k < 9; k++) g[k] = row_sum_to_lane15(g[k]);
+                    if ((lane & 15) == 15 && ((cb >> (lg.row * 16)) & 0xFFFFull)) {
+#pragma unroll
+                        for (int k = 0; k < 9; k++) atomicAdd(&s_gacc[k][j], g[k]);
+                        s_gflag[j] = 1;
                     }
                 }
             }
-            if (__ballot(contrib)) {
+            __syncthreads();
+            // one set of global atomics per entry of the batch that received gradients
+            for (int i = tid; i < (int)(b1 - b0); i += AS_BLOCK) {
+                if (s_gflag[i]) {
+                    const int64_t id = sh.id[i];
 #pragma unroll
-                for (int k = 0; k < 9; k++) g[k] = wave_sum(g[k]);
-                if (lane == 0) {
-                    const int64_t id = s_id[j];
-#pragma unroll
-                    for (int k = 0; k < 9; k++) atomicAdd(&grad2d[k * stride + id], g[k]);
+                    for (int k = 0; k < 9; k++) {
+                        atomicAdd(&grad2d[k * stride + id], s_gacc[k][i]);
+                        s_gacc[k][i] = 0.f;
+                    }
+                    s_gflag[i] = 0;
                 }
             }
+            __syncthreads();
+            b1 = b0;
         }
-        __syncthreads();
-        b1 = b0;
+    }
+}
+
+// Tiles ordered by descending list length (33 length classes with power-of-two
+// boundaries), so the longest lists are dispatched first.  The order within a
+// class is irrelevant: every tile's outputs are independent of the others.
+__global__ void __launch_bounds__(1024) k_tile_order(const uint32_t *__restrict__ ranges, int tiles,
+                                                     uint32_t *__restrict__ order) {
+    __shared__ uint32_t s_cnt[33], s_off[33];
+    const int tid = threadIdx.x;
+    if (tid < 33) s_cnt[tid] = 0;
+    __syncthreads();
+    for (int t = tid; t < tiles; t += blockDim.x) {
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        const int cls = len ? 32 - __clz(len) : 0;   // 0..32, larger = longer
+        atomicAdd(&s_cnt[32 - cls], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int c = 0; c < 33; c++) {
+            s_off[c] = run;
+            run += s_cnt[c];
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < tiles; t += blockDim.x) {
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        const int cls = len ? 32 - __clz(len) : 0;
+        order[atomicAdd(&s_off[32 - cls], 1u)] = (uint32_t)t;
     }
 }
 
 }  // namespace
 
-void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const DevCam &cam, const float *gt, float *image,
-                      hipStream_t s) {
-    const int tiles = f->tiles_x * f->tiles_y;
-    hipLaunchKernelGGL(k_blend_fwd, dim3(tiles), dim3(AS_BLOCK), 0, s, f->ranges, vals, f->rec,
-                       reinterpret_cast<const short4 *>(f->box), cam, f->tiles_x, gt, image, f->t_final, f->last,
-                       f->n_contrib, f->dom, f->err, reinterpret_cast<unsigned long long *>(f->err_minmax));
+void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);
 }
 
-void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const DevCam &cam, const float *dL_dimage,
-                      float *grad2d, int64_t g2d_stride, hipStream_t s) {
-    const int tiles = f->tiles_x * f->tiles_y;
-    hipLaunchKernelGGL(k_blend_bwd, dim3(tiles), dim3(AS_BLOCK), 0, s, f->ranges, vals, f->rec,
-                       reinterpret_cast<const short4 *>(f->box), cam, f->tiles_x, f->t_final, f->last, f->n_contrib,
-                       dL_dimage, grad2d, g2d_stride);
+namespace {
+// Resident blocks of a kernel on the whole device (persistent grid size).
+template <typename Kern>
+int resident_blocks(Kern k, int n_cu) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, AS_BLOCK, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * (n_cu > 0 ? n_cu : 1);
+}
+}  // namespace
+
+void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
+                      const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s) {
+    const int tiles = vt.tile_base[vt.n_views];
+    if (tiles == 0) return;
+    const short4 *b4 = reinterpret_cast<const short4 *>(f->box);
+    unsigned long long *mm = reinterpret_cast<unsigned long long *>(f->err_minmax);
+    if (bl.persistent) launch_fill_u32(f->queue, 0u, 1, s);
+#define AS_FWD(B, PER)                                                                                             \
+    do {                                                                                                           \
+        static int grid_p = 0;                                                                                     \
+        int grid = tiles;                                                                                          \
+        if (PER) {                                                                                                 \
+            if (!grid_p) grid_p = resident_blocks(k_blend_fwd<B, PER>, bl.n_cu);                                   \
+            grid = grid_p < tiles ? grid_p : tiles;                                                                \
+        }                                                                                                          \
+        hipLaunchKernelGGL((k_blend_fwd<B, PER>), dim3(grid), dim3(AS_BLOCK), 0, s, f->ranges, tile_order, vals,  \
+                           f->rec, b4, vt, gt, image, f->t_final, f->last, f->n_contrib, f->dom, f->err, mm,      \
+                           f->queue, tiles);                                                                       \
+    } while (0)
+    if (bl.persistent) {
+        if (bl.batch >= 1024) AS_FWD(1024, true);
+        else if (bl.batch >= 512) AS_FWD(512, true);
+        else AS_FWD(256, true);
+    } else {
+        if (bl.batch >= 1024) AS_FWD(1024, false);
+        else if (bl.batch >= 512) AS_FWD(512, false);
+        else AS_FWD(256, false);
+    }
+#undef AS_FWD
+}
+
+void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
+                      const ViewTable &vt, const ViewImagesC &dL_dimage, float *grad2d, int64_t g2d_stride,
+                      hipStream_t s) {
+    const int tiles = vt.tile_base[vt.n_views];
+    if (tiles == 0) return;
+    const short4 *b4 = reinterpret_cast<const short4 *>(f->box);
+    if (bl.persistent) launch_fill_u32(f->queue + 1, 0u, 1, s);
+#define AS_BWD(B, PER)                                                                                             \
+    do {                                                                                                           \
+        static int grid_p = 0;                                                                                     \
+        int grid = tiles;                                                                                          \
+        if (PER) {                                                                                                 \
+            if (!grid_p) grid_p = resident_blocks(k_blend_bwd<B, PER>, bl.n_cu);                                   \
+            grid = grid_p < tiles ? grid_p : tiles;                                                                \
+        }                                                                                                          \
+        hipLaunchKernelGGL((k_blend_bwd<B, PER>), dim3(grid), dim3(AS_BLOCK), 0, s, f->ranges, tile_order, vals,  \
+                           f->rec, b4, vt, f->t_final, f->last, f->n_contrib, dL_dimage, grad2d, g2d_stride,      \
+                           f->queue + 1, tiles);                                                                   \
+    } while (0)
+    if (bl.persistent) {
+        if (bl.batch >= 1024) AS_BWD(1024, true);
+        else if (bl.batch >= 512) AS_BWD(512, true);
+        else AS_BWD(256, true);
+    } else {
+        if (bl.batch >= 1024) AS_BWD(1024, false);
+        else if (bl.batch >= 512) AS_BWD(512, false);
+        else AS_BWD(256, false);
+    }
+#undef AS_BWD
 }

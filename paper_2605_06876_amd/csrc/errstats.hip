@@ -184,21 +184,22 @@ __global__ void k_moments(int W, int H, const int32_t *__restrict__ label, const
             v[0] = 1; v[1] = x; v[2] = y; v[3] = x * x; v[4] = x * y; v[5] = y * y;
         }
     }
-    const bool act = s >= 0;
-    const uint64_t acts = __ballot(act);
-    if (!acts) return;
-    const int leader = __ffsll((unsigned long long)acts) - 1;
-    const int64_t s0 = __shfl(s, leader, 64);
-    if (__ballot(act && s == s0) == acts) {
+    // one set of atomics per distinct region among the wave's 64 pixels (a
+    // wave spans one image row segment, which few regions cross)
+    uint64_t pending = __ballot(s >= 0);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int64_t s0 = __shfl(s, leader, 64);
+        const bool mine = s == s0;
+        pending &= ~__ballot(mine);
+        int64_t t[6];
+#pragma unroll
         for (int k = 0; k < 6; k++) {
-            int64_t t = v[k];
-            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-            v[k] = t;
+            t[k] = mine ? v[k] : 0;
+            for (int o = 32; o > 0; o >>= 1) t[k] += __shfl_xor(t[k], o, 64);
         }
         if ((int)__lane_id() == leader)
-            for (int k = 0; k < 6; k++) atomicAdd(&mom[s0 * 6 + k], (unsigned long long)v[k]);
-    } else if (act) {
-        for (int k = 0; k < 6; k++) atomicAdd(&mom[s * 6 + k], (unsigned long long)v[k]);
+            for (int k = 0; k < 6; k++) atomicAdd(&mom[s0 * 6 + k], (unsigned long long)t[k]);
     }
 }
 

@@ -12,6 +12,7 @@
 #define AS_BLOCK 256        // threads per tile block: one 16x16 tile, four wave64
 #define AS_NEAR 0.2
 #define AS_LOWPASS 0.3
+#define AS_MAX_VIEWS 16   // views of one batched render
 
 // Blend record of one projected Gaussian, 48 bytes (three float4):
 //   [0] mean_x hi, mean_y hi, mean_x lo, mean_y lo  (mean = hi + lo, continuous pixel frame)
@@ -57,45 +58,75 @@ struct DevBuf {
 hipError_t devbuf_ensure(DevBuf &b, size_t bytes);
 void devbuf_free(DevBuf &b);
 
+// The views of one render, passed by value to the kernels.  View v owns
+//   entries  [ent_base[v], ent_base[v+1])  (its Gaussians, projected),
+//   tiles    [tile_base[v], tile_base[v+1]) (global tile ids, row-major within the view),
+//   pixels   [pix_base[v], pix_base[v+1])   (of the packed per-pixel maps).
+struct ViewTable {
+    int32_t n_views;
+    int32_t tile_base[AS_MAX_VIEWS + 1];
+    int32_t tiles_x[AS_MAX_VIEWS];
+    uint32_t ent_base[AS_MAX_VIEWS + 1];
+    int64_t pix_base[AS_MAX_VIEWS + 1];
+    DevCam cam[AS_MAX_VIEWS];
+};
+
+// Per-view image pointers ([3][H][W] each).
+struct ViewImages {
+    float *p[AS_MAX_VIEWS];
+};
+struct ViewImagesC {
+    const float *p[AS_MAX_VIEWS];
+};
+// Per-view Gaussian sets of a render (views may share one).
+struct SceneTable {
+    GaussPtrs g[AS_MAX_VIEWS];
+};
+
 struct as_frame {
     as_ctx *ctx;
-    int64_t n_cap, key_cap;
-    int32_t W, H, tiles_x, tiles_y;
+    int32_t max_views;
+    int32_t fixed_w, fixed_h;   // single-view frames: the one size they render (0: any)
     int32_t auto_grow;
-    // per Gaussian
+    int64_t ent_cap, pix_cap, tile_cap, key_cap;
+    // per entry (a Gaussian in one view)
     BlendRec *rec;
     uint32_t *depth_key;
-    int16_t *box;          // [n][4]
+    int16_t *box;          // [entries][4]
     uint32_t *ntiles;
-    uint32_t *offsets;     // [n] key offsets, in depth order
-    float *grad2d;         // [9][n]
-    // depth-first binning: Gaussians sorted by depth, then keys by tile
-    uint64_t *dkeys[2];
+    uint32_t *offsets;     // key offsets, in depth order
+    float *grad2d;         // [9][ent_cap]
+    // depth-first binning: entries sorted by depth, then keys by tile
+    uint32_t *dkeys[2];
     uint32_t *dvals[2];
-    uint32_t *nt_sorted;   // [n] tiles touched, in depth order
-    uint32_t *n_gauss;     // [1] device copy of n for the depth sort
+    uint32_t *nt_sorted;   // tiles touched, in depth order
+    uint32_t *n_ent;       // [1] device copy of the entry count
     DevBuf dsort_hist;
-    // pairs
-    uint64_t *keys[2];
+    // pairs: tile id (key) and entry id (value)
+    uint32_t *keys[2];
     uint32_t *vals[2];
     int sorted_sel;
     uint32_t *ranges;      // [tiles][2]
+    uint32_t *tile_order;  // [tiles] dispatch order of the blend kernels
+    int use_order;         // tile_order is valid for the last render
     uint32_t *n_keys;      // [1] device
     uint32_t *h_nkeys;     // pinned host mirror
-    // per pixel
+    uint32_t *queue;       // [2] tile counters of the persistent blend kernels
+    // per pixel, packed over the views
     float *t_final;
     uint32_t *last;
     uint32_t *n_contrib;
     int32_t *dom;
     double *err;
-    uint64_t *err_minmax;
+    uint64_t *err_minmax;  // [max_views][2]
     // scratch for scans and the sorter
     DevBuf scan_tmp, sort_hist;
     // state of the last render
     int has_render;
-    int64_t n_last;
-    int32_t deg_last;
+    ViewTable vt;
+    SceneTable scenes;
     int32_t has_gt;
+    int32_t persistent_last;
 };
 
 struct StageRec {
@@ -108,6 +139,11 @@ struct as_ctx {
     DevBuf es[16];    // error-statistics scratch (errstats.hip names the slots)
     DevBuf sp[24];    // adaptive-split scratch (split.hip names the slots)
     DevBuf dbg[4];    // test hooks
+    int lds_batch = 256;          // launch tuning (as_set_tuning)
+    int longest_first = 1;
+    int persistent = 0;
+    int radix_bits = 8;
+    int n_cu = 0;                 // compute units of the device
     int timing = 0;
     StageRec *recs = nullptr;     // recorded stage event pairs
     int n_recs = 0, cap_recs = 0;
@@ -127,11 +163,12 @@ struct StageTimer {
 
 // ---- launchers (each defined in the .hip file that holds the kernel) -------------
 
-// projection (project.hip)
-void launch_project(const GaussPtrs &g, const DevCam &cam, int tiles_x, BlendRec *rec, uint32_t *depth_key,
-                    int16_t *box, uint32_t *ntiles, hipStream_t s);
-// projection backward (project_bwd.hip)
-void launch_project_bwd(const GaussPtrs &g, const DevCam &cam, const uint32_t *ntiles, const float *grad2d,
+// projection (project.hip): every view's Gaussians into its entry range
+void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, int deg, BlendRec *rec,
+                    uint32_t *depth_key, int16_t *box, uint32_t *ntiles, hipStream_t s);
+// projection backward (project_bwd.hip): one Gaussian set seen in every view
+// of vt; gradients summed over the views in view order
+void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t *ntiles, const float *grad2d,
                         int64_t g2d_stride, GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s);
 
 // scans (binning.hip): exclusive scans with the total written to *total
@@ -140,28 +177,24 @@ void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, voi
 void scan_u8_to_i64(const uint8_t *in, int64_t *out, int64_t n, int64_t *total, void *tmp, hipStream_t s);
 void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total, void *tmp, hipStream_t s);
 
-// binning (binning.hip)
-void launch_emit_keys(int64_t n, const uint32_t *depth_key, const int16_t *box, const uint32_t *ntiles,
-                      const uint32_t *offsets, int tiles_x, int64_t key_cap, uint64_t *keys, uint32_t *vals,
-                      hipStream_t s);
+// LSD radix sort (binning.hip).  Sorts (keys[0], vals[0]) stably on bits
+// [lo_bit, hi_bit) with digits of radix_bits (4..8) bits, ping-ponging with
+// (keys[1], vals[1]); returns which buffer holds the result.  The element
+// count is read from the device (*n_dev, clamped to cap); n_hint sizes the grid.
 size_t sort_hist_bytes(int64_t n_hint);
-// Sorts (keys[0], vals[0]) on the low key_bits bits, ping-ponging with
-// (keys[1], vals[1]); returns which buffer holds the result.  The element count
-// is read from the device (*n_dev, clamped to cap); n_hint sizes the grid.
-int radix_sort_pairs(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint,
-                     int key_bits, void *hist, hipStream_t s);
-// The same on bits [lo_bit, hi_bit) only (8-bit digits from lo_bit upwards).
-int radix_sort_pairs_range(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint,
-                           int lo_bit, int hi_bit, void *hist, hipStream_t s);
-// Depth-first binning helpers: (depth, id) pairs, gathers, and key emission in
-// the depth order a stable depth sort produced.
-void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint64_t *keys, uint32_t *vals, uint32_t *n32,
+int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
+                   int hi_bit, int radix_bits, void *hist, hipStream_t s);
+int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
+                   int hi_bit, int radix_bits, void *hist, hipStream_t s);
+// Depth-first binning helpers: (depth, entry) pairs, gathers, and key emission
+// in the depth order a stable depth sort produced.
+void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals, uint32_t *n32,
                         hipStream_t s);
 void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint32_t *dst, hipStream_t s);
-void launch_emit_sorted(int64_t n, const uint32_t *order, const uint32_t *depth_key, const int16_t *box,
-                        const uint32_t *ntiles, const uint32_t *offsets, int tiles_x, int64_t key_cap, uint64_t *keys,
+void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
+                        const uint32_t *ntiles, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
                         uint32_t *vals, hipStream_t s);
-void launch_ranges(const uint64_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
+void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
                    hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -169,10 +202,17 @@ void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 
 // blend (blend.hip)
-void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const DevCam &cam, const float *gt, float *image,
+struct BlendLaunch {
+    int batch;         // LDS depth: 256, 512 or 1024 records
+    int persistent;    // 1: one resident grid pulling tiles from f->queue
+    int n_cu;
+};
+void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipStream_t s);
+void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
+                      const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s);
+void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
+                      const ViewTable &vt, const ViewImagesC &dL_dimage, float *grad2d, int64_t g2d_stride,
                       hipStream_t s);
-void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const DevCam &cam, const float *dL_dimage,
-                      float *grad2d, int64_t g2d_stride, hipStream_t s);
 
 // error statistics (errstats.hip)
 void launch_error_map(int W, int H, const float *image, const float *gt, double *err, uint64_t *minmax,
@@ -206,6 +246,18 @@ __device__ __forceinline__ double wave_min_d(double v) {
 }
 __device__ __forceinline__ double wave_max_d(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+// View holding a global tile id / an entry id (linear scans over at most
+// AS_MAX_VIEWS bases; the tables are kernel arguments).
+__device__ __forceinline__ int view_of_tile(const ViewTable &vt, int tile) {
+    int v = 0;
+    for (int k = 1; k < vt.n_views; k++) v += tile >= vt.tile_base[k] ? 1 : 0;
+    return v;
+}
+__device__ __forceinline__ int view_of_entry(const ViewTable &vt, uint32_t e) {
+    int v = 0;
+    for (int k = 1; k < vt.n_views; k++) v += e >= vt.ent_base[k] ? 1 : 0;
     return v;
 }
 __device__ __forceinline__ uint64_t lanemask_lt() {

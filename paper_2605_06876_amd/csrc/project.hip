@@ -2,7 +2,10 @@
 // Gaussian (Sec. 3 of the paper: each Gaussian is projected to the image plane
 // and its view-dependent colour decoded from SH along the viewing direction).
 //
-// One thread per Gaussian, struct-of-arrays reads (coalesced).  All arithmetic
+// One thread per (view, Gaussian) entry, struct-of-arrays reads (coalesced);
+// blocks alternate over the views of a batch (view index fastest), so the
+// views of one chunk of Gaussians read its parameters while they are still in
+// L2.  All arithmetic
 // is FP64 and this file is compiled with -ffp-contract=off: the depth key and
 // the pixel box decide which (tile, Gaussian) pairs exist, so they are
 // computed with a fixed expression order and IEEE-rounded operations.
@@ -18,12 +21,16 @@ __device__ __forceinline__ void quat_to_rot_d(double w, double x, double y, doub
 }
 
 template <int DEG>
-__global__ void __launch_bounds__(256) k_project(GaussPtrs g, DevCam cam, int tiles_x, BlendRec *__restrict__ rec,
+__global__ void __launch_bounds__(256) k_project(const SceneTable sc, const ViewTable vt, BlendRec *__restrict__ rec,
                                                  uint32_t *__restrict__ depth_key, short4 *__restrict__ box,
                                                  uint32_t *__restrict__ ntiles) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(blockIdx.x % (unsigned)vt.n_views);
+    const int64_t i = (int64_t)(blockIdx.x / (unsigned)vt.n_views) * blockDim.x + threadIdx.x;
+    const GaussPtrs &g = sc.g[v];
+    const DevCam &cam = vt.cam[v];
     if (i >= g.n) return;
     const int64_t n = g.n;
+    const int64_t e = (int64_t)vt.ent_base[v] + i;
     double mu[3], s[3], q[4];
     for (int k = 0; k < 3; k++) mu[k] = (double)g.means[k * n + i];
     for (int k = 0; k < 3; k++) s[k] = exp((double)g.log_scales[k * n + i]);
@@ -38,7 +45,7 @@ __global__ void __launch_bounds__(256) k_project(GaussPtrs g, DevCam cam, int ti
     double tv[3];
     for (int r = 0; r < 3; r++) tv[r] = Rc[r * 3 + 0] * mu[0] + Rc[r * 3 + 1] * mu[1] + Rc[r * 3 + 2] * mu[2] + tc[r];
     const double tx = tv[0], ty = tv[1], tz = tv[2];
-    depth_key[i] = __float_as_uint((float)tz);
+    depth_key[e] = __float_as_uint((float)tz);
 
     BlendRec rr;
     rr.m = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -121,23 +128,22 @@ __global__ void __launch_bounds__(256) k_project(GaussPtrs g, DevCam cam, int ti
         nt = (uint32_t)((ix1 / AS_TILE_W - ix0 / AS_TILE_W + 1) * (iy1 / AS_TILE_H - iy0 / AS_TILE_H + 1));
     } while (0);
 
-    rec[i] = rr;
-    box[i] = bx;
-    ntiles[i] = nt;
-    (void)tiles_x;
+    rec[e] = rr;
+    box[e] = bx;
+    ntiles[e] = nt;
 }
 
 }  // namespace
 
-void launch_project(const GaussPtrs &g, const DevCam &cam, int tiles_x, BlendRec *rec, uint32_t *depth_key,
-                    int16_t *box, uint32_t *ntiles, hipStream_t s) {
-    if (g.n == 0) return;
-    const int64_t blocks = (g.n + 255) / 256;
+void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, int deg, BlendRec *rec,
+                    uint32_t *depth_key, int16_t *box, uint32_t *ntiles, hipStream_t s) {
+    if (max_n == 0 || vt.n_views == 0) return;
+    const int64_t blocks = (max_n + 255) / 256 * vt.n_views;
     short4 *b4 = reinterpret_cast<short4 *>(box);
-    switch (g.deg) {
-    case 0: hipLaunchKernelGGL(k_project<0>, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key, b4, ntiles); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key, b4, ntiles); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key, b4, ntiles); break;
-    default: hipLaunchKernelGGL(k_project<3>, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, tiles_x, rec, depth_key, b4, ntiles); break;
+    switch (deg) {
+    case 0: hipLaunchKernelGGL(k_project<0>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles); break;
+    default: hipLaunchKernelGGL(k_project<3>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles); break;
     }
 }

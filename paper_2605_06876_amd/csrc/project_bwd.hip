@@ -1,7 +1,10 @@
 // Reverse pass of the projection (Sec. 3): from the per-Gaussian 2D gradients
 // (mean, conic, opacity, colour) accumulated by the blend back to the stored
 // parameters (means, log-scales, quaternions, opacity logits, SH).  One thread
-// per Gaussian, FP64, struct-of-arrays reads and writes.
+// per Gaussian, FP64, struct-of-arrays reads and writes.  A Gaussian set seen
+// in several views of a batch gets one launch per view; every launch after
+// the first adds its view's gradient to the output (a fixed order, so the sum
+// is deterministic).
 //
 // Chain: colour = max(0, sum_k Y_k(d) sh_k + 1/2) with d = (mu - o_v)/|mu - o_v|;
 // mean2d = (fx tx/tz + cx, fy ty/tz + cy); conic = inverse(J W Sigma W^T J^T
@@ -12,15 +15,19 @@
 
 namespace {
 
+__device__ __forceinline__ void put(float *p, float v, bool acc) { *p = acc ? *p + v : v; }
+
 template <int DEG>
 __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, const uint32_t *__restrict__ ntiles,
                                                      const float *__restrict__ g2d, int64_t gs, GradPtrs out,
-                                                     float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count) {
+                                                     float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count,
+                                                     int accum) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
     const int64_t n = g.n, os = out.stride;
     constexpr int nk = (DEG + 1) * (DEG + 1);
     if (ntiles[i] == 0) {
+        if (accum) return;
         for (int k = 0; k < 3; k++) { out.means[k * os + i] = 0.f; out.log_scales[k * os + i] = 0.f; }
         for (int k = 0; k < 4; k++) out.quats[k * os + i] = 0.f;
         out.opac[i] = 0.f;
@@ -55,7 +62,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, co
 
     double dmu[3] = {0.0, 0.0, 0.0};
     // opacity
-    out.opac[i] = (float)(gop * o * (1.0 - o));
+    put(&out.opac[i], (float)(gop * o * (1.0 - o)), accum != 0);
     // colour and view direction
     double oc[3];
     for (int j = 0; j < 3; j++) oc[j] = -(Rc[0 * 3 + j] * tc[0] + Rc[1 * 3 + j] * tc[1] + Rc[2 * 3 + j] * tc[2]);
@@ -75,7 +82,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, co
         const double gc = clamped ? 0.0 : grgb[ch];
 #pragma unroll
         for (int k = 0; k < nk; k++) {
-            out.sh[((int64_t)k * 3 + ch) * os + i] = (float)(Y[k] * gc);
+            put(&out.sh[((int64_t)k * 3 + ch) * os + i], (float)(Y[k] * gc), accum != 0);
             const double shv = (double)g.sh[((int64_t)k * 3 + ch) * n + i];
             for (int a = 0; a < 3; a++) gd[a] += dY[k][a] * shv * gc;
         }
@@ -158,13 +165,13 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, co
         dt[2] += dJ[5] * (fy * (cy_ / tz) / (tz * tz));
     }
     for (int a = 0; a < 3; a++) dmu[a] += Rc[0 * 3 + a] * dt[0] + Rc[1 * 3 + a] * dt[1] + Rc[2 * 3 + a] * dt[2];
-    for (int a = 0; a < 3; a++) out.means[a * os + i] = (float)dmu[a];
+    for (int a = 0; a < 3; a++) put(&out.means[a * os + i], (float)dmu[a], accum != 0);
     // scales
     for (int k = 0; k < 3; k++) {
         double acc = 0.0;
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) acc += Rg[a * 3 + k] * dS[a * 3 + b] * Rg[b * 3 + k];
-        out.log_scales[k * os + i] = (float)(2.0 * s[k] * s[k] * acc);
+        put(&out.log_scales[k * os + i], (float)(2.0 * s[k] * s[k] * acc), accum != 0);
     }
     // rotation -> quaternion
     double dR[9];
@@ -184,19 +191,25 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, co
                    y * dR[7]);
     const double qn[4] = {w, x, y, z};
     const double qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-    for (int k = 0; k < 4; k++) out.quats[k * os + i] = (float)((dq[k] - qn[k] * qd) / qnorm);
+    for (int k = 0; k < 4; k++) put(&out.quats[k * os + i], (float)((dq[k] - qn[k] * qd) / qnorm), accum != 0);
 }
 
 }  // namespace
 
-void launch_project_bwd(const GaussPtrs &g, const DevCam &cam, const uint32_t *ntiles, const float *grad2d,
+void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t *ntiles, const float *grad2d,
                         int64_t g2d_stride, GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
-    switch (g.deg) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
+    for (int v = 0; v < vt.n_views; v++) {
+        const DevCam &cam = vt.cam[v];
+        const uint32_t *nt = ntiles + vt.ent_base[v];
+        const float *g2 = grad2d + vt.ent_base[v];
+        const int accum = v > 0;
+        switch (g.deg) {
+        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(256), 0, s, g, cam, nt, g2, g2d_stride, out, g2d_norm, vis_count, accum); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(256), 0, s, g, cam, nt, g2, g2d_stride, out, g2d_norm, vis_count, accum); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(256), 0, s, g, cam, nt, g2, g2d_stride, out, g2d_norm, vis_count, accum); break;
+        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, g, cam, nt, g2, g2d_stride, out, g2d_norm, vis_count, accum); break;
+        }
     }
 }

@@ -506,6 +506,15 @@ int bits_for(int64_t v) {   // bits needed to represent 0..v
     return b;
 }
 
+constexpr int CAM_CHUNK = 16;
+struct CamChunk {
+    int m;
+    DevCam cam[CAM_CHUNK];
+};
+__global__ void k_store_cams(const CamChunk c, DevCam *__restrict__ dst) {
+    if ((int)threadIdx.x < c.m) dst[threadIdx.x] = c.cam[threadIdx.x];
+}
+
 }  // namespace
 
 as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *cand, int64_t n_cand,
@@ -549,22 +558,17 @@ as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *can
     uint8_t *removed = (uint8_t *)sp[SP_REM].p;
     int64_t *remscan = (int64_t *)sp[SP_REMSCAN].p;
 
-    if (n_views > 0) {
-        DevCam hc[64];
-        for (int v0 = 0; v0 < n_views; v0 += 64) {
-            const int m = n_views - v0 < 64 ? n_views - v0 : 64;
-            for (int k = 0; k < m; k++) hc[k] = to_devcam(views[v0 + k]);
-            if ((e = hipMemcpyAsync(dcams + v0, hc, sizeof(DevCam) * m, hipMemcpyHostToDevice, s)) != hipSuccess ||
-                (e = hipStreamSynchronize(s)) != hipSuccess) {
-                as_set_error("camera upload failed: %s", hipGetErrorString(e));
-                return AS_ERR_HIP;
-            }
-        }
+    // cameras travel as kernel arguments (no host copy, no synchronisation)
+    for (int v0 = 0; v0 < n_views; v0 += CAM_CHUNK) {
+        CamChunk cc;
+        cc.m = n_views - v0 < CAM_CHUNK ? n_views - v0 : CAM_CHUNK;
+        for (int k = 0; k < cc.m; k++) cc.cam[k] = to_devcam(views[v0 + k]);
+        hipLaunchKernelGGL(k_store_cams, dim3(1), dim3(64), 0, s, cc, dcams + v0);
     }
     const unsigned gcap = (unsigned)((cap + 255) / 256);
     hipLaunchKernelGGL(k_reg_prep, dim3(1), dim3(1), 0, s, rb.count, cap, n32);
     hipLaunchKernelGGL(k_reg_keys, dim3(gcap), dim3(256), 0, s, rb.records, n32, cap, lb, vb, keys[0], vals[0]);
-    const int sel = radix_sort_pairs(keys, vals, n32, cap, cap, lb + vb + cb, sp[SP_HIST].p, s);
+    const int sel = radix_sort_u64(keys, vals, n32, cap, cap, 0, lb + vb + cb, 8, sp[SP_HIST].p, s);
     const uint32_t *order = vals[sel];
     launch_fill_i64(rs, 0, nc1, s);
     launch_fill_i64(re, 0, nc1, s);
