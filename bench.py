@@ -48,6 +48,7 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-densify", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-view leg")
     ap.add_argument("--json", default="", help="also write the JSON line to this file")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tuning)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -187,6 +188,80 @@ def densify_bench(ctx):
                 new_rows=int(res[2].sum().item()), n_out=int(res[4].item()),
                 modes=dict(vanilla=int((mode == 0).sum()), reset=int((mode == 1).sum()), adaptive=int((mode == 2).sum())),
                 stage_ms={k: round(v[0] / reps, 4) for k, v in st.items() if v[1]})
+
+
+C4_SIZES = [(640, 480), (800, 600), (960, 640), (1024, 768), (1256, 828), (1280, 720), (1440, 960), (1600, 1064)]
+
+
+def batched_bench(reps=10):
+    """8 cameras of uneven resolution (640x480 up to 1600x1064) on a radius-4
+    sphere over 1,500,000 clustered Gaussians (SH 3): forward + backward of
+    all views as (a) the plain per-view loop (one render and one backward
+    call per view), (b) one batched render + one batched backward, (c) the
+    batched step replayed from a HIP graph.  Same tuning for all three (tuned
+    on the batched step)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_06876_amd import api, autotune, synth
+
+    n = 1_500_000
+    scene = synth.scene_clusters(n, 1004, 3)
+    cams = synth.sphere_cameras(len(C4_SIZES), 4.0, C4_SIZES, seed=1004)
+    g = api.Gaussians.from_scene(scene)
+    del scene
+    rng = np.random.default_rng(1004)
+    dLs = [torch.from_numpy(rng.normal(0.0, 1.0 / (3 * c.width * c.height), (3, c.height, c.width))
+                            .astype(np.float32)).cuda() for c in cams]
+    images = [torch.empty(3, c.height, c.width, device="cuda") for c in cams]
+    grads = api.Gaussians.empty(n, 3)
+    px = sum(c.width * c.height for c in cams)
+    ctx = api.Context(0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        probe = api.BatchFrame.for_views(ctx, n, cams, key_cap=64 * n)
+        api.render_batch(ctx, g, cams, probe, images=images)
+        s.synchronize()
+        K = probe.n_keys()
+        probe.close()
+        frame = api.BatchFrame.for_views(ctx, n, cams, key_cap=K + K // 4 + 4096, auto_grow=False)
+        frames = [api.Frame(ctx, n, c.width, c.height, key_cap=K) for c in cams]
+
+        def batched():
+            api.render_batch(ctx, g, cams, frame, images=images)
+            api.render_backward_batch(ctx, g, frame, dLs, grads=grads)
+
+        def loop():
+            for c, f, im, dl in zip(cams, frames, images, dLs):
+                api.render(ctx, g, c, f, image=im)
+                api.render_backward(ctx, g, c, f, dl, grads=grads)
+
+        key = autotune.workload_key(px // len(cams), 1, n, 3, views=len(cams))
+        best, tune_ms = autotune.autotune_step(ctx, batched, key, reps=2, cache_path=None, use_cache=False)
+        batched()
+        s.synchronize()
+        graph = api.Graph.capture(ctx, batched, s)
+
+    def timed(fn):
+        with torch.cuda.stream(s):
+            fn()
+            s.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            s.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    ms_loop = timed(loop)
+    ms_batch = timed(batched)
+    ms_graph = timed(lambda: graph.launch(s))
+    graph.close()
+    return dict(views=len(cams), sizes=["%dx%d" % wh for wh in C4_SIZES], gaussians=n, pixels=px, pairs_tile=K,
+                tuning=best, ms_per_view_loop=round(ms_loop, 4), ms_batched=round(ms_batch, 4),
+                ms_batched_graph=round(ms_graph, 4),
+                mpix_s_per_view_loop=round(px / ms_loop / 1e3, 2), mpix_s_batched=round(px / ms_batch / 1e3, 2),
+                mpix_s_batched_graph=round(px / ms_graph / 1e3, 2),
+                speedup_batched_graph_vs_loop=round(ms_loop / ms_graph, 3))
 
 
 def cpu_baseline():
@@ -346,6 +421,9 @@ def main():
     if not args.no_densify:
         log("bench: densification step (500k Gaussians, 16 views)")
         out["densify"] = densify_bench(res["ctx"])
+    if not args.no_batched:
+        log("bench: batched training render (8 uneven views, 1.5M Gaussians)")
+        out["batched"] = batched_bench()
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

@@ -26,6 +26,8 @@
 // (conic pre-scaled by -log2(e)/2, opacity folded into the exponent); the
 // forward and the reverse pass share the staged values and the helper below,
 // so they take identical alpha decisions.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace {
@@ -36,14 +38,17 @@ constexpr float T_STOP = 1e-4f;
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr float LN2 = 0.6931471805599453f;
 
+// A staged record: 48 bytes, read by the hit loops as three 16-byte LDS loads
+// issued together.
 struct StagedRec {
     float4 mc;  // mean x, mean y (tile-relative), a', b'
     float4 cc;  // c', log2(o), r, g
+    float4 ex;  // b, box masks (bits), entry id (bits), 0
 };
 
-__device__ __forceinline__ float blend_exponent(float dx, float dy, const StagedRec &r) {
+__device__ __forceinline__ float blend_exponent(float dx, float dy, const float4 &mc, const float4 &cc) {
 #pragma clang fp contract(off)
-    return __fmaf_rn(r.mc.z * dx, dx, __fmaf_rn(r.cc.x * dy, dy, __fmaf_rn(r.mc.w * dx, dy, r.cc.y)));
+    return __fmaf_rn(mc.z * dx, dx, __fmaf_rn(cc.x * dy, dy, __fmaf_rn(mc.w * dx, dy, cc.y)));
 }
 
 __device__ __forceinline__ uint32_t span_mask(int lo, int hi) {   // bits lo..hi of 16, clamped
@@ -52,6 +57,10 @@ __device__ __forceinline__ uint32_t span_mask(int lo, int hi) {   // bits lo..hi
     if (hi < lo) return 0u;
     return ((2u << hi) - 1u) & ~((1u << lo) - 1u);
 }
+
+// Index type of the per-row hit lists: one byte covers a batch of 256.
+template <int BATCH>
+using HitT = typename std::conditional<(BATCH <= 256), uint8_t, uint16_t>::type;
 
 // Registers of one record fetched ahead of its batch.
 struct Fetched {
@@ -67,19 +76,17 @@ __device__ __forceinline__ void fetch(const uint32_t *__restrict__ vals, const B
     f.b = box[f.id];
 }
 
-__device__ __forceinline__ void stage(const Fetched &f, int ox, int oy, StagedRec *s_rec, float *s_blue,
-                                      int32_t *s_id, uint32_t *s_mask, int t) {
+__device__ __forceinline__ void stage(const Fetched &f, int ox, int oy, StagedRec *s_rec, int t) {
 #pragma clang fp contract(off)
     const float mx = (f.r.m.x - (float)ox) + f.r.m.z;
     const float my = (f.r.m.y - (float)oy) + f.r.m.w;
     const float k = -0.5f * LOG2E;
+    const uint32_t mask = span_mask(f.b.x - ox, f.b.z - ox) | (span_mask(f.b.y - oy, f.b.w - oy) << 16);
     StagedRec sr;
     sr.mc = make_float4(mx, my, k * f.r.c.x, -LOG2E * f.r.c.y);
     sr.cc = make_float4(k * f.r.c.z, __log2f(f.r.c.w), f.r.rgb.x, f.r.rgb.y);
+    sr.ex = make_float4(f.r.rgb.z, __uint_as_float(mask), __uint_as_float(f.id), 1.0f / f.r.c.w);
     s_rec[t] = sr;
-    s_blue[t] = f.r.rgb.z;
-    s_id[t] = (int32_t)f.id;
-    s_mask[t] = span_mask(f.b.x - ox, f.b.z - ox) | (span_mask(f.b.y - oy, f.b.w - oy) << 16);
 }
 
 // Pixel geometry of a lane: 16-lane row `row` of wave w owns 4x4 block
@@ -107,8 +114,8 @@ __device__ __forceinline__ LaneGeom lane_geom(int tid) {
 // this lane's row count.  `ok(j)` adds a condition that is the same for the
 // whole wave.
 template <int BATCH, typename Ok>
-__device__ __forceinline__ int compact_rows(const uint32_t *s_mask, int cnt, uint16_t (*hits)[BATCH], int w, int row,
-                                            Ok ok) {
+__device__ __forceinline__ int compact_rows(const StagedRec *s_rec, int cnt, HitT<BATCH> (*hits)[BATCH + 4], int w,
+                                            int row, Ok ok) {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lanemask_lt();
     // the four blocks of wave w: sb = 4w + r -> sbx = r (w even: blocks 0-3 of a block row)
@@ -118,13 +125,13 @@ __device__ __forceinline__ int compact_rows(const uint32_t *s_mask, int cnt, uin
 #pragma unroll
     for (int k = 0; k < BATCH / 64; k++) {
         const int j = k * 64 + lane;
-        const uint32_t m = j < cnt ? s_mask[j] : 0u;
+        const uint32_t m = j < cnt ? __float_as_uint(s_rec[j].ex.y) : 0u;
         const bool any = (m & by) && ok(j);
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const bool hit = any && (m & (0xFu << (r * 4)));
             const uint64_t bal = __ballot(hit);
-            if (hit) hits[r][n[r] + __popcll(bal & lt)] = (uint16_t)j;
+            if (hit) hits[r][n[r] + __popcll(bal & lt)] = (HitT<BATCH>)j;
             n[r] += __popcll(bal);
         }
     }
@@ -150,10 +157,7 @@ __device__ __forceinline__ float row_sum_to_lane15(float v0) {
 template <int BATCH>
 struct BlendShared {
     StagedRec rec[BATCH];
-    float blue[BATCH];
-    int32_t id[BATCH];
-    uint32_t mask[BATCH];
-    uint16_t hits[AS_BLOCK / 64][4][BATCH];
+    HitT<BATCH> hits[AS_BLOCK / 64][4][BATCH + 4];  // +4: the loops read one index ahead
 };
 
 // Next tile of this block: a queue slot (persistent grid) or the block index;
@@ -188,7 +192,7 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
     __shared__ uint32_t s_next;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const LaneGeom lg = lane_geom(tid);
-    const uint16_t *hits = sh.hits[w][lg.row];
+    const HitT<BATCH> *hits = sh.hits[w][lg.row];
     const float px = (float)lg.lx + 0.5f, py = (float)lg.ly + 0.5f;
     uint32_t idx;
     for (int iter = 0; next_tile<PERSIST>(queue, n_tiles, iter, idx, &s_next); iter++) {
@@ -216,39 +220,43 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
 #pragma unroll
             for (int k = 0; k < R; k++) {
                 const int t = k * AS_BLOCK + tid;
-                if (b0 + t < end) stage(nf[k], ox, oy, sh.rec, sh.blue, sh.id, sh.mask, t);
+                if (b0 + t < end) stage(nf[k], ox, oy, sh.rec, t);
                 if (b0 + BATCH + t < end) fetch(vals, rec, box, b0 + BATCH + t, nf[k]);
             }
             __syncthreads();
             if (__ballot(!done) == 0) continue;                 // the whole wave has saturated
             const int cnt = (int)min((uint32_t)BATCH, end - b0);
-            const int nh = compact_rows<BATCH>(sh.mask, cnt, sh.hits[w], w, lg.row, [](int) { return true; });
+            const int nh = compact_rows<BATCH>(sh.rec, cnt, sh.hits[w], w, lg.row, [](int) { return true; });
             if (done) continue;
+            // one index ahead: the next record's LDS loads do not wait on the index load
+            int jn = hits[0];
             for (int h = 0; h < nh; h++) {
-                const int j = hits[h];
-                const uint32_t m = sh.mask[j];
-                if (!((m >> lg.lx) & (m >> (16 + lg.ly)) & 1u)) continue;   // box misses this pixel
-                const StagedRec r = sh.rec[j];
-                const float dx = r.mc.x - px, dy = r.mc.y - py;
-                const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, r));
+                const int j = jn;
+                jn = hits[h + 1];
+                const float4 q0 = sh.rec[j].mc, q1 = sh.rec[j].cc, q2 = sh.rec[j].ex;
+                const uint32_t m = __float_as_uint(q2.y);
+                const bool inb = (m >> lg.lx) & (m >> (16 + lg.ly)) & 1u;   // the box holds this pixel
+                const float dx = q0.x - px, dy = q0.y - py;
+                const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, q0, q1));
                 const float alpha = fminf(ALPHA_MAX, araw);
-                if (alpha < ALPHA_MIN) continue;
+                const bool ok = inb && alpha >= ALPHA_MIN;
                 const float testT = T * (1.0f - alpha);
-                if (testT < T_STOP) {
+                if (ok && testT < T_STOP) {
                     done = 1;
                     break;
                 }
-                const float wgt = alpha * T;
-                C0 += wgt * r.cc.z;
-                C1 += wgt * r.cc.w;
-                C2 += wgt * sh.blue[j];
+                // a non-contributor adds exactly zero and changes nothing
+                const float wgt = ok ? alpha * T : 0.0f;
+                C0 += wgt * q1.z;
+                C1 += wgt * q1.w;
+                C2 += wgt * q2.x;
                 if (wgt > wbest) {
                     wbest = wgt;
-                    dom = sh.id[j];
+                    dom = (int32_t)__float_as_uint(q2.z);
                 }
-                T = testT;
-                last = b0 + (uint32_t)j;
-                nc++;
+                T = ok ? testT : T;
+                last = ok ? b0 + (uint32_t)j : last;
+                nc += ok ? 1u : 0u;
             }
         }
 
@@ -312,12 +320,12 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
     constexpr int R = BATCH / AS_BLOCK;
     __shared__ BlendShared<BATCH> sh;
     __shared__ float s_gacc[9][BATCH];
-    __shared__ uint32_t s_gflag[BATCH];
+    __shared__ uint8_t s_gflag[BATCH];
     __shared__ uint32_t s_maxlast;
     __shared__ uint32_t s_next;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const LaneGeom lg = lane_geom(tid);
-    const uint16_t *hits = sh.hits[w][lg.row];
+    const HitT<BATCH> *hits = sh.hits[w][lg.row];
     const float px = (float)lg.lx + 0.5f, py = (float)lg.ly + 0.5f;
     for (int i = tid; i < BATCH; i += AS_BLOCK) {
         s_gflag[i] = 0;
@@ -377,60 +385,60 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
 #pragma unroll
             for (int k = 0; k < R; k++) {
                 const int t = k * AS_BLOCK + tid;
-                if (b0 + t < b1) stage(nf[k], ox, oy, sh.rec, sh.blue, sh.id, sh.mask, t);
+                if (b0 + t < b1) stage(nf[k], ox, oy, sh.rec, t);
                 if (n0 + t < n1) fetch(vals, rec, box, n0 + t, nf[k]);
             }
             __syncthreads();
-            const int nh = compact_rows<BATCH>(sh.mask, (int)(b1 - b0), sh.hits[w], w, lg.row,
+            const int nh = compact_rows<BATCH>(sh.rec, (int)(b1 - b0), sh.hits[w], w, lg.row,
                                                [&](int j) { return b0 + (uint32_t)j < wlast; });
             // the wave walks max over its rows of the row counts; rows past their
             // own count idle
             int nmax = nh;
             for (int o = 16; o < 64; o <<= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
+            int jn = hits[nmax > 0 ? nmax - 1 : 0];   // one index ahead, as in the forward loop
             for (int h = nmax - 1; h >= 0; h--) {
                 const bool valid = h < nh;
-                const int j = valid ? hits[h] : 0;
+                const int j = valid ? jn : 0;
+                jn = hits[h > 0 ? h - 1 : 0];
+                const float4 q0 = sh.rec[j].mc, q1 = sh.rec[j].cc, q2 = sh.rec[j].ex;
+                const uint32_t m = __float_as_uint(q2.y);
                 const uint32_t gidx = b0 + (uint32_t)j;
-                const uint32_t m = sh.mask[j];
+                const float dx = q0.x - px, dy = q0.y - py;
+                const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, q0, q1));
+                const float alpha = fminf(ALPHA_MAX, araw);
+                const bool contrib = valid && has && gidx <= lastp && ((m >> lg.lx) & (m >> (16 + lg.ly)) & 1u) &&
+                                     alpha >= ALPHA_MIN;
                 float g[9];
 #pragma unroll
                 for (int k = 0; k < 9; k++) g[k] = 0.f;
-                bool contrib = false;
-                if (valid && has && gidx <= lastp && ((m >> lg.lx) & (m >> (16 + lg.ly)) & 1u)) {
-                    const StagedRec r = sh.rec[j];
-                    const float dx = r.mc.x - px, dy = r.mc.y - py;
-                    const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, r));
-                    const float alpha = fminf(ALPHA_MAX, araw);
-                    if (alpha >= ALPHA_MIN) {
-                        contrib = true;
-                        const float om = 1.0f - alpha;
-                        T = T / om;
-                        const float wgt = alpha * T;
-                        const float c0 = r.cc.z, c1 = r.cc.w, c2 = sh.blue[j];
-                        acc0 = last_alpha * lc0 + (1.0f - last_alpha) * acc0;
-                        acc1 = last_alpha * lc1 + (1.0f - last_alpha) * acc1;
-                        acc2 = last_alpha * lc2 + (1.0f - last_alpha) * acc2;
-                        lc0 = c0; lc1 = c1; lc2 = c2;
-                        float dLda = (c0 - acc0) * dL0 + (c1 - acc1) * dL1 + (c2 - acc2) * dL2;
-                        dLda *= T;
-                        last_alpha = alpha;
-                        dLda += (-Tfin / om) * bgdot;
-                        g[6] = wgt * dL0;
-                        g[7] = wgt * dL1;
-                        g[8] = wgt * dL2;
-                        if (araw < ALPHA_MAX) {
-                            // alpha = o exp(p): dalpha/do = alpha/o, dalpha/dp = alpha;
-                            // p = -(a dx^2 + c dy^2)/2 - b dx dy with the unscaled conic
-                            const float o = exp2f(r.cc.y);
-                            g[5] = dLda * araw / o;
-                            const float dp = dLda * araw;
-                            const float a = -2.0f * LN2 * r.mc.z, b = -LN2 * r.mc.w, c = -2.0f * LN2 * r.cc.x;
-                            g[0] = dp * (-(a * dx + b * dy));
-                            g[1] = dp * (-(c * dy + b * dx));
-                            g[2] = dp * (-0.5f * dx * dx);
-                            g[3] = dp * (-dx * dy);
-                            g[4] = dp * (-0.5f * dy * dy);
-                        }
+                if (contrib) {
+                    const float om = 1.0f - alpha;
+                    const float rom = __builtin_amdgcn_rcpf(om);
+                    T = T * rom;
+                    const float wgt = alpha * T;
+                    const float c0 = q1.z, c1 = q1.w, c2 = q2.x;
+                    acc0 = last_alpha * lc0 + (1.0f - last_alpha) * acc0;
+                    acc1 = last_alpha * lc1 + (1.0f - last_alpha) * acc1;
+                    acc2 = last_alpha * lc2 + (1.0f - last_alpha) * acc2;
+                    lc0 = c0; lc1 = c1; lc2 = c2;
+                    float dLda = (c0 - acc0) * dL0 + (c1 - acc1) * dL1 + (c2 - acc2) * dL2;
+                    dLda *= T;
+                    last_alpha = alpha;
+                    dLda += (-Tfin * rom) * bgdot;
+                    g[6] = wgt * dL0;
+                    g[7] = wgt * dL1;
+                    g[8] = wgt * dL2;
+                    if (araw < ALPHA_MAX) {
+                        // alpha = o exp(p): dalpha/do = alpha/o, dalpha/dp = alpha;
+                        // p = -(a dx^2 + c dy^2)/2 - b dx dy with the unscaled conic
+                        const float dp = dLda * araw;
+                        g[5] = dp * q2.w;   // q2.w = 1/o
+                        const float a = -2.0f * LN2 * q0.z, b = -LN2 * q0.w, c = -2.0f * LN2 * q1.x;
+                        g[0] = dp * (-(a * dx + b * dy));
+                        g[1] = dp * (-(c * dy + b * dx));
+                        g[2] = dp * (-0.5f * dx * dx);
+                        g[3] = dp * (-dx * dy);
+                        g[4] = dp * (-0.5f * dy * dy);
                     }
                 }
                 const uint64_t cb = __ballot(contrib);
@@ -448,7 +456,7 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
             // one set of global atomics per entry of the batch that received gradients
             for (int i = tid; i < (int)(b1 - b0); i += AS_BLOCK) {
                 if (s_gflag[i]) {
-                    const int64_t id = sh.id[i];
+                    const int64_t id = (int64_t)__float_as_uint(sh.rec[i].ex.z);
 #pragma unroll
                     for (int k = 0; k < 9; k++) {
                         atomicAdd(&grad2d[k * stride + id], s_gacc[k][i]);
