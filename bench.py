@@ -49,6 +49,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-densify", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-view leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--json", default="", help="also write the JSON line to this file")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tuning)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -264,6 +266,56 @@ def batched_bench(reps=10):
                 speedup_batched_graph_vs_loop=round(ms_loop / ms_graph, 3))
 
 
+def serving_bench(seconds=5.0, rate=200.0, burst=400):
+    """Four resident scenes (300k, 600k, 1.2M, 2M clustered Gaussians, SH 3);
+    render requests with random poses on a radius-4 sphere and resolutions
+    drawn from {640x480, 1280x720, 1920x1080}.  (a) Poisson arrivals at
+    `rate`/s for `seconds`: continuous batching over 3 slots vs the plain
+    sequential loop on the same request list; (b) a burst of `burst`
+    requests arriving at once (throughput bound)."""
+    import torch
+
+    from paper_2605_06876_amd import api, serve, synth
+
+    sizes = [(640, 480), (1280, 720), (1920, 1080)]
+    ns = [300_000, 600_000, 1_200_000, 2_000_000]
+    scenes = [api.Gaussians.from_scene(synth.scene_clusters(n, 2001 + k, 3)) for k, n in enumerate(ns)]
+    ctx = api.Context(0)
+    n_slots, max_views = 3, 8
+    spec = serve.default_spec(ns, sizes, max_views, 24 << 30, n_slots)
+    ex = serve.GpuExecutor(ctx, scenes, spec, n_slots)
+    cam_fn = lambda rng, w, h: synth.random_pose_camera(rng, 4.0, w, h)
+
+    def fresh(reqs):
+        return [serve.Request(r.rid, r.scene, r.cam, r.arrival) for r in reqs]
+
+    warm = serve.poisson_requests(24, 0.0, len(ns), sizes, cam_fn, seed=1)
+    sched = serve.Scheduler(ex, spec, ns)
+    serve.serve_open_loop(sched, warm)
+    serve.serve_sequential(ex, fresh(warm))
+    torch.cuda.synchronize()
+    out = dict(scenes=ns, sizes=["%dx%d" % s for s in sizes], slots=n_slots, max_views=max_views,
+               hbm=serve.hbm_footprint(scenes, spec, n_slots), slot_pairs=spec.pairs)
+    n = int(seconds * rate)
+    reqs = serve.poisson_requests(n, rate, len(ns), sizes, cam_fn, seed=2005)
+    sched = serve.Scheduler(ex, spec, ns)
+    wall = serve.serve_open_loop(sched, reqs)
+    out["poisson"] = dict(rate_per_s=rate, batched=serve.latency_stats(sched.completed, wall),
+                          batches=sched.batches, overflows=ex.overflows)
+    seq = fresh(reqs)
+    wall = serve.serve_sequential(ex, seq)
+    out["poisson"]["sequential"] = serve.latency_stats(seq, wall)
+    reqs = serve.poisson_requests(burst, 0.0, len(ns), sizes, cam_fn, seed=2006)
+    sched = serve.Scheduler(ex, spec, ns)
+    wall = serve.serve_open_loop(sched, reqs)
+    out["burst"] = dict(requests=burst, batched=serve.latency_stats(sched.completed, wall), batches=sched.batches)
+    seq = fresh(reqs)
+    wall = serve.serve_sequential(ex, seq)
+    out["burst"]["sequential"] = serve.latency_stats(seq, wall)
+    ex.close()
+    return out
+
+
 def cpu_baseline():
     """The CPU oracle on the same training step: projection of all 1M
     Gaussians, forward + backward compositing of every pixel of the 1256x828
@@ -424,6 +476,9 @@ def main():
     if not args.no_batched:
         log("bench: batched training render (8 uneven views, 1.5M Gaussians)")
         out["batched"] = batched_bench()
+    if not args.no_serve:
+        log("bench: serving (4 resident scenes, Poisson arrivals)")
+        out["serving"] = serving_bench(args.serve_seconds)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

@@ -153,6 +153,10 @@ as_status as_frame_create(as_ctx *ctx, int64_t n_cap, int32_t width, int32_t hei
 as_status as_frame_create_batch(as_ctx *ctx, int32_t max_views, int64_t entry_cap, int64_t pixel_cap,
                                 int64_t tile_cap, int64_t key_cap, int32_t auto_grow, as_frame **out);
 void as_frame_destroy(as_frame *f);
+/* Copy the pair count of the last render (all views) to dst ([1], device
+ * memory) on `stream`, after the work already queued there; lets a caller
+ * that never synchronises the render check it against key_cap later. */
+as_status as_frame_pair_count(const as_frame *f, uint32_t *dst, void *stream);
 /* View 0 (as_frame_get_view) or view v of the last render. */
 as_status as_frame_get_view(const as_frame *f, as_frame_view *out);
 as_status as_frame_get_view_of(const as_frame *f, int32_t view, as_frame_view *out);

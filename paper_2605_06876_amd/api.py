@@ -68,7 +68,8 @@ REGION_DTYPE = np.dtype([
 assert REGION_DTYPE.itemsize == 152
 
 EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "as_frame_create",
-            "as_frame_create_batch", "as_frame_destroy", "as_frame_get_view", "as_frame_get_view_of", "as_render",
+            "as_frame_create_batch", "as_frame_destroy", "as_frame_get_view", "as_frame_get_view_of",
+            "as_frame_pair_count", "as_render",
             "as_render_backward", "as_render_batch", "as_render_backward_batch", "as_error_map",
             "as_accumulate_error_stats", "as_adaptive_split", "as_set_tuning", "as_get_tuning", "as_timing_enable",
             "as_timing_read", "as_graph_begin", "as_graph_end", "as_graph_launch", "as_graph_destroy",
@@ -246,6 +247,14 @@ class Frame:
     def n_keys(self):
         v = self.view()
         return int(self._dev(v.n_keys, 4).view(np.uint32)[0])
+
+    def pair_count_async(self, dst, stream=None):
+        """Queue a copy of the last render's pair count into dst (int32 [1], device)."""
+        _check(lib().as_frame_pair_count(self.handle, _ptr(dst), _stream(stream)))
+
+    @property
+    def key_cap(self):
+        return int(self.view().key_cap)
 
     def host_state(self, n, view=0):
         """Keys, values, ranges, per-Gaussian and per-pixel state of one view

@@ -330,6 +330,12 @@ as_status as_frame_get_view_of(const as_frame *f, int32_t view, as_frame_view *v
 
 as_status as_frame_get_view(const as_frame *f, as_frame_view *v) { return as_frame_get_view_of(f, 0, v); }
 
+as_status as_frame_pair_count(const as_frame *f, uint32_t *dst, void *stream) {
+    if (!f || !dst) { as_set_error("as_frame_pair_count: null argument"); return AS_ERR_ARG; }
+    launch_copy_u32(f->n_keys, dst, 1, (hipStream_t)stream);
+    return launch_status("as_frame_pair_count");
+}
+
 static bool capturing(hipStream_t s) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;

@@ -331,6 +331,11 @@ __global__ void k_fp64_ops(const double *a, const double *b, int64_t n, double *
     out[3 * n + i] = log(a[i]);
 }
 
+__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 template <typename T>
 void fill_impl(T *p, T v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
@@ -440,6 +445,12 @@ void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) { fill_impl
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) { fill_impl<uint32_t>(p, v, n, s); }
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) { fill_impl<uint64_t>(p, v, n, s); }
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) { fill_impl<int64_t>(p, v, n, s); }
+void launch_copy_u32(const uint32_t *src, uint32_t *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
+}
 
 void launch_fp64_ops(const double *a, const double *b, int64_t n, double *out, hipStream_t s) {
     if (n == 0) return;

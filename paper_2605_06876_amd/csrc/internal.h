@@ -200,6 +200,7 @@ void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+void launch_copy_u32(const uint32_t *src, uint32_t *dst, int64_t n, hipStream_t s);
 
 // blend (blend.hip)
 struct BlendLaunch {

@@ -1,0 +1,262 @@
+"""Render-request serving with continuous batching over resident scenes.
+
+Scenes (Gaussian sets) stay resident on the device.  Requests (scene, camera,
+arrival time) enter a FIFO queue when they arrive.  The server owns a fixed
+number of slots; each slot is a stream plus the memory one batched render
+needs (a batch frame of fixed entry / pixel / tile / pair capacity; output
+images are allocated per request).  Whenever a slot is free, the oldest
+waiting requests are
+admitted into it for as long as their footprint fits the slot's memory (the
+HBM budget is split over the slots up front, so admission is by footprint),
+and the slot renders them as one batched launch (views of different scenes
+and sizes together).  Requests that arrive while other batches are on the GPU
+are admitted as soon as a slot frees up; the slots' streams overlap on the
+device.  A request completes when its slot's completion event has fired;
+latency is completion minus arrival.
+
+A batch whose pairs overflow the slot's pair capacity (known only after the
+render) is rendered again one view at a time with frames that grow on demand,
+so every request gets the exact image.
+
+The executor is separable: GpuExecutor renders with the library; the
+scheduler logic (admission, batching, bookkeeping) runs the same with any
+object providing the same methods (tests drive it with a simulated one).
+"""
+import collections
+import math
+import time
+
+import numpy as np
+
+
+class Request:
+    __slots__ = ("rid", "scene", "cam", "arrival", "done", "image", "slot", "batch_size", "retried")
+
+    def __init__(self, rid, scene, cam, arrival):
+        self.rid, self.scene, self.cam, self.arrival = rid, scene, cam, arrival
+        self.done = None
+        self.image = None
+        self.slot = None
+        self.batch_size = 0
+        self.retried = False
+
+    @property
+    def pixels(self):
+        return self.cam.width * self.cam.height
+
+    @property
+    def tiles(self):
+        return ((self.cam.width + 15) // 16) * ((self.cam.height + 15) // 16)
+
+
+class SlotSpec:
+    """Capacities of one slot (what one batched launch may use)."""
+
+    def __init__(self, max_views, entries, pixels, tiles, pairs):
+        self.max_views, self.entries, self.pixels, self.tiles, self.pairs = max_views, entries, pixels, tiles, pairs
+
+    # bytes of device memory the slot holds (its frame, as the library allocates it, and its in-flight images)
+    def bytes(self):
+        per_entry = 48 + 4 + 8 + 4 + 4 + 36 + 16 + 4      # record, depth, box, tiles, offset, 2D grads, sort pairs, gather
+        per_pixel = 4 + 4 + 4 + 4 + 8 + 12                 # T, last, count, dominant, error, RGB image
+        return self.entries * per_entry + self.pixels * per_pixel + self.tiles * 12 + self.pairs * 16
+
+
+def plan_slots(budget_bytes, n_slots, max_views, pixels_per_slot, entries_per_slot, tiles_per_slot):
+    """Split what the budget leaves after the entry / pixel / tile arrays over
+    pair capacity (16 bytes a pair: two key and two value buffers)."""
+    spec = SlotSpec(max_views, entries_per_slot, pixels_per_slot, tiles_per_slot, 0)
+    left = budget_bytes // n_slots - spec.bytes()
+    if left <= 16 * 65536:
+        raise ValueError("budget of %d bytes cannot hold %d slots" % (budget_bytes, n_slots))
+    spec.pairs = int(min(left // 16, 0xFFFFFFFF))
+    return spec
+
+
+class Scheduler:
+    """FIFO admission into free slots, by footprint."""
+
+    def __init__(self, executor, spec, scene_sizes):
+        self.ex = executor
+        self.spec = spec
+        self.scene_sizes = scene_sizes
+        self.queue = collections.deque()
+        self.free = list(range(executor.n_slots))
+        self.busy = {}                     # slot -> list of requests
+        self.completed = []
+        self.batches = 0
+
+    def fits(self, batch, r):
+        if len(batch) + 1 > self.spec.max_views:
+            return False
+        ent = sum(self.scene_sizes[q.scene] for q in batch) + self.scene_sizes[r.scene]
+        px = sum(q.pixels for q in batch) + r.pixels
+        tl = sum(q.tiles for q in batch) + r.tiles
+        return ent <= self.spec.entries and px <= self.spec.pixels and tl <= self.spec.tiles
+
+    def admit(self, r):
+        if not self.fits([], r):
+            raise ValueError("request %d alone exceeds a slot" % r.rid)
+        self.queue.append(r)
+
+    def launch_ready(self):
+        """Fill every free slot from the head of the queue."""
+        while self.free and self.queue:
+            slot = self.free.pop(0)
+            batch = [self.queue.popleft()]
+            while self.queue and self.fits(batch, self.queue[0]):
+                batch.append(self.queue.popleft())
+            for r in batch:
+                r.slot, r.batch_size = slot, len(batch)
+            self.ex.launch(slot, batch)
+            self.busy[slot] = batch
+            self.batches += 1
+
+    def poll(self, now_fn):
+        """Retire finished slots; returns the number of requests completed."""
+        n = 0
+        for slot in list(self.busy):
+            if self.ex.finished(slot):
+                batch = self.busy.pop(slot)
+                self.ex.retire(slot, batch)
+                t = now_fn()
+                for r in batch:
+                    r.done = t
+                self.completed.extend(batch)
+                self.free.append(slot)
+                n += len(batch)
+        return n
+
+    def idle(self):
+        return not self.queue and not self.busy
+
+
+def serve_open_loop(sched, requests, clock=time.perf_counter, spin=None):
+    """Replay `requests` (sorted by arrival, seconds from the start) against
+    the scheduler in real time; returns when all have completed."""
+    t0 = clock()
+    now = lambda: clock() - t0
+    i, n = 0, len(requests)
+    while len(sched.completed) < n:
+        t = now()
+        while i < n and requests[i].arrival <= t:
+            sched.admit(requests[i])
+            i += 1
+        sched.launch_ready()
+        sched.poll(now)
+        if spin is not None:
+            spin()
+    return now()
+
+
+def serve_sequential(ex, requests, clock=time.perf_counter):
+    """The plain loop: one request at a time, in arrival order, each
+    rendered alone as soon as it has arrived and the previous one is done."""
+    t0 = clock()
+    now = lambda: clock() - t0
+    for r in requests:
+        while now() < r.arrival:
+            pass
+        ex.render_one(r)
+        r.done = now()
+    return now()
+
+
+def latency_stats(requests, wall_s):
+    lat = np.array([r.done - r.arrival for r in requests]) * 1e3
+    px = sum(r.pixels for r in requests)
+    return dict(requests=len(requests), p50_ms=round(float(np.percentile(lat, 50)), 3),
+                p99_ms=round(float(np.percentile(lat, 99)), 3), mean_ms=round(float(lat.mean()), 3),
+                max_ms=round(float(lat.max()), 3), wall_s=round(wall_s, 4),
+                mpix_s=round(px / wall_s / 1e6, 2), req_s=round(len(requests) / wall_s, 2))
+
+
+def poisson_requests(n, rate, n_scenes, sizes, cam_fn, seed):
+    """n requests with exponential inter-arrival times (rate per second),
+    uniform scene and resolution choices; cam_fn(rng, W, H) makes the pose."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n)) if rate else np.zeros(n)
+    out = []
+    for k in range(n):
+        W, H = sizes[rng.integers(len(sizes))]
+        out.append(Request(k, int(rng.integers(n_scenes)), cam_fn(rng, W, H), float(t[k])))
+    return out
+
+
+class GpuExecutor:
+    """Slots backed by the library: a stream, a batch frame that never
+    synchronises and a pair-count mailbox per slot.  Each request's image is
+    allocated on its slot's stream when the batch is launched and handed to
+    the caller when it completes."""
+
+    def __init__(self, ctx, scenes, spec, n_slots):
+        import torch
+
+        from . import api
+        self.api, self.torch = api, torch
+        self.ctx, self.scenes, self.spec, self.n_slots = ctx, scenes, spec, n_slots
+        self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
+        self.frames = [api.BatchFrame(ctx, spec.max_views, spec.entries, spec.pixels, spec.tiles, spec.pairs,
+                                      auto_grow=False) for _ in range(n_slots)]
+        self.count_dev = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(n_slots)]
+        self.count_host = [torch.zeros(1, dtype=torch.int32).pin_memory() for _ in range(n_slots)]
+        self.events = [None] * n_slots
+        self.single = {}
+        self.overflows = 0
+
+    def launch(self, slot, batch):
+        torch, api = self.torch, self.api
+        s = self.streams[slot]
+        with torch.cuda.stream(s):
+            imgs = [torch.empty(3, r.cam.height, r.cam.width, dtype=torch.float32, device="cuda") for r in batch]
+            api.render_batch(self.ctx, [self.scenes[r.scene] for r in batch], [r.cam for r in batch],
+                             self.frames[slot], images=imgs)
+            self.frames[slot].pair_count_async(self.count_dev[slot])
+            self.count_host[slot].copy_(self.count_dev[slot], non_blocking=True)
+            for r, im in zip(batch, imgs):
+                r.image = im
+            ev = torch.cuda.Event()
+            ev.record(s)
+        self.events[slot] = ev
+
+    def finished(self, slot):
+        return self.events[slot].query()
+
+    def retire(self, slot, batch):
+        """Re-render one by one if the batch's pairs overflowed the slot."""
+        pairs = int(self.count_host[slot][0]) & 0xFFFFFFFF
+        if pairs > self.spec.pairs:
+            self.overflows += 1
+            for r in batch:
+                self.render_one(r)
+                r.retried = True
+
+    def render_one(self, r):
+        torch, api = self.torch, self.api
+        key = (r.scene, r.cam.width, r.cam.height)
+        f = self.single.get(key)
+        if f is None:
+            f = api.Frame(self.ctx, self.scenes[r.scene].n, r.cam.width, r.cam.height, auto_grow=True)
+            self.single[key] = f
+        r.image = api.render(self.ctx, self.scenes[r.scene], r.cam, f)
+        torch.cuda.current_stream().synchronize()
+
+    def close(self):
+        for f in self.frames + list(self.single.values()):
+            f.close()
+
+
+def hbm_footprint(scenes, spec, n_slots):
+    """Device bytes held by the resident scenes and the slots."""
+    sc = sum(4 * (g.means.numel() + g.log_scales.numel() + g.quats.numel() + g.opacity_logits.numel() +
+                  g.sh.numel()) for g in scenes)
+    return dict(scenes_bytes=int(sc), slots_bytes=int(n_slots * spec.bytes()), total_bytes=int(sc + n_slots * spec.bytes()))
+
+
+def default_spec(scene_sizes, sizes, max_views, budget_bytes, n_slots):
+    """Slot capacities for max_views views of the largest size and scene."""
+    W, H = max(sizes, key=lambda s: s[0] * s[1])
+    px = max_views * W * H
+    tiles = max_views * math.ceil(W / 16) * math.ceil(H / 16)
+    ent = max_views * max(scene_sizes)
+    return plan_slots(budget_bytes, n_slots, max_views, px, ent, tiles)
