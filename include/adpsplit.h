@@ -69,13 +69,41 @@ typedef struct {
     int32_t sh_degree;
 } as_gaussians_mut;
 
+/* Split methods: the full AdpSplit and the steps of its ablation (Table 2:
+ * an adaptive number of randomly placed children, then child
+ * initialisation from the regions without merging) plus the fixed-cardinality
+ * random split it replaces (Eq. (vanilla_split_sample); N = 2 is 3DGS,
+ * N = 5 the five-child split of Sec. 1). */
+enum {
+    AS_VARIANT_ADPSPLIT = 0,     /* region children, merged, capped at n_max; parent copy at o/(N+1) */
+    AS_VARIANT_FIXED_N = 1,      /* every candidate: fixed_n random children, parent removed */
+    AS_VARIANT_ADAPTIVE_N = 2,   /* N = min(proposals, n_max) random children, parent removed */
+    AS_VARIANT_CHILD_INIT = 3    /* one child per proposal (no merging), capped at n_max; parent copy */
+};
+
+/* Alternative readings of passages the paper leaves open (bit flags; 0 = the
+ * readings the oracle and this library take by default). */
+enum {
+    AS_SPLIT_ERODE_SIDE = 1,     /* erosion element: square of side r_erode + 1 (offsets -r/2 .. r - r/2), not 2 r_erode + 1 */
+    AS_SPLIT_CROSS_VIEW = 2,     /* merge only proposals of different views */
+    AS_SPLIT_EXTENT_MAX = 4,     /* rank for the n_max cap by the largest scale, not s1 s2 s3 */
+    AS_SPLIT_SHARE_OPACITY = 8   /* children and parent copy all get opacity o/(N+1) */
+};
+
 /* AdpSplit hyper-parameters (Sec. 5 "Implementation": tau_l1 0.1, r_erode 2,
  * m_min 5, L 3, N_max 19, gamma_d 2.0, gamma_c 0.15); eps is the t*
- * stabiliser of Eq. (tstar), eta the shrink factor of Eq. (vanilla_split_scale). */
+ * stabiliser of Eq. (tstar), eta the shrink factor of Eq. (vanilla_split_scale).
+ * noise_n is the number of standard-normal triples per candidate in the
+ * `noise` input of as_adaptive_split (0 means 2); it must cover the largest
+ * random split the variant makes (2; fixed_n; n_max). */
 typedef struct {
     double tau_l1;
     int32_t r_erode, m_min, L, n_max;
     double gamma_d, gamma_c, eps, eta;
+    int32_t variant;     /* AS_VARIANT_* */
+    uint32_t flags;      /* AS_SPLIT_* */
+    int32_t fixed_n;     /* children per candidate of AS_VARIANT_FIXED_N */
+    int32_t noise_n;
 } as_split_params;
 
 /* One retained error region (Sec. 4.1 statistics).  Integer moments are over
@@ -244,13 +272,15 @@ as_status as_accumulate_error_stats(as_ctx *ctx, int32_t width, int32_t height, 
  * extent, and the mode: VANILLA (0, no attributed pixel: the fixed N = 2 split
  * of Eq. (vanilla_split_sample)), RESET (1, attributed pixels but no
  * surviving region: no rows, parent kept), ADAPTIVE (2: N_i children plus a
- * parent copy with opacity o / (N_i + 1)).
+ * parent copy with opacity o / (N_i + 1)); other variants (params->variant)
+ * use mode RANDOM (3: count random children of Eq. (vanilla_split_sample)
+ * with N = count, parent removed).
  *   cand       : [n_cand] candidate ids, strictly ascending
  *   regions    : the regions of all sampled views (any order)
  *   views      : host array [n_views]; a region's view id indexes it
  *   attr_count : [n]
- *   noise      : [n_cand][2][3] standard normals for the VANILLA children
- *   out        : rows = capacity (>= n + n_cand * max(2, n_max + 1) always suffices)
+ *   noise      : [n_cand][noise_n][3] standard normals for the random children
+ *   out        : rows = capacity (>= n + n_cand * max(2, n_max + 1, fixed_n) always suffices)
  *   mode, count: out [n_cand]; offset: out [n_cand] exclusive scan of count
  *   n_out      : out [1] device; the new set is the non-removed Gaussians in
  *                order, then one block per candidate in ascending id order

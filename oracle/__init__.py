@@ -195,14 +195,25 @@ def project_backward(scene, cam, g2d):
     return out
 
 
+VARIANT_ADPSPLIT, VARIANT_FIXED_N, VARIANT_ADAPTIVE_N, VARIANT_CHILD_INIT = 0, 1, 2, 3
+FLAG_ERODE_SIDE, FLAG_CROSS_VIEW, FLAG_EXTENT_MAX, FLAG_SHARE_OPACITY = 1, 2, 4, 8
+
+
 class SplitParams:
     """Sec. 5 defaults: tau_l1 0.1, r_erode 2, m_min 5, L 3, N_max 19,
-    gamma_d 2.0, gamma_c 0.15; eps 1e-8 [A15]; eta 0.8 [A24]."""
+    gamma_d 2.0, gamma_c 0.15; eps 1e-8 [A15]; eta 0.8 [A24].  variant: the
+    full method (0) or a step of the Table 2 ablation / the fixed-N random
+    split (1 fixed N, 2 adaptive N with random placement, 3 child
+    initialisation without merging); flags: alternative readings (1 erosion
+    square of side r+1 [A11], 2 cross-view merging only [A18], 4 extent =
+    largest scale [A22], 8 shared opacity o/(N+1) [A23]); noise_n: normals
+    per candidate in the noise input (0 = 2)."""
 
     def __init__(self, tau_l1=0.1, r_erode=2, m_min=5, L=3, n_max=19, gamma_d=2.0, gamma_c=0.15, eps=1e-8,
-                 eta=0.8):
+                 eta=0.8, variant=0, flags=0, fixed_n=2, noise_n=0):
         self.tau_l1, self.r_erode, self.m_min, self.L, self.n_max = tau_l1, r_erode, m_min, L, n_max
         self.gamma_d, self.gamma_c, self.eps, self.eta = gamma_d, gamma_c, eps, eta
+        self.variant, self.flags, self.fixed_n, self.noise_n = variant, flags, fixed_n, noise_n
 
 
 def error_stats(img, gt, dom, is_cand, view, params, attr, cap=None, want_maps=False):
@@ -228,7 +239,8 @@ def error_stats(img, gt, dom, is_cand, view, params, attr, cap=None, want_maps=F
     r = lib().orc_error_stats(ctypes.c_int(W), ctypes.c_int(H), _p(img), _p(gt), _p(dom),
                               ctypes.c_int64(is_cand.shape[0]), _p(is_cand), ctypes.c_int(view),
                               ctypes.c_double(params.tau_l1), ctypes.c_int(params.r_erode),
-                              ctypes.c_int(params.m_min), ctypes.c_int(params.L), _p(attr), _p(regs),
+                              ctypes.c_int(params.m_min), ctypes.c_int(params.L),
+                              ctypes.c_int(1 if params.flags & FLAG_ERODE_SIDE else 0), _p(attr), _p(regs),
                               ctypes.c_int64(cap), *ptrs)
     if r < 0:
         raise RuntimeError("oracle region capacity exceeded: need %d" % (-r - 1))
@@ -244,11 +256,13 @@ def adaptive_split(scene, cand, regions, cams, attr, params, noise, out_cap=None
     regions = np.ascontiguousarray(regions, dtype=REGION_DTYPE)
     camp = np.ascontiguousarray(np.stack([pack_camera(c) for c in cams]) if len(cams) else np.zeros((1, 21)))
     attr = _c(attr, np.int32)
-    noise = _c(noise, np.float32).reshape(nc * 6) if nc else np.zeros(6, np.float32)
-    prm = np.array([params.gamma_d, params.gamma_c, params.eps, params.eta, params.n_max], np.float64)
+    nz = params.noise_n if params.noise_n > 0 else 2
+    noise = _c(noise, np.float32).reshape(nc * nz * 3) if nc else np.zeros(3 * nz, np.float32)
+    prm = np.array([params.gamma_d, params.gamma_c, params.eps, params.eta, params.n_max, params.variant,
+                    params.flags, params.fixed_n, params.noise_n], np.float64)
     nk = (scene.sh_degree + 1) ** 2
     if out_cap is None:
-        out_cap = n + nc * max(2, params.n_max + 1)
+        out_cap = n + nc * max(2, params.n_max + 1, params.fixed_n if params.variant == VARIANT_FIXED_N else 0)
     mode = np.zeros(max(nc, 1), np.uint8)
     count = np.zeros(max(nc, 1), np.int32)
     offset = np.zeros(max(nc, 1), np.int64)

@@ -722,7 +722,7 @@ static void region_stats(oregion *r) {
  * Returns the number of retained regions, or -(count)-1 if cap was exceeded. */
 int64_t orc_error_stats(int W, int H, const float *img, const float *gt, const int32_t *dom,
                         int64_t n, const uint8_t *is_cand, int view, double tau, int r_erode, int m_min,
-                        int L, int32_t *attr, oregion *regions, int64_t cap,
+                        int L, int erode_side, int32_t *attr, oregion *regions, int64_t cap,
                         double *E_out, uint8_t *M_out, uint8_t *Mp_out, uint8_t *B_out, int32_t *label_out) {
     (void)n;
     int64_t P = (int64_t)W * H;
@@ -745,12 +745,14 @@ int64_t orc_error_stats(int W, int H, const float *img, const float *gt, const i
         int32_t d = dom[u];
         if (M[u] && d >= 0 && is_cand[d]) attr[d] += 1;
     }
-    /* erosion with a (2r+1)^2 square; pixels outside the image count as set [A11] */
+    /* erosion with a (2r+1)^2 square; pixels outside the image count as set [A11].
+     * Alternative reading (erode_side): a square of side r+1, offsets -r/2 .. r - r/2. */
+    int lo = erode_side ? r_erode / 2 : r_erode, hi = erode_side ? r_erode - r_erode / 2 : r_erode;
     for (int y = 0; y < H; y++)
         for (int x = 0; x < W; x++) {
             int keep = M[(int64_t)y * W + x];
-            for (int dy = -r_erode; dy <= r_erode && keep; dy++)
-                for (int dx = -r_erode; dx <= r_erode && keep; dx++) {
+            for (int dy = -lo; dy <= hi && keep; dy++)
+                for (int dx = -lo; dx <= hi && keep; dx++) {
                     int xx = x + dx, yy = y + dy;
                     if (xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
                     if (!M[(int64_t)yy * W + xx]) keep = 0;
@@ -820,7 +822,7 @@ int64_t orc_error_stats(int W, int H, const float *img, const float *gt, const i
 /* Sec. 4.2 + App. A: one child proposal per retained region.               */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int ok;
+    int ok, view;
     double mu[3], R[9], s[3], rgb[3];
     double Sinv[9], Sig[9];
 } oprop;
@@ -997,6 +999,9 @@ static void rot_to_quat(const double R[9], double q[4]) {
 typedef struct {
     double gamma_d, gamma_c, eps, eta;
     int n_max;
+    int variant;      /* 0 AdpSplit, 1 fixed N random, 2 adaptive N random, 3 child init without merging (Table 2) */
+    int flags;        /* 2 merge across views only [A18 alt], 4 extent = max scale [A22 alt], 8 shared opacity [A23 B] */
+    int fixed_n, noise_n;
 } osplit;
 
 typedef struct { double mu[3], R[9], s[3], rgb[3], extent; int64_t rep; } ogroup;
@@ -1037,6 +1042,8 @@ int64_t orc_adaptive_split(int64_t n, int deg, const float *means, const float *
     osplit sp;
     sp.gamma_d = params[0]; sp.gamma_c = params[1]; sp.eps = params[2]; sp.eta = params[3];
     sp.n_max = (int)params[4];
+    sp.variant = (int)params[5]; sp.flags = (int)params[6]; sp.fixed_n = (int)params[7];
+    sp.noise_n = (int)params[8] > 0 ? (int)params[8] : 2;
     int nk = (deg + 1) * (deg + 1);
     ocam *cams = (ocam *)malloc(sizeof(ocam) * (n_views > 0 ? n_views : 1));
     for (int v = 0; v < n_views; v++) cam_unpack(cams_packed + 21 * v, &cams[v]);
@@ -1063,14 +1070,17 @@ int64_t orc_adaptive_split(int64_t n, int deg, const float *means, const float *
         int64_t np = 0;
         for (int64_t k = 0; k < nr; k++) {
             const oregion *r = &regions[ord[r0 + k].idx];
+            if (sp.variant == 1) break;   /* the fixed-N random split ignores the regions */
             child_from_region(&par, r, &cams[r->view], sp.eps, &props[np]);
+            props[np].view = r->view;
             if (props[np].ok) np++;
         }
         /* Eq. (merge_conditions) over every pair of this parent's proposals [A17-A19] */
         int64_t *uf = (int64_t *)malloc(sizeof(int64_t) * (size_t)(np > 0 ? np : 1));
         for (int64_t a = 0; a < np; a++) uf[a] = a;
-        for (int64_t a = 0; a < np; a++)
+        for (int64_t a = 0; a < np && sp.variant == 0; a++)   /* the ablation variants do not merge */
             for (int64_t b = a + 1; b < np; b++) {
+                if ((sp.flags & 2) && props[a].view == props[b].view) continue;   /* [A18] alternative */
                 double dl[3] = {props[b].mu[0] - props[a].mu[0], props[b].mu[1] - props[a].mu[1],
                                 props[b].mu[2] - props[a].mu[2]};
                 double dm = maha(props[a].Sinv, dl) + maha(props[b].Sinv, dl);
@@ -1128,15 +1138,18 @@ int64_t orc_adaptive_split(int64_t n, int deg, const float *means, const float *
                 }
                 memcpy(gr.R, E, sizeof(gr.R));
             }
-            gr.extent = gr.s[0] * gr.s[1] * gr.s[2];
+            if (sp.flags & 4) gr.extent = fmax(gr.s[0], fmax(gr.s[1], gr.s[2]));   /* [A22] alternative */
+            else gr.extent = gr.s[0] * gr.s[1] * gr.s[2];
             groups[ng++] = gr;
         }
         /* keep the N_max largest by covariance extent */
         qsort(groups, (size_t)ng, sizeof(ogroup), group_cmp);
         if (ng > sp.n_max) ng = sp.n_max;
         /* mode selection (Sec. 5 "Implementation") */
-        if (attr[id] == 0) { mode[ci] = 0; count[ci] = 2; }
+        if (sp.variant == 1) { mode[ci] = 3; count[ci] = sp.fixed_n; }          /* fixed-N random split */
+        else if (attr[id] == 0) { mode[ci] = 0; count[ci] = 2; }
         else if (ng == 0) { mode[ci] = 1; count[ci] = 0; }
+        else if (sp.variant == 2) { mode[ci] = 3; count[ci] = (int32_t)ng; }    /* adaptive N, random placement */
         else { mode[ci] = 2; count[ci] = (int32_t)ng + 1; }
         if (mode[ci] == 2) {
             kept[ci] = (ogroup *)malloc(sizeof(ogroup) * (size_t)ng);
@@ -1175,17 +1188,18 @@ int64_t orc_adaptive_split(int64_t n, int deg, const float *means, const float *
         int64_t base = nsurv + offset[ci];
         ogauss par;
         load_gauss(n, id, means, log_scales, quats, opac, &par);
-        if (mode[ci] == 0) {
-            /* Eq. (vanilla_split_sample), Eq. (vanilla_split_scale) with N = 2 */
-            for (int c2 = 0; c2 < 2; c2++) {
+        if (mode[ci] == 0 || mode[ci] == 3) {
+            /* Eq. (vanilla_split_sample), Eq. (vanilla_split_scale) with N = count (2 for the fallback) */
+            int N = count[ci];
+            for (int c2 = 0; c2 < N; c2++) {
                 int64_t dst = base + c2;
                 COPY_ROW(dst, id);
                 double dl[3];
-                for (int k = 0; k < 3; k++) dl[k] = par.s[k] * (double)noise[(ci * 2 + c2) * 3 + k];
+                for (int k = 0; k < 3; k++) dl[k] = par.s[k] * (double)noise[(ci * sp.noise_n + c2) * 3 + k];
                 for (int k = 0; k < 3; k++) {
                     double m = par.mu[k] + (par.R[k * 3 + 0] * dl[0] + par.R[k * 3 + 1] * dl[1] + par.R[k * 3 + 2] * dl[2]);
                     o_means[k * out_cap + dst] = (float)m;
-                    o_log_scales[k * out_cap + dst] = (float)((double)log_scales[k * n + id] - log(sp.eta * 2.0));
+                    o_log_scales[k * out_cap + dst] = (float)((double)log_scales[k * n + id] - log(sp.eta * (double)N));
                 }
             }
         } else if (mode[ci] == 2) {
@@ -1207,6 +1221,8 @@ int64_t orc_adaptive_split(int64_t n, int deg, const float *means, const float *
             COPY_ROW(dst, id);
             double pr = par.o / (double)(ng + 1);
             o_opac[dst] = (float)log(pr / (1.0 - pr));
+            if (sp.flags & 8)   /* [A23] second reading: the whole block at o/(N_i+1) */
+                for (int g2 = 0; g2 < ng; g2++) o_opac[base + g2] = o_opac[dst];
         }
     }
 #undef COPY_ROW

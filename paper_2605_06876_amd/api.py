@@ -43,7 +43,9 @@ class _Gaussians(ctypes.Structure):
 class _SplitParams(ctypes.Structure):
     _fields_ = [("tau_l1", ctypes.c_double), ("r_erode", ctypes.c_int32), ("m_min", ctypes.c_int32),
                 ("L", ctypes.c_int32), ("n_max", ctypes.c_int32), ("gamma_d", ctypes.c_double),
-                ("gamma_c", ctypes.c_double), ("eps", ctypes.c_double), ("eta", ctypes.c_double)]
+                ("gamma_c", ctypes.c_double), ("eps", ctypes.c_double), ("eta", ctypes.c_double),
+                ("variant", ctypes.c_int32), ("flags", ctypes.c_uint32), ("fixed_n", ctypes.c_int32),
+                ("noise_n", ctypes.c_int32)]
 
 
 class _RegionBuf(ctypes.Structure):
@@ -134,17 +136,25 @@ def camera_struct(cam):
     return c
 
 
+VARIANT_ADPSPLIT, VARIANT_FIXED_N, VARIANT_ADAPTIVE_N, VARIANT_CHILD_INIT = 0, 1, 2, 3
+SPLIT_ERODE_SIDE, SPLIT_CROSS_VIEW, SPLIT_EXTENT_MAX, SPLIT_SHARE_OPACITY = 1, 2, 4, 8
+MODE_RANDOM = 3
+
+
 class SplitParams:
     """AdpSplit hyper-parameters; defaults from Sec. 5 (tau_l1 0.1, r_erode 2,
-    m_min 5, L 3, N_max 19, gamma_d 2.0, gamma_c 0.15), eps 1e-8, eta 0.8."""
+    m_min 5, L 3, N_max 19, gamma_d 2.0, gamma_c 0.15), eps 1e-8, eta 0.8;
+    variant / flags / fixed_n / noise_n as as_split_params."""
 
-    def __init__(self, tau_l1=0.1, r_erode=2, m_min=5, L=3, n_max=19, gamma_d=2.0, gamma_c=0.15, eps=1e-8, eta=0.8):
+    def __init__(self, tau_l1=0.1, r_erode=2, m_min=5, L=3, n_max=19, gamma_d=2.0, gamma_c=0.15, eps=1e-8, eta=0.8,
+                 variant=0, flags=0, fixed_n=2, noise_n=0):
         self.tau_l1, self.r_erode, self.m_min, self.L, self.n_max = tau_l1, r_erode, m_min, L, n_max
         self.gamma_d, self.gamma_c, self.eps, self.eta = gamma_d, gamma_c, eps, eta
+        self.variant, self.flags, self.fixed_n, self.noise_n = variant, flags, fixed_n, noise_n
 
     def struct(self):
         return _SplitParams(self.tau_l1, self.r_erode, self.m_min, self.L, self.n_max, self.gamma_d, self.gamma_c,
-                            self.eps, self.eta)
+                            self.eps, self.eta, self.variant, self.flags, self.fixed_n, self.noise_n)
 
 
 class Gaussians:
@@ -484,7 +494,7 @@ def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=
     count, offset, n_out tensor)."""
     nc = int(cand.shape[0])
     if out is None:
-        cap = g.n + nc * max(2, params.n_max + 1)
+        cap = g.n + nc * max(2, params.n_max + 1, params.fixed_n if params.variant == VARIANT_FIXED_N else 0)
         out = Gaussians.empty(max(cap, 1), g.sh_degree)
     mode = torch.zeros(max(nc, 1), dtype=torch.uint8, device="cuda")
     count = torch.zeros(max(nc, 1), dtype=torch.int32, device="cuda")

@@ -23,6 +23,7 @@ SOURCES = {
     "project.hip": ["-ffp-contract=off"],
     "project_bwd.hip": ["-ffp-contract=off"],
     "binning.hip": [],
+    "radix.hip": [],
     "blend.hip": [],
     "errstats.hip": ["-ffp-contract=off"],
     "split.hip": ["-ffp-contract=off"],

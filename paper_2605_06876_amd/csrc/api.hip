@@ -73,8 +73,16 @@ GradPtrs mptrs(const as_gaussians_mut *g) {
 bool check_params(const as_split_params *p, const char *what) {
     if (!p) { as_set_error("%s: null params", what); return false; }
     if (!(p->tau_l1 >= 0.0 && p->tau_l1 < 1.0) || p->r_erode < 0 || p->r_erode > 64 || p->m_min < 1 || p->L < 1 ||
-        p->L > 255 || p->n_max < 0 || !(p->gamma_d >= 0.0) || !(p->gamma_c >= 0.0) || !(p->eps >= 0.0) || !(p->eta > 0.0)) {
+        p->L > 255 || p->n_max < 0 || p->n_max > 4096 || !(p->gamma_d >= 0.0) || !(p->gamma_c >= 0.0) ||
+        !(p->eps >= 0.0) || !(p->eta > 0.0)) {
         as_set_error("%s: parameter out of range", what);
+        return false;
+    }
+    if (p->variant < AS_VARIANT_ADPSPLIT || p->variant > AS_VARIANT_CHILD_INIT ||
+        (p->flags & ~(uint32_t)(AS_SPLIT_ERODE_SIDE | AS_SPLIT_CROSS_VIEW | AS_SPLIT_EXTENT_MAX | AS_SPLIT_SHARE_OPACITY)) ||
+        (p->variant == AS_VARIANT_FIXED_N && (p->fixed_n < 1 || p->fixed_n > 4096)) || p->noise_n < 0) {
+        as_set_error("%s: variant %d / flags 0x%x / fixed_n %d / noise_n %d invalid", what, p->variant, p->flags,
+                     p->fixed_n, p->noise_n);
         return false;
     }
     return true;
@@ -593,7 +601,13 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
         return AS_ERR_ARG;
     }
     if (!check_gauss(g, "as_adaptive_split") || !check_params(params, "as_adaptive_split")) return AS_ERR_ARG;
-    const int64_t per = params->n_max + 1 > 2 ? params->n_max + 1 : 2;
+    if ((params->noise_n ? params->noise_n : 2) < split_noise_need(*params)) {
+        as_set_error("as_adaptive_split: noise_n %d below the %d random children this variant may draw",
+                     params->noise_n, split_noise_need(*params));
+        return AS_ERR_ARG;
+    }
+    int64_t per = params->n_max + 1 > 2 ? params->n_max + 1 : 2;
+    if (params->variant == AS_VARIANT_FIXED_N && params->fixed_n > per) per = params->fixed_n;
     const int64_t bound = g->n + n_cand * per;
     if (!check_mut(out, 0, g->sh_degree, "as_adaptive_split")) return AS_ERR_ARG;
     if (out->n < bound) {

@@ -1,5 +1,5 @@
-// Tile binning: exclusive scans, tile key emission, a stable LSD radix sort
-// staged through LDS, and per-tile ranges.
+// Tile binning: exclusive scans, tile key emission and per-tile ranges (the
+// radix sort between them is in radix.hip).
 //
 // The rasterizer composites each pixel over the Gaussians in ascending
 // (depth, id) order (Sec. 3, front-to-back blending).  The host sorts the
@@ -194,114 +194,6 @@ __global__ void k_gather_u32(int64_t n, const uint32_t *__restrict__ src, const 
     if (r < n) dst[r] = src[idx[r]];
 }
 
-// ---- LSD radix sort --------------------------------------------------------------------
-//
-// One pass per digit of RB bits: a per-block digit histogram (block-major
-// chunks of the input), an exclusive scan of the digit-major histogram, and a
-// stable scatter.  Inside a block, a wave ranks its 64 keys among equal digits
-// with RB ballots (lanes whose digit matches bit by bit), and per-wave digit
-// counters in LDS carry the running offsets across the wave's rounds.
-
-constexpr int RS_THREADS = 256;
-constexpr int RS_TILE = 1024;   // keys per block iteration: 4 waves x 4 rounds x 64 lanes
-
-__device__ __forceinline__ void rs_chunk(int64_t n, int G, int b, int64_t *beg, int64_t *end) {
-    int64_t chunk = (n + G - 1) / G;
-    chunk = (chunk + RS_TILE - 1) / RS_TILE * RS_TILE;
-    *beg = (int64_t)b * chunk;
-    *end = *beg + chunk < n ? *beg + chunk : n;
-}
-
-template <typename K, int RB>
-__global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const K *__restrict__ kin, const uint32_t *n_dev,
-                                                           int64_t cap, int shift, uint32_t mask,
-                                                           uint32_t *__restrict__ hist) {
-    constexpr int NB = 1 << RB;
-    __shared__ uint32_t s_h[4][NB];
-    const int tid = threadIdx.x, w = tid >> 6;
-    if (tid < NB)
-        for (int k = 0; k < 4; k++) s_h[k][tid] = 0;
-    __syncthreads();
-    int64_t n = *n_dev;
-    if (n > cap) n = cap;
-    int64_t beg, end;
-    rs_chunk(n, gridDim.x, blockIdx.x, &beg, &end);
-    for (int64_t idx = beg + tid; idx < end; idx += RS_THREADS) {
-        const uint32_t d = (uint32_t)(kin[idx] >> shift) & mask;
-        atomicAdd(&s_h[w][d], 1u);
-    }
-    __syncthreads();
-    if (tid < NB) hist[(int64_t)tid * gridDim.x + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
-}
-
-template <typename K, int RB>
-__global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const K *__restrict__ kin,
-                                                              const uint32_t *__restrict__ vin, K *__restrict__ kout,
-                                                              uint32_t *__restrict__ vout, const uint32_t *n_dev,
-                                                              int64_t cap, int shift, uint32_t mask,
-                                                              const uint32_t *__restrict__ hist) {
-    constexpr int NB = 1 << RB;
-    __shared__ uint32_t s_base[NB];
-    __shared__ uint32_t s_cnt[4][NB];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    int64_t n = *n_dev;
-    if (n > cap) n = cap;
-    int64_t beg, end;
-    rs_chunk(n, gridDim.x, blockIdx.x, &beg, &end);
-    if (tid < NB) s_base[tid] = hist[(int64_t)tid * gridDim.x + blockIdx.x];
-    const uint64_t lt = lanemask_lt();
-    for (int64_t t0 = beg; t0 < end; t0 += RS_TILE) {
-        if (tid < NB)
-            for (int k = 0; k < 4; k++) s_cnt[k][tid] = 0;
-        __syncthreads();
-        K key[4];
-        uint32_t val[4], dig[4], loc[4];
-        bool ok[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int64_t idx = t0 + w * 256 + j * 64 + lane;
-            ok[j] = idx < end;
-            key[j] = ok[j] ? kin[idx] : (K)0;
-            val[j] = ok[j] ? vin[idx] : 0u;
-            const uint32_t d = (uint32_t)(key[j] >> shift) & mask;
-            dig[j] = d;
-            uint64_t peers = __ballot(ok[j]);
-#pragma unroll
-            for (int bit = 0; bit < RB; bit++) {
-                const bool set = (d >> bit) & 1u;
-                const uint64_t m = __ballot(set);
-                peers &= set ? m : ~m;
-            }
-            const uint32_t rank = (uint32_t)__popcll(peers & lt);
-            const uint32_t before = s_cnt[w][d];
-            __builtin_amdgcn_wave_barrier();
-            if (ok[j] && rank == 0) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
-            __builtin_amdgcn_wave_barrier();
-            loc[j] = before + rank;
-        }
-        __syncthreads();
-        if (tid < NB) {
-            const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
-            const uint32_t base = s_base[tid];
-            s_cnt[0][tid] = base;
-            s_cnt[1][tid] = base + c0;
-            s_cnt[2][tid] = base + c0 + c1;
-            s_cnt[3][tid] = base + c0 + c1 + c2;
-            s_base[tid] = base + c0 + c1 + c2 + c3;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            if (ok[j]) {
-                const uint32_t pos = s_cnt[w][dig[j]] + loc[j];
-                kout[pos] = key[j];
-                vout[pos] = val[j];
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // [start, end) of every tile in the sorted tile keys (tiles without keys keep
 // the [0, 0) the caller filled).
 __global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles,
@@ -344,49 +236,6 @@ void fill_impl(T *p, T v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
 }
 
-int rs_grid(int64_t n_hint) {
-    int64_t g = (n_hint + 8 * RS_TILE - 1) / (8 * RS_TILE);
-    if (g < 1) g = 1;
-    if (g > 2048) g = 2048;
-    return (int)g;
-}
-
-template <typename K, int RB>
-void radix_pass(K *kin, uint32_t *vin, K *kout, uint32_t *vout, const uint32_t *n_dev, int64_t cap, int G, int shift,
-                int width, uint32_t *h, void *tmp, hipStream_t s) {
-    const uint32_t mask = (1u << width) - 1u;   // width <= RB: digits above the range stay out
-    hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(G), dim3(RS_THREADS), 0, s, kin, n_dev, cap, shift, mask, h);
-    scan_impl<uint32_t, uint32_t>(h, h, (int64_t)(1 << RB) * G, (uint32_t *)nullptr, tmp, s);
-    hipLaunchKernelGGL((k_radix_scatter<K, RB>), dim3(G), dim3(RS_THREADS), 0, s, kin, vin, kout, vout, n_dev, cap,
-                       shift, mask, h);
-}
-
-template <typename K>
-int radix_sort_impl(K *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
-                    int hi_bit, int rb, void *hist, hipStream_t s) {
-    const int G = rs_grid(n_hint);
-    uint32_t *h = reinterpret_cast<uint32_t *>(hist);
-    void *tmp = reinterpret_cast<char *>(hist) + (size_t)(256 * G) * 4;
-    if (rb < 4) rb = 4;
-    if (rb > 8) rb = 8;
-    int sel = 0;
-    for (int shift = lo_bit; shift < hi_bit; shift += rb) {
-        // the last digit needs only the bits that are left
-        const int w = hi_bit - shift < rb ? hi_bit - shift : rb;
-        K *ki = keys[sel], *ko = keys[sel ^ 1];
-        uint32_t *vi = vals[sel], *vo = vals[sel ^ 1];
-        switch (w) {
-        case 1: case 2: case 3: case 4: radix_pass<K, 4>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
-        case 5: radix_pass<K, 5>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
-        case 6: radix_pass<K, 6>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
-        case 7: radix_pass<K, 7>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
-        default: radix_pass<K, 8>(ki, vi, ko, vo, n_dev, cap, G, shift, w, h, tmp, s); break;
-        }
-        sel ^= 1;
-    }
-    return sel;
-}
-
 }  // namespace
 
 size_t scan_tmp_bytes(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE + 1) * 8 + 256; }
@@ -399,21 +248,6 @@ void scan_u8_to_i64(const uint8_t *in, int64_t *out, int64_t n, int64_t *total, 
 }
 void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total, void *tmp, hipStream_t s) {
     scan_impl<int32_t, int64_t>(in, out, n, total, tmp, s);
-}
-
-size_t sort_hist_bytes(int64_t n_hint) {
-    const int64_t G = rs_grid(n_hint);
-    return (size_t)(256 * G) * 4 + scan_tmp_bytes(256 * G) + 64;
-}
-
-int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
-                   int hi_bit, int radix_bits, void *hist, hipStream_t s) {
-    return radix_sort_impl<uint32_t>(keys, vals, n_dev, cap, n_hint, lo_bit, hi_bit, radix_bits, hist, s);
-}
-
-int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
-                   int hi_bit, int radix_bits, void *hist, hipStream_t s) {
-    return radix_sort_impl<uint64_t>(keys, vals, n_dev, cap, n_hint, lo_bit, hi_bit, radix_bits, hist, s);
 }
 
 void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals, uint32_t *n32,

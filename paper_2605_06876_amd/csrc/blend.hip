@@ -46,9 +46,11 @@ struct StagedRec {
     float4 ex;  // b, box masks (bits), entry id (bits), 0
 };
 
+// q = a' dx^2 + b' dx dy + c' dy^2 + log2(o) as (a' dx + b' dy) dx + (c' dy dy
+// + log2(o)): two multiplies and three fused multiply-adds.
 __device__ __forceinline__ float blend_exponent(float dx, float dy, const float4 &mc, const float4 &cc) {
 #pragma clang fp contract(off)
-    return __fmaf_rn(mc.z * dx, dx, __fmaf_rn(cc.x * dy, dy, __fmaf_rn(mc.w * dx, dy, cc.y)));
+    return __fmaf_rn(__fmaf_rn(mc.z, dx, mc.w * dy), dx, __fmaf_rn(cc.x * dy, dy, cc.y));
 }
 
 __device__ __forceinline__ uint32_t span_mask(int lo, int hi) {   // bits lo..hi of 16, clamped
@@ -93,6 +95,7 @@ __device__ __forceinline__ void stage(const Fetched &f, int ox, int oy, StagedRe
 // sb = 4 w + row of the tile (blocks in row-major order).
 struct LaneGeom {
     int lx, ly, row;
+    uint32_t pbits;    // this pixel's column and row bits in a record's box masks
     uint32_t bx, by;   // the block's column / row bits in a record's box masks
 };
 
@@ -106,6 +109,7 @@ __device__ __forceinline__ LaneGeom lane_geom(int tid) {
     g.ly = sby * 4 + (c >> 2);
     g.bx = 0xFu << (sbx * 4);
     g.by = (0xFu << (sby * 4)) << 16;
+    g.pbits = (1u << g.lx) | (1u << (16 + g.ly));
     return g;
 }
 
@@ -143,14 +147,14 @@ __device__ __forceinline__ float dpp_f(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, true));
 }
 
-// Sum over the 16 lanes of each DPP row; the row's total lands in its lane 15
-// (every lane of the wave must be active).
-__device__ __forceinline__ float row_sum_to_lane15(float v0) {
-    float v = v0 + dpp_f<0x111, 0xf, 0xf>(v0);   // row_shr:1
-    v += dpp_f<0x112, 0xf, 0xf>(v0);              // row_shr:2
-    v += dpp_f<0x113, 0xf, 0xf>(v0);              // row_shr:3  -> lanes hold sums of 4
-    v += dpp_f<0x114, 0xf, 0xe>(v);               // row_shr:4 into banks 1-3
-    v += dpp_f<0x118, 0xf, 0xc>(v);               // row_shr:8 into banks 2-3
+// Sum over the 16 lanes of each DPP row, every lane gets the total: butterfly
+// over lane distance 1, 2 (quad permutations), 4 (half-row mirror) and 8 (row
+// mirror), four DPP adds (every lane of the wave must be active).
+__device__ __forceinline__ float row_sum(float v) {
+    v += dpp_f<0xB1, 0xf, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E, 0xf, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f<0x141, 0xf, 0xf>(v);   // row_half_mirror: quads 0<->1, 2<->3 (each quad holds one value)
+    v += dpp_f<0x140, 0xf, 0xf>(v);   // row_mirror: halves 0<->1
     return v;
 }
 
@@ -228,35 +232,60 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
             const int cnt = (int)min((uint32_t)BATCH, end - b0);
             const int nh = compact_rows<BATCH>(sh.rec, cnt, sh.hits[w], w, lg.row, [](int) { return true; });
             if (done) continue;
-            // one index ahead: the next record's LDS loads do not wait on the index load
-            int jn = hits[0];
-            for (int h = 0; h < nh; h++) {
-                const int j = jn;
-                jn = hits[h + 1];
-                const float4 q0 = sh.rec[j].mc, q1 = sh.rec[j].cc, q2 = sh.rec[j].ex;
-                const uint32_t m = __float_as_uint(q2.y);
-                const bool inb = (m >> lg.lx) & (m >> (16 + lg.ly)) & 1u;   // the box holds this pixel
-                const float dx = q0.x - px, dy = q0.y - py;
-                const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, q0, q1));
-                const float alpha = fminf(ALPHA_MAX, araw);
-                const bool ok = inb && alpha >= ALPHA_MIN;
-                const float testT = T * (1.0f - alpha);
-                if (ok && testT < T_STOP) {
+            // Two hits per step: both records' loads and alpha evaluations are
+            // independent and overlap; only the compositing is sequential.
+            // The next step's indices are loaded one step ahead.
+            int ja = hits[0], jb = hits[1];
+            int h = 0;
+            for (; h < nh; h += 2) {
+                const bool two = h + 1 < nh;
+                const int j0 = ja, j1 = two ? jb : ja;
+                ja = hits[h + 2];
+                jb = hits[h + 3];
+                const float4 a0 = sh.rec[j0].mc, a1 = sh.rec[j0].cc, a2 = sh.rec[j0].ex;
+                const float4 b0q = sh.rec[j1].mc, b1q = sh.rec[j1].cc, b2q = sh.rec[j1].ex;
+                const uint32_t ma = __float_as_uint(a2.y), mb = __float_as_uint(b2q.y);
+                const float dxa = a0.x - px, dya = a0.y - py, dxb = b0q.x - px, dyb = b0q.y - py;
+                const float rawa = __builtin_amdgcn_exp2f(blend_exponent(dxa, dya, a0, a1));
+                const float rawb = __builtin_amdgcn_exp2f(blend_exponent(dxb, dyb, b0q, b1q));
+                const float alpha_a = fminf(ALPHA_MAX, rawa), alpha_b = fminf(ALPHA_MAX, rawb);
+                const bool oka = (ma & lg.pbits) == lg.pbits && alpha_a >= ALPHA_MIN;   // box holds the pixel
+                const bool okb = two && (mb & lg.pbits) == lg.pbits && alpha_b >= ALPHA_MIN;
+                // first record
+                float testT = T * (1.0f - alpha_a);
+                if (oka && testT < T_STOP) {
                     done = 1;
                     break;
                 }
                 // a non-contributor adds exactly zero and changes nothing
-                const float wgt = ok ? alpha * T : 0.0f;
-                C0 += wgt * q1.z;
-                C1 += wgt * q1.w;
-                C2 += wgt * q2.x;
+                float wgt = oka ? alpha_a * T : 0.0f;
+                C0 += wgt * a1.z;
+                C1 += wgt * a1.w;
+                C2 += wgt * a2.x;
                 if (wgt > wbest) {
                     wbest = wgt;
-                    dom = (int32_t)__float_as_uint(q2.z);
+                    dom = (int32_t)__float_as_uint(a2.z);
                 }
-                T = ok ? testT : T;
-                last = ok ? b0 + (uint32_t)j : last;
-                nc += ok ? 1u : 0u;
+                T = oka ? testT : T;
+                last = oka ? b0 + (uint32_t)j0 : last;
+                nc += oka ? 1u : 0u;
+                // second record
+                testT = T * (1.0f - alpha_b);
+                if (okb && testT < T_STOP) {
+                    done = 1;
+                    break;
+                }
+                wgt = okb ? alpha_b * T : 0.0f;
+                C0 += wgt * b1q.z;
+                C1 += wgt * b1q.w;
+                C2 += wgt * b2q.x;
+                if (wgt > wbest) {
+                    wbest = wgt;
+                    dom = (int32_t)__float_as_uint(b2q.z);
+                }
+                T = okb ? testT : T;
+                last = okb ? b0 + (uint32_t)j1 : last;
+                nc += okb ? 1u : 0u;
             }
         }
 
@@ -406,7 +435,7 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
                 const float dx = q0.x - px, dy = q0.y - py;
                 const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, q0, q1));
                 const float alpha = fminf(ALPHA_MAX, araw);
-                const bool contrib = valid && has && gidx <= lastp && ((m >> lg.lx) & (m >> (16 + lg.ly)) & 1u) &&
+                const bool contrib = valid && has && gidx <= lastp && (m & lg.pbits) == lg.pbits &&
                                      alpha >= ALPHA_MIN;
                 float g[9];
 #pragma unroll
@@ -444,7 +473,7 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
                 const uint64_t cb = __ballot(contrib);
                 if (cb) {
 #pragma unroll
-                    for (int k = 0; k < 9; k++) g[k] = row_sum_to_lane15(g[k]);
+                    for (int k = 0; k < 9; k++) g[k] = row_sum(g[k]);
                     if ((lane & 15) == 15 && ((cb >> (lg.row * 16)) & 0xFFFFull)) {
 #pragma unroll
                         for (int k = 0; k < 9; k++) atomicAdd(&s_gacc[k][j], g[k]);

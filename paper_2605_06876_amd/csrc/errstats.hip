@@ -7,12 +7,13 @@
 // computed in FP64 / exact integers; this file is compiled with
 // -ffp-contract=off.  Connected components use a lock-free union-find whose
 // roots are always the smallest pixel index of their component, so labels are
-// canonical and independent of thread scheduling.
+// canonical and independent of thread scheduling: first inside 16x16 tiles in
+// LDS (fused with the erosion), then across tile borders in global memory.
 #include "internal.h"
 
 namespace {
 
-enum { ES_M, ES_B, ES_LABEL, ES_FLAG, ES_SLOT, ES_ROOT, ES_MOM, ES_KEEP, ES_KIDX, ES_SCAN, ES_TOT };
+enum { ES_M, ES_B, ES_LABEL, ES_MOM, ES_KEEP, ES_KIDX, ES_SCAN, ES_TOT };
 
 __device__ __forceinline__ double dev_bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
@@ -72,32 +73,6 @@ __global__ void k_classify(int64_t P, const double *__restrict__ err, const unsi
     }
 }
 
-// M' = erosion of M with a (2r+1)^2 square (outside counts as set); active
-// pixels start as their own component.
-__global__ void k_erode_init(int W, int H, int r, const uint8_t *__restrict__ M, const int32_t *__restrict__ dom,
-                             const uint8_t *__restrict__ is_cand, int32_t *__restrict__ label) {
-    const int64_t P = (int64_t)W * H;
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= P) return;
-    const int x = (int)(u % W), y = (int)(u / W);
-    bool keep = M[u] != 0;
-    for (int dy = -r; dy <= r && keep; dy++) {
-        const int yy = y + dy;
-        if (yy < 0 || yy >= H) continue;
-        for (int dx = -r; dx <= r; dx++) {
-            const int xx = x + dx;
-            if (xx < 0 || xx >= W) continue;
-            if (!M[(int64_t)yy * W + xx]) {
-                keep = false;
-                break;
-            }
-        }
-    }
-    const int32_t d = dom[u];
-    const bool active = keep && d >= 0 && is_cand[d];
-    label[u] = active ? (int32_t)u : -1;
-}
-
 __device__ __forceinline__ int32_t uf_load(const int32_t *L, int32_t x) {
     return __hip_atomic_load(L + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -128,13 +103,134 @@ __device__ __forceinline__ void uf_unite(int32_t *L, int32_t a, int32_t b) {
     }
 }
 
-__global__ void k_ccl_union(int W, int H, const int32_t *__restrict__ dom, const uint8_t *__restrict__ B,
-                            int32_t *label) {
+// The same union-find on a block's LDS array.
+__device__ __forceinline__ int lds_find(int32_t *L, int x) {
+    int p = __hip_atomic_load(L + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    while (p != x) {
+        x = p;
+        p = __hip_atomic_load(L + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    return x;
+}
+
+__device__ __forceinline__ void lds_unite(int32_t *L, int a, int b) {
+    while (true) {
+        a = lds_find(L, a);
+        b = lds_find(L, b);
+        if (a == b) return;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicMin(L + a, b);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+constexpr int ET = 16;      // pixel tile of the erosion / local components
+constexpr int EMAX_R = 8;   // erosion radii up to this use an LDS tile with halo
+constexpr int ES = ET + 2 * EMAX_R;
+
+// M' = erosion of M with a square element of offsets [-lo, hi] per axis
+// ((2r+1)^2: lo = hi = r; pixels outside the image count as set); active = M'
+// and a candidate dominates the pixel.  Then the
+// 8-connected components of equal (D, B) inside the block's 16x16 tile, with
+// an LDS union-find whose roots are the smallest tile-local index, which is
+// also the smallest image index of the tile's part of the component.  Writes
+// label = image index of that root (-1 inactive).
+__global__ void __launch_bounds__(ET * ET) k_erode_ccl_local(int W, int H, int tiles_x, int r, int lo, int hi,
+                                                             const uint8_t *__restrict__ M,
+                                                             const int32_t *__restrict__ dom,
+                                                             const uint8_t *__restrict__ B,
+                                                             const uint8_t *__restrict__ is_cand,
+                                                             int32_t *__restrict__ label) {
+    __shared__ uint8_t s_m[ES * ES];
+    __shared__ uint8_t s_row[ES * ET];
+    __shared__ int32_t s_par[ET * ET];
+    __shared__ int32_t s_dom[ET * ET];
+    __shared__ uint8_t s_b[ET * ET];
+    const int tid = threadIdx.x;
+    const int tx = (int)blockIdx.x % tiles_x, ty = (int)blockIdx.x / tiles_x;
+    const int ox = tx * ET, oy = ty * ET;
+    const int lx = tid % ET, ly = tid / ET, x = ox + lx, y = oy + ly;
+    const bool inside = x < W && y < H;
+    const int64_t u = (int64_t)y * W + x;
+    bool e;
+    if (r <= EMAX_R) {   // lo, hi <= r
+        const int S = ET + lo + hi;
+        for (int i = tid; i < S * S; i += ET * ET) {
+            const int hx = i % S, hy = i / S, gx = ox + hx - lo, gy = oy + hy - lo;
+            s_m[i] = (gx < 0 || gy < 0 || gx >= W || gy >= H) ? 1 : M[(int64_t)gy * W + gx];
+        }
+        __syncthreads();
+        for (int i = tid; i < S * ET; i += ET * ET) {   // AND along rows
+            const int cx = i % ET, hy = i / ET;
+            uint8_t a = 1;
+            for (int k = 0; k <= lo + hi; k++) a &= s_m[hy * S + cx + k];
+            s_row[i] = a;
+        }
+        __syncthreads();
+        uint8_t a = 1;                                  // then along columns
+        for (int k = 0; k <= lo + hi; k++) a &= s_row[(ly + k) * ET + lx];
+        e = a != 0;
+    } else {
+        e = inside && M[u] != 0;
+        for (int dy = -lo; dy <= hi && e; dy++) {
+            const int yy = y + dy;
+            if (yy < 0 || yy >= H) continue;
+            for (int dx = -lo; dx <= hi; dx++) {
+                const int xx = x + dx;
+                if (xx < 0 || xx >= W) continue;
+                if (!M[(int64_t)yy * W + xx]) {
+                    e = false;
+                    break;
+                }
+            }
+        }
+    }
+    const int32_t d = inside ? dom[u] : -1;
+    const bool active = inside && e && d >= 0 && is_cand[d];
+    const uint8_t b = inside ? B[u] : 0;
+    s_par[tid] = active ? tid : -1;
+    s_dom[tid] = d;
+    s_b[tid] = b;
+    __syncthreads();
+    if (active) {
+        const int nx[4] = {-1, -1, 0, 1};
+        const int ny[4] = {0, -1, -1, -1};
+        for (int k = 0; k < 4; k++) {
+            const int qx = lx + nx[k], qy = ly + ny[k];
+            if (qx < 0 || qy < 0 || qx >= ET) continue;
+            const int q = qy * ET + qx;
+            if (s_par[q] < 0 || s_dom[q] != d || s_b[q] != b) continue;   // activity never changes here
+            lds_unite(s_par, tid, q);
+        }
+    }
+    __syncthreads();
+    if (inside) {
+        int32_t lab = -1;
+        if (active) {
+            const int rt = lds_find(s_par, tid);
+            lab = (int32_t)((int64_t)(oy + rt / ET) * W + ox + rt % ET);
+        }
+        label[u] = lab;
+    }
+}
+
+// Join the tile-local components across tile borders: only pixels whose W,
+// NW, N or NE neighbour lies in another tile link, with the global
+// union-find (roots are the smallest image index).
+__global__ void k_ccl_border(int W, int H, const int32_t *__restrict__ dom, const uint8_t *__restrict__ B,
+                             int32_t *label) {
     const int64_t P = (int64_t)W * H;
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= P) return;
-    if (label[u] < 0) return;
     const int x = (int)(u % W), y = (int)(u / W);
+    const int lx = x % ET, ly = y % ET;
+    if (lx != 0 && ly != 0 && lx != ET - 1) return;
+    if (uf_load(label, (int32_t)u) < 0) return;
     const int32_t d = dom[u];
     const uint8_t b = B[u];
     const int nx[4] = {-1, -1, 0, 1};
@@ -142,6 +238,7 @@ __global__ void k_ccl_union(int W, int H, const int32_t *__restrict__ dom, const
     for (int k = 0; k < 4; k++) {
         const int xx = x + nx[k], yy = y + ny[k];
         if (xx < 0 || yy < 0 || xx >= W) continue;
+        if (xx / ET == x / ET && yy / ET == y / ET) continue;   // joined by the local pass
         const int64_t q = (int64_t)yy * W + xx;
         if (uf_load(label, (int32_t)q) < 0) continue;
         if (dom[q] != d || B[q] != b) continue;
@@ -149,29 +246,20 @@ __global__ void k_ccl_union(int W, int H, const int32_t *__restrict__ dom, const
     }
 }
 
-__global__ void k_ccl_flatten(int64_t P, int32_t *label, uint8_t *__restrict__ root_flag) {
+// Every active pixel's label becomes its root; each root clears its moments.
+__global__ void k_ccl_flatten(int64_t P, int32_t *label, unsigned long long *__restrict__ mom) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= P) return;
-    const int32_t l = label[u];
-    if (l < 0) {
-        root_flag[u] = 0;
-        return;
-    }
+    if (label[u] < 0) return;
     const int32_t r = uf_find(label, (int32_t)u);
-    root_flag[u] = (r == (int32_t)u);
     label[u] = r;
+    if (r == (int32_t)u)
+        for (int k = 0; k < 6; k++) mom[u * 6 + k] = 0ull;
 }
 
-__global__ void k_slot_roots(int64_t P, const uint8_t *__restrict__ root_flag, const int64_t *__restrict__ slot,
-                             int32_t *__restrict__ slot_root) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= P) return;
-    if (root_flag[u]) slot_root[slot[u]] = (int32_t)u;
-}
-
-// Exact integer moments A, Sx, Sy, Sxx, Sxy, Syy per component.
-__global__ void k_moments(int W, int H, const int32_t *__restrict__ label, const int64_t *__restrict__ slot,
-                          unsigned long long *__restrict__ mom) {
+// Exact integer moments A, Sx, Sy, Sxx, Sxy, Syy per component, stored at the
+// component's root pixel.
+__global__ void k_moments(int W, int H, const int32_t *__restrict__ label, unsigned long long *__restrict__ mom) {
     const int64_t P = (int64_t)W * H;
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t s = -1;
@@ -179,7 +267,7 @@ __global__ void k_moments(int W, int H, const int32_t *__restrict__ label, const
     if (u < P) {
         const int32_t l = label[u];
         if (l >= 0) {
-            s = slot[l];
+            s = l;
             const int64_t x = u % W, y = u / W;
             v[0] = 1; v[1] = x; v[2] = y; v[3] = x * x; v[4] = x * y; v[5] = y * y;
         }
@@ -203,11 +291,12 @@ __global__ void k_moments(int W, int H, const int32_t *__restrict__ label, const
     }
 }
 
-__global__ void k_region_keep(const int64_t *__restrict__ n_slots, int64_t cap_slots,
-                              const unsigned long long *__restrict__ mom, int m_min, uint8_t *__restrict__ keep) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= cap_slots) return;
-    keep[s] = (s < *n_slots) && ((int64_t)mom[s * 6] >= (int64_t)m_min);
+// A component is kept (Eq. (min_region_area)) at its root pixel.
+__global__ void k_region_keep(int64_t P, const int32_t *__restrict__ label, const unsigned long long *__restrict__ mom,
+                              int m_min, uint8_t *__restrict__ keep) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= P) return;
+    keep[u] = label[u] == (int32_t)u && (int64_t)mom[u * 6] >= (int64_t)m_min;
 }
 
 __device__ __forceinline__ double central_moment(int64_t A, int64_t sab, int64_t sa, int64_t sb) {
@@ -219,19 +308,20 @@ __device__ __forceinline__ double central_moment(int64_t A, int64_t sab, int64_t
     return dnum / (dA * dA);
 }
 
-__global__ void k_region_emit(int W, int H, int view, const int64_t *__restrict__ n_slots, int64_t cap_slots,
-                              const unsigned long long *__restrict__ mom, const uint8_t *__restrict__ keep,
-                              const int64_t *__restrict__ kidx, const int32_t *__restrict__ slot_root,
+// One record per kept component, in ascending label order (kidx is the
+// exclusive scan of keep over the pixels).
+__global__ void k_region_emit(int W, int H, int view, const unsigned long long *__restrict__ mom,
+                              const uint8_t *__restrict__ keep, const int64_t *__restrict__ kidx,
                               const int32_t *__restrict__ dom, const uint8_t *__restrict__ B,
                               const float *__restrict__ gt, as_region *__restrict__ out, int64_t out_cap,
                               const int64_t *__restrict__ count) {
+    const int64_t P = (int64_t)W * H;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= cap_slots || s >= *n_slots || !keep[s]) return;
+    if (s >= P || !keep[s]) return;
     const int64_t pos = *count + kidx[s];
     if (pos >= out_cap) return;
-    const int64_t P = (int64_t)W * H;
     as_region r;
-    const int32_t root = slot_root[s];
+    const int32_t root = (int32_t)s;
     r.cand = dom[root];
     r.view = view;
     r.label = root;
@@ -304,8 +394,7 @@ as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const ui
     hipError_t e = hipSuccess;
     DevBuf *es = ctx->es;
     if ((e = devbuf_ensure(es[ES_M], P)) != hipSuccess || (e = devbuf_ensure(es[ES_B], P)) != hipSuccess ||
-        (e = devbuf_ensure(es[ES_LABEL], P * 4)) != hipSuccess || (e = devbuf_ensure(es[ES_FLAG], P)) != hipSuccess ||
-        (e = devbuf_ensure(es[ES_SLOT], P * 8)) != hipSuccess || (e = devbuf_ensure(es[ES_ROOT], P * 4)) != hipSuccess ||
+        (e = devbuf_ensure(es[ES_LABEL], P * 4)) != hipSuccess ||
         (e = devbuf_ensure(es[ES_MOM], P * 48)) != hipSuccess || (e = devbuf_ensure(es[ES_KEEP], P)) != hipSuccess ||
         (e = devbuf_ensure(es[ES_KIDX], P * 8)) != hipSuccess ||
         (e = devbuf_ensure(es[ES_SCAN], scan_tmp_bytes(P))) != hipSuccess ||
@@ -313,25 +402,27 @@ as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const ui
         as_set_error("error-stats scratch allocation failed: %s", hipGetErrorString(e));
         return AS_ERR_HIP;
     }
-    uint8_t *M = (uint8_t *)es[ES_M].p, *B = (uint8_t *)es[ES_B].p, *flag = (uint8_t *)es[ES_FLAG].p;
+    uint8_t *M = (uint8_t *)es[ES_M].p, *B = (uint8_t *)es[ES_B].p;
     uint8_t *keep = (uint8_t *)es[ES_KEEP].p;
-    int32_t *label = (int32_t *)es[ES_LABEL].p, *root = (int32_t *)es[ES_ROOT].p;
-    int64_t *slot = (int64_t *)es[ES_SLOT].p, *kidx = (int64_t *)es[ES_KIDX].p, *tot = (int64_t *)es[ES_TOT].p;
+    int32_t *label = (int32_t *)es[ES_LABEL].p;
+    int64_t *kidx = (int64_t *)es[ES_KIDX].p, *tot = (int64_t *)es[ES_TOT].p;
     unsigned long long *mom = (unsigned long long *)es[ES_MOM].p;
     const unsigned grid = (unsigned)((P + 255) / 256);
+    const int tiles_x = (W + ET - 1) / ET, tiles = tiles_x * ((H + ET - 1) / ET);
     hipLaunchKernelGGL(k_classify, dim3(grid), dim3(256), 0, s, P, err,
                        reinterpret_cast<const unsigned long long *>(minmax), dom, is_cand, p.tau_l1, p.L, M, B, attr);
-    hipLaunchKernelGGL(k_erode_init, dim3(grid), dim3(256), 0, s, W, H, p.r_erode, M, dom, is_cand, label);
-    hipLaunchKernelGGL(k_ccl_union, dim3(grid), dim3(256), 0, s, W, H, dom, B, label);
-    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid), dim3(256), 0, s, P, label, flag);
-    scan_u8_to_i64(flag, slot, P, tot, es[ES_SCAN].p, s);
-    hipLaunchKernelGGL(k_slot_roots, dim3(grid), dim3(256), 0, s, P, flag, slot, root);
-    launch_fill_u64(reinterpret_cast<uint64_t *>(mom), 0ull, P * 6, s);
-    hipLaunchKernelGGL(k_moments, dim3(grid), dim3(256), 0, s, W, H, label, slot, mom);
-    hipLaunchKernelGGL(k_region_keep, dim3(grid), dim3(256), 0, s, tot, P, mom, p.m_min, keep);
-    scan_u8_to_i64(keep, kidx, P, tot + 1, es[ES_SCAN].p, s);
-    hipLaunchKernelGGL(k_region_emit, dim3(grid), dim3(256), 0, s, W, H, view, tot, P, mom, keep, kidx, root, dom, B,
-                       gt, rb.records, rb.capacity, rb.count);
-    hipLaunchKernelGGL(k_count_add, dim3(1), dim3(1), 0, s, rb.count, tot + 1);
+    // element offsets: [-r, r] per axis, or a side of r + 1 (flag)
+    const int lo = (p.flags & AS_SPLIT_ERODE_SIDE) ? p.r_erode / 2 : p.r_erode;
+    const int hi = (p.flags & AS_SPLIT_ERODE_SIDE) ? p.r_erode - p.r_erode / 2 : p.r_erode;
+    hipLaunchKernelGGL(k_erode_ccl_local, dim3(tiles), dim3(ET * ET), 0, s, W, H, tiles_x, p.r_erode, lo, hi, M, dom,
+                       B, is_cand, label);
+    hipLaunchKernelGGL(k_ccl_border, dim3(grid), dim3(256), 0, s, W, H, dom, B, label);
+    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid), dim3(256), 0, s, P, label, mom);
+    hipLaunchKernelGGL(k_moments, dim3(grid), dim3(256), 0, s, W, H, label, mom);
+    hipLaunchKernelGGL(k_region_keep, dim3(grid), dim3(256), 0, s, P, label, mom, p.m_min, keep);
+    scan_u8_to_i64(keep, kidx, P, tot, es[ES_SCAN].p, s);
+    hipLaunchKernelGGL(k_region_emit, dim3(grid), dim3(256), 0, s, W, H, view, mom, keep, kidx, dom, B, gt,
+                       rb.records, rb.capacity, rb.count);
+    hipLaunchKernelGGL(k_count_add, dim3(1), dim3(1), 0, s, rb.count, tot);
     return AS_OK;
 }

@@ -223,6 +223,13 @@ as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const ui
                           as_region_buf &rb, int32_t *attr, hipStream_t s);
 
 // adaptive split (split.hip)
+// Random children per candidate the variant may draw noise for.
+static inline int split_noise_need(const as_split_params &p) {
+    int need = 2;
+    if (p.variant == AS_VARIANT_FIXED_N && p.fixed_n > need) need = p.fixed_n;
+    if (p.variant == AS_VARIANT_ADAPTIVE_N && p.n_max > need) need = p.n_max;
+    return need;
+}
 as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *cand, int64_t n_cand,
                              const as_region_buf &rb, const as_camera *views, int n_views, const int32_t *attr,
                              const as_split_params &p, const float *noise, GradPtrs out, int64_t out_cap,

@@ -1,24 +1,29 @@
-// Reverse pass of the projection (Sec. 3): from the per-Gaussian 2D gradients
+// Reverse pass of the projection (Sec. 3): from the per-entry 2D gradients
 // (mean, conic, opacity, colour) accumulated by the blend back to the stored
 // parameters (means, log-scales, quaternions, opacity logits, SH).  One thread
-// per Gaussian, FP64, struct-of-arrays reads and writes.  A Gaussian set seen
-// in several views of a batch gets one launch per view; every launch after
-// the first adds its view's gradient to the output (a fixed order, so the sum
-// is deterministic).
+// per Gaussian, FP64, struct-of-arrays reads and writes.  A batch of views is
+// one launch: each thread walks the views in order and sums their
+// contributions (a fixed order, so the sum is deterministic), then writes
+// every gradient once; a single view uses a leaner kernel with the same
+// arithmetic.
 //
 // Chain: colour = max(0, sum_k Y_k(d) sh_k + 1/2) with d = (mu - o_v)/|mu - o_v|;
 // mean2d = (fx tx/tz + cx, fy ty/tz + cy); conic = inverse(J W Sigma W^T J^T
 // + 0.3 I) with J the perspective Jacobian at the clamped centre; Sigma =
-// R(q/|q|) diag(exp(2 log s)) R^T; o = sigmoid(logit).
+// R(q/|q|) diag(exp(2 log s)) R^T; o = sigmoid(logit).  The scale and
+// rotation gradients are linear in dL/dSigma, so dL/dSigma is summed over the
+// views first and mapped to (log s, q) once.
 #include "internal.h"
 #include "sh_device.h"
 
 namespace {
 
+// One view, or one view of several added to the output (accum): the form
+// that keeps the fewest values live, used when a render has one view.
 __device__ __forceinline__ void put(float *p, float v, bool acc) { *p = acc ? *p + v : v; }
 
 template <int DEG>
-__global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, const uint32_t *__restrict__ ntiles,
+__global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam cam, const uint32_t *__restrict__ ntiles,
                                                      const float *__restrict__ g2d, int64_t gs, GradPtrs out,
                                                      float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count,
                                                      int accum) {
@@ -194,22 +199,228 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, DevCam cam, co
     for (int k = 0; k < 4; k++) put(&out.quats[k * os + i], (float)((dq[k] - qn[k] * qd) / qnorm), accum != 0);
 }
 
+
+// All views of a batch in one pass per Gaussian.
+template <int DEG>
+__global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTable vt, const uint32_t *__restrict__ ntiles,
+                                                     const float *__restrict__ g2d, int64_t gs, GradPtrs out,
+                                                     float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count) {
+    constexpr int nk = (DEG + 1) * (DEG + 1);
+    // SH gradient accumulators live in LDS (thread-private columns), not registers
+    __shared__ float s_dsh[nk * 3][256];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+    if (i >= g.n) return;
+    const int64_t n = g.n, os = out.stride;
+#pragma unroll
+    for (int k = 0; k < nk * 3; k++) s_dsh[k][tid] = 0.f;
+
+    double mu[3], s[3], q[4];
+    for (int k = 0; k < 3; k++) mu[k] = (double)g.means[k * n + i];
+    for (int k = 0; k < 3; k++) s[k] = exp((double)g.log_scales[k * n + i]);
+    for (int k = 0; k < 4; k++) q[k] = (double)g.quats[k * n + i];
+    const double o = 1.0 / (1.0 + exp(-(double)g.opac[i]));
+    const double qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double w = q[0] / qnorm, x = q[1] / qnorm, y = q[2] / qnorm, z = q[3] / qnorm;
+    const double Rg[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                          2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                          2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+
+    double dmu[3] = {0.0, 0.0, 0.0};
+    double dS[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double gop = 0.0;
+    float nrm = 0.f;
+    int32_t vis = 0;
+
+    for (int v = 0; v < vt.n_views; v++) {
+        // keeps the SH coefficients' loads inside the loop (from cache) instead
+        // of 48 doubles held in registers across it
+        __asm__ __volatile__("" ::: "memory");
+        const int64_t e = (int64_t)vt.ent_base[v] + i;
+        if (ntiles[e] == 0) continue;
+        const DevCam &cam = vt.cam[v];
+        const double gm0 = g2d[0 * gs + e], gm1 = g2d[1 * gs + e];
+        const double gca = g2d[2 * gs + e], gcb = g2d[3 * gs + e], gcc = g2d[4 * gs + e];
+        const double grgb[3] = {g2d[6 * gs + e], g2d[7 * gs + e], g2d[8 * gs + e]};
+        gop += g2d[5 * gs + e];
+        nrm += (float)sqrt(gm0 * gm0 + gm1 * gm1);
+        vis += 1;
+
+        double Rc[9], tc[3];
+        for (int k = 0; k < 9; k++) Rc[k] = (double)cam.R[k];
+        for (int k = 0; k < 3; k++) tc[k] = (double)cam.t[k];
+        const double fx = cam.fx, fy = cam.fy;
+        double tv[3];
+        for (int r = 0; r < 3; r++) tv[r] = Rc[r * 3 + 0] * mu[0] + Rc[r * 3 + 1] * mu[1] + Rc[r * 3 + 2] * mu[2] + tc[r];
+        const double tx = tv[0], ty = tv[1], tz = tv[2];
+
+        // colour and view direction
+        double oc[3];
+        for (int j = 0; j < 3; j++) oc[j] = -(Rc[0 * 3 + j] * tc[0] + Rc[1 * 3 + j] * tc[1] + Rc[2 * 3 + j] * tc[2]);
+        const double vv[3] = {mu[0] - oc[0], mu[1] - oc[1], mu[2] - oc[2]};
+        const double vn = sqrt(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+        const double d[3] = {vv[0] / vn, vv[1] / vn, vv[2] / vn};
+        double Y[16], dY[16][3];
+        sh_eval_basis(d[0], d[1], d[2], DEG, Y);
+        sh_eval_basis_grad(d[0], d[1], d[2], DEG, dY);
+        double gd[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            double raw = 0.0;
+#pragma unroll
+            for (int k = 0; k < nk; k++) raw += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
+            const bool clamped = raw + 0.5 < 0.0;
+            const double gc = clamped ? 0.0 : grgb[ch];
+#pragma unroll
+            for (int k = 0; k < nk; k++) {
+                s_dsh[k * 3 + ch][tid] += (float)(Y[k] * gc);
+                const double shv = (double)g.sh[((int64_t)k * 3 + ch) * n + i];
+                for (int a = 0; a < 3; a++) gd[a] += dY[k][a] * shv * gc;
+            }
+        }
+        const double ddot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+        for (int a = 0; a < 3; a++) dmu[a] += (gd[a] - d[a] * ddot) / vn;
+
+        // mean2d
+        double dt[3] = {0.0, 0.0, 0.0};
+        dt[0] += gm0 * fx / tz;
+        dt[1] += gm1 * fy / tz;
+        dt[2] += -gm0 * fx * tx / (tz * tz) - gm1 * fy * ty / (tz * tz);
+
+        // conic = inverse(cov): dL/dcov = -K G K
+        const double limx = 1.3 * ((double)cam.W / (2.0 * fx));
+        const double limy = 1.3 * ((double)cam.H / (2.0 * fy));
+        const double txtz = tx / tz, tytz = ty / tz;
+        const bool clx = txtz < -limx || txtz > limx, cly = tytz < -limy || tytz > limy;
+        const double cx_ = fmin(limx, fmax(-limx, txtz)) * tz;
+        const double cy_ = fmin(limy, fmax(-limy, tytz)) * tz;
+        const double J[6] = {fx / tz, 0.0, -(fx * cx_) / (tz * tz), 0.0, fy / tz, -(fy * cy_) / (tz * tz)};
+        double T[6];
+        for (int r = 0; r < 2; r++)
+            for (int k = 0; k < 3; k++)
+                T[r * 3 + k] = J[r * 3 + 0] * Rc[k] + J[r * 3 + 1] * Rc[3 + k] + J[r * 3 + 2] * Rc[6 + k];
+        double Sg[9];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; k++) acc += Rg[a * 3 + k] * (s[k] * s[k]) * Rg[b * 3 + k];
+                Sg[a * 3 + b] = acc;
+            }
+        double C2[4];
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; k++)
+                    for (int l = 0; l < 3; l++) acc += T[a * 3 + k] * Sg[k * 3 + l] * T[b * 3 + l];
+                C2[a * 2 + b] = acc;
+            }
+        const double A = C2[0] + AS_LOWPASS, B = C2[1], Cc = C2[3] + AS_LOWPASS;
+        const double det = A * Cc - B * B;
+        const double K[4] = {Cc / det, -B / det, -B / det, A / det};
+        const double Gk[4] = {gca, 0.5 * gcb, 0.5 * gcb, gcc};
+        double KG[4], Gc[4];
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) KG[a * 2 + b] = K[a * 2] * Gk[b] + K[a * 2 + 1] * Gk[2 + b];
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) Gc[a * 2 + b] = -(KG[a * 2] * K[b] + KG[a * 2 + 1] * K[2 + b]);
+        double dT[6];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double acc = 0.0;
+                for (int r = 0; r < 2; r++)
+                    for (int qq = 0; qq < 2; qq++) acc += T[r * 3 + a] * Gc[r * 2 + qq] * T[qq * 3 + b];
+                dS[a * 3 + b] += acc;
+            }
+        for (int r = 0; r < 2; r++)
+            for (int k = 0; k < 3; k++) {
+                double acc = 0.0;
+                for (int qq = 0; qq < 2; qq++)
+                    for (int l = 0; l < 3; l++) acc += Gc[r * 2 + qq] * T[qq * 3 + l] * Sg[l * 3 + k];
+                dT[r * 3 + k] = 2.0 * acc;
+            }
+        double dJ[6];
+        for (int r = 0; r < 2; r++)
+            for (int k = 0; k < 3; k++)
+                dJ[r * 3 + k] =
+                    dT[r * 3 + 0] * Rc[k * 3 + 0] + dT[r * 3 + 1] * Rc[k * 3 + 1] + dT[r * 3 + 2] * Rc[k * 3 + 2];
+        dt[2] += dJ[0] * (-fx / (tz * tz)) + dJ[4] * (-fy / (tz * tz));
+        if (!clx) {
+            dt[0] += dJ[2] * (-fx / (tz * tz));
+            dt[2] += dJ[2] * (2.0 * fx * tx / (tz * tz * tz));
+        } else {
+            dt[2] += dJ[2] * (fx * (cx_ / tz) / (tz * tz));
+        }
+        if (!cly) {
+            dt[1] += dJ[5] * (-fy / (tz * tz));
+            dt[2] += dJ[5] * (2.0 * fy * ty / (tz * tz * tz));
+        } else {
+            dt[2] += dJ[5] * (fy * (cy_ / tz) / (tz * tz));
+        }
+        for (int a = 0; a < 3; a++) dmu[a] += Rc[0 * 3 + a] * dt[0] + Rc[1 * 3 + a] * dt[1] + Rc[2 * 3 + a] * dt[2];
+    }
+
+    if (vis && g2d_norm) g2d_norm[i] += nrm;
+    if (vis && vis_count) vis_count[i] += vis;
+    if (!vis) {   // no view saw it: zero gradients
+        for (int k = 0; k < 3; k++) { out.means[k * os + i] = 0.f; out.log_scales[k * os + i] = 0.f; }
+        for (int k = 0; k < 4; k++) out.quats[k * os + i] = 0.f;
+        out.opac[i] = 0.f;
+#pragma unroll
+        for (int k = 0; k < nk * 3; k++) out.sh[(int64_t)k * os + i] = 0.f;
+        return;
+    }
+    out.opac[i] = (float)(gop * o * (1.0 - o));
+#pragma unroll
+    for (int k = 0; k < nk * 3; k++) out.sh[(int64_t)k * os + i] = s_dsh[k][tid];
+    for (int a = 0; a < 3; a++) out.means[a * os + i] = (float)dmu[a];
+    // scales
+    for (int k = 0; k < 3; k++) {
+        double acc = 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) acc += Rg[a * 3 + k] * dS[a * 3 + b] * Rg[b * 3 + k];
+        out.log_scales[k * os + i] = (float)(2.0 * s[k] * s[k] * acc);
+    }
+    // rotation -> quaternion
+    double dR[9];
+    for (int a = 0; a < 3; a++)
+        for (int k = 0; k < 3; k++) {
+            double acc = 0.0;
+            for (int b = 0; b < 3; b++) acc += dS[a * 3 + b] * Rg[b * 3 + k];
+            dR[a * 3 + k] = 2.0 * acc * s[k] * s[k];
+        }
+    double dq[4];
+    dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                   2.0 * x * dR[8]);
+    dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                   2.0 * y * dR[8]);
+    dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
+                   y * dR[7]);
+    const double qn[4] = {w, x, y, z};
+    const double qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+    for (int k = 0; k < 4; k++) out.quats[k * os + i] = (float)((dq[k] - qn[k] * qd) / qnorm);
+}
+
 }  // namespace
 
 void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t *ntiles, const float *grad2d,
                         int64_t g2d_stride, GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
-    for (int v = 0; v < vt.n_views; v++) {
-        const DevCam &cam = vt.cam[v];
-        const uint32_t *nt = ntiles + vt.ent_base[v];
-        const float *g2 = grad2d + vt.ent_base[v];
-        const int accum = v > 0;
+    if (vt.n_views == 1) {
+        const DevCam &cam = vt.cam[0];
         switch (g.deg) {
-        case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(256), 0, s, g, cam, nt, g2, g2d_stride, out, g2d_norm, vis_count, accum); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(256), 0, s, g, cam, nt, g2, g2d_stride, out, g2d_norm, vis_count, accum); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(256), 0, s, g, cam, nt, g2, g2d_stride, out, g2d_norm, vis_count, accum); break;
-        default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, g, cam, nt, g2, g2d_stride, out, g2d_norm, vis_count, accum); break;
+        case 0: hipLaunchKernelGGL(k_project_bwd_view<0>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count, 0); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd_view<1>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count, 0); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd_view<2>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count, 0); break;
+        default: hipLaunchKernelGGL(k_project_bwd_view<3>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count, 0); break;
         }
+        return;
+    }
+    switch (g.deg) {
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
     }
 }

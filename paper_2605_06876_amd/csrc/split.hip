@@ -9,7 +9,9 @@
 //   3. one wave per candidate: transitive merge graph under
 //      Eq. (merge_conditions) (lock-free union-find, roots = first member),
 //      merged parameters of Eq. (merge_cov), ranking by covariance extent and
-//      the N_max cap, then the mode (vanilla / reset / adaptive) and count;
+//      the N_max cap, then the mode (vanilla / reset / adaptive / random) and
+//      count (the ablation variants of Table 2 skip the merge, or the region
+//      children altogether);
 //   4. scans of the counts and of the removal mask, survivor copy and child
 //      write-out.
 // All decision arithmetic is FP64 with a fixed expression order; this file is
@@ -25,7 +27,7 @@ constexpr double C0_SH = 0.28209479177387814;   // degree-0 real SH constant 1/(
 
 struct Prop {
     double mu[3], R[9], s[3], rgb[3], Sig[9], Sinv[9];
-    int32_t ok, pad;
+    int32_t ok, view;
 };
 
 struct Group {
@@ -263,7 +265,7 @@ __global__ void k_propose(GaussPtrs g, const as_region *__restrict__ recs, const
     const as_region r = recs[order[i]];
     Prop p;
     p.ok = 0;
-    p.pad = 0;
+    p.view = r.view;
     if (find_cand(cand, n_cand, r.cand) >= 0 && r.view >= 0 && r.view < n_views && r.cand < g.n) {
         Parent par;
         load_parent(g, r.cand, par);
@@ -306,10 +308,19 @@ __global__ void __launch_bounds__(256) k_merge(GaussPtrs g, const int32_t *__res
                                                int32_t *__restrict__ uf_all, int32_t *__restrict__ root_all,
                                                Group *__restrict__ grp_all, int32_t *__restrict__ kept_all,
                                                int32_t *__restrict__ nkept, double gamma_d, double gamma_c,
-                                               int n_max, uint8_t *__restrict__ mode, int32_t *__restrict__ count) {
+                                               int n_max, int variant, uint32_t flags, int fixed_n,
+                                               uint8_t *__restrict__ mode, int32_t *__restrict__ count) {
     const int lane = threadIdx.x & 63;
     const int64_t ci = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ci >= n_cand) return;
+    if (variant == AS_VARIANT_FIXED_N) {   // the random split with a fixed N, whatever the regions say
+        if (lane == 0) {
+            mode[ci] = 3;
+            count[ci] = fixed_n;
+            nkept[ci] = 0;
+        }
+        return;
+    }
     const int64_t rs = rs_a[ci], re = re_a[ci];
     const int32_t np = (int32_t)(re - rs);
     const Prop *pp = props + rs;
@@ -321,11 +332,14 @@ __global__ void __launch_bounds__(256) k_merge(GaussPtrs g, const int32_t *__res
     for (int32_t j = lane; j < np; j += 64) uf[j] = pp[j].ok ? j : -1;
     __threadfence();
     __builtin_amdgcn_wave_barrier();
-    // Eq. (merge_conditions) over every pair of this parent's proposals
-    for (int32_t a = 0; a < np; a++) {
+    // Eq. (merge_conditions) over every pair of this parent's proposals (the
+    // ablation variants do not merge)
+    const bool merge = variant == AS_VARIANT_ADPSPLIT;
+    for (int32_t a = 0; merge && a < np; a++) {
         if (!pp[a].ok) continue;
         for (int32_t b = a + 1 + lane; b < np; b += 64) {
             if (!pp[b].ok) continue;
+            if ((flags & AS_SPLIT_CROSS_VIEW) && pp[b].view == pp[a].view) continue;
             const double dl[3] = {pp[b].mu[0] - pp[a].mu[0], pp[b].mu[1] - pp[a].mu[1], pp[b].mu[2] - pp[a].mu[2]};
             const double dm = maha(pp[a].Sinv, dl) + maha(pp[b].Sinv, dl);
             double dc = 0.0;
@@ -386,7 +400,14 @@ __global__ void __launch_bounds__(256) k_merge(GaussPtrs g, const int32_t *__res
             }
             for (int k = 0; k < 9; k++) gr.R[k] = E[k];
         }
-        gr.extent = gr.s[0] * gr.s[1] * gr.s[2];
+        if (flags & AS_SPLIT_EXTENT_MAX) {
+            double m = gr.s[0];
+            if (gr.s[1] > m) m = gr.s[1];
+            if (gr.s[2] > m) m = gr.s[2];
+            gr.extent = m;
+        } else {
+            gr.extent = gr.s[0] * gr.s[1] * gr.s[2];
+        }
         grp[j] = gr;
     }
     __threadfence();
@@ -410,6 +431,7 @@ __global__ void __launch_bounds__(256) k_merge(GaussPtrs g, const int32_t *__res
         int32_t cnt;
         if (attr[id] == 0) { md = 0; cnt = 2; }
         else if (nk == 0) { md = 1; cnt = 0; }
+        else if (variant == AS_VARIANT_ADAPTIVE_N) { md = 3; cnt = nk; }   // as many random children as proposals
         else { md = 2; cnt = nk + 1; }
         mode[ci] = md;
         count[ci] = cnt;
@@ -452,7 +474,8 @@ __global__ void k_write_children(GaussPtrs g, const int32_t *__restrict__ cand, 
                                  const uint8_t *__restrict__ mode, const int64_t *__restrict__ offset,
                                  const int64_t *__restrict__ tot, const int64_t *__restrict__ rs_a,
                                  const Group *__restrict__ grp_all, const int32_t *__restrict__ kept_all,
-                                 const int32_t *__restrict__ nkept, const float *__restrict__ noise, double eta,
+                                 const int32_t *__restrict__ nkept, const int32_t *__restrict__ count,
+                                 const float *__restrict__ noise, int noise_n, double eta, uint32_t flags,
                                  GradPtrs out, int64_t *__restrict__ n_out) {
     const int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n_surv = g.n - tot[0];
@@ -463,18 +486,21 @@ __global__ void k_write_children(GaussPtrs g, const int32_t *__restrict__ cand, 
     const uint8_t md = mode[ci];
     const int64_t os = out.stride;
     const int nk = (g.deg + 1) * (g.deg + 1);
-    if (md == 0) {
+    if (md == 0 || md == 3) {
+        // Eq. (vanilla_split_sample), Eq. (vanilla_split_scale) with N = count
+        // (2 for the VANILLA fallback)
+        const int32_t N = count[ci];
         Parent par;
         load_parent(g, id, par);
-        for (int c2 = 0; c2 < 2; c2++) {
+        for (int c2 = 0; c2 < N; c2++) {
             const int64_t dst = base + c2;
             copy_row(g, id, out, dst);
             double dl[3];
-            for (int k = 0; k < 3; k++) dl[k] = par.s[k] * (double)noise[(ci * 2 + c2) * 3 + k];
+            for (int k = 0; k < 3; k++) dl[k] = par.s[k] * (double)noise[((int64_t)ci * noise_n + c2) * 3 + k];
             for (int k = 0; k < 3; k++) {
                 const double m = par.mu[k] + (par.R[k * 3 + 0] * dl[0] + par.R[k * 3 + 1] * dl[1] + par.R[k * 3 + 2] * dl[2]);
                 out.means[k * os + dst] = (float)m;
-                out.log_scales[k * os + dst] = (float)((double)g.log_scales[k * g.n + id] - log(eta * 2.0));
+                out.log_scales[k * os + dst] = (float)((double)g.log_scales[k * g.n + id] - log(eta * (double)N));
             }
         }
     } else if (md == 2) {
@@ -488,7 +514,7 @@ __global__ void k_write_children(GaussPtrs g, const int32_t *__restrict__ cand, 
             for (int k = 0; k < 3; k++) out.means[k * os + dst] = (float)gr.mu[k];
             for (int k = 0; k < 3; k++) out.log_scales[k * os + dst] = (float)log(gr.s[k]);
             for (int k = 0; k < 4; k++) out.quats[k * os + dst] = (float)q[k];
-            out.opac[dst] = g.opac[id];
+            out.opac[dst] = g.opac[id];   // Eq. (child_params): the parent's opacity
             for (int ch = 0; ch < 3; ch++) out.sh[(int64_t)ch * os + dst] = (float)((gr.rgb[ch] - 0.5) / C0_SH);
             for (int k = 3; k < nk * 3; k++) out.sh[(int64_t)k * os + dst] = 0.0f;
         }
@@ -496,7 +522,10 @@ __global__ void k_write_children(GaussPtrs g, const int32_t *__restrict__ cand, 
         copy_row(g, id, out, dst);
         const double o = 1.0 / (1.0 + exp(-(double)g.opac[id]));
         const double pr = o / (double)(ng + 1);
-        out.opac[dst] = (float)log(pr / (1.0 - pr));
+        const float shared = (float)log(pr / (1.0 - pr));
+        out.opac[dst] = shared;
+        if (flags & AS_SPLIT_SHARE_OPACITY)   // second reading: every row of the block at o/(N+1)
+            for (int32_t r = 0; r < ng; r++) out.opac[base + r] = shared;
     }
 }
 
@@ -577,7 +606,8 @@ as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *can
                        n_views, p.eps, props);
     if (n_cand > 0)
         hipLaunchKernelGGL(k_merge, dim3((unsigned)((n_cand + 3) / 4)), dim3(256), 0, s, g, cand, n_cand, attr, rs,
-                           re, props, uf, rootof, grp, kept, nkept, p.gamma_d, p.gamma_c, p.n_max, mode, count);
+                           re, props, uf, rootof, grp, kept, nkept, p.gamma_d, p.gamma_c, p.n_max, p.variant, p.flags,
+                           p.fixed_n, mode, count);
     scan_i32_to_i64(count, offset, n_cand, tot + 1, sp[SP_SCAN].p, s);
     launch_fill_u8(removed, 0, g.n > 0 ? g.n : 1, s);
     if (n_cand > 0)
@@ -588,6 +618,7 @@ as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *can
         hipLaunchKernelGGL(k_copy_survivors, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g, removed,
                            remscan, out);
     hipLaunchKernelGGL(k_write_children, dim3((unsigned)((nc1 + 255) / 256)), dim3(256), 0, s, g, cand, n_cand, mode,
-                       offset, tot, rs, grp, kept, nkept, noise, p.eta, out, n_out);
+                       offset, tot, rs, grp, kept, nkept, count, noise, p.noise_n ? p.noise_n : 2, p.eta, p.flags, out,
+                       n_out);
     return AS_OK;
 }

@@ -43,7 +43,8 @@ def gpu_error_stats(ctx, img, gt, dom, is_cand, view, prm, regions, attr):
 
 
 def gparams(o):
-    return api.SplitParams(o.tau_l1, o.r_erode, o.m_min, o.L, o.n_max, o.gamma_d, o.gamma_c, o.eps, o.eta)
+    return api.SplitParams(o.tau_l1, o.r_erode, o.m_min, o.L, o.n_max, o.gamma_d, o.gamma_c, o.eps, o.eta,
+                           o.variant, o.flags, o.fixed_n, o.noise_n)
 
 
 def compare_regions(got, want):
@@ -69,6 +70,44 @@ def test_error_stats_bit_exact(ctx, H, W, n, seed, r):
     torch.cuda.synchronize()
     got = regions.host()
     say("%dx%d: %d regions, %d attributed pixels" % (W, H, len(want), attr_o.sum()))
+    compare_regions(got, want)
+    np.testing.assert_array_equal(attr_g.cpu().numpy(), attr_o)
+
+
+def stripes_fixture(H, W, seed, widen=0):
+    """Long crossing stripes of high error (regions spanning many 16x16
+    tiles and crossing tile borders repeatedly) over four dominant cells."""
+    rng = np.random.default_rng(seed)
+    gt = synth.smooth_image(H, W, seed + 1)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    err = rng.normal(0.0, 0.02, size=(3, H, W))
+    for k in range(6):
+        th = rng.uniform(0, np.pi)
+        c = rng.uniform(0.2, 0.8) * (W * abs(np.cos(th)) + H * abs(np.sin(th)))
+        dist = np.abs(xx * np.cos(th) + yy * np.sin(th) - c)
+        amp = 0.6 + 0.4 * np.sin(xx / 37.0 + yy / 23.0 + k)      # error bands change along the stripe
+        err = err + (dist < rng.uniform(4, 9) + widen)[None] * amp[None] * np.sign(rng.normal(size=(3, 1, 1)))
+    sx, sy = rng.uniform(0, W, 4), rng.uniform(0, H, 4)
+    dom = np.argmin([(xx - sx[k]) ** 2 + (yy - sy[k]) ** 2 for k in range(4)], axis=0).astype(np.int32)
+    is_cand = np.ones(4, np.uint8)
+    return (gt + err).astype(np.float32), gt, dom, is_cand
+
+
+@pytest.mark.parametrize("r", [0, 1, 8, 9, 12])
+def test_error_stats_components_across_many_tiles(ctx, r):
+    """Regions spanning many tiles; erosion radii on both sides of the LDS
+    halo limit (8) of the fused erosion + local labelling kernel."""
+    H, W = 300, 257
+    img, gt, dom, is_cand = stripes_fixture(H, W, seed=50 + r, widen=r)
+    prm = oracle.SplitParams(r_erode=r)
+    attr_o = np.zeros(4, np.int32)
+    want, maps = oracle.error_stats(img, gt, dom, is_cand, 1, prm, attr_o)
+    regions = api.RegionBuffer(H * W)
+    attr_g = torch.zeros(4, dtype=torch.int32, device="cuda")
+    gpu_error_stats(ctx, img, gt, dom, is_cand, 1, gparams(prm), regions, attr_g)
+    torch.cuda.synchronize()
+    got = regions.host()
+    say("r=%d: %d regions, largest %d pixels" % (r, len(want), int(want["area"].max()) if len(want) else 0))
     compare_regions(got, want)
     np.testing.assert_array_equal(attr_g.cpu().numpy(), attr_o)
 
@@ -121,6 +160,8 @@ def run_both_split(ctx, scene, views, maps_per_view, is_cand, prm, seed):
     regs_o = np.concatenate(regs_o) if regs_o else np.zeros(0, oracle.REGION_DTYPE)
     cand = np.nonzero(is_cand)[0].astype(np.int32)
     noise = synth.vanilla_noise(len(cand), seed)
+    if prm.noise_n > 2:
+        noise = np.random.default_rng(seed).normal(size=(len(cand), prm.noise_n, 3)).astype(np.float32)
     want = oracle.adaptive_split(scene, cand, regs_o, views, attr_o, prm, noise)
     g = api.Gaussians.from_scene(scene)
     out, mode, count, offset, n_out = api.adaptive_split(ctx, g, torch.from_numpy(cand).cuda(), regions, views, attr_g,
@@ -174,6 +215,29 @@ def test_split_on_synthetic_maps(ctx, seed, m_min):
     assert (want["mode"] == 2).sum() > 0
     if m_min > 5:
         assert (want["mode"] == 1).sum() > 0
+    compare_split(want, got)
+
+
+@pytest.mark.parametrize("variant,flags,fixed_n", [
+    (oracle.VARIANT_FIXED_N, 0, 5), (oracle.VARIANT_ADAPTIVE_N, 0, 2), (oracle.VARIANT_CHILD_INIT, 0, 2),
+    (oracle.VARIANT_ADPSPLIT, oracle.FLAG_CROSS_VIEW | oracle.FLAG_EXTENT_MAX, 2),
+    (oracle.VARIANT_ADPSPLIT, oracle.FLAG_SHARE_OPACITY | oracle.FLAG_ERODE_SIDE, 2),
+    (oracle.VARIANT_CHILD_INIT, oracle.FLAG_ERODE_SIDE | oracle.FLAG_EXTENT_MAX, 2)])
+def test_split_variants_and_readings(ctx, variant, flags, fixed_n):
+    """The Table 2 ablation steps, the fixed-N random split and the
+    alternative readings: modes, counts and offsets bit-exact, children to the
+    float bars, on synthetic maps of several views."""
+    H, W, n, V = 120, 160, 60, 4
+    seed = 21 + variant * 7 + flags
+    scene = synth.scene_uniform_sh0(n, seed=seed)
+    views = views_for(V, W, H, seed)
+    rng = np.random.default_rng(seed)
+    is_cand = (rng.uniform(size=n) < 0.5).astype(np.uint8)
+    maps = [synth.error_map_fixture(H, W, n, seed=seed * 100 + v, n_sites=60, n_blobs=80)[:3] for v in range(V)]
+    prm = oracle.SplitParams(variant=variant, flags=flags, fixed_n=fixed_n, noise_n=19, r_erode=3)
+    want, got, attr = run_both_split(ctx, scene, views, maps, is_cand, prm, seed)
+    say("variant %d flags %d: modes %s, new rows %d" % (variant, flags, np.bincount(want["mode"], minlength=4),
+                                                       want["count"].sum()))
     compare_split(want, got)
 
 

@@ -512,3 +512,117 @@ def test_end_to_end_maps_to_counts():
     np.testing.assert_array_equal(out["mode"], [2, 1, 0])
     np.testing.assert_array_equal(out["count"], [3, 0, 2])
     assert out["n_out"] == 1 + 5
+
+
+# ---- Table 2 ablation variants, the fixed-N random split, alternative readings ------------
+
+def test_fixed_n_random_split_statistics():
+    """Fixed N = 5 random children (the five-child split of Sec. 1): N rows per
+    candidate whatever the regions say, scales shrunk by eta * N, and the
+    offsets of the children from the parent centre have the parent's
+    covariance (checked statistically over many candidates)."""
+    n = 400
+    rng = np.random.default_rng(3)
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    ls = np.log([0.3, 0.1, 0.05])
+    scene = synth.Scene(np.zeros((3, n), np.float32), np.repeat(ls[:, None], n, 1).astype(np.float32),
+                        np.repeat(q[:, None], n, 1).astype(np.float32), np.full(n, 0.4, np.float32),
+                        np.zeros((1, 3, n), np.float32), 0)
+    N = 5
+    prm = oracle.SplitParams(variant=oracle.VARIANT_FIXED_N, fixed_n=N, noise_n=N)
+    noise = rng.normal(size=(n, N, 3)).astype(np.float32)
+    reg = region_record(0, 0, 1, 70.0, 40.0, (1, 0), 2.0, 1.0, (0.5, 0.5, 0.5))
+    out = oracle.adaptive_split(scene, np.arange(n, dtype=np.int32), reg, [CAM], np.ones(n, np.int32), prm, noise)
+    assert (out["mode"] == 3).all() and (out["count"] == N).all() and out["n_out"] == n * N
+    np.testing.assert_allclose(np.exp(out["log_scales"][:, 0].astype(np.float64)), np.exp(ls) / (0.8 * N), rtol=1e-6)
+    off = out["means"][:, : n * N].astype(np.float64)
+    R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    S = R @ np.diag(np.exp(2 * ls)) @ R.T
+    emp = off @ off.T / off.shape[1]
+    assert np.abs(emp - S).max() <= 0.1 * np.abs(S).max()
+
+
+def test_ablation_steps_on_one_region_seen_twice():
+    """The same region in two views: AdpSplit merges the two proposals (one
+    child + parent copy), child initialisation without merging keeps both
+    (two children + parent copy), adaptive N places two random children."""
+    reg_a = region_record(0, 0, 17, 70.0, 40.0, (0.8, 0.6), 4.0, 1.5, (0.9, 0.1, 0.2))
+    reg_b = region_record(0, 1, 5, 70.0, 40.0, (0.8, 0.6), 4.0, 1.5, (0.9, 0.1, 0.2))
+    noise = np.zeros((1, 19, 3), np.float32)
+    full = split_one(PAR, [reg_a, reg_b], [CAM, CAM])
+    ci = split_one(PAR, [reg_a, reg_b], [CAM, CAM], prm=oracle.SplitParams(variant=oracle.VARIANT_CHILD_INIT))
+    an = split_one(PAR, [reg_a, reg_b], [CAM, CAM], noise=noise,
+                   prm=oracle.SplitParams(variant=oracle.VARIANT_ADAPTIVE_N, noise_n=19))
+    assert (full["mode"][0], full["count"][0]) == (oracle.MODE_ADAPTIVE, 2)
+    assert (ci["mode"][0], ci["count"][0]) == (oracle.MODE_ADAPTIVE, 3)
+    assert (an["mode"][0], an["count"][0]) == (3, 2)
+    # child initialisation: each child is its region's proposal
+    ok, muc, R, s = oracle.child_proposal(PAR, reg_a, CAM)
+    for c in range(2):
+        np.testing.assert_allclose(ci["means"][:, c], muc, rtol=1e-6)
+    # adaptive N with zero noise: children sit on the parent, scales / (eta * 2)
+    for c in range(2):
+        np.testing.assert_array_equal(an["means"][:, c], PAR.means[:, 0])
+        np.testing.assert_allclose(np.exp(an["log_scales"][:, c].astype(np.float64)),
+                                   np.exp(PAR.log_scales[:, 0].astype(np.float64)) / 1.6, rtol=1e-6)
+    assert an["n_out"] == 2   # parent removed, no copy
+
+
+@pytest.mark.parametrize("variant", [oracle.VARIANT_ADAPTIVE_N, oracle.VARIANT_CHILD_INIT])
+def test_ablation_counts_track_regions(variant):
+    par = parent((0.0, 0.0, 0.0), [math.log(0.02)] * 3, logit=0.7)
+    for k in (1, 4, 25):
+        out = split_one(par, _separated_regions(k), [CAM], noise=np.zeros((1, 19, 3), np.float32),
+                        prm=oracle.SplitParams(variant=variant, noise_n=19))
+        nk = min(k, 19)
+        assert out["count"][0] == (nk if variant == oracle.VARIANT_ADAPTIVE_N else nk + 1)
+
+
+def test_cross_view_flag_keeps_same_view_pairs_apart():
+    a = region_record(0, 0, 1, 60.0, 48.0, (1, 0), 2.0, 2.0, (0.5, 0.5, 0.5))
+    b = region_record(0, 0, 2, 60.5, 48.0, (1, 0), 2.0, 2.0, (0.5, 0.5, 0.5))
+    b2 = region_record(0, 1, 2, 60.5, 48.0, (1, 0), 2.0, 2.0, (0.5, 0.5, 0.5))
+    fl = oracle.SplitParams(flags=oracle.FLAG_CROSS_VIEW)
+    assert split_one(PAR, [a, b], [CAM])["count"][0] == 2           # default: any pair links
+    assert split_one(PAR, [a, b], [CAM], prm=fl)["count"][0] == 3   # same view: not merged
+    assert split_one(PAR, [a, b2], [CAM, CAM], prm=fl)["count"][0] == 2
+
+
+def test_extent_flag_changes_which_child_the_cap_keeps():
+    """Two separated children, N_max = 1: one is long and thin (larger
+    maximum scale), the other round (larger s1 s2 s3)."""
+    par = parent((0.0, 0.0, 0.0), [math.log(0.5)] * 3, logit=0.7)
+    thin = region_record(0, 0, 1, 30.0, 30.0, (1, 0), 6.0, 0.3, (0.1, 0.5, 0.5))
+    round_ = region_record(0, 0, 2, 90.0, 60.0, (1, 0), 3.0, 3.0, (0.9, 0.5, 0.5))
+    C0 = 1 / (2 * math.sqrt(math.pi))
+    prod = split_one(par, [thin, round_], [CAM], prm=oracle.SplitParams(n_max=1))
+    mx = split_one(par, [thin, round_], [CAM], prm=oracle.SplitParams(n_max=1, flags=oracle.FLAG_EXTENT_MAX))
+    assert prod["sh"][0, 0, 0] * C0 + 0.5 == pytest.approx(0.9, abs=1e-6)   # round: larger product
+    assert mx["sh"][0, 0, 0] * C0 + 0.5 == pytest.approx(0.1, abs=1e-6)     # thin: larger maximum
+
+
+def test_shared_opacity_flag():
+    par = parent((0.0, 0.0, 0.0), [math.log(0.02)] * 3, logit=0.7)
+    out = split_one(par, _separated_regions(3), [CAM], prm=oracle.SplitParams(flags=oracle.FLAG_SHARE_OPACITY))
+    o = 1 / (1 + math.exp(-0.7))
+    got = 1 / (1 + np.exp(-out["opacity_logits"][:4].astype(np.float64)))
+    np.testing.assert_allclose(got, o / 4, rtol=1e-6)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_erosion_side_flag_on_a_block(r):
+    """A square element of side r+1 (offsets -floor(r/2) .. r - floor(r/2))
+    erodes a w x h block away from the borders to (w - r) x (h - r), shifted
+    by the element's asymmetry."""
+    H, W = 40, 50
+    E = np.zeros((H, W))
+    E[10:30, 12:40] = 1.0
+    dom = np.zeros((H, W), np.int32)
+    img, gt, dom, is_cand = maps_from_error(E, dom)
+    prm = oracle.SplitParams(r_erode=r, flags=oracle.FLAG_ERODE_SIDE, m_min=1)
+    regs, maps = oracle.error_stats(img, gt, dom, is_cand, 0, prm, np.zeros(1, np.int32), want_maps=True)
+    lo, hi = r // 2, r - r // 2
+    want = np.zeros((H, W), bool)
+    want[10 + lo:30 - hi, 12 + lo:40 - hi] = True
+    np.testing.assert_array_equal(maps["Mp"].astype(bool), want)
