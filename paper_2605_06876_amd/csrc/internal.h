@@ -177,11 +177,12 @@ void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, voi
 void scan_u8_to_i64(const uint8_t *in, int64_t *out, int64_t n, int64_t *total, void *tmp, hipStream_t s);
 void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total, void *tmp, hipStream_t s);
 
-// LSD radix sort (binning.hip).  Sorts (keys[0], vals[0]) stably on bits
+// LSD radix sort (radix.hip).  Sorts (keys[0], vals[0]) stably on bits
 // [lo_bit, hi_bit) with digits of radix_bits (4..8) bits, ping-ponging with
 // (keys[1], vals[1]); returns which buffer holds the result.  The element
-// count is read from the device (*n_dev, clamped to cap); n_hint sizes the grid.
-size_t sort_hist_bytes(int64_t n_hint);
+// count is read from the device (*n_dev, clamped to cap); n_hint sizes the
+// grid.  hist is a workspace of sort_hist_bytes(cap) bytes for the same cap.
+size_t sort_hist_bytes(int64_t cap);
 int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
                    int hi_bit, int radix_bits, void *hist, hipStream_t s);
 int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
