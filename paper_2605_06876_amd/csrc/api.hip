@@ -224,7 +224,7 @@ void as_frame_destroy(as_frame *f) {
     if (!f) return;
     (void)hipSetDevice(f->ctx->device);
     void *ptrs[] = {f->rec, f->depth_key, f->box, f->ntiles, f->offsets, f->grad2d, f->ranges, f->n_keys,
-                    f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax, f->dkeys[0], f->dkeys[1],
+                    f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax, f->tile_err, f->dkeys[0], f->dkeys[1],
                     f->dvals[0], f->dvals[1], f->nt_sorted, f->n_ent, f->tile_order, f->queue};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -258,6 +258,7 @@ static as_status frame_alloc(as_ctx *ctx, int32_t max_views, int64_t ent_cap, in
         (e = dmalloc(&f->t_final, pix_cap)) != hipSuccess || (e = dmalloc(&f->last, pix_cap)) != hipSuccess ||
         (e = dmalloc(&f->n_contrib, pix_cap)) != hipSuccess || (e = dmalloc(&f->dom, pix_cap)) != hipSuccess ||
         (e = dmalloc(&f->err, pix_cap)) != hipSuccess || (e = dmalloc(&f->err_minmax, 2 * max_views)) != hipSuccess ||
+        (e = dmalloc(&f->tile_err, tile_cap * 2)) != hipSuccess ||
         (e = dmalloc(&f->dkeys[0], ent_cap)) != hipSuccess || (e = dmalloc(&f->dkeys[1], ent_cap)) != hipSuccess ||
         (e = dmalloc(&f->dvals[0], ent_cap)) != hipSuccess || (e = dmalloc(&f->dvals[1], ent_cap)) != hipSuccess ||
         (e = dmalloc(&f->nt_sorted, ent_cap)) != hipSuccess || (e = dmalloc(&f->n_ent, 4)) != hipSuccess ||
@@ -465,12 +466,6 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
         launch_ranges(f->keys[sel], f->n_keys, f->key_cap, tiles, f->ranges, s);
         f->use_order = ctx->longest_first;
         if (f->use_order) launch_tile_order(f->ranges, (int)tiles, f->tile_order, s);
-    }
-    if (gt) {
-        for (int v = 0; v < n_views; v++) {
-            launch_fill_u64(f->err_minmax + 2 * v, 0x7ff0000000000000ull, 1, s);
-            launch_fill_u64(f->err_minmax + 2 * v + 1, 0ull, 1, s);
-        }
     }
     const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
     {

@@ -189,11 +189,12 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                                                         float *__restrict__ t_final, uint32_t *__restrict__ last_out,
                                                         uint32_t *__restrict__ ncontrib_out,
                                                         int32_t *__restrict__ dom_out, double *__restrict__ err,
-                                                        unsigned long long *__restrict__ minmax, uint32_t *queue,
+                                                        unsigned long long *__restrict__ tile_err, uint32_t *queue,
                                                         int n_tiles) {
     constexpr int R = BATCH / AS_BLOCK;
     __shared__ BlendShared<BATCH> sh;
     __shared__ uint32_t s_next;
+    __shared__ unsigned long long s_emin[AS_BLOCK / 64], s_emax[AS_BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const LaneGeom lg = lane_geom(tid);
     const HitT<BATCH> *hits = sh.hits[w][lg.row];
@@ -314,12 +315,26 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
             }
         }
         if (gt) {
-            // e >= 0, so the IEEE bit patterns order like the values
+            // The tile's error range, stored per tile and reduced per view by
+            // a second kernel: device-wide atomics on one word per view
+            // serialise at the memory side and stall every block's gathers.
+            // e >= 0, so the IEEE bit patterns order like the values.
             const double emin = wave_min_d(inside ? e : __longlong_as_double(0x7ff0000000000000ll));
             const double emax = wave_max_d(inside ? e : 0.0);
             if (lane == 0) {
-                atomicMin(&minmax[2 * v], (unsigned long long)__double_as_longlong(emin));
-                atomicMax(&minmax[2 * v + 1], (unsigned long long)__double_as_longlong(emax));
+                s_emin[w] = (unsigned long long)__double_as_longlong(emin);
+                s_emax[w] = (unsigned long long)__double_as_longlong(emax);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                unsigned long long a = s_emin[0], b = s_emax[0];
+#pragma unroll
+                for (int k = 1; k < AS_BLOCK / 64; k++) {
+                    a = s_emin[k] < a ? s_emin[k] : a;
+                    b = s_emax[k] > b ? s_emax[k] : b;
+                }
+                tile_err[2 * tile] = a;
+                tile_err[2 * tile + 1] = b;
             }
         }
     }
@@ -537,6 +552,41 @@ void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipSt
 }
 
 namespace {
+// Error range of each view with a target image: the minimum and maximum of
+// its tiles' ranges (one block per view).
+__global__ void __launch_bounds__(AS_BLOCK) k_err_minmax(const ViewTable vt, const ViewImagesC gts,
+                                                         const unsigned long long *__restrict__ tile_err,
+                                                         unsigned long long *__restrict__ minmax) {
+    __shared__ unsigned long long s_mn[AS_BLOCK / 64], s_mx[AS_BLOCK / 64];
+    const int v = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    unsigned long long mn = 0x7ff0000000000000ull, mx = 0ull;
+    if (gts.p[v]) {
+        for (int t = vt.tile_base[v] + tid; t < vt.tile_base[v + 1]; t += AS_BLOCK) {
+            const unsigned long long a = tile_err[2 * t], b = tile_err[2 * t + 1];
+            mn = a < mn ? a : mn;
+            mx = b > mx ? b : mx;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    if (lane == 0) {
+        s_mn[w] = mn;
+        s_mx[w] = mx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 1; k < AS_BLOCK / 64; k++) {
+            mn = s_mn[k] < mn ? s_mn[k] : mn;
+            mx = s_mx[k] > mx ? s_mx[k] : mx;
+        }
+        minmax[2 * v] = mn;
+        minmax[2 * v + 1] = mx;
+    }
+}
+
 // Resident blocks of a kernel on the whole device (persistent grid size).
 template <typename Kern>
 int resident_blocks(Kern k, int n_cu) {
@@ -551,7 +601,7 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
     const int tiles = vt.tile_base[vt.n_views];
     if (tiles == 0) return;
     const short4 *b4 = reinterpret_cast<const short4 *>(f->box);
-    unsigned long long *mm = reinterpret_cast<unsigned long long *>(f->err_minmax);
+    unsigned long long *te = reinterpret_cast<unsigned long long *>(f->tile_err);
     if (bl.persistent) launch_fill_u32(f->queue, 0u, 1, s);
 #define AS_FWD(B, PER)                                                                                             \
     do {                                                                                                           \
@@ -562,7 +612,7 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
             grid = grid_p < tiles ? grid_p : tiles;                                                                \
         }                                                                                                          \
         hipLaunchKernelGGL((k_blend_fwd<B, PER>), dim3(grid), dim3(AS_BLOCK), 0, s, f->ranges, tile_order, vals,  \
-                           f->rec, b4, vt, gt, image, f->t_final, f->last, f->n_contrib, f->dom, f->err, mm,      \
+                           f->rec, b4, vt, gt, image, f->t_final, f->last, f->n_contrib, f->dom, f->err, te,      \
                            f->queue, tiles);                                                                       \
     } while (0)
     if (bl.persistent) {
@@ -575,6 +625,11 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         else AS_FWD(256, false);
     }
 #undef AS_FWD
+    bool any_gt = false;
+    for (int v = 0; v < vt.n_views; v++) any_gt = any_gt || gt.p[v] != nullptr;
+    if (any_gt)
+        hipLaunchKernelGGL(k_err_minmax, dim3(vt.n_views), dim3(AS_BLOCK), 0, s, vt, gt, te,
+                           reinterpret_cast<unsigned long long *>(f->err_minmax));
 }
 
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,

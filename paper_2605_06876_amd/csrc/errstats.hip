@@ -17,24 +17,39 @@ enum { ES_M, ES_B, ES_LABEL, ES_MOM, ES_KEEP, ES_KIDX, ES_SCAN, ES_TOT };
 
 __device__ __forceinline__ double dev_bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
-__global__ void k_error_map(int W, int H, const float *__restrict__ img, const float *__restrict__ gt,
-                            double *__restrict__ err, unsigned long long *__restrict__ minmax) {
+// Per-pixel L1 error and its range.  A bounded grid strides over the pixels
+// and each block issues one pair of range atomics: device-wide atomics on the
+// same two words serialise at the memory side, so there are few of them.
+__global__ void __launch_bounds__(256) k_error_map(int W, int H, const float *__restrict__ img,
+                                                   const float *__restrict__ gt, double *__restrict__ err,
+                                                   unsigned long long *__restrict__ minmax) {
+    __shared__ double s_mn[4], s_mx[4];
     const int64_t P = (int64_t)W * H;
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double e = 0.0;
-    const bool in = u < P;
-    if (in) {
+    double mn = __longlong_as_double(0x7ff0000000000000ll), mx = 0.0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < P; u += (int64_t)gridDim.x * blockDim.x) {
         const double d0 = fabs((double)img[u] - (double)gt[u]);
         const double d1 = fabs((double)img[P + u] - (double)gt[P + u]);
         const double d2 = fabs((double)img[2 * P + u] - (double)gt[2 * P + u]);
-        e = (d0 + d1) + d2;
+        const double e = (d0 + d1) + d2;
         err[u] = e;
+        mn = fmin(mn, e);
+        mx = fmax(mx, e);
     }
-    const double emin = wave_min_d(in ? e : __longlong_as_double(0x7ff0000000000000ll));
-    const double emax = wave_max_d(in ? e : 0.0);
+    mn = wave_min_d(mn);
+    mx = wave_max_d(mx);
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicMin(&minmax[0], (unsigned long long)__double_as_longlong(emin));
-        atomicMax(&minmax[1], (unsigned long long)__double_as_longlong(emax));
+        s_mn[w] = mn;
+        s_mx[w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; k++) {
+            mn = fmin(mn, s_mn[k]);
+            mx = fmax(mx, s_mx[k]);
+        }
+        atomicMin(&minmax[0], (unsigned long long)__double_as_longlong(mn));
+        atomicMax(&minmax[1], (unsigned long long)__double_as_longlong(mx));
     }
 }
 
@@ -381,7 +396,9 @@ void launch_error_map(int W, int H, const float *image, const float *gt, double 
     launch_fill_u64(minmax, 0x7ff0000000000000ull, 1, s);
     launch_fill_u64(minmax + 1, 0ull, 1, s);
     if (P == 0) return;
-    hipLaunchKernelGGL(k_error_map, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, W, H, image, gt, err,
+    int64_t g = (P + 255) / 256;
+    if (g > 512) g = 512;
+    hipLaunchKernelGGL(k_error_map, dim3((unsigned)g), dim3(256), 0, s, W, H, image, gt, err,
                        reinterpret_cast<unsigned long long *>(minmax));
 }
 

@@ -119,6 +119,7 @@ struct as_frame {
     int32_t *dom;
     double *err;
     uint64_t *err_minmax;  // [max_views][2]
+    uint64_t *tile_err;    // [tile_cap][2] per-tile error min / max (IEEE bits), reduced into err_minmax
     // scratch for scans and the sorter
     DevBuf scan_tmp, sort_hist;
     // state of the last render
