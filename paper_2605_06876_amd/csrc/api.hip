@@ -225,7 +225,8 @@ void as_frame_destroy(as_frame *f) {
     (void)hipSetDevice(f->ctx->device);
     void *ptrs[] = {f->rec, f->depth_key, f->box, f->ntiles, f->offsets, f->grad2d, f->ranges, f->n_keys,
                     f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax, f->tile_err, f->dkeys[0], f->dkeys[1],
-                    f->dvals[0], f->dvals[1], f->nt_sorted, f->n_ent, f->tile_order, f->queue};
+                    f->dvals[0], f->dvals[1], f->nt_sorted, f->n_ent, f->tile_order, f->tile_work, f->tile_order_bwd,
+                    f->queue};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_keys(f);
@@ -255,6 +256,7 @@ static as_status frame_alloc(as_ctx *ctx, int32_t max_views, int64_t ent_cap, in
         (e = dmalloc(&f->offsets, ent_cap)) != hipSuccess || (e = dmalloc(&f->grad2d, ent_cap * 9)) != hipSuccess ||
         (e = dmalloc(&f->ranges, tile_cap * 2)) != hipSuccess || (e = dmalloc(&f->n_keys, 4)) != hipSuccess ||
         (e = dmalloc(&f->tile_order, tile_cap)) != hipSuccess || (e = dmalloc(&f->queue, 2)) != hipSuccess ||
+        (e = dmalloc(&f->tile_work, tile_cap)) != hipSuccess || (e = dmalloc(&f->tile_order_bwd, tile_cap)) != hipSuccess ||
         (e = dmalloc(&f->t_final, pix_cap)) != hipSuccess || (e = dmalloc(&f->last, pix_cap)) != hipSuccess ||
         (e = dmalloc(&f->n_contrib, pix_cap)) != hipSuccess || (e = dmalloc(&f->dom, pix_cap)) != hipSuccess ||
         (e = dmalloc(&f->err, pix_cap)) != hipSuccess || (e = dmalloc(&f->err_minmax, 2 * max_views)) != hipSuccess ||
@@ -471,6 +473,9 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     {
         StageTimer t(ctx, AS_STAGE_BLEND_FWD, s);
         launch_blend_fwd(f, f->vals[sel], f->use_order ? f->tile_order : nullptr, bl, vt, gi, im, s);
+        // the reverse pass's cost per tile follows its contributors, which only
+        // the forward pass knows: order the reverse dispatch by them
+        if (f->use_order) launch_tile_order_work(f->tile_work, (int)tiles, f->tile_order_bwd, s);
     }
     const as_status st = launch_status("as_render");
     if (st != AS_OK) return st;
@@ -518,10 +523,9 @@ as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame 
     const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
     {
         StageTimer t(ctx, AS_STAGE_BLEND_BWD, s);
-        for (int k = 0; k < 9; k++)
-            launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d + k * f->ent_cap), 0u, ents, s);
-        launch_blend_bwd(f, f->vals[f->sorted_sel], f->use_order ? f->tile_order : nullptr, bl, vt, dl, f->grad2d,
-                         f->ent_cap, s);
+        launch_fill_rows_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9, ents, f->ent_cap, s);
+        launch_blend_bwd(f, f->vals[f->sorted_sel], f->use_order ? f->tile_order_bwd : nullptr, bl, vt, dl,
+                         f->grad2d, f->ent_cap, s);
     }
     {
         StageTimer t(ctx, AS_STAGE_PROJECT_BWD, s);

@@ -189,12 +189,14 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                                                         float *__restrict__ t_final, uint32_t *__restrict__ last_out,
                                                         uint32_t *__restrict__ ncontrib_out,
                                                         int32_t *__restrict__ dom_out, double *__restrict__ err,
-                                                        unsigned long long *__restrict__ tile_err, uint32_t *queue,
+                                                        unsigned long long *__restrict__ tile_err,
+                                                        uint32_t *__restrict__ tile_work, uint32_t *queue,
                                                         int n_tiles) {
     constexpr int R = BATCH / AS_BLOCK;
     __shared__ BlendShared<BATCH> sh;
     __shared__ uint32_t s_next;
     __shared__ unsigned long long s_emin[AS_BLOCK / 64], s_emax[AS_BLOCK / 64];
+    __shared__ uint32_t s_nc[AS_BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const LaneGeom lg = lane_geom(tid);
     const HitT<BATCH> *hits = sh.hits[w][lg.row];
@@ -314,25 +316,35 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                 err[pix] = e;
             }
         }
+        // Per tile: the contributors summed over its pixels (the reverse
+        // pass's dispatch order) and, with a target, the error range, which a
+        // second kernel reduces per view: device-wide atomics on one word per
+        // view serialise at the memory side and stall every block's gathers.
+        // e >= 0, so the IEEE bit patterns order like the values.
+        uint32_t ncs = inside ? nc : 0u;
+        for (int o = 32; o > 0; o >>= 1) ncs += (uint32_t)__shfl_xor((int)ncs, o, 64);
+        double emin = 0.0, emax = 0.0;
         if (gt) {
-            // The tile's error range, stored per tile and reduced per view by
-            // a second kernel: device-wide atomics on one word per view
-            // serialise at the memory side and stall every block's gathers.
-            // e >= 0, so the IEEE bit patterns order like the values.
-            const double emin = wave_min_d(inside ? e : __longlong_as_double(0x7ff0000000000000ll));
-            const double emax = wave_max_d(inside ? e : 0.0);
-            if (lane == 0) {
-                s_emin[w] = (unsigned long long)__double_as_longlong(emin);
-                s_emax[w] = (unsigned long long)__double_as_longlong(emax);
-            }
-            __syncthreads();
-            if (tid == 0) {
-                unsigned long long a = s_emin[0], b = s_emax[0];
+            emin = wave_min_d(inside ? e : __longlong_as_double(0x7ff0000000000000ll));
+            emax = wave_max_d(inside ? e : 0.0);
+        }
+        if (lane == 0) {
+            s_nc[w] = ncs;
+            s_emin[w] = (unsigned long long)__double_as_longlong(emin);
+            s_emax[w] = (unsigned long long)__double_as_longlong(emax);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t nsum = s_nc[0];
+            unsigned long long a = s_emin[0], b = s_emax[0];
 #pragma unroll
-                for (int k = 1; k < AS_BLOCK / 64; k++) {
-                    a = s_emin[k] < a ? s_emin[k] : a;
-                    b = s_emax[k] > b ? s_emax[k] : b;
-                }
+            for (int k = 1; k < AS_BLOCK / 64; k++) {
+                nsum += s_nc[k];
+                a = s_emin[k] < a ? s_emin[k] : a;
+                b = s_emax[k] > b ? s_emax[k] : b;
+            }
+            tile_work[tile] = nsum;
+            if (gt) {
                 tile_err[2 * tile] = a;
                 tile_err[2 * tile + 1] = b;
             }
@@ -545,10 +557,43 @@ __global__ void __launch_bounds__(1024) k_tile_order(const uint32_t *__restrict_
     }
 }
 
+// Tiles ordered by descending work (contributors summed over the tile's
+// pixels), in 129 classes: four per octave, so tiles of similar cost share a
+// class and the heaviest are dispatched first.
+__device__ __forceinline__ int work_class(uint32_t wk) {
+    if (wk == 0) return 0;
+    const int lg = 31 - __clz(wk);
+    const int frac = lg >= 2 ? (int)((wk >> (lg - 2)) & 3u) : (int)((wk << (2 - lg)) & 3u);
+    return 1 + 4 * lg + frac;   // 1..128
+}
+
+__global__ void __launch_bounds__(1024) k_tile_order_work(const uint32_t *__restrict__ work, int tiles,
+                                                          uint32_t *__restrict__ order) {
+    __shared__ uint32_t s_cnt[129], s_off[129];
+    const int tid = threadIdx.x;
+    if (tid < 129) s_cnt[tid] = 0;
+    __syncthreads();
+    for (int t = tid; t < tiles; t += blockDim.x) atomicAdd(&s_cnt[128 - work_class(work[t])], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int c = 0; c < 129; c++) {
+            s_off[c] = run;
+            run += s_cnt[c];
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < tiles; t += blockDim.x) order[atomicAdd(&s_off[128 - work_class(work[t])], 1u)] = (uint32_t)t;
+}
+
 }  // namespace
 
 void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipStream_t s) {
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);
+}
+
+void launch_tile_order_work(const uint32_t *work, int tiles, uint32_t *order, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_order_work, dim3(1), dim3(1024), 0, s, work, tiles, order);
 }
 
 namespace {
@@ -613,6 +658,7 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         }                                                                                                          \
         hipLaunchKernelGGL((k_blend_fwd<B, PER>), dim3(grid), dim3(AS_BLOCK), 0, s, f->ranges, tile_order, vals,  \
                            f->rec, b4, vt, gt, image, f->t_final, f->last, f->n_contrib, f->dom, f->err, te,      \
+                           f->tile_work,                                                                   \
                            f->queue, tiles);                                                                       \
     } while (0)
     if (bl.persistent) {

@@ -107,7 +107,9 @@ struct as_frame {
     uint32_t *vals[2];
     int sorted_sel;
     uint32_t *ranges;      // [tiles][2]
-    uint32_t *tile_order;  // [tiles] dispatch order of the blend kernels
+    uint32_t *tile_order;  // [tiles] dispatch order of the forward blend (longest list first)
+    uint32_t *tile_work;   // [tiles] contributors summed over the tile's pixels, from the forward blend
+    uint32_t *tile_order_bwd;  // [tiles] dispatch order of the reverse blend (most contributors first)
     int use_order;         // tile_order is valid for the last render
     uint32_t *n_keys;      // [1] device
     uint32_t *h_nkeys;     // pinned host mirror
@@ -201,6 +203,7 @@ void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+void launch_fill_rows_u32(uint32_t *p, uint32_t v, int rows, int64_t n, int64_t stride, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 void launch_copy_u32(const uint32_t *src, uint32_t *dst, int64_t n, hipStream_t s);
 
@@ -211,6 +214,7 @@ struct BlendLaunch {
     int n_cu;
 };
 void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipStream_t s);
+void launch_tile_order_work(const uint32_t *work, int tiles, uint32_t *order, hipStream_t s);
 void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
                       const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s);
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
