@@ -300,7 +300,8 @@ typedef struct {
     int32_t lds_batch;       /* Gaussian records staged per LDS batch by the blend kernels: 256, 512 or 1024 */
     int32_t longest_first;   /* nonzero: tiles are dispatched in descending order of list length */
     int32_t persistent;      /* nonzero: the blend kernels run as one resident grid pulling tiles from a queue */
-    int32_t radix_bits;      /* digit width of the radix sorts, 4..8 */
+    int32_t radix_bits;      /* digit width of the (tile, entry) pair sort, 4..8 (the 32-bit
+                                depth keys always take 8: four passes) */
 } as_tuning;
 
 /* Set / read the context's tuning (defaults: lds_batch 256, longest_first 1,

@@ -429,7 +429,8 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     {
         StageTimer t(ctx, AS_STAGE_SORT, s);
         launch_depth_pairs(n, f->depth_key, f->dkeys[0], f->dvals[0], f->n_ent, s);
-        const int dsel = radix_sort_u32(f->dkeys, f->dvals, f->n_ent, f->ent_cap, n, 0, 32, ctx->radix_bits,
+        // 32-bit keys: 8-bit digits give the fewest passes (four)
+        const int dsel = radix_sort_u32(f->dkeys, f->dvals, f->n_ent, f->ent_cap, n, 0, 32, 8,
                                         f->dsort_hist.p, s);
         order = f->dvals[dsel];
     }
