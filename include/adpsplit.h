@@ -292,6 +292,84 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
                             as_gaussians_mut *out, uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out,
                             void *stream);
 
+/* ---- the optimisation loop around the path -------------------------------------- */
+/* The split runs inside 3DGS's training loop (Sec. 3: adaptive density
+ * control clones small and splits large Gaussians with a high view-averaged
+ * screen-space gradient and prunes transparent ones; Sec. 5 "Implementation":
+ * AdpSplit replaces the split and keeps the rest).  These entry points are the
+ * loop's per-iteration steps (loss, Adam) and its densification bookkeeping
+ * (selection, row maps, clone + prune, optimiser-state carry-over). */
+
+/* Adam hyper-parameters with the per-group learning rates of 3DGS. */
+typedef struct {
+    float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_sh_dc, lr_sh_rest;
+    float beta1, beta2, eps;
+} as_adam_params;
+
+/* One bias-corrected Adam step on every parameter (Kingma and Ba, Alg. 1):
+ *   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+ *   p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * params, m, v: updated in place; grads: read.  All four sets have the same row
+ * count (params->n) and SH degree; SH coefficient 0 takes lr_sh_dc, the others
+ * lr_sh_rest.  step = t >= 1.  AS_ERR_ARG on mismatched sets or t < 1. */
+as_status as_adam_step(as_ctx *ctx, as_gaussians_mut *params, const as_gaussians *grads, as_gaussians_mut *m,
+                       as_gaussians_mut *v, const as_adam_params *hp, int32_t step, void *stream);
+
+/* L1 photometric loss of an image against its target: sums[0] = sum |d|,
+ * sums[1] = sum d^2 over the 3 H W values (d = image - gt, FP64 sums; the
+ * mean L1 is sums[0] / (3 H W), the PSNR of [0, 1] images is
+ * -10 log10(sums[1] / (3 H W))), and, when dL_dimage is not NULL, the
+ * gradient of the mean L1: sign(d) / (3 H W) (sign(0) = 0).
+ *   image, gt, dL_dimage: [3][H][W]; sums: device [2], overwritten. */
+as_status as_l1_loss(as_ctx *ctx, int32_t width, int32_t height, const float *image, const float *gt, float *dL_dimage,
+                     double *sums, void *stream);
+
+/* Densification selection of 3DGS's adaptive density control: with the
+ * view-averaged gradient a_i = g2d_accum[i] / max(vis_count[i], 1) (FP64) and
+ * the largest scale s_i = exp(max_k log_scales[k][i]) (FP64), Gaussian i is
+ * selected when a_i >= grad_threshold; a selected Gaussian is cloned when
+ * s_i <= size_threshold and is a split candidate otherwise.
+ *   clone_mask, is_candidate: out [n] 0/1; cand: out [n], the candidate ids
+ *   ascending; n_cand: out device [1]. */
+as_status as_densify_select(as_ctx *ctx, const as_gaussians *g, const float *g2d_accum, const int32_t *vis_count,
+                            double grad_threshold, double size_threshold, uint8_t *clone_mask, uint8_t *is_candidate,
+                            int32_t *cand, int64_t *n_cand, void *stream);
+
+/* Row map of an as_adaptive_split output: row_src[r] = the input row that
+ * output row r copies (the non-removed Gaussians, in order), or -1 for the
+ * rows the split created (children and parent copies).  A candidate's parent
+ * is removed unless its mode is RESET (1).
+ *   cand, mode: [n_cand] as passed to / returned by as_adaptive_split
+ *   row_src: out [capacity]; rows past the survivors are -1. */
+as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t n_cand, const uint8_t *mode,
+                           int32_t *row_src, int64_t capacity, void *stream);
+
+/* Clone and prune (3DGS adaptive density control): Gaussian i is kept when
+ * sigmoid(opacity_logit) >= min_opacity and, if max_scale > 0,
+ * exp(max_k log_scales[k][i]) <= max_scale (decisions in FP64).  Output: the
+ * kept rows in order, then a copy of every kept row with clone_mask set, in
+ * order.  state_src[r] = state_in[i] (or i when state_in is NULL) for the kept
+ * copy of row i and -1 for a clone (a clone starts with fresh optimiser state).
+ *   g: n rows; clone_mask, state_in: NULL or [n]
+ *   out: capacity rows (row stride out->n; n + clones always suffices)
+ *   state_src: out [capacity]; n_out: out device [1].
+ * AS_ERR_CAPACITY when out->n < g->n. */
+as_status as_clone_prune(as_ctx *ctx, const as_gaussians *g, const uint8_t *clone_mask, const int32_t *state_in,
+                         double min_opacity, double max_scale, as_gaussians_mut *out, int32_t *state_src,
+                         int64_t *n_out, void *stream);
+
+/* dst row r = src row map[r] for map[r] >= 0, zeros for map[r] = -1 (carries
+ * optimiser state across a densification).  src: rows with stride src->n;
+ * dst: n_rows rows with stride dst->n >= n_rows; the same SH degree. */
+as_status as_gather_rows(as_ctx *ctx, const as_gaussians *src, const int32_t *map, int64_t n_rows,
+                         as_gaussians_mut *dst, void *stream);
+
+/* Opacity reset of 3DGS's density control: opacity <- min(opacity,
+ * max_opacity), in logit space, and the Adam moments of the opacities (m_op,
+ * v_op: NULL or [n]) cleared. */
+as_status as_reset_opacity(as_ctx *ctx, as_gaussians_mut *g, double max_opacity, float *m_op, float *v_op,
+                           void *stream);
+
 /* ---- launch tuning ---------------------------------------------------------------- */
 
 /* Launch choices that change speed but never results (the autotuner in the

@@ -75,7 +75,8 @@ EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "a
             "as_render_backward", "as_render_batch", "as_render_backward_batch", "as_error_map",
             "as_accumulate_error_stats", "as_adaptive_split", "as_set_tuning", "as_get_tuning", "as_timing_enable",
             "as_timing_read", "as_graph_begin", "as_graph_end", "as_graph_launch", "as_graph_destroy",
-            "as_debug_sort_pairs", "as_debug_fp64_ops")
+            "as_debug_sort_pairs", "as_debug_fp64_ops", "as_adam_step", "as_l1_loss", "as_densify_select",
+            "as_split_row_map", "as_clone_prune", "as_gather_rows", "as_reset_opacity")
 _NO_STATUS = ("as_last_error", "as_version", "as_ctx_destroy", "as_frame_destroy", "as_graph_destroy")
 
 STAGES = ("project", "scan", "emit", "sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd", "error_map",
@@ -511,6 +512,106 @@ def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=
                                    _ptr(count) if nc else None, _ptr(offset) if nc else None, _ptr(n_out),
                                    _stream(stream)))
     return out, mode[:nc], count[:nc], offset[:nc], n_out
+
+
+# ---- optimisation loop -----------------------------------------------------------
+
+class _AdamParams(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_float) for f in ("lr_means", "lr_log_scales", "lr_quats", "lr_opacity", "lr_sh_dc",
+                                              "lr_sh_rest", "beta1", "beta2", "eps")]
+
+
+class AdamParams:
+    """Adam with 3DGS's per-group learning rates (means 1.6e-4 times the scene
+    extent, decayed by the caller; log scales 5e-3; quaternions 1e-3;
+    opacity 5e-2; SH DC 2.5e-3, higher SH 2.5e-3 / 20; eps 1e-15)."""
+
+    def __init__(self, lr_means=1.6e-4, lr_log_scales=5e-3, lr_quats=1e-3, lr_opacity=5e-2, lr_sh_dc=2.5e-3,
+                 lr_sh_rest=2.5e-3 / 20, beta1=0.9, beta2=0.999, eps=1e-15):
+        self.lr_means, self.lr_log_scales, self.lr_quats, self.lr_opacity = lr_means, lr_log_scales, lr_quats, lr_opacity
+        self.lr_sh_dc, self.lr_sh_rest, self.beta1, self.beta2, self.eps = lr_sh_dc, lr_sh_rest, beta1, beta2, eps
+
+    def struct(self):
+        return _AdamParams(self.lr_means, self.lr_log_scales, self.lr_quats, self.lr_opacity, self.lr_sh_dc,
+                           self.lr_sh_rest, self.beta1, self.beta2, self.eps)
+
+
+def adam_step(ctx, params, grads, m, v, hp, step, stream=None):
+    """as_adam_step: params, m, v updated in place."""
+    pm, mm, vm = _GaussiansMut.of(params), _GaussiansMut.of(m), _GaussiansMut.of(v)
+    gs = grads.struct()
+    h = hp.struct()
+    _check(lib().as_adam_step(ctx.handle, ctypes.byref(pm), ctypes.byref(gs), ctypes.byref(mm), ctypes.byref(vm),
+                              ctypes.byref(h), ctypes.c_int32(step), _stream(stream)))
+
+
+def l1_loss(ctx, image, gt, dL=None, sums=None, want_grad=True, stream=None):
+    """as_l1_loss: returns (dL or None, sums[2] = (sum |d|, sum d^2)) on the device."""
+    H, W = image.shape[1], image.shape[2]
+    if want_grad and dL is None:
+        dL = torch.empty_like(image)
+    if sums is None:
+        sums = torch.empty(2, dtype=torch.float64, device="cuda")
+    _check(lib().as_l1_loss(ctx.handle, ctypes.c_int32(W), ctypes.c_int32(H), _ptr(image), _ptr(gt),
+                            _ptr(dL) if want_grad else None, _ptr(sums), _stream(stream)))
+    return (dL if want_grad else None), sums
+
+
+def densify_select(ctx, g, g2d_accum, vis_count, grad_threshold, size_threshold, stream=None):
+    """as_densify_select: (clone_mask u8 [n], is_candidate u8 [n], cand i32 [n] (first n_cand valid), n_cand)."""
+    n = g.n
+    clone = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+    is_cand = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+    cand = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    n_cand = torch.empty(1, dtype=torch.int64, device="cuda")
+    gs = g.struct()
+    _check(lib().as_densify_select(ctx.handle, ctypes.byref(gs), _ptr(g2d_accum), _ptr(vis_count),
+                                   ctypes.c_double(grad_threshold), ctypes.c_double(size_threshold), _ptr(clone),
+                                   _ptr(is_cand), _ptr(cand), _ptr(n_cand), _stream(stream)))
+    return clone[:n], is_cand[:n], cand, n_cand
+
+
+def split_row_map(ctx, n, cand, mode, capacity, stream=None):
+    """as_split_row_map: row_src i32 [capacity]."""
+    nc = int(cand.shape[0])
+    row_src = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda")
+    _check(lib().as_split_row_map(ctx.handle, ctypes.c_int64(n), _ptr(cand) if nc else None, ctypes.c_int64(nc),
+                                  _ptr(mode) if nc else None, _ptr(row_src), ctypes.c_int64(capacity),
+                                  _stream(stream)))
+    return row_src[:capacity]
+
+
+def clone_prune(ctx, g, clone_mask, state_in, min_opacity, max_scale, out=None, stream=None):
+    """as_clone_prune: (out Gaussians with 2 n rows of capacity, state_src i32, n_out device tensor)."""
+    n = g.n
+    if out is None:
+        out = Gaussians.empty(max(2 * n, 1), g.sh_degree)
+    state_src = torch.empty(max(out.n, 1), dtype=torch.int32, device="cuda")
+    n_out = torch.empty(1, dtype=torch.int64, device="cuda")
+    gs = g.struct()
+    om = _GaussiansMut.of(out)
+    _check(lib().as_clone_prune(ctx.handle, ctypes.byref(gs), _ptr(clone_mask), _ptr(state_in),
+                                ctypes.c_double(min_opacity), ctypes.c_double(max_scale), ctypes.byref(om),
+                                _ptr(state_src), _ptr(n_out), _stream(stream)))
+    return out, state_src, n_out
+
+
+def gather_rows(ctx, src, row_map, n_rows, dst=None, stream=None):
+    """as_gather_rows: dst row r = src row map[r] (zeros for -1)."""
+    if dst is None:
+        dst = Gaussians.empty(max(n_rows, 1), src.sh_degree)
+    ss = src.struct()
+    dm = _GaussiansMut.of(dst)
+    _check(lib().as_gather_rows(ctx.handle, ctypes.byref(ss), _ptr(row_map) if n_rows else None,
+                                ctypes.c_int64(n_rows), ctypes.byref(dm), _stream(stream)))
+    return dst
+
+
+def reset_opacity(ctx, g, max_opacity, m_op=None, v_op=None, stream=None):
+    """as_reset_opacity: in place."""
+    gm = _GaussiansMut.of(g)
+    _check(lib().as_reset_opacity(ctx.handle, ctypes.byref(gm), ctypes.c_double(max_opacity), _ptr(m_op), _ptr(v_op),
+                                  _stream(stream)))
 
 
 class _Tuning(ctypes.Structure):

@@ -27,6 +27,7 @@ SOURCES = {
     "blend.hip": [],
     "errstats.hip": ["-ffp-contract=off"],
     "split.hip": ["-ffp-contract=off"],
+    "train.hip": ["-ffp-contract=off"],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-munsafe-fp-atomics",

@@ -210,6 +210,7 @@ void as_ctx_destroy(as_ctx *ctx) {
     for (auto &b : ctx->es) devbuf_free(b);
     for (auto &b : ctx->sp) devbuf_free(b);
     for (auto &b : ctx->dbg) devbuf_free(b);
+    for (auto &b : ctx->tr) devbuf_free(b);
     for (int k = 0; k < ctx->n_recs; k++) {
         (void)hipEventDestroy(ctx->recs[k].beg);
         (void)hipEventDestroy(ctx->recs[k].end);
@@ -563,6 +564,160 @@ as_status as_error_map(as_ctx *ctx, int32_t width, int32_t height, const float *
         launch_error_map(width, height, image, gt, err, err_minmax, (hipStream_t)stream);
     }
     return launch_status("as_error_map");
+}
+
+// ---- optimisation loop ----------------------------------------------------------
+// scratch slots of ctx->tr
+enum { TR_PART, TR_FLAG, TR_SCAN, TR_TMP, TR_DUP, TR_DSCAN, TR_TOT, TR_TMP2 };
+
+static bool same_shape(const as_gaussians_mut *a, int64_t n, int32_t deg, const char *what, const char *name) {
+    if (!a) { as_set_error("%s: null %s", what, name); return false; }
+    if (a->n != n || a->sh_degree != deg) {
+        as_set_error("%s: %s has %lld rows, degree %d (expected %lld, %d)", what, name, (long long)a->n, a->sh_degree,
+                     (long long)n, deg);
+        return false;
+    }
+    if (n > 0 && (!a->means || !a->log_scales || !a->quats || !a->opacity_logits || !a->sh)) {
+        as_set_error("%s: null pointer in %s", what, name);
+        return false;
+    }
+    return true;
+}
+
+as_status as_adam_step(as_ctx *ctx, as_gaussians_mut *params, const as_gaussians *grads, as_gaussians_mut *m,
+                       as_gaussians_mut *v, const as_adam_params *hp, int32_t step, void *stream) {
+    const char *what = "as_adam_step";
+    if (!ctx || !params || !hp) { as_set_error("%s: null argument", what); return AS_ERR_ARG; }
+    if (step < 1) { as_set_error("%s: step %d < 1", what, step); return AS_ERR_ARG; }
+    if (params->sh_degree < 0 || params->sh_degree > 3) { as_set_error("%s: sh_degree %d", what, params->sh_degree); return AS_ERR_ARG; }
+    if (!same_shape(params, params->n, params->sh_degree, what, "params") || !check_gauss(grads, what) ||
+        !same_shape(m, params->n, params->sh_degree, what, "m") || !same_shape(v, params->n, params->sh_degree, what, "v"))
+        return AS_ERR_ARG;
+    if (grads->n != params->n || grads->sh_degree != params->sh_degree) {
+        as_set_error("%s: grads has %lld rows, degree %d", what, (long long)grads->n, grads->sh_degree);
+        return AS_ERR_ARG;
+    }
+    launch_adam(*params, *grads, *m, *v, *hp, step, (hipStream_t)stream);
+    return launch_status(what);
+}
+
+as_status as_l1_loss(as_ctx *ctx, int32_t width, int32_t height, const float *image, const float *gt, float *dL_dimage,
+                     double *sums, void *stream) {
+    const char *what = "as_l1_loss";
+    if (!ctx || !image || !gt || !sums || width < 1 || height < 1) { as_set_error("%s: bad argument", what); return AS_ERR_ARG; }
+    if (bad(devbuf_ensure(ctx->tr[TR_PART], l1_partials_bytes()), "as_l1_loss: scratch")) return AS_ERR_HIP;
+    launch_l1(width, height, image, gt, dL_dimage, sums, (double *)ctx->tr[TR_PART].p, (hipStream_t)stream);
+    return launch_status(what);
+}
+
+as_status as_densify_select(as_ctx *ctx, const as_gaussians *g, const float *g2d_accum, const int32_t *vis_count,
+                            double grad_threshold, double size_threshold, uint8_t *clone_mask, uint8_t *is_candidate,
+                            int32_t *cand, int64_t *n_cand, void *stream) {
+    const char *what = "as_densify_select";
+    if (!ctx) { as_set_error("%s: null context", what); return AS_ERR_ARG; }
+    if (!check_gauss(g, what)) return AS_ERR_ARG;
+    if (!n_cand || (g->n > 0 && (!g2d_accum || !vis_count || !clone_mask || !is_candidate || !cand))) {
+        as_set_error("%s: null argument", what);
+        return AS_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = g->n;
+    if (bad(devbuf_ensure(ctx->tr[TR_SCAN], (size_t)(n > 0 ? n : 1) * 8), "as_densify_select: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_TMP], scan_tmp_bytes(n > 0 ? n : 1)), "as_densify_select: scratch"))
+        return AS_ERR_HIP;
+    if (n == 0) {
+        launch_fill_i64(n_cand, 0, 1, s);
+        return launch_status(what);
+    }
+    launch_select(*g, g2d_accum, vis_count, grad_threshold, size_threshold, clone_mask, is_candidate, s);
+    int64_t *scan = (int64_t *)ctx->tr[TR_SCAN].p;
+    scan_u8_to_i64(is_candidate, scan, n, n_cand, ctx->tr[TR_TMP].p, s);
+    launch_compact_ids(n, is_candidate, scan, cand, s);
+    return launch_status(what);
+}
+
+as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t n_cand, const uint8_t *mode,
+                           int32_t *row_src, int64_t capacity, void *stream) {
+    const char *what = "as_split_row_map";
+    if (!ctx || n < 0 || n_cand < 0 || capacity < n || (n_cand > 0 && (!cand || !mode)) || (capacity > 0 && !row_src)) {
+        as_set_error("%s: bad argument (n %lld, candidates %lld, capacity %lld)", what, (long long)n, (long long)n_cand,
+                     (long long)capacity);
+        return AS_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t m = n > 0 ? n : 1;
+    if (bad(devbuf_ensure(ctx->tr[TR_FLAG], (size_t)m), "as_split_row_map: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_SCAN], (size_t)m * 8), "as_split_row_map: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_TMP], scan_tmp_bytes(m)), "as_split_row_map: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_TOT], 16), "as_split_row_map: scratch"))
+        return AS_ERR_HIP;
+    if (capacity > 0) launch_fill_u32(reinterpret_cast<uint32_t *>(row_src), 0xFFFFFFFFu, capacity, s);
+    if (n == 0) return launch_status(what);
+    uint8_t *keep = (uint8_t *)ctx->tr[TR_FLAG].p;
+    int64_t *pos = (int64_t *)ctx->tr[TR_SCAN].p;
+    launch_fill_u8(keep, 1, n, s);
+    launch_mark_kept(cand, n_cand, mode, n, keep, s);
+    scan_u8_to_i64(keep, pos, n, (int64_t *)ctx->tr[TR_TOT].p, ctx->tr[TR_TMP].p, s);
+    launch_row_map(n, keep, pos, capacity, row_src, s);
+    return launch_status(what);
+}
+
+as_status as_clone_prune(as_ctx *ctx, const as_gaussians *g, const uint8_t *clone_mask, const int32_t *state_in,
+                         double min_opacity, double max_scale, as_gaussians_mut *out, int32_t *state_src,
+                         int64_t *n_out, void *stream) {
+    const char *what = "as_clone_prune";
+    if (!ctx) { as_set_error("%s: null context", what); return AS_ERR_ARG; }
+    if (!check_gauss(g, what)) return AS_ERR_ARG;
+    if (!out || !state_src || !n_out) { as_set_error("%s: null output", what); return AS_ERR_ARG; }
+    if (out->n < 2 * g->n) {
+        as_set_error("%s: output capacity %lld < 2 x %lld rows (every row may be cloned)", what, (long long)out->n,
+                     (long long)g->n);
+        return AS_ERR_CAPACITY;
+    }
+    if (!check_mut(out, 2 * g->n, g->sh_degree, what)) return AS_ERR_ARG;
+    if (g->n > 0 && (out->means == g->means || out->sh == g->sh)) { as_set_error("%s: output aliases the input", what); return AS_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = g->n, m = n > 0 ? n : 1;
+    if (bad(devbuf_ensure(ctx->tr[TR_FLAG], (size_t)m), "as_clone_prune: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_DUP], (size_t)m), "as_clone_prune: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_SCAN], (size_t)m * 8), "as_clone_prune: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_DSCAN], (size_t)m * 8), "as_clone_prune: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_TMP], scan_tmp_bytes(m)), "as_clone_prune: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_TMP2], scan_tmp_bytes(m)), "as_clone_prune: scratch") ||
+        bad(devbuf_ensure(ctx->tr[TR_TOT], 16), "as_clone_prune: scratch"))
+        return AS_ERR_HIP;
+    int64_t *tot = (int64_t *)ctx->tr[TR_TOT].p;
+    if (n == 0) {
+        launch_fill_i64(n_out, 0, 1, s);
+        return launch_status(what);
+    }
+    uint8_t *keep = (uint8_t *)ctx->tr[TR_FLAG].p, *dup = (uint8_t *)ctx->tr[TR_DUP].p;
+    int64_t *kpos = (int64_t *)ctx->tr[TR_SCAN].p, *dpos = (int64_t *)ctx->tr[TR_DSCAN].p;
+    launch_prune_flags(*g, clone_mask, min_opacity, max_scale, keep, dup, s);
+    scan_u8_to_i64(keep, kpos, n, tot, ctx->tr[TR_TMP].p, s);
+    scan_u8_to_i64(dup, dpos, n, tot + 1, ctx->tr[TR_TMP2].p, s);
+    launch_clone_prune_write(*g, *out, keep, dup, kpos, dpos, tot, tot + 1, state_in, state_src, n_out, s);
+    return launch_status(what);
+}
+
+as_status as_gather_rows(as_ctx *ctx, const as_gaussians *src, const int32_t *map, int64_t n_rows,
+                         as_gaussians_mut *dst, void *stream) {
+    const char *what = "as_gather_rows";
+    if (!ctx || n_rows < 0 || !check_gauss(src, what) || (n_rows > 0 && !map)) { as_set_error("%s: bad argument", what); return AS_ERR_ARG; }
+    if (!check_mut(dst, n_rows, src->sh_degree, what)) return AS_ERR_ARG;
+    launch_gather_rows(*src, map, n_rows, *dst, (hipStream_t)stream);
+    return launch_status(what);
+}
+
+as_status as_reset_opacity(as_ctx *ctx, as_gaussians_mut *g, double max_opacity, float *m_op, float *v_op,
+                           void *stream) {
+    const char *what = "as_reset_opacity";
+    if (!ctx || !g || g->n < 0 || (g->n > 0 && !g->opacity_logits) || !(max_opacity > 0.0 && max_opacity < 1.0)) {
+        as_set_error("%s: bad argument", what);
+        return AS_ERR_ARG;
+    }
+    launch_reset_opacity(*g, (float)log(max_opacity / (1.0 - max_opacity)), m_op, v_op, (hipStream_t)stream);
+    return launch_status(what);
 }
 
 as_status as_accumulate_error_stats(as_ctx *ctx, int32_t width, int32_t height, const double *err,

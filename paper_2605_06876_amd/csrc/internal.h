@@ -142,6 +142,7 @@ struct as_ctx {
     DevBuf es[16];    // error-statistics scratch (errstats.hip names the slots)
     DevBuf sp[24];    // adaptive-split scratch (split.hip names the slots)
     DevBuf dbg[4];    // test hooks
+    DevBuf tr[8];     // optimisation-loop scratch (train.hip kernels; slots named in api.hip)
     int lds_batch = 256;          // launch tuning (as_set_tuning)
     int longest_first = 1;
     int persistent = 0;
@@ -220,6 +221,29 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
                       const ViewTable &vt, const ViewImagesC &dL_dimage, float *grad2d, int64_t g2d_stride,
                       hipStream_t s);
+
+// optimisation loop (train.hip)
+int train_set_rows(int deg);
+void launch_adam(const as_gaussians_mut &p, const as_gaussians &g, const as_gaussians_mut &m, const as_gaussians_mut &v,
+                 const as_adam_params &hp, int32_t step, hipStream_t s);
+size_t l1_partials_bytes();
+void launch_l1(int W, int H, const float *img, const float *gt, float *dL, double *sums, double *partials,
+               hipStream_t s);
+void launch_select(const as_gaussians &g, const float *accum, const int32_t *vis, double thr, double size_thr,
+                   uint8_t *clone, uint8_t *cand_flag, hipStream_t s);
+void launch_compact_ids(int64_t n, const uint8_t *flag, const int64_t *scan, int32_t *out, hipStream_t s);
+void launch_mark_kept(const int32_t *cand, int64_t n_cand, const uint8_t *mode, int64_t n, uint8_t *keep, hipStream_t s);
+void launch_row_map(int64_t n, const uint8_t *keep, const int64_t *pos, int64_t capacity, int32_t *row_src,
+                    hipStream_t s);
+void launch_prune_flags(const as_gaussians &g, const uint8_t *clone_mask, double min_op, double max_scale,
+                        uint8_t *keep, uint8_t *dup, hipStream_t s);
+void launch_clone_prune_write(const as_gaussians &g, const as_gaussians_mut &out, const uint8_t *keep,
+                              const uint8_t *dup, const int64_t *kpos, const int64_t *dpos, const int64_t *n_keep,
+                              const int64_t *n_dup, const int32_t *state_in, int32_t *state_src, int64_t *n_out,
+                              hipStream_t s);
+void launch_gather_rows(const as_gaussians &src, const int32_t *map, int64_t n_rows, const as_gaussians_mut &dst,
+                        hipStream_t s);
+void launch_reset_opacity(const as_gaussians_mut &g, float cap, float *m, float *v, hipStream_t s);
 
 // error statistics (errstats.hip)
 void launch_error_map(int W, int H, const float *image, const float *gt, double *err, uint64_t *minmax,
