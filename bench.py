@@ -11,7 +11,7 @@ views, top-5% candidates, adaptive split) and the CPU oracle on a bounded
 sample of the same workload.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only),
---no-cpu-baseline, --no-densify.
+--no-cpu-baseline, --no-densify, --no-training, --no-batched, --no-serve.
 """
 import argparse
 import json
@@ -48,6 +48,7 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-densify", action="store_true")
+    ap.add_argument("--no-training", action="store_true", help="skip the end-to-end densification training leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-view leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -198,10 +199,49 @@ def densify_bench(ctx):
     st = api.timing_read(ctx)
     api.timing_enable(ctx, False)
     mode = res[1].cpu().numpy()
+    # the split step of each method on the same regions (Table 2's ablation
+    # steps, the fixed-N random split with N = 2 as in 3DGS and N = 5)
+    variants = {}
+    for name, kw in (("adpsplit", {}), ("fixed_n2", dict(variant=api.VARIANT_FIXED_N, fixed_n=2)),
+                     ("fixed_n5", dict(variant=api.VARIANT_FIXED_N, fixed_n=5, noise_n=5)),
+                     ("adaptive_n", dict(variant=api.VARIANT_ADAPTIVE_N, noise_n=params.n_max)),
+                     ("child_init", dict(variant=api.VARIANT_CHILD_INIT))):
+        vp = api.SplitParams(**kw)
+        nz = noise if vp.noise_n <= 2 else torch.from_numpy(
+            np.random.default_rng(5).standard_normal((len(cand), vp.noise_n, 3)).astype(np.float32)).cuda()
+        vout = api.Gaussians.empty(n + len(cand) * max(2, vp.n_max + 1, vp.fixed_n), 3)
+        r = api.adaptive_split(ctx, g, cand_t, regions, views, attr, vp, nz, out=vout)
+        torch.cuda.synchronize()
+        tv = time.perf_counter()
+        for _ in range(reps):
+            r = api.adaptive_split(ctx, g, cand_t, regions, views, attr, vp, nz, out=vout)
+        torch.cuda.synchronize()
+        variants[name] = dict(split_ms=round((time.perf_counter() - tv) * 1e3 / reps, 3),
+                              new_rows=int(r[2].sum().item()), n_out=int(r[4].item()))
     return dict(ms=(t1 - t0) * 1e3 / reps, n=n, views=V, candidates=len(cand), regions=int(regions.count.item()),
                 new_rows=int(res[2].sum().item()), n_out=int(res[4].item()),
                 modes=dict(vanilla=int((mode == 0).sum()), reset=int((mode == 1).sum()), adaptive=int((mode == 2).sum())),
-                stage_ms={k: round(v[0] / reps, 4) for k, v in st.items() if v[1]})
+                stage_ms={k: round(v[0] / reps, 4) for k, v in st.items() if v[1]}, split_variants=variants)
+
+
+def training_bench(ctx):
+    """Synthetic end-to-end densification training (3DGS's loop with adaptive
+    density control, shortened schedule): a 200,000-Gaussian teacher rendered
+    from 48 training and 8 held-out cameras at 640x480; a student initialised
+    from 20,000 noisy teacher centres; 3000 iterations, densification every
+    100 from 300 to 2100 with the vanilla N = 2 split or AdpSplit (20 sampled
+    views).  Held-out PSNR against training time (evaluation excluded) and
+    the number of Gaussians, every 250 iterations."""
+    from paper_2605_06876_amd import train
+
+    pb = train.Problem(ctx, n_teacher=200_000, n_train=48, n_eval=8, size=(640, 480), seed=7)
+    res = train.compare(ctx, pb, iters=3000, seed=0, n_init=20_000)
+    out = dict(teacher=200_000, size="640x480", train_views=48, eval_views=8, init=20_000, iters=3000)
+    for method, r in res.items():
+        out[method] = {k: v for k, v in r.items() if k != "history"}
+        out[method]["curve"] = [[h["it"], h["train_s"], h["psnr"], h["n"]] for h in r["history"]]
+    out["curve_columns"] = ["iteration", "train_s", "psnr_db", "gaussians"]
+    return out
 
 
 C4_SIZES = [(640, 480), (800, 600), (960, 640), (1024, 768), (1256, 828), (1280, 720), (1440, 960), (1600, 1064)]
@@ -485,6 +525,9 @@ def main():
     if not args.no_densify:
         log("bench: densification step (500k Gaussians, 16 views)")
         out["densify"] = densify_bench(res["ctx"])
+    if not args.no_training:
+        log("bench: end-to-end densification training (vanilla split vs AdpSplit)")
+        out["training"] = training_bench(res["ctx"])
     if not args.no_batched:
         log("bench: batched training render (8 uneven views, 1.5M Gaussians)")
         out["batched"] = batched_bench()

@@ -335,14 +335,16 @@ as_status as_densify_select(as_ctx *ctx, const as_gaussians *g, const float *g2d
                             double grad_threshold, double size_threshold, uint8_t *clone_mask, uint8_t *is_candidate,
                             int32_t *cand, int64_t *n_cand, void *stream);
 
-/* Row map of an as_adaptive_split output: row_src[r] = the input row that
- * output row r copies (the non-removed Gaussians, in order), or -1 for the
- * rows the split created (children and parent copies).  A candidate's parent
- * is removed unless its mode is RESET (1).
+/* Row map of an as_adaptive_split output: row_src[r] = state_in[i] (or i
+ * when state_in is NULL) for the input row i that output row r copies (the
+ * non-removed Gaussians, in order), and -1 for the rows the split created
+ * (children and parent copies).  A candidate's parent is removed unless its
+ * mode is RESET (1).  state_in composes maps across successive steps.
  *   cand, mode: [n_cand] as passed to / returned by as_adaptive_split
+ *   state_in: NULL or [n]
  *   row_src: out [capacity]; rows past the survivors are -1. */
 as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t n_cand, const uint8_t *mode,
-                           int32_t *row_src, int64_t capacity, void *stream);
+                           const int32_t *state_in, int32_t *row_src, int64_t capacity, void *stream);
 
 /* Clone and prune (3DGS adaptive density control): Gaussian i is kept when
  * sigmoid(opacity_logit) >= min_opacity and, if max_scale > 0,

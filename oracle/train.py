@@ -77,16 +77,17 @@ def densify_select(g, g2d_accum, vis_count, grad_threshold, size_threshold):
     return clone, cand, np.nonzero(cand)[0].astype(np.int32)
 
 
-def split_row_map(n, cand, mode, capacity):
-    """row_src [capacity]: the surviving input rows in order, -1 after them.
-    A candidate's parent survives only when its mode is RESET (1)."""
+def split_row_map(n, cand, mode, capacity, state_in=None):
+    """row_src [capacity]: the surviving input rows in order (through
+    state_in when given), -1 after them.  A candidate's parent survives only
+    when its mode is RESET (1)."""
     removed = np.zeros(n, bool)
     for c, md in zip(np.asarray(cand), np.asarray(mode)):
         if int(md) != 1:
             removed[int(c)] = True
     surv = np.nonzero(~removed)[0]
     out = np.full(capacity, -1, np.int64)
-    out[: len(surv)] = surv
+    out[: len(surv)] = surv if state_in is None else np.asarray(state_in, np.int64)[surv]
     return out
 
 

@@ -571,12 +571,12 @@ def densify_select(ctx, g, g2d_accum, vis_count, grad_threshold, size_threshold,
     return clone[:n], is_cand[:n], cand, n_cand
 
 
-def split_row_map(ctx, n, cand, mode, capacity, stream=None):
+def split_row_map(ctx, n, cand, mode, capacity, state_in=None, stream=None):
     """as_split_row_map: row_src i32 [capacity]."""
     nc = int(cand.shape[0])
     row_src = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda")
     _check(lib().as_split_row_map(ctx.handle, ctypes.c_int64(n), _ptr(cand) if nc else None, ctypes.c_int64(nc),
-                                  _ptr(mode) if nc else None, _ptr(row_src), ctypes.c_int64(capacity),
+                                  _ptr(mode) if nc else None, _ptr(state_in), _ptr(row_src), ctypes.c_int64(capacity),
                                   _stream(stream)))
     return row_src[:capacity]
 

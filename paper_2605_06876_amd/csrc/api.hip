@@ -637,7 +637,7 @@ as_status as_densify_select(as_ctx *ctx, const as_gaussians *g, const float *g2d
 }
 
 as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t n_cand, const uint8_t *mode,
-                           int32_t *row_src, int64_t capacity, void *stream) {
+                           const int32_t *state_in, int32_t *row_src, int64_t capacity, void *stream) {
     const char *what = "as_split_row_map";
     if (!ctx || n < 0 || n_cand < 0 || capacity < n || (n_cand > 0 && (!cand || !mode)) || (capacity > 0 && !row_src)) {
         as_set_error("%s: bad argument (n %lld, candidates %lld, capacity %lld)", what, (long long)n, (long long)n_cand,
@@ -658,7 +658,7 @@ as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t 
     launch_fill_u8(keep, 1, n, s);
     launch_mark_kept(cand, n_cand, mode, n, keep, s);
     scan_u8_to_i64(keep, pos, n, (int64_t *)ctx->tr[TR_TOT].p, ctx->tr[TR_TMP].p, s);
-    launch_row_map(n, keep, pos, capacity, row_src, s);
+    launch_row_map(n, keep, pos, state_in, capacity, row_src, s);
     return launch_status(what);
 }
 

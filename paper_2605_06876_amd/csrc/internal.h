@@ -233,8 +233,8 @@ void launch_select(const as_gaussians &g, const float *accum, const int32_t *vis
                    uint8_t *clone, uint8_t *cand_flag, hipStream_t s);
 void launch_compact_ids(int64_t n, const uint8_t *flag, const int64_t *scan, int32_t *out, hipStream_t s);
 void launch_mark_kept(const int32_t *cand, int64_t n_cand, const uint8_t *mode, int64_t n, uint8_t *keep, hipStream_t s);
-void launch_row_map(int64_t n, const uint8_t *keep, const int64_t *pos, int64_t capacity, int32_t *row_src,
-                    hipStream_t s);
+void launch_row_map(int64_t n, const uint8_t *keep, const int64_t *pos, const int32_t *state_in, int64_t capacity,
+                    int32_t *row_src, hipStream_t s);
 void launch_prune_flags(const as_gaussians &g, const uint8_t *clone_mask, double min_op, double max_scale,
                         uint8_t *keep, uint8_t *dup, hipStream_t s);
 void launch_clone_prune_write(const as_gaussians &g, const as_gaussians_mut &out, const uint8_t *keep,

@@ -154,10 +154,10 @@ __global__ void __launch_bounds__(TB) k_mark_kept(const int32_t *__restrict__ ca
 }
 
 __global__ void __launch_bounds__(TB) k_row_map(int64_t n, const uint8_t *__restrict__ keep,
-                                                const int64_t *__restrict__ pos, int64_t capacity,
-                                                int32_t *__restrict__ row_src) {
+                                                const int64_t *__restrict__ pos, const int32_t *__restrict__ state_in,
+                                                int64_t capacity, int32_t *__restrict__ row_src) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (i < n && keep[i] && pos[i] < capacity) row_src[pos[i]] = (int32_t)i;
+    if (i < n && keep[i] && pos[i] < capacity) row_src[pos[i]] = state_in ? state_in[i] : (int32_t)i;
 }
 
 __global__ void __launch_bounds__(TB) k_prune_flags(int64_t n, const float *__restrict__ op,
@@ -270,10 +270,11 @@ void launch_mark_kept(const int32_t *cand, int64_t n_cand, const uint8_t *mode, 
     hipLaunchKernelGGL(k_mark_kept, dim3(blocks_for(n_cand, 1ll << 30)), dim3(TB), 0, s, cand, n_cand, mode, n, keep);
 }
 
-void launch_row_map(int64_t n, const uint8_t *keep, const int64_t *pos, int64_t capacity, int32_t *row_src,
-                    hipStream_t s) {
+void launch_row_map(int64_t n, const uint8_t *keep, const int64_t *pos, const int32_t *state_in, int64_t capacity,
+                    int32_t *row_src, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_row_map, dim3(blocks_for(n, 1ll << 30)), dim3(TB), 0, s, n, keep, pos, capacity, row_src);
+    hipLaunchKernelGGL(k_row_map, dim3(blocks_for(n, 1ll << 30)), dim3(TB), 0, s, n, keep, pos, state_in, capacity,
+                       row_src);
 }
 
 void launch_prune_flags(const as_gaussians &g, const uint8_t *clone_mask, double min_op, double max_scale,

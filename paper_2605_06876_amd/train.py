@@ -1,0 +1,235 @@
+"""Synthetic end-to-end densification training: 3DGS's optimisation loop with
+adaptive density control (Sec. 3), where the split of large high-gradient
+Gaussians is either AdpSplit (Sec. 4, the method) or the vanilla fixed-N = 2
+random split it replaces (Eq. (vanilla_split_sample)).
+
+A teacher scene (synthetic clustered Gaussians) is rendered from training and
+held-out cameras with the library; a student initialised from a sparse noisy
+subsample of the teacher's centres is trained against the training renders.
+Every step runs in the library's kernels: render, L1 loss and gradient,
+reverse pass, Adam, and at each densification interval selection, clone,
+split (for AdpSplit: V renders with error statistics, then the adaptive
+split), prune and the carry-over of the Adam moments through the row maps.
+Host code only orders the calls, reads back counts and allocates.
+
+The schedule is 3DGS's, shortened (defaults below): densify every 100
+iterations inside a window, opacity reset inside the window, the learning
+rate of the means decayed log-linearly, the gradient threshold 2e-4 of 3DGS
+(stated for NDC coordinates) converted to pixel units.  Differences from the
+reference loop, all stated in the design notes: L1 loss only (no D-SSIM), the
+full SH degree from the start, no screen-space size prune.
+"""
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import api, synth
+
+
+class TrainConfig:
+    def __init__(self, method="adpsplit", iters=3000, densify_from=300, densify_until=2100, densify_every=100,
+                 opacity_reset_every=1200, grad_threshold_ndc=2e-4, percent_dense=0.01, min_opacity=0.005,
+                 max_world_scale=0.1, views_per_split=20, split_params=None, eval_every=250, max_gaussians=2_000_000,
+                 lr_means_final=0.01, seed=0):
+        assert method in ("adpsplit", "vanilla")
+        self.method, self.iters = method, iters
+        self.densify_from, self.densify_until, self.densify_every = densify_from, densify_until, densify_every
+        self.opacity_reset_every, self.grad_threshold_ndc = opacity_reset_every, grad_threshold_ndc
+        self.percent_dense, self.min_opacity, self.max_world_scale = percent_dense, min_opacity, max_world_scale
+        self.views_per_split = views_per_split
+        self.split_params = split_params if split_params is not None else api.SplitParams()
+        self.eval_every, self.max_gaussians, self.lr_means_final, self.seed = eval_every, max_gaussians, lr_means_final, seed
+
+
+class Problem:
+    """Teacher, cameras and target images (rendered once with the library)."""
+
+    def __init__(self, ctx, n_teacher=100_000, n_train=48, n_eval=8, size=(480, 360), radius=3.0, seed=7,
+                 sh_degree=3):
+        self.ctx, self.W, self.H, self.sh_degree = ctx, size[0], size[1], sh_degree
+        self.teacher = synth.scene_clusters(n_teacher, seed, sh_degree, log_scale_mu=-4.0, log_scale_sd=0.6)
+        self.train_cams = synth.sphere_cameras(n_train, radius, [size], seed=seed)
+        self.eval_cams = synth.sphere_cameras(n_eval, radius * 1.05, [size], seed=seed + 1000)
+        # 3DGS's scene extent: 1.1 times the largest camera distance from the cameras' centre
+        centres = np.stack([-np.asarray(c.R, np.float64).T @ np.asarray(c.t, np.float64) for c in self.train_cams])
+        self.extent = 1.1 * float(np.linalg.norm(centres - centres.mean(0), axis=1).max())
+        g = api.Gaussians.from_scene(self.teacher)
+        frame = api.Frame(ctx, g.n, self.W, self.H, key_cap=32 * g.n)
+        self.train_gt = [api.render(ctx, g, c, frame).clone() for c in self.train_cams]
+        self.eval_gt = [api.render(ctx, g, c, frame).clone() for c in self.eval_cams]
+        torch.cuda.synchronize()
+        frame.close()
+
+
+def init_student(teacher, n0, seed, noise=0.01):
+    """3DGS-style initialisation from a sparse point cloud: a random subset of
+    the teacher's centres with positional noise, colours from the teacher's DC
+    term, isotropic scales from the mean squared distance to the three nearest
+    neighbours, identity rotations, opacity 0.1, higher SH zero."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(teacher.n, n0, replace=False))
+    pts = teacher.means[:, idx].T.astype(np.float64) + rng.normal(0, noise, (n0, 3))
+    d, _ = cKDTree(pts).query(pts, k=4)
+    d2 = np.maximum((d[:, 1:] ** 2).mean(1), 1e-7)
+    nk = (teacher.sh_degree + 1) ** 2
+    sh = np.zeros((nk, 3, n0), np.float32)
+    sh[0] = teacher.sh[0][:, idx] + rng.normal(0, 0.05, (3, n0))
+    f = np.float32
+    return synth.Scene(pts.T.astype(f), np.repeat(np.log(np.sqrt(d2))[None], 3, 0).astype(f),
+                       np.tile(np.array([[1], [0], [0], [0]], f), (1, n0)),
+                       np.full(n0, math.log(0.1 / 0.9), f), sh, teacher.sh_degree)
+
+
+class Trainer:
+    def __init__(self, ctx, problem, cfg, n_init=10_000):
+        self.ctx, self.pb, self.cfg = ctx, problem, cfg
+        self.rng = np.random.default_rng(cfg.seed)
+        self.g = api.Gaussians.from_scene(init_student(problem.teacher, n_init, cfg.seed))
+        self.deg = self.g.sh_degree
+        self.hp = api.AdamParams()
+        W, H = problem.W, problem.H
+        # 3DGS's threshold is on the NDC-space gradient, d/d(ndc) = (W/2, H/2) d/d(pixel)
+        self.thr = cfg.grad_threshold_ndc / (0.25 * (W + H))
+        self.image = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
+        self.frame = None
+        self._reset_state(self.g.n, fresh_moments=True)
+        self.regions = api.RegionBuffer(cfg.views_per_split * W * H // cfg.split_params.m_min // 4 + 1024)
+        self.history, self.densify_ms, self.split_counts = [], [], []
+        self.train_s, self.reset_done = 0.0, False
+
+    def _reset_state(self, n, fresh_moments=False):
+        if fresh_moments:
+            self.m = api.Gaussians.empty(n, self.deg)
+            self.v = api.Gaussians.empty(n, self.deg)
+        self.grads = api.Gaussians.empty(n, self.deg)
+        self.accum = torch.zeros(n, dtype=torch.float32, device="cuda")
+        self.vis = torch.zeros(n, dtype=torch.int32, device="cuda")
+        self._ensure_frame(n)
+
+    def _ensure_frame(self, n):
+        if self.frame is None or self.frame.n_cap < n:
+            if self.frame is not None:
+                self.frame.close()
+            self.frame = api.Frame(self.ctx, max(2 * n, 1), self.pb.W, self.pb.H, key_cap=32 * max(2 * n, 1))
+            self.dm = self.frame.device_maps()
+
+    def lr_means(self, it):
+        t = min(max(it / self.cfg.iters, 0.0), 1.0)
+        a = 1.6e-4 * self.pb.extent
+        return math.exp(math.log(a) * (1 - t) + math.log(a * self.cfg.lr_means_final) * t)
+
+    def step(self, it):
+        pb, ctx = self.pb, self.ctx
+        k = int(self.rng.integers(len(pb.train_cams)))
+        api.render(ctx, self.g, pb.train_cams[k], self.frame, image=self.image)
+        dL, _ = api.l1_loss(ctx, self.image, pb.train_gt[k])
+        api.render_backward(ctx, self.g, pb.train_cams[k], self.frame, dL, grads=self.grads, g2d_norm=self.accum,
+                            vis_count=self.vis)
+        self.hp.lr_means = self.lr_means(it)
+        api.adam_step(ctx, self.g, self.grads, self.m, self.v, self.hp, it)
+
+    def densify(self, it):
+        cfg, pb, ctx = self.cfg, self.pb, self.ctx
+        g, n = self.g, self.g.n
+        clone, is_cand, cand, n_cand = api.densify_select(ctx, g, self.accum, self.vis, self.thr,
+                                                          cfg.percent_dense * pb.extent)
+        nc = int(n_cand.item())
+        # 1. clones appended after the originals (no pruning yet): candidate ids stay valid
+        g1, st1, n1 = api.clone_prune(ctx, g, clone, None, 0.0, 0.0)
+        n1 = int(n1.item())
+        g1, st1 = g1.rows(n1), st1[:n1].contiguous()
+        # 2. split of the candidates
+        cand = cand[:nc].contiguous()
+        if nc > 0:
+            self._ensure_frame(n1)
+            noise = torch.from_numpy(synth.vanilla_noise(nc, int(self.rng.integers(1 << 30)))).cuda()
+            attr = torch.zeros(n1, dtype=torch.int32, device="cuda")
+            self.regions.count.zero_()
+            if cfg.method == "adpsplit":
+                params = cfg.split_params
+                is_cand1 = torch.zeros(n1, dtype=torch.uint8, device="cuda")
+                is_cand1[:n] = is_cand
+                views = self.rng.choice(len(pb.train_cams), min(cfg.views_per_split, len(pb.train_cams)),
+                                        replace=False)
+                for j, vi in enumerate(views):
+                    api.render(ctx, g1, pb.train_cams[vi], self.frame, gt=pb.train_gt[vi], image=self.image)
+                    api.accumulate_error_stats(ctx, pb.W, pb.H, self.dm["err"], self.dm["err_minmax"], self.dm["dom"],
+                                               pb.train_gt[vi], j, is_cand1, params, self.regions, attr)
+                cams = [pb.train_cams[vi] for vi in views]
+            else:
+                params = api.SplitParams(variant=api.VARIANT_FIXED_N, fixed_n=2)
+                cams = [pb.train_cams[0]]
+            out, mode, count, _, n2 = api.adaptive_split(ctx, g1, cand, self.regions, cams, attr, params, noise)
+            n2 = int(n2.item())
+            st2 = api.split_row_map(ctx, n1, cand, mode, out.n, state_in=st1)[:n2].contiguous()
+            g2 = out.rows(n2)
+            self.split_counts.append(int(count.sum().item()))
+        else:
+            g2, st2 = g1, st1
+        # 3. prune (the world-size test from the first opacity reset on)
+        max_scale = cfg.max_world_scale * pb.extent if self.reset_done else 0.0
+        g3, st3, n3 = api.clone_prune(ctx, g2, None, st2, cfg.min_opacity, max_scale)
+        n3 = int(n3.item())
+        self.g = g3.rows(n3)
+        st3 = st3[:n3].contiguous()
+        self.last_state_map = st3
+        # 4. Adam moments follow their rows; new rows start from zero
+        self.m = api.gather_rows(ctx, self.m, st3, n3)
+        self.v = api.gather_rows(ctx, self.v, st3, n3)
+        self._reset_state(n3)
+        return dict(it=it, n_before=n, clones=n1 - n, candidates=nc, n_after=n3)
+
+    def evaluate(self):
+        pb, ctx = self.pb, self.ctx
+        psnr = []
+        for cam, gt in zip(pb.eval_cams, pb.eval_gt):
+            api.render(ctx, self.g, cam, self.frame, image=self.image)
+            _, sums = api.l1_loss(ctx, self.image, gt, want_grad=False)
+            mse = float(sums[1].item()) / (3 * pb.W * pb.H)
+            psnr.append(-10.0 * math.log10(max(mse, 1e-12)))
+        return float(np.mean(psnr))
+
+    def run(self, log=None):
+        cfg = self.cfg
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.history.append(dict(it=0, train_s=0.0, psnr=self.evaluate(), n=self.g.n))
+        t0 = time.perf_counter()
+        for it in range(1, cfg.iters + 1):
+            self.step(it)
+            if cfg.densify_from <= it <= cfg.densify_until and it % cfg.densify_every == 0 and \
+                    self.g.n < cfg.max_gaussians:
+                td = time.perf_counter()
+                info = self.densify(it)
+                torch.cuda.synchronize()
+                self.densify_ms.append((time.perf_counter() - td) * 1e3)
+                if log:
+                    log("  it %d: %s" % (it, info))
+            if it % cfg.opacity_reset_every == 0 and it < cfg.densify_until:
+                api.reset_opacity(self.ctx, self.g, 0.01, self.m.opacity_logits, self.v.opacity_logits)
+                self.reset_done = True
+            if it % cfg.eval_every == 0 or it == cfg.iters:
+                torch.cuda.synchronize()
+                self.train_s += time.perf_counter() - t0
+                self.history.append(dict(it=it, train_s=round(self.train_s, 4), psnr=round(self.evaluate(), 4),
+                                         n=self.g.n))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+        return dict(method=cfg.method, final_psnr=self.history[-1]["psnr"], final_n=self.g.n,
+                    train_s=round(self.train_s, 4), densify_ms_mean=round(float(np.mean(self.densify_ms)), 3)
+                    if self.densify_ms else 0.0, densify_calls=len(self.densify_ms),
+                    split_rows=int(sum(self.split_counts)), history=self.history)
+
+
+def compare(ctx, problem=None, iters=3000, seed=0, n_init=10_000, log=None, **kw):
+    """Vanilla split vs AdpSplit on the same problem and initialisation."""
+    pb = problem if problem is not None else Problem(ctx)
+    out = {}
+    for method in ("vanilla", "adpsplit"):
+        tr = Trainer(ctx, pb, TrainConfig(method=method, iters=iters, seed=seed, **kw), n_init=n_init)
+        out[method] = tr.run(log=log)
+        tr.frame.close()
+    return out

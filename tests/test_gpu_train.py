@@ -151,15 +151,17 @@ def test_densify_select_empty_set(ctx):
     assert int(n_cand.item()) == 0
 
 
-@pytest.mark.parametrize("n,k", [(10, 3), (40001, 5003), (300, 0)])
-def test_split_row_map_matches_oracle(ctx, n, k):
+@pytest.mark.parametrize("n,k,compose", [(10, 3, False), (40001, 5003, True), (300, 0, False)])
+def test_split_row_map_matches_oracle(ctx, n, k, compose):
     rng = np.random.default_rng(n + k)
     cand = np.sort(rng.choice(n, k, replace=False)).astype(np.int32)
     mode = rng.integers(0, 4, k).astype(np.uint8)
+    state = rng.integers(-1, 2 * n, n).astype(np.int32) if compose else None
     cap = n + 3 * k + 7
-    rs = api.split_row_map(ctx, n, torch.from_numpy(cand).cuda(), torch.from_numpy(mode).cuda(), cap)
+    rs = api.split_row_map(ctx, n, torch.from_numpy(cand).cuda(), torch.from_numpy(mode).cuda(), cap,
+                           state_in=torch.from_numpy(state).cuda() if compose else None)
     torch.cuda.synchronize()
-    np.testing.assert_array_equal(rs.cpu().numpy(), otrain.split_row_map(n, cand, mode, cap))
+    np.testing.assert_array_equal(rs.cpu().numpy(), otrain.split_row_map(n, cand, mode, cap, state))
 
 
 def test_split_row_map_against_a_gpu_split(ctx):

@@ -108,6 +108,8 @@ def test_split_row_map_matches_the_split_oracle_rows():
 def test_split_row_map_hand_case():
     rm = otrain.split_row_map(6, np.array([1, 3, 4]), np.array([0, 1, 2]), 9)
     assert rm.tolist() == [0, 2, 3, 5, -1, -1, -1, -1, -1]
+    rm = otrain.split_row_map(6, np.array([1, 3, 4]), np.array([0, 1, 2]), 5, state_in=[7, 8, -1, 9, 10, 11])
+    assert rm.tolist() == [7, -1, 9, 11, -1]
 
 
 def test_clone_prune_hand_case():
