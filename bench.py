@@ -415,7 +415,7 @@ def load_workload_constants():
 
 
 KERNEL_SOURCES = {
-    "project": "project.hip", "scan": "binning.hip", "emit": "binning.hip", "sort": "binning.hip",
+    "project": "project.hip", "scan": "binning.hip", "emit": "binning.hip", "sort": "radix.hip",
     "ranges": "binning.hip", "blend_fwd": "blend.hip", "blend_bwd": "blend.hip", "project_bwd": "project_bwd.hip",
     "error_stats": "errstats.hip",
 }

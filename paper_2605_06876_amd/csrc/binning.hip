@@ -128,7 +128,7 @@ void scan_impl(const Tin *in, Tout *out, int64_t n, Tout *total, void *tmp, hipS
 // counts are.
 __global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *__restrict__ order, const ViewTable vt,
                                                      const short4 *__restrict__ box,
-                                                     const uint32_t *__restrict__ ntiles,
+                                                     const uint32_t *__restrict__ nt_sorted,
                                                      const uint32_t *__restrict__ offsets, int64_t key_cap,
                                                      uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     __shared__ uint32_t s_off[4][64], s_id[4][64], s_nt[4][64];
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *
     uint64_t end = 0;
     if (r < n) {
         e = order[r];
-        nt = ntiles[e];
+        nt = nt_sorted[r];   // the tiles-touched counts in depth order (read in sequence, not gathered)
         off = offsets[r];
         end = (uint64_t)off + nt;
         if (nt) {
@@ -270,11 +270,11 @@ void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint
 }
 
 void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
-                        const uint32_t *ntiles, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
+                        const uint32_t *nt_sorted, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
                         uint32_t *vals, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_emit_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order, vt,
-                       reinterpret_cast<const short4 *>(box), ntiles, offsets, key_cap, keys, vals);
+                       reinterpret_cast<const short4 *>(box), nt_sorted, offsets, key_cap, keys, vals);
 }
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,

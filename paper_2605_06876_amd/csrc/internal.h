@@ -197,7 +197,7 @@ void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint32_t *keys, ui
                         hipStream_t s);
 void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint32_t *dst, hipStream_t s);
 void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
-                        const uint32_t *ntiles, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
+                        const uint32_t *nt_sorted, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
                         uint32_t *vals, hipStream_t s);
 void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
                    hipStream_t s);
