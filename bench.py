@@ -186,6 +186,20 @@ def densify_bench(ctx):
                                        regions, attr)
         return api.adaptive_split(ctx, g, cand_t, regions, views, attr, params, noise, out=out)
 
+    # the same step with the V sampled views rendered by one batched launch
+    bframe = api.BatchFrame.for_views(ctx, n, views, key_cap=16 * n * V)
+    bimages = [torch.empty(3, H, W, dtype=torch.float32, device="cuda") for _ in views]
+
+    def densify_batched():
+        regions.count.zero_()
+        attr.zero_()
+        api.render_batch(ctx, g, views, bframe, gts=gts, images=bimages)
+        for v in range(V):
+            m = bmaps[v]
+            api.accumulate_error_stats(ctx, W, H, m["err"], m["err_minmax"], m["dom"], gts[v], v, is_cand, params,
+                                       regions, attr)
+        return api.adaptive_split(ctx, g, cand_t, regions, views, attr, params, noise, out=out)
+
     densify()
     torch.cuda.synchronize()
     api.timing_enable(ctx, True)
@@ -198,6 +212,19 @@ def densify_bench(ctx):
     t1 = time.perf_counter()
     st = api.timing_read(ctx)
     api.timing_enable(ctx, False)
+    loop_rows, loop_n = int(res[2].sum().item()), int(res[4].item())
+    api.render_batch(ctx, g, views, bframe, gts=gts, images=bimages)   # sizes the batch frame
+    bmaps = [bframe.device_maps(v) for v in range(V)]
+    rb = densify_batched()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(reps):
+        rb = densify_batched()
+    torch.cuda.synchronize()
+    batched_ms = (time.perf_counter() - tb) * 1e3 / reps
+    if int(rb[2].sum().item()) != loop_rows or int(rb[4].item()) != loop_n:
+        raise RuntimeError("bench: batched densification differs from the per-view loop")
+    bframe.close()
     mode = res[1].cpu().numpy()
     # the split step of each method on the same regions (Table 2's ablation
     # steps, the fixed-N random split with N = 2 as in 3DGS and N = 5)
@@ -218,7 +245,8 @@ def densify_bench(ctx):
         torch.cuda.synchronize()
         variants[name] = dict(split_ms=round((time.perf_counter() - tv) * 1e3 / reps, 3),
                               new_rows=int(r[2].sum().item()), n_out=int(r[4].item()))
-    return dict(ms=(t1 - t0) * 1e3 / reps, n=n, views=V, candidates=len(cand), regions=int(regions.count.item()),
+    return dict(ms=(t1 - t0) * 1e3 / reps, ms_batched_views=round(batched_ms, 3), n=n, views=V, candidates=len(cand),
+                regions=int(regions.count.item()),
                 new_rows=int(res[2].sum().item()), n_out=int(res[4].item()),
                 modes=dict(vanilla=int((mode == 0).sum()), reset=int((mode == 1).sum()), adaptive=int((mode == 2).sum())),
                 stage_ms={k: round(v[0] / reps, 4) for k, v in st.items() if v[1]}, split_variants=variants)

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libadpsplit.so")
 _lib = None
 
 AS_OK, AS_ERR_ARG, AS_ERR_CAPACITY, AS_ERR_HIP, AS_ERR_STATE = 0, 1, 2, 3, 4
+MAX_VIEWS = 16   # views of one batched render
 MODE_VANILLA, MODE_RESET, MODE_ADAPTIVE = 0, 1, 2
 
 

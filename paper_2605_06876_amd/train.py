@@ -116,6 +116,20 @@ class Trainer:
             self.frame = api.Frame(self.ctx, max(2 * n, 1), self.pb.W, self.pb.H, key_cap=32 * max(2 * n, 1))
             self.dm = self.frame.device_maps()
 
+    def _batch_frame(self, n, views):
+        """A batch frame for `views` views of n Gaussians (grown on demand)."""
+        need = n * api.MAX_VIEWS
+        if getattr(self, "bframe", None) is None or self.bframe_entries < need:
+            if getattr(self, "bframe", None) is not None:
+                self.bframe.close()
+            ent = 2 * need
+            cams = [self.pb.train_cams[0]] * api.MAX_VIEWS
+            self.bframe = api.BatchFrame.for_views(self.ctx, 2 * n, cams, key_cap=16 * ent)
+            self.bframe_entries = ent
+            self.bimages = [torch.empty(3, self.pb.H, self.pb.W, dtype=torch.float32, device="cuda")
+                            for _ in range(api.MAX_VIEWS)]
+        return self.bframe
+
     def lr_means(self, it):
         t = min(max(it / self.cfg.iters, 0.0), 1.0)
         a = 1.6e-4 * self.pb.extent
@@ -154,11 +168,17 @@ class Trainer:
                 is_cand1[:n] = is_cand
                 views = self.rng.choice(len(pb.train_cams), min(cfg.views_per_split, len(pb.train_cams)),
                                         replace=False)
-                for j, vi in enumerate(views):
-                    api.render(ctx, g1, pb.train_cams[vi], self.frame, gt=pb.train_gt[vi], image=self.image)
-                    api.accumulate_error_stats(ctx, pb.W, pb.H, self.dm["err"], self.dm["err_minmax"], self.dm["dom"],
-                                               pb.train_gt[vi], j, is_cand1, params, self.regions, attr)
                 cams = [pb.train_cams[vi] for vi in views]
+                # the sampled views in batched launches of up to 16 views each
+                for c0 in range(0, len(views), api.MAX_VIEWS):
+                    chunk = views[c0:c0 + api.MAX_VIEWS]
+                    bf = self._batch_frame(n1, len(chunk))
+                    api.render_batch(ctx, g1, [pb.train_cams[vi] for vi in chunk], bf,
+                                     gts=[pb.train_gt[vi] for vi in chunk], images=self.bimages[:len(chunk)])
+                    for j, vi in enumerate(chunk):
+                        m = bf.device_maps(j)
+                        api.accumulate_error_stats(ctx, pb.W, pb.H, m["err"], m["err_minmax"], m["dom"],
+                                                   pb.train_gt[vi], c0 + j, is_cand1, params, self.regions, attr)
             else:
                 params = api.SplitParams(variant=api.VARIANT_FIXED_N, fixed_n=2)
                 cams = [pb.train_cams[0]]
@@ -232,4 +252,6 @@ def compare(ctx, problem=None, iters=3000, seed=0, n_init=10_000, log=None, **kw
         tr = Trainer(ctx, pb, TrainConfig(method=method, iters=iters, seed=seed, **kw), n_init=n_init)
         out[method] = tr.run(log=log)
         tr.frame.close()
+        if getattr(tr, "bframe", None) is not None:
+            tr.bframe.close()
     return out
