@@ -8,12 +8,14 @@
 // -ffp-contract=off.  Connected components use a lock-free union-find whose
 // roots are always the smallest pixel index of their component, so labels are
 // canonical and independent of thread scheduling: first inside 16x16 tiles in
-// LDS (fused with the erosion), then across tile borders in global memory.
+// LDS (fused with the classification and the erosion), then across tile
+// borders in global memory.  Kept regions take their record slots from per-block
+// counts scanned by one block, so records stay in ascending label order.
 #include "internal.h"
 
 namespace {
 
-enum { ES_M, ES_B, ES_LABEL, ES_MOM, ES_KEEP, ES_KIDX, ES_SCAN, ES_TOT };
+enum { ES_B, ES_LABEL, ES_MOM, ES_KEEP, ES_KIDX };
 
 __device__ __forceinline__ double dev_bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
@@ -53,39 +55,18 @@ __global__ void __launch_bounds__(256) k_error_map(int W, int H, const float *__
     }
 }
 
-// E, M, B and the pre-erosion attribution count.
-__global__ void k_classify(int64_t P, const double *__restrict__ err, const unsigned long long *__restrict__ minmax,
-                           const int32_t *__restrict__ dom, const uint8_t *__restrict__ is_cand, double tau, int L,
-                           uint8_t *__restrict__ M, uint8_t *__restrict__ B, int32_t *__restrict__ attr) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool hit = false;
-    int32_t d = -1;
-    if (u < P) {
-        const double emin = dev_bits_to_double(minmax[0]), emax = dev_bits_to_double(minmax[1]);
-        const double E = (emax == emin) ? 0.0 : (err[u] - emin) / (emax - emin);
-        const bool m = E > tau;
-        uint8_t b = 0;
-        if (m) {
-            double bb = floor(((E - tau) * (double)L) / (1.0 - tau));
-            if (bb > (double)(L - 1)) bb = (double)(L - 1);
-            b = (uint8_t)bb;
-        }
-        M[u] = m;
-        B[u] = b;
-        d = dom[u];
-        hit = m && d >= 0 && is_cand[d];
+// E = normalised error (Eq. (l1map)), M = [E > tau], band B = floor((E - tau) L / (1 - tau)) clamped to L - 1
+__device__ __forceinline__ bool classify_px(double e, double emin, double emax, double tau, int L, uint8_t *band) {
+    const double E = (emax == emin) ? 0.0 : (e - emin) / (emax - emin);
+    const bool m = E > tau;
+    uint8_t b = 0;
+    if (m) {
+        double bb = floor(((E - tau) * (double)L) / (1.0 - tau));
+        if (bb > (double)(L - 1)) bb = (double)(L - 1);
+        b = (uint8_t)bb;
     }
-    // attr[d] += 1 per hit; one atomic per wave when all hits share d
-    const uint64_t hits = __ballot(hit);
-    if (!hits) return;
-    const int leader = __ffsll((unsigned long long)hits) - 1;
-    const int32_t d0 = __shfl(d, leader, 64);
-    const uint64_t same = __ballot(hit && d == d0);
-    if (same == hits) {
-        if ((int)__lane_id() == leader) atomicAdd(&attr[d0], (int32_t)__popcll(hits));
-    } else if (hit) {
-        atomicAdd(&attr[d], 1);
-    }
+    *band = b;
+    return m;
 }
 
 __device__ __forceinline__ int32_t uf_load(const int32_t *L, int32_t x) {
@@ -156,10 +137,12 @@ constexpr int ES = ET + 2 * EMAX_R;
 // also the smallest image index of the tile's part of the component.  Writes
 // label = image index of that root (-1 inactive).
 __global__ void __launch_bounds__(ET * ET) k_erode_ccl_local(int W, int H, int tiles_x, int r, int lo, int hi,
-                                                             const uint8_t *__restrict__ M,
-                                                             const int32_t *__restrict__ dom,
-                                                             const uint8_t *__restrict__ B,
+                                                             const double *__restrict__ err,
+                                                             const unsigned long long *__restrict__ minmax, double tau,
+                                                             int L, const int32_t *__restrict__ dom,
+                                                             uint8_t *__restrict__ B,
                                                              const uint8_t *__restrict__ is_cand,
+                                                             int32_t *__restrict__ attr,
                                                              int32_t *__restrict__ label) {
     __shared__ uint8_t s_m[ES * ES];
     __shared__ uint8_t s_row[ES * ET];
@@ -172,12 +155,37 @@ __global__ void __launch_bounds__(ET * ET) k_erode_ccl_local(int W, int H, int t
     const int lx = tid % ET, ly = tid / ET, x = ox + lx, y = oy + ly;
     const bool inside = x < W && y < H;
     const int64_t u = (int64_t)y * W + x;
+    const double emin = dev_bits_to_double(minmax[0]), emax = dev_bits_to_double(minmax[1]);
+    uint8_t scratch_band;
+    // this pixel's class and band (written for the later passes), and the
+    // attribution count before erosion: attr[D] += 1 per high-error pixel
+    // dominated by a candidate, one atomic per wave when all hits share D
+    uint8_t b = 0;
+    const bool m_own = inside && classify_px(err[u], emin, emax, tau, L, &b);
+    if (inside) B[u] = b;
+    const int32_t d = inside ? dom[u] : -1;
+    {
+        const bool hit = m_own && d >= 0 && is_cand[d];
+        const uint64_t hits = __ballot(hit);
+        if (hits) {
+            const int leader = __ffsll((unsigned long long)hits) - 1;
+            const int32_t d0 = __shfl(d, leader, 64);
+            const uint64_t same = __ballot(hit && d == d0);
+            if (same == hits) {
+                if ((int)__lane_id() == leader) atomicAdd(&attr[d0], (int32_t)__popcll(hits));
+            } else if (hit) {
+                atomicAdd(&attr[d], 1);
+            }
+        }
+    }
     bool e;
     if (r <= EMAX_R) {   // lo, hi <= r
         const int S = ET + lo + hi;
         for (int i = tid; i < S * S; i += ET * ET) {
             const int hx = i % S, hy = i / S, gx = ox + hx - lo, gy = oy + hy - lo;
-            s_m[i] = (gx < 0 || gy < 0 || gx >= W || gy >= H) ? 1 : M[(int64_t)gy * W + gx];
+            s_m[i] = (gx < 0 || gy < 0 || gx >= W || gy >= H)
+                         ? 1
+                         : classify_px(err[(int64_t)gy * W + gx], emin, emax, tau, L, &scratch_band);
         }
         __syncthreads();
         for (int i = tid; i < S * ET; i += ET * ET) {   // AND along rows
@@ -191,23 +199,21 @@ __global__ void __launch_bounds__(ET * ET) k_erode_ccl_local(int W, int H, int t
         for (int k = 0; k <= lo + hi; k++) a &= s_row[(ly + k) * ET + lx];
         e = a != 0;
     } else {
-        e = inside && M[u] != 0;
+        e = m_own;
         for (int dy = -lo; dy <= hi && e; dy++) {
             const int yy = y + dy;
             if (yy < 0 || yy >= H) continue;
             for (int dx = -lo; dx <= hi; dx++) {
                 const int xx = x + dx;
                 if (xx < 0 || xx >= W) continue;
-                if (!M[(int64_t)yy * W + xx]) {
+                if (!classify_px(err[(int64_t)yy * W + xx], emin, emax, tau, L, &scratch_band)) {
                     e = false;
                     break;
                 }
             }
         }
     }
-    const int32_t d = inside ? dom[u] : -1;
     const bool active = inside && e && d >= 0 && is_cand[d];
-    const uint8_t b = inside ? B[u] : 0;
     s_par[tid] = active ? tid : -1;
     s_dom[tid] = d;
     s_b[tid] = b;
@@ -307,11 +313,46 @@ __global__ void k_moments(int W, int H, const int32_t *__restrict__ label, unsig
 }
 
 // A component is kept (Eq. (min_region_area)) at its root pixel.
-__global__ void k_region_keep(int64_t P, const int32_t *__restrict__ label, const unsigned long long *__restrict__ mom,
-                              int m_min, uint8_t *__restrict__ keep) {
+// Kept components (roots with area >= m_min) and the number per block of 256
+// pixels.
+__global__ void __launch_bounds__(256) k_region_keep(int64_t P, const int32_t *__restrict__ label,
+                                                     const unsigned long long *__restrict__ mom, int m_min,
+                                                     uint8_t *__restrict__ keep, int64_t *__restrict__ part) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= P) return;
-    keep[u] = label[u] == (int32_t)u && (int64_t)mom[u * 6] >= (int64_t)m_min;
+    const bool k = u < P && label[u] == (int32_t)u && (int64_t)mom[u * 6] >= (int64_t)m_min;
+    if (u < P) keep[u] = k;
+    const int c = __syncthreads_count(k);
+    if (threadIdx.x == 0) part[blockIdx.x] = c;
+}
+
+// One block: the per-block counts become the first record slot of each
+// block (after the records already in the buffer), and the buffer's count
+// advances by the total.
+__global__ void __launch_bounds__(1024) k_region_slots(int64_t *__restrict__ part, int64_t nblk,
+                                                       int64_t *__restrict__ count) {
+    __shared__ int64_t s_w[16];
+    __shared__ int64_t s_carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_carry = *count;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nblk; b0 += 1024) {
+        const int64_t b = b0 + tid;
+        const int64_t v = b < nblk ? part[b] : 0;
+        int64_t inc = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) s_w[w] = inc;
+        __syncthreads();
+        int64_t pre = s_carry;
+        for (int k = 0; k < w; k++) pre += s_w[k];
+        if (b < nblk) part[b] = pre + inc - v;
+        __syncthreads();
+        if (tid == 1023) s_carry = pre + inc;
+        __syncthreads();
+    }
+    if (tid == 0) *count = s_carry;
 }
 
 __device__ __forceinline__ double central_moment(int64_t A, int64_t sab, int64_t sa, int64_t sb) {
@@ -323,17 +364,25 @@ __device__ __forceinline__ double central_moment(int64_t A, int64_t sab, int64_t
     return dnum / (dA * dA);
 }
 
-// One record per kept component, in ascending label order (kidx is the
-// exclusive scan of keep over the pixels).
-__global__ void k_region_emit(int W, int H, int view, const unsigned long long *__restrict__ mom,
-                              const uint8_t *__restrict__ keep, const int64_t *__restrict__ kidx,
-                              const int32_t *__restrict__ dom, const uint8_t *__restrict__ B,
-                              const float *__restrict__ gt, as_region *__restrict__ out, int64_t out_cap,
-                              const int64_t *__restrict__ count) {
+// One record per kept component, in ascending label order: a block's first
+// slot (k_region_slots) plus the kept pixels before this one in the block.
+__global__ void __launch_bounds__(256) k_region_emit(int W, int H, int view, const unsigned long long *__restrict__ mom,
+                                                     const uint8_t *__restrict__ keep, const int64_t *__restrict__ slot,
+                                                     const int32_t *__restrict__ dom, const uint8_t *__restrict__ B,
+                                                     const float *__restrict__ gt, as_region *__restrict__ out,
+                                                     int64_t out_cap) {
+    __shared__ int s_w[4];
     const int64_t P = (int64_t)W * H;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= P || !keep[s]) return;
-    const int64_t pos = *count + kidx[s];
+    const bool k = s < P && keep[s];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t bal = __ballot(k);
+    if (lane == 0) s_w[w] = __popcll(bal);
+    __syncthreads();
+    int before = __popcll(bal & ((1ull << lane) - 1ull));
+    for (int q = 0; q < w; q++) before += s_w[q];
+    if (!k) return;
+    const int64_t pos = slot[blockIdx.x] + before;
     if (pos >= out_cap) return;
     as_region r;
     const int32_t root = (int32_t)s;
@@ -387,7 +436,6 @@ __global__ void k_region_emit(int W, int H, int view, const unsigned long long *
     out[pos] = r;
 }
 
-__global__ void k_count_add(int64_t *count, const int64_t *__restrict__ kept) { *count += *kept; }
 
 }  // namespace
 
@@ -410,36 +458,35 @@ as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const ui
     if (P == 0) return AS_OK;
     hipError_t e = hipSuccess;
     DevBuf *es = ctx->es;
-    if ((e = devbuf_ensure(es[ES_M], P)) != hipSuccess || (e = devbuf_ensure(es[ES_B], P)) != hipSuccess ||
+    if ((e = devbuf_ensure(es[ES_B], P)) != hipSuccess ||
         (e = devbuf_ensure(es[ES_LABEL], P * 4)) != hipSuccess ||
         (e = devbuf_ensure(es[ES_MOM], P * 48)) != hipSuccess || (e = devbuf_ensure(es[ES_KEEP], P)) != hipSuccess ||
-        (e = devbuf_ensure(es[ES_KIDX], P * 8)) != hipSuccess ||
-        (e = devbuf_ensure(es[ES_SCAN], scan_tmp_bytes(P))) != hipSuccess ||
-        (e = devbuf_ensure(es[ES_TOT], 64)) != hipSuccess) {
+        (e = devbuf_ensure(es[ES_KIDX], (size_t)((P + 255) / 256) * 8)) != hipSuccess) {
         as_set_error("error-stats scratch allocation failed: %s", hipGetErrorString(e));
         return AS_ERR_HIP;
     }
-    uint8_t *M = (uint8_t *)es[ES_M].p, *B = (uint8_t *)es[ES_B].p;
+    uint8_t *B = (uint8_t *)es[ES_B].p;
     uint8_t *keep = (uint8_t *)es[ES_KEEP].p;
     int32_t *label = (int32_t *)es[ES_LABEL].p;
-    int64_t *kidx = (int64_t *)es[ES_KIDX].p, *tot = (int64_t *)es[ES_TOT].p;
+    int64_t *kidx = (int64_t *)es[ES_KIDX].p;   // per block of 256 pixels: kept roots, then first record slot
     unsigned long long *mom = (unsigned long long *)es[ES_MOM].p;
     const unsigned grid = (unsigned)((P + 255) / 256);
     const int tiles_x = (W + ET - 1) / ET, tiles = tiles_x * ((H + ET - 1) / ET);
-    hipLaunchKernelGGL(k_classify, dim3(grid), dim3(256), 0, s, P, err,
-                       reinterpret_cast<const unsigned long long *>(minmax), dom, is_cand, p.tau_l1, p.L, M, B, attr);
+
     // element offsets: [-r, r] per axis, or a side of r + 1 (flag)
     const int lo = (p.flags & AS_SPLIT_ERODE_SIDE) ? p.r_erode / 2 : p.r_erode;
     const int hi = (p.flags & AS_SPLIT_ERODE_SIDE) ? p.r_erode - p.r_erode / 2 : p.r_erode;
-    hipLaunchKernelGGL(k_erode_ccl_local, dim3(tiles), dim3(ET * ET), 0, s, W, H, tiles_x, p.r_erode, lo, hi, M, dom,
-                       B, is_cand, label);
+    // classification, attribution, erosion and the tile-local components in one pass
+    hipLaunchKernelGGL(k_erode_ccl_local, dim3(tiles), dim3(ET * ET), 0, s, W, H, tiles_x, p.r_erode, lo, hi, err,
+                       reinterpret_cast<const unsigned long long *>(minmax), p.tau_l1, p.L, dom, B, is_cand, attr,
+                       label);
     hipLaunchKernelGGL(k_ccl_border, dim3(grid), dim3(256), 0, s, W, H, dom, B, label);
     hipLaunchKernelGGL(k_ccl_flatten, dim3(grid), dim3(256), 0, s, P, label, mom);
     hipLaunchKernelGGL(k_moments, dim3(grid), dim3(256), 0, s, W, H, label, mom);
-    hipLaunchKernelGGL(k_region_keep, dim3(grid), dim3(256), 0, s, P, label, mom, p.m_min, keep);
-    scan_u8_to_i64(keep, kidx, P, tot, es[ES_SCAN].p, s);
+    // kept roots, one record slot per block (advancing the buffer's count), records
+    hipLaunchKernelGGL(k_region_keep, dim3(grid), dim3(256), 0, s, P, label, mom, p.m_min, keep, kidx);
+    hipLaunchKernelGGL(k_region_slots, dim3(1), dim3(1024), 0, s, kidx, (int64_t)grid, rb.count);
     hipLaunchKernelGGL(k_region_emit, dim3(grid), dim3(256), 0, s, W, H, view, mom, keep, kidx, dom, B, gt,
-                       rb.records, rb.capacity, rb.count);
-    hipLaunchKernelGGL(k_count_add, dim3(1), dim3(1), 0, s, rb.count, tot);
+                       rb.records, rb.capacity);
     return AS_OK;
 }
