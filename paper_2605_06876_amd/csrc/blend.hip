@@ -354,14 +354,17 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
 
 // Reverse pass.  For contributor k of a pixel with alpha a_k and transmittance
 // T_k in front of it, dC/dc_k = a_k T_k and
-//   dC/da_k = T_k (c_k - A_k) - T_final bg / (1 - a_k),
-// where A_k is the colour composited behind k normalised by T_{k+1}; walking
-// the list backwards from the last contributor restores T_k = T_{k+1}/(1-a_k)
-// and A_k incrementally.  Gradients reach (o, conic, mean) only where
-// alpha = o G is below the 0.99 clamp.  Each row sums its 16 pixels' nine
-// gradients of a Gaussian with DPP, lane 15 adds them into the batch slot of
-// that Gaussian in LDS, and after the batch one pass issues the global
-// atomics: one set per (Gaussian, tile).
+//   dL/da_k = T_k (c_k . dL) - B_k / (1 - a_k),
+// where B_k = sum over the contributors j behind k of (c_j . dL) a_j T_j plus
+// (bg . dL) T_final; walking the list backwards from the last contributor
+// restores T_k = T_{k+1}/(1-a_k) and B_k incrementally.  Gradients reach
+// (o, conic, mean) only where alpha = o G is below the 0.99 clamp.  Each row
+// sums over its 16 pixels, with DPP, the colour gradients and the moments
+// dp, dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2 of dp = dL/dp (p the Gaussian's
+// exponent) for the Gaussian it visits; lane 15 adds them into the batch slot
+// of that Gaussian in LDS, and after the batch one pass turns the moments into
+// mean, conic and opacity gradients and issues the global atomics: one set
+// per (Gaussian, tile).
 template <int BATCH, bool PERSIST>
 __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restrict__ ranges,
                                                         const uint32_t *__restrict__ tile_order,
@@ -425,7 +428,9 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
         uint32_t wlast = has ? lastp + 1 : 0;
         for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
 
-        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, last_alpha = 0.f, lc0 = 0.f, lc1 = 0.f, lc2 = 0.f;
+        // Bb = bg.dL T_final + sum over the contributors behind the current
+        // one of (c_j . dL) alpha_j T_j: the colour behind, in absolute terms
+        float Bb = Tfin * bgdot;
 
         // batches [b0, b1) walk the list backwards from hi_end
         Fetched nf[R];
@@ -451,6 +456,7 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
             // own count idle
             int nmax = nh;
             for (int o = 16; o < 64; o <<= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
+            nmax = __builtin_amdgcn_readfirstlane(nmax);   // wave-uniform: scalar loop control
             int jn = hits[nmax > 0 ? nmax - 1 : 0];   // one index ahead, as in the forward loop
             for (int h = nmax - 1; h >= 0; h--) {
                 const bool valid = h < nh;
@@ -464,58 +470,54 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
                 const float alpha = fminf(ALPHA_MAX, araw);
                 const bool contrib = valid && has && gidx <= lastp && (m & lg.pbits) == lg.pbits &&
                                      alpha >= ALPHA_MIN;
-                float g[9];
-#pragma unroll
-                for (int k = 0; k < 9; k++) g[k] = 0.f;
-                if (contrib) {
-                    const float om = 1.0f - alpha;
-                    const float rom = __builtin_amdgcn_rcpf(om);
-                    T = T * rom;
-                    const float wgt = alpha * T;
-                    const float c0 = q1.z, c1 = q1.w, c2 = q2.x;
-                    acc0 = last_alpha * lc0 + (1.0f - last_alpha) * acc0;
-                    acc1 = last_alpha * lc1 + (1.0f - last_alpha) * acc1;
-                    acc2 = last_alpha * lc2 + (1.0f - last_alpha) * acc2;
-                    lc0 = c0; lc1 = c1; lc2 = c2;
-                    float dLda = (c0 - acc0) * dL0 + (c1 - acc1) * dL1 + (c2 - acc2) * dL2;
-                    dLda *= T;
-                    last_alpha = alpha;
-                    dLda += (-Tfin * rom) * bgdot;
-                    g[6] = wgt * dL0;
-                    g[7] = wgt * dL1;
-                    g[8] = wgt * dL2;
-                    if (araw < ALPHA_MAX) {
-                        // alpha = o exp(p): dalpha/do = alpha/o, dalpha/dp = alpha;
-                        // p = -(a dx^2 + c dy^2)/2 - b dx dy with the unscaled conic
-                        const float dp = dLda * araw;
-                        g[5] = dp * q2.w;   // q2.w = 1/o
-                        const float a = -2.0f * LN2 * q0.z, b = -LN2 * q0.w, c = -2.0f * LN2 * q1.x;
-                        g[0] = dp * (-(a * dx + b * dy));
-                        g[1] = dp * (-(c * dy + b * dx));
-                        g[2] = dp * (-0.5f * dx * dx);
-                        g[3] = dp * (-dx * dy);
-                        g[4] = dp * (-0.5f * dy * dy);
-                    }
-                }
                 const uint64_t cb = __ballot(contrib);
-                if (cb) {
+                if (!cb) continue;
+                // Every lane evaluates the step; a non-contributor's weight and
+                // dp are zero, so its sums and state stay unchanged.
+                const float rom = __builtin_amdgcn_rcpf(1.0f - alpha);
+                const float Tk = T * rom;
+                T = contrib ? Tk : T;
+                const float cdl = q1.z * dL0 + q1.w * dL1 + q2.x * dL2;
+                const float wgt = contrib ? alpha * Tk : 0.0f;
+                // dL/dalpha_k = T_k (c_k . dL) - Bb / (1 - alpha_k)
+                const float dLda = Tk * cdl - Bb * rom;
+                Bb += wgt * cdl;
+                // alpha = o exp(p): dalpha/dp = alpha below the clamp; the sums
+                // of dp and of dp times the pixel offsets become the mean,
+                // conic and opacity gradients when the batch is flushed
+                const float dp = (contrib && araw < ALPHA_MAX) ? dLda * araw : 0.0f;
+                const float dpx = dp * dx, dpy = dp * dy;
+                float g[9] = {dp, dpx, dpy, dpx * dx, dpx * dy, dpy * dy, wgt * dL0, wgt * dL1, wgt * dL2};
 #pragma unroll
-                    for (int k = 0; k < 9; k++) g[k] = row_sum(g[k]);
-                    if ((lane & 15) == 15 && ((cb >> (lg.row * 16)) & 0xFFFFull)) {
+                for (int k = 0; k < 9; k++) {
+                    g[k] = row_sum(g[k]);
+                    // keeps each sum's last DPP add in this block: sunk into
+                    // the branch below it would split into a move and an add
+                    asm volatile("" : "+v"(g[k]));
+                }
+                if ((lane & 15) == 15 && ((cb >> (lg.row * 16)) & 0xFFFFull)) {
 #pragma unroll
-                        for (int k = 0; k < 9; k++) atomicAdd(&s_gacc[k][j], g[k]);
-                        s_gflag[j] = 1;
-                    }
+                    for (int k = 0; k < 9; k++) atomicAdd(&s_gacc[k][j], g[k]);
+                    s_gflag[j] = 1;
                 }
             }
             __syncthreads();
-            // one set of global atomics per entry of the batch that received gradients
+            // One set of global atomics per entry of the batch that received
+            // gradients.  With the pixel offsets dx = mean - pixel and
+            // p = -(a dx^2 + c dy^2)/2 - b dx dy (unscaled conic a, b, c):
+            // dp/dmean = -(a dx + b dy, c dy + b dx), dp/d(a, b, c) =
+            // -(dx^2/2, dx dy, dy^2/2) and dalpha/do = alpha/o.
             for (int i = tid; i < (int)(b1 - b0); i += AS_BLOCK) {
                 if (s_gflag[i]) {
-                    const int64_t id = (int64_t)__float_as_uint(sh.rec[i].ex.z);
+                    const float4 q0 = sh.rec[i].mc, q1 = sh.rec[i].cc, q2 = sh.rec[i].ex;
+                    const int64_t id = (int64_t)__float_as_uint(q2.z);
+                    const float a = -2.0f * LN2 * q0.z, b = -LN2 * q0.w, c = -2.0f * LN2 * q1.x;
+                    const float s0 = s_gacc[0][i], sx = s_gacc[1][i], sy = s_gacc[2][i];
+                    const float gv[9] = {-(a * sx + b * sy), -(c * sy + b * sx), -0.5f * s_gacc[3][i], -s_gacc[4][i],
+                                         -0.5f * s_gacc[5][i], s0 * q2.w, s_gacc[6][i], s_gacc[7][i], s_gacc[8][i]};
 #pragma unroll
                     for (int k = 0; k < 9; k++) {
-                        atomicAdd(&grad2d[k * stride + id], s_gacc[k][i]);
+                        atomicAdd(&grad2d[k * stride + id], gv[k]);
                         s_gacc[k][i] = 0.f;
                     }
                     s_gflag[i] = 0;
