@@ -227,7 +227,7 @@ void as_frame_destroy(as_frame *f) {
     void *ptrs[] = {f->rec, f->depth_key, f->box, f->ntiles, f->offsets, f->grad2d, f->ranges, f->n_keys,
                     f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax, f->tile_err, f->dkeys[0], f->dkeys[1],
                     f->dvals[0], f->dvals[1], f->nt_sorted, f->n_ent, f->tile_order, f->tile_work, f->tile_order_bwd,
-                    f->queue};
+                    f->queue, f->tile_hi, f->ckpt, f->bwd_items, f->n_items};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_keys(f);
@@ -258,6 +258,8 @@ static as_status frame_alloc(as_ctx *ctx, int32_t max_views, int64_t ent_cap, in
         (e = dmalloc(&f->ranges, tile_cap * 2)) != hipSuccess || (e = dmalloc(&f->n_keys, 4)) != hipSuccess ||
         (e = dmalloc(&f->tile_order, tile_cap)) != hipSuccess || (e = dmalloc(&f->queue, 2)) != hipSuccess ||
         (e = dmalloc(&f->tile_work, tile_cap)) != hipSuccess || (e = dmalloc(&f->tile_order_bwd, tile_cap)) != hipSuccess ||
+        (e = dmalloc(&f->tile_hi, tile_cap)) != hipSuccess || (e = dmalloc(&f->n_items, 1)) != hipSuccess ||
+        (e = dmalloc(&f->bwd_items, tile_cap * (AS_CK_MAX + 1) * 2)) != hipSuccess ||
         (e = dmalloc(&f->t_final, pix_cap)) != hipSuccess || (e = dmalloc(&f->last, pix_cap)) != hipSuccess ||
         (e = dmalloc(&f->n_contrib, pix_cap)) != hipSuccess || (e = dmalloc(&f->dom, pix_cap)) != hipSuccess ||
         (e = dmalloc(&f->err, pix_cap)) != hipSuccess || (e = dmalloc(&f->err_minmax, 2 * max_views)) != hipSuccess ||
@@ -474,10 +476,12 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
     {
         StageTimer t(ctx, AS_STAGE_BLEND_FWD, s);
+        f->ck_written = f->ckpt != nullptr;
+        f->ck_seg = blend_fwd_batch(bl);
         launch_blend_fwd(f, f->vals[sel], f->use_order ? f->tile_order : nullptr, bl, vt, gi, im, s);
         // the reverse pass's cost per tile follows its contributors, which only
         // the forward pass knows: order the reverse dispatch by them
-        if (f->use_order) launch_tile_order_work(f->tile_work, (int)tiles, f->tile_order_bwd, s);
+        launch_after_fwd(f, vt, gi, f->use_order, s);
     }
     const as_status st = launch_status("as_render");
     if (st != AS_OK) return st;
@@ -523,6 +527,15 @@ as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame 
     for (int v = 0; v < vt.n_views; v++) dl.p[v] = dL_dimages[v];
     const int64_t ents = vt.ent_base[vt.n_views];
     const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
+    // The forward writes checkpoints once their buffer exists; the first
+    // reverse pass allocates it (a failed allocation only costs speed: the
+    // reverse pass then walks each tile in one piece).
+    if (!f->ckpt) {
+        if (dmalloc(&f->ckpt, f->tile_cap * AS_CK_MAX * 256 * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            f->ckpt = nullptr;
+        }
+    }
     {
         StageTimer t(ctx, AS_STAGE_BLEND_BWD, s);
         launch_fill_rows_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9, ents, f->ent_cap, s);

@@ -114,17 +114,15 @@ __device__ __forceinline__ LaneGeom lane_geom(int tid) {
 }
 
 // For each row of this wave, the indices j < cnt (ascending) of the staged
-// records whose box meets the row's 4x4 block, into hits[row][..]; returns
-// this lane's row count.  `ok(j)` adds a condition that is the same for the
-// whole wave.
+// records whose box meets the row's pixel block, into hits[row][..]; returns
+// this lane's row count.  Row r of the wave covers tile columns 4r .. 4r+3;
+// `by` holds the box-mask bits of the tile rows the wave covers.  `ok(j)`
+// adds a condition that is the same for the whole wave.
 template <int BATCH, typename Ok>
-__device__ __forceinline__ int compact_rows(const StagedRec *s_rec, int cnt, HitT<BATCH> (*hits)[BATCH + 4], int w,
-                                            int row, Ok ok) {
+__device__ __forceinline__ int compact_rows(const StagedRec *s_rec, int cnt, HitT<BATCH> (*hits)[BATCH + 4],
+                                            uint32_t by, int row, Ok ok) {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lanemask_lt();
-    // the four blocks of wave w: sb = 4w + r -> sbx = r (w even: blocks 0-3 of a block row)
-    const int sby = w;   // sb = 4 w + r -> sby = w, sbx = r
-    const uint32_t by = (0xFu << (sby * 4)) << 16;
     int n[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < BATCH / 64; k++) {
@@ -190,13 +188,14 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                                                         uint32_t *__restrict__ ncontrib_out,
                                                         int32_t *__restrict__ dom_out, double *__restrict__ err,
                                                         unsigned long long *__restrict__ tile_err,
-                                                        uint32_t *__restrict__ tile_work, uint32_t *queue,
-                                                        int n_tiles) {
+                                                        uint32_t *__restrict__ tile_work,
+                                                        uint32_t *__restrict__ tile_hi, float4 *__restrict__ ckpt,
+                                                        uint32_t *queue, int n_tiles) {
     constexpr int R = BATCH / AS_BLOCK;
     __shared__ BlendShared<BATCH> sh;
     __shared__ uint32_t s_next;
     __shared__ unsigned long long s_emin[AS_BLOCK / 64], s_emax[AS_BLOCK / 64];
-    __shared__ uint32_t s_nc[AS_BLOCK / 64];
+    __shared__ uint32_t s_nc[AS_BLOCK / 64], s_hi[AS_BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const LaneGeom lg = lane_geom(tid);
     const HitT<BATCH> *hits = sh.hits[w][lg.row];
@@ -217,6 +216,11 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
         int32_t dom = -1;
         uint32_t last = 0, nc = 0;
         int done = inside ? 0 : 1;
+        // checkpoint slots of this pixel: (T, colour composited so far) at
+        // the top of batches 1 .. AS_CK_MAX; the epilogue turns the colour
+        // into the colour behind the boundary
+        float4 *ck = ckpt ? ckpt + (size_t)tile * AS_CK_MAX * 256 + lg.ly * 16 + lg.lx : nullptr;
+        int nck = 0;
 
         Fetched nf[R];
 #pragma unroll
@@ -224,6 +228,10 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
             if (start + k * AS_BLOCK + tid < end) fetch(vals, rec, box, start + k * AS_BLOCK + tid, nf[k]);
         for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
             if (__syncthreads_count(done) == AS_BLOCK) break;   // also: the previous batch is consumed
+            if (ck && b0 > start && nck < AS_CK_MAX) {
+                if (inside) ck[nck * 256] = make_float4(T, C0, C1, C2);
+                nck++;
+            }
 #pragma unroll
             for (int k = 0; k < R; k++) {
                 const int t = k * AS_BLOCK + tid;
@@ -233,7 +241,8 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
             __syncthreads();
             if (__ballot(!done) == 0) continue;                 // the whole wave has saturated
             const int cnt = (int)min((uint32_t)BATCH, end - b0);
-            const int nh = compact_rows<BATCH>(sh.rec, cnt, sh.hits[w], w, lg.row, [](int) { return true; });
+            const int nh = compact_rows<BATCH>(sh.rec, cnt, sh.hits[w], (0xFu << (w * 4)) << 16, lg.row,
+                                               [](int) { return true; });
             if (done) continue;
             // Two hits per step: both records' loads and alpha evaluations are
             // independent and overlap; only the compositing is sequential.
@@ -307,6 +316,10 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
             t_final[pix] = T;
             last_out[pix] = last;
             ncontrib_out[pix] = nc;
+            for (int k = 0; k < nck; k++) {
+                const float4 c = ck[k * 256];
+                ck[k * 256] = make_float4(c.x, C0 - c.y, C1 - c.z, C2 - c.w);
+            }
             dom_out[pix] = dom < 0 ? -1 : dom - (int32_t)vt.ent_base[v];
             if (gt) {
                 const double d0 = fabs((double)r0 - (double)gt[pl]);
@@ -322,7 +335,11 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
         // view serialise at the memory side and stall every block's gathers.
         // e >= 0, so the IEEE bit patterns order like the values.
         uint32_t ncs = inside ? nc : 0u;
-        for (int o = 32; o > 0; o >>= 1) ncs += (uint32_t)__shfl_xor((int)ncs, o, 64);
+        uint32_t hi = inside && nc ? last + 1 : 0u;
+        for (int o = 32; o > 0; o >>= 1) {
+            ncs += (uint32_t)__shfl_xor((int)ncs, o, 64);
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+        }
         double emin = 0.0, emax = 0.0;
         if (gt) {
             emin = wave_min_d(inside ? e : __longlong_as_double(0x7ff0000000000000ll));
@@ -330,20 +347,23 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
         }
         if (lane == 0) {
             s_nc[w] = ncs;
+            s_hi[w] = hi;
             s_emin[w] = (unsigned long long)__double_as_longlong(emin);
             s_emax[w] = (unsigned long long)__double_as_longlong(emax);
         }
         __syncthreads();
         if (tid == 0) {
-            uint32_t nsum = s_nc[0];
+            uint32_t nsum = s_nc[0], hmax = s_hi[0];
             unsigned long long a = s_emin[0], b = s_emax[0];
 #pragma unroll
             for (int k = 1; k < AS_BLOCK / 64; k++) {
                 nsum += s_nc[k];
+                hmax = max(hmax, s_hi[k]);
                 a = s_emin[k] < a ? s_emin[k] : a;
                 b = s_emax[k] > b ? s_emax[k] : b;
             }
             tile_work[tile] = nsum;
+            tile_hi[tile] = hmax;
             if (gt) {
                 tile_err[2 * tile] = a;
                 tile_err[2 * tile + 1] = b;
@@ -358,99 +378,164 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
 // where B_k = sum over the contributors j behind k of (c_j . dL) a_j T_j plus
 // (bg . dL) T_final; walking the list backwards from the last contributor
 // restores T_k = T_{k+1}/(1-a_k) and B_k incrementally.  Gradients reach
-// (o, conic, mean) only where alpha = o G is below the 0.99 clamp.  Each row
-// sums over its 16 pixels, with DPP, the colour gradients and the moments
-// dp, dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2 of dp = dL/dp (p the Gaussian's
-// exponent) for the Gaussian it visits; lane 15 adds them into the batch slot
-// of that Gaussian in LDS, and after the batch one pass turns the moments into
-// mean, conic and opacity gradients and issues the global atomics: one set
-// per (Gaussian, tile).
+// (o, conic, mean) only where alpha = o G is below the 0.99 clamp.
+//
+// Work decomposition: one 16x16 tile per block of two wave64, two pixels per
+// lane.  Row `row` of wave w owns the 4x8 pixel block at tile columns
+// 4 row .. 4 row + 3 and tile rows 8 w .. 8 w + 7; lane c of the row holds
+// pixel A = (4 row + c % 4, 8 w + c / 4) and pixel B four rows below it.  A
+// step of a row visits one Gaussian for its 32 pixels, so each staged record
+// read, index, reduction and LDS update serves two pixels.  Per step the row
+// sums over its pixels, with DPP, the colour gradients and the moments
+// dp, dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2 of dp = dL/dp (p the
+// Gaussian's exponent, dx, dy the offsets mean - pixel; A and B share dx);
+// lane 15 adds them into the batch slot of that Gaussian in LDS, and after the
+// batch one pass turns the moments into mean, conic and opacity gradients and
+// issues the global atomics: one set per (Gaussian, tile).
+constexpr int BWD_BLOCK = 128;
+
+template <int BATCH>
+struct BwdShared {
+    StagedRec rec[BATCH];
+    HitT<BATCH> hits[BWD_BLOCK / 64][4][BATCH + 4];   // +4: the loop reads one index ahead
+    float gacc[9][BATCH];
+    uint8_t gflag[BATCH];
+};
+
+// Next work item of a reverse-pass block: a queue slot (persistent grid) or
+// a grid-strided index; false when the block is done.
+template <bool PERSIST>
+__device__ __forceinline__ bool next_item(uint32_t *queue, uint32_t n, int iter, uint32_t &idx, uint32_t *s_next) {
+    if (!PERSIST) {
+        idx = blockIdx.x + (uint32_t)iter * gridDim.x;
+        return idx < n;
+    }
+    if (threadIdx.x == 0) *s_next = atomicAdd(queue, 1u);
+    __syncthreads();
+    idx = *s_next;
+    __syncthreads();
+    return idx < n;
+}
+
+// A work item is one segment of a tile's list: with checkpoints, segment k
+// covers entries [start + k S, start + (k + 1) S) and the last segment runs to
+// one past the tile's last contributor; a walk starts from the state at the
+// segment's end (the forward's checkpoint, or T_final for the last segment).
 template <int BATCH, bool PERSIST>
-__global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restrict__ ranges,
-                                                        const uint32_t *__restrict__ tile_order,
-                                                        const uint32_t *__restrict__ vals,
-                                                        const BlendRec *__restrict__ rec,
-                                                        const short4 *__restrict__ box, const ViewTable vt,
-                                                        const float *__restrict__ t_final,
-                                                        const uint32_t *__restrict__ last_in,
-                                                        const uint32_t *__restrict__ ncontrib_in,
-                                                        const ViewImagesC dLs, float *__restrict__ grad2d,
-                                                        int64_t stride, uint32_t *queue, int n_tiles) {
-    constexpr int R = BATCH / AS_BLOCK;
-    __shared__ BlendShared<BATCH> sh;
-    __shared__ float s_gacc[9][BATCH];
-    __shared__ uint8_t s_gflag[BATCH];
-    __shared__ uint32_t s_maxlast;
+__global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restrict__ ranges,
+                                                         const uint32_t *__restrict__ items,
+                                                         const uint32_t *__restrict__ n_items,
+                                                         const uint32_t *__restrict__ tile_hi,
+                                                         const float4 *__restrict__ ckpt, uint32_t seg_len,
+                                                         const uint32_t *__restrict__ vals,
+                                                         const BlendRec *__restrict__ rec,
+                                                         const short4 *__restrict__ box, const ViewTable vt,
+                                                         const float *__restrict__ t_final,
+                                                         const uint32_t *__restrict__ last_in,
+                                                         const uint32_t *__restrict__ ncontrib_in,
+                                                         const ViewImagesC dLs, float *__restrict__ grad2d,
+                                                         int64_t stride, uint32_t *queue) {
+    constexpr int R = BATCH / BWD_BLOCK;
+    __shared__ BwdShared<BATCH> sh;
     __shared__ uint32_t s_next;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const LaneGeom lg = lane_geom(tid);
-    const HitT<BATCH> *hits = sh.hits[w][lg.row];
-    const float px = (float)lg.lx + 0.5f, py = (float)lg.ly + 0.5f;
-    for (int i = tid; i < BATCH; i += AS_BLOCK) {
-        s_gflag[i] = 0;
+    const int row = lane >> 4, c = lane & 15;
+    const int lx = row * 4 + (c & 3), ly = w * 8 + (c >> 2);
+    const uint32_t pbA = (1u << lx) | (1u << (16 + ly)), pbB = (1u << lx) | (1u << (20 + ly));
+    const uint32_t by = (0xFFu << (w * 8)) << 16;
+    const HitT<BATCH> *hits = sh.hits[w][row];
+    const float px = (float)lx + 0.5f, pyA = (float)ly + 0.5f, pyB = (float)(ly + 4) + 0.5f;
+    for (int i = tid; i < BATCH; i += BWD_BLOCK) {
+        sh.gflag[i] = 0;
 #pragma unroll
-        for (int k = 0; k < 9; k++) s_gacc[k][i] = 0.f;
+        for (int k = 0; k < 9; k++) sh.gacc[k][i] = 0.f;
     }
+    const uint32_t n_it = *n_items;
     uint32_t idx;
-    for (int iter = 0; next_tile<PERSIST>(queue, n_tiles, iter, idx, &s_next); iter++) {
-        const int tile = tile_order ? (int)tile_order[idx] : (int)idx;
+    for (int iter = 0; next_item<PERSIST>(queue, n_it, iter, idx, &s_next); iter++) {
+        const int tile = (int)items[2 * idx];
+        const uint32_t seg = items[2 * idx + 1];
         const int v = view_of_tile(vt, tile);
         const int lt = tile - vt.tile_base[v], tiles_x = vt.tiles_x[v];
         const int W = vt.cam[v].W, H = vt.cam[v].H;
         const int tx = lt % tiles_x, ty = lt / tiles_x;
         const int ox = tx * AS_TILE_W, oy = ty * AS_TILE_H;
-        const int x = ox + lg.lx, y = oy + lg.ly;
-        const bool inside = x < W && y < H;
-        const uint32_t start = ranges[2 * tile];
+        const int x = ox + lx, yA = oy + ly, yB = yA + 4;
+        const uint32_t start = ranges[2 * tile], hi = tile_hi[tile];
+        uint32_t s0 = start, s1 = hi;
+        bool last_seg = true;
+        if (ckpt) {
+            const uint32_t nseg = min((hi - start + seg_len - 1) / seg_len, (uint32_t)AS_CK_MAX + 1u);
+            s0 = start + seg * seg_len;
+            last_seg = seg + 1 == nseg;
+            s1 = last_seg ? hi : s0 + seg_len;
+        }
 
         const int64_t P = (int64_t)W * H;
-        const int64_t pl = (int64_t)y * W + x, pix = vt.pix_base[v] + pl;
-        float T = 1.0f, Tfin = 1.0f, dL0 = 0.f, dL1 = 0.f, dL2 = 0.f;
-        uint32_t lastp = 0;
-        bool has = false;
-        if (inside) {
-            const float *dL_dimage = dLs.p[v];
-            Tfin = t_final[pix];
-            T = Tfin;
-            has = ncontrib_in[pix] > 0;
-            lastp = last_in[pix];
-            dL0 = dL_dimage[pl];
-            dL1 = dL_dimage[P + pl];
-            dL2 = dL_dimage[2 * P + pl];
+        const int64_t plA = (int64_t)yA * W + x, plB = plA + 4 * (int64_t)W;
+        const float bg0 = vt.cam[v].bg[0], bg1 = vt.cam[v].bg[1], bg2 = vt.cam[v].bg[2];
+        // per pixel: one past the last contributor (0: none), dL and the
+        // state at the segment's end: T and
+        //   Bb = bg.dL T_final + sum over the contributors behind of
+        //        (c_j . dL) alpha_j T_j
+        // (the colour behind, in absolute terms)
+        float TA = 1.0f, TB = 1.0f, BbA = 0.f, BbB = 0.f;
+        float dA0 = 0.f, dA1 = 0.f, dA2 = 0.f, dB0 = 0.f, dB1 = 0.f, dB2 = 0.f;
+        uint32_t lA = 0, lB = 0;
+        const float *dL_dimage = dLs.p[v];
+        const float4 *ck = last_seg ? nullptr : ckpt + ((size_t)tile * AS_CK_MAX + seg) * 256;
+        if (x < W && yA < H) {
+            const int64_t pix = vt.pix_base[v] + plA;
+            const float Tf = t_final[pix];
+            lA = ncontrib_in[pix] > 0 ? last_in[pix] + 1 : 0u;
+            dA0 = dL_dimage[plA];
+            dA1 = dL_dimage[P + plA];
+            dA2 = dL_dimage[2 * P + plA];
+            BbA = Tf * (bg0 * dA0 + bg1 * dA1 + bg2 * dA2);
+            TA = Tf;
+            if (ck) {
+                const float4 q = ck[ly * 16 + lx];
+                TA = q.x;
+                BbA += q.y * dA0 + q.z * dA1 + q.w * dA2;
+            }
         }
-        const float bgdot = vt.cam[v].bg[0] * dL0 + vt.cam[v].bg[1] * dL1 + vt.cam[v].bg[2] * dL2;
-        if (tid == 0) s_maxlast = 0;
-        __syncthreads();
-        if (has) atomicMax(&s_maxlast, lastp + 1);
-        __syncthreads();
-        const uint32_t hi_end = s_maxlast > start ? s_maxlast : start;   // one past the block's last contributor
-        // one past the wave's last contributor (wave-uniform)
-        uint32_t wlast = has ? lastp + 1 : 0;
+        if (x < W && yB < H) {
+            const int64_t pix = vt.pix_base[v] + plB;
+            const float Tf = t_final[pix];
+            lB = ncontrib_in[pix] > 0 ? last_in[pix] + 1 : 0u;
+            dB0 = dL_dimage[plB];
+            dB1 = dL_dimage[P + plB];
+            dB2 = dL_dimage[2 * P + plB];
+            BbB = Tf * (bg0 * dB0 + bg1 * dB1 + bg2 * dB2);
+            TB = Tf;
+            if (ck) {
+                const float4 q = ck[(ly + 4) * 16 + lx];
+                TB = q.x;
+                BbB += q.y * dB0 + q.z * dB1 + q.w * dB2;
+            }
+        }
+        uint32_t wlast = max(lA, lB);   // one past the wave's last contributor (wave-uniform)
         for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
 
-        // Bb = bg.dL T_final + sum over the contributors behind the current
-        // one of (c_j . dL) alpha_j T_j: the colour behind, in absolute terms
-        float Bb = Tfin * bgdot;
-
-        // batches [b0, b1) walk the list backwards from hi_end
+        // batches [b0, b1) walk the segment backwards from its end
         Fetched nf[R];
         {
-            const uint32_t b0 = hi_end - start > (uint32_t)BATCH ? hi_end - BATCH : start;
+            const uint32_t b0 = s1 - s0 > (uint32_t)BATCH ? s1 - BATCH : s0;
 #pragma unroll
             for (int k = 0; k < R; k++)
-                if (b0 + k * AS_BLOCK + tid < hi_end) fetch(vals, rec, box, b0 + k * AS_BLOCK + tid, nf[k]);
+                if (b0 + k * BWD_BLOCK + tid < s1) fetch(vals, rec, box, b0 + k * BWD_BLOCK + tid, nf[k]);
         }
-        for (uint32_t b1 = hi_end; b1 > start;) {
-            const uint32_t b0 = b1 - start > (uint32_t)BATCH ? b1 - BATCH : start;
-            const uint32_t n1 = b0, n0 = n1 - start > (uint32_t)BATCH ? n1 - BATCH : start;
+        for (uint32_t b1 = s1; b1 > s0;) {
+            const uint32_t b0 = b1 - s0 > (uint32_t)BATCH ? b1 - BATCH : s0;
+            const uint32_t n1 = b0, n0 = n1 - s0 > (uint32_t)BATCH ? n1 - BATCH : s0;
 #pragma unroll
             for (int k = 0; k < R; k++) {
-                const int t = k * AS_BLOCK + tid;
+                const int t = k * BWD_BLOCK + tid;
                 if (b0 + t < b1) stage(nf[k], ox, oy, sh.rec, t);
                 if (n0 + t < n1) fetch(vals, rec, box, n0 + t, nf[k]);
             }
             __syncthreads();
-            const int nh = compact_rows<BATCH>(sh.rec, (int)(b1 - b0), sh.hits[w], w, lg.row,
+            const int nh = compact_rows<BATCH>(sh.rec, (int)(b1 - b0), sh.hits[w], by, row,
                                                [&](int j) { return b0 + (uint32_t)j < wlast; });
             // the wave walks max over its rows of the row counts; rows past their
             // own count idle
@@ -465,29 +550,42 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
                 const float4 q0 = sh.rec[j].mc, q1 = sh.rec[j].cc, q2 = sh.rec[j].ex;
                 const uint32_t m = __float_as_uint(q2.y);
                 const uint32_t gidx = b0 + (uint32_t)j;
-                const float dx = q0.x - px, dy = q0.y - py;
-                const float araw = __builtin_amdgcn_exp2f(blend_exponent(dx, dy, q0, q1));
-                const float alpha = fminf(ALPHA_MAX, araw);
-                const bool contrib = valid && has && gidx <= lastp && (m & lg.pbits) == lg.pbits &&
-                                     alpha >= ALPHA_MIN;
-                const uint64_t cb = __ballot(contrib);
+                const float dx = q0.x - px, dyA = q0.y - pyA, dyB = q0.y - pyB;
+                const float arA = __builtin_amdgcn_exp2f(blend_exponent(dx, dyA, q0, q1));
+                const float arB = __builtin_amdgcn_exp2f(blend_exponent(dx, dyB, q0, q1));
+                const float alA = fminf(ALPHA_MAX, arA), alB = fminf(ALPHA_MAX, arB);
+                const bool cA = valid && gidx < lA && (m & pbA) == pbA && alA >= ALPHA_MIN;
+                const bool cB = valid && gidx < lB && (m & pbB) == pbB && alB >= ALPHA_MIN;
+                const uint64_t cb = __ballot(cA || cB);
                 if (!cb) continue;
-                // Every lane evaluates the step; a non-contributor's weight and
-                // dp are zero, so its sums and state stay unchanged.
-                const float rom = __builtin_amdgcn_rcpf(1.0f - alpha);
-                const float Tk = T * rom;
-                T = contrib ? Tk : T;
-                const float cdl = q1.z * dL0 + q1.w * dL1 + q2.x * dL2;
-                const float wgt = contrib ? alpha * Tk : 0.0f;
+                // Every lane evaluates the step for both pixels; a
+                // non-contributor's weight and dp are zero, so its sums and
+                // state stay unchanged.
+                const float cdlA = q1.z * dA0 + q1.w * dA1 + q2.x * dA2;
+                const float cdlB = q1.z * dB0 + q1.w * dB1 + q2.x * dB2;
+                const float romA = __builtin_amdgcn_rcpf(1.0f - alA), romB = __builtin_amdgcn_rcpf(1.0f - alB);
+                const float TkA = TA * romA, TkB = TB * romB;
+                TA = cA ? TkA : TA;
+                TB = cB ? TkB : TB;
+                const float wA = cA ? alA * TkA : 0.0f, wB = cB ? alB * TkB : 0.0f;
                 // dL/dalpha_k = T_k (c_k . dL) - Bb / (1 - alpha_k)
-                const float dLda = Tk * cdl - Bb * rom;
-                Bb += wgt * cdl;
-                // alpha = o exp(p): dalpha/dp = alpha below the clamp; the sums
-                // of dp and of dp times the pixel offsets become the mean,
-                // conic and opacity gradients when the batch is flushed
-                const float dp = (contrib && araw < ALPHA_MAX) ? dLda * araw : 0.0f;
-                const float dpx = dp * dx, dpy = dp * dy;
-                float g[9] = {dp, dpx, dpy, dpx * dx, dpx * dy, dpy * dy, wgt * dL0, wgt * dL1, wgt * dL2};
+                const float dLdaA = TkA * cdlA - BbA * romA, dLdaB = TkB * cdlB - BbB * romB;
+                BbA += wA * cdlA;
+                BbB += wB * cdlB;
+                // alpha = o exp(p): dalpha/dp = alpha below the clamp
+                const float dpA = (cA && arA < ALPHA_MAX) ? dLdaA * arA : 0.0f;
+                const float dpB = (cB && arB < ALPHA_MAX) ? dLdaB * arB : 0.0f;
+                const float dpyA = dpA * dyA, dpyB = dpB * dyB;
+                const float s0 = dpA + dpB, sy = dpyA + dpyB, sx = s0 * dx;
+                float g[9] = {s0,
+                              sx,
+                              sy,
+                              sx * dx,
+                              sy * dx,
+                              dpyA * dyA + dpyB * dyB,
+                              wA * dA0 + wB * dB0,
+                              wA * dA1 + wB * dB1,
+                              wA * dA2 + wB * dB2};
 #pragma unroll
                 for (int k = 0; k < 9; k++) {
                     g[k] = row_sum(g[k]);
@@ -495,32 +593,32 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_bwd(const uint32_t *__restri
                     // the branch below it would split into a move and an add
                     asm volatile("" : "+v"(g[k]));
                 }
-                if ((lane & 15) == 15 && ((cb >> (lg.row * 16)) & 0xFFFFull)) {
+                if (c == 15 && ((cb >> (row * 16)) & 0xFFFFull)) {
 #pragma unroll
-                    for (int k = 0; k < 9; k++) atomicAdd(&s_gacc[k][j], g[k]);
-                    s_gflag[j] = 1;
+                    for (int k = 0; k < 9; k++) atomicAdd(&sh.gacc[k][j], g[k]);
+                    sh.gflag[j] = 1;
                 }
             }
             __syncthreads();
             // One set of global atomics per entry of the batch that received
-            // gradients.  With the pixel offsets dx = mean - pixel and
-            // p = -(a dx^2 + c dy^2)/2 - b dx dy (unscaled conic a, b, c):
-            // dp/dmean = -(a dx + b dy, c dy + b dx), dp/d(a, b, c) =
-            // -(dx^2/2, dx dy, dy^2/2) and dalpha/do = alpha/o.
-            for (int i = tid; i < (int)(b1 - b0); i += AS_BLOCK) {
-                if (s_gflag[i]) {
+            // gradients.  With p = -(a dx^2 + c dy^2)/2 - b dx dy (unscaled
+            // conic a, b, c): dp/dmean = -(a dx + b dy, c dy + b dx),
+            // dp/d(a, b, c) = -(dx^2/2, dx dy, dy^2/2) and dalpha/do = alpha/o.
+            for (int i = tid; i < (int)(b1 - b0); i += BWD_BLOCK) {
+                if (sh.gflag[i]) {
                     const float4 q0 = sh.rec[i].mc, q1 = sh.rec[i].cc, q2 = sh.rec[i].ex;
                     const int64_t id = (int64_t)__float_as_uint(q2.z);
-                    const float a = -2.0f * LN2 * q0.z, b = -LN2 * q0.w, c = -2.0f * LN2 * q1.x;
-                    const float s0 = s_gacc[0][i], sx = s_gacc[1][i], sy = s_gacc[2][i];
-                    const float gv[9] = {-(a * sx + b * sy), -(c * sy + b * sx), -0.5f * s_gacc[3][i], -s_gacc[4][i],
-                                         -0.5f * s_gacc[5][i], s0 * q2.w, s_gacc[6][i], s_gacc[7][i], s_gacc[8][i]};
+                    const float a = -2.0f * LN2 * q0.z, b = -LN2 * q0.w, cc = -2.0f * LN2 * q1.x;
+                    const float s0 = sh.gacc[0][i], sx = sh.gacc[1][i], sy = sh.gacc[2][i];
+                    const float gv[9] = {-(a * sx + b * sy),       -(cc * sy + b * sx), -0.5f * sh.gacc[3][i],
+                                         -sh.gacc[4][i],           -0.5f * sh.gacc[5][i], s0 * q2.w,
+                                         sh.gacc[6][i],            sh.gacc[7][i],         sh.gacc[8][i]};
 #pragma unroll
                     for (int k = 0; k < 9; k++) {
                         atomicAdd(&grad2d[k * stride + id], gv[k]);
-                        s_gacc[k][i] = 0.f;
+                        sh.gacc[k][i] = 0.f;
                     }
-                    s_gflag[i] = 0;
+                    sh.gflag[i] = 0;
                 }
             }
             __syncthreads();
@@ -569,23 +667,98 @@ __device__ __forceinline__ int work_class(uint32_t wk) {
     return 1 + 4 * lg + frac;   // 1..128
 }
 
-__global__ void __launch_bounds__(1024) k_tile_order_work(const uint32_t *__restrict__ work, int tiles,
-                                                          uint32_t *__restrict__ order) {
+// After the forward blend, in one block: the error range of each view with a
+// target (minimum and maximum over its tiles' ranges; device-wide atomics on
+// one word per view would serialise at the memory side), the reverse pass's
+// dispatch order (tiles by descending contributor count, 129 classes: four
+// per octave, heaviest first) and its work items: the tiles in that order,
+// each expanded into its segments (one without checkpoints), by a block-wide
+// exclusive scan of the segment counts.
+__global__ void __launch_bounds__(1024) k_after_fwd(const ViewTable vt, const ViewImagesC gts,
+                                                    const unsigned long long *__restrict__ tile_err,
+                                                    unsigned long long *__restrict__ minmax,
+                                                    const uint32_t *__restrict__ work, int order_on,
+                                                    uint32_t *__restrict__ order, const uint32_t *__restrict__ ranges,
+                                                    const uint32_t *__restrict__ tile_hi, uint32_t seg_len, int ck,
+                                                    uint32_t *__restrict__ items, uint32_t *__restrict__ n_items) {
     __shared__ uint32_t s_cnt[129], s_off[129];
-    const int tid = threadIdx.x;
-    if (tid < 129) s_cnt[tid] = 0;
-    __syncthreads();
-    for (int t = tid; t < tiles; t += blockDim.x) atomicAdd(&s_cnt[128 - work_class(work[t])], 1u);
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int c = 0; c < 129; c++) {
-            s_off[c] = run;
-            run += s_cnt[c];
+    __shared__ unsigned long long s_mn[16], s_mx[16];
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tiles = vt.tile_base[vt.n_views];
+    for (int v = 0; v < vt.n_views; v++) {
+        if (!gts.p[v]) continue;
+        unsigned long long mn = 0x7ff0000000000000ull, mx = 0ull;
+        for (int t = vt.tile_base[v] + tid; t < vt.tile_base[v + 1]; t += 1024) {
+            const unsigned long long a = tile_err[2 * t], b = tile_err[2 * t + 1];
+            mn = a < mn ? a : mn;
+            mx = b > mx ? b : mx;
         }
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+            mn = a < mn ? a : mn;
+            mx = b > mx ? b : mx;
+        }
+        if (lane == 0) {
+            s_mn[w] = mn;
+            s_mx[w] = mx;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int k = 1; k < 16; k++) {
+                mn = s_mn[k] < mn ? s_mn[k] : mn;
+                mx = s_mx[k] > mx ? s_mx[k] : mx;
+            }
+            minmax[2 * v] = mn;
+            minmax[2 * v + 1] = mx;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int t = tid; t < tiles; t += blockDim.x) order[atomicAdd(&s_off[128 - work_class(work[t])], 1u)] = (uint32_t)t;
+    if (order_on) {
+        if (tid < 129) s_cnt[tid] = 0;
+        __syncthreads();
+        for (int t = tid; t < tiles; t += 1024) atomicAdd(&s_cnt[128 - work_class(work[t])], 1u);
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t run = 0;
+            for (int c = 0; c < 129; c++) {
+                s_off[c] = run;
+                run += s_cnt[c];
+            }
+        }
+        __syncthreads();
+        for (int t = tid; t < tiles; t += 1024) order[atomicAdd(&s_off[128 - work_class(work[t])], 1u)] = (uint32_t)t;
+    }
+    if (tid == 0) s_carry = 0;
+    __syncthreads();   // also: the order written above is visible to the whole block
+    for (int base = 0; base < tiles; base += 1024) {
+        const int i = base + tid;
+        uint32_t tile = 0, nseg = 0;
+        if (i < tiles) {
+            tile = order_on ? order[i] : (uint32_t)i;
+            const uint32_t start = ranges[2 * tile], hi = tile_hi[tile];
+            if (hi > start) nseg = ck ? min((hi - start + seg_len - 1) / seg_len, (uint32_t)AS_CK_MAX + 1u) : 1u;
+        }
+        uint32_t incl = nseg;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) s_w[w] = incl;
+        __syncthreads();
+        uint32_t before = s_carry;
+        for (int k = 0; k < w; k++) before += s_w[k];
+        const uint32_t off = before + incl - nseg;
+        for (uint32_t k = 0; k < nseg; k++) {
+            items[2 * (off + k)] = tile;
+            items[2 * (off + k) + 1] = k;
+        }
+        __syncthreads();
+        if (tid == 1023) s_carry = before + incl;
+        __syncthreads();
+    }
+    if (tid == 0) *n_items = s_carry;
 }
 
 }  // namespace
@@ -594,54 +767,26 @@ void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipSt
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);
 }
 
-void launch_tile_order_work(const uint32_t *work, int tiles, uint32_t *order, hipStream_t s) {
-    hipLaunchKernelGGL(k_tile_order_work, dim3(1), dim3(1024), 0, s, work, tiles, order);
+void launch_after_fwd(const as_frame *f, const ViewTable &vt, const ViewImagesC &gt, int order_on, hipStream_t s) {
+    const int tiles = vt.tile_base[vt.n_views];
+    if (tiles == 0) return;
+    hipLaunchKernelGGL(k_after_fwd, dim3(1), dim3(1024), 0, s, vt, gt,
+                       reinterpret_cast<const unsigned long long *>(f->tile_err),
+                       reinterpret_cast<unsigned long long *>(f->err_minmax), f->tile_work, order_on, f->tile_order_bwd,
+                       f->ranges, f->tile_hi, (uint32_t)f->ck_seg, f->ck_written ? 1 : 0, f->bwd_items, f->n_items);
 }
 
 namespace {
-// Error range of each view with a target image: the minimum and maximum of
-// its tiles' ranges (one block per view).
-__global__ void __launch_bounds__(AS_BLOCK) k_err_minmax(const ViewTable vt, const ViewImagesC gts,
-                                                         const unsigned long long *__restrict__ tile_err,
-                                                         unsigned long long *__restrict__ minmax) {
-    __shared__ unsigned long long s_mn[AS_BLOCK / 64], s_mx[AS_BLOCK / 64];
-    const int v = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    unsigned long long mn = 0x7ff0000000000000ull, mx = 0ull;
-    if (gts.p[v]) {
-        for (int t = vt.tile_base[v] + tid; t < vt.tile_base[v + 1]; t += AS_BLOCK) {
-            const unsigned long long a = tile_err[2 * t], b = tile_err[2 * t + 1];
-            mn = a < mn ? a : mn;
-            mx = b > mx ? b : mx;
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
-        mn = a < mn ? a : mn;
-        mx = b > mx ? b : mx;
-    }
-    if (lane == 0) {
-        s_mn[w] = mn;
-        s_mx[w] = mx;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        for (int k = 1; k < AS_BLOCK / 64; k++) {
-            mn = s_mn[k] < mn ? s_mn[k] : mn;
-            mx = s_mx[k] > mx ? s_mx[k] : mx;
-        }
-        minmax[2 * v] = mn;
-        minmax[2 * v + 1] = mx;
-    }
-}
-
 // Resident blocks of a kernel on the whole device (persistent grid size).
 template <typename Kern>
-int resident_blocks(Kern k, int n_cu) {
+int resident_blocks(Kern k, int n_cu, int block = AS_BLOCK) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, AS_BLOCK, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, 0) != hipSuccess || per_cu < 1) per_cu = 1;
     return per_cu * (n_cu > 0 ? n_cu : 1);
 }
 }  // namespace
+
+int blend_fwd_batch(const BlendLaunch &bl) { return bl.batch >= 1024 ? 1024 : bl.batch >= 512 ? 512 : 256; }
 
 void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
                       const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s) {
@@ -660,8 +805,7 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         }                                                                                                          \
         hipLaunchKernelGGL((k_blend_fwd<B, PER>), dim3(grid), dim3(AS_BLOCK), 0, s, f->ranges, tile_order, vals,  \
                            f->rec, b4, vt, gt, image, f->t_final, f->last, f->n_contrib, f->dom, f->err, te,      \
-                           f->tile_work,                                                                   \
-                           f->queue, tiles);                                                                       \
+                           f->tile_work, f->tile_hi, reinterpret_cast<float4 *>(f->ckpt), f->queue, tiles);        \
     } while (0)
     if (bl.persistent) {
         if (bl.batch >= 1024) AS_FWD(1024, true);
@@ -673,11 +817,6 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         else AS_FWD(256, false);
     }
 #undef AS_FWD
-    bool any_gt = false;
-    for (int v = 0; v < vt.n_views; v++) any_gt = any_gt || gt.p[v] != nullptr;
-    if (any_gt)
-        hipLaunchKernelGGL(k_err_minmax, dim3(vt.n_views), dim3(AS_BLOCK), 0, s, vt, gt, te,
-                           reinterpret_cast<unsigned long long *>(f->err_minmax));
 }
 
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
@@ -686,27 +825,32 @@ void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
     const int tiles = vt.tile_base[vt.n_views];
     if (tiles == 0) return;
     const short4 *b4 = reinterpret_cast<const short4 *>(f->box);
+    const bool ck = f->ck_written && f->ckpt;
+    const uint32_t seg_len = (uint32_t)f->ck_seg;
     if (bl.persistent) launch_fill_u32(f->queue + 1, 0u, 1, s);
+    const float4 *ckp = ck ? reinterpret_cast<const float4 *>(f->ckpt) : nullptr;
+    // one block per item for the usual count (most tiles are one segment);
+    // blocks stride over the items beyond the grid
+    const int grid_items = ck ? 2 * tiles : tiles;
 #define AS_BWD(B, PER)                                                                                             \
     do {                                                                                                           \
         static int grid_p = 0;                                                                                     \
-        int grid = tiles;                                                                                          \
+        int grid = grid_items;                                                                                     \
         if (PER) {                                                                                                 \
-            if (!grid_p) grid_p = resident_blocks(k_blend_bwd<B, PER>, bl.n_cu);                                   \
-            grid = grid_p < tiles ? grid_p : tiles;                                                                \
+            if (!grid_p) grid_p = resident_blocks(k_blend_bwd<B, PER>, bl.n_cu, BWD_BLOCK);                        \
+            grid = grid_p < grid_items ? grid_p : grid_items;                                                      \
         }                                                                                                          \
-        hipLaunchKernelGGL((k_blend_bwd<B, PER>), dim3(grid), dim3(AS_BLOCK), 0, s, f->ranges, tile_order, vals,  \
-                           f->rec, b4, vt, f->t_final, f->last, f->n_contrib, dL_dimage, grad2d, g2d_stride,      \
-                           f->queue + 1, tiles);                                                                   \
+        hipLaunchKernelGGL((k_blend_bwd<B, PER>), dim3(grid), dim3(BWD_BLOCK), 0, s, f->ranges, f->bwd_items,     \
+                           f->n_items, f->tile_hi, ckp, seg_len, vals, f->rec, b4, vt, f->t_final, f->last,        \
+                           f->n_contrib, dL_dimage, grad2d, g2d_stride, f->queue + 1);                             \
     } while (0)
+    // the reverse pass stages half the forward's depth: two waves per tile
     if (bl.persistent) {
-        if (bl.batch >= 1024) AS_BWD(1024, true);
-        else if (bl.batch >= 512) AS_BWD(512, true);
-        else AS_BWD(256, true);
+        if (bl.batch >= 512) AS_BWD(256, true);
+        else AS_BWD(128, true);
     } else {
-        if (bl.batch >= 1024) AS_BWD(1024, false);
-        else if (bl.batch >= 512) AS_BWD(512, false);
-        else AS_BWD(256, false);
+        if (bl.batch >= 512) AS_BWD(256, false);
+        else AS_BWD(128, false);
     }
 #undef AS_BWD
 }

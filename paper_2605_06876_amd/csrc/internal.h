@@ -10,6 +10,7 @@
 #define AS_TILE_W 16
 #define AS_TILE_H 16
 #define AS_BLOCK 256        // threads per tile block: one 16x16 tile, four wave64
+#define AS_CK_MAX 3         // forward checkpoints per tile (the reverse pass splits a tile into up to 4 segments)
 #define AS_NEAR 0.2
 #define AS_LOWPASS 0.3
 #define AS_MAX_VIEWS 16   // views of one batched render
@@ -110,6 +111,13 @@ struct as_frame {
     uint32_t *tile_order;  // [tiles] dispatch order of the forward blend (longest list first)
     uint32_t *tile_work;   // [tiles] contributors summed over the tile's pixels, from the forward blend
     uint32_t *tile_order_bwd;  // [tiles] dispatch order of the reverse blend (most contributors first)
+    uint32_t *tile_hi;     // [tiles] one past the tile's last contributor (0: none), from the forward blend
+    float *ckpt;           // [tile_cap][AS_CK_MAX][256][4] per pixel (T, colour behind) at the forward's batch
+                           // boundaries; allocated by the first reverse pass
+    uint32_t *bwd_items;   // [tile_cap * (AS_CK_MAX + 1)][2] (tile, segment) work items of the reverse blend
+    uint32_t *n_items;     // [1] device count of bwd_items
+    int ck_written;        // the last render wrote checkpoints
+    int ck_seg;            // their spacing in list entries (the forward's batch depth)
     int use_order;         // tile_order is valid for the last render
     uint32_t *n_keys;      // [1] device
     uint32_t *h_nkeys;     // pinned host mirror
@@ -214,8 +222,12 @@ struct BlendLaunch {
     int persistent;    // 1: one resident grid pulling tiles from f->queue
     int n_cu;
 };
+// The forward blend's LDS depth for a launch (256, 512 or 1024 records).
+int blend_fwd_batch(const BlendLaunch &bl);
 void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipStream_t s);
-void launch_tile_order_work(const uint32_t *work, int tiles, uint32_t *order, hipStream_t s);
+// After the forward blend: per-view error ranges, the reverse pass's dispatch
+// order (when order_on) and its work items, from the render's checkpoint state.
+void launch_after_fwd(const as_frame *f, const ViewTable &vt, const ViewImagesC &gt, int order_on, hipStream_t s);
 void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
                       const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s);
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
