@@ -223,6 +223,54 @@ def test_backward_accumulates_adc_statistic(ctx, c1):
     del g2d
 
 
+def _flagged_gaussians(pr, flag):
+    flagged = np.zeros(pr.n, bool)
+    fy, fx = np.nonzero(flag)
+    for x, y in zip(fx, fy):
+        b = pr.box
+        flagged |= (pr.valid == 1) & (b[:, 0] <= x) & (x <= b[:, 2]) & (b[:, 1] <= y) & (y <= b[:, 3])
+    return flagged
+
+
+def test_backward_segments_match_oracle(ctx):
+    """Tiles whose contributors run past one forward batch (256 entries): after
+    a render that wrote checkpoints, the reverse pass walks each such tile as
+    independent segments starting from the forward's checkpoints.  Gradients
+    match the oracle, as do those of the first reverse pass, which precedes
+    the checkpoint buffer and walks every tile in one piece."""
+    base = synth.scene_uniform_sh0(3000, seed=91, log_scale_mu=-2.5, log_scale_sd=0.3)
+    # o ~ 0.08: pixels stay far from saturation across a few hundred Gaussians
+    scene = synth.Scene(base.means, base.log_scales, base.quats, np.full(3000, -2.5, np.float32), base.sh, 0)
+    cam = synth.look_at((0.2, -0.1, -3.5), (0.0, 0.0, 0.0), 64, 64, 60.0, bg=(0.3, 0.2, 0.1))
+    g = api.Gaussians.from_scene(scene)
+    frame = api.Frame(ctx, g.n, cam.width, cam.height)
+    G = np.random.default_rng(8).normal(size=(3, 64, 64)).astype(np.float32)
+    Gt = torch.from_numpy(G).cuda()
+    say("segments: render, reverse pass in one piece")
+    api.render(ctx, g, cam, frame)
+    g_one = api.render_backward(ctx, g, cam, frame, Gt)
+    say("segments: render with checkpoints, segmented reverse pass")
+    api.render(ctx, g, cam, frame)
+    g_seg = api.render_backward(ctx, g, cam, frame, Gt)
+    torch.cuda.synchronize()
+    st = frame.host_state(g.n)
+    hi = np.zeros(st["ranges"].shape[0], np.int64)
+    ys, xs = np.nonzero(st["n_contrib"] > 0)
+    np.maximum.at(hi, (ys // 16) * st["tiles_x"] + xs // 16, st["last"][ys, xs].astype(np.int64) + 1)
+    n_long = int((hi - st["ranges"][:, 0].astype(np.int64) > 256).sum())
+    say("segments: %d of %d tiles have contributors past entry 256" % (n_long, len(hi)))
+    assert n_long > 0
+    pr = oracle.project(scene, cam)
+    _, maps = oracle.render_image(pr)
+    pix = oracle.all_pixels(cam.width, cam.height)
+    g2d = oracle.render_backward_pixels(pr, pix, G.transpose(1, 2, 0).reshape(-1, 3).astype(np.float64))
+    gref = oracle.project_backward(scene, cam, g2d)
+    flagged = _flagged_gaussians(pr, maps["flag"])
+    res_seg = _grad_compare(g_seg, gref, exclude=flagged)
+    res_one = _grad_compare(g_one, gref, exclude=flagged)
+    say("segments: " + ", ".join("%s %.2e / %.2e" % (k, res_seg[k][0], res_one[k][0]) for k in res_seg))
+
+
 # ---- edge cases ---------------------------------------------------------------------
 
 @pytest.mark.parametrize("W,H", [(1, 1), (17, 5), (33, 47), (130, 70)])
