@@ -423,7 +423,8 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     f->has_render = 0;
     {
         StageTimer t(ctx, AS_STAGE_PROJECT, s);
-        launch_project(sc, vt, max_n, deg, f->rec, f->depth_key, f->box, f->ntiles, s);
+        launch_project(sc, vt, max_n, deg, f->rec, f->depth_key, f->box, f->ntiles, f->dkeys[0], f->dvals[0], f->n_ent,
+                       s);
     }
     // Depth-first binning: a stable sort of the entries by depth, keys
     // emitted in that order, then a stable sort on the tile ids alone, gives
@@ -431,7 +432,6 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     const uint32_t *order;
     {
         StageTimer t(ctx, AS_STAGE_SORT, s);
-        launch_depth_pairs(n, f->depth_key, f->dkeys[0], f->dvals[0], f->n_ent, s);
         // 32-bit keys: 8-bit digits give the fewest passes (four)
         const int dsel = radix_sort_u32(f->dkeys, f->dvals, f->n_ent, f->ent_cap, n, 0, 32, 8,
                                         f->dsort_hist.p, s);

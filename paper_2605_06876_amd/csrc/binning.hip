@@ -179,15 +179,6 @@ __global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *
 }
 
 // (depth key, entry) pairs of every entry for the depth sort.
-__global__ void k_depth_pairs(int64_t n, const uint32_t *__restrict__ depth_key, uint32_t *__restrict__ keys,
-                              uint32_t *__restrict__ vals, uint32_t *__restrict__ n32) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *n32 = (uint32_t)n;
-    if (i >= n) return;
-    keys[i] = depth_key[i];
-    vals[i] = (uint32_t)i;
-}
-
 __global__ void k_gather_u32(int64_t n, const uint32_t *__restrict__ src, const uint32_t *__restrict__ idx,
                              uint32_t *__restrict__ dst) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,12 +247,6 @@ void scan_u8_to_i64(const uint8_t *in, int64_t *out, int64_t n, int64_t *total, 
 }
 void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total, void *tmp, hipStream_t s) {
     scan_impl<int32_t, int64_t>(in, out, n, total, tmp, s);
-}
-
-void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals, uint32_t *n32,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_depth_pairs, dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)), dim3(256), 0, s, n,
-                       depth_key, keys, vals, n32);
 }
 
 void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint32_t *dst, hipStream_t s) {

@@ -176,8 +176,11 @@ struct StageTimer {
 // ---- launchers (each defined in the .hip file that holds the kernel) -------------
 
 // projection (project.hip): every view's Gaussians into its entry range
+// Projection of every entry; also writes the depth sort's input pairs
+// (depth key, entry id) and the device entry count.
 void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, int deg, BlendRec *rec,
-                    uint32_t *depth_key, int16_t *box, uint32_t *ntiles, hipStream_t s);
+                    uint32_t *depth_key, int16_t *box, uint32_t *ntiles, uint32_t *sort_keys, uint32_t *sort_vals,
+                    uint32_t *n_ent, hipStream_t s);
 // projection backward (project_bwd.hip): one Gaussian set seen in every view
 // of vt; gradients summed over the views in view order
 void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t *ntiles, const float *grad2d,
@@ -199,10 +202,8 @@ int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, 
                    int hi_bit, int radix_bits, void *hist, hipStream_t s);
 int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
                    int hi_bit, int radix_bits, void *hist, hipStream_t s);
-// Depth-first binning helpers: (depth, entry) pairs, gathers, and key emission
+// Depth-first binning helpers: gathers and key emission
 // in the depth order a stable depth sort produced.
-void launch_depth_pairs(int64_t n, const uint32_t *depth_key, uint32_t *keys, uint32_t *vals, uint32_t *n32,
-                        hipStream_t s);
 void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint32_t *dst, hipStream_t s);
 void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
                         const uint32_t *nt_sorted, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,

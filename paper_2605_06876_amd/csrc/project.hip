@@ -23,11 +23,13 @@ __device__ __forceinline__ void quat_to_rot_d(double w, double x, double y, doub
 template <int DEG>
 __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const ViewTable vt, BlendRec *__restrict__ rec,
                                                  uint32_t *__restrict__ depth_key, short4 *__restrict__ box,
-                                                 uint32_t *__restrict__ ntiles) {
+                                                 uint32_t *__restrict__ ntiles, uint32_t *__restrict__ sort_keys,
+                                                 uint32_t *__restrict__ sort_vals, uint32_t *__restrict__ n_ent) {
     const int v = (int)(blockIdx.x % (unsigned)vt.n_views);
     const int64_t i = (int64_t)(blockIdx.x / (unsigned)vt.n_views) * blockDim.x + threadIdx.x;
     const GaussPtrs &g = sc.g[v];
     const DevCam &cam = vt.cam[v];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_ent = (uint32_t)vt.ent_base[vt.n_views];
     if (i >= g.n) return;
     const int64_t n = g.n;
     const int64_t e = (int64_t)vt.ent_base[v] + i;
@@ -45,7 +47,11 @@ __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const View
     double tv[3];
     for (int r = 0; r < 3; r++) tv[r] = Rc[r * 3 + 0] * mu[0] + Rc[r * 3 + 1] * mu[1] + Rc[r * 3 + 2] * mu[2] + tc[r];
     const double tx = tv[0], ty = tv[1], tz = tv[2];
-    depth_key[e] = __float_as_uint((float)tz);
+    // the depth key, also as the (key, entry) input of the depth sort
+    const uint32_t dk = __float_as_uint((float)tz);
+    depth_key[e] = dk;
+    sort_keys[e] = dk;
+    sort_vals[e] = (uint32_t)e;
 
     BlendRec rr;
     rr.m = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -136,14 +142,22 @@ __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const View
 }  // namespace
 
 void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, int deg, BlendRec *rec,
-                    uint32_t *depth_key, int16_t *box, uint32_t *ntiles, hipStream_t s) {
-    if (max_n == 0 || vt.n_views == 0) return;
+                    uint32_t *depth_key, int16_t *box, uint32_t *ntiles, uint32_t *sort_keys, uint32_t *sort_vals,
+                    uint32_t *n_ent, hipStream_t s) {
+    if (max_n == 0 || vt.n_views == 0) {
+        launch_fill_u32(n_ent, 0u, 1, s);
+        return;
+    }
     const int64_t blocks = (max_n + 255) / 256 * vt.n_views;
     short4 *b4 = reinterpret_cast<short4 *>(box);
     switch (deg) {
-    case 0: hipLaunchKernelGGL(k_project<0>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles); break;
-    default: hipLaunchKernelGGL(k_project<3>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles); break;
+    case 0: hipLaunchKernelGGL(k_project<0>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles, sort_keys,
+                                  sort_vals, n_ent); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles, sort_keys,
+                                  sort_vals, n_ent); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles, sort_keys,
+                                  sort_vals, n_ent); break;
+    default: hipLaunchKernelGGL(k_project<3>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles, sort_keys,
+                                  sort_vals, n_ent); break;
     }
 }
