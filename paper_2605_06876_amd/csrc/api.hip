@@ -432,14 +432,14 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     const uint32_t *order;
     {
         StageTimer t(ctx, AS_STAGE_SORT, s);
-        // 32-bit keys: 8-bit digits give the fewest passes (four)
+        // 32-bit keys: 8-bit digits give the fewest passes (four); the last
+        // pass also gathers each entry's tile count into depth order
         const int dsel = radix_sort_u32(f->dkeys, f->dvals, f->n_ent, f->ent_cap, n, 0, 32, 8,
-                                        f->dsort_hist.p, s);
+                                        f->dsort_hist.p, s, f->ntiles, f->nt_sorted);
         order = f->dvals[dsel];
     }
     {
         StageTimer t(ctx, AS_STAGE_SCAN, s);
-        launch_gather_u32(n, f->ntiles, order, f->nt_sorted, s);
         scan_u32(f->nt_sorted, f->offsets, n, f->n_keys, f->scan_tmp.p, s);
     }
     int64_t n_hint = f->key_cap;

@@ -179,12 +179,6 @@ __global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *
 }
 
 // (depth key, entry) pairs of every entry for the depth sort.
-__global__ void k_gather_u32(int64_t n, const uint32_t *__restrict__ src, const uint32_t *__restrict__ idx,
-                             uint32_t *__restrict__ dst) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) dst[r] = src[idx[r]];
-}
-
 // [start, end) of every tile in the sorted tile keys (tiles without keys keep
 // the [0, 0) the caller filled).
 __global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles,
@@ -247,11 +241,6 @@ void scan_u8_to_i64(const uint8_t *in, int64_t *out, int64_t n, int64_t *total, 
 }
 void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total, void *tmp, hipStream_t s) {
     scan_impl<int32_t, int64_t>(in, out, n, total, tmp, s);
-}
-
-void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint32_t *dst, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_gather_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, src, idx, dst);
 }
 
 void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,

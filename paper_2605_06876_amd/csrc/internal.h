@@ -198,13 +198,15 @@ void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total,
 // count is read from the device (*n_dev, clamped to cap); n_hint sizes the
 // grid.  hist is a workspace of sort_hist_bytes(cap) bytes for the same cap.
 size_t sort_hist_bytes(int64_t cap);
+// gather_src/gather_dst (optional): the last pass also writes
+// gather_dst[r] = gather_src[sorted value r].
 int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
-                   int hi_bit, int radix_bits, void *hist, hipStream_t s);
+                   int hi_bit, int radix_bits, void *hist, hipStream_t s, const uint32_t *gather_src = nullptr,
+                   uint32_t *gather_dst = nullptr);
 int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
                    int hi_bit, int radix_bits, void *hist, hipStream_t s);
-// Depth-first binning helpers: gathers and key emission
-// in the depth order a stable depth sort produced.
-void launch_gather_u32(int64_t n, const uint32_t *src, const uint32_t *idx, uint32_t *dst, hipStream_t s);
+// Depth-first binning: key emission in the depth order a stable depth sort
+// produced.
 void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
                         const uint32_t *nt_sorted, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
                         uint32_t *vals, hipStream_t s);

@@ -136,7 +136,8 @@ template <typename K, int RB>
 __global__ void __launch_bounds__(RS_THREADS, sizeof(K) == 4 ? 3 : 2)
     k_rs_down(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
               uint32_t *__restrict__ vout, const uint32_t *n_dev, int64_t cap, int shift, uint32_t mask,
-              const uint32_t *__restrict__ offs, const uint32_t *__restrict__ total, int64_t tstride) {
+              const uint32_t *__restrict__ offs, const uint32_t *__restrict__ total, int64_t tstride,
+              const uint32_t *__restrict__ gsrc, uint32_t *__restrict__ gdst) {
     constexpr int NB = 1 << RB;
     __shared__ uint32_t s_wcnt[4][NB];   // per-wave digit counts, then each wave's offset inside the tile's digit run
     __shared__ uint32_t s_boff[NB];      // tile-local start of each digit's run
@@ -218,6 +219,7 @@ __global__ void __launch_bounds__(RS_THREADS, sizeof(K) == 4 ? 3 : 2)
             const uint32_t g = s_gdst[d] + (uint32_t)(i - (int)s_boff[d]);
             kout[g] = k;
             vout[g] = s_val[i];
+            if (gsrc) gdst[g] = gsrc[s_val[i]];   // optional gather through the sorted values
         }
         __syncthreads();   // the LDS of this tile is free for the next
     }
@@ -227,17 +229,18 @@ int64_t rs_tiles(int64_t n) { return (n + RS_TILE - 1) / RS_TILE > 0 ? (n + RS_T
 
 template <typename K, int RB>
 void rs_pass(K *ki, uint32_t *vi, K *ko, uint32_t *vo, const uint32_t *n_dev, int64_t cap, int64_t grid, int shift,
-             uint32_t mask, uint32_t *total, uint32_t *counts, int64_t tstride, hipStream_t s) {
+             uint32_t mask, uint32_t *total, uint32_t *counts, int64_t tstride, const uint32_t *gsrc, uint32_t *gdst,
+             hipStream_t s) {
     hipLaunchKernelGGL((k_rs_up<K, RB>), dim3((unsigned)grid), dim3(RS_THREADS), 0, s, ki, n_dev, cap, shift, mask,
                        counts, tstride);
     hipLaunchKernelGGL(k_rs_scan, dim3(1u << RB), dim3(RS_THREADS), 0, s, counts, tstride, n_dev, cap, total);
     hipLaunchKernelGGL((k_rs_down<K, RB>), dim3((unsigned)grid), dim3(RS_THREADS), 0, s, ki, vi, ko, vo, n_dev, cap,
-                       shift, mask, counts, total, tstride);
+                       shift, mask, counts, total, tstride, gsrc, gdst);
 }
 
 template <typename K>
 int rs_sort(K *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit, int hi_bit,
-            int rb, void *ws, hipStream_t s) {
+            int rb, void *ws, const uint32_t *gsrc, uint32_t *gdst, hipStream_t s) {
     if (rb < 4) rb = 4;
     if (rb > 8) rb = 8;
     const int kbits = (int)sizeof(K) * 8;
@@ -253,12 +256,15 @@ int rs_sort(K *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, i
         const uint32_t mask = (1u << wdt) - 1u;
         K *ki = keys[sel], *ko = keys[sel ^ 1];
         uint32_t *vi = vals[sel], *vo = vals[sel ^ 1];
+        const bool last = sh + rb >= hi_bit;
+        const uint32_t *gs = last ? gsrc : nullptr;
+        uint32_t *gd = last ? gdst : nullptr;
         switch (rb) {
-        case 4: rs_pass<K, 4>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, s); break;
-        case 5: rs_pass<K, 5>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, s); break;
-        case 6: rs_pass<K, 6>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, s); break;
-        case 7: rs_pass<K, 7>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, s); break;
-        default: rs_pass<K, 8>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, s); break;
+        case 4: rs_pass<K, 4>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
+        case 5: rs_pass<K, 5>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
+        case 6: rs_pass<K, 6>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
+        case 7: rs_pass<K, 7>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
+        default: rs_pass<K, 8>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
         }
         sel ^= 1;
     }
@@ -270,11 +276,13 @@ int rs_sort(K *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, i
 size_t sort_hist_bytes(int64_t cap) { return RS_HEAD + (size_t)rs_tiles(cap) * 256 * 4 + 256; }
 
 int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
-                   int hi_bit, int radix_bits, void *hist, hipStream_t s) {
-    return rs_sort<uint32_t>(keys, vals, n_dev, cap, n_hint, lo_bit, hi_bit, radix_bits, hist, s);
+                   int hi_bit, int radix_bits, void *hist, hipStream_t s, const uint32_t *gather_src,
+                   uint32_t *gather_dst) {
+    return rs_sort<uint32_t>(keys, vals, n_dev, cap, n_hint, lo_bit, hi_bit, radix_bits, hist, gather_src, gather_dst,
+                             s);
 }
 
 int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
                    int hi_bit, int radix_bits, void *hist, hipStream_t s) {
-    return rs_sort<uint64_t>(keys, vals, n_dev, cap, n_hint, lo_bit, hi_bit, radix_bits, hist, s);
+    return rs_sort<uint64_t>(keys, vals, n_dev, cap, n_hint, lo_bit, hi_bit, radix_bits, hist, nullptr, nullptr, s);
 }
