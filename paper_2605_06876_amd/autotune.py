@@ -6,7 +6,8 @@ same order, and every radix width gives the same stable order), and the
 backward differs only in the order of its float atomics.  For a workload the
 tuner times the caller's own step (a render + backward by default) for every
 blend configuration (LDS depth x tile order x persistent grid), then for every
-radix digit width with the best blend configuration, and keeps the fastest.
+radix digit width with the best blend configuration, and keeps the fastest
+(the better of two interleaved rounds per candidate, after a warm-up).
 Results are cached in a JSON file keyed by the workload.
 """
 import json
@@ -66,23 +67,23 @@ def autotune_step(ctx, run, key, reps=5, cache_path=DEFAULT_CACHE, use_cache=Tru
         api.set_tuning(ctx, **best)
         return best, cache[key].get("ms", {})
     times = {}
-    best, best_ms = None, float("inf")
-    for c in BLEND_CANDIDATES:
-        t = dict(c, radix_bits=8)
-        api.set_tuning(ctx, **t)
-        ms = time_step(run, reps)
-        times[name_of(t)] = ms
-        if ms < best_ms:
-            best, best_ms = t, ms
-    for rb in RADIX_CANDIDATES:
-        if rb == 8:
-            continue
-        t = dict(best, radix_bits=rb)
-        api.set_tuning(ctx, **t)
-        ms = time_step(run, reps)
-        times[name_of(t)] = ms
-        if ms < best_ms:
-            best, best_ms = t, ms
+    # Warm the device first (clocks, the library's first-use allocations), and
+    # keep the better of two interleaved rounds per candidate, so the first
+    # candidates are not timed cold.
+    for _ in range(3):
+        run()
+    torch.cuda.synchronize()
+
+    def rounds(cands):
+        for _ in range(2):
+            for t in cands:
+                api.set_tuning(ctx, **t)
+                ms = time_step(run, reps)
+                times[name_of(t)] = min(times.get(name_of(t), float("inf")), ms)
+        return min(cands, key=lambda t: times[name_of(t)])
+
+    best = rounds([dict(c, radix_bits=8) for c in BLEND_CANDIDATES])
+    best = rounds([dict(best, radix_bits=rb) for rb in RADIX_CANDIDATES])
     api.set_tuning(ctx, **best)
     if cache_path:
         cache[key] = dict(tuning=best, ms=times)

@@ -185,11 +185,29 @@ __global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *n_de
                          uint32_t *__restrict__ ranges) {
     int64_t n = *n_dev;
     if (n > cap) n = cap;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t t = keys[i];
-        if (t >= (uint64_t)n_tiles) continue;
-        if (i == 0 || keys[i - 1] != t) ranges[2 * t] = (uint32_t)i;
-        if (i == n - 1 || keys[i + 1] != t) ranges[2 * t + 1] = (uint32_t)(i + 1);
+    // four consecutive keys per thread from one 16-byte load (the buffers are
+    // 256-byte aligned with slack past their capacity), plus one neighbour on
+    // each side; a sentinel stands for "no key" at the ends
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
+    const int64_t chunks = (n + 3) / 4;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < chunks; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i0 = 4 * c;
+        const uint4 q = *reinterpret_cast<const uint4 *>(keys + i0);
+        const uint32_t k[4] = {q.x, q.y, q.z, q.w};
+        uint32_t prev = i0 > 0 ? keys[i0 - 1] : NONE;
+        const uint32_t after = i0 + 4 < n ? keys[i0 + 4] : NONE;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int64_t i = i0 + j;
+            if (i >= n) break;
+            const uint32_t t = k[j];
+            const uint32_t nx = j < 3 ? (i + 1 < n ? k[j + 1] : NONE) : after;
+            if (t < (uint64_t)n_tiles) {
+                if (prev != t) ranges[2 * t] = (uint32_t)i;
+                if (nx != t) ranges[2 * t + 1] = (uint32_t)(i + 1);
+            }
+            prev = t;
+        }
     }
 }
 
