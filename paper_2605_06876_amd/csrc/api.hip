@@ -458,7 +458,8 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     }
     {
         StageTimer t(ctx, AS_STAGE_EMIT, s);
-        launch_emit_sorted(n, order, vt, f->box, f->nt_sorted, f->offsets, f->key_cap, f->keys[0], f->vals[0], s);
+        launch_emit_sorted(n, order, vt, f->box, f->nt_sorted, f->offsets, f->key_cap, f->keys[0], f->vals[0],
+                           f->ranges, tiles, s);
     }
     int sel;
     {

@@ -130,9 +130,14 @@ __global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *
                                                      const short4 *__restrict__ box,
                                                      const uint32_t *__restrict__ nt_sorted,
                                                      const uint32_t *__restrict__ offsets, int64_t key_cap,
-                                                     uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+                                                     uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                     uint32_t *__restrict__ ranges, int64_t range_words) {
     __shared__ uint32_t s_off[4][64], s_id[4][64], s_nt[4][64];
     __shared__ int32_t s_t0[4][64], s_bw[4][64], s_tx[4][64];
+    // the tile ranges start empty: tiles without keys keep [0, 0)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < range_words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        ranges[i] = 0u;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t r0 = (int64_t)blockIdx.x * blockDim.x + w * 64;
     if (r0 >= n) return;   // wave-uniform
@@ -263,15 +268,19 @@ void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total,
 
 void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
                         const uint32_t *nt_sorted, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
-                        uint32_t *vals, hipStream_t s) {
-    if (n == 0) return;
+                        uint32_t *vals, uint32_t *ranges, int64_t n_tiles, hipStream_t s) {
+    if (n == 0) {
+        fill_impl<uint32_t>(ranges, 0u, 2 * n_tiles, s);
+        return;
+    }
     hipLaunchKernelGGL(k_emit_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order, vt,
-                       reinterpret_cast<const short4 *>(box), nt_sorted, offsets, key_cap, keys, vals);
+                       reinterpret_cast<const short4 *>(box), nt_sorted, offsets, key_cap, keys, vals, ranges,
+                       2 * n_tiles);
 }
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
                    hipStream_t s) {
-    fill_impl<uint32_t>(ranges, 0u, 2 * n_tiles, s);
+    // the key emission has zeroed the ranges
     hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, s, keys, n_dev, cap, n_tiles, ranges);
 }
 

@@ -205,11 +205,13 @@ int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, 
                    uint32_t *gather_dst = nullptr);
 int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
                    int hi_bit, int radix_bits, void *hist, hipStream_t s);
-// Depth-first binning: key emission in the depth order a stable depth sort
-// produced.
+// Depth-first binning: keys emitted in the depth order a stable depth sort
+// produced; the emission also empties the tile ranges ([0, 0) for every tile)
+// ahead of launch_ranges.
 void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
                         const uint32_t *nt_sorted, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
-                        uint32_t *vals, hipStream_t s);
+                        uint32_t *vals, uint32_t *ranges, int64_t n_tiles, hipStream_t s);
+// [start, end) of each tile with keys (ranges emptied by launch_emit_sorted).
 void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
                    hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
