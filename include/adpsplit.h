@@ -206,7 +206,13 @@ as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as
 
 /* Reverse pass of the last as_render into `frame` (the differentiable
  * rasterizer of Sec. 3): recomputes the blend per tile backwards from the
- * stored final transmittance and last-contributor index.
+ * stored final transmittance and last-contributor index.  The first reverse
+ * pass on a frame allocates its checkpoint buffer (4 KB per tile per
+ * checkpoint, 3 checkpoints per tile, held until as_frame_destroy); renders
+ * after that write per-pixel checkpoints at their batch boundaries, and the
+ * reverse pass splits long tile lists at them into independent segments.  If
+ * that allocation fails the reverse pass walks each tile in one piece (same
+ * results up to float rounding, no error).
  *   dL_dimage : [3][H][W]
  *   grads     : out, overwritten; same layout and degree as g, stride g->n
  *   g2d_norm  : NULL or [n]; += |dL/d(mean2d)| (pixel units) for each Gaussian
