@@ -211,8 +211,9 @@ as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as
  * checkpoint, 3 checkpoints per tile, held until as_frame_destroy); renders
  * after that write per-pixel checkpoints at their batch boundaries, and the
  * reverse pass splits long tile lists at them into independent segments.  If
- * that allocation fails the reverse pass walks each tile in one piece (same
- * results up to float rounding, no error).
+ * that allocation fails, or the first reverse pass runs inside a graph
+ * capture (which allocates nothing), the reverse pass walks each tile in one
+ * piece (same results up to float rounding, no error).
  *   dL_dimage : [3][H][W]
  *   grads     : out, overwritten; same layout and degree as g, stride g->n
  *   g2d_norm  : NULL or [n]; += |dL/d(mean2d)| (pixel units) for each Gaussian

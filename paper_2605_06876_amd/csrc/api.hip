@@ -530,8 +530,9 @@ as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame 
     const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
     // The forward writes checkpoints once their buffer exists; the first
     // reverse pass allocates it (a failed allocation only costs speed: the
-    // reverse pass then walks each tile in one piece).
-    if (!f->ckpt) {
+    // reverse pass then walks each tile in one piece).  Never while the stream
+    // is being captured: an allocation there would invalidate the graph.
+    if (!f->ckpt && !capturing(s)) {
         if (dmalloc(&f->ckpt, f->tile_cap * AS_CK_MAX * 256 * 4) != hipSuccess) {
             (void)hipGetLastError();
             f->ckpt = nullptr;

@@ -208,6 +208,39 @@ def test_graph_replay_matches_eager(ctx):
     graph.close()
 
 
+def test_first_backward_inside_a_capture(ctx):
+    """The first reverse pass on a frame allocates its checkpoint buffer,
+    except inside a graph capture, which must allocate nothing: captured as a
+    frame's first backward, render + backward replays like the eager step."""
+    scene = synth.scene_clusters(4000, seed=14, sh_degree=1, log_scale_mu=-3.8, log_scale_sd=0.5)
+    g = api.Gaussians.from_scene(scene)
+    cams = cams_for([(80, 64), (64, 96)], seed=10)
+    dLs = [torch.from_numpy(np.random.default_rng(20 + k).normal(size=(3, c.height, c.width)).astype(np.float32)).cuda()
+           for k, c in enumerate(cams)]
+    s = torch.cuda.Stream()
+    frame = api.BatchFrame.for_views(ctx, g.n, cams, key_cap=1 << 20, auto_grow=False)
+    out_imgs = [torch.empty(3, c.height, c.width, device="cuda") for c in cams]
+    grads = api.Gaussians.empty(g.n, 1)
+    with torch.cuda.stream(s):   # a render only: the backward is first seen inside the capture
+        api.render_batch(ctx, g, cams, frame, images=out_imgs)
+    s.synchronize()
+
+    def step():
+        api.render_batch(ctx, g, cams, frame, images=out_imgs)
+        api.render_backward_batch(ctx, g, frame, dLs, grads=grads)
+
+    graph = api.Graph.capture(ctx, step, s)
+    ref_frame = api.BatchFrame.for_views(ctx, g.n, cams)
+    for rep in range(3):
+        graph.launch(s)
+        s.synchronize()
+        got_g = [getattr(grads, f).clone() for f in FIELDS]
+        _, want_g = _replay_check(ctx, g, cams, ref_frame, None, dLs, torch.cuda.current_stream())
+        for i, f in enumerate(FIELDS):
+            assert rel(got_g[i], want_g[i]) <= 1e-5, "replay %d %s" % (rep, f)
+    graph.close()
+
+
 def test_capture_refuses_a_synchronising_frame(ctx):
     g = api.Gaussians.from_scene(synth.scene_uniform_sh0(200, seed=2))
     cam = cams_for([(32, 32)], seed=2)[0]
