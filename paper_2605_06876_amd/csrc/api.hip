@@ -337,8 +337,8 @@ as_status as_frame_get_view_of(const as_frame *f, int32_t view, as_frame_view *v
     v->t_final = f->t_final + pb; v->last = f->last + pb; v->n_contrib = f->n_contrib + pb; v->dom = f->dom + pb;
     v->err = f->err + pb;
     v->err_minmax = f->err_minmax + 2 * (have ? view : 0);
-    v->grad2d = f->grad2d + eb;
-    v->grad2d_stride = f->ent_cap;
+    v->grad2d = f->grad2d + 9 * eb;
+    v->grad2d_stride = 9;
     return AS_OK;
 }
 
@@ -540,13 +540,13 @@ as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame 
     }
     {
         StageTimer t(ctx, AS_STAGE_BLEND_BWD, s);
-        launch_fill_rows_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9, ents, f->ent_cap, s);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9 * ents, s);
         launch_blend_bwd(f, f->vals[f->sorted_sel], f->use_order ? f->tile_order_bwd : nullptr, bl, vt, dl,
-                         f->grad2d, f->ent_cap, s);
+                         f->grad2d, s);
     }
     {
         StageTimer t(ctx, AS_STAGE_PROJECT_BWD, s);
-        launch_project_bwd(gptrs(g), vt, f->ntiles, f->grad2d, f->ent_cap, mptrs(grads), g2d_norm, vis_count, s);
+        launch_project_bwd(gptrs(g), vt, f->ntiles, f->grad2d, mptrs(grads), g2d_norm, vis_count, s);
     }
     return launch_status("as_render_backward");
 }

@@ -222,14 +222,6 @@ __global__ void k_fill(T *p, T v, int64_t n) {
         p[i] = v;
 }
 
-// rows x n elements, rows `stride` elements apart (grid.y = rows)
-template <typename T>
-__global__ void k_fill_rows(T *p, T v, int64_t n, int64_t stride) {
-    T *row = p + (int64_t)blockIdx.y * stride;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        row[i] = v;
-}
-
 __global__ void k_fp64_ops(const double *a, const double *b, int64_t n, double *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -287,12 +279,6 @@ void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) { fill_impl<uint8_t>(p, v, n, s); }
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) { fill_impl<uint32_t>(p, v, n, s); }
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) { fill_impl<uint64_t>(p, v, n, s); }
-void launch_fill_rows_u32(uint32_t *p, uint32_t v, int rows, int64_t n, int64_t stride, hipStream_t s) {
-    if (n <= 0 || rows <= 0) return;
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL((k_fill_rows<uint32_t>), dim3((unsigned)blocks, (unsigned)rows), dim3(256), 0, s, p, v, n, stride);
-}
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) { fill_impl<int64_t>(p, v, n, s); }
 void launch_copy_u32(const uint32_t *src, uint32_t *dst, int64_t n, hipStream_t s) {
     if (n <= 0) return;

@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
                                                          const uint32_t *__restrict__ last_in,
                                                          const uint32_t *__restrict__ ncontrib_in,
                                                          const ViewImagesC dLs, float *__restrict__ grad2d,
-                                                         int64_t stride, uint32_t *queue) {
+                                                         uint32_t *queue) {
     constexpr int R = BATCH / BWD_BLOCK;
     __shared__ BwdShared<BATCH> sh;
     __shared__ uint32_t s_next;
@@ -604,20 +604,30 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
             // gradients.  With p = -(a dx^2 + c dy^2)/2 - b dx dy (unscaled
             // conic a, b, c): dp/dmean = -(a dx + b dy, c dy + b dx),
             // dp/d(a, b, c) = -(dx^2/2, dx dy, dy^2/2) and dalpha/do = alpha/o.
-            for (int i = tid; i < (int)(b1 - b0); i += BWD_BLOCK) {
+            // Lanes take (entry, value) pairs, so the nine atomics of an entry
+            // go to the nine consecutive words of its entry-major row from
+            // neighbouring lanes of one instruction.
+            for (int f = tid; f < 9 * (int)(b1 - b0); f += BWD_BLOCK) {
+                const int i = f / 9, k = f - 9 * i;
                 if (sh.gflag[i]) {
                     const float4 q0 = sh.rec[i].mc, q1 = sh.rec[i].cc, q2 = sh.rec[i].ex;
                     const int64_t id = (int64_t)__float_as_uint(q2.z);
                     const float a = -2.0f * LN2 * q0.z, b = -LN2 * q0.w, cc = -2.0f * LN2 * q1.x;
-                    const float s0 = sh.gacc[0][i], sx = sh.gacc[1][i], sy = sh.gacc[2][i];
-                    const float gv[9] = {-(a * sx + b * sy),       -(cc * sy + b * sx), -0.5f * sh.gacc[3][i],
-                                         -sh.gacc[4][i],           -0.5f * sh.gacc[5][i], s0 * q2.w,
-                                         sh.gacc[6][i],            sh.gacc[7][i],         sh.gacc[8][i]};
+                    float gv = sh.gacc[k][i];   // colour gradients (k = 6, 7, 8) as summed
+                    if (k == 0) gv = -(a * sh.gacc[1][i] + b * sh.gacc[2][i]);
+                    else if (k == 1) gv = -(cc * sh.gacc[2][i] + b * sh.gacc[1][i]);
+                    else if (k == 2) gv = -0.5f * sh.gacc[3][i];
+                    else if (k == 3) gv = -sh.gacc[4][i];
+                    else if (k == 4) gv = -0.5f * sh.gacc[5][i];
+                    else if (k == 5) gv = sh.gacc[0][i] * q2.w;
+                    atomicAdd(&grad2d[id * 9 + k], gv);
+                }
+            }
+            __syncthreads();
+            for (int i = tid; i < (int)(b1 - b0); i += BWD_BLOCK) {
+                if (sh.gflag[i]) {
 #pragma unroll
-                    for (int k = 0; k < 9; k++) {
-                        atomicAdd(&grad2d[k * stride + id], gv[k]);
-                        sh.gacc[k][i] = 0.f;
-                    }
+                    for (int k = 0; k < 9; k++) sh.gacc[k][i] = 0.f;
                     sh.gflag[i] = 0;
                 }
             }
@@ -820,8 +830,7 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
 }
 
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
-                      const ViewTable &vt, const ViewImagesC &dL_dimage, float *grad2d, int64_t g2d_stride,
-                      hipStream_t s) {
+                      const ViewTable &vt, const ViewImagesC &dL_dimage, float *grad2d, hipStream_t s) {
     const int tiles = vt.tile_base[vt.n_views];
     if (tiles == 0) return;
     const short4 *b4 = reinterpret_cast<const short4 *>(f->box);
@@ -842,7 +851,7 @@ void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         }                                                                                                          \
         hipLaunchKernelGGL((k_blend_bwd<B, PER>), dim3(grid), dim3(BWD_BLOCK), 0, s, f->ranges, f->bwd_items,     \
                            f->n_items, f->tile_hi, ckp, seg_len, vals, f->rec, b4, vt, f->t_final, f->last,        \
-                           f->n_contrib, dL_dimage, grad2d, g2d_stride, f->queue + 1);                             \
+                           f->n_contrib, dL_dimage, grad2d, f->queue + 1);                                         \
     } while (0)
     // the reverse pass stages half the forward's depth: two waves per tile
     if (bl.persistent) {

@@ -96,7 +96,7 @@ struct as_frame {
     int16_t *box;          // [entries][4]
     uint32_t *ntiles;
     uint32_t *offsets;     // key offsets, in depth order
-    float *grad2d;         // [9][ent_cap]
+    float *grad2d;         // [ent_cap][9] entry-major: the 2D gradients of entry e at 9 e .. 9 e + 8
     // depth-first binning: entries sorted by depth, then keys by tile
     uint32_t *dkeys[2];
     uint32_t *dvals[2];
@@ -184,7 +184,7 @@ void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, in
 // projection backward (project_bwd.hip): one Gaussian set seen in every view
 // of vt; gradients summed over the views in view order
 void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t *ntiles, const float *grad2d,
-                        int64_t g2d_stride, GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s);
+                        GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s);
 
 // scans (binning.hip): exclusive scans with the total written to *total
 size_t scan_tmp_bytes(int64_t n);
@@ -217,7 +217,6 @@ void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
-void launch_fill_rows_u32(uint32_t *p, uint32_t v, int rows, int64_t n, int64_t stride, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 void launch_copy_u32(const uint32_t *src, uint32_t *dst, int64_t n, hipStream_t s);
 
@@ -236,8 +235,7 @@ void launch_after_fwd(const as_frame *f, const ViewTable &vt, const ViewImagesC 
 void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
                       const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s);
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
-                      const ViewTable &vt, const ViewImagesC &dL_dimage, float *grad2d, int64_t g2d_stride,
-                      hipStream_t s);
+                      const ViewTable &vt, const ViewImagesC &dL_dimage, float *grad2d, hipStream_t s);
 
 // optimisation loop (train.hip)
 int train_set_rows(int deg);

@@ -24,7 +24,7 @@ __device__ __forceinline__ void put(float *p, float v, bool acc) { *p = acc ? *p
 
 template <int DEG>
 __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam cam, const uint32_t *__restrict__ ntiles,
-                                                     const float *__restrict__ g2d, int64_t gs, GradPtrs out,
+                                                     const float *__restrict__ g2d, GradPtrs out,
                                                      float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count,
                                                      int accum) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -40,10 +40,10 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
         for (int k = 0; k < nk * 3; k++) out.sh[(int64_t)k * os + i] = 0.f;
         return;
     }
-    const double gm0 = g2d[0 * gs + i], gm1 = g2d[1 * gs + i];
-    const double gca = g2d[2 * gs + i], gcb = g2d[3 * gs + i], gcc = g2d[4 * gs + i];
-    const double gop = g2d[5 * gs + i];
-    const double grgb[3] = {g2d[6 * gs + i], g2d[7 * gs + i], g2d[8 * gs + i]};
+    const double gm0 = g2d[i * 9 + 0], gm1 = g2d[i * 9 + 1];
+    const double gca = g2d[i * 9 + 2], gcb = g2d[i * 9 + 3], gcc = g2d[i * 9 + 4];
+    const double gop = g2d[i * 9 + 5];
+    const double grgb[3] = {g2d[i * 9 + 6], g2d[i * 9 + 7], g2d[i * 9 + 8]};
     if (g2d_norm) g2d_norm[i] += (float)sqrt(gm0 * gm0 + gm1 * gm1);
     if (vis_count) vis_count[i] += 1;
 
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
 // All views of a batch in one pass per Gaussian.
 template <int DEG>
 __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTable vt, const uint32_t *__restrict__ ntiles,
-                                                     const float *__restrict__ g2d, int64_t gs, GradPtrs out,
+                                                     const float *__restrict__ g2d, GradPtrs out,
                                                      float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count) {
     constexpr int nk = (DEG + 1) * (DEG + 1);
     // SH gradient accumulators live in LDS (thread-private columns), not registers
@@ -239,10 +239,10 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTabl
         const int64_t e = (int64_t)vt.ent_base[v] + i;
         if (ntiles[e] == 0) continue;
         const DevCam &cam = vt.cam[v];
-        const double gm0 = g2d[0 * gs + e], gm1 = g2d[1 * gs + e];
-        const double gca = g2d[2 * gs + e], gcb = g2d[3 * gs + e], gcc = g2d[4 * gs + e];
-        const double grgb[3] = {g2d[6 * gs + e], g2d[7 * gs + e], g2d[8 * gs + e]};
-        gop += g2d[5 * gs + e];
+        const double gm0 = g2d[e * 9 + 0], gm1 = g2d[e * 9 + 1];
+        const double gca = g2d[e * 9 + 2], gcb = g2d[e * 9 + 3], gcc = g2d[e * 9 + 4];
+        const double grgb[3] = {g2d[e * 9 + 6], g2d[e * 9 + 7], g2d[e * 9 + 8]};
+        gop += g2d[e * 9 + 5];
         nrm += (float)sqrt(gm0 * gm0 + gm1 * gm1);
         vis += 1;
 
@@ -404,23 +404,23 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTabl
 }  // namespace
 
 void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t *ntiles, const float *grad2d,
-                        int64_t g2d_stride, GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s) {
+                        GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
     if (vt.n_views == 1) {
         const DevCam &cam = vt.cam[0];
         switch (g.deg) {
-        case 0: hipLaunchKernelGGL(k_project_bwd_view<0>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count, 0); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd_view<1>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count, 0); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd_view<2>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count, 0); break;
-        default: hipLaunchKernelGGL(k_project_bwd_view<3>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count, 0); break;
+        case 0: hipLaunchKernelGGL(k_project_bwd_view<0>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, out, g2d_norm, vis_count, 0); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd_view<1>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, out, g2d_norm, vis_count, 0); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd_view<2>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, out, g2d_norm, vis_count, 0); break;
+        default: hipLaunchKernelGGL(k_project_bwd_view<3>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, out, g2d_norm, vis_count, 0); break;
         }
         return;
     }
     switch (g.deg) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, g2d_stride, out, g2d_norm, vis_count); break;
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out, g2d_norm, vis_count); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out, g2d_norm, vis_count); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out, g2d_norm, vis_count); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out, g2d_norm, vis_count); break;
     }
 }
