@@ -523,6 +523,15 @@ def main():
             pk = PEAK_HBM_GBS if b == "hbm" else PEAK_VALU_TOPS
             all_roofs[k] = dict(ms=round(per_step[k], 4), achieved=round(ach, 2),
                                 unit="GB/s" if b == "hbm" else "TOP/s", frac=round(ach / pk, 4))
+    # both blends against the VALU roofline together (the forward stage
+    # includes the single-block post-forward kernel)
+    blend_roof = None
+    if per_step.get("blend_fwd", 0) > 0 and per_step.get("blend_bwd", 0) > 0:
+        t_fb = (per_step["blend_fwd"] + per_step["blend_bwd"]) / 1e3
+        ach = P_alg * (OPS_FWD_PER_PAIR + OPS_BWD_PER_PAIR) / 1e12 / t_fb
+        blend_roof = dict(bound="alu", achieved=round(ach, 3), peak=round(PEAK_VALU_TOPS, 2), unit="TOP/s",
+                          frac=round(ach / PEAK_VALU_TOPS, 4), stages=["blend_fwd", "blend_bwd"],
+                          ms=round(t_fb * 1e3, 4))
     mpix = W * H / 1e6
     value = mpix / (res["ms"] / 1e3)
     fb_ms = sum(per_step.get(k, 0.0) for k in ("project", "scan", "emit", "sort", "ranges", "blend_fwd", "blend_bwd",
@@ -548,6 +557,7 @@ def main():
         "roofline": roof,
         "stage_ms": {k: round(v, 4) for k, v in per_step.items()},
         "stage_roofline": all_roofs,
+        "blend_roofline": blend_roof,
         "fwd_bwd_kernels_ms": round(fb_ms, 4),
     }
     if not args.no_densify:
