@@ -263,14 +263,15 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                 const float alpha_a = fminf(ALPHA_MAX, rawa), alpha_b = fminf(ALPHA_MAX, rawb);
                 const bool oka = (ma & lg.pbits) == lg.pbits && alpha_a >= ALPHA_MIN;   // box holds the pixel
                 const bool okb = two && (mb & lg.pbits) == lg.pbits && alpha_b >= ALPHA_MIN;
-                // first record
-                float testT = T * (1.0f - alpha_a);
-                if (oka && testT < T_STOP) {
-                    done = 1;
-                    break;
-                }
-                // a non-contributor adds exactly zero and changes nothing
-                float wgt = oka ? alpha_a * T : 0.0f;
+                // Both records are decided with selects and the loop leaves
+                // once after them, so the second record's loads are not held
+                // back behind a branch.  A record that would take T below the
+                // stop threshold is not added, and nothing after it is; a
+                // non-contributor adds exactly zero and changes nothing.
+                const float tA = T * (1.0f - alpha_a);
+                const bool stopA = oka && tA < T_STOP;
+                const bool useA = oka && !stopA;
+                float wgt = useA ? alpha_a * T : 0.0f;
                 C0 += wgt * a1.z;
                 C1 += wgt * a1.w;
                 C2 += wgt * a2.x;
@@ -278,16 +279,13 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                     wbest = wgt;
                     dom = (int32_t)__float_as_uint(a2.z);
                 }
-                T = oka ? testT : T;
-                last = oka ? b0 + (uint32_t)j0 : last;
-                nc += oka ? 1u : 0u;
-                // second record
-                testT = T * (1.0f - alpha_b);
-                if (okb && testT < T_STOP) {
-                    done = 1;
-                    break;
-                }
-                wgt = okb ? alpha_b * T : 0.0f;
+                T = useA ? tA : T;
+                last = useA ? b0 + (uint32_t)j0 : last;
+                nc += useA ? 1u : 0u;
+                const float tB = T * (1.0f - alpha_b);
+                const bool stopB = !stopA && okb && tB < T_STOP;
+                const bool useB = !stopA && okb && !stopB;
+                wgt = useB ? alpha_b * T : 0.0f;
                 C0 += wgt * b1q.z;
                 C1 += wgt * b1q.w;
                 C2 += wgt * b2q.x;
@@ -295,9 +293,13 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                     wbest = wgt;
                     dom = (int32_t)__float_as_uint(b2q.z);
                 }
-                T = okb ? testT : T;
-                last = okb ? b0 + (uint32_t)j1 : last;
-                nc += okb ? 1u : 0u;
+                T = useB ? tB : T;
+                last = useB ? b0 + (uint32_t)j1 : last;
+                nc += useB ? 1u : 0u;
+                if (stopA || stopB) {
+                    done = 1;
+                    break;
+                }
             }
         }
 
