@@ -473,7 +473,7 @@ def measured_traffic(stage):
 def main():
     args = _args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'Sharding'). "
+        print("bench.py measures one GPU: the library runs on a single device and has no multi-GPU path. "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
