@@ -1,8 +1,10 @@
 // Stable LSD radix sort of (key, u32 value) pairs for gfx950, reduce-then-scan
 // organisation: no block ever waits on another.
 //
-// Keys are taken in tiles of 4096 (256 threads x 16).  Each digit pass is three
-// launches:
+// Keys are taken in tiles of 4096 (256 threads x 16 rounds), or of 2048
+// (256 x 8) when the element count hint gives fewer than 512 of the larger
+// tiles: one block per CU leaves each CU's loads waiting on each other, two
+// overlap.  Each digit pass is three launches:
 //   up     per-tile digit counts, from an LDS histogram kept in 8 copies (a
 //          lane adds into copy lane % 8, so lanes with equal digits mostly hit
 //          different words), stored digit-major: counts[d][tile];
@@ -11,7 +13,7 @@
 //   down   each tile scans the digit totals for the start of every digit's
 //          output range, ranks its keys among equal digits (per wave: RB ballots
 //          give the lanes with the same digit; per-wave counters in LDS carry
-//          offsets across the wave's 16 rounds, which keeps the sort stable),
+//          offsets across the wave's rounds, which keeps the sort stable),
 //          reorders the tile by digit in LDS and writes each digit's run to its
 //          offset, consecutive threads to consecutive addresses.
 // All of a tile's loads are issued before the ranking starts: the wave
@@ -24,14 +26,18 @@
 // 4096 blocks); blocks loop over tiles until the device-side count is covered.
 //
 // Workspace (sort_hist_bytes(cap)): digit totals [256] u32, then counts
-// [256][tiles(cap)] u32.
+// [256][tiles(cap)] u32, sized for the 2048-key tiles and used with the row
+// stride of the tile size a sort takes.
 #include "internal.h"
 
 namespace {
 
 constexpr int RS_THREADS = 256;
-constexpr int RS_ROUNDS = 16;                       // keys per thread and tile
-constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;     // 4096 keys per tile
+// Keys per thread and tile: 16 (4096-key tiles), or 8 (2048-key tiles) where
+// the larger tiles would give the device fewer than two blocks per CU.
+constexpr int RS_ROUNDS_BIG = 16, RS_ROUNDS_SMALL = 8;
+constexpr int RS_TILE_MIN = RS_THREADS * RS_ROUNDS_SMALL;
+constexpr int64_t RS_SMALL_BELOW = 512;             // 4096-key tiles under which the small tiles are used
 constexpr int RS_COPIES = 8;                        // LDS histogram copies of the up pass
 constexpr int64_t RS_MAX_BLOCKS = 4096;
 constexpr size_t RS_HEAD = 256 * 4;                 // digit totals, bytes
@@ -41,8 +47,8 @@ __device__ __forceinline__ int64_t clamp_n(const uint32_t *n_dev, int64_t cap) {
     return n > cap ? cap : n;
 }
 
-__device__ __forceinline__ int64_t tiles_of(int64_t n, int64_t tstride) {
-    const int64_t t = (n + RS_TILE - 1) / RS_TILE;
+__device__ __forceinline__ int64_t tiles_of(int64_t n, int64_t tstride, int tile) {
+    const int64_t t = (n + tile - 1) / tile;
     return t < tstride ? t : tstride;
 }
 
@@ -62,15 +68,16 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *s_wave
     return pre + inc - v;
 }
 
-template <typename K, int RB>
+template <typename K, int RB, int RS_ROUNDS>
 __global__ void __launch_bounds__(RS_THREADS) k_rs_up(const K *__restrict__ keys, const uint32_t *n_dev, int64_t cap,
                                                       int shift, uint32_t mask, uint32_t *__restrict__ counts,
                                                       int64_t tstride) {
     constexpr int NB = 1 << RB, HS = NB + 1;   // copy stride: equal digits of different copies sit in different banks
+    constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
     __shared__ uint32_t s_h[RS_COPIES * HS];
     const int tid = threadIdx.x;
     const int64_t n = clamp_n(n_dev, cap);
-    const int64_t T = tiles_of(n, tstride);
+    const int64_t T = tiles_of(n, tstride, RS_TILE);
     const int cp = (tid & (RS_COPIES - 1)) * HS;
     for (int64_t t = blockIdx.x; t < T; t += gridDim.x) {
         for (int i = tid; i < RS_COPIES * HS; i += RS_THREADS) s_h[i] = 0;
@@ -100,12 +107,13 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_up(const K *__restrict__ keys
 // One block per digit: the column's exclusive prefix over tiles, in place,
 // and the column's total.
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scan(uint32_t *__restrict__ counts, int64_t tstride,
-                                                        const uint32_t *n_dev, int64_t cap, uint32_t *__restrict__ total) {
+                                                        const uint32_t *n_dev, int64_t cap, int tile,
+                                                        uint32_t *__restrict__ total) {
     constexpr int PER = 8;   // consecutive tiles per thread
     __shared__ uint32_t s_wave[4];
     __shared__ uint32_t s_tot;
     const int tid = threadIdx.x, d = blockIdx.x;
-    const int64_t T = tiles_of(clamp_n(n_dev, cap), tstride);
+    const int64_t T = tiles_of(clamp_n(n_dev, cap), tstride, tile);
     uint32_t carry = 0;
     uint32_t *col = counts + (int64_t)d * tstride;
     for (int64_t t0 = 0; t0 < T; t0 += RS_THREADS * PER) {
@@ -132,13 +140,14 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scan(uint32_t *__restrict__ c
     if (tid == 0) total[d] = carry;
 }
 
-template <typename K, int RB>
+template <typename K, int RB, int RS_ROUNDS>
 __global__ void __launch_bounds__(RS_THREADS, sizeof(K) == 4 ? 3 : 2)
     k_rs_down(const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
               uint32_t *__restrict__ vout, const uint32_t *n_dev, int64_t cap, int shift, uint32_t mask,
               const uint32_t *__restrict__ offs, const uint32_t *__restrict__ total, int64_t tstride,
               const uint32_t *__restrict__ gsrc, uint32_t *__restrict__ gdst) {
     constexpr int NB = 1 << RB;
+    constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
     __shared__ uint32_t s_wcnt[4][NB];   // per-wave digit counts, then each wave's offset inside the tile's digit run
     __shared__ uint32_t s_boff[NB];      // tile-local start of each digit's run
     __shared__ uint32_t s_gdst[NB];      // output offset of the tile's run of each digit
@@ -147,7 +156,7 @@ __global__ void __launch_bounds__(RS_THREADS, sizeof(K) == 4 ? 3 : 2)
     __shared__ uint32_t s_val[RS_TILE];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t n = clamp_n(n_dev, cap);
-    const int64_t T = tiles_of(n, tstride);
+    const int64_t T = tiles_of(n, tstride, RS_TILE);
     const uint64_t lt = lanemask_lt();
     for (int64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
         // the tile's offset in each digit's column and the digit totals are
@@ -225,17 +234,30 @@ __global__ void __launch_bounds__(RS_THREADS, sizeof(K) == 4 ? 3 : 2)
     }
 }
 
-int64_t rs_tiles(int64_t n) { return (n + RS_TILE - 1) / RS_TILE > 0 ? (n + RS_TILE - 1) / RS_TILE : 1; }
+int64_t rs_tiles(int64_t n, int tile) { return (n + tile - 1) / tile > 0 ? (n + tile - 1) / tile : 1; }
+
+template <typename K, int RB, int R>
+void rs_pass_r(K *ki, uint32_t *vi, K *ko, uint32_t *vo, const uint32_t *n_dev, int64_t cap, int64_t grid, int shift,
+               uint32_t mask, uint32_t *total, uint32_t *counts, int64_t tstride, const uint32_t *gsrc, uint32_t *gdst,
+               hipStream_t s) {
+    hipLaunchKernelGGL((k_rs_up<K, RB, R>), dim3((unsigned)grid), dim3(RS_THREADS), 0, s, ki, n_dev, cap, shift, mask,
+                       counts, tstride);
+    hipLaunchKernelGGL(k_rs_scan, dim3(1u << RB), dim3(RS_THREADS), 0, s, counts, tstride, n_dev, cap,
+                       RS_THREADS * R, total);
+    hipLaunchKernelGGL((k_rs_down<K, RB, R>), dim3((unsigned)grid), dim3(RS_THREADS), 0, s, ki, vi, ko, vo, n_dev,
+                       cap, shift, mask, counts, total, tstride, gsrc, gdst);
+}
 
 template <typename K, int RB>
-void rs_pass(K *ki, uint32_t *vi, K *ko, uint32_t *vo, const uint32_t *n_dev, int64_t cap, int64_t grid, int shift,
-             uint32_t mask, uint32_t *total, uint32_t *counts, int64_t tstride, const uint32_t *gsrc, uint32_t *gdst,
-             hipStream_t s) {
-    hipLaunchKernelGGL((k_rs_up<K, RB>), dim3((unsigned)grid), dim3(RS_THREADS), 0, s, ki, n_dev, cap, shift, mask,
-                       counts, tstride);
-    hipLaunchKernelGGL(k_rs_scan, dim3(1u << RB), dim3(RS_THREADS), 0, s, counts, tstride, n_dev, cap, total);
-    hipLaunchKernelGGL((k_rs_down<K, RB>), dim3((unsigned)grid), dim3(RS_THREADS), 0, s, ki, vi, ko, vo, n_dev, cap,
-                       shift, mask, counts, total, tstride, gsrc, gdst);
+void rs_pass(bool small, K *ki, uint32_t *vi, K *ko, uint32_t *vo, const uint32_t *n_dev, int64_t cap, int64_t grid,
+             int shift, uint32_t mask, uint32_t *total, uint32_t *counts, int64_t tstride, const uint32_t *gsrc,
+             uint32_t *gdst, hipStream_t s) {
+    if (small)
+        rs_pass_r<K, RB, RS_ROUNDS_SMALL>(ki, vi, ko, vo, n_dev, cap, grid, shift, mask, total, counts, tstride, gsrc,
+                                          gdst, s);
+    else
+        rs_pass_r<K, RB, RS_ROUNDS_BIG>(ki, vi, ko, vo, n_dev, cap, grid, shift, mask, total, counts, tstride, gsrc,
+                                        gdst, s);
 }
 
 template <typename K>
@@ -245,8 +267,11 @@ int rs_sort(K *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, i
     if (rb > 8) rb = 8;
     const int kbits = (int)sizeof(K) * 8;
     if (hi_bit > kbits) hi_bit = kbits;
-    const int64_t tstride = rs_tiles(cap);
-    int64_t grid = rs_tiles(n_hint < cap ? n_hint : cap);
+    const int64_t nh = n_hint < cap ? n_hint : cap;
+    const bool small = rs_tiles(nh, RS_THREADS * RS_ROUNDS_BIG) < RS_SMALL_BELOW;
+    const int tile = RS_THREADS * (small ? RS_ROUNDS_SMALL : RS_ROUNDS_BIG);
+    const int64_t tstride = rs_tiles(cap, tile);   // within the workspace: sized for the smallest tile
+    int64_t grid = rs_tiles(nh, tile);
     if (grid > RS_MAX_BLOCKS) grid = RS_MAX_BLOCKS;
     uint32_t *total = reinterpret_cast<uint32_t *>(ws);
     uint32_t *counts = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(ws) + RS_HEAD);
@@ -260,11 +285,11 @@ int rs_sort(K *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, i
         const uint32_t *gs = last ? gsrc : nullptr;
         uint32_t *gd = last ? gdst : nullptr;
         switch (rb) {
-        case 4: rs_pass<K, 4>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
-        case 5: rs_pass<K, 5>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
-        case 6: rs_pass<K, 6>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
-        case 7: rs_pass<K, 7>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
-        default: rs_pass<K, 8>(ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
+        case 4: rs_pass<K, 4>(small, ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
+        case 5: rs_pass<K, 5>(small, ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
+        case 6: rs_pass<K, 6>(small, ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
+        case 7: rs_pass<K, 7>(small, ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
+        default: rs_pass<K, 8>(small, ki, vi, ko, vo, n_dev, cap, grid, sh, mask, total, counts, tstride, gs, gd, s); break;
         }
         sel ^= 1;
     }
@@ -273,7 +298,7 @@ int rs_sort(K *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, i
 
 }  // namespace
 
-size_t sort_hist_bytes(int64_t cap) { return RS_HEAD + (size_t)rs_tiles(cap) * 256 * 4 + 256; }
+size_t sort_hist_bytes(int64_t cap) { return RS_HEAD + (size_t)rs_tiles(cap, RS_TILE_MIN) * 256 * 4 + 256; }
 
 int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
                    int hi_bit, int radix_bits, void *hist, hipStream_t s, const uint32_t *gather_src,
