@@ -92,6 +92,23 @@ def test_radix_sort_is_a_stable_sort(ctx, n, bits, dup):
     np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[o])
 
 
+@pytest.mark.parametrize("n", [511 * 4096, 511 * 4096 + 1, 2_500_003])
+def test_radix_sort_both_tile_sizes(ctx, n):
+    """Sorts of fewer than 512 tiles of 4096 keys take 2048-key tiles, larger
+    ones 4096-key tiles: both sides of that threshold, with and without a
+    partial last tile, give the stable order."""
+    rng = np.random.default_rng(n)
+    keys = rng.integers(0, 1 << 40, size=n, dtype=np.uint64)
+    keys[::3] &= np.uint64(0xFFF)   # runs of equal keys across tiles
+    vals = np.arange(n, dtype=np.uint32)
+    kt = torch.from_numpy(keys.view(np.int64)).cuda()
+    vt = torch.from_numpy(vals.view(np.int32)).cuda()
+    api.debug_sort_pairs(ctx, kt, vt, 40)
+    o = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(kt.cpu().numpy().view(np.uint64), keys[o])
+    np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[o])
+
+
 @pytest.mark.parametrize("radix_bits", [4, 5, 6, 7])
 @pytest.mark.parametrize("n,bits", [(777_777, 13), (300_001, 32), (5000, 45)])
 def test_radix_sort_digit_widths(n, bits, radix_bits):
