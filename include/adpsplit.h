@@ -160,7 +160,10 @@ typedef struct {
 
 /* ---- context and state ------------------------------------------------------ */
 
-/* Create a context bound to HIP device `device`. */
+/* Create a context bound to HIP device `device`.  Frames keep the device
+ * they were created on, so a context and its frames may be destroyed in any
+ * order (a frame destroyed after its context reads nothing from it); every
+ * other call on a frame needs its context alive. */
 as_status as_ctx_create(int device, as_ctx **out);
 void as_ctx_destroy(as_ctx *ctx);
 /* Text of the last error raised on this thread (static storage). */

@@ -223,7 +223,7 @@ void as_ctx_destroy(as_ctx *ctx) {
 
 void as_frame_destroy(as_frame *f) {
     if (!f) return;
-    (void)hipSetDevice(f->ctx->device);
+    (void)hipSetDevice(f->device);
     void *ptrs[] = {f->rec, f->depth_key, f->box, f->ntiles, f->offsets, f->grad2d, f->ranges, f->n_keys,
                     f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax, f->tile_err, f->dkeys[0], f->dkeys[1],
                     f->dvals[0], f->dvals[1], f->nt_sorted, f->n_ent, f->tile_order, f->tile_work, f->tile_order_bwd,
@@ -244,6 +244,7 @@ static as_status frame_alloc(as_ctx *ctx, int32_t max_views, int64_t ent_cap, in
     as_frame *f = new (std::nothrow) as_frame();
     if (!f) { as_set_error("as_frame_create: out of host memory"); return AS_ERR_HIP; }
     f->ctx = ctx;
+    f->device = ctx->device;
     f->max_views = max_views;
     f->fixed_w = fixed_w;
     f->fixed_h = fixed_h;

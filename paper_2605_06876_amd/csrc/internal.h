@@ -86,6 +86,7 @@ struct SceneTable {
 
 struct as_frame {
     as_ctx *ctx;
+    int device;   // the context's device, kept so that destroying the frame never reads the context
     int32_t max_views;
     int32_t fixed_w, fixed_h;   // single-view frames: the one size they render (0: any)
     int32_t auto_grow;

@@ -254,3 +254,16 @@ def test_capture_refuses_a_synchronising_frame(ctx):
         img = api.render(ctx, g, cam, frame)
     s.synchronize()
     assert torch.isfinite(img).all()
+
+
+def test_frame_destroyed_after_its_context():
+    """Python's cycle collector finalises objects in no fixed order, so a frame
+    can be freed after its context: that must read nothing from the freed
+    context and leave no HIP error for the next call to pick up."""
+    c = api.Context(0)
+    f = api.Frame(c, 100, 32, 32)
+    c.close()
+    f.close()
+    x = torch.arange(16, dtype=torch.float32).cuda() * 2.0
+    torch.cuda.synchronize()
+    assert x[-1].item() == 30.0
