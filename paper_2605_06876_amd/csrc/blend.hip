@@ -693,12 +693,24 @@ __global__ void __launch_bounds__(1024) k_after_fwd(const ViewTable vt, const Vi
                                                     uint32_t *__restrict__ order, const uint32_t *__restrict__ ranges,
                                                     const uint32_t *__restrict__ tile_hi, uint32_t seg_len, int ck,
                                                     uint32_t *__restrict__ items, uint32_t *__restrict__ n_items) {
+    // up to AF_LDS_TILES tiles, the ordered tiles and their segment counts
+    // are also kept in LDS, so the item expansion gathers nothing from memory
+    constexpr int AF_LDS_TILES = 16384;
+    __shared__ uint16_t s_tile[AF_LDS_TILES];
+    __shared__ uint8_t s_nseg[AF_LDS_TILES];
     __shared__ uint32_t s_cnt[129], s_off[129];
     __shared__ unsigned long long s_mn[16], s_mx[16];
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int tiles = vt.tile_base[vt.n_views];
+    const bool in_lds = order_on && tiles <= AF_LDS_TILES;
+    // segments of a tile: one per checkpointed batch boundary it crosses, plus one
+    auto nseg_of = [&](uint32_t tile) -> uint32_t {
+        const uint32_t start = ranges[2 * tile], hi = tile_hi[tile];
+        if (hi <= start) return 0u;
+        return ck ? min((hi - start + seg_len - 1) / seg_len, (uint32_t)AS_CK_MAX + 1u) : 1u;
+    };
     for (int v = 0; v < vt.n_views; v++) {
         if (!gts.p[v]) continue;
         unsigned long long mn = 0x7ff0000000000000ull, mx = 0ull;
@@ -740,7 +752,15 @@ __global__ void __launch_bounds__(1024) k_after_fwd(const ViewTable vt, const Vi
             }
         }
         __syncthreads();
-        for (int t = tid; t < tiles; t += 1024) order[atomicAdd(&s_off[128 - work_class(work[t])], 1u)] = (uint32_t)t;
+        for (int t = tid; t < tiles; t += 1024) {
+            const uint32_t ns = in_lds ? nseg_of((uint32_t)t) : 0u;
+            const uint32_t slot = atomicAdd(&s_off[128 - work_class(work[t])], 1u);
+            order[slot] = (uint32_t)t;
+            if (in_lds) {
+                s_tile[slot] = (uint16_t)t;
+                s_nseg[slot] = (uint8_t)ns;
+            }
+        }
     }
     if (tid == 0) s_carry = 0;
     __syncthreads();   // also: the order written above is visible to the whole block
@@ -748,9 +768,13 @@ __global__ void __launch_bounds__(1024) k_after_fwd(const ViewTable vt, const Vi
         const int i = base + tid;
         uint32_t tile = 0, nseg = 0;
         if (i < tiles) {
-            tile = order_on ? order[i] : (uint32_t)i;
-            const uint32_t start = ranges[2 * tile], hi = tile_hi[tile];
-            if (hi > start) nseg = ck ? min((hi - start + seg_len - 1) / seg_len, (uint32_t)AS_CK_MAX + 1u) : 1u;
+            if (in_lds) {
+                tile = s_tile[i];
+                nseg = s_nseg[i];
+            } else {
+                tile = order_on ? order[i] : (uint32_t)i;
+                nseg = nseg_of(tile);
+            }
         }
         uint32_t incl = nseg;
         for (int o = 1; o < 64; o <<= 1) {
