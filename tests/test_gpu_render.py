@@ -478,3 +478,32 @@ def test_tuning_never_changes_results(ctx, c2, batch, lpt, persistent, radix):
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         x, y = getattr(grads, name), getattr(ref_grads, name)
         assert (torch.linalg.norm(x - y) <= 1e-4 * torch.linalg.norm(y)).item(), name
+
+
+def test_dispatch_order_past_the_lds_tile_limit():
+    """A view of more than 16,384 tiles builds the reverse pass's work items
+    from memory rather than LDS: with dispatch ordering on it must give the
+    same forward, bit for bit, and the same gradients up to atomic order as
+    the unordered dispatch, also once checkpoints split the tile lists."""
+    cam = synth.sphere_cameras(1, 3.2, [(2112, 2112)], seed=5)[0]
+    assert (cam.width // 16) * (cam.height // 16) > 16384
+    g = api.Gaussians.from_scene(synth.scene_clusters(200_000, seed=5, sh_degree=1))
+    gt = torch.from_numpy(synth.smooth_image(cam.height, cam.width, seed=5)).cuda()
+    G = torch.from_numpy(np.random.default_rng(5).normal(size=(3, cam.height, cam.width)).astype(np.float32)).cuda()
+    out = []
+    for lpt in (True, False):
+        c = api.Context(0)
+        api.set_tuning(c, lds_batch=256, longest_first=lpt)
+        frame = api.Frame(c, g.n, cam.width, cam.height)
+        for _ in range(2):   # the second backward walks checkpointed segments
+            img = api.render(c, g, cam, frame, gt=gt)
+            grads = api.render_backward(c, g, cam, frame, G)
+        torch.cuda.synchronize()
+        out.append((img.clone(), frame.host_state(g.n), grads))
+    (ia, sa, ga), (ib, sb, gb) = out
+    assert torch.equal(ia, ib)
+    for k in ("t_final", "n_contrib", "dom", "last", "err", "ranges"):
+        np.testing.assert_array_equal(sa[k], sb[k], err_msg=k)
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        x, y = getattr(ga, name), getattr(gb, name)
+        assert (torch.linalg.norm(x - y) <= 1e-4 * torch.linalg.norm(y)).item(), name
