@@ -764,19 +764,26 @@ __global__ void __launch_bounds__(1024) k_after_fwd(const ViewTable vt, const Vi
     }
     if (tid == 0) s_carry = 0;
     __syncthreads();   // also: the order written above is visible to the whole block
-    for (int base = 0; base < tiles; base += 1024) {
-        const int i = base + tid;
-        uint32_t tile = 0, nseg = 0;
-        if (i < tiles) {
-            if (in_lds) {
-                tile = s_tile[i];
-                nseg = s_nseg[i];
-            } else {
-                tile = order_on ? order[i] : (uint32_t)i;
-                nseg = nseg_of(tile);
+    // four consecutive dispatch slots per thread, 4096 per block-wide scan
+    for (int base = 0; base < tiles; base += 4096) {
+        uint32_t tl[4], ns[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int i = base + 4 * tid + k;
+            tl[k] = 0u;
+            ns[k] = 0u;
+            if (i < tiles) {
+                if (in_lds) {
+                    tl[k] = s_tile[i];
+                    ns[k] = s_nseg[i];
+                } else {
+                    tl[k] = order_on ? order[i] : (uint32_t)i;
+                    ns[k] = nseg_of(tl[k]);
+                }
             }
+            sum += ns[k];
         }
-        uint32_t incl = nseg;
+        uint32_t incl = sum;
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t t = (uint32_t)__shfl_up((int)incl, o, 64);
             if (lane >= o) incl += t;
@@ -785,11 +792,11 @@ __global__ void __launch_bounds__(1024) k_after_fwd(const ViewTable vt, const Vi
         __syncthreads();
         uint32_t before = s_carry;
         for (int k = 0; k < w; k++) before += s_w[k];
-        const uint32_t off = before + incl - nseg;
-        for (uint32_t k = 0; k < nseg; k++) {
-            items[2 * (off + k)] = tile;
-            items[2 * (off + k) + 1] = k;
-        }
+        uint32_t off = before + incl - sum;
+        uint2 *it = reinterpret_cast<uint2 *>(items);   // (tile, segment) pairs
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            for (uint32_t j = 0; j < ns[k]; j++) it[off++] = make_uint2(tl[k], j);
         __syncthreads();
         if (tid == 1023) s_carry = before + incl;
         __syncthreads();
