@@ -22,7 +22,9 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
   error_stats             pinned (hand-built maps, brute-force counts, BFS
                           against scipy.ndimage labelling, rectangle moments)
   adaptive_split          pinned per stage (closed-form t*, axis-aligned child
-                          shape, merge identities, hand-built mode counts);
+                          shape, merge identities, closed-form merged mean,
+                          colour, axes and scales of Eq. (merge_cov) via
+                          merge_group, hand-built mode counts);
                           whole-method fidelity to the authors' unreleased
                           code is "parity unpinned" (no code or worked example
                           exists to compare against)
@@ -295,6 +297,20 @@ def jacobi3(A):
     lam = np.zeros(3)
     lib().orc_jacobi3(_p(A), _p(V), _p(lam))
     return V.reshape(3, 3), lam
+
+
+def merge_group(mu, R, s, rgb):
+    """Eq. (merge_cov) for M proposals given directly: mu [M,3], R [M,3,3],
+    s [M,3], rgb [M,3].  Returns (mean, colour, E [3,3] with the axes as
+    columns, scales sqrt(lambda) [3]); the split merges with the same code."""
+    mu = _c(mu, np.float64).reshape(-1, 3)
+    M = mu.shape[0]
+    R = _c(R, np.float64).reshape(M, 9)
+    s = _c(s, np.float64).reshape(M, 3)
+    rgb = _c(rgb, np.float64).reshape(M, 3)
+    mo, co, Ro, so = np.zeros(3), np.zeros(3), np.zeros(9), np.zeros(3)
+    lib().orc_merge_group(ctypes.c_int64(M), _p(mu), _p(R), _p(s), _p(rgb), _p(mo), _p(co), _p(Ro), _p(so))
+    return mo, co, Ro.reshape(3, 3), so
 
 
 def child_proposal(parent, region, cam, eps=1e-8):

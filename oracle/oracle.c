@@ -832,6 +832,21 @@ static double clipv(double x, double a) {
     return x < 0.0 ? -m : m;
 }
 
+/* Covariance R diag(s^2) R^T of a proposal and its inverse R diag(1/s^2) R^T
+ * (Eq. (child_cov); the inverse is the metric of Eq. (merge_conditions)). */
+static void prop_cov(oprop *p) {
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            double acc = 0.0, acci = 0.0;
+            for (int k = 0; k < 3; k++) {
+                acc += p->R[a * 3 + k] * (p->s[k] * p->s[k]) * p->R[b * 3 + k];
+                acci += p->R[a * 3 + k] * (1.0 / (p->s[k] * p->s[k])) * p->R[b * 3 + k];
+            }
+            p->Sig[a * 3 + b] = acc;
+            p->Sinv[a * 3 + b] = acci;
+        }
+}
+
 static void child_from_region(const ogauss *par, const oregion *r, const ocam *c, double eps, oprop *p) {
     memset(p, 0, sizeof(*p));
     double ov[3];
@@ -894,16 +909,7 @@ static void child_from_region(const ogauss *par, const oregion *r, const ocam *c
         p->R[k * 3 + 2] = c->R[2 * 3 + k];
     }
     for (int ch = 0; ch < 3; ch++) p->rgb[ch] = r->rgb[ch];
-    for (int a = 0; a < 3; a++)
-        for (int b = 0; b < 3; b++) {
-            double acc = 0.0, acci = 0.0;
-            for (int k = 0; k < 3; k++) {
-                acc += p->R[a * 3 + k] * (p->s[k] * p->s[k]) * p->R[b * 3 + k];
-                acci += p->R[a * 3 + k] * (1.0 / (p->s[k] * p->s[k])) * p->R[b * 3 + k];
-            }
-            p->Sig[a * 3 + b] = acc;
-            p->Sinv[a * 3 + b] = acci;
-        }
+    prop_cov(p);
     p->ok = 1;
 }
 
@@ -1024,6 +1030,75 @@ static int64_t uf_find(int64_t *par, int64_t a) {
     return a;
 }
 
+/* Eq. (merge_cov): the merged child of one group of proposals, given in
+ * member order.  Mean and colour are the member averages; the axes E are the
+ * eigenvectors of the mean covariance (descending eigenvalues, det +1 [A21]);
+ * the scale along axis e_r is the largest member reach along it, the offset
+ * |e_r^T (mu_m - mean)| plus the member's 1-sigma extent sqrt(e_r^T Sigma_m
+ * e_r) [A20], so lambda_r is that reach squared.  A lone proposal is its own
+ * merge result. */
+static void merge_members(const oprop *const *mem, int64_t M, ogroup *gr) {
+    memset(gr, 0, sizeof(*gr));
+    if (M == 1) {
+        memcpy(gr->mu, mem[0]->mu, sizeof(gr->mu));
+        memcpy(gr->rgb, mem[0]->rgb, sizeof(gr->rgb));
+        memcpy(gr->R, mem[0]->R, sizeof(gr->R));
+        memcpy(gr->s, mem[0]->s, sizeof(gr->s));
+        return;
+    }
+    double Sbar[9] = {0};
+    for (int64_t m = 0; m < M; m++) {
+        for (int k = 0; k < 3; k++) { gr->mu[k] += mem[m]->mu[k]; gr->rgb[k] += mem[m]->rgb[k]; }
+        for (int k = 0; k < 9; k++) Sbar[k] += mem[m]->Sig[k];
+    }
+    for (int k = 0; k < 3; k++) { gr->mu[k] = gr->mu[k] / (double)M; gr->rgb[k] = gr->rgb[k] / (double)M; }
+    for (int k = 0; k < 9; k++) Sbar[k] = Sbar[k] / (double)M;
+    double E[9], lam[3];
+    jacobi3(Sbar, E, lam);
+    for (int r = 0; r < 3; r++) {
+        double er[3] = {E[0 * 3 + r], E[1 * 3 + r], E[2 * 3 + r]};
+        double best = 0.0;
+        for (int64_t m = 0; m < M; m++) {
+            const oprop *p = mem[m];
+            double off = fabs(er[0] * (p->mu[0] - gr->mu[0]) + er[1] * (p->mu[1] - gr->mu[1]) +
+                              er[2] * (p->mu[2] - gr->mu[2]));
+            double Se[3];
+            for (int k = 0; k < 3; k++)
+                Se[k] = p->Sig[k * 3 + 0] * er[0] + p->Sig[k * 3 + 1] * er[1] + p->Sig[k * 3 + 2] * er[2];
+            double sig = sqrt(er[0] * Se[0] + er[1] * Se[1] + er[2] * Se[2]);   /* [A20] */
+            double reach = off + sig;
+            if (reach > best) best = reach;
+        }
+        gr->s[r] = best;   /* sqrt(lambda_r) */
+    }
+    memcpy(gr->R, E, sizeof(gr->R));
+}
+
+/* Eq. (merge_cov) for M proposals given directly (mu [M][3], R [M][9]
+ * row-major, s [M][3], rgb [M][3]), exported for the closed-form pins; the
+ * split calls the same merge_members. */
+void orc_merge_group(int64_t M, const double *mu, const double *R, const double *s, const double *rgb,
+                     double *mu_out, double *rgb_out, double *R_out, double *s_out) {
+    oprop *props = (oprop *)calloc((size_t)(M > 0 ? M : 1), sizeof(oprop));
+    const oprop **mem = (const oprop **)malloc(sizeof(oprop *) * (size_t)(M > 0 ? M : 1));
+    for (int64_t m = 0; m < M; m++) {
+        memcpy(props[m].mu, mu + 3 * m, sizeof(props[m].mu));
+        memcpy(props[m].R, R + 9 * m, sizeof(props[m].R));
+        memcpy(props[m].s, s + 3 * m, sizeof(props[m].s));
+        memcpy(props[m].rgb, rgb + 3 * m, sizeof(props[m].rgb));
+        prop_cov(&props[m]);
+        props[m].ok = 1;
+        mem[m] = &props[m];
+    }
+    ogroup gr;
+    merge_members(mem, M, &gr);
+    memcpy(mu_out, gr.mu, sizeof(gr.mu));
+    memcpy(rgb_out, gr.rgb, sizeof(gr.rgb));
+    memcpy(R_out, gr.R, sizeof(gr.R));
+    memcpy(s_out, gr.s, sizeof(gr.s));
+    free(props); free(mem);
+}
+
 /* Sec. 4.2-4.3 + implementation details: the adaptive split of every
  * candidate.  Inputs: parameters (SoA, n rows), candidate ids (ascending),
  * retained regions of all views (any order), the views' packed cameras, the
@@ -1096,48 +1171,16 @@ int64_t orc_adaptive_split(int64_t n, int deg, const float *means, const float *
             }
         /* Eq. (merge_cov): one merged child per connected group */
         ogroup *groups = (ogroup *)malloc(sizeof(ogroup) * (size_t)(np > 0 ? np : 1));
+        const oprop **mem = (const oprop **)malloc(sizeof(oprop *) * (size_t)(np > 0 ? np : 1));
         int64_t ng = 0;
         for (int64_t a = 0; a < np; a++) {
             if (uf_find(uf, a) != a) continue;   /* a is the group's first member */
             ogroup gr;
-            memset(&gr, 0, sizeof(gr));
-            gr.rep = a;
             int64_t M = 0;
-            double Sbar[9] = {0};
-            for (int64_t m = a; m < np; m++) {
-                if (uf_find(uf, m) != a) continue;
-                M++;
-                for (int k = 0; k < 3; k++) { gr.mu[k] += props[m].mu[k]; gr.rgb[k] += props[m].rgb[k]; }
-                for (int k = 0; k < 9; k++) Sbar[k] += props[m].Sig[k];
-            }
-            if (M == 1) {   /* a lone proposal is its own merge result */
-                memcpy(gr.mu, props[a].mu, sizeof(gr.mu));
-                memcpy(gr.rgb, props[a].rgb, sizeof(gr.rgb));
-                memcpy(gr.R, props[a].R, sizeof(gr.R));
-                memcpy(gr.s, props[a].s, sizeof(gr.s));
-            } else {
-                for (int k = 0; k < 3; k++) { gr.mu[k] = gr.mu[k] / (double)M; gr.rgb[k] = gr.rgb[k] / (double)M; }
-                for (int k = 0; k < 9; k++) Sbar[k] = Sbar[k] / (double)M;
-                double E[9], lam[3];
-                jacobi3(Sbar, E, lam);
-                for (int r = 0; r < 3; r++) {
-                    double er[3] = {E[0 * 3 + r], E[1 * 3 + r], E[2 * 3 + r]};
-                    double best = 0.0;
-                    for (int64_t m = a; m < np; m++) {
-                        if (uf_find(uf, m) != a) continue;
-                        double off = fabs(er[0] * (props[m].mu[0] - gr.mu[0]) + er[1] * (props[m].mu[1] - gr.mu[1]) +
-                                          er[2] * (props[m].mu[2] - gr.mu[2]));
-                        double Se[3];
-                        for (int k = 0; k < 3; k++)
-                            Se[k] = props[m].Sig[k * 3 + 0] * er[0] + props[m].Sig[k * 3 + 1] * er[1] + props[m].Sig[k * 3 + 2] * er[2];
-                        double sig = sqrt(er[0] * Se[0] + er[1] * Se[1] + er[2] * Se[2]);   /* [A20] */
-                        double reach = off + sig;
-                        if (reach > best) best = reach;
-                    }
-                    gr.s[r] = best;   /* sqrt(lambda_r) */
-                }
-                memcpy(gr.R, E, sizeof(gr.R));
-            }
+            for (int64_t m = a; m < np; m++)
+                if (uf_find(uf, m) == a) mem[M++] = &props[m];
+            merge_members(mem, M, &gr);
+            gr.rep = a;
             if (sp.flags & 4) gr.extent = fmax(gr.s[0], fmax(gr.s[1], gr.s[2]));   /* [A22] alternative */
             else gr.extent = gr.s[0] * gr.s[1] * gr.s[2];
             groups[ng++] = gr;
@@ -1155,7 +1198,7 @@ int64_t orc_adaptive_split(int64_t n, int deg, const float *means, const float *
             kept[ci] = (ogroup *)malloc(sizeof(ogroup) * (size_t)ng);
             memcpy(kept[ci], groups, sizeof(ogroup) * (size_t)ng);
         }
-        free(props); free(uf); free(groups);
+        free(props); free(uf); free(groups); free(mem);
     }
     /* append (Sec. 3, end; Sec. 5 "Implementation") */
     uint8_t *removed = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);

@@ -410,6 +410,115 @@ def test_merged_group_encloses_members():
             assert abs(e @ (mu - mum)) + math.sqrt(e @ S @ e) <= math.sqrt(lam[r]) * (1 + 1e-5)
 
 
+# Closed forms of Eq. (merge_cov).  For axis-aligned members whose mean
+# covariance has distinct eigenvalues, the merged axes are the coordinate axes
+# (descending variance) and the merged scale along each axis is the largest
+# member reach along it: offset from the merged mean plus the member's own
+# scale on that axis.
+
+def _axis_members(offsets, scales, colours, Q=None, centre=(0.0, 0.0, 0.0)):
+    Q = np.eye(3) if Q is None else Q
+    mu = np.array([centre]) + (Q @ np.asarray(offsets, np.float64).T).T
+    R = np.repeat(Q[None], len(offsets), axis=0)
+    return mu, R, np.asarray(scales, np.float64), np.asarray(colours, np.float64)
+
+
+def _axes_match(E, Q):
+    """E's columns equal Q's up to sign, and det E = +1 [A21]."""
+    np.testing.assert_allclose(np.abs(E.T @ Q), np.eye(3), atol=1e-12)
+    assert abs(np.linalg.det(E) - 1.0) < 1e-12
+
+
+def test_merge_pair_closed_form():
+    """Two members of scales (s1, s2, s3), s1 > s2 > s3, offset by d along x
+    with different colours: mean = midpoint, colour = average, axes = x, y,
+    z, scales (d/2 + s1, s2, s3)."""
+    d, sc = 0.4, (0.3, 0.2, 0.1)
+    c = (0.25, -0.5, 1.5)
+    mu, R, s, rgb = _axis_members([(-d / 2, 0, 0), (d / 2, 0, 0)], [sc, sc],
+                                  [(0.9, 0.2, 0.4), (0.7, 0.6, 0.0)], centre=c)
+    m, col, E, sm = oracle.merge_group(mu, R, s, rgb)
+    np.testing.assert_allclose(m, c, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(col, [0.8, 0.4, 0.2], rtol=0, atol=1e-15)
+    _axes_match(E, np.eye(3))
+    np.testing.assert_allclose(sm ** 2, [(d / 2 + sc[0]) ** 2, sc[1] ** 2, sc[2] ** 2], rtol=1e-12)
+
+
+def test_merge_pair_rotated_closed_form():
+    """The same pair rotated by Q about an arbitrary centre: the axes rotate
+    with it and the scales do not change."""
+    d, sc = 0.4, (0.3, 0.2, 0.1)
+    for seed in range(5):
+        Q = Rotation.random(random_state=seed).as_matrix()
+        mu, R, s, rgb = _axis_members([(-d / 2, 0, 0), (d / 2, 0, 0)], [sc, sc],
+                                      [(0.9, 0.2, 0.4), (0.7, 0.6, 0.0)], Q=Q, centre=(1.0, 2.0, -3.0))
+        m, col, E, sm = oracle.merge_group(mu, R, s, rgb)
+        np.testing.assert_allclose(m, (1.0, 2.0, -3.0), rtol=0, atol=1e-14)
+        np.testing.assert_allclose(col, [0.8, 0.4, 0.2], rtol=0, atol=1e-15)
+        _axes_match(E, Q)
+        np.testing.assert_allclose(sm, [d / 2 + sc[0], sc[1], sc[2]], rtol=1e-12)
+
+
+def test_merge_three_members_takes_the_max_reach():
+    """Three members of unequal shape at uneven x offsets: each merged scale
+    is the largest member reach on that axis, which differs from the sum over
+    members and from the first member's reach."""
+    offs = [(-0.5, 0.0, 0.0), (0.1, 0.0, 0.0), (0.7, 0.0, 0.0)]
+    scs = [(0.30, 0.12, 0.05), (0.25, 0.21, 0.04), (0.35, 0.15, 0.08)]
+    cols = [(0.1, 0.2, 0.3), (0.4, 0.5, 0.6), (0.7, 0.8, 0.3)]
+    mu, R, s, rgb = _axis_members(offs, scs, cols)
+    m, col, E, sm = oracle.merge_group(mu, R, s, rgb)
+    xbar = (-0.5 + 0.1 + 0.7) / 3
+    np.testing.assert_allclose(m, [xbar, 0, 0], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(col, np.mean(cols, axis=0), rtol=0, atol=1e-15)
+    # mean covariance diag(mean s_x^2, mean s_y^2, mean s_z^2) is already
+    # ordered x > y > z here, so the axes are x, y, z
+    sq = np.square(scs).mean(0)
+    assert sq[0] > sq[1] > sq[2]
+    _axes_match(E, np.eye(3))
+    want = [max(abs(o[0] - xbar) + t[0] for o, t in zip(offs, scs)),
+            max(t[1] for t in scs), max(t[2] for t in scs)]
+    np.testing.assert_allclose(sm, want, rtol=1e-12)
+    # the max is not the sum, nor the first member's reach, nor the last's
+    assert abs(sm[1] - sum(t[1] for t in scs)) > 0.1
+    assert abs(sm[1] - scs[0][1]) > 0.05 and abs(sm[0] - (abs(offs[0][0] - xbar) + scs[0][0])) > 0.05
+
+
+def test_merge_axes_follow_the_mean_covariance_order():
+    """When the members' variance is largest along z, the first merged axis
+    is z: the axes come from the mean covariance, in descending order."""
+    mu, R, s, rgb = _axis_members([(0, 0, -0.1), (0, 0, 0.1)], [(0.1, 0.2, 0.5), (0.1, 0.2, 0.5)],
+                                  [(0.5, 0.5, 0.5)] * 2)
+    m, col, E, sm = oracle.merge_group(mu, R, s, rgb)
+    P = np.array([[0, 0, 1], [0, 1, 0], [1, 0, 0]], np.float64)   # columns z, y, x
+    _axes_match(E, P)
+    np.testing.assert_allclose(sm, [0.1 + 0.5, 0.2, 0.1], rtol=1e-12)
+
+
+def test_split_writes_the_merged_child():
+    """Through the whole split: two regions in two views whose proposals
+    merge.  The child's mean, colour (read back from the SH DC) and
+    covariance are the merge of the two proposals, and the colour is the
+    average of two different region colours."""
+    a = region_record(0, 0, 1, 60.0, 48.0, (1, 0), 3.0, 1.0, (0.50, 0.40, 0.30))
+    b = region_record(0, 1, 2, 60.6, 48.3, (0.6, 0.8), 2.0, 1.2, (0.60, 0.30, 0.40))
+    out = split_one(PAR, [a, b], [CAM, CAM])
+    assert out["mode"][0] == oracle.MODE_ADAPTIVE and out["count"][0] == 2
+    props = [oracle.child_proposal(PAR, r, CAM) for r in (a, b)]
+    assert all(p[0] for p in props)
+    mu = np.stack([p[1] for p in props])
+    R = np.stack([p[2] for p in props])
+    sc = np.stack([p[3] for p in props])
+    m, col, E, sm = oracle.merge_group(mu, R, sc, [(0.50, 0.40, 0.30), (0.60, 0.30, 0.40)])
+    np.testing.assert_allclose(m, mu.mean(0), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(col, [0.55, 0.35, 0.35], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(out["means"][:, 0], m, rtol=1e-6)
+    C0 = 1 / (2 * math.sqrt(math.pi))
+    np.testing.assert_allclose(out["sh"][0, :, 0].astype(np.float64) * C0 + 0.5, [0.55, 0.35, 0.35], rtol=1e-6)
+    np.testing.assert_allclose(cov_of(out["quats"][:, 0], out["log_scales"][:, 0]), E @ np.diag(sm ** 2) @ E.T,
+                               rtol=1e-5, atol=1e-9)
+
+
 def test_vanilla_fallback_without_attribution():
     noise = synth.vanilla_noise(1, 3)
     out = split_one(PAR, [], [CAM], attr_val=0, noise=noise)
