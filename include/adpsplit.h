@@ -457,6 +457,16 @@ as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64
  * check that the decision arithmetic rounds like the host's.  out[4][n]. */
 as_status as_debug_fp64_ops(as_ctx *ctx, const double *a, const double *b, int64_t n, double *out, void *stream);
 
+/* The forward and reverse blends' unclamped alpha o G of Eq. (rendering),
+ * evaluated in FP32 from the staged record of the last render exactly as the
+ * blend kernels evaluate it, for n (pixel, Gaussian) pairs of view 0 of the
+ * frame: pix [n][2] (x, y) int32, gauss [n] Gaussian ids (visible in the
+ * view: tiles touched > 0), out [n] float.  Used to measure the FP32 rounding
+ * of the alpha decisions against an FP64 reference.  AS_ERR_STATE without a
+ * render; no bounds checks beyond the arguments' shapes. */
+as_status as_debug_blend_alpha(const as_frame *f, int32_t view, int64_t n, const int32_t *pix, const uint32_t *gauss,
+                               float *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -104,6 +104,8 @@ class Projected:
         self.tview = np.zeros((n, 3))
         self.depth_key = np.zeros(n, np.uint32)
         self.box = np.zeros((n, 4), np.int32)
+        # culling / box-edge decisions within transcendental rounding of a threshold
+        self.box_flag = np.zeros(n, np.uint8)
 
 
 def project(scene, cam):
@@ -114,7 +116,7 @@ def project(scene, cam):
     pc = pack_camera(cam)
     lib().orc_project(ctypes.c_int64(n), ctypes.c_int(scene.sh_degree), _p(m), _p(s), _p(q), _p(o), _p(sh),
                       _p(pc), _p(pr.valid), _p(pr.mean2d), _p(pr.cov2d), _p(pr.conic), _p(pr.rgb),
-                      _p(pr.opacity), _p(pr.tview), _p(pr.depth_key), _p(pr.box))
+                      _p(pr.opacity), _p(pr.tview), _p(pr.depth_key), _p(pr.box), _p(pr.box_flag))
     pr.width, pr.height = int(cam.width), int(cam.height)
     pr.bg = np.asarray(cam.bg, np.float32).astype(np.float64)
     return pr
@@ -155,6 +157,16 @@ def render_pixels(pr, pix):
                             _p(pr.opacity), _p(pr.depth_key), _p(pr.box), _p(_c(pr.bg, np.float64)),
                             ctypes.c_int64(npix), _p(pix), _p(out["color"]), _p(out["T"]), _p(out["ncontrib"]),
                             _p(out["dom"]), _p(out["last"]), _p(out["flag"]), _p(out["pairs"]))
+    return out
+
+
+def alpha_pairs(pr, pix, ids):
+    """Unclamped alpha o G (FP64) of Gaussian ids[k] at pixel pix[k] = (x, y)."""
+    pix = _c(pix, np.int32)
+    ids = _c(ids, np.int64)
+    out = np.zeros(len(ids))
+    lib().orc_alpha_pairs(_p(pr.mean2d), _p(pr.conic), _p(pr.opacity), ctypes.c_int64(len(ids)), _p(pix), _p(ids),
+                          _p(out))
     return out
 
 
@@ -325,10 +337,18 @@ def child_proposal(parent, region, cam, eps=1e-8):
     return bool(ok), mu, R.reshape(3, 3), sc
 
 
-def render_rows(pr, y0=0, y1=None, dL_dcolor=None):
+def render_rows(pr, y0=0, y1=None, dL_dcolor=None, margins=False, grad_abs=False):
     """Eq. (rendering) for every pixel of rows [y0, y1) (same arithmetic as
     render_pixels, gathered per row).  With dL_dcolor [(y1-y0)*W, 3] the
-    reverse pass runs too and the 2D gradients are returned under "grad"."""
+    reverse pass runs too and the 2D gradients are returned under "grad".
+
+    margins=True adds "margins" [npix, 4]: each decision's smallest relative
+    distance to its threshold (alpha vs 1/255, T(1 - alpha) vs 1e-4, the
+    dominant weight's lead over the runner-up, o G vs the 0.99 clamp; inf
+    where the decision never arises).  grad_abs=True (with dL_dcolor) adds
+    grad["abs"] [n, 9]: per Gaussian the summed magnitudes of the products
+    that make up each 2D gradient (mean x, y; conic a, b, c; opacity; colour
+    r, g, b), the scale of its floating-point rounding error."""
     W = pr.width
     y1 = pr.height if y1 is None else y1
     npix = (y1 - y0) * W
@@ -342,9 +362,17 @@ def render_rows(pr, y0=0, y1=None, dL_dcolor=None):
         gC = _c(dL_dcolor, np.float64).reshape(npix, 3)
         out["grad"] = dict(mean2d=np.zeros((n, 2)), conic=np.zeros((n, 3)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
         gp = [_p(out["grad"][k]) for k in ("mean2d", "conic", "opacity", "rgb")]
+    mp = ga = None
+    if margins:
+        out["margins"] = np.zeros((npix, 4))
+        mp = _p(out["margins"])
+    if grad_abs:
+        assert dL_dcolor is not None, "grad_abs needs dL_dcolor"
+        out["grad"]["abs"] = np.zeros((n, 9))
+        ga = _p(out["grad"]["abs"])
     lib().orc_render_rows(ctypes.c_int64(n), _p(pr.valid), _p(pr.mean2d), _p(pr.conic), _p(pr.rgb), _p(pr.opacity),
                           _p(pr.depth_key), _p(pr.box), _p(_c(pr.bg, np.float64)), ctypes.c_int(W), ctypes.c_int(y0),
                           ctypes.c_int(y1), _p(out["color"]), _p(out["T"]), _p(out["ncontrib"]), _p(out["dom"]),
                           _p(out["last"]), _p(out["flag"]), _p(out["pairs"]), _p(gC) if gC is not None else None,
-                          *gp)
+                          *gp, mp, ga)
     return out

@@ -194,7 +194,19 @@ typedef struct {
     double o;
     uint32_t depth_key; /* bits of float(t_z) */
     int box[4];         /* inclusive pixel range x0, y0, x1, y1 */
+    int box_flag;       /* a culling or box-edge decision lies within transcendental rounding of its threshold */
 } oproj;
+
+/* Box decisions go through exp (scale, opacity) and log (the alpha level); a
+ * device's FP64 exp and log may differ from the host's by an ulp, so a value
+ * this close (relative) to a threshold can round either way.  The margin is
+ * far above an ulp (about 1e6 of them) and still flags almost nothing. */
+#define FLAG_BOX_REL 1e-10
+
+/* distance of v to the nearest integer, relative to the magnitudes forming v */
+static int near_integer(double v, double scale) {
+    return fabs(v - nearbyint(v)) <= FLAG_BOX_REL * (scale + 1.0);
+}
 
 static int project_one(int64_t n, int deg, int64_t i, const float *means, const float *log_scales,
                        const float *quats, const float *opac, const float *sh, const ocam *c, oproj *p) {
@@ -257,9 +269,16 @@ static int project_one(int64_t n, int deg, int64_t i, const float *means, const 
         p->rgb[ch] = acc < 0.0 ? 0.0 : acc;
     }
     /* compact box: alpha >= 1/255 <=> d^T conic d <= 2 ln(255 o) */
+    if (fabs(255.0 * g.o - 1.0) <= FLAG_BOX_REL) p->box_flag = 1;
     if (!(g.o >= ALPHA_MIN)) return 0;
     double kk = 2.0 * log(255.0 * g.o);
     double hx = sqrt(kk * A), hy = sqrt(kk * Cc);
+    {
+        double sx = fabs(p->mean[0]) + hx, sy = fabs(p->mean[1]) + hy;
+        if (near_integer(p->mean[0] - hx - 0.5, sx) || near_integer(p->mean[0] + hx - 0.5, sx) ||
+            near_integer(p->mean[1] - hy - 0.5, sy) || near_integer(p->mean[1] + hy - 0.5, sy))
+            p->box_flag = 1;
+    }
     double x0 = ceil(p->mean[0] - hx - 0.5), x1 = floor(p->mean[0] + hx - 0.5);
     double y0 = ceil(p->mean[1] - hy - 0.5), y1 = floor(p->mean[1] + hy - 0.5);
     x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
@@ -274,7 +293,7 @@ static int project_one(int64_t n, int deg, int64_t i, const float *means, const 
 void orc_project(int64_t n, int deg, const float *means, const float *log_scales, const float *quats,
                  const float *opac, const float *sh, const double *cam_packed,
                  int32_t *valid, double *mean2d, double *cov2d, double *conic, double *rgb, double *opacity,
-                 double *tview, uint32_t *depth_key, int32_t *box) {
+                 double *tview, uint32_t *depth_key, int32_t *box, uint8_t *box_flag) {
     ocam c;
     cam_unpack(cam_packed, &c);
 #pragma omp parallel for schedule(static)
@@ -290,6 +309,7 @@ void orc_project(int64_t n, int deg, const float *means, const float *log_scales
         opacity[i] = p.o;
         depth_key[i] = p.depth_key;
         for (int k = 0; k < 4; k++) box[i * 4 + k] = p.valid ? p.box[k] : 0;
+        if (box_flag) box_flag[i] = (uint8_t)p.box_flag;
     }
 }
 
@@ -374,6 +394,7 @@ static int64_t depth_order(int64_t n, const int32_t *valid, const uint32_t *dept
 #define FLAG_ALPHA_REL 1e-4
 #define FLAG_T_REL 2e-4
 #define FLAG_DOM_REL 1e-4
+#define FLAG_CLAMP_REL 1e-4   /* o G near the 0.99 clamp: the reverse pass's branch of min(0.99, o G) */
 
 typedef struct {
     double color[3], T;
@@ -414,6 +435,7 @@ static void render_pixel(int x, int y, int64_t m, const int64_t *order, const do
         double testT = T * (1.0 - a);
         if (fabs(testT - T_STOP) <= FLAG_T_REL * T_STOP) flag = 1;
         if (testT < T_STOP) break;
+        if (fabs(araw - ALPHA_MAX) <= FLAG_CLAMP_REL * ALPHA_MAX) flag = 1;
         double w = a * T;
         for (int ch = 0; ch < 3; ch++) C[ch] += w * rgb[i * 3 + ch];
         if (w > wbest) { wsecond = wbest; wbest = w; dom = i; }
@@ -426,6 +448,19 @@ static void render_pixel(int x, int y, int64_t m, const int64_t *order, const do
     for (int ch = 0; ch < 3; ch++) out->color[ch] = C[ch] + T * bg[ch];
     out->T = T; out->ncontrib = nc; out->dom = dom; out->last = last; out->flag = flag; out->pairs = pairs;
     out->wbest = wbest; out->wsecond = wsecond;
+}
+
+/* Unclamped alpha o G (FP64) of Gaussian ids[k] at the centre of pixel
+ * pix[k] = {x, y}, for measuring how far an FP32 evaluation strays. */
+void orc_alpha_pairs(const double *mean2d, const double *conic, const double *opacity, int64_t np,
+                     const int32_t *pix, const int64_t *ids, double *out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < np; k++) {
+        int64_t i = ids[k];
+        double G;
+        alpha_at(mean2d + i * 2, conic + i * 3, opacity[i], pix[k * 2] + 0.5, pix[k * 2 + 1] + 0.5, &G);
+        out[k] = opacity[i] * G;
+    }
 }
 
 /* Render the listed pixels (npix x {x, y}).  Inputs are the per-Gaussian rows
@@ -1302,7 +1337,7 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
                      const double *opacity, const uint32_t *depth_key, const int32_t *box, const double *bg, int W,
                      int y0, int y1, double *color, double *Tfinal, int32_t *ncontrib, int64_t *dom, int64_t *last,
                      uint8_t *flag, int64_t *pairs, const double *dL_dcolor, double *g_mean, double *g_conic,
-                     double *g_opac, double *g_rgb) {
+                     double *g_opac, double *g_rgb, double *margins, double *g_abs) {
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     int64_t m = depth_order(n, valid, depth_key, order);
     if (dL_dcolor) {
@@ -1310,6 +1345,7 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
         memset(g_conic, 0, sizeof(double) * 3 * n);
         memset(g_opac, 0, sizeof(double) * n);
         memset(g_rgb, 0, sizeof(double) * 3 * n);
+        if (g_abs) memset(g_abs, 0, sizeof(double) * 9 * n);
     }
 #pragma omp parallel
     {
@@ -1333,6 +1369,8 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
                 double T = 1.0, C[3] = {0, 0, 0}, wbest = -1.0, wsecond = -1.0;
                 int64_t dm = -1, ls = -1, pr = 0;
                 int nc = 0, fl = 0;
+                /* smallest relative distance of each decision to its threshold */
+                double mg_a = INFINITY, mg_t = INFINITY, mg_c = INFINITY;
                 for (int64_t k = 0; k < nr; k++) {
                     int64_t i = row[k];
                     const int32_t *b = box + i * 4;
@@ -1341,11 +1379,18 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
                     double G;
                     double a = alpha_at(mean2d + i * 2, conic + i * 3, opacity[i], px, py, &G);
                     double araw = opacity[i] * G;
+                    double ra = fabs(araw - ALPHA_MIN) / ALPHA_MIN;
+                    if (ra < mg_a) mg_a = ra;
                     if (fabs(araw - ALPHA_MIN) <= FLAG_ALPHA_REL * ALPHA_MIN) fl = 1;
                     if (a < ALPHA_MIN) continue;
                     double testT = T * (1.0 - a);
+                    double rt = fabs(testT - T_STOP) / T_STOP;
+                    if (rt < mg_t) mg_t = rt;
                     if (fabs(testT - T_STOP) <= FLAG_T_REL * T_STOP) fl = 1;
                     if (testT < T_STOP) break;
+                    double rc = fabs(araw - ALPHA_MAX) / ALPHA_MAX;
+                    if (rc < mg_c) mg_c = rc;
+                    if (fabs(araw - ALPHA_MAX) <= FLAG_CLAMP_REL * ALPHA_MAX) fl = 1;
                     double w = a * T;
                     for (int ch = 0; ch < 3; ch++) C[ch] += w * rgb[i * 3 + ch];
                     if (w > wbest) { wsecond = wbest; wbest = w; dm = i; }
@@ -1367,6 +1412,12 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
                 if (dm >= 0 && wsecond >= 0.0 && wbest - wsecond <= FLAG_DOM_REL * wbest) fl = 1;
                 for (int ch = 0; ch < 3; ch++) color[p * 3 + ch] = C[ch] + T * bg[ch];
                 Tfinal[p] = T; ncontrib[p] = nc; dom[p] = dm; last[p] = ls; flag[p] = (uint8_t)fl; pairs[p] = pr;
+                if (margins) {
+                    margins[p * 4 + 0] = mg_a;
+                    margins[p * 4 + 1] = mg_t;
+                    margins[p * 4 + 2] = (dm >= 0 && wsecond >= 0.0) ? (wbest - wsecond) / wbest : INFINITY;
+                    margins[p * 4 + 3] = mg_c;
+                }
                 if (!dL_dcolor) continue;
                 const double *gC = dL_dcolor + p * 3;
                 double S[3];
@@ -1374,18 +1425,37 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
                 for (int k = nc - 1; k >= 0; k--) {
                     int64_t i = lid[x][k];
                     double a = lal[x][k], Tk = lT[x][k], G = lG[x][k];
-                    double dLda = 0.0;
+                    double dLda = 0.0, mag = 0.0;
                     for (int ch = 0; ch < 3; ch++) {
 #pragma omp atomic
                         g_rgb[i * 3 + ch] += a * Tk * gC[ch];
                         dLda += gC[ch] * (Tk * rgb[i * 3 + ch] - S[ch] / (1.0 - a));
+                        /* every factor but gC is non-negative: the sum of the
+                           magnitudes of dLda's terms */
+                        mag += fabs(gC[ch]) * (Tk * rgb[i * 3 + ch] + S[ch] / (1.0 - a));
                     }
+                    if (g_abs)
+                        for (int ch = 0; ch < 3; ch++) {
+#pragma omp atomic
+                            g_abs[i * 9 + 6 + ch] += a * Tk * fabs(gC[ch]);
+                        }
                     for (int ch = 0; ch < 3; ch++) S[ch] += a * Tk * rgb[i * 3 + ch];
                     double o = opacity[i];
                     if (o * G < ALPHA_MAX) {
                         double dLdpow = dLda * o * G;
                         double dx = mean2d[i * 2] - px, dy = mean2d[i * 2 + 1] - py;
                         const double *cn = conic + i * 3;
+                        if (g_abs) {
+                            /* magnitudes of the products summed into each 2D gradient */
+                            double mp = mag * o * G;
+                            double t9[6] = {mp * (fabs(cn[0] * dx) + fabs(cn[1] * dy)),
+                                            mp * (fabs(cn[2] * dy) + fabs(cn[1] * dx)),
+                                            mp * 0.5 * dx * dx, mp * fabs(dx * dy), mp * 0.5 * dy * dy, mag * G};
+                            for (int q = 0; q < 6; q++) {
+#pragma omp atomic
+                                g_abs[i * 9 + q] += t9[q];
+                            }
+                        }
 #pragma omp atomic
                         g_opac[i] += dLda * G;
 #pragma omp atomic

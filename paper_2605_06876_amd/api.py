@@ -76,7 +76,7 @@ EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "a
             "as_render_backward", "as_render_batch", "as_render_backward_batch", "as_error_map",
             "as_accumulate_error_stats", "as_adaptive_split", "as_set_tuning", "as_get_tuning", "as_timing_enable",
             "as_timing_read", "as_graph_begin", "as_graph_end", "as_graph_launch", "as_graph_destroy",
-            "as_debug_sort_pairs", "as_debug_fp64_ops", "as_adam_step", "as_l1_loss", "as_densify_select",
+            "as_debug_sort_pairs", "as_debug_fp64_ops", "as_debug_blend_alpha", "as_adam_step", "as_l1_loss", "as_densify_select",
             "as_split_row_map", "as_clone_prune", "as_gather_rows", "as_reset_opacity")
 _NO_STATUS = ("as_last_error", "as_version", "as_ctx_destroy", "as_frame_destroy", "as_graph_destroy")
 
@@ -653,4 +653,15 @@ def debug_fp64_ops(ctx, a, b, stream=None):
     out = torch.empty(4, a.shape[0], dtype=torch.float64, device="cuda")
     _check(lib().as_debug_fp64_ops(ctx.handle, _ptr(a), _ptr(b), ctypes.c_int64(a.shape[0]), _ptr(out),
                                    _stream(stream)))
+    return out
+
+
+def debug_blend_alpha(frame, pix, gauss, stream=None):
+    """as_debug_blend_alpha: the blend's FP32 unclamped alpha o G for (pixel,
+    Gaussian) pairs of the frame's last render (view 0).  pix: int32 [n, 2]
+    (x, y); gauss: int32 [n] visible Gaussian ids.  Returns float32 [n]."""
+    n = int(pix.shape[0])
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(lib().as_debug_blend_alpha(frame.handle, ctypes.c_int32(0), ctypes.c_int64(n), _ptr(pix), _ptr(gauss),
+                                      _ptr(out), _stream(stream)))
     return out

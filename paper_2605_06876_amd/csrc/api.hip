@@ -932,4 +932,22 @@ as_status as_debug_fp64_ops(as_ctx *ctx, const double *a, const double *b, int64
     return launch_status("as_debug_fp64_ops");
 }
 
+as_status as_debug_blend_alpha(const as_frame *f, int32_t view, int64_t n, const int32_t *pix,
+                               const uint32_t *gauss, float *out, void *stream) {
+    if (!f || n < 0 || (n > 0 && (!pix || !gauss || !out))) {
+        as_set_error("as_debug_blend_alpha: bad argument");
+        return AS_ERR_ARG;
+    }
+    if (!f->has_render || view < 0 || view >= f->vt.n_views) {
+        as_set_error("as_debug_blend_alpha: view %d not in the last render", view);
+        return AS_ERR_STATE;
+    }
+    if (f->vt.ent_base[view] != 0) {
+        as_set_error("as_debug_blend_alpha: only the first view's entries are addressed by Gaussian id");
+        return AS_ERR_ARG;
+    }
+    launch_debug_alpha(f, n, pix, gauss, out, (hipStream_t)stream);
+    return launch_status("as_debug_blend_alpha");
+}
+
 }  // extern "C"

@@ -78,7 +78,7 @@ __device__ __forceinline__ void fetch(const uint32_t *__restrict__ vals, const B
     f.b = box[f.id];
 }
 
-__device__ __forceinline__ void stage(const Fetched &f, int ox, int oy, StagedRec *s_rec, int t) {
+__device__ __forceinline__ StagedRec make_staged(const Fetched &f, int ox, int oy) {
 #pragma clang fp contract(off)
     const float mx = (f.r.m.x - (float)ox) + f.r.m.z;
     const float my = (f.r.m.y - (float)oy) + f.r.m.w;
@@ -88,7 +88,11 @@ __device__ __forceinline__ void stage(const Fetched &f, int ox, int oy, StagedRe
     sr.mc = make_float4(mx, my, k * f.r.c.x, -LOG2E * f.r.c.y);
     sr.cc = make_float4(k * f.r.c.z, __log2f(f.r.c.w), f.r.rgb.x, f.r.rgb.y);
     sr.ex = make_float4(f.r.rgb.z, __uint_as_float(mask), __uint_as_float(f.id), 1.0f / f.r.c.w);
-    s_rec[t] = sr;
+    return sr;
+}
+
+__device__ __forceinline__ void stage(const Fetched &f, int ox, int oy, StagedRec *s_rec, int t) {
+    s_rec[t] = make_staged(f, ox, oy);
 }
 
 // Pixel geometry of a lane: 16-lane row `row` of wave w owns 4x4 block
@@ -804,7 +808,33 @@ __global__ void __launch_bounds__(1024) k_after_fwd(const ViewTable vt, const Vi
     if (tid == 0) *n_items = s_carry;
 }
 
+// Test hook: the blend's unclamped alpha o G = exp2(q) of entry ent[i] at
+// pixel pix[i] (view coordinates), staged for the pixel's tile exactly as the
+// blend kernels stage it.
+__global__ void k_debug_alpha(const BlendRec *__restrict__ rec, const short4 *__restrict__ box, int64_t n,
+                              const int32_t *__restrict__ pix, const uint32_t *__restrict__ ent,
+                              float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int x = pix[2 * i], y = pix[2 * i + 1];
+    const int ox = (x / AS_TILE_W) * AS_TILE_W, oy = (y / AS_TILE_H) * AS_TILE_H;
+    Fetched f;
+    f.id = ent[i];
+    f.r = rec[f.id];
+    f.b = box[f.id];
+    const StagedRec sr = make_staged(f, ox, oy);
+    const float px = (float)(x - ox) + 0.5f, py = (float)(y - oy) + 0.5f;
+    out[i] = __builtin_amdgcn_exp2f(blend_exponent(sr.mc.x - px, sr.mc.y - py, sr.mc, sr.cc));
+}
+
 }  // namespace
+
+void launch_debug_alpha(const as_frame *f, int64_t n, const int32_t *pix, const uint32_t *ent, float *out,
+                        hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_debug_alpha, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f->rec,
+                       reinterpret_cast<const short4 *>(f->box), n, pix, ent, out);
+}
 
 void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipStream_t s) {
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);

@@ -235,6 +235,8 @@ void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipSt
 void launch_after_fwd(const as_frame *f, const ViewTable &vt, const ViewImagesC &gt, int order_on, hipStream_t s);
 void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
                       const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s);
+void launch_debug_alpha(const as_frame *f, int64_t n, const int32_t *pix, const uint32_t *ent, float *out,
+                        hipStream_t s);
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
                       const ViewTable &vt, const ViewImagesC &dL_dimage, float *grad2d, hipStream_t s);
 

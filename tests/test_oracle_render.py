@@ -415,3 +415,128 @@ def test_row_sweep_equals_per_pixel_compositing():
     # a band of rows equals the same rows of the full image
     c = oracle.render_rows(pr, 40, 57)
     np.testing.assert_array_equal(c["color"], a["color"][40 * cam.width:57 * cam.width])
+
+
+# ---- decision margins, gradient magnitudes and box-edge flags -------------------------
+# The parity tests exclude pixels whose FP64 decision lies within the FP32
+# rounding of a threshold, and bound each 2D gradient's rounding error by the
+# summed magnitude of its products.  These pin the quantities they use.
+
+def test_margins_single_gaussian_closed_form():
+    """One Gaussian: the alpha margin of a pixel is |o G - 1/255| / (1/255),
+    the clamp margin |o G - 0.99| / 0.99, no stop or dominant tie, and the
+    flag is set exactly when a margin falls below its threshold."""
+    f, z = 80.0, 4.0
+    cam = axis_camera(W=64, H=64, f=f, z=-z)
+    mx = (32.5 - 32.0) * z / f
+    sc = one_gaussian((mx, mx, 0.0), [-3.0] * 3, logit=0.4, dc=(0.5, -0.2, 1.0))
+    pr = oracle.project(sc, cam)
+    r = oracle.render_rows(pr, margins=True)
+    W = cam.width
+    m, cn = pr.mean2d[0], pr.conic[0]
+    o = pr.opacity[0]
+    b = pr.box[0]
+    for (x, y) in [(32, 32), (33, 31), (34, 33), (int(b[2]), int(b[1])), (int(b[2]) + 1, 32)]:
+        p = y * W + x
+        if not (b[0] <= x <= b[2] and b[1] <= y <= b[3]):   # outside the box: no decision
+            assert np.isinf(r["margins"][p]).all()
+            continue
+        dx, dy = m[0] - (x + 0.5), m[1] - (y + 0.5)
+        G = math.exp(-0.5 * (cn[0] * dx * dx + cn[2] * dy * dy) - cn[1] * dx * dy)
+        np.testing.assert_allclose(r["margins"][p, 0], abs(o * G - 1 / 255) * 255, rtol=1e-12)
+        if o * G < 1 / 255:   # skipped: no stop or clamp decision
+            assert np.isinf(r["margins"][p, 1:]).all()
+            continue
+        np.testing.assert_allclose(r["margins"][p, 3], abs(o * G - 0.99) / 0.99, rtol=1e-12)
+        assert r["margins"][p, 2] == np.inf   # a single contributor has no runner-up
+        np.testing.assert_allclose(r["margins"][p, 1], abs((1 - o * G) - 1e-4) / 1e-4, rtol=1e-12)
+    # outside every box: no decision at all
+    assert np.isinf(r["margins"][0]).all()
+    thr = np.array([1e-4, 2e-4, 1e-4, 1e-4])
+    np.testing.assert_array_equal(r["flag"], (r["margins"] <= thr).any(1).astype(np.uint8))
+
+
+def test_margins_reproduce_the_flags_c1():
+    scene, cam, _ = synth.c1_inputs(seed=23)
+    pr = oracle.project(scene, cam)
+    r = oracle.render_rows(pr, margins=True)
+    thr = np.array([1e-4, 2e-4, 1e-4, 1e-4])
+    np.testing.assert_array_equal(r["flag"], (r["margins"] <= thr).any(1).astype(np.uint8))
+    # the dominant margin is the lead of the largest weight over the second
+    assert (r["margins"][:, 2] >= 0).all()
+
+
+def test_gradient_magnitudes_bound_and_equal_single_term():
+    """grad["abs"] >= |grad| for every Gaussian and quantity (a sum of
+    magnitudes bounds the magnitude of the sum), with equality for a single
+    pixel and a single channel of upstream gradient, where each 2D gradient
+    is one product."""
+    scene, cam, _ = synth.c1_inputs(seed=29)
+    pr = oracle.project(scene, cam)
+    G = np.random.default_rng(2).normal(size=(cam.width * cam.height, 3))
+    r = oracle.render_rows(pr, dL_dcolor=G, grad_abs=True)
+    g = r["grad"]
+    full = np.concatenate([g["mean2d"], g["conic"], g["opacity"][:, None], g["rgb"]], 1)
+    assert (g["abs"] >= np.abs(full) * (1 - 1e-12)).all()
+    assert (g["abs"][pr.valid == 0] == 0).all()
+    # one pixel, one Gaussian, one channel: |sum| = sum of |.| for colour,
+    # opacity and the conic entries (single products)
+    f, z = 80.0, 4.0
+    cam1 = axis_camera(W=64, H=64, f=f, z=-z)
+    sc = one_gaussian((0.013, -0.02, 0.0), [-3.0, -2.7, -3.2], q=(0.9, 0.1, 0.3, -0.2), logit=0.4,
+                      dc=(0.5, -0.2, 1.0))
+    pr1 = oracle.project(sc, cam1)
+    G1 = np.zeros((64 * 64, 3))
+    G1[33 * 64 + 30, 1] = -0.7
+    r1 = oracle.render_rows(pr1, dL_dcolor=G1, grad_abs=True)
+    g1 = r1["grad"]
+    full1 = np.concatenate([g1["mean2d"], g1["conic"], g1["opacity"][:, None], g1["rgb"]], 1)[0]
+    np.testing.assert_allclose(g1["abs"][0, 2:], np.abs(full1[2:]), rtol=1e-12)
+
+
+def test_box_edge_flag_marks_only_edges_at_rounding_distance():
+    """A Gaussian whose box edge m - h - 1/2 sits on an integer to within
+    FP64 rounding is flagged; the random C1 and C2-like scenes flag (almost)
+    nothing."""
+    f, z = 80.0, 4.0
+    cam = axis_camera(W=64, H=64, f=f, z=-z)
+    sc = one_gaussian((0.0, 0.0, 0.0), [-3.0] * 3, logit=0.4)
+    pr = oracle.project(sc, cam)
+    assert pr.box_flag[0] == 0
+    # move the mean so that m_x - h_x - 1/2 lands on an integer: h depends
+    # only on the covariance and opacity, which a shift along x leaves as is
+    # up to the Jacobian's x term; iterate the shift to the rounding level
+    mx = 0.0
+    for _ in range(6):
+        sc = one_gaussian((mx, 0.0, 0.0), [-3.0] * 3, logit=0.4)
+        p = oracle.project(sc, cam)
+        A = p.cov2d[0, 0]
+        o = p.opacity[0]
+        h = math.sqrt(2 * math.log(255 * o) * A)
+        edge = p.mean2d[0, 0] - h - 0.5
+        mx += (round(edge) - edge) * z / f
+    sc = one_gaussian((mx, 0.0, 0.0), [-3.0] * 3, logit=0.4)
+    p = oracle.project(sc, cam)
+    A = p.cov2d[0, 0]
+    h = math.sqrt(2 * math.log(255 * p.opacity[0]) * A)
+    edge = p.mean2d[0, 0] - h - 0.5
+    assert abs(edge - round(edge)) <= 1e-10 * (abs(p.mean2d[0, 0]) + h + 1)
+    assert p.box_flag[0] == 1
+    scene, cam2, _ = synth.c1_inputs(seed=31)
+    assert oracle.project(scene, cam2).box_flag.sum() == 0
+
+
+def test_alpha_pairs_equal_the_render_of_a_single_gaussian():
+    """alpha_pairs gives the o G the compositing uses: one Gaussian, black
+    background, pixel = min(0.99, o G) c where o G >= 1/255."""
+    f, z = 80.0, 4.0
+    cam = axis_camera(W=64, H=64, f=f, z=-z)
+    sc = one_gaussian((0.013, -0.02, 0.0), [-3.0, -2.7, -3.2], q=(0.9, 0.1, 0.3, -0.2), logit=0.4,
+                      dc=(0.5, -0.2, 1.0))
+    pr = oracle.project(sc, cam)
+    pix = np.array([[32, 32], [30, 33], [35, 29]], np.int32)
+    a = oracle.alpha_pairs(pr, pix, np.zeros(3, np.int64))
+    r = oracle.render_pixels(pr, pix)
+    for k in range(3):
+        if a[k] >= 1 / 255:
+            np.testing.assert_allclose(r["color"][k], min(a[k], 0.99) * pr.rgb[0], rtol=1e-14)
