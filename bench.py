@@ -30,15 +30,27 @@ PEAK_HBM_GBS = 8000.0
 # non-packed FP32 op per lane per clock; transcendentals at a quarter rate)
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic VALU lane-ops per (pixel, Gaussian) pair, counted from the
-# formulas (add/sub/mul/fma/min/compare/select = 1, exp = 4 at quarter rate):
-# forward: offset 2, exponent 9, exp 4, alpha 2, alpha test 1, transmittance 2,
-# stop test 1, weight 1, colour 3, dominant test+select 3  -> 28
-# backward: the forward's 17 up to the transmittance, restore T 1 (division
-# as reciprocal+mul: 4+1), colour grads 3, accumulators 9, dL/dalpha 6+1,
-# background term 3, opacity/exponent grads 2, mean grads 6, conic grads 6 -> 59
-OPS_FWD_PER_PAIR = 28
-OPS_BWD_PER_PAIR = 59
+# Algorithmic VALU lane-ops, counted from the formulas of Eq. (rendering)
+# (add/sub/mul/fma/min/compare/select = 1, exp = 4 at quarter rate).  Every
+# algorithmic pair (a pixel inside a Gaussian's compact box, in depth order
+# up to the pixel's stop point) evaluates alpha and tests it:
+#   offset 2, exponent 9, exp 4, alpha 2, alpha test 1                  -> 18
+# and only a contributor (alpha >= 1/255) composites or takes gradients:
+#   forward: transmittance 2, stop test 1, weight 1, colour 3,
+#            dominant test + select 3                                   -> 10
+#   reverse: restore T 5 (reciprocal 4 + mul), colour grads 3,
+#            accumulators 9, dL/dalpha 7, background term 3,
+#            opacity / exponent grads 2, mean grads 6, conic grads 6    -> 41
+# The pair and contributor counts are the oracle's (tests/golden).
+OPS_ALPHA_PER_PAIR = 18
+OPS_FWD_PER_CONTRIB = 10
+OPS_BWD_PER_CONTRIB = 41
+
+
+def blend_ops(pairs, contributors):
+    """Algorithmic lane-ops of the forward and of the reverse blend."""
+    return (pairs * OPS_ALPHA_PER_PAIR + contributors * OPS_FWD_PER_CONTRIB,
+            pairs * OPS_ALPHA_PER_PAIR + contributors * OPS_BWD_PER_CONTRIB)
 
 
 def _args():
@@ -78,7 +90,7 @@ def training_step_bench(args):
     log("bench: generating the 1M-Gaussian workload")
     scene, cam, gt = synth.c2_inputs()
     n, W, H = scene.n, cam.width, cam.height
-    ctx = api.Context(0)
+    ctx = api.Context(0, max_pixels=W * H)   # the error statistics' scratch, reserved at set-up
     g = api.Gaussians.from_scene(scene)
     gtt = torch.from_numpy(gt).cuda()
     G = torch.from_numpy(np.random.default_rng(7).normal(0.0, 1.0 / (3 * W * H), (3, H, W)).astype(np.float32)).cuda()
@@ -176,6 +188,8 @@ def densify_bench(ctx):
     attr = torch.zeros(n, dtype=torch.int32, device="cuda")
     out = api.Gaussians.empty(n + len(cand) * (params.n_max + 1), 3)
     dm = frame.device_maps()
+    ctx.reserve(max_pixels=W * H, max_gaussians=n, max_candidates=len(cand), max_regions=regions.capacity,
+                max_views=V)
 
     def densify():
         regions.count.zero_()
@@ -489,7 +503,8 @@ def main():
         del src, dst
     res = training_step_bench(args)
     consts = load_workload_constants()
-    P_alg = consts["pairs"]
+    P_alg, C_alg = consts["pairs"], consts["contributors"]
+    ops_fwd, ops_bwd = blend_ops(P_alg, C_alg)
     n, W, H, K = res["n"], res["W"], res["H"], res["K"]
     # stage time per step (a stage may record more than one segment per step)
     per_step = {k: v[0] / res["stage_steps"] for k, v in res["stages"].items() if v[1]}
@@ -500,8 +515,8 @@ def main():
         "emit": ("hbm", (n * 16 + K * 12) / 1e9, "GB"),
         "sort": ("hbm", K * 24 / 1e9, "GB"),
         "ranges": ("hbm", (K * 8 + 8 * ((W + 15) // 16) * ((H + 15) // 16)) / 1e9, "GB"),
-        "blend_fwd": ("alu", P_alg * OPS_FWD_PER_PAIR / 1e12, "TOP"),
-        "blend_bwd": ("alu", P_alg * OPS_BWD_PER_PAIR / 1e12, "TOP"),
+        "blend_fwd": ("alu", ops_fwd / 1e12, "TOP"),
+        "blend_bwd": ("alu", ops_bwd / 1e12, "TOP"),
         "project_bwd": ("hbm", n * (2 * sh3_bytes() + 36 + 4 + 16) / 1e9, "GB"),
         "error_stats": ("hbm", W * H * 30 / 1e9, "GB"),
     }
@@ -528,7 +543,7 @@ def main():
     blend_roof = None
     if per_step.get("blend_fwd", 0) > 0 and per_step.get("blend_bwd", 0) > 0:
         t_fb = (per_step["blend_fwd"] + per_step["blend_bwd"]) / 1e3
-        ach = P_alg * (OPS_FWD_PER_PAIR + OPS_BWD_PER_PAIR) / 1e12 / t_fb
+        ach = (ops_fwd + ops_bwd) / 1e12 / t_fb
         blend_roof = dict(bound="alu", achieved=round(ach, 3), peak=round(PEAK_VALU_TOPS, 2), unit="TOP/s",
                           frac=round(ach / PEAK_VALU_TOPS, 4), stages=["blend_fwd", "blend_bwd"],
                           ms=round(t_fb * 1e3, 4))
@@ -552,6 +567,7 @@ def main():
         "config": {"workload": "training step: render + L1 error statistics (5% candidates) + backward, "
                                "1,000,000 Gaussians SH3, one 1256x828 view",
                    "gaussians": n, "width": W, "height": H, "sh_degree": 3, "pairs_tile": K, "pairs_alg": P_alg,
+                   "contributors_alg": C_alg,
                    "regions": res["n_regions"], "tuning": res["tuning"]},
         "tuning_candidates_ms": res["tuning_ms"],
         "roofline": roof,

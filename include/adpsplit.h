@@ -138,7 +138,9 @@ typedef struct {
     int64_t n_cap, key_cap;
     int32_t tile_base;        /* global id of the view's first tile */
     uint32_t ent_base;        /* global entry id of the view's Gaussian 0 */
-    uint32_t *n_keys;         /* [1] number of (tile, entry) pairs of the last render, all views */
+    uint32_t *n_keys;         /* [2] (tile, entry) pairs of the last render, all views: [0] the
+                                 number it needed, [1] the number written to keys / vals
+                                 (fewer when [0] > key_cap) */
     uint32_t *keys;           /* [key_cap] sorted global tile ids */
     uint32_t *vals;           /* [key_cap] entry id of each sorted pair (entry = ent_base of its view + Gaussian id) */
     uint32_t *ranges;         /* [tiles][2] start, end into keys/vals of the view's tiles */
@@ -170,21 +172,70 @@ void as_ctx_destroy(as_ctx *ctx);
 const char *as_last_error(void);
 const char *as_version(void);
 
+/* Context scratch for the error statistics, the split and the loop's
+ * densification calls.  Those calls never allocate: each checks its sizes
+ * against the context's reservation and returns AS_ERR_CAPACITY (naming the
+ * field to raise) when they exceed it. */
+typedef struct {
+    int64_t max_pixels;      /* largest W x H given to as_accumulate_error_stats */
+    int64_t max_gaussians;   /* largest Gaussian set given to as_adaptive_split, as_densify_select,
+                                as_split_row_map and as_clone_prune */
+    int64_t max_candidates;  /* largest candidate capacity given to as_adaptive_split */
+    int64_t max_regions;     /* largest region-buffer capacity given to as_adaptive_split */
+    int32_t max_views;       /* most views given to as_adaptive_split */
+} as_reserve;
+/* Grow the context's scratch to cover `r` (each field the maximum of the
+ * current and the requested value).  A set-up call: it may allocate, so
+ * AS_ERR_STATE inside a graph capture. */
+as_status as_ctx_reserve(as_ctx *ctx, const as_reserve *r);
+/* The context's current reservation. */
+as_status as_ctx_get_reserve(const as_ctx *ctx, as_reserve *r);
+/* Device bytes of the scratch a context reserved for `r` holds. */
+as_status as_ctx_reserve_bytes(const as_reserve *r, size_t *bytes);
+
+/* Frame flags. */
+enum {
+    AS_FRAME_FORWARD_ONLY = 1   /* no checkpoint buffer (12 KiB per tile): for frames that are only
+                                   rendered (serving, error statistics); a reverse pass on such a
+                                   frame walks every tile's list in one piece (same results up to
+                                   float rounding) */
+};
+
 /* Allocate the per-view state of the rasterizer: n_cap Gaussians, a width x
  * height image, and key_cap (tile, Gaussian) pairs (<= 2^32 - 1).  The frame
- * owns its device memory; as_frame_destroy frees it.  When `auto_grow` is
- * nonzero, as_render synchronises once after binning to read the pair count
- * and grows the key buffers if needed; when zero, the render never
- * synchronises, and a pair count above key_cap leaves *n_keys > key_cap with
- * the pairs beyond capacity dropped (the caller checks and re-renders). */
+ * owns its device memory, all of it allocated here (as_frame_bytes gives the
+ * total); as_frame_destroy frees it.  The calls that render into a frame and
+ * run its reverse pass never allocate and never synchronise.  A render whose
+ * pairs exceed key_cap writes the pairs of the entries (in depth order) that
+ * fit whole and renders from those; the frame's *n_keys still reports the full
+ * demand, so a caller that reads it after synchronising and finds it above
+ * key_cap reserves more with as_frame_reserve_keys and renders again.
+ *   flags : 0 or AS_FRAME_FORWARD_ONLY.  AS_ERR_STATE inside a graph capture. */
 as_status as_frame_create(as_ctx *ctx, int64_t n_cap, int32_t width, int32_t height, int64_t key_cap,
-                          int32_t auto_grow, as_frame **out);
+                          uint32_t flags, as_frame **out);
 /* A frame for batched renders of up to max_views (<= 16) views of any sizes:
  * entry_cap bounds the sum over the views of their Gaussian counts,
  * pixel_cap the sum of W x H, tile_cap the sum of 16 x 16 tiles (a W x H view
- * has ceil(W/16) ceil(H/16)); key_cap and auto_grow as above. */
+ * has ceil(W/16) ceil(H/16)); key_cap and flags as above. */
 as_status as_frame_create_batch(as_ctx *ctx, int32_t max_views, int64_t entry_cap, int64_t pixel_cap,
-                                int64_t tile_cap, int64_t key_cap, int32_t auto_grow, as_frame **out);
+                                int64_t tile_cap, int64_t key_cap, uint32_t flags, as_frame **out);
+/* Grow a frame's pair capacity to key_cap (no-op if it already holds that
+ * many).  A set-up call: it waits for the device, frees and reallocates the
+ * pair buffers and forgets the last render (render again before a reverse
+ * pass).  AS_ERR_STATE inside a graph capture. */
+as_status as_frame_reserve_keys(as_frame *f, int64_t key_cap);
+/* Device bytes a frame with these capacities and flags holds (the sum of its
+ * allocations as requested from hipMalloc), without creating it.  Capacities
+ * as as_frame_create_batch; a frame of as_frame_create has max_views 1,
+ * pixel_cap W H and tile_cap ceil(W/16) ceil(H/16). */
+as_status as_frame_bytes(int32_t max_views, int64_t entry_cap, int64_t pixel_cap, int64_t tile_cap, int64_t key_cap,
+                         uint32_t flags, size_t *bytes);
+/* Workspace of a render of n Gaussians in each of n_cams (1..16) cameras
+ * (host array): the bytes of the frame sized for exactly those views
+ * (entries n x n_cams, their pixels and tiles) with key_cap pairs, i.e.
+ * as_frame_bytes of that frame. */
+as_status as_workspace_size(const as_ctx *ctx, int64_t n, const as_camera *cams, int32_t n_cams, int64_t key_cap,
+                            uint32_t flags, size_t *bytes);
 void as_frame_destroy(as_frame *f);
 /* Copy the pair count of the last render (all views) to dst ([1], device
  * memory) on `stream`, after the work already queued there; lets a caller
@@ -211,14 +262,12 @@ as_status as_render(as_ctx *ctx, const as_gaussians *g, const as_camera *cam, as
 
 /* Reverse pass of the last as_render into `frame` (the differentiable
  * rasterizer of Sec. 3): recomputes the blend per tile backwards from the
- * stored final transmittance and last-contributor index.  The first reverse
- * pass on a frame allocates its checkpoint buffer (4 KB per tile per
- * checkpoint, 3 checkpoints per tile, held until as_frame_destroy); renders
- * after that write per-pixel checkpoints at their batch boundaries, and the
- * reverse pass splits long tile lists at them into independent segments.  If
- * that allocation fails, or the first reverse pass runs inside a graph
- * capture (which allocates nothing), the reverse pass walks each tile in one
- * piece (same results up to float rounding, no error).
+ * stored final transmittance and last-contributor index.  Renders into a
+ * frame write per-pixel checkpoints (T, colour behind) at the forward's
+ * batch boundaries (up to 3 per tile, in the frame's checkpoint buffer), and
+ * this pass splits long tile lists at them into independent segments; a
+ * forward-only frame has no checkpoints and this pass walks each tile in one
+ * piece (same results up to float rounding).  Allocates nothing.
  *   dL_dimage : [3][H][W]
  *   grads     : out, overwritten; same layout and degree as g, stride g->n
  *   g2d_norm  : NULL or [n]; += |dL/d(mean2d)| (pixel units) for each Gaussian
@@ -270,7 +319,9 @@ as_status as_error_map(as_ctx *ctx, int32_t width, int32_t height, const float *
  *   dom             : [H][W] dominant map (-1 = none)
  *   gt              : [3][H][W] target (colour at the centroid)
  *   is_candidate    : [n] 0/1 split-candidate mask
- *   attr_count      : [n] accumulated */
+ *   attr_count      : [n] accumulated
+ * Uses the context's reserved scratch and allocates nothing: AS_ERR_CAPACITY
+ * when width x height exceeds the reservation's max_pixels. */
 as_status as_accumulate_error_stats(as_ctx *ctx, int32_t width, int32_t height, const double *err,
                                     const uint64_t *err_minmax, const int32_t *dom, const float *gt, int32_t view_id,
                                     int64_t n, const uint8_t *is_candidate, const as_split_params *params,
@@ -297,7 +348,9 @@ as_status as_accumulate_error_stats(as_ctx *ctx, int32_t width, int32_t height, 
  *   n_out      : out [1] device; the new set is the non-removed Gaussians in
  *                order, then one block per candidate in ascending id order
  *                (children by descending extent, then the parent copy).
- * Returns AS_ERR_CAPACITY when out->n is below the bound above. */
+ * Returns AS_ERR_CAPACITY when out->n is below the bound above, or when the
+ * region capacity, n_cand, n_views or g->n exceed the context's reservation
+ * (max_regions, max_candidates, max_views, max_gaussians); allocates nothing. */
 as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *cand, int64_t n_cand,
                             const as_region_buf *regions, const as_camera *views, int32_t n_views,
                             const int32_t *attr_count, const as_split_params *params, const float *noise,
@@ -310,7 +363,10 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
  * screen-space gradient and prunes transparent ones; Sec. 5 "Implementation":
  * AdpSplit replaces the split and keeps the rest).  These entry points are the
  * loop's per-iteration steps (loss, Adam) and its densification bookkeeping
- * (selection, row maps, clone + prune, optimiser-state carry-over). */
+ * (selection, row maps, clone + prune, optimiser-state carry-over).  None of
+ * them allocates; as_densify_select, as_split_row_map and as_clone_prune use
+ * the context's scratch reserved for max_gaussians rows (AS_ERR_CAPACITY
+ * beyond it). */
 
 /* Adam hyper-parameters with the per-group learning rates of 3DGS. */
 typedef struct {
@@ -435,11 +491,12 @@ as_status as_timing_read(as_ctx *ctx, double *ms, int64_t *runs);
 /* Record every call made on `stream` between as_graph_begin and as_graph_end
  * into a HIP graph, replayed by as_graph_launch with the same arguments
  * (the device buffers the calls named must stay allocated, and their
- * contents at replay time are the inputs).  None of the calls of this
- * library synchronise or allocate while a stream is capturing: frames must
- * have auto_grow = 0 and every context buffer must already have its size,
- * so each captured call is made once outside the capture first
- * (AS_ERR_STATE otherwise).  Per-stage timing is suspended while capturing. */
+ * contents at replay time are the inputs).  The calls of the path and of
+ * the loop never synchronise or allocate, so any of them can be captured once
+ * the frames exist and the context's reservation covers the sizes; the
+ * set-up calls (frame creation, as_frame_reserve_keys, as_ctx_reserve)
+ * return AS_ERR_STATE inside a capture.  Per-stage timing is suspended while
+ * capturing. */
 typedef struct as_graph as_graph;
 as_status as_graph_begin(as_ctx *ctx, void *stream);
 as_status as_graph_end(as_ctx *ctx, void *stream, as_graph **out);
@@ -449,7 +506,8 @@ void as_graph_destroy(as_graph *graph);
 /* ---- test hooks --------------------------------------------------------------- */
 
 /* Stable LSD radix sort of n (key, value) pairs on the low key_bits bits, in
- * place (the sorter the binning uses, with the context's radix_bits).
+ * place (the sorter the binning uses, with the context's radix_bits).  A
+ * test hook: it grows its own scratch on demand (it allocates).
  * keys [n], vals [n]; bits at and above key_bits are ignored. */
 as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, int32_t key_bits, void *stream);
 

@@ -70,8 +70,17 @@ REGION_DTYPE = np.dtype([
     ("rgb", "<f4", (3,)), ("pad1", "<f4")])
 assert REGION_DTYPE.itemsize == 152
 
-EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "as_frame_create",
-            "as_frame_create_batch", "as_frame_destroy", "as_frame_get_view", "as_frame_get_view_of",
+class _Reserve(ctypes.Structure):
+    _fields_ = [("max_pixels", ctypes.c_int64), ("max_gaussians", ctypes.c_int64), ("max_candidates", ctypes.c_int64),
+                ("max_regions", ctypes.c_int64), ("max_views", ctypes.c_int32)]
+
+
+RESERVE_FIELDS = ("max_pixels", "max_gaussians", "max_candidates", "max_regions", "max_views")
+FRAME_FORWARD_ONLY = 1
+
+EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "as_ctx_reserve", "as_ctx_get_reserve",
+            "as_ctx_reserve_bytes", "as_frame_create", "as_frame_create_batch", "as_frame_reserve_keys",
+            "as_frame_bytes", "as_workspace_size", "as_frame_destroy", "as_frame_get_view", "as_frame_get_view_of",
             "as_frame_pair_count", "as_render",
             "as_render_backward", "as_render_batch", "as_render_backward_batch", "as_error_map",
             "as_accumulate_error_stats", "as_adaptive_split", "as_set_tuning", "as_get_tuning", "as_timing_enable",
@@ -198,14 +207,62 @@ class Gaussians:
                          self.sh[:, :, :n].contiguous(), self.sh_degree)
 
 
-class Context:
-    """An as_ctx bound to one device."""
+def _reserve_struct(r):
+    unknown = set(r) - set(RESERVE_FIELDS)
+    if unknown:
+        raise TypeError("unknown reservation fields %s" % sorted(unknown))
+    return _Reserve(*[int(r.get(f, 0)) for f in RESERVE_FIELDS])
 
-    def __init__(self, device=0):
+
+def reserve_bytes(**r):
+    """as_ctx_reserve_bytes: device bytes of a context reservation."""
+    out = ctypes.c_size_t()
+    _check(lib().as_ctx_reserve_bytes(ctypes.byref(_reserve_struct(r)), ctypes.byref(out)))
+    return int(out.value)
+
+
+def frame_bytes(max_views, entry_cap, pixel_cap, tile_cap, key_cap, forward_only=False):
+    """as_frame_bytes: device bytes of a frame with these capacities."""
+    out = ctypes.c_size_t()
+    _check(lib().as_frame_bytes(ctypes.c_int32(max_views), ctypes.c_int64(entry_cap), ctypes.c_int64(pixel_cap),
+                                ctypes.c_int64(tile_cap), ctypes.c_int64(key_cap),
+                                ctypes.c_uint32(FRAME_FORWARD_ONLY if forward_only else 0), ctypes.byref(out)))
+    return int(out.value)
+
+
+def workspace_size(ctx, n, cams, key_cap, forward_only=False):
+    """as_workspace_size: bytes of the frame for n Gaussians in these cameras."""
+    out = ctypes.c_size_t()
+    cs = (_Camera * len(cams))(*[camera_struct(c) for c in cams])
+    _check(lib().as_workspace_size(ctx.handle, ctypes.c_int64(n), cs, ctypes.c_int32(len(cams)),
+                                   ctypes.c_int64(key_cap), ctypes.c_uint32(FRAME_FORWARD_ONLY if forward_only else 0),
+                                   ctypes.byref(out)))
+    return int(out.value)
+
+
+class Context:
+    """An as_ctx bound to one device.  Keyword arguments (max_pixels,
+    max_gaussians, max_candidates, max_regions, max_views) reserve the
+    context's scratch at creation (as_ctx_reserve); the error statistics, the
+    split and the loop's densification calls raise AS_ERR_CAPACITY beyond
+    the reservation, they never allocate."""
+
+    def __init__(self, device=0, **reserve):
         self.device = device
         h = ctypes.c_void_p()
         _check(lib().as_ctx_create(ctypes.c_int(device), ctypes.byref(h)))
         self.handle = h
+        if reserve:
+            self.reserve(**reserve)
+
+    def reserve(self, **r):
+        """Grow the reservation to at least r (fields as as_reserve)."""
+        _check(lib().as_ctx_reserve(self.handle, ctypes.byref(_reserve_struct(r))))
+
+    def reserved(self):
+        r = _Reserve()
+        _check(lib().as_ctx_get_reserve(self.handle, ctypes.byref(r)))
+        return {f: int(getattr(r, f)) for f in RESERVE_FIELDS}
 
     def close(self):
         if self.handle:
@@ -221,15 +278,41 @@ class Context:
 
 class Frame:
     """Rasterizer state (as_frame): one view of a fixed size, or (batch=True
-    through BatchFrame) up to 16 views of any sizes."""
+    through BatchFrame) up to 16 views of any sizes.  The library renders into
+    a frame without allocating or synchronising; with auto_grow the binding's
+    render helpers read the pair count back after each render and, when it
+    exceeds the capacity, reserve more (as_frame_reserve_keys) and render
+    again.  forward_only frames hold no reverse-pass checkpoints."""
 
-    def __init__(self, ctx, n_cap, width, height, key_cap=None, auto_grow=True):
+    def __init__(self, ctx, n_cap, width, height, key_cap=None, auto_grow=True, forward_only=False):
         if key_cap is None:
             key_cap = max(1 << 16, 8 * n_cap)
         h = ctypes.c_void_p()
         _check(lib().as_frame_create(ctx.handle, ctypes.c_int64(n_cap), ctypes.c_int32(width), ctypes.c_int32(height),
-                                     ctypes.c_int64(key_cap), ctypes.c_int32(1 if auto_grow else 0), ctypes.byref(h)))
+                                     ctypes.c_int64(key_cap), ctypes.c_uint32(FRAME_FORWARD_ONLY if forward_only else 0),
+                                     ctypes.byref(h)))
         self.ctx, self.handle, self.width, self.height, self.n_cap = ctx, h, width, height, n_cap
+        self.auto_grow = auto_grow
+
+    def reserve_keys(self, key_cap):
+        """as_frame_reserve_keys (a set-up call: synchronises, may allocate)."""
+        _check(lib().as_frame_reserve_keys(self.handle, ctypes.c_int64(key_cap)))
+
+    def _check_capturable(self):
+        if self.auto_grow and torch.cuda.is_current_stream_capturing():
+            raise AdpSplitError(AS_ERR_STATE, "a frame with auto_grow reads its pair count back after each render "
+                                              "and cannot be captured in a graph")
+
+    def _fit_keys(self):
+        """After a render: True (and the pair buffers grown) when its pairs did
+        not fit, so the caller renders again."""
+        if not self.auto_grow:
+            return False
+        K = self.n_keys()
+        if K <= self.key_cap:
+            return False
+        self.reserve_keys(min(K + K // 4 + 1024, 0xFFFFFFFF))
+        return True
 
     def view(self, v=0):
         out = _FrameView()
@@ -257,8 +340,14 @@ class Frame:
         return out
 
     def n_keys(self):
+        """Pairs the last render needed (all views)."""
         v = self.view()
         return int(self._dev(v.n_keys, 4).view(np.uint32)[0])
+
+    def n_emitted(self):
+        """Pairs the last render wrote (fewer than n_keys() when over key_cap)."""
+        v = self.view()
+        return int(self._dev(v.n_keys, 8).view(np.uint32)[1])
 
     def pair_count_async(self, dst, stream=None):
         """Queue a copy of the last render's pair count into dst (int32 [1], device)."""
@@ -275,7 +364,7 @@ class Frame:
         (tile of the view) << 32 | depth bits, the form of a (tile | depth)
         sort, and `gauss` its Gaussian id (meaningful for this view's pairs)."""
         v = self.view(view)
-        K = min(self.n_keys(), v.key_cap)
+        K = self.n_emitted()
         H, W = v.height, v.width
         P = W * H
         T = v.tiles_x * v.tiles_y
@@ -309,22 +398,26 @@ class Frame:
 class BatchFrame(Frame):
     """as_frame_create_batch: state for batched renders of up to max_views views."""
 
-    def __init__(self, ctx, max_views, entry_cap, pixel_cap, tile_cap, key_cap=None, auto_grow=True):
+    def __init__(self, ctx, max_views, entry_cap, pixel_cap, tile_cap, key_cap=None, auto_grow=True,
+                 forward_only=False):
         if key_cap is None:
             key_cap = max(1 << 16, 8 * entry_cap)
         h = ctypes.c_void_p()
         _check(lib().as_frame_create_batch(ctx.handle, ctypes.c_int32(max_views), ctypes.c_int64(entry_cap),
                                            ctypes.c_int64(pixel_cap), ctypes.c_int64(tile_cap),
-                                           ctypes.c_int64(key_cap), ctypes.c_int32(1 if auto_grow else 0),
+                                           ctypes.c_int64(key_cap),
+                                           ctypes.c_uint32(FRAME_FORWARD_ONLY if forward_only else 0),
                                            ctypes.byref(h)))
         self.ctx, self.handle, self.n_cap, self.max_views = ctx, h, entry_cap, max_views
+        self.auto_grow = auto_grow
 
     @staticmethod
-    def for_views(ctx, n_per_view, cams, key_cap=None, auto_grow=True):
+    def for_views(ctx, n_per_view, cams, key_cap=None, auto_grow=True, forward_only=False):
         """A frame sized for exactly these views (n_per_view: int or list)."""
         ns = n_per_view if isinstance(n_per_view, (list, tuple)) else [n_per_view] * len(cams)
         tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
-        return BatchFrame(ctx, len(cams), sum(ns), sum(c.width * c.height for c in cams), tiles, key_cap, auto_grow)
+        return BatchFrame(ctx, len(cams), sum(ns), sum(c.width * c.height for c in cams), tiles, key_cap, auto_grow,
+                          forward_only)
 
 
 _hiprt = None
@@ -351,9 +444,12 @@ def render(ctx, g, cam, frame, gt=None, image=None, stream=None):
         image = torch.empty(3, cam.height, cam.width, dtype=torch.float32, device="cuda")
     gs = g.struct()
     c = camera_struct(cam)
-    _check(lib().as_render(ctx.handle, ctypes.byref(gs), ctypes.byref(c), frame.handle, _ptr(gt), _ptr(image),
-                           _stream(stream)))
-    return image
+    frame._check_capturable()
+    while True:
+        _check(lib().as_render(ctx.handle, ctypes.byref(gs), ctypes.byref(c), frame.handle, _ptr(gt), _ptr(image),
+                               _stream(stream)))
+        if not frame._fit_keys():
+            return image
 
 
 def render_backward(ctx, g, cam, frame, dL_dimage, grads=None, g2d_norm=None, vis_count=None, stream=None):
@@ -380,8 +476,11 @@ def render_batch(ctx, scenes, cams, frame, gts=None, images=None, stream=None):
     cs = (_Camera * V)(*[camera_struct(c) for c in cams])
     ims = (ctypes.c_void_p * V)(*[_ptr(t).value for t in images])
     gp = (ctypes.c_void_p * V)(*[_ptr(t).value for t in gts]) if gts is not None else None
-    _check(lib().as_render_batch(ctx.handle, ss, cs, ctypes.c_int32(V), frame.handle, gp, ims, _stream(stream)))
-    return images
+    frame._check_capturable()
+    while True:
+        _check(lib().as_render_batch(ctx.handle, ss, cs, ctypes.c_int32(V), frame.handle, gp, ims, _stream(stream)))
+        if not frame._fit_keys():
+            return images
 
 
 def render_backward_batch(ctx, g, frame, dL_dimages, grads=None, g2d_norm=None, vis_count=None, stream=None):
@@ -491,17 +590,22 @@ def accumulate_error_stats(ctx, width, height, err, err_minmax, dom, gt, view_id
                                            ctypes.byref(rb), _ptr(attr_count), _stream(stream)))
 
 
-def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=None, stream=None):
+def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=None, mode=None, count=None,
+                   offset=None, n_out=None, stream=None):
     """as_adaptive_split.  Returns (out Gaussians with capacity rows, mode,
-    count, offset, n_out tensor)."""
+    count, offset, n_out tensor); outputs not passed are allocated here."""
     nc = int(cand.shape[0])
     if out is None:
         cap = g.n + nc * max(2, params.n_max + 1, params.fixed_n if params.variant == VARIANT_FIXED_N else 0)
         out = Gaussians.empty(max(cap, 1), g.sh_degree)
-    mode = torch.zeros(max(nc, 1), dtype=torch.uint8, device="cuda")
-    count = torch.zeros(max(nc, 1), dtype=torch.int32, device="cuda")
-    offset = torch.zeros(max(nc, 1), dtype=torch.int64, device="cuda")
-    n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    if mode is None:
+        mode = torch.zeros(max(nc, 1), dtype=torch.uint8, device="cuda")
+    if count is None:
+        count = torch.zeros(max(nc, 1), dtype=torch.int32, device="cuda")
+    if offset is None:
+        offset = torch.zeros(max(nc, 1), dtype=torch.int64, device="cuda")
+    if n_out is None:
+        n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
     cams = (_Camera * max(len(views), 1))(*[camera_struct(v) for v in views])
     gs = g.struct()
     p = params.struct()

@@ -93,23 +93,71 @@ hipError_t dmalloc(T **p, size_t count) {
     return hipMalloc((void **)p, count * sizeof(T) + 256);
 }
 
-void free_keys(as_frame *f) {
-    for (int k = 0; k < 2; k++) {
-        if (f->keys[k]) (void)hipFree(f->keys[k]);
-        if (f->vals[k]) (void)hipFree(f->vals[k]);
-        f->keys[k] = nullptr;
-        f->vals[k] = nullptr;
-    }
+// scratch slots of ctx->tr (the optimisation loop's calls)
+enum { TR_PART, TR_FLAG, TR_SCAN, TR_TMP, TR_DUP, TR_DSCAN, TR_TOT, TR_TMP2 };
+
+// Bytes of the loop's Gaussian-sized slots for up to n rows (TR_PART and
+// TR_TOT are fixed and allocated with the context).
+void tr_need(int64_t n, size_t need[8]) {
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    for (int k = 0; k < 8; k++) need[k] = 0;
+    need[TR_FLAG] = m;
+    need[TR_DUP] = m;
+    need[TR_SCAN] = m * 8;
+    need[TR_DSCAN] = m * 8;
+    need[TR_TMP] = scan_tmp_bytes((int64_t)m);
+    need[TR_TMP2] = scan_tmp_bytes((int64_t)m);
 }
 
-hipError_t alloc_keys(as_frame *f, int64_t key_cap) {
-    hipError_t e;
+size_t round256(size_t b) { return ((b < 256 ? 256 : b) + 255) & ~(size_t)255; }
+
+// Every device buffer of a frame with the capacities and flags in f, in one
+// table: visit(slot, bytes) is called once per buffer.  frame_alloc,
+// as_frame_destroy and the size queries walk the same table, so the bytes a
+// query reports are the bytes a frame holds.  `keys_only` visits just the
+// buffers that scale with the pair capacity (as_frame_reserve_keys).
+template <typename V>
+void frame_buffers(as_frame *f, bool keys_only, V &&visit) {
+    const int64_t ent = f->ent_cap, pix = f->pix_cap, tile = f->tile_cap, key = f->key_cap;
+    auto arr = [&](auto **p, int64_t count) { visit((void **)p, round256((size_t)count * sizeof(**p) + 256)); };
+    auto dbuf = [&](DevBuf &b, size_t bytes) {
+        b.bytes = round256(bytes);
+        visit(&b.p, b.bytes);
+    };
     for (int k = 0; k < 2; k++) {
-        if ((e = dmalloc(&f->keys[k], key_cap)) != hipSuccess) return e;
-        if ((e = dmalloc(&f->vals[k], key_cap)) != hipSuccess) return e;
+        arr(&f->keys[k], key);
+        arr(&f->vals[k], key);
     }
-    f->key_cap = key_cap;
-    return devbuf_ensure(f->sort_hist, sort_hist_bytes(key_cap));
+    dbuf(f->sort_hist, sort_hist_bytes(key));
+    if (keys_only) return;
+    arr(&f->rec, ent); arr(&f->depth_key, ent); arr(&f->box, ent * 4); arr(&f->ntiles, ent); arr(&f->offsets, ent);
+    arr(&f->grad2d, ent * 9);
+    arr(&f->dkeys[0], ent); arr(&f->dkeys[1], ent); arr(&f->dvals[0], ent); arr(&f->dvals[1], ent);
+    arr(&f->nt_sorted, ent); arr(&f->n_ent, 4); arr(&f->n_keys, 4);
+    dbuf(f->dsort_hist, sort_hist_bytes(ent));
+    dbuf(f->scan_tmp, scan_tmp_bytes(ent));
+    arr(&f->ranges, tile * 2); arr(&f->tile_order, tile); arr(&f->queue, 2); arr(&f->tile_work, tile);
+    arr(&f->tile_order_bwd, tile); arr(&f->tile_hi, tile); arr(&f->n_items, 1);
+    arr(&f->bwd_items, tile * (AS_CK_MAX + 1) * 2);
+    arr(&f->tile_err, tile * 2);
+    if (!(f->flags & AS_FRAME_FORWARD_ONLY)) arr(&f->ckpt, tile * AS_CK_MAX * 256 * 4);
+    arr(&f->t_final, pix); arr(&f->last, pix); arr(&f->n_contrib, pix); arr(&f->dom, pix); arr(&f->err, pix);
+    arr(&f->err_minmax, 2 * (int64_t)f->max_views);
+}
+
+void frame_free_buffers(as_frame *f, bool keys_only) {
+    frame_buffers(f, keys_only, [](void **p, size_t) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    });
+}
+
+hipError_t frame_alloc_buffers(as_frame *f, bool keys_only) {
+    hipError_t e = hipSuccess;
+    frame_buffers(f, keys_only, [&](void **p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, bytes);
+    });
+    return e;
 }
 }  // namespace
 
@@ -200,6 +248,12 @@ as_status as_ctx_create(int device, as_ctx **out) {
     if (!c) { as_set_error("as_ctx_create: out of host memory"); return AS_ERR_HIP; }
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
+    // fixed-size scratch of the loss partials and the loop's totals
+    if (bad(devbuf_ensure(c->tr[TR_PART], l1_partials_bytes()), "as_ctx_create: scratch") ||
+        bad(devbuf_ensure(c->tr[TR_TOT], 16), "as_ctx_create: scratch")) {
+        as_ctx_destroy(c);
+        return AS_ERR_HIP;
+    }
     *out = c;
     return AS_OK;
 }
@@ -221,58 +275,125 @@ void as_ctx_destroy(as_ctx *ctx) {
     delete ctx;
 }
 
+static as_reserve reserve_max(const as_reserve &a, const as_reserve &b) {
+    as_reserve r;
+    r.max_pixels = a.max_pixels > b.max_pixels ? a.max_pixels : b.max_pixels;
+    r.max_gaussians = a.max_gaussians > b.max_gaussians ? a.max_gaussians : b.max_gaussians;
+    r.max_candidates = a.max_candidates > b.max_candidates ? a.max_candidates : b.max_candidates;
+    r.max_regions = a.max_regions > b.max_regions ? a.max_regions : b.max_regions;
+    r.max_views = a.max_views > b.max_views ? a.max_views : b.max_views;
+    return r;
+}
+
+static bool reserve_ok(const as_reserve *r, const char *what) {
+    if (!r || r->max_pixels < 0 || r->max_pixels > 0x7FFFFFFFll || r->max_gaussians < 0 ||
+        r->max_gaussians > 0xFFFFFFFFll || r->max_candidates < 0 || r->max_candidates > 0xFFFFFFFFll ||
+        r->max_regions < 0 || r->max_regions > 0xFFFFFFFFll || r->max_views < 0 || r->max_views > 65536) {
+        as_set_error("%s: reservation out of range", what);
+        return false;
+    }
+    return true;
+}
+
+static size_t loop_reserve_bytes(int64_t n) {
+    if (n <= 0) return 0;
+    size_t need[8], total = 0;
+    tr_need(n, need);
+    for (int k = 0; k < 8; k++)
+        if (need[k]) total += devbuf_size(need[k]);
+    return total;
+}
+
+as_status as_ctx_reserve(as_ctx *ctx, const as_reserve *r) {
+    if (!ctx) { as_set_error("as_ctx_reserve: null context"); return AS_ERR_ARG; }
+    if (!reserve_ok(r, "as_ctx_reserve")) return AS_ERR_ARG;
+    if (g_capturing) { as_set_error("as_ctx_reserve: allocates, so not inside a graph capture"); return AS_ERR_STATE; }
+    if (bad(hipSetDevice(ctx->device), "hipSetDevice")) return AS_ERR_HIP;
+    const as_reserve nr = reserve_max(ctx->res, *r);
+    hipError_t e = errstats_reserve(ctx, nr.max_pixels);
+    if (e == hipSuccess) e = split_reserve(ctx, nr);
+    if (e == hipSuccess && nr.max_gaussians > 0) {
+        size_t need[8];
+        tr_need(nr.max_gaussians, need);
+        for (int k = 0; k < 8 && e == hipSuccess; k++)
+            if (need[k]) e = devbuf_ensure(ctx->tr[k], need[k]);
+    }
+    if (e != hipSuccess) {
+        as_set_error("as_ctx_reserve: allocation failed: %s", hipGetErrorString(e));
+        (void)hipGetLastError();
+        return AS_ERR_HIP;
+    }
+    ctx->res = nr;
+    return AS_OK;
+}
+
+as_status as_ctx_get_reserve(const as_ctx *ctx, as_reserve *r) {
+    if (!ctx || !r) { as_set_error("as_ctx_get_reserve: null argument"); return AS_ERR_ARG; }
+    *r = ctx->res;
+    return AS_OK;
+}
+
+as_status as_ctx_reserve_bytes(const as_reserve *r, size_t *bytes) {
+    if (!bytes) { as_set_error("as_ctx_reserve_bytes: null argument"); return AS_ERR_ARG; }
+    if (!reserve_ok(r, "as_ctx_reserve_bytes")) return AS_ERR_ARG;
+    *bytes = errstats_reserve_bytes(r->max_pixels) + split_reserve_bytes(*r) + loop_reserve_bytes(r->max_gaussians);
+    return AS_OK;
+}
+
 void as_frame_destroy(as_frame *f) {
     if (!f) return;
     (void)hipSetDevice(f->device);
-    void *ptrs[] = {f->rec, f->depth_key, f->box, f->ntiles, f->offsets, f->grad2d, f->ranges, f->n_keys,
-                    f->t_final, f->last, f->n_contrib, f->dom, f->err, f->err_minmax, f->tile_err, f->dkeys[0], f->dkeys[1],
-                    f->dvals[0], f->dvals[1], f->nt_sorted, f->n_ent, f->tile_order, f->tile_work, f->tile_order_bwd,
-                    f->queue, f->tile_hi, f->ckpt, f->bwd_items, f->n_items};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    free_keys(f);
-    devbuf_free(f->scan_tmp);
-    devbuf_free(f->sort_hist);
-    devbuf_free(f->dsort_hist);
-    if (f->h_nkeys) (void)hipHostFree(f->h_nkeys);
+    frame_free_buffers(f, false);
     delete f;
 }
 
+static bool frame_caps_ok(int32_t max_views, int64_t ent_cap, int64_t pix_cap, int64_t tile_cap, int64_t key_cap,
+                          uint32_t flags, const char *what) {
+    if (max_views < 1 || max_views > AS_MAX_VIEWS || ent_cap < 1 || ent_cap > 0xFFFFFFFFll || pix_cap < 1 ||
+        pix_cap > 0x7FFFFFFFll || tile_cap < 1 || tile_cap > 0x7FFFFFFFll || key_cap < 1 || key_cap > 0xFFFFFFFFll ||
+        (flags & ~(uint32_t)AS_FRAME_FORWARD_ONLY)) {
+        as_set_error("%s: size out of range (views %d, entries %lld, pixels %lld, tiles %lld, keys %lld, flags 0x%x)",
+                     what, max_views, (long long)ent_cap, (long long)pix_cap, (long long)tile_cap, (long long)key_cap,
+                     flags);
+        return false;
+    }
+    return true;
+}
+
+static void frame_set_caps(as_frame *f, int32_t max_views, int64_t ent_cap, int64_t pix_cap, int64_t tile_cap,
+                           int64_t key_cap, uint32_t flags) {
+    f->max_views = max_views;
+    f->ent_cap = ent_cap;
+    f->pix_cap = pix_cap;
+    f->tile_cap = tile_cap;
+    f->key_cap = key_cap;
+    f->flags = flags;
+}
+
+static size_t frame_bytes(int32_t max_views, int64_t ent_cap, int64_t pix_cap, int64_t tile_cap, int64_t key_cap,
+                          uint32_t flags) {
+    as_frame f;
+    frame_set_caps(&f, max_views, ent_cap, pix_cap, tile_cap, key_cap, flags);
+    size_t total = 0;
+    frame_buffers(&f, false, [&](void **, size_t bytes) { total += bytes; });
+    return total;
+}
+
 static as_status frame_alloc(as_ctx *ctx, int32_t max_views, int64_t ent_cap, int64_t pix_cap, int64_t tile_cap,
-                             int64_t key_cap, int32_t auto_grow, int32_t fixed_w, int32_t fixed_h, as_frame **out) {
+                             int64_t key_cap, uint32_t flags, int32_t fixed_w, int32_t fixed_h, as_frame **out) {
     if (bad(hipSetDevice(ctx->device), "hipSetDevice")) return AS_ERR_HIP;
+    if (g_capturing) { as_set_error("as_frame_create: allocates, so not inside a graph capture"); return AS_ERR_STATE; }
     as_frame *f = new (std::nothrow) as_frame();
     if (!f) { as_set_error("as_frame_create: out of host memory"); return AS_ERR_HIP; }
     f->ctx = ctx;
     f->device = ctx->device;
-    f->max_views = max_views;
     f->fixed_w = fixed_w;
     f->fixed_h = fixed_h;
-    f->auto_grow = auto_grow;
-    f->ent_cap = ent_cap;
-    f->pix_cap = pix_cap;
-    f->tile_cap = tile_cap;
-    hipError_t e = hipSuccess;
-    if ((e = dmalloc(&f->rec, ent_cap)) != hipSuccess || (e = dmalloc(&f->depth_key, ent_cap)) != hipSuccess ||
-        (e = dmalloc(&f->box, ent_cap * 4)) != hipSuccess || (e = dmalloc(&f->ntiles, ent_cap)) != hipSuccess ||
-        (e = dmalloc(&f->offsets, ent_cap)) != hipSuccess || (e = dmalloc(&f->grad2d, ent_cap * 9)) != hipSuccess ||
-        (e = dmalloc(&f->ranges, tile_cap * 2)) != hipSuccess || (e = dmalloc(&f->n_keys, 4)) != hipSuccess ||
-        (e = dmalloc(&f->tile_order, tile_cap)) != hipSuccess || (e = dmalloc(&f->queue, 2)) != hipSuccess ||
-        (e = dmalloc(&f->tile_work, tile_cap)) != hipSuccess || (e = dmalloc(&f->tile_order_bwd, tile_cap)) != hipSuccess ||
-        (e = dmalloc(&f->tile_hi, tile_cap)) != hipSuccess || (e = dmalloc(&f->n_items, 1)) != hipSuccess ||
-        (e = dmalloc(&f->bwd_items, tile_cap * (AS_CK_MAX + 1) * 2)) != hipSuccess ||
-        (e = dmalloc(&f->t_final, pix_cap)) != hipSuccess || (e = dmalloc(&f->last, pix_cap)) != hipSuccess ||
-        (e = dmalloc(&f->n_contrib, pix_cap)) != hipSuccess || (e = dmalloc(&f->dom, pix_cap)) != hipSuccess ||
-        (e = dmalloc(&f->err, pix_cap)) != hipSuccess || (e = dmalloc(&f->err_minmax, 2 * max_views)) != hipSuccess ||
-        (e = dmalloc(&f->tile_err, tile_cap * 2)) != hipSuccess ||
-        (e = dmalloc(&f->dkeys[0], ent_cap)) != hipSuccess || (e = dmalloc(&f->dkeys[1], ent_cap)) != hipSuccess ||
-        (e = dmalloc(&f->dvals[0], ent_cap)) != hipSuccess || (e = dmalloc(&f->dvals[1], ent_cap)) != hipSuccess ||
-        (e = dmalloc(&f->nt_sorted, ent_cap)) != hipSuccess || (e = dmalloc(&f->n_ent, 4)) != hipSuccess ||
-        (e = devbuf_ensure(f->dsort_hist, sort_hist_bytes(ent_cap))) != hipSuccess ||
-        (e = alloc_keys(f, key_cap)) != hipSuccess ||
-        (e = devbuf_ensure(f->scan_tmp, scan_tmp_bytes(ent_cap))) != hipSuccess ||
-        (e = hipHostMalloc((void **)&f->h_nkeys, 64, hipHostMallocDefault)) != hipSuccess) {
+    frame_set_caps(f, max_views, ent_cap, pix_cap, tile_cap, key_cap, flags);
+    const hipError_t e = frame_alloc_buffers(f, false);
+    if (e != hipSuccess) {
         as_set_error("as_frame_create: allocation failed: %s", hipGetErrorString(e));
+        (void)hipGetLastError();
         as_frame_destroy(f);
         return AS_ERR_HIP;
     }
@@ -281,31 +402,74 @@ static as_status frame_alloc(as_ctx *ctx, int32_t max_views, int64_t ent_cap, in
 }
 
 as_status as_frame_create(as_ctx *ctx, int64_t n_cap, int32_t width, int32_t height, int64_t key_cap,
-                          int32_t auto_grow, as_frame **out) {
+                          uint32_t flags, as_frame **out) {
     if (!ctx || !out) { as_set_error("as_frame_create: null argument"); return AS_ERR_ARG; }
     *out = nullptr;
-    if (n_cap < 1 || n_cap > 0xFFFFFFFFll || width < 1 || height < 1 || width > 32767 || height > 32767 ||
-        key_cap < 1 || key_cap > 0xFFFFFFFFll) {
-        as_set_error("as_frame_create: size out of range (n_cap %lld, %dx%d, key_cap %lld)", (long long)n_cap, width,
-                     height, (long long)key_cap);
+    if (width < 1 || height < 1 || width > 32767 || height > 32767) {
+        as_set_error("as_frame_create: size %dx%d out of range", width, height);
         return AS_ERR_ARG;
     }
     const int64_t tiles = (int64_t)((width + AS_TILE_W - 1) / AS_TILE_W) * ((height + AS_TILE_H - 1) / AS_TILE_H);
-    return frame_alloc(ctx, 1, n_cap, (int64_t)width * height, tiles, key_cap, auto_grow, width, height, out);
+    if (!frame_caps_ok(1, n_cap, (int64_t)width * height, tiles, key_cap, flags, "as_frame_create")) return AS_ERR_ARG;
+    return frame_alloc(ctx, 1, n_cap, (int64_t)width * height, tiles, key_cap, flags, width, height, out);
 }
 
 as_status as_frame_create_batch(as_ctx *ctx, int32_t max_views, int64_t entry_cap, int64_t pixel_cap,
-                                int64_t tile_cap, int64_t key_cap, int32_t auto_grow, as_frame **out) {
+                                int64_t tile_cap, int64_t key_cap, uint32_t flags, as_frame **out) {
     if (!ctx || !out) { as_set_error("as_frame_create_batch: null argument"); return AS_ERR_ARG; }
     *out = nullptr;
-    if (max_views < 1 || max_views > AS_MAX_VIEWS || entry_cap < 1 || entry_cap > 0xFFFFFFFFll || pixel_cap < 1 ||
-        pixel_cap > 0x7FFFFFFFll || tile_cap < 1 || tile_cap > 0x7FFFFFFFll || key_cap < 1 || key_cap > 0xFFFFFFFFll) {
-        as_set_error("as_frame_create_batch: size out of range (views %d, entries %lld, pixels %lld, tiles %lld, "
-                     "keys %lld)", max_views, (long long)entry_cap, (long long)pixel_cap, (long long)tile_cap,
-                     (long long)key_cap);
+    if (!frame_caps_ok(max_views, entry_cap, pixel_cap, tile_cap, key_cap, flags, "as_frame_create_batch"))
+        return AS_ERR_ARG;
+    return frame_alloc(ctx, max_views, entry_cap, pixel_cap, tile_cap, key_cap, flags, 0, 0, out);
+}
+
+as_status as_frame_reserve_keys(as_frame *f, int64_t key_cap) {
+    if (!f) { as_set_error("as_frame_reserve_keys: null frame"); return AS_ERR_ARG; }
+    if (key_cap < 1 || key_cap > 0xFFFFFFFFll) {
+        as_set_error("as_frame_reserve_keys: key_cap %lld out of range", (long long)key_cap);
         return AS_ERR_ARG;
     }
-    return frame_alloc(ctx, max_views, entry_cap, pixel_cap, tile_cap, key_cap, auto_grow, 0, 0, out);
+    if (key_cap <= f->key_cap) return AS_OK;
+    if (g_capturing) { as_set_error("as_frame_reserve_keys: allocates, so not inside a graph capture"); return AS_ERR_STATE; }
+    if (bad(hipSetDevice(f->device), "hipSetDevice")) return AS_ERR_HIP;
+    // the pair buffers hold no state between renders: the next render rewrites them
+    if (bad(hipDeviceSynchronize(), "as_frame_reserve_keys: synchronise")) return AS_ERR_HIP;
+    frame_free_buffers(f, true);
+    f->key_cap = key_cap;
+    f->has_render = 0;
+    const hipError_t e = frame_alloc_buffers(f, true);
+    if (e != hipSuccess) {
+        as_set_error("as_frame_reserve_keys: allocation failed: %s", hipGetErrorString(e));
+        (void)hipGetLastError();
+        frame_free_buffers(f, true);
+        f->key_cap = 0;
+        return AS_ERR_HIP;
+    }
+    return AS_OK;
+}
+
+as_status as_frame_bytes(int32_t max_views, int64_t entry_cap, int64_t pixel_cap, int64_t tile_cap, int64_t key_cap,
+                         uint32_t flags, size_t *bytes) {
+    if (!bytes) { as_set_error("as_frame_bytes: null argument"); return AS_ERR_ARG; }
+    if (!frame_caps_ok(max_views, entry_cap, pixel_cap, tile_cap, key_cap, flags, "as_frame_bytes")) return AS_ERR_ARG;
+    *bytes = frame_bytes(max_views, entry_cap, pixel_cap, tile_cap, key_cap, flags);
+    return AS_OK;
+}
+
+as_status as_workspace_size(const as_ctx *ctx, int64_t n, const as_camera *cams, int32_t n_cams, int64_t key_cap,
+                            uint32_t flags, size_t *bytes) {
+    if (!ctx || !cams || !bytes || n < 1 || n_cams < 1 || n_cams > AS_MAX_VIEWS) {
+        as_set_error("as_workspace_size: bad argument");
+        return AS_ERR_ARG;
+    }
+    int64_t pix = 0, tiles = 0;
+    for (int v = 0; v < n_cams; v++) {
+        const int64_t W = cams[v].width, H = cams[v].height;
+        if (W < 1 || H < 1 || W > 32767 || H > 32767) { as_set_error("as_workspace_size: view %d size", v); return AS_ERR_ARG; }
+        pix += W * H;
+        tiles += ((W + AS_TILE_W - 1) / AS_TILE_W) * ((H + AS_TILE_H - 1) / AS_TILE_H);
+    }
+    return as_frame_bytes(n_cams, n * n_cams, pix, tiles, key_cap, flags, bytes);
 }
 
 as_status as_frame_get_view_of(const as_frame *f, int32_t view, as_frame_view *v) {
@@ -415,11 +579,6 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     vt.tile_base[n_views] = (int32_t)tiles;
     vt.ent_base[n_views] = (uint32_t)ents;
     vt.pix_base[n_views] = pix;
-    const bool cap = capturing(s);
-    if (cap && f->auto_grow) {
-        as_set_error("as_render: a frame with auto_grow synchronises and cannot be captured");
-        return AS_ERR_STATE;
-    }
     const int64_t n = ents;
     f->has_render = 0;
     {
@@ -443,35 +602,26 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
         StageTimer t(ctx, AS_STAGE_SCAN, s);
         scan_u32(f->nt_sorted, f->offsets, n, f->n_keys, f->scan_tmp.p, s);
     }
-    int64_t n_hint = f->key_cap;
-    if (f->auto_grow) {
-        if (bad(hipMemcpyAsync(f->h_nkeys, f->n_keys, 4, hipMemcpyDeviceToHost, s), "as_render: pair count readback") ||
-            bad(hipStreamSynchronize(s), "as_render: synchronise"))
-            return AS_ERR_HIP;
-        const int64_t K = *f->h_nkeys;
-        if (K > f->key_cap) {
-            free_keys(f);
-            int64_t kc = K + K / 4 + 1024;
-            if (kc > 0xFFFFFFFFll) kc = 0xFFFFFFFFll;
-            if (bad(alloc_keys(f, kc), "as_render: growing the key buffers")) return AS_ERR_HIP;
-        }
-        n_hint = K;
-    }
+    // the pair count stays on the device: the emission writes the pairs that
+    // fit (*n_keys keeps the demand for the caller's capacity check) and the
+    // pair sort's grid is sized by the capacity
+    const int64_t n_hint = f->key_cap;
     {
         StageTimer t(ctx, AS_STAGE_EMIT, s);
         launch_emit_sorted(n, order, vt, f->box, f->nt_sorted, f->offsets, f->key_cap, f->keys[0], f->vals[0],
-                           f->ranges, tiles, s);
+                           f->n_keys + 1, f->ranges, tiles, s);
     }
     int sel;
     {
         StageTimer t(ctx, AS_STAGE_SORT, s);
-        sel = radix_sort_u32(f->keys, f->vals, f->n_keys, f->key_cap, n_hint, 0, tile_bits(tiles), ctx->radix_bits,
-                             f->sort_hist.p, s);
+        // only the pairs written (a render over the capacity writes a prefix)
+        sel = radix_sort_u32(f->keys, f->vals, f->n_keys + 1, f->key_cap, n_hint, 0, tile_bits(tiles),
+                             ctx->radix_bits, f->sort_hist.p, s);
     }
     f->sorted_sel = sel;
     {
         StageTimer t(ctx, AS_STAGE_RANGES, s);
-        launch_ranges(f->keys[sel], f->n_keys, f->key_cap, tiles, f->ranges, s);
+        launch_ranges(f->keys[sel], f->n_keys + 1, f->key_cap, tiles, f->ranges, s);
         f->use_order = ctx->longest_first;
         if (f->use_order) launch_tile_order(f->ranges, (int)tiles, f->tile_order, s);
     }
@@ -529,16 +679,9 @@ as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame 
     for (int v = 0; v < vt.n_views; v++) dl.p[v] = dL_dimages[v];
     const int64_t ents = vt.ent_base[vt.n_views];
     const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
-    // The forward writes checkpoints once their buffer exists; the first
-    // reverse pass allocates it (a failed allocation only costs speed: the
-    // reverse pass then walks each tile in one piece).  Never while the stream
-    // is being captured: an allocation there would invalidate the graph.
-    if (!f->ckpt && !capturing(s)) {
-        if (dmalloc(&f->ckpt, f->tile_cap * AS_CK_MAX * 256 * 4) != hipSuccess) {
-            (void)hipGetLastError();
-            f->ckpt = nullptr;
-        }
-    }
+    // Frames hold their checkpoint buffer from creation (unless created
+    // forward-only): renders write checkpoints at the forward's batch
+    // boundaries and this pass splits long tile lists at them.
     {
         StageTimer t(ctx, AS_STAGE_BLEND_BWD, s);
         launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9 * ents, s);
@@ -583,8 +726,14 @@ as_status as_error_map(as_ctx *ctx, int32_t width, int32_t height, const float *
 }
 
 // ---- optimisation loop ----------------------------------------------------------
-// scratch slots of ctx->tr
-enum { TR_PART, TR_FLAG, TR_SCAN, TR_TMP, TR_DUP, TR_DSCAN, TR_TOT, TR_TMP2 };
+
+// The loop's calls over n Gaussians use the reserved slots of ctx->tr.
+static bool loop_reserved(const as_ctx *ctx, int64_t n, const char *what) {
+    if (n == 0 || n <= ctx->res.max_gaussians) return true;
+    as_set_error("%s: %lld Gaussians need max_gaussians >= %lld in as_ctx_reserve (reserved %lld)", what, (long long)n,
+                 (long long)n, (long long)ctx->res.max_gaussians);
+    return false;
+}
 
 static bool same_shape(const as_gaussians_mut *a, int64_t n, int32_t deg, const char *what, const char *name) {
     if (!a) { as_set_error("%s: null %s", what, name); return false; }
@@ -621,7 +770,6 @@ as_status as_l1_loss(as_ctx *ctx, int32_t width, int32_t height, const float *im
                      double *sums, void *stream) {
     const char *what = "as_l1_loss";
     if (!ctx || !image || !gt || !sums || width < 1 || height < 1) { as_set_error("%s: bad argument", what); return AS_ERR_ARG; }
-    if (bad(devbuf_ensure(ctx->tr[TR_PART], l1_partials_bytes()), "as_l1_loss: scratch")) return AS_ERR_HIP;
     launch_l1(width, height, image, gt, dL_dimage, sums, (double *)ctx->tr[TR_PART].p, (hipStream_t)stream);
     return launch_status(what);
 }
@@ -638,9 +786,7 @@ as_status as_densify_select(as_ctx *ctx, const as_gaussians *g, const float *g2d
     }
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = g->n;
-    if (bad(devbuf_ensure(ctx->tr[TR_SCAN], (size_t)(n > 0 ? n : 1) * 8), "as_densify_select: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_TMP], scan_tmp_bytes(n > 0 ? n : 1)), "as_densify_select: scratch"))
-        return AS_ERR_HIP;
+    if (!loop_reserved(ctx, n, what)) return AS_ERR_CAPACITY;
     if (n == 0) {
         launch_fill_i64(n_cand, 0, 1, s);
         return launch_status(what);
@@ -662,11 +808,7 @@ as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t 
     }
     hipStream_t s = (hipStream_t)stream;
     const int64_t m = n > 0 ? n : 1;
-    if (bad(devbuf_ensure(ctx->tr[TR_FLAG], (size_t)m), "as_split_row_map: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_SCAN], (size_t)m * 8), "as_split_row_map: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_TMP], scan_tmp_bytes(m)), "as_split_row_map: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_TOT], 16), "as_split_row_map: scratch"))
-        return AS_ERR_HIP;
+    if (!loop_reserved(ctx, n, what)) return AS_ERR_CAPACITY;
     if (capacity > 0) launch_fill_u32(reinterpret_cast<uint32_t *>(row_src), 0xFFFFFFFFu, capacity, s);
     if (n == 0) return launch_status(what);
     uint8_t *keep = (uint8_t *)ctx->tr[TR_FLAG].p;
@@ -694,14 +836,7 @@ as_status as_clone_prune(as_ctx *ctx, const as_gaussians *g, const uint8_t *clon
     if (g->n > 0 && (out->means == g->means || out->sh == g->sh)) { as_set_error("%s: output aliases the input", what); return AS_ERR_ARG; }
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = g->n, m = n > 0 ? n : 1;
-    if (bad(devbuf_ensure(ctx->tr[TR_FLAG], (size_t)m), "as_clone_prune: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_DUP], (size_t)m), "as_clone_prune: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_SCAN], (size_t)m * 8), "as_clone_prune: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_DSCAN], (size_t)m * 8), "as_clone_prune: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_TMP], scan_tmp_bytes(m)), "as_clone_prune: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_TMP2], scan_tmp_bytes(m)), "as_clone_prune: scratch") ||
-        bad(devbuf_ensure(ctx->tr[TR_TOT], 16), "as_clone_prune: scratch"))
-        return AS_ERR_HIP;
+    if (!loop_reserved(ctx, n, what)) return AS_ERR_CAPACITY;
     int64_t *tot = (int64_t *)ctx->tr[TR_TOT].p;
     if (n == 0) {
         launch_fill_i64(n_out, 0, 1, s);

@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *
                                                      const uint32_t *__restrict__ nt_sorted,
                                                      const uint32_t *__restrict__ offsets, int64_t key_cap,
                                                      uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                     uint32_t *__restrict__ ranges, int64_t range_words) {
+                                                     uint32_t *__restrict__ n_emit, uint32_t *__restrict__ ranges,
+                                                     int64_t range_words) {
     __shared__ uint32_t s_off[4][64], s_id[4][64], s_nt[4][64];
     __shared__ int32_t s_t0[4][64], s_bw[4][64], s_tx[4][64];
     // the tile ranges start empty: tiles without keys keep [0, 0)
@@ -149,6 +150,11 @@ __global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *
         nt = nt_sorted[r];   // the tiles-touched counts in depth order (read in sequence, not gathered)
         off = offsets[r];
         end = (uint64_t)off + nt;
+        // the pairs actually written: all of them when they fit, else those
+        // before the one entry whose run crosses the capacity (it and every
+        // later entry are dropped whole, so [0, *n_emit) holds no gap)
+        if (nt && (uint64_t)off <= (uint64_t)key_cap && (uint64_t)key_cap < end) *n_emit = off;
+        if (r == n - 1 && end <= (uint64_t)key_cap) *n_emit = (uint32_t)end;
         if (nt) {
             const int v = view_of_entry(vt, e);
             const short4 b = box[e];
@@ -260,13 +266,14 @@ void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total,
 
 void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
                         const uint32_t *nt_sorted, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
-                        uint32_t *vals, uint32_t *ranges, int64_t n_tiles, hipStream_t s) {
+                        uint32_t *vals, uint32_t *n_emit, uint32_t *ranges, int64_t n_tiles, hipStream_t s) {
     if (n == 0) {
         fill_impl<uint32_t>(ranges, 0u, 2 * n_tiles, s);
+        fill_impl<uint32_t>(n_emit, 0u, 1, s);
         return;
     }
     hipLaunchKernelGGL(k_emit_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, order, vt,
-                       reinterpret_cast<const short4 *>(box), nt_sorted, offsets, key_cap, keys, vals, ranges,
+                       reinterpret_cast<const short4 *>(box), nt_sorted, offsets, key_cap, keys, vals, n_emit, ranges,
                        2 * n_tiles);
 }
 

@@ -15,7 +15,19 @@
 
 namespace {
 
-enum { ES_B, ES_LABEL, ES_MOM, ES_KEEP, ES_KIDX };
+enum { ES_B, ES_LABEL, ES_MOM, ES_KEEP, ES_KIDX, ES_COUNT };
+
+// Bytes of each scratch slot for a view of P pixels: bands, labels, the six
+// integer moments per (root) pixel, keep flags, and two words per block of
+// 256 pixels.
+void es_need(int64_t P, size_t need[ES_COUNT]) {
+    const size_t p = (size_t)(P > 0 ? P : 1);
+    need[ES_B] = p;
+    need[ES_LABEL] = p * 4;
+    need[ES_MOM] = p * 48;
+    need[ES_KEEP] = p;
+    need[ES_KIDX] = (p + 255) / 256 * 8;
+}
 
 __device__ __forceinline__ double dev_bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
@@ -450,21 +462,35 @@ void launch_error_map(int W, int H, const float *image, const float *gt, double 
                        reinterpret_cast<unsigned long long *>(minmax));
 }
 
+size_t errstats_reserve_bytes(int64_t max_pixels) {
+    if (max_pixels <= 0) return 0;
+    size_t need[ES_COUNT], total = 0;
+    es_need(max_pixels, need);
+    for (int k = 0; k < ES_COUNT; k++) total += devbuf_size(need[k]);
+    return total;
+}
+
+hipError_t errstats_reserve(as_ctx *ctx, int64_t max_pixels) {
+    if (max_pixels <= 0) return hipSuccess;
+    size_t need[ES_COUNT];
+    es_need(max_pixels, need);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < ES_COUNT && e == hipSuccess; k++) e = devbuf_ensure(ctx->es[k], need[k]);
+    return e;
+}
+
 as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const uint64_t *minmax, const int32_t *dom,
                           const float *gt, int view, int64_t n, const uint8_t *is_cand, const as_split_params &p,
                           as_region_buf &rb, int32_t *attr, hipStream_t s) {
     (void)n;
     const int64_t P = (int64_t)W * H;
     if (P == 0) return AS_OK;
-    hipError_t e = hipSuccess;
-    DevBuf *es = ctx->es;
-    if ((e = devbuf_ensure(es[ES_B], P)) != hipSuccess ||
-        (e = devbuf_ensure(es[ES_LABEL], P * 4)) != hipSuccess ||
-        (e = devbuf_ensure(es[ES_MOM], P * 48)) != hipSuccess || (e = devbuf_ensure(es[ES_KEEP], P)) != hipSuccess ||
-        (e = devbuf_ensure(es[ES_KIDX], (size_t)((P + 255) / 256) * 8)) != hipSuccess) {
-        as_set_error("error-stats scratch allocation failed: %s", hipGetErrorString(e));
-        return AS_ERR_HIP;
+    if (P > ctx->res.max_pixels) {
+        as_set_error("as_accumulate_error_stats: a %dx%d view needs max_pixels >= %lld in as_ctx_reserve (reserved "
+                     "%lld)", W, H, (long long)P, (long long)ctx->res.max_pixels);
+        return AS_ERR_CAPACITY;
     }
+    DevBuf *es = ctx->es;
     uint8_t *B = (uint8_t *)es[ES_B].p;
     uint8_t *keep = (uint8_t *)es[ES_KEEP].p;
     int32_t *label = (int32_t *)es[ES_LABEL].p;

@@ -51,13 +51,17 @@ struct GradPtrs {
     int64_t stride;
 };
 
-// A growable device buffer.
+// A growable device buffer.  devbuf_ensure allocates devbuf_size(bytes),
+// and only the set-up calls (as_ctx_create, as_ctx_reserve) call it.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
 };
+static inline size_t devbuf_size(size_t bytes) { return ((bytes < 256 ? 256 : bytes) + 255) & ~(size_t)255; }
 hipError_t devbuf_ensure(DevBuf &b, size_t bytes);
 void devbuf_free(DevBuf &b);
+// True when b holds at least `bytes` (the calls check their scratch with it).
+static inline bool devbuf_has(const DevBuf &b, size_t bytes) { return b.p && b.bytes >= bytes; }
 
 // The views of one render, passed by value to the kernels.  View v owns
 //   entries  [ent_base[v], ent_base[v+1])  (its Gaussians, projected),
@@ -89,7 +93,7 @@ struct as_frame {
     int device;   // the context's device, kept so that destroying the frame never reads the context
     int32_t max_views;
     int32_t fixed_w, fixed_h;   // single-view frames: the one size they render (0: any)
-    int32_t auto_grow;
+    uint32_t flags;             // AS_FRAME_*
     int64_t ent_cap, pix_cap, tile_cap, key_cap;
     // per entry (a Gaussian in one view)
     BlendRec *rec;
@@ -114,14 +118,13 @@ struct as_frame {
     uint32_t *tile_order_bwd;  // [tiles] dispatch order of the reverse blend (most contributors first)
     uint32_t *tile_hi;     // [tiles] one past the tile's last contributor (0: none), from the forward blend
     float *ckpt;           // [tile_cap][AS_CK_MAX][256][4] per pixel (T, colour behind) at the forward's batch
-                           // boundaries; allocated by the first reverse pass
+                           // boundaries; NULL in forward-only frames
     uint32_t *bwd_items;   // [tile_cap * (AS_CK_MAX + 1)][2] (tile, segment) work items of the reverse blend
     uint32_t *n_items;     // [1] device count of bwd_items
     int ck_written;        // the last render wrote checkpoints
     int ck_seg;            // their spacing in list entries (the forward's batch depth)
     int use_order;         // tile_order is valid for the last render
-    uint32_t *n_keys;      // [1] device
-    uint32_t *h_nkeys;     // pinned host mirror
+    uint32_t *n_keys;      // [2] device: pairs the render needs, pairs it wrote (fewer when over key_cap)
     uint32_t *queue;       // [2] tile counters of the persistent blend kernels
     // per pixel, packed over the views
     float *t_final;
@@ -152,6 +155,7 @@ struct as_ctx {
     DevBuf sp[24];    // adaptive-split scratch (split.hip names the slots)
     DevBuf dbg[4];    // test hooks
     DevBuf tr[8];     // optimisation-loop scratch (train.hip kernels; slots named in api.hip)
+    as_reserve res{};             // what es, sp and tr hold (as_ctx_reserve)
     int lds_batch = 256;          // launch tuning (as_set_tuning)
     int longest_first = 1;
     int persistent = 0;
@@ -208,10 +212,11 @@ int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, 
                    int hi_bit, int radix_bits, void *hist, hipStream_t s);
 // Depth-first binning: keys emitted in the depth order a stable depth sort
 // produced; the emission also empties the tile ranges ([0, 0) for every tile)
-// ahead of launch_ranges.
+// ahead of launch_ranges.  *n_emit gets the number of pairs written: all of
+// them when they fit in key_cap, else the offset of the first entry dropped.
 void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, const int16_t *box,
                         const uint32_t *nt_sorted, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
-                        uint32_t *vals, uint32_t *ranges, int64_t n_tiles, hipStream_t s);
+                        uint32_t *vals, uint32_t *n_emit, uint32_t *ranges, int64_t n_tiles, hipStream_t s);
 // [start, end) of each tile with keys (ranges emptied by launch_emit_sorted).
 void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
                    hipStream_t s);
@@ -266,6 +271,9 @@ void launch_reset_opacity(const as_gaussians_mut &g, float cap, float *m, float 
 // error statistics (errstats.hip)
 void launch_error_map(int W, int H, const float *image, const float *gt, double *err, uint64_t *minmax,
                       hipStream_t s);
+// Scratch of the error statistics for views of up to max_pixels pixels.
+size_t errstats_reserve_bytes(int64_t max_pixels);
+hipError_t errstats_reserve(as_ctx *ctx, int64_t max_pixels);
 as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const uint64_t *minmax, const int32_t *dom,
                           const float *gt, int view, int64_t n, const uint8_t *is_cand, const as_split_params &p,
                           as_region_buf &rb, int32_t *attr, hipStream_t s);
@@ -278,6 +286,9 @@ static inline int split_noise_need(const as_split_params &p) {
     if (p.variant == AS_VARIANT_ADAPTIVE_N && p.n_max > need) need = p.n_max;
     return need;
 }
+// Scratch of the split for the region, candidate, view and Gaussian maxima of r.
+size_t split_reserve_bytes(const as_reserve &r);
+hipError_t split_reserve(as_ctx *ctx, const as_reserve &r);
 as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *cand, int64_t n_cand,
                              const as_region_buf &rb, const as_camera *views, int n_views, const int32_t *attr,
                              const as_split_params &p, const float *noise, GradPtrs out, int64_t out_cap,

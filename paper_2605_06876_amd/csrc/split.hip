@@ -21,7 +21,7 @@
 namespace {
 
 enum { SP_K0, SP_K1, SP_V0, SP_V1, SP_HIST, SP_N, SP_RS, SP_RE, SP_PROP, SP_UF, SP_ROOT, SP_GRP, SP_KEPT, SP_NKEPT,
-       SP_CAMS, SP_REM, SP_REMSCAN, SP_SCAN, SP_TOT };
+       SP_CAMS, SP_REM, SP_REMSCAN, SP_SCAN, SP_TOT, SP_COUNT };
 
 constexpr double C0_SH = 0.28209479177387814;   // degree-0 real SH constant 1/(2 sqrt(pi))
 
@@ -546,6 +546,38 @@ __global__ void k_store_cams(const CamChunk c, DevCam *__restrict__ dst) {
 
 }  // namespace
 
+// Bytes of each scratch slot for region capacity `cap`, `nc` candidates, `nv`
+// views and `n` Gaussians: the region sort's keys, values and histogram, the
+// candidates' region ranges, proposals, union-find, groups and kept lists,
+// the camera table, the removal mask and its scan.
+static void sp_need(int64_t cap, int64_t nc, int64_t nv, int64_t n, size_t need[SP_COUNT]) {
+    cap = cap > 0 ? cap : 1;
+    nc = nc > 0 ? nc : 1;
+    nv = nv > 0 ? nv : 1;
+    n = n > 0 ? n : 1;
+    const size_t v[SP_COUNT] = {(size_t)cap * 8, (size_t)cap * 8, (size_t)cap * 4, (size_t)cap * 4, sort_hist_bytes(cap),
+                                64, (size_t)nc * 8, (size_t)nc * 8, (size_t)cap * sizeof(Prop), (size_t)cap * 4,
+                                (size_t)cap * 4, (size_t)cap * sizeof(Group), (size_t)cap * 4, (size_t)nc * 4,
+                                (size_t)nv * sizeof(DevCam), (size_t)n, (size_t)n * 8, scan_tmp_bytes(n > nc ? n : nc),
+                                64};
+    for (int k = 0; k < SP_COUNT; k++) need[k] = v[k];
+}
+
+size_t split_reserve_bytes(const as_reserve &r) {
+    size_t need[SP_COUNT], total = 0;
+    sp_need(r.max_regions, r.max_candidates, r.max_views, r.max_gaussians, need);
+    for (int k = 0; k < SP_COUNT; k++) total += devbuf_size(need[k]);
+    return total;
+}
+
+hipError_t split_reserve(as_ctx *ctx, const as_reserve &r) {
+    size_t need[SP_COUNT];
+    sp_need(r.max_regions, r.max_candidates, r.max_views, r.max_gaussians, need);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < SP_COUNT && e == hipSuccess; k++) e = devbuf_ensure(ctx->sp[k], need[k]);
+    return e;
+}
+
 as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *cand, int64_t n_cand,
                              const as_region_buf &rb, const as_camera *views, int n_views, const int32_t *attr,
                              const as_split_params &p, const float *noise, GradPtrs out, int64_t out_cap,
@@ -562,19 +594,17 @@ as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *can
         as_set_error("region sort key needs %d bits (> 64)", lb + vb + cb);
         return AS_ERR_ARG;
     }
+    // the scratch sizes of sp_need (every count at least 1) must be reserved
+    const int64_t nc1 = n_cand > 0 ? n_cand : 1, nv1 = n_views > 0 ? n_views : 1, n1 = g.n > 0 ? g.n : 1;
+    const as_reserve &res = ctx->res;
+    if (cap > res.max_regions || nc1 > res.max_candidates || nv1 > res.max_views || n1 > res.max_gaussians) {
+        as_set_error("as_adaptive_split: needs max_regions >= %lld, max_candidates >= %lld, max_views >= %lld, "
+                     "max_gaussians >= %lld in as_ctx_reserve (reserved %lld, %lld, %d, %lld)", (long long)cap,
+                     (long long)nc1, (long long)nv1, (long long)n1, (long long)res.max_regions,
+                     (long long)res.max_candidates, res.max_views, (long long)res.max_gaussians);
+        return AS_ERR_CAPACITY;
+    }
     DevBuf *sp = ctx->sp;
-    hipError_t e = hipSuccess;
-    const int64_t nc1 = n_cand > 0 ? n_cand : 1;
-    const size_t need[] = {(size_t)cap * 8, (size_t)cap * 8, (size_t)cap * 4, (size_t)cap * 4, sort_hist_bytes(cap),
-                           64, (size_t)nc1 * 8, (size_t)nc1 * 8, (size_t)cap * sizeof(Prop), (size_t)cap * 4,
-                           (size_t)cap * 4, (size_t)cap * sizeof(Group), (size_t)cap * 4, (size_t)nc1 * 4,
-                           (size_t)(n_views > 0 ? n_views : 1) * sizeof(DevCam), (size_t)(g.n > 0 ? g.n : 1),
-                           (size_t)(g.n > 0 ? g.n : 1) * 8, scan_tmp_bytes(g.n > nc1 ? g.n : nc1), 64};
-    for (int k = 0; k <= SP_TOT; k++)
-        if ((e = devbuf_ensure(sp[k], need[k])) != hipSuccess) {
-            as_set_error("split scratch allocation failed: %s", hipGetErrorString(e));
-            return AS_ERR_HIP;
-        }
     uint64_t *keys[2] = {(uint64_t *)sp[SP_K0].p, (uint64_t *)sp[SP_K1].p};
     uint32_t *vals[2] = {(uint32_t *)sp[SP_V0].p, (uint32_t *)sp[SP_V1].p};
     uint32_t *n32 = (uint32_t *)sp[SP_N].p;

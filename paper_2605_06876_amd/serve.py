@@ -55,21 +55,30 @@ class SlotSpec:
     def __init__(self, max_views, entries, pixels, tiles, pairs):
         self.max_views, self.entries, self.pixels, self.tiles, self.pairs = max_views, entries, pixels, tiles, pairs
 
-    # bytes of device memory the slot holds (its frame, as the library allocates it, and its in-flight images)
     def bytes(self):
-        per_entry = 48 + 4 + 8 + 4 + 4 + 36 + 16 + 4      # record, depth, box, tiles, offset, 2D grads, sort pairs, gather
-        per_pixel = 4 + 4 + 4 + 4 + 8 + 12                 # T, last, count, dominant, error, RGB image
-        return self.entries * per_entry + self.pixels * per_pixel + self.tiles * 12 + self.pairs * 16
+        """Device bytes the slot holds: its forward-only batch frame, as the
+        library reports it (as_frame_bytes), plus its in-flight images."""
+        from . import api
+        frame = api.frame_bytes(self.max_views, self.entries, self.pixels, self.tiles, max(self.pairs, 1),
+                                forward_only=True)
+        return frame + 12 * self.pixels
 
 
 def plan_slots(budget_bytes, n_slots, max_views, pixels_per_slot, entries_per_slot, tiles_per_slot):
-    """Split what the budget leaves after the entry / pixel / tile arrays over
-    pair capacity (16 bytes a pair: two key and two value buffers)."""
-    spec = SlotSpec(max_views, entries_per_slot, pixels_per_slot, tiles_per_slot, 0)
-    left = budget_bytes // n_slots - spec.bytes()
-    if left <= 16 * 65536:
+    """Give each slot the largest pair capacity whose footprint (frame +
+    images, from the library's size query) fits its share of the budget."""
+    spec = SlotSpec(max_views, entries_per_slot, pixels_per_slot, tiles_per_slot, 1)
+    share = budget_bytes // n_slots
+    base = spec.bytes()
+    probe = 1 << 20
+    spec.pairs = 1 + probe
+    per_pair = (spec.bytes() - base) / probe
+    pairs = int((share - base) / per_pair) if share > base else 0
+    if pairs <= 65536:
         raise ValueError("budget of %d bytes cannot hold %d slots" % (budget_bytes, n_slots))
-    spec.pairs = int(min(left // 16, 0xFFFFFFFF))
+    spec.pairs = int(min(pairs, 0xFFFFFFFF))
+    while spec.bytes() > share:
+        spec.pairs -= 4096
     return spec
 
 
@@ -197,7 +206,7 @@ class GpuExecutor:
         self.ctx, self.scenes, self.spec, self.n_slots = ctx, scenes, spec, n_slots
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
         self.frames = [api.BatchFrame(ctx, spec.max_views, spec.entries, spec.pixels, spec.tiles, spec.pairs,
-                                      auto_grow=False) for _ in range(n_slots)]
+                                      auto_grow=False, forward_only=True) for _ in range(n_slots)]
         self.count_dev = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(n_slots)]
         self.count_host = [torch.zeros(1, dtype=torch.int32).pin_memory() for _ in range(n_slots)]
         self.events = [None] * n_slots
@@ -236,7 +245,8 @@ class GpuExecutor:
         key = (r.scene, r.cam.width, r.cam.height)
         f = self.single.get(key)
         if f is None:
-            f = api.Frame(self.ctx, self.scenes[r.scene].n, r.cam.width, r.cam.height, auto_grow=True)
+            f = api.Frame(self.ctx, self.scenes[r.scene].n, r.cam.width, r.cam.height, auto_grow=True,
+                          forward_only=True)
             self.single[key] = f
         r.image = api.render(self.ctx, self.scenes[r.scene], r.cam, f)
         torch.cuda.current_stream().synchronize()

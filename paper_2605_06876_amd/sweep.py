@@ -61,6 +61,8 @@ class DensifyWorkload:
         regions = api.RegionBuffer(V * W * H // max(params.m_min, 1) // 4 + 1024)
         attr = torch.zeros(self.n, dtype=torch.int32, device="cuda")
         out = api.Gaussians.empty(self.n + nc * max(2, params.n_max + 1), 3)
+        ctx.reserve(max_pixels=W * H, max_gaussians=self.n, max_candidates=nc, max_regions=regions.capacity,
+                    max_views=V)
 
         def once():
             regions.count.zero_()

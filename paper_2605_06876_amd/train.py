@@ -148,6 +148,10 @@ class Trainer:
     def densify(self, it):
         cfg, pb, ctx = self.cfg, self.pb, self.ctx
         g, n = self.g, self.g.n
+        # the densification's scratch, reserved ahead of its calls (a set-up
+        # step between iterations: the calls themselves never allocate)
+        ctx.reserve(max_gaussians=2 * n, max_candidates=max(n, 1), max_pixels=pb.W * pb.H,
+                    max_regions=self.regions.capacity, max_views=max(cfg.views_per_split, 1))
         clone, is_cand, cand, n_cand = api.densify_select(ctx, g, self.accum, self.vis, self.thr,
                                                           cfg.percent_dense * pb.extent)
         nc = int(n_cand.item())
@@ -191,6 +195,7 @@ class Trainer:
             g2, st2 = g1, st1
         # 3. prune (the world-size test from the first opacity reset on)
         max_scale = cfg.max_world_scale * pb.extent if self.reset_done else 0.0
+        ctx.reserve(max_gaussians=g2.n)
         g3, st3, n3 = api.clone_prune(ctx, g2, None, st2, cfg.min_opacity, max_scale)
         n3 = int(n3.item())
         self.g = g3.rows(n3)

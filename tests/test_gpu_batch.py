@@ -209,8 +209,8 @@ def test_graph_replay_matches_eager(ctx):
 
 
 def test_first_backward_inside_a_capture(ctx):
-    """The first reverse pass on a frame allocates its checkpoint buffer,
-    except inside a graph capture, which must allocate nothing: captured as a
+    """A frame holds its checkpoint buffer from creation, so a reverse pass
+    first seen inside a graph capture allocates nothing: captured as a
     frame's first backward, render + backward replays like the eager step."""
     scene = synth.scene_clusters(4000, seed=14, sh_degree=1, log_scale_mu=-3.8, log_scale_sd=0.5)
     g = api.Gaussians.from_scene(scene)
@@ -241,7 +241,9 @@ def test_first_backward_inside_a_capture(ctx):
     graph.close()
 
 
-def test_capture_refuses_a_synchronising_frame(ctx):
+def test_capture_refuses_a_growing_frame(ctx):
+    """A frame with auto_grow reads its pair count back after each render (the
+    binding's growth policy), which a graph capture cannot hold."""
     g = api.Gaussians.from_scene(synth.scene_uniform_sh0(200, seed=2))
     cam = cams_for([(32, 32)], seed=2)[0]
     frame = api.Frame(ctx, g.n, 32, 32, auto_grow=True)

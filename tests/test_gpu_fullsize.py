@@ -50,8 +50,8 @@ def say(msg):
     sys.stdout.flush()
 
 
-def tuned_ctx():
-    c = api.Context(0)
+def tuned_ctx(**reserve):
+    c = api.Context(0, **reserve)
     api.set_tuning(c, **TUNING)
     return c
 
@@ -243,8 +243,9 @@ def test_c3_error_stats_and_split_stage_isolated():
     the oracle's error statistics, whose regions and attribution counts must
     be identical, and the GPU's regions then feed both splits, whose modes,
     counts, offsets and output rows must match."""
-    ctx = tuned_ctx()
     n, W, H, V = 500_000, 1256, 828, 16
+    ctx = tuned_ctx(max_pixels=W * H, max_gaussians=n, max_candidates=n // 20, max_regions=V * W * H // 5 // 4,
+                    max_views=V)
     scene = synth.scene_clusters(n, 1003, 3)
     views = synth.sphere_cameras(V, 4.0, [(W, H)], seed=1003)
     gts_np = [synth.smooth_image(H, W, 2000 + v) for v in range(V)]

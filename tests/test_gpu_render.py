@@ -4,6 +4,7 @@ Bars: bit-exact depth keys, boxes, tile keys, sort order, ranges, contributor
 counts and dominant ids on pixels whose FP64 decisions are not within the
 FP32 margin of a threshold (flagged by the oracle); image max-abs <= 1e-4 on
 unflagged pixels; gradients: per tensor ||d||/||ref|| <= 1e-3."""
+import copy
 import sys
 
 import numpy as np
@@ -253,19 +254,20 @@ def test_backward_segments_match_oracle(ctx):
     """Tiles whose contributors run past one forward batch (256 entries): after
     a render that wrote checkpoints, the reverse pass walks each such tile as
     independent segments starting from the forward's checkpoints.  Gradients
-    match the oracle, as do those of the first reverse pass, which precedes
-    the checkpoint buffer and walks every tile in one piece."""
+    match the oracle, as do those of a forward-only frame, which holds no
+    checkpoints and walks every tile in one piece."""
     base = synth.scene_uniform_sh0(3000, seed=91, log_scale_mu=-2.5, log_scale_sd=0.3)
     # o ~ 0.08: pixels stay far from saturation across a few hundred Gaussians
     scene = synth.Scene(base.means, base.log_scales, base.quats, np.full(3000, -2.5, np.float32), base.sh, 0)
     cam = synth.look_at((0.2, -0.1, -3.5), (0.0, 0.0, 0.0), 64, 64, 60.0, bg=(0.3, 0.2, 0.1))
     g = api.Gaussians.from_scene(scene)
     frame = api.Frame(ctx, g.n, cam.width, cam.height)
+    frame_one = api.Frame(ctx, g.n, cam.width, cam.height, forward_only=True)
     G = np.random.default_rng(8).normal(size=(3, 64, 64)).astype(np.float32)
     Gt = torch.from_numpy(G).cuda()
-    say("segments: render, reverse pass in one piece")
-    api.render(ctx, g, cam, frame)
-    g_one = api.render_backward(ctx, g, cam, frame, Gt)
+    say("segments: forward-only frame, reverse pass in one piece")
+    api.render(ctx, g, cam, frame_one)
+    g_one = api.render_backward(ctx, g, cam, frame_one, Gt)
     say("segments: render with checkpoints, segmented reverse pass")
     api.render(ctx, g, cam, frame)
     g_seg = api.render_backward(ctx, g, cam, frame, Gt)
@@ -319,12 +321,55 @@ def test_everything_culled_and_empty_tiles(ctx):
 
 def test_key_capacity_growth(ctx):
     scene, cam, gt = synth.c1_inputs(seed=21)
-    g, frame, img = gpu_render(ctx, scene, cam, key_cap=16)   # far too small: the render grows it
+    # far too small: the binding reads the count back, reserves and renders again
+    g, frame, img = gpu_render(ctx, scene, cam, key_cap=16)
     pr = oracle.project(scene, cam)
     keys, vals, ranges = oracle.bin_tiles(pr, 16, 16)
     st = frame.host_state(g.n)
     np.testing.assert_array_equal(st["keys"], keys)
     assert frame.view().key_cap >= len(keys)
+
+
+def _depth_prefix(pr, key_cap):
+    """The Gaussians whose tile runs fit whole in key_cap pairs when emitted in
+    (depth key, id) order: a copy of the projection with the rest culled."""
+    v = np.nonzero(pr.valid)[0]
+    b = pr.box[v].astype(np.int64)
+    nt = ((b[:, 2] // 16) - (b[:, 0] // 16) + 1) * ((b[:, 3] // 16) - (b[:, 1] // 16) + 1)
+    order = np.lexsort((v, pr.depth_key[v]))
+    end = np.cumsum(nt[order])
+    dropped = v[order][end > key_cap]
+    kept = copy.copy(pr)
+    kept.valid = pr.valid.copy()
+    kept.valid[dropped] = 0
+    return kept, int(end[-1]), int(end[end <= key_cap][-1]) if (end <= key_cap).any() else 0
+
+
+@pytest.mark.parametrize("key_cap", [1, 700, 2500])
+def test_render_over_key_capacity(ctx, key_cap):
+    """A frame that does not grow (the serving slots' kind) rendering more
+    pairs than it holds: the emission writes the pairs of the entries that fit
+    whole, in depth order; the sort, the tile ranges and the blend use exactly
+    those, the frame still reports the full demand, and the image is the
+    render of that depth prefix."""
+    scene, cam, gt = synth.c1_inputs(seed=23)
+    g = api.Gaussians.from_scene(scene)
+    frame = api.Frame(ctx, g.n, cam.width, cam.height, key_cap=key_cap, auto_grow=False)
+    img = api.render(ctx, g, cam, frame).cpu().numpy()
+    pr = oracle.project(scene, cam)
+    kept, demand, fit = _depth_prefix(pr, key_cap)
+    keys, vals, ranges = oracle.bin_tiles(kept, 16, 16)
+    st = frame.host_state(g.n)
+    say("key_cap %d: demand %d, emitted %d" % (key_cap, frame.n_keys(), frame.n_emitted()))
+    assert frame.n_keys() == demand > key_cap
+    assert frame.n_emitted() == fit == len(keys)
+    np.testing.assert_array_equal(st["keys"], keys)
+    np.testing.assert_array_equal(st["vals"], vals)
+    np.testing.assert_array_equal(st["ranges"], ranges)
+    assert int(st["ranges"][:, 1].max()) <= fit
+    ref, maps = oracle.render_image(kept)
+    ok = maps["flag"] == 0
+    assert np.abs(img.astype(np.float64) - ref)[:, ok].max() <= 1e-4
 
 
 def test_bad_arguments_are_rejected(ctx):

@@ -29,7 +29,9 @@ def say(msg):
 
 @pytest.fixture(scope="module")
 def ctx():
-    return api.Context(0)
+    # scratch for the largest case below (a 1256x828 map; the split tests' regions)
+    return api.Context(0, max_pixels=1256 * 828, max_gaussians=10_000, max_candidates=5_000, max_regions=1 << 17,
+                       max_views=16)
 
 
 def gpu_error_stats(ctx, img, gt, dom, is_cand, view, prm, regions, attr):

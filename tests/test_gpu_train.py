@@ -32,7 +32,8 @@ def say(msg):
 
 @pytest.fixture(scope="module")
 def ctx():
-    return api.Context(0)
+    # scratch for the largest Gaussian set of the loop calls below
+    return api.Context(0, max_gaussians=1 << 17, max_candidates=1 << 12, max_regions=1 << 10, max_views=4)
 
 
 def rand_set(n, deg, rng, ls_mu=-3.0):
