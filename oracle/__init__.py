@@ -160,14 +160,17 @@ def render_pixels(pr, pix):
     return out
 
 
-def alpha_pairs(pr, pix, ids):
-    """Unclamped alpha o G (FP64) of Gaussian ids[k] at pixel pix[k] = (x, y)."""
+def alpha_pairs(pr, pix, ids, with_bound=False):
+    """Unclamped alpha o G (FP64) of Gaussian ids[k] at pixel pix[k] = (x, y);
+    with_bound=True also returns the relative error bound the near-threshold
+    flags assume for the blend's FP32 evaluation of that alpha."""
     pix = _c(pix, np.int32)
     ids = _c(ids, np.int64)
     out = np.zeros(len(ids))
+    bound = np.zeros(len(ids)) if with_bound else None
     lib().orc_alpha_pairs(_p(pr.mean2d), _p(pr.conic), _p(pr.opacity), ctypes.c_int64(len(ids)), _p(pix), _p(ids),
-                          _p(out))
-    return out
+                          _p(out), _p(bound) if with_bound else None)
+    return (out, bound) if with_bound else out
 
 
 def render_image(pr):
@@ -342,10 +345,13 @@ def render_rows(pr, y0=0, y1=None, dL_dcolor=None, margins=False, grad_abs=False
     render_pixels, gathered per row).  With dL_dcolor [(y1-y0)*W, 3] the
     reverse pass runs too and the 2D gradients are returned under "grad".
 
-    margins=True adds "margins" [npix, 4]: each decision's smallest relative
-    distance to its threshold (alpha vs 1/255, T(1 - alpha) vs 1e-4, the
-    dominant weight's lead over the runner-up, o G vs the 0.99 clamp; inf
-    where the decision never arises).  grad_abs=True (with dL_dcolor) adds
+    margins=True adds "margins" [npix, 4]: for each decision (alpha vs 1/255,
+    T(1 - alpha) vs 1e-4, the dominant weight's lead over the runner-up, o G
+    vs the 0.99 clamp) the smallest ratio of its relative distance to the
+    threshold over its FP32 error bound plus 1e-6 (inf where the decision
+    never arises); the pixel is flagged when any ratio is at most 1.  It also
+    adds "t_bound" [npix]: the relative error bound those flags assume for an
+    FP32 evaluation of the final transmittance.  grad_abs=True (with dL_dcolor) adds
     grad["abs"] [n, 9]: per Gaussian the summed magnitudes of the products
     that make up each 2D gradient (mean x, y; conic a, b, c; opacity; colour
     r, g, b), the scale of its floating-point rounding error."""
@@ -362,10 +368,12 @@ def render_rows(pr, y0=0, y1=None, dL_dcolor=None, margins=False, grad_abs=False
         gC = _c(dL_dcolor, np.float64).reshape(npix, 3)
         out["grad"] = dict(mean2d=np.zeros((n, 2)), conic=np.zeros((n, 3)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
         gp = [_p(out["grad"][k]) for k in ("mean2d", "conic", "opacity", "rgb")]
-    mp = ga = None
+    mp = ga = tb = None
     if margins:
         out["margins"] = np.zeros((npix, 4))
+        out["t_bound"] = np.zeros(npix)
         mp = _p(out["margins"])
+        tb = _p(out["t_bound"])
     if grad_abs:
         assert dL_dcolor is not None, "grad_abs needs dL_dcolor"
         out["grad"]["abs"] = np.zeros((n, 9))
@@ -374,5 +382,5 @@ def render_rows(pr, y0=0, y1=None, dL_dcolor=None, margins=False, grad_abs=False
                           _p(pr.depth_key), _p(pr.box), _p(_c(pr.bg, np.float64)), ctypes.c_int(W), ctypes.c_int(y0),
                           ctypes.c_int(y1), _p(out["color"]), _p(out["T"]), _p(out["ncontrib"]), _p(out["dom"]),
                           _p(out["last"]), _p(out["flag"]), _p(out["pairs"]), _p(gC) if gC is not None else None,
-                          *gp, mp, ga)
+                          *gp, mp, ga, tb)
     return out

@@ -388,13 +388,57 @@ static int64_t depth_order(int64_t n, const int32_t *valid, const uint32_t *dept
     return m;
 }
 
-/* Decision margins under which a pixel is flagged as near-threshold: the GPU
- * evaluates alpha and transmittance in FP32, so a decision whose FP64 value
- * lies this close to its threshold may legitimately differ. */
-#define FLAG_ALPHA_REL 1e-4
-#define FLAG_T_REL 2e-4
-#define FLAG_DOM_REL 1e-4
-#define FLAG_CLAMP_REL 1e-4   /* o G near the 0.99 clamp: the reverse pass's branch of min(0.99, o G) */
+/* Near-threshold flags (reading B1).  The GPU takes the blend's decisions
+ * (alpha vs 1/255, T (1 - alpha) vs 1e-4, the dominant weight's lead, o G vs
+ * the 0.99 clamp) in FP32; a pixel is flagged, and left out of the exact
+ * comparisons, when the FP64 value of one of them lies within an error bound
+ * of the FP32 evaluation from its threshold.
+ *
+ * Alpha: the kernel forms the exponent from the conic rounded to FP32, the
+ * pixel offset from the FP32 mean and a few fused multiply-adds, so the error
+ * of the exponent is a few units of roundoff u = 2^-24 times the summed
+ * magnitudes of its terms (M below; large for thin, tilted ellipses, where
+ * the terms cancel), plus the offset's rounding (at most u (|d| + 16)) times
+ * the exponent's gradient, plus the rounding of log2(o) and exp2.  The
+ * relative bound of o G is FP32_K u (2 M + |grad| (|dx| + |dy| + 32) + 4)
+ * with FP32_K = 16, several times the count of roundings.
+ * Transmittance: T's relative error grows by a_k e_k / (1 - a_k) + 2u per
+ * contributor (e_k: its alpha bound), or by 1e-6 + 2u for a clamped one.
+ * Weights a T carry the sum of the two.  Every decision is compared in units
+ * of its bound (plus a floor of FLAG_FLOOR): a margin of at most 1 flags. */
+#define U32 5.9604644775390625e-8   /* 2^-24 */
+/* The clamp 0.99 in FP32 is 0.99 + 9.5e-9, so a clamped contributor's
+ * 1 - alpha is 9.5e-7 smaller, relatively, than in FP64. */
+#define CLAMP_ONE_MINUS_REL 1e-6
+#define FP32_K 16.0
+#define FLAG_FLOOR 1e-6
+
+/* Relative error bound of the blend's FP32 o G at offset (dx, dy) = mean -
+ * pixel centre (the exponent's magnitude is at most M, so M enters twice). */
+static double alpha_bound(const double *cn, double dx, double dy) {
+    const double M = 0.5 * fabs(cn[0]) * dx * dx + fabs(cn[1] * dx * dy) + 0.5 * fabs(cn[2]) * dy * dy;
+    const double grad = fabs(cn[0] * dx + cn[1] * dy) + fabs(cn[2] * dy + cn[1] * dx);
+    return FP32_K * U32 * (2.0 * M + grad * (fabs(dx) + fabs(dy) + 32.0) + 4.0);
+}
+
+/* Margins of one pixel's decisions, each the smallest (relative distance to
+ * the threshold) / (its error bound) over the decisions taken; inf when a
+ * decision never arises. */
+typedef struct {
+    double a, t, d, c;      /* alpha, stop, dominant, clamp */
+    double errT;            /* relative error bound of T so far */
+    double eb, es;          /* error bounds of the best and the second weight */
+} omargin;
+
+static void margin_init(omargin *m) {
+    m->a = m->t = m->d = m->c = INFINITY;
+    m->errT = 0.0; m->eb = m->es = 0.0;
+}
+static void margin_note(double *mg, double dist, double bound) {
+    const double r = dist / (bound + FLAG_FLOOR);
+    if (r < *mg) *mg = r;
+}
+static int margin_flag(const omargin *m) { return m->a <= 1.0 || m->t <= 1.0 || m->d <= 1.0 || m->c <= 1.0; }
 
 typedef struct {
     double color[3], T;
@@ -420,8 +464,10 @@ static void render_pixel(int x, int y, int64_t m, const int64_t *order, const do
     double px = x + 0.5, py = y + 0.5;
     double T = 1.0, C[3] = {0, 0, 0}, wbest = -1.0, wsecond = -1.0;
     int64_t dom = -1, last = -1;
-    int nc = 0, flag = 0;
+    int nc = 0;
     int64_t pairs = 0;
+    omargin mg;
+    margin_init(&mg);
     for (int64_t k = 0; k < m; k++) {
         int64_t i = order[k];
         const int32_t *b = box + i * 4;
@@ -430,36 +476,45 @@ static void render_pixel(int x, int y, int64_t m, const int64_t *order, const do
         double araw_G;
         double a = alpha_at(mean2d + i * 2, conic + i * 3, opacity[i], px, py, &araw_G);
         double araw = opacity[i] * araw_G;
-        if (fabs(araw - ALPHA_MIN) <= FLAG_ALPHA_REL * ALPHA_MIN) flag = 1;
+        const double dx = mean2d[i * 2] - px, dy = mean2d[i * 2 + 1] - py;
+        const double ra = alpha_bound(conic + i * 3, dx, dy);
+        margin_note(&mg.a, fabs(araw - ALPHA_MIN) / ALPHA_MIN, ra);
         if (a < ALPHA_MIN) continue;
+        const double ea = araw < ALPHA_MAX ? ra : 1e-8;   /* the clamped alpha: 0.99 in FP32 */
+        const double eT = mg.errT + (araw < ALPHA_MAX ? a * ea / (1.0 - a) : CLAMP_ONE_MINUS_REL) + 2.0 * U32;
         double testT = T * (1.0 - a);
-        if (fabs(testT - T_STOP) <= FLAG_T_REL * T_STOP) flag = 1;
+        margin_note(&mg.t, fabs(testT - T_STOP) / T_STOP, eT);
         if (testT < T_STOP) break;
-        if (fabs(araw - ALPHA_MAX) <= FLAG_CLAMP_REL * ALPHA_MAX) flag = 1;
+        margin_note(&mg.c, fabs(araw - ALPHA_MAX) / ALPHA_MAX, ra);
         double w = a * T;
+        const double ew = ea + mg.errT + U32;
         for (int ch = 0; ch < 3; ch++) C[ch] += w * rgb[i * 3 + ch];
-        if (w > wbest) { wsecond = wbest; wbest = w; dom = i; }
-        else if (w > wsecond) wsecond = w;
+        if (w > wbest) { wsecond = wbest; mg.es = mg.eb; wbest = w; mg.eb = ew; dom = i; }
+        else if (w > wsecond) { wsecond = w; mg.es = ew; }
+        mg.errT = eT;
         T = testT;
         nc++;
         last = i;
     }
-    if (dom >= 0 && wsecond >= 0.0 && wbest - wsecond <= FLAG_DOM_REL * wbest) flag = 1;
+    if (dom >= 0 && wsecond >= 0.0) margin_note(&mg.d, (wbest - wsecond) / wbest, mg.eb + mg.es);
     for (int ch = 0; ch < 3; ch++) out->color[ch] = C[ch] + T * bg[ch];
-    out->T = T; out->ncontrib = nc; out->dom = dom; out->last = last; out->flag = flag; out->pairs = pairs;
+    out->T = T; out->ncontrib = nc; out->dom = dom; out->last = last; out->flag = margin_flag(&mg);
+    out->pairs = pairs;
     out->wbest = wbest; out->wsecond = wsecond;
 }
 
 /* Unclamped alpha o G (FP64) of Gaussian ids[k] at the centre of pixel
  * pix[k] = {x, y}, for measuring how far an FP32 evaluation strays. */
 void orc_alpha_pairs(const double *mean2d, const double *conic, const double *opacity, int64_t np,
-                     const int32_t *pix, const int64_t *ids, double *out) {
+                     const int32_t *pix, const int64_t *ids, double *out, double *bound) {
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < np; k++) {
         int64_t i = ids[k];
         double G;
-        alpha_at(mean2d + i * 2, conic + i * 3, opacity[i], pix[k * 2] + 0.5, pix[k * 2 + 1] + 0.5, &G);
+        const double px = pix[k * 2] + 0.5, py = pix[k * 2 + 1] + 0.5;
+        alpha_at(mean2d + i * 2, conic + i * 3, opacity[i], px, py, &G);
         out[k] = opacity[i] * G;
+        if (bound) bound[k] = alpha_bound(conic + i * 3, mean2d[i * 2] - px, mean2d[i * 2 + 1] - py);
     }
 }
 
@@ -1337,7 +1392,7 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
                      const double *opacity, const uint32_t *depth_key, const int32_t *box, const double *bg, int W,
                      int y0, int y1, double *color, double *Tfinal, int32_t *ncontrib, int64_t *dom, int64_t *last,
                      uint8_t *flag, int64_t *pairs, const double *dL_dcolor, double *g_mean, double *g_conic,
-                     double *g_opac, double *g_rgb, double *margins, double *g_abs) {
+                     double *g_opac, double *g_rgb, double *margins, double *g_abs, double *t_bound) {
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     int64_t m = depth_order(n, valid, depth_key, order);
     if (dL_dcolor) {
@@ -1368,9 +1423,9 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
                 double px = x + 0.5, py = y + 0.5;
                 double T = 1.0, C[3] = {0, 0, 0}, wbest = -1.0, wsecond = -1.0;
                 int64_t dm = -1, ls = -1, pr = 0;
-                int nc = 0, fl = 0;
-                /* smallest relative distance of each decision to its threshold */
-                double mg_a = INFINITY, mg_t = INFINITY, mg_c = INFINITY;
+                int nc = 0;
+                omargin mg;   /* decision margins in units of their FP32 error bounds */
+                margin_init(&mg);
                 for (int64_t k = 0; k < nr; k++) {
                     int64_t i = row[k];
                     const int32_t *b = box + i * 4;
@@ -1379,22 +1434,22 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
                     double G;
                     double a = alpha_at(mean2d + i * 2, conic + i * 3, opacity[i], px, py, &G);
                     double araw = opacity[i] * G;
-                    double ra = fabs(araw - ALPHA_MIN) / ALPHA_MIN;
-                    if (ra < mg_a) mg_a = ra;
-                    if (fabs(araw - ALPHA_MIN) <= FLAG_ALPHA_REL * ALPHA_MIN) fl = 1;
+                    const double ra = alpha_bound(conic + i * 3, mean2d[i * 2] - px, mean2d[i * 2 + 1] - py);
+                    margin_note(&mg.a, fabs(araw - ALPHA_MIN) / ALPHA_MIN, ra);
                     if (a < ALPHA_MIN) continue;
+                    const double ea = araw < ALPHA_MAX ? ra : 1e-8;   /* the clamped alpha: 0.99 in FP32 */
+                    const double eT = mg.errT + (araw < ALPHA_MAX ? a * ea / (1.0 - a) : CLAMP_ONE_MINUS_REL) +
+                                      2.0 * U32;
                     double testT = T * (1.0 - a);
-                    double rt = fabs(testT - T_STOP) / T_STOP;
-                    if (rt < mg_t) mg_t = rt;
-                    if (fabs(testT - T_STOP) <= FLAG_T_REL * T_STOP) fl = 1;
+                    margin_note(&mg.t, fabs(testT - T_STOP) / T_STOP, eT);
                     if (testT < T_STOP) break;
-                    double rc = fabs(araw - ALPHA_MAX) / ALPHA_MAX;
-                    if (rc < mg_c) mg_c = rc;
-                    if (fabs(araw - ALPHA_MAX) <= FLAG_CLAMP_REL * ALPHA_MAX) fl = 1;
+                    margin_note(&mg.c, fabs(araw - ALPHA_MAX) / ALPHA_MAX, ra);
                     double w = a * T;
+                    const double ew = ea + mg.errT + U32;
                     for (int ch = 0; ch < 3; ch++) C[ch] += w * rgb[i * 3 + ch];
-                    if (w > wbest) { wsecond = wbest; wbest = w; dm = i; }
-                    else if (w > wsecond) wsecond = w;
+                    if (w > wbest) { wsecond = wbest; mg.es = mg.eb; wbest = w; mg.eb = ew; dm = i; }
+                    else if (w > wsecond) { wsecond = w; mg.es = ew; }
+                    mg.errT = eT;
                     if (dL_dcolor) {
                         if (nc == cap[x]) {
                             cap[x] = cap[x] ? 2 * cap[x] : 64;
@@ -1409,15 +1464,17 @@ void orc_render_rows(int64_t n, const int32_t *valid, const double *mean2d, cons
                     nc++;
                     ls = i;
                 }
-                if (dm >= 0 && wsecond >= 0.0 && wbest - wsecond <= FLAG_DOM_REL * wbest) fl = 1;
+                if (dm >= 0 && wsecond >= 0.0) margin_note(&mg.d, (wbest - wsecond) / wbest, mg.eb + mg.es);
                 for (int ch = 0; ch < 3; ch++) color[p * 3 + ch] = C[ch] + T * bg[ch];
-                Tfinal[p] = T; ncontrib[p] = nc; dom[p] = dm; last[p] = ls; flag[p] = (uint8_t)fl; pairs[p] = pr;
+                Tfinal[p] = T; ncontrib[p] = nc; dom[p] = dm; last[p] = ls; flag[p] = (uint8_t)margin_flag(&mg);
+                pairs[p] = pr;
                 if (margins) {
-                    margins[p * 4 + 0] = mg_a;
-                    margins[p * 4 + 1] = mg_t;
-                    margins[p * 4 + 2] = (dm >= 0 && wsecond >= 0.0) ? (wbest - wsecond) / wbest : INFINITY;
-                    margins[p * 4 + 3] = mg_c;
+                    margins[p * 4 + 0] = mg.a;
+                    margins[p * 4 + 1] = mg.t;
+                    margins[p * 4 + 2] = mg.d;
+                    margins[p * 4 + 3] = mg.c;
                 }
+                if (t_bound) t_bound[p] = mg.errT;
                 if (!dL_dcolor) continue;
                 const double *gC = dL_dcolor + p * 3;
                 double S[3];

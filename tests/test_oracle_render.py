@@ -422,10 +422,22 @@ def test_row_sweep_equals_per_pixel_compositing():
 # rounding of a threshold, and bound each 2D gradient's rounding error by the
 # summed magnitude of its products.  These pin the quantities they use.
 
+U32 = 2.0 ** -24
+
+
+def fp32_alpha_bound(cn, dx, dy):
+    """The flags' relative error bound of the blend's FP32 o G (reading B1)."""
+    M = 0.5 * abs(cn[0]) * dx * dx + abs(cn[1] * dx * dy) + 0.5 * abs(cn[2]) * dy * dy
+    grad = abs(cn[0] * dx + cn[1] * dy) + abs(cn[2] * dy + cn[1] * dx)
+    return 16 * U32 * (2 * M + grad * (abs(dx) + abs(dy) + 32) + 4)
+
+
 def test_margins_single_gaussian_closed_form():
-    """One Gaussian: the alpha margin of a pixel is |o G - 1/255| / (1/255),
-    the clamp margin |o G - 0.99| / 0.99, no stop or dominant tie, and the
-    flag is set exactly when a margin falls below its threshold."""
+    """One Gaussian: the alpha margin of a pixel is |o G - 1/255| / (1/255)
+    over (its FP32 bound + 1e-6), the clamp margin |o G - 0.99| / 0.99 over
+    the same, the stop margin |(1 - o G) - 1e-4| / 1e-4 over (o G e / (1 - o G)
+    + 2u + 1e-6, with 1e-6 for the first term when o G is clamped), no
+    dominant tie, and the flag is set exactly when a margin is at most 1."""
     f, z = 80.0, 4.0
     cam = axis_camera(W=64, H=64, f=f, z=-z)
     mx = (32.5 - 32.0) * z / f
@@ -443,27 +455,77 @@ def test_margins_single_gaussian_closed_form():
             continue
         dx, dy = m[0] - (x + 0.5), m[1] - (y + 0.5)
         G = math.exp(-0.5 * (cn[0] * dx * dx + cn[2] * dy * dy) - cn[1] * dx * dy)
-        np.testing.assert_allclose(r["margins"][p, 0], abs(o * G - 1 / 255) * 255, rtol=1e-12)
+        e = fp32_alpha_bound(cn, dx, dy)
+        np.testing.assert_allclose(r["margins"][p, 0], abs(o * G - 1 / 255) * 255 / (e + 1e-6), rtol=1e-12)
         if o * G < 1 / 255:   # skipped: no stop or clamp decision
             assert np.isinf(r["margins"][p, 1:]).all()
             continue
-        np.testing.assert_allclose(r["margins"][p, 3], abs(o * G - 0.99) / 0.99, rtol=1e-12)
+        np.testing.assert_allclose(r["margins"][p, 3], abs(o * G - 0.99) / 0.99 / (e + 1e-6), rtol=1e-12)
         assert r["margins"][p, 2] == np.inf   # a single contributor has no runner-up
-        np.testing.assert_allclose(r["margins"][p, 1], abs((1 - o * G) - 1e-4) / 1e-4, rtol=1e-12)
+        a = min(o * G, 0.99)
+        eT = (a * e / (1 - a) if o * G < 0.99 else 1e-6) + 2 * U32
+        np.testing.assert_allclose(r["margins"][p, 1], abs((1 - a) - 1e-4) / 1e-4 / (eT + 1e-6), rtol=1e-12)
     # outside every box: no decision at all
     assert np.isinf(r["margins"][0]).all()
-    thr = np.array([1e-4, 2e-4, 1e-4, 1e-4])
-    np.testing.assert_array_equal(r["flag"], (r["margins"] <= thr).any(1).astype(np.uint8))
+    np.testing.assert_array_equal(r["flag"], (r["margins"] <= 1.0).any(1).astype(np.uint8))
 
 
 def test_margins_reproduce_the_flags_c1():
     scene, cam, _ = synth.c1_inputs(seed=23)
     pr = oracle.project(scene, cam)
     r = oracle.render_rows(pr, margins=True)
-    thr = np.array([1e-4, 2e-4, 1e-4, 1e-4])
-    np.testing.assert_array_equal(r["flag"], (r["margins"] <= thr).any(1).astype(np.uint8))
+    np.testing.assert_array_equal(r["flag"], (r["margins"] <= 1.0).any(1).astype(np.uint8))
+    # the same flags from the per-pixel renderer
+    pix = oracle.all_pixels(cam.width, cam.height)
+    np.testing.assert_array_equal(oracle.render_pixels(pr, pix)["flag"], r["flag"])
     # the dominant margin is the lead of the largest weight over the second
     assert (r["margins"][:, 2] >= 0).all()
+
+
+def test_fp32_alpha_bound_covers_an_fp32_evaluation():
+    """The flags' error bound is above the error of an FP32 evaluation of
+    o G: conic rounded to FP32 and scaled, the offset taken from an FP32
+    tile-relative mean, the exponent formed with separate FP32 products and
+    sums (more roundings than fused multiply-adds) and exp2 in FP32.  Tried on
+    ellipses from isotropic to 10^4 : 1 and tilted, at pixels across the box
+    and on the alpha = 1/255 contour, where the terms cancel the most."""
+    rng = np.random.default_rng(5)
+    f = np.float32
+    worst = 0.0
+    for _ in range(3000):
+        s1, s2 = np.exp(rng.uniform(-1.0, 4.5, 2))
+        th = rng.uniform(0, np.pi)
+        Rm = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        Sig = Rm @ np.diag([s1 * s1, s2 * s2]) @ Rm.T + 0.3 * np.eye(2)
+        cn = np.linalg.inv(Sig)
+        cn = (cn[0, 0], cn[0, 1], cn[1, 1])
+        o = rng.uniform(1 / 250, 1.0)
+        mean = rng.uniform(0, 2000, 2)
+        k = 2 * np.log(255 * o)
+        # points on the contour (where alpha = 1/255) and inside it
+        t = rng.uniform(0, 2 * np.pi, 8)
+        L = np.linalg.cholesky(Sig * k)
+        pts = (L @ np.stack([np.cos(t), np.sin(t)])).T * rng.choice([1.0, 0.5, 0.1], (8, 1))
+        for d in pts:
+            px, py = mean[0] - d[0], mean[1] - d[1]
+            x, y = math.floor(px - 0.5), math.floor(py - 0.5)   # the pixel whose centre is nearest
+            dx64, dy64 = mean[0] - (x + 0.5), mean[1] - (y + 0.5)
+            p64 = -0.5 * (cn[0] * dx64 * dx64 + cn[2] * dy64 * dy64) - cn[1] * dx64 * dy64
+            a64 = o * math.exp(p64)
+            ox, oy = (x // 16) * 16, (y // 16) * 16
+            mhx, mhy = f(mean[0]), f(mean[1])
+            mx = (mhx - f(ox)) + f(mean[0] - float(mhx))
+            my = (mhy - f(oy)) + f(mean[1] - float(mhy))
+            dx, dy = mx - f(x - ox + 0.5), my - f(y - oy + 0.5)
+            kk = f(-0.5 * 1.4426950408889634)
+            a_, b_, c_ = kk * f(cn[0]), f(-1.4426950408889634) * f(cn[1]), kk * f(cn[2])
+            q = (a_ * dx + b_ * dy) * dx + (c_ * dy * dy + np.log2(f(o)))
+            a32 = float(np.exp2(f(q)))
+            rel = abs(a32 - a64) / a64
+            e = fp32_alpha_bound(cn, dx64, dy64)
+            worst = max(worst, rel / e)
+            assert rel <= e, (rel, e, s1, s2, th)
+    assert worst > 0.0
 
 
 def test_gradient_magnitudes_bound_and_equal_single_term():
