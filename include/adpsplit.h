@@ -165,7 +165,10 @@ typedef struct {
 /* Create a context bound to HIP device `device`.  Frames keep the device
  * they were created on, so a context and its frames may be destroyed in any
  * order (a frame destroyed after its context reads nothing from it); every
- * other call on a frame needs its context alive. */
+ * other call on a frame needs its context alive.  Creation also loads the
+ * library's GPU code on the device (one empty launch per code object, then a
+ * device synchronisation), so the first call of each kind allocates nothing
+ * either. */
 as_status as_ctx_create(int device, as_ctx **out);
 void as_ctx_destroy(as_ctx *ctx);
 /* Text of the last error raised on this thread (static storage). */
@@ -450,10 +453,14 @@ typedef struct {
     int32_t persistent;      /* nonzero: the blend kernels run as one resident grid pulling tiles from a queue */
     int32_t radix_bits;      /* digit width of the (tile, entry) pair sort, 4..8 (the 32-bit
                                 depth keys always take 8: four passes) */
+    int32_t block_cull;      /* nonzero: the blend kernels skip a Gaussian for a 4x4 pixel block of a
+                                tile unless its alpha >= 1/255 ellipse (with a margin above the
+                                FP32 evaluation error) meets the block; zero: the pixel box alone
+                                decides.  The contributor sets, and so every output, are the same */
 } as_tuning;
 
 /* Set / read the context's tuning (defaults: lds_batch 256, longest_first 1,
- * persistent 0, radix_bits 8).  AS_ERR_ARG for an lds_batch other than 256,
+ * persistent 0, radix_bits 8, block_cull 1).  AS_ERR_ARG for an lds_batch other than 256,
  * 512 or 1024 or a radix_bits outside 4..8. */
 as_status as_set_tuning(as_ctx *ctx, const as_tuning *t);
 as_status as_get_tuning(const as_ctx *ctx, as_tuning *t);

@@ -721,11 +721,11 @@ def reset_opacity(ctx, g, max_opacity, m_op=None, v_op=None, stream=None):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("lds_batch", ctypes.c_int32), ("longest_first", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("radix_bits", ctypes.c_int32)]
+                ("radix_bits", ctypes.c_int32), ("block_cull", ctypes.c_int32)]
 
 
-def set_tuning(ctx, lds_batch=256, longest_first=True, persistent=False, radix_bits=8):
-    t = _Tuning(lds_batch, 1 if longest_first else 0, 1 if persistent else 0, radix_bits)
+def set_tuning(ctx, lds_batch=256, longest_first=True, persistent=False, radix_bits=8, block_cull=True):
+    t = _Tuning(lds_batch, 1 if longest_first else 0, 1 if persistent else 0, radix_bits, 1 if block_cull else 0)
     _check(lib().as_set_tuning(ctx.handle, ctypes.byref(t)))
 
 
@@ -733,7 +733,7 @@ def get_tuning(ctx):
     t = _Tuning()
     _check(lib().as_get_tuning(ctx.handle, ctypes.byref(t)))
     return dict(lds_batch=t.lds_batch, longest_first=bool(t.longest_first), persistent=bool(t.persistent),
-                radix_bits=t.radix_bits)
+                radix_bits=t.radix_bits, block_cull=bool(t.block_cull))
 
 
 def timing_enable(ctx, on=True):

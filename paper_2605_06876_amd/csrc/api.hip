@@ -129,6 +129,7 @@ void frame_buffers(as_frame *f, bool keys_only, V &&visit) {
         arr(&f->vals[k], key);
     }
     dbuf(f->sort_hist, sort_hist_bytes(key));
+    if (!(f->flags & AS_FRAME_FORWARD_ONLY)) arr(&f->bmask, key);
     if (keys_only) return;
     arr(&f->rec, ent); arr(&f->depth_key, ent); arr(&f->box, ent * 4); arr(&f->ntiles, ent); arr(&f->offsets, ent);
     arr(&f->grad2d, ent * 9);
@@ -251,6 +252,21 @@ as_status as_ctx_create(int device, as_ctx **out) {
     // fixed-size scratch of the loss partials and the loop's totals
     if (bad(devbuf_ensure(c->tr[TR_PART], l1_partials_bytes()), "as_ctx_create: scratch") ||
         bad(devbuf_ensure(c->tr[TR_TOT], 16), "as_ctx_create: scratch")) {
+        as_ctx_destroy(c);
+        return AS_ERR_HIP;
+    }
+    // load every source file's code object now (see AS_WARM_KERNEL)
+    warm_api(nullptr);
+    warm_binning(nullptr);
+    warm_blend(nullptr);
+    warm_errstats(nullptr);
+    warm_project(nullptr);
+    warm_project_bwd(nullptr);
+    warm_radix(nullptr);
+    warm_split(nullptr);
+    warm_train(nullptr);
+    if (bad(hipGetLastError(), "as_ctx_create: code-object warm-up") ||
+        bad(hipDeviceSynchronize(), "as_ctx_create: code-object warm-up")) {
         as_ctx_destroy(c);
         return AS_ERR_HIP;
     }
@@ -625,10 +641,11 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
         f->use_order = ctx->longest_first;
         if (f->use_order) launch_tile_order(f->ranges, (int)tiles, f->tile_order, s);
     }
-    const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
+    const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu, ctx->block_cull};
     {
         StageTimer t(ctx, AS_STAGE_BLEND_FWD, s);
         f->ck_written = f->ckpt != nullptr;
+        f->bm_written = f->bmask != nullptr;
         f->ck_seg = blend_fwd_batch(bl);
         launch_blend_fwd(f, f->vals[sel], f->use_order ? f->tile_order : nullptr, bl, vt, gi, im, s);
         // the reverse pass's cost per tile follows its contributors, which only
@@ -678,7 +695,7 @@ as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame 
     memset(&dl, 0, sizeof(dl));
     for (int v = 0; v < vt.n_views; v++) dl.p[v] = dL_dimages[v];
     const int64_t ents = vt.ent_base[vt.n_views];
-    const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu};
+    const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu, ctx->block_cull};
     // Frames hold their checkpoint buffer from creation (unless created
     // forward-only): renders write checkpoints at the forward's batch
     // boundaries and this pass splits long tile lists at them.
@@ -949,6 +966,7 @@ as_status as_set_tuning(as_ctx *ctx, const as_tuning *t) {
     ctx->longest_first = t->longest_first != 0;
     ctx->persistent = t->persistent != 0;
     ctx->radix_bits = t->radix_bits;
+    ctx->block_cull = t->block_cull != 0;
     return AS_OK;
 }
 
@@ -958,6 +976,7 @@ as_status as_get_tuning(const as_ctx *ctx, as_tuning *t) {
     t->longest_first = ctx->longest_first;
     t->persistent = ctx->persistent;
     t->radix_bits = ctx->radix_bits;
+    t->block_cull = ctx->block_cull;
     return AS_OK;
 }
 
@@ -1086,3 +1105,5 @@ as_status as_debug_blend_alpha(const as_frame *f, int32_t view, int64_t n, const
 }
 
 }  // extern "C"
+
+AS_WARM_KERNEL(api)

@@ -298,3 +298,5 @@ void launch_fp64_ops(const double *a, const double *b, int64_t n, double *out, h
     if (n == 0) return;
     hipLaunchKernelGGL(k_fp64_ops, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n, out);
 }
+
+AS_WARM_KERNEL(binning)

@@ -95,6 +95,72 @@ __device__ __forceinline__ void stage(const Fetched &f, int ox, int oy, StagedRe
     s_rec[t] = make_staged(f, ox, oy);
 }
 
+// Which of the tile's sixteen 4x4 pixel blocks a staged record may
+// contribute to: bit 4 by + bx for the block at tile columns 4 bx .. 4 bx + 3
+// and rows 4 by .. 4 by + 3.  Always a subset of the blocks its pixel box
+// meets; with `ellipse` also of the blocks the ellipse alpha >= 1/255 meets.
+//
+// A pixel contributes only if exp2(q) >= 1/255, i.e. (with P = -a', R = -b'/2,
+// S = -c', L = log2 o and d = pixel - mean) the quadratic form
+// P dx^2 + 2 R dx dy + S dy^2 <= L + log2(255).  The kernels evaluate q in
+// FP32, with an error below 5 ulp of the sum of the terms' magnitudes; inside
+// the ellipse that sum is at most 4 t / (1 - rho^2) (rho^2 = R^2 / (P S), t
+// <= 8), so the threshold is raised by 2e-5 (1 + 1 / (1 - rho^2)), above that
+// bound, and the extents below are padded for their own rounding.  Every
+// pixel the kernels can take as a contributor therefore lies in a block whose
+// bit is set; a block skipped holds no contributor, so the outputs are those
+// of the box test alone.
+//
+// Per band of four pixel rows the ellipse's x-extent is taken in closed form:
+// for fixed dy the ellipse spans xc(dy) -+ hw(dy) with xc = -(R/P) dy and
+// hw = sqrt((t - (det/P) dy^2) / P), det = P S - R^2; the left edge
+// xc - hw is convex in dy with its minimum -hx at the ellipse's leftmost point
+// (dy = R hx / S), so over a band its minimum is -hx when that point lies in
+// the band and the value at the band's nearer end otherwise; the right edge
+// mirrors it.
+__device__ __forceinline__ uint32_t block_mask(const StagedRec &sr, bool ellipse) {
+    const uint32_t m = __float_as_uint(sr.ex.y);
+    // blocks the pixel box meets: nonzero nibbles of the column and row masks
+    auto nib = [](uint32_t x) {
+        const uint32_t t = (x | (x >> 1) | (x >> 2) | (x >> 3)) & 0x1111u;
+        return (t | (t >> 3) | (t >> 6) | (t >> 9)) & 0xFu;
+    };
+    const uint32_t cb = nib(m & 0xFFFFu), rb = nib(m >> 16);
+    const uint32_t rspread = (rb & 1u) | ((rb & 2u) << 3) | ((rb & 4u) << 6) | ((rb & 8u) << 9);
+    const uint32_t box16 = rspread * cb;   // cb copied into the nibble of every row block
+    if (!ellipse || box16 == 0u) return box16;
+    const float P = -sr.mc.z, R = -0.5f * sr.mc.w, S = -sr.cc.x, L = sr.cc.y;
+    const double det = (double)P * (double)S - (double)R * (double)R;   // products exact in FP64
+    if (!(P > 0.f) || !(S > 0.f) || !(det > 0.0)) return box16;
+    const float inv_omr = (float)(((double)P * (double)S) / det);       // 1 / (1 - rho^2) >= 1
+    const float t = L + 7.99435343685886f + 2e-5f * (1.0f + inv_omr);
+    if (!(t > 0.f)) return t <= 0.f ? 0u : box16;
+    const float detf = (float)det, iP = 1.0f / P;
+    const float hx = sqrtf(t * S / detf), hy = sqrtf(t * P / detf);
+    if (!(hx < 1e6f) || !(hy < 1e6f)) return box16;
+    const float kc = -R * iP, u = t * iP, e = detf * iP * iP;
+    const float dyL = R * hx / S;           // leftmost point's dy; the rightmost is at -dyL
+    const float hyp = hy * (1.0f + 1e-5f) + 1e-3f;
+    const float padx = 1e-3f + 4e-5f * hx;
+    const float slack = 1e-5f * u;          // keeps rounding in u - e y^2 from narrowing the band
+    auto edge = [&](float y, float sgn) { return kc * y + sgn * sqrtf(fmaxf(0.f, u - e * y * y + slack)); };
+    uint32_t ell = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        const float y0 = fmaxf((float)(4 * b) + 0.5f - sr.mc.y, -hyp);
+        const float y1 = fminf((float)(4 * b) + 3.5f - sr.mc.y, hyp);
+        const float xmin = (dyL >= y0 && dyL <= y1 ? -hx : edge(dyL < y0 ? y0 : y1, -1.0f)) - padx;
+        const float xmax = (-dyL >= y0 && -dyL <= y1 ? hx : edge(-dyL < y0 ? y0 : y1, 1.0f)) + padx;
+        // columns 4k .. 4k + 3 have pixel centres 4k + 0.5 .. 4k + 3.5
+        const float kmin = fminf(fmaxf(ceilf((xmin + sr.mc.x - 3.5f) * 0.25f), 0.f), 4.f);
+        const float kmax = fminf(fmaxf(floorf((xmax + sr.mc.x - 0.5f) * 0.25f), -1.f), 3.f);
+        const int k0 = (int)kmin, k1 = (int)kmax;
+        const uint32_t bits = (y0 <= y1 && k0 <= k1) ? ((2u << k1) - (1u << k0)) : 0u;
+        ell |= bits << (4 * b);
+    }
+    return ell & box16;
+}
+
 // Pixel geometry of a lane: 16-lane row `row` of wave w owns 4x4 block
 // sb = 4 w + row of the tile (blocks in row-major order).
 struct LaneGeom {
@@ -118,24 +184,24 @@ __device__ __forceinline__ LaneGeom lane_geom(int tid) {
 }
 
 // For each row of this wave, the indices j < cnt (ascending) of the staged
-// records whose box meets the row's pixel block, into hits[row][..]; returns
-// this lane's row count.  Row r of the wave covers tile columns 4r .. 4r+3;
-// `by` holds the box-mask bits of the tile rows the wave covers.  `ok(j)`
-// adds a condition that is the same for the whole wave.
+// records whose block mask (block_mask) meets the row's pixel block, into
+// hits[row][..]; returns this lane's row count.  Row r takes the blocks of
+// sel0 << r (sel0: the bits of row 0's block or blocks).  `ok(j)` adds a
+// condition that is the same for the whole wave.
 template <int BATCH, typename Ok>
-__device__ __forceinline__ int compact_rows(const StagedRec *s_rec, int cnt, HitT<BATCH> (*hits)[BATCH + 4],
-                                            uint32_t by, int row, Ok ok) {
+__device__ __forceinline__ int compact_rows(const uint16_t *s_bm, int cnt, HitT<BATCH> (*hits)[BATCH + 4],
+                                            uint32_t sel0, int row, Ok ok) {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lanemask_lt();
     int n[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < BATCH / 64; k++) {
         const int j = k * 64 + lane;
-        const uint32_t m = j < cnt ? __float_as_uint(s_rec[j].ex.y) : 0u;
-        const bool any = (m & by) && ok(j);
+        const uint32_t bm = j < cnt ? (uint32_t)s_bm[j] : 0u;
+        const bool any = (bm & (sel0 * 0xFu)) && ok(j);
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            const bool hit = any && (m & (0xFu << (r * 4)));
+            const bool hit = any && (bm & (sel0 << r));
             const uint64_t bal = __ballot(hit);
             if (hit) hits[r][n[r] + __popcll(bal & lt)] = (HitT<BATCH>)j;
             n[r] += __popcll(bal);
@@ -163,6 +229,7 @@ __device__ __forceinline__ float row_sum(float v) {
 template <int BATCH>
 struct BlendShared {
     StagedRec rec[BATCH];
+    uint16_t bm[BATCH];                              // block masks (block_mask)
     HitT<BATCH> hits[AS_BLOCK / 64][4][BATCH + 4];  // +4: the loops read one index ahead
 };
 
@@ -194,6 +261,7 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                                                         unsigned long long *__restrict__ tile_err,
                                                         uint32_t *__restrict__ tile_work,
                                                         uint32_t *__restrict__ tile_hi, float4 *__restrict__ ckpt,
+                                                        uint16_t *__restrict__ bm_out, int ellipse,
                                                         uint32_t *queue, int n_tiles) {
     constexpr int R = BATCH / AS_BLOCK;
     __shared__ BlendShared<BATCH> sh;
@@ -239,13 +307,20 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
 #pragma unroll
             for (int k = 0; k < R; k++) {
                 const int t = k * AS_BLOCK + tid;
-                if (b0 + t < end) stage(nf[k], ox, oy, sh.rec, t);
+                if (b0 + t < end) {
+                    const StagedRec sr = make_staged(nf[k], ox, oy);
+                    const uint32_t bm = block_mask(sr, ellipse != 0);
+                    sh.rec[t] = sr;
+                    sh.bm[t] = (uint16_t)bm;
+                    if (bm_out) bm_out[b0 + t] = (uint16_t)bm;   // the reverse pass reuses it
+                }
                 if (b0 + BATCH + t < end) fetch(vals, rec, box, b0 + BATCH + t, nf[k]);
             }
             __syncthreads();
             if (__ballot(!done) == 0) continue;                 // the whole wave has saturated
             const int cnt = (int)min((uint32_t)BATCH, end - b0);
-            const int nh = compact_rows<BATCH>(sh.rec, cnt, sh.hits[w], (0xFu << (w * 4)) << 16, lg.row,
+            // wave w's rows are the 4x4 blocks 4 w .. 4 w + 3
+            const int nh = compact_rows<BATCH>(sh.bm, cnt, sh.hits[w], 1u << (4 * w), lg.row,
                                                [](int) { return true; });
             if (done) continue;
             // Two hits per step: both records' loads and alpha evaluations are
@@ -403,6 +478,7 @@ constexpr int BWD_BLOCK = 128;
 template <int BATCH>
 struct BwdShared {
     StagedRec rec[BATCH];
+    uint16_t bm[BATCH];
     HitT<BATCH> hits[BWD_BLOCK / 64][4][BATCH + 4];   // +4: the loop reads one index ahead
     float gacc[9][BATCH];
     uint8_t gflag[BATCH];
@@ -440,6 +516,7 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
                                                          const uint32_t *__restrict__ last_in,
                                                          const uint32_t *__restrict__ ncontrib_in,
                                                          const ViewImagesC dLs, float *__restrict__ grad2d,
+                                                         const uint16_t *__restrict__ bm_in, int ellipse,
                                                          uint32_t *queue) {
     constexpr int R = BATCH / BWD_BLOCK;
     __shared__ BwdShared<BATCH> sh;
@@ -448,7 +525,8 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
     const int row = lane >> 4, c = lane & 15;
     const int lx = row * 4 + (c & 3), ly = w * 8 + (c >> 2);
     const uint32_t pbA = (1u << lx) | (1u << (16 + ly)), pbB = (1u << lx) | (1u << (20 + ly));
-    const uint32_t by = (0xFFu << (w * 8)) << 16;
+    // row r of wave w covers the 4x4 blocks (r, 2 w) and (r, 2 w + 1)
+    const uint32_t sel0 = (1u << (8 * w)) | (1u << (8 * w + 4));
     const HitT<BATCH> *hits = sh.hits[w][row];
     const float px = (float)lx + 0.5f, pyA = (float)ly + 0.5f, pyB = (float)(ly + 4) + 0.5f;
     for (int i = tid; i < BATCH; i += BWD_BLOCK) {
@@ -524,12 +602,19 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
         for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
 
         // batches [b0, b1) walk the segment backwards from its end
+        // block masks come from the forward (bm_in) or, in frames without
+        // that buffer, are recomputed here; both are the same function of the
+        // staged record, and any conservative mask gives the same outputs
         Fetched nf[R];
+        uint16_t nbm[R];
         {
             const uint32_t b0 = s1 - s0 > (uint32_t)BATCH ? s1 - BATCH : s0;
 #pragma unroll
             for (int k = 0; k < R; k++)
-                if (b0 + k * BWD_BLOCK + tid < s1) fetch(vals, rec, box, b0 + k * BWD_BLOCK + tid, nf[k]);
+                if (b0 + k * BWD_BLOCK + tid < s1) {
+                    fetch(vals, rec, box, b0 + k * BWD_BLOCK + tid, nf[k]);
+                    if (bm_in) nbm[k] = bm_in[b0 + k * BWD_BLOCK + tid];
+                }
         }
         for (uint32_t b1 = s1; b1 > s0;) {
             const uint32_t b0 = b1 - s0 > (uint32_t)BATCH ? b1 - BATCH : s0;
@@ -537,11 +622,18 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
 #pragma unroll
             for (int k = 0; k < R; k++) {
                 const int t = k * BWD_BLOCK + tid;
-                if (b0 + t < b1) stage(nf[k], ox, oy, sh.rec, t);
-                if (n0 + t < n1) fetch(vals, rec, box, n0 + t, nf[k]);
+                if (b0 + t < b1) {
+                    const StagedRec sr = make_staged(nf[k], ox, oy);
+                    sh.rec[t] = sr;
+                    sh.bm[t] = bm_in ? nbm[k] : (uint16_t)block_mask(sr, ellipse != 0);
+                }
+                if (n0 + t < n1) {
+                    fetch(vals, rec, box, n0 + t, nf[k]);
+                    if (bm_in) nbm[k] = bm_in[n0 + t];
+                }
             }
             __syncthreads();
-            const int nh = compact_rows<BATCH>(sh.rec, (int)(b1 - b0), sh.hits[w], by, row,
+            const int nh = compact_rows<BATCH>(sh.bm, (int)(b1 - b0), sh.hits[w], sel0, row,
                                                [&](int j) { return b0 + (uint32_t)j < wlast; });
             // the wave walks max over its rows of the row counts; rows past their
             // own count idle
@@ -878,7 +970,8 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         }                                                                                                          \
         hipLaunchKernelGGL((k_blend_fwd<B, PER>), dim3(grid), dim3(AS_BLOCK), 0, s, f->ranges, tile_order, vals,  \
                            f->rec, b4, vt, gt, image, f->t_final, f->last, f->n_contrib, f->dom, f->err, te,      \
-                           f->tile_work, f->tile_hi, reinterpret_cast<float4 *>(f->ckpt), f->queue, tiles);        \
+                           f->tile_work, f->tile_hi, reinterpret_cast<float4 *>(f->ckpt), f->bmask,               \
+                           bl.ellipse, f->queue, tiles);                                                           \
     } while (0)
     if (bl.persistent) {
         if (bl.batch >= 1024) AS_FWD(1024, true);
@@ -914,7 +1007,8 @@ void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         }                                                                                                          \
         hipLaunchKernelGGL((k_blend_bwd<B, PER>), dim3(grid), dim3(BWD_BLOCK), 0, s, f->ranges, f->bwd_items,     \
                            f->n_items, f->tile_hi, ckp, seg_len, vals, f->rec, b4, vt, f->t_final, f->last,        \
-                           f->n_contrib, dL_dimage, grad2d, f->queue + 1);                                         \
+                           f->n_contrib, dL_dimage, grad2d, f->bm_written ? f->bmask : nullptr, bl.ellipse,        \
+                           f->queue + 1);                                                                          \
     } while (0)
     // the reverse pass stages half the forward's depth: two waves per tile
     if (bl.persistent) {
@@ -926,3 +1020,5 @@ void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
     }
 #undef AS_BWD
 }
+
+AS_WARM_KERNEL(blend)

@@ -516,3 +516,5 @@ as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const ui
                        rb.records, rb.capacity);
     return AS_OK;
 }
+
+AS_WARM_KERNEL(errstats)

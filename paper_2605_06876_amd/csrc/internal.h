@@ -119,6 +119,9 @@ struct as_frame {
     uint32_t *tile_hi;     // [tiles] one past the tile's last contributor (0: none), from the forward blend
     float *ckpt;           // [tile_cap][AS_CK_MAX][256][4] per pixel (T, colour behind) at the forward's batch
                            // boundaries; NULL in forward-only frames
+    uint16_t *bmask;       // [key_cap] per sorted pair: the 4x4 pixel blocks of its tile it may contribute to,
+                           // from the forward blend for the reverse blend; NULL in forward-only frames
+    int bm_written;        // the last render wrote bmask for every pair the reverse pass walks
     uint32_t *bwd_items;   // [tile_cap * (AS_CK_MAX + 1)][2] (tile, segment) work items of the reverse blend
     uint32_t *n_items;     // [1] device count of bwd_items
     int ck_written;        // the last render wrote checkpoints
@@ -160,6 +163,7 @@ struct as_ctx {
     int longest_first = 1;
     int persistent = 0;
     int radix_bits = 8;
+    int block_cull = 1;
     int n_cu = 0;                 // compute units of the device
     int timing = 0;
     StageRec *recs = nullptr;     // recorded stage event pairs
@@ -231,6 +235,7 @@ struct BlendLaunch {
     int batch;         // LDS depth: 256, 512 or 1024 records
     int persistent;    // 1: one resident grid pulling tiles from f->queue
     int n_cu;
+    int ellipse;       // 1: per-block culling by the alpha >= 1/255 ellipse, not only the box
 };
 // The forward blend's LDS depth for a launch (256, 512 or 1024 records).
 int blend_fwd_batch(const BlendLaunch &bl);
@@ -293,6 +298,23 @@ as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *can
                              const as_region_buf &rb, const as_camera *views, int n_views, const int32_t *attr,
                              const as_split_params &p, const float *noise, GradPtrs out, int64_t out_cap,
                              uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out, hipStream_t s);
+
+// Code-object warm-up.  Each source file's kernels are a code object of their
+// own, which the runtime loads, allocating device memory for it, at the first
+// launch from that file.  The context launches one empty kernel per file at
+// creation, so that no call of the path triggers such a load.
+#define AS_WARM_KERNEL(name)                                                        \
+    __global__ void k_warm_##name() {}                                              \
+    void warm_##name(hipStream_t s) { hipLaunchKernelGGL(k_warm_##name, dim3(1), dim3(1), 0, s); }
+void warm_api(hipStream_t s);
+void warm_binning(hipStream_t s);
+void warm_blend(hipStream_t s);
+void warm_errstats(hipStream_t s);
+void warm_project(hipStream_t s);
+void warm_project_bwd(hipStream_t s);
+void warm_radix(hipStream_t s);
+void warm_split(hipStream_t s);
+void warm_train(hipStream_t s);
 
 // debug (binning.hip)
 void launch_fp64_ops(const double *a, const double *b, int64_t n, double *out, hipStream_t s);

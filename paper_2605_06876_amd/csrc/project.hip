@@ -161,3 +161,5 @@ void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, in
                                   sort_vals, n_ent); break;
     }
 }
+
+AS_WARM_KERNEL(project)

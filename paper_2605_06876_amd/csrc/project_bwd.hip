@@ -424,3 +424,5 @@ void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t 
     default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out, g2d_norm, vis_count); break;
     }
 }
+
+AS_WARM_KERNEL(project_bwd)

@@ -311,3 +311,5 @@ int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, 
                    int hi_bit, int radix_bits, void *hist, hipStream_t s) {
     return rs_sort<uint64_t>(keys, vals, n_dev, cap, n_hint, lo_bit, hi_bit, radix_bits, hist, nullptr, nullptr, s);
 }
+
+AS_WARM_KERNEL(radix)

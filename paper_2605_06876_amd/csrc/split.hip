@@ -652,3 +652,5 @@ as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *can
                        n_out);
     return AS_OK;
 }
+
+AS_WARM_KERNEL(split)

@@ -306,3 +306,5 @@ void launch_reset_opacity(const as_gaussians_mut &g, float cap, float *m, float 
     hipLaunchKernelGGL(k_reset_opacity, dim3(blocks_for(g.n, 1ll << 30)), dim3(TB), 0, s, g.n, g.opacity_logits, cap,
                        m, v);
 }
+
+AS_WARM_KERNEL(train)

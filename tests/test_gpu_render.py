@@ -192,7 +192,7 @@ def _grad_compare(gr, gref, exclude=None, tol=1e-3):
         elem = np.abs(a - b) <= tol * (np.abs(b) + rms) + 1e-12
         out[name] = (rel, elem.mean())
         assert rel <= tol, (name, rel)
-        assert elem.mean() >= 0.999, (name, elem.mean())
+        assert elem.all(), (name, int((~elem).sum()), elem.size)
     return out
 
 
@@ -496,22 +496,26 @@ def test_autograd_function_matches_oracle_gradients(c1):
     assert (r.vis_count.cpu().numpy() == (pr.valid == 1)).all()
 
 
-@pytest.mark.parametrize("batch,lpt,persistent,radix", [(256, False, False, 8), (256, True, True, 8),
-                                                       (512, True, False, 6), (1024, True, True, 5),
-                                                       (1024, False, False, 4), (512, False, True, 7)])
-def test_tuning_never_changes_results(ctx, c2, batch, lpt, persistent, radix):
+@pytest.mark.parametrize("batch,lpt,persistent,radix,cull", [(256, False, False, 8, True), (256, True, True, 8, True),
+                                                            (512, True, False, 6, True), (1024, True, True, 5, True),
+                                                            (1024, False, False, 4, True), (512, False, True, 7, True),
+                                                            (256, True, False, 7, False)])
+def test_tuning_never_changes_results(ctx, c2, batch, lpt, persistent, radix, cull):
     """Every launch tuning gives a bit-identical forward (same per-pixel
-    operations in the same order) and gradients equal up to atomic order."""
+    operations in the same order) and gradients equal up to atomic order.
+    The reference culls by the pixel box alone, so the ellipse block culling
+    is shown to drop no contributor on all 1,039,968 pixels."""
     cam = c2["cam"]
     ctx2 = api.Context(0)
-    api.set_tuning(ctx2, lds_batch=batch, longest_first=lpt, persistent=persistent, radix_bits=radix)
+    api.set_tuning(ctx2, lds_batch=batch, longest_first=lpt, persistent=persistent, radix_bits=radix,
+                   block_cull=cull)
     g = c2["g"]
     frame = api.Frame(ctx2, g.n, cam.width, cam.height)
     img = api.render(ctx2, g, cam, frame, gt=torch.from_numpy(c2["gt"]).cuda())
     G = torch.from_numpy(np.random.default_rng(9).normal(size=(3, cam.height, cam.width)).astype(np.float32)).cuda()
     grads = api.render_backward(ctx2, g, cam, frame, G)
     ref_ctx = api.Context(0)
-    api.set_tuning(ref_ctx, lds_batch=256, longest_first=False)
+    api.set_tuning(ref_ctx, lds_batch=256, longest_first=False, block_cull=False)
     ref_frame = api.Frame(ref_ctx, g.n, cam.width, cam.height)
     ref = api.render(ref_ctx, g, cam, ref_frame, gt=torch.from_numpy(c2["gt"]).cuda())
     ref_grads = api.render_backward(ref_ctx, g, cam, ref_frame, G)
