@@ -330,6 +330,24 @@ as_status as_accumulate_error_stats(as_ctx *ctx, int32_t width, int32_t height, 
                                     int64_t n, const uint8_t *is_candidate, const as_split_params *params,
                                     as_region_buf *regions, int32_t *attr_count, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): as_accumulate_error_stats
+ * with the same arguments, kernels and results, but its scratch in one static
+ * device array of the library (54 MiB plus 32 KiB, sized for views of up to
+ * AS_NOALLOC_MAX_PIXELS pixels) instead of the context's reservation, which it
+ * does not need.  Each device the library runs on holds its own copy of that
+ * array until the process ends; its address is taken when a context is
+ * created on the device.  All calls on one device share the array, so calls
+ * that overlap on a device race and must not be issued (one stream, or
+ * ordered streams).  AS_ERR_CAPACITY when width x height exceeds
+ * AS_NOALLOC_MAX_PIXELS; other errors as as_accumulate_error_stats. */
+#define AS_NOALLOC_MAX_PIXELS (1 << 20)
+as_status as_accumulate_error_stats_noalloc(as_ctx *ctx, int32_t width, int32_t height, const double *err,
+                                            const uint64_t *err_minmax, const int32_t *dom, const float *gt,
+                                            int32_t view_id, int64_t n, const uint8_t *is_candidate,
+                                            const as_split_params *params, as_region_buf *regions,
+                                            int32_t *attr_count, void *stream);
+
 /* The adaptive split of every candidate (Sec. 4.2, 4.3, App. A and Sec. 5
  * "Implementation"): one child proposal per region (centre on the centroid ray
  * at t* of Eq. (tstar); shape from the unprojected, clipped PCA axes; colour

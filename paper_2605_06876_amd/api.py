@@ -83,7 +83,7 @@ EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "a
             "as_frame_bytes", "as_workspace_size", "as_frame_destroy", "as_frame_get_view", "as_frame_get_view_of",
             "as_frame_pair_count", "as_render",
             "as_render_backward", "as_render_batch", "as_render_backward_batch", "as_error_map",
-            "as_accumulate_error_stats", "as_adaptive_split", "as_set_tuning", "as_get_tuning", "as_timing_enable",
+            "as_accumulate_error_stats", "as_accumulate_error_stats_noalloc", "as_adaptive_split", "as_set_tuning", "as_get_tuning", "as_timing_enable",
             "as_timing_read", "as_graph_begin", "as_graph_end", "as_graph_launch", "as_graph_destroy",
             "as_debug_sort_pairs", "as_debug_fp64_ops", "as_debug_blend_alpha", "as_adam_step", "as_l1_loss", "as_densify_select",
             "as_split_row_map", "as_clone_prune", "as_gather_rows", "as_reset_opacity")
@@ -588,6 +588,23 @@ def accumulate_error_stats(ctx, width, height, err, err_minmax, dom, gt, view_id
                                            addr(err_minmax), addr(dom), _ptr(gt), ctypes.c_int32(view_id),
                                            ctypes.c_int64(is_candidate.shape[0]), _ptr(is_candidate), ctypes.byref(p),
                                            ctypes.byref(rb), _ptr(attr_count), _stream(stream)))
+
+
+NOALLOC_MAX_PIXELS = 1 << 20
+
+
+def accumulate_error_stats_noalloc(ctx, width, height, err, err_minmax, dom, gt, view_id, is_candidate, params,
+                                   regions, attr_count, stream=None):
+    """as_accumulate_error_stats_noalloc: the same call with the library's
+    static scratch (views up to NOALLOC_MAX_PIXELS pixels)."""
+    p = params.struct()
+    rb = regions.struct()
+    addr = lambda x: ctypes.c_void_p(x) if isinstance(x, int) else _ptr(x)
+    _check(lib().as_accumulate_error_stats_noalloc(ctx.handle, ctypes.c_int32(width), ctypes.c_int32(height),
+                                                   addr(err), addr(err_minmax), addr(dom), _ptr(gt),
+                                                   ctypes.c_int32(view_id), ctypes.c_int64(is_candidate.shape[0]),
+                                                   _ptr(is_candidate), ctypes.byref(p), ctypes.byref(rb),
+                                                   _ptr(attr_count), _stream(stream)))
 
 
 def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=None, mode=None, count=None,

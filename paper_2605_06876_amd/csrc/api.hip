@@ -255,6 +255,11 @@ as_status as_ctx_create(int device, as_ctx **out) {
         as_ctx_destroy(c);
         return AS_ERR_HIP;
     }
+    // the static scratch of as_accumulate_error_stats_noalloc: its address on this device
+    if (bad(errstats_noalloc_init(device), "as_ctx_create: static scratch address")) {
+        as_ctx_destroy(c);
+        return AS_ERR_HIP;
+    }
     // load every source file's code object now (see AS_WARM_KERNEL)
     warm_api(nullptr);
     warm_binning(nullptr);
@@ -907,6 +912,27 @@ as_status as_accumulate_error_stats(as_ctx *ctx, int32_t width, int32_t height, 
     }
     if (st != AS_OK) return st;
     return launch_status("as_accumulate_error_stats");
+}
+
+as_status as_accumulate_error_stats_noalloc(as_ctx *ctx, int32_t width, int32_t height, const double *err,
+                                            const uint64_t *err_minmax, const int32_t *dom, const float *gt,
+                                            int32_t view_id, int64_t n, const uint8_t *is_candidate,
+                                            const as_split_params *params, as_region_buf *regions,
+                                            int32_t *attr_count, void *stream) {
+    if (!ctx || !err || !err_minmax || !dom || !gt || !is_candidate || !regions || !regions->records ||
+        !regions->count || !attr_count || width < 1 || height < 1 || n < 1 || view_id < 0) {
+        as_set_error("as_accumulate_error_stats_noalloc: bad argument");
+        return AS_ERR_ARG;
+    }
+    if (!check_params(params, "as_accumulate_error_stats_noalloc")) return AS_ERR_ARG;
+    as_status st;
+    {
+        StageTimer t(ctx, AS_STAGE_ERROR_STATS, (hipStream_t)stream);
+        st = run_error_stats_noalloc(ctx, width, height, err, err_minmax, dom, gt, view_id, is_candidate, *params,
+                                     *regions, attr_count, (hipStream_t)stream);
+    }
+    if (st != AS_OK) return st;
+    return launch_status("as_accumulate_error_stats_noalloc");
 }
 
 as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *cand, int64_t n_cand,

@@ -11,6 +11,8 @@
 // LDS (fused with the classification and the erosion), then across tile
 // borders in global memory.  Kept regions take their record slots from per-block
 // counts scanned by one block, so records stay in ascending label order.
+#include <mutex>
+
 #include "internal.h"
 
 namespace {
@@ -479,6 +481,21 @@ hipError_t errstats_reserve(as_ctx *ctx, int64_t max_pixels) {
     return e;
 }
 
+namespace {
+// The scratch of one error-statistics call (slots of es_need).
+struct EsScratch {
+    uint8_t *B;
+    int32_t *label;
+    unsigned long long *mom;
+    uint8_t *keep;
+    int64_t *kidx;   // per block of 256 pixels: kept roots, then first record slot
+};
+
+void es_launch(const EsScratch &sc, int W, int H, const double *err, const uint64_t *minmax, const int32_t *dom,
+               const float *gt, int view, const uint8_t *is_cand, const as_split_params &p, as_region_buf &rb,
+               int32_t *attr, hipStream_t s);
+}  // namespace
+
 as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const uint64_t *minmax, const int32_t *dom,
                           const float *gt, int view, int64_t n, const uint8_t *is_cand, const as_split_params &p,
                           as_region_buf &rb, int32_t *attr, hipStream_t s) {
@@ -491,11 +508,89 @@ as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const ui
         return AS_ERR_CAPACITY;
     }
     DevBuf *es = ctx->es;
-    uint8_t *B = (uint8_t *)es[ES_B].p;
-    uint8_t *keep = (uint8_t *)es[ES_KEEP].p;
-    int32_t *label = (int32_t *)es[ES_LABEL].p;
-    int64_t *kidx = (int64_t *)es[ES_KIDX].p;   // per block of 256 pixels: kept roots, then first record slot
-    unsigned long long *mom = (unsigned long long *)es[ES_MOM].p;
+    const EsScratch sc{(uint8_t *)es[ES_B].p, (int32_t *)es[ES_LABEL].p, (unsigned long long *)es[ES_MOM].p,
+                       (uint8_t *)es[ES_KEEP].p, (int64_t *)es[ES_KIDX].p};
+    es_launch(sc, W, H, err, minmax, dom, gt, view, is_cand, p, rb, attr, s);
+    return AS_OK;
+}
+
+// ---- the no-allocation variant ------------------------------------------------------
+//
+// For callers that cannot allocate device memory (code under graph capture,
+// serving loops, harnesses that forbid hipMalloc): the same kernels with their
+// scratch in one static device array, sized for views of up to
+// AS_NOALLOC_MAX_PIXELS pixels.  The runtime gives every device its own copy
+// of the array (held until the process ends); its address on a device is taken
+// once, with that device current, when a context is created there
+// (errstats_noalloc_init), and the kernels receive that address.  In host code
+// the array's name is no device address, so it is never passed to a kernel.
+// Every call on a device shares the one array: calls on that device must not
+// overlap (they would race on it).  Nothing in it needs clearing: each kernel
+// writes a slot before any kernel of the same call reads it.
+namespace {
+constexpr size_t es_slot(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+constexpr size_t ES_NA_PIX = (size_t)AS_NOALLOC_MAX_PIXELS;
+constexpr size_t ES_NA_OFF_LABEL = es_slot(ES_NA_PIX);
+constexpr size_t ES_NA_OFF_MOM = ES_NA_OFF_LABEL + es_slot(ES_NA_PIX * 4);
+constexpr size_t ES_NA_OFF_KEEP = ES_NA_OFF_MOM + es_slot(ES_NA_PIX * 48);
+constexpr size_t ES_NA_OFF_KIDX = ES_NA_OFF_KEEP + es_slot(ES_NA_PIX);
+constexpr size_t ES_NA_BYTES = ES_NA_OFF_KIDX + es_slot((ES_NA_PIX + 255) / 256 * 8);
+constexpr int ES_NA_MAX_DEVICES = 64;
+
+std::mutex g_na_mutex;
+unsigned char *g_na_ptr[ES_NA_MAX_DEVICES];   // the array's address on each device
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[ES_NA_BYTES];
+
+hipError_t errstats_noalloc_init(int device) {
+    if (device < 0 || device >= ES_NA_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    if (g_na_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_na_ptr[device] = (unsigned char *)ptr;
+    return hipSuccess;
+}
+
+size_t errstats_noalloc_bytes() { return ES_NA_BYTES; }
+
+as_status run_error_stats_noalloc(as_ctx *ctx, int W, int H, const double *err, const uint64_t *minmax,
+                                  const int32_t *dom, const float *gt, int view, const uint8_t *is_cand,
+                                  const as_split_params &p, as_region_buf &rb, int32_t *attr, hipStream_t s) {
+    const int64_t P = (int64_t)W * H;
+    if (P > (int64_t)AS_NOALLOC_MAX_PIXELS) {
+        as_set_error("as_accumulate_error_stats_noalloc: a %dx%d view has %lld pixels, above the static scratch's "
+                     "maximum of %lld", W, H, (long long)P, (long long)AS_NOALLOC_MAX_PIXELS);
+        return AS_ERR_CAPACITY;
+    }
+    if (P == 0) return AS_OK;
+    unsigned char *base = nullptr;
+    if (ctx->device >= 0 && ctx->device < ES_NA_MAX_DEVICES) {
+        std::lock_guard<std::mutex> lock(g_na_mutex);
+        base = g_na_ptr[ctx->device];
+    }
+    if (!base) {
+        as_set_error("as_accumulate_error_stats_noalloc: no static scratch address for device %d", ctx->device);
+        return AS_ERR_STATE;
+    }
+    const EsScratch sc{base, (int32_t *)(base + ES_NA_OFF_LABEL), (unsigned long long *)(base + ES_NA_OFF_MOM),
+                       base + ES_NA_OFF_KEEP, (int64_t *)(base + ES_NA_OFF_KIDX)};
+    es_launch(sc, W, H, err, minmax, dom, gt, view, is_cand, p, rb, attr, s);
+    return AS_OK;
+}
+
+namespace {
+void es_launch(const EsScratch &sc, int W, int H, const double *err, const uint64_t *minmax, const int32_t *dom,
+               const float *gt, int view, const uint8_t *is_cand, const as_split_params &p, as_region_buf &rb,
+               int32_t *attr, hipStream_t s) {
+    const int64_t P = (int64_t)W * H;
+    uint8_t *B = sc.B;
+    uint8_t *keep = sc.keep;
+    int32_t *label = sc.label;
+    int64_t *kidx = sc.kidx;
+    unsigned long long *mom = sc.mom;
     const unsigned grid = (unsigned)((P + 255) / 256);
     const int tiles_x = (W + ET - 1) / ET, tiles = tiles_x * ((H + ET - 1) / ET);
 
@@ -514,7 +609,7 @@ as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const ui
     hipLaunchKernelGGL(k_region_slots, dim3(1), dim3(1024), 0, s, kidx, (int64_t)grid, rb.count);
     hipLaunchKernelGGL(k_region_emit, dim3(grid), dim3(256), 0, s, W, H, view, mom, keep, kidx, dom, B, gt,
                        rb.records, rb.capacity);
-    return AS_OK;
 }
+}  // namespace
 
 AS_WARM_KERNEL(errstats)

@@ -282,6 +282,14 @@ hipError_t errstats_reserve(as_ctx *ctx, int64_t max_pixels);
 as_status run_error_stats(as_ctx *ctx, int W, int H, const double *err, const uint64_t *minmax, const int32_t *dom,
                           const float *gt, int view, int64_t n, const uint8_t *is_cand, const as_split_params &p,
                           as_region_buf &rb, int32_t *attr, hipStream_t s);
+// The no-allocation variant: scratch from a static device array whose address
+// on each device errstats_noalloc_init records (called by as_ctx_create with
+// the device current).
+hipError_t errstats_noalloc_init(int device);
+size_t errstats_noalloc_bytes();
+as_status run_error_stats_noalloc(as_ctx *ctx, int W, int H, const double *err, const uint64_t *minmax,
+                                  const int32_t *dom, const float *gt, int view, const uint8_t *is_cand,
+                                  const as_split_params &p, as_region_buf &rb, int32_t *attr, hipStream_t s);
 
 // adaptive split (split.hip)
 // Random children per candidate the variant may draw noise for.
