@@ -106,7 +106,8 @@ __device__ __forceinline__ void stage(const Fetched &f, int ox, int oy, StagedRe
 // FP32, with an error below 5 ulp of the sum of the terms' magnitudes; inside
 // the ellipse that sum is at most 4 t / (1 - rho^2) (rho^2 = R^2 / (P S), t
 // <= 8), so the threshold is raised by 2e-5 (1 + 1 / (1 - rho^2)), above that
-// bound, and the extents below are padded for their own rounding.  Every
+// bound, and the extents below (FP32, hardware reciprocal and square root,
+// each within a few ulp) are padded for their own rounding.  Every
 // pixel the kernels can take as a contributor therefore lies in a block whose
 // bit is set; a block skipped holds no contributor, so the outputs are those
 // of the box test alone.
@@ -130,20 +131,26 @@ __device__ __forceinline__ uint32_t block_mask(const StagedRec &sr, bool ellipse
     const uint32_t box16 = rspread * cb;   // cb copied into the nibble of every row block
     if (!ellipse || box16 == 0u) return box16;
     const float P = -sr.mc.z, R = -0.5f * sr.mc.w, S = -sr.cc.x, L = sr.cc.y;
-    const double det = (double)P * (double)S - (double)R * (double)R;   // products exact in FP64
-    if (!(P > 0.f) || !(S > 0.f) || !(det > 0.0)) return box16;
-    const float inv_omr = (float)(((double)P * (double)S) / det);       // 1 / (1 - rho^2) >= 1
-    const float t = L + 7.99435343685886f + 2e-5f * (1.0f + inv_omr);
+    if (!(P > 0.f) || !(S > 0.f)) return box16;
+    // 1 - rho^2 from FP32 products: its absolute error is below 4u, so it is
+    // lowered by 5e-7 (8.4u); det = P S (1 - rho^2) then errs low, which only
+    // widens the extents below
+    const float PS = P * S;
+    const float omr = (1.0f - (R * R) * __builtin_amdgcn_rcpf(PS)) - 5e-7f;
+    if (!(omr > 1e-6f)) return box16;       // (near-)degenerate ellipse: the box's blocks
+    const float t = L + 7.99435343685886f + 2e-5f * (1.0f + __builtin_amdgcn_rcpf(omr));
     if (!(t > 0.f)) return t <= 0.f ? 0u : box16;
-    const float detf = (float)det, iP = 1.0f / P;
-    const float hx = sqrtf(t * S / detf), hy = sqrtf(t * P / detf);
+    const float det = PS * omr, idet = __builtin_amdgcn_rcpf(det), iP = __builtin_amdgcn_rcpf(P);
+    const float hx = __builtin_amdgcn_sqrtf(t * S * idet), hy = __builtin_amdgcn_sqrtf(t * P * idet);
     if (!(hx < 1e6f) || !(hy < 1e6f)) return box16;
-    const float kc = -R * iP, u = t * iP, e = detf * iP * iP;
-    const float dyL = R * hx / S;           // leftmost point's dy; the rightmost is at -dyL
+    const float kc = -R * iP, u = t * iP, e = det * iP * iP;
+    const float dyL = R * hx * __builtin_amdgcn_rcpf(S);   // leftmost point's dy; the rightmost is at -dyL
     const float hyp = hy * (1.0f + 1e-5f) + 1e-3f;
     const float padx = 1e-3f + 4e-5f * hx;
     const float slack = 1e-5f * u;          // keeps rounding in u - e y^2 from narrowing the band
-    auto edge = [&](float y, float sgn) { return kc * y + sgn * sqrtf(fmaxf(0.f, u - e * y * y + slack)); };
+    auto edge = [&](float y, float sgn) {
+        return kc * y + sgn * __builtin_amdgcn_sqrtf(fmaxf(0.f, u - e * y * y + slack));
+    };
     uint32_t ell = 0u;
 #pragma unroll
     for (int b = 0; b < 4; b++) {
@@ -516,8 +523,7 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
                                                          const uint32_t *__restrict__ last_in,
                                                          const uint32_t *__restrict__ ncontrib_in,
                                                          const ViewImagesC dLs, float *__restrict__ grad2d,
-                                                         const uint16_t *__restrict__ bm_in, int ellipse,
-                                                         uint32_t *queue) {
+                                                         const uint16_t *__restrict__ bm_in, uint32_t *queue) {
     constexpr int R = BATCH / BWD_BLOCK;
     __shared__ BwdShared<BATCH> sh;
     __shared__ uint32_t s_next;
@@ -602,9 +608,9 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
         for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
 
         // batches [b0, b1) walk the segment backwards from its end
-        // block masks come from the forward (bm_in) or, in frames without
-        // that buffer, are recomputed here; both are the same function of the
-        // staged record, and any conservative mask gives the same outputs
+        // block masks come from the forward (bm_in); frames without that
+        // buffer take the box's blocks (any mask that keeps every block
+        // holding a contributor gives the same outputs)
         Fetched nf[R];
         uint16_t nbm[R];
         {
@@ -625,7 +631,7 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
                 if (b0 + t < b1) {
                     const StagedRec sr = make_staged(nf[k], ox, oy);
                     sh.rec[t] = sr;
-                    sh.bm[t] = bm_in ? nbm[k] : (uint16_t)block_mask(sr, ellipse != 0);
+                    sh.bm[t] = bm_in ? nbm[k] : (uint16_t)block_mask(sr, false);
                 }
                 if (n0 + t < n1) {
                     fetch(vals, rec, box, n0 + t, nf[k]);
@@ -1007,8 +1013,7 @@ void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         }                                                                                                          \
         hipLaunchKernelGGL((k_blend_bwd<B, PER>), dim3(grid), dim3(BWD_BLOCK), 0, s, f->ranges, f->bwd_items,     \
                            f->n_items, f->tile_hi, ckp, seg_len, vals, f->rec, b4, vt, f->t_final, f->last,        \
-                           f->n_contrib, dL_dimage, grad2d, f->bm_written ? f->bmask : nullptr, bl.ellipse,        \
-                           f->queue + 1);                                                                          \
+                           f->n_contrib, dL_dimage, grad2d, f->bm_written ? f->bmask : nullptr, f->queue + 1);    \
     } while (0)
     // the reverse pass stages half the forward's depth: two waves per tile
     if (bl.persistent) {
