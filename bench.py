@@ -259,7 +259,46 @@ def densify_bench(ctx):
         torch.cuda.synchronize()
         variants[name] = dict(split_ms=round((time.perf_counter() - tv) * 1e3 / reps, 3),
                               new_rows=int(r[2].sum().item()), n_out=int(r[4].item()))
+    # the full density-control step (select, the 16 views' renders and error
+    # statistics, clone, split, row map, prune, moment gather) with every count
+    # on the device, run eagerly and replayed as one HIP graph; selection by
+    # rank: the gradient threshold is the n/20-th largest view-averaged
+    # gradient, and every selected Gaussian is a split candidate
+    from paper_2605_06876_amd import densify as dens
+    a64 = (g2d.double() / vis.clamp(min=1).double()).cpu().numpy()
+    thr = float(np.sort(a64)[::-1][n // 20 - 1])
+    m0, v0 = api.Gaussians.empty(n, 3), api.Gaussians.empty(n, 3)
+    step = dens.DensifyStep(ctx, n, 3, "adpsplit", params, views, gts, regions, cand_cap=n // 20 + 1024,
+                            key_cap_per_entry=16)
+    step.noise.copy_(torch.from_numpy(synth.vanilla_noise(step.cc, 5, step.noise_n)).view_as(step.noise))
+    sargs = (g, m0, v0, g2d, vis, thr, 0.0, 0.005, 0.0)
+    step.run(*sargs)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(reps):
+        step.run(*sargs)
+    torch.cuda.synchronize()
+    step_eager_ms = (time.perf_counter() - ts) * 1e3 / reps
+    eager_n = int(step.n_out.item())
+    gs = torch.cuda.Stream()
+    graph = step.capture(gs, *sargs)
+    graph.launch(gs)
+    gs.synchronize()
+    tg = time.perf_counter()
+    for _ in range(reps):
+        graph.launch(gs)
+    gs.synchronize()
+    step_graph_ms = (time.perf_counter() - tg) * 1e3 / reps
+    if int(step.n_out.item()) != eager_n:
+        raise RuntimeError("bench: graph replay of the density-control step differs from the eager step")
+    full_step = dict(ms_eager=round(step_eager_ms, 3), ms_graph=round(step_graph_ms, 3),
+                     candidates=int(step.sel[3].item()), n_out=eager_n,
+                     note="select + 16 batched renders with error statistics + clone + split + row map + prune + "
+                          "moment gather, counts on the device")
+    graph.close()
+    step.close()
     return dict(ms=(t1 - t0) * 1e3 / reps, ms_batched_views=round(batched_ms, 3), n=n, views=V, candidates=len(cand),
+                full_step=full_step,
                 regions=int(regions.count.item()),
                 new_rows=int(res[2].sum().item()), n_out=int(res[4].item()),
                 modes=dict(vanilla=int((mode == 0).sum()), reset=int((mode == 1).sum()), adaptive=int((mode == 2).sum())),

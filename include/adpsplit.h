@@ -61,6 +61,10 @@ typedef struct {
     const float *means, *log_scales, *quats, *opacity_logits, *sh;
     int64_t n;
     int32_t sh_degree;
+    const int64_t *n_dev;   /* NULL, or device [1]: the rows in use (<= n; n is then the row stride and the
+                               capacity).  Taken by the densification calls (as_clone_prune,
+                               as_adaptive_split, as_gather_rows) so that a step's row count never
+                               travels to the host; every other call refuses it (AS_ERR_ARG) */
 } as_gaussians;
 
 typedef struct {
@@ -369,6 +373,11 @@ as_status as_accumulate_error_stats_noalloc(as_ctx *ctx, int32_t width, int32_t 
  *   n_out      : out [1] device; the new set is the non-removed Gaussians in
  *                order, then one block per candidate in ascending id order
  *                (children by descending extent, then the parent copy).
+ *   n_cand_dev : NULL, or device [1]: the candidates in use (<= n_cand, which is
+ *                then the capacity of cand, mode, count and offset; entries past
+ *                it get mode 0 and count 0).  With g->n_dev as well, nothing of the
+ *                call depends on a count the host has not set, so it can follow
+ *                as_densify_select and as_clone_prune inside one graph capture.
  * Returns AS_ERR_CAPACITY when out->n is below the bound above, or when the
  * region capacity, n_cand, n_views or g->n exceed the context's reservation
  * (max_regions, max_candidates, max_views, max_gaussians); allocates nothing. */
@@ -376,7 +385,7 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
                             const as_region_buf *regions, const as_camera *views, int32_t n_views,
                             const int32_t *attr_count, const as_split_params *params, const float *noise,
                             as_gaussians_mut *out, uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out,
-                            void *stream);
+                            const int64_t *n_cand_dev, void *stream);
 
 /* ---- the optimisation loop around the path -------------------------------------- */
 /* The split runs inside 3DGS's training loop (Sec. 3: adaptive density
@@ -431,9 +440,13 @@ as_status as_densify_select(as_ctx *ctx, const as_gaussians *g, const float *g2d
  * mode is RESET (1).  state_in composes maps across successive steps.
  *   cand, mode: [n_cand] as passed to / returned by as_adaptive_split
  *   state_in: NULL or [n]
- *   row_src: out [capacity]; rows past the survivors are -1. */
+ *   row_src: out [capacity]; rows past the survivors are -1.
+ *   n_dev, n_cand_dev: NULL, or device [1] counts of the input rows and of the
+ *   candidates in use (n and n_cand are then capacities), as for
+ *   as_adaptive_split. */
 as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t n_cand, const uint8_t *mode,
-                           const int32_t *state_in, int32_t *row_src, int64_t capacity, void *stream);
+                           const int32_t *state_in, int32_t *row_src, int64_t capacity, const int64_t *n_dev,
+                           const int64_t *n_cand_dev, void *stream);
 
 /* Clone and prune (3DGS adaptive density control): Gaussian i is kept when
  * sigmoid(opacity_logit) >= min_opacity and, if max_scale > 0,
@@ -441,19 +454,20 @@ as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t 
  * kept rows in order, then a copy of every kept row with clone_mask set, in
  * order.  state_src[r] = state_in[i] (or i when state_in is NULL) for the kept
  * copy of row i and -1 for a clone (a clone starts with fresh optimiser state).
- *   g: n rows; clone_mask, state_in: NULL or [n]
+ *   g: n rows (or *g->n_dev of a capacity of n); clone_mask, state_in: NULL or [n]
  *   out: capacity rows (row stride out->n; n + clones always suffices)
  *   state_src: out [capacity]; n_out: out device [1].
- * AS_ERR_CAPACITY when out->n < g->n. */
+ * AS_ERR_CAPACITY when out->n < 2 g->n with a clone mask, or < g->n without. */
 as_status as_clone_prune(as_ctx *ctx, const as_gaussians *g, const uint8_t *clone_mask, const int32_t *state_in,
                          double min_opacity, double max_scale, as_gaussians_mut *out, int32_t *state_src,
                          int64_t *n_out, void *stream);
 
 /* dst row r = src row map[r] for map[r] >= 0, zeros for map[r] = -1 (carries
  * optimiser state across a densification).  src: rows with stride src->n;
- * dst: n_rows rows with stride dst->n >= n_rows; the same SH degree. */
+ * dst: n_rows rows with stride dst->n >= n_rows; the same SH degree.
+ * n_rows_dev: NULL, or device [1]: the rows to write (<= n_rows, a capacity). */
 as_status as_gather_rows(as_ctx *ctx, const as_gaussians *src, const int32_t *map, int64_t n_rows,
-                         as_gaussians_mut *dst, void *stream);
+                         as_gaussians_mut *dst, const int64_t *n_rows_dev, void *stream);
 
 /* Opacity reset of 3DGS's density control: opacity <- min(opacity,
  * max_opacity), in logit space, and the Adam moments of the opacities (m_op,

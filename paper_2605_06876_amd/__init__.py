@@ -9,7 +9,7 @@ __version__ = "0.1.0"
 
 
 def __getattr__(name):
-    if name in ("api", "synth", "autograd", "autotune", "serve", "train", "sweep"):
+    if name in ("api", "synth", "autograd", "autotune", "serve", "train", "sweep", "densify"):
         import importlib
         return importlib.import_module("." + name, __name__)
     raise AttributeError(name)

@@ -38,7 +38,21 @@ class _Camera(ctypes.Structure):
 class _Gaussians(ctypes.Structure):
     _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
                 ("opacity_logits", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("sh_degree", ctypes.c_int32), ("n_dev", ctypes.c_void_p)]
+
+
+class _GaussiansMut(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacity_logits", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n", ctypes.c_int64),
                 ("sh_degree", ctypes.c_int32)]
+
+    @staticmethod
+    def of(g):
+        m = _GaussiansMut()
+        m.means, m.log_scales, m.quats = _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats)
+        m.opacity_logits, m.sh = _ptr(g.opacity_logits), _ptr(g.sh)
+        m.n, m.sh_degree = int(g.means.shape[1]), g.sh_degree
+        return m
 
 
 class _SplitParams(ctypes.Structure):
@@ -173,9 +187,15 @@ class Gaussians:
 
     FIELDS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
-    def __init__(self, means, log_scales, quats, opacity_logits, sh, sh_degree):
+    def __init__(self, means, log_scales, quats, opacity_logits, sh, sh_degree, n_dev=None):
         self.means, self.log_scales, self.quats = means, log_scales, quats
         self.opacity_logits, self.sh, self.sh_degree = opacity_logits, sh, int(sh_degree)
+        # optional device [1] int64: the rows in use (n is then the capacity)
+        self.n_dev = n_dev
+
+    def counted(self, n_dev):
+        """The same buffers with a device row count (for the densification calls)."""
+        return Gaussians(self.means, self.log_scales, self.quats, self.opacity_logits, self.sh, self.sh_degree, n_dev)
 
     @property
     def n(self):
@@ -198,7 +218,7 @@ class Gaussians:
 
     def struct(self):
         return _Gaussians(_ptr(self.means), _ptr(self.log_scales), _ptr(self.quats), _ptr(self.opacity_logits),
-                          _ptr(self.sh), self.n, self.sh_degree)
+                          _ptr(self.sh), self.n, self.sh_degree, _ptr(self.n_dev))
 
     def rows(self, n):
         """First n rows (views with the full row stride are not contiguous, so copy)."""
@@ -534,16 +554,6 @@ class Graph:
             pass
 
 
-class _GaussiansMut(_Gaussians):
-    @staticmethod
-    def of(g):
-        m = _GaussiansMut()
-        m.means, m.log_scales, m.quats = _ptr(g.means), _ptr(g.log_scales), _ptr(g.quats)
-        m.opacity_logits, m.sh = _ptr(g.opacity_logits), _ptr(g.sh)
-        m.n, m.sh_degree = int(g.means.shape[1]), g.sh_degree
-        return m
-
-
 def error_map(ctx, image, gt, err=None, err_minmax=None, stream=None):
     """as_error_map: FP64 L1 error map and its min/max bit patterns."""
     H, W = image.shape[1], image.shape[2]
@@ -608,9 +618,11 @@ def accumulate_error_stats_noalloc(ctx, width, height, err, err_minmax, dom, gt,
 
 
 def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=None, mode=None, count=None,
-                   offset=None, n_out=None, stream=None):
+                   offset=None, n_out=None, n_cand_dev=None, stream=None):
     """as_adaptive_split.  Returns (out Gaussians with capacity rows, mode,
-    count, offset, n_out tensor); outputs not passed are allocated here."""
+    count, offset, n_out tensor); outputs not passed are allocated here.
+    n_cand_dev: optional device count of the candidates in use (cand's length
+    is then a capacity)."""
     nc = int(cand.shape[0])
     if out is None:
         cap = g.n + nc * max(2, params.n_max + 1, params.fixed_n if params.variant == VARIANT_FIXED_N else 0)
@@ -631,7 +643,7 @@ def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=
     _check(lib().as_adaptive_split(ctx.handle, ctypes.byref(gs), _ptr(cand) if nc else None, ctypes.c_int64(nc),
                                    ctypes.byref(rb), cams, ctypes.c_int32(len(views)), _ptr(attr_count), ctypes.byref(p),
                                    _ptr(noise) if nc else None, ctypes.byref(om), _ptr(mode) if nc else None,
-                                   _ptr(count) if nc else None, _ptr(offset) if nc else None, _ptr(n_out),
+                                   _ptr(count) if nc else None, _ptr(offset) if nc else None, _ptr(n_out), _ptr(n_cand_dev),
                                    _stream(stream)))
     return out, mode[:nc], count[:nc], offset[:nc], n_out
 
@@ -679,13 +691,17 @@ def l1_loss(ctx, image, gt, dL=None, sums=None, want_grad=True, stream=None):
     return (dL if want_grad else None), sums
 
 
-def densify_select(ctx, g, g2d_accum, vis_count, grad_threshold, size_threshold, stream=None):
-    """as_densify_select: (clone_mask u8 [n], is_candidate u8 [n], cand i32 [n] (first n_cand valid), n_cand)."""
+def densify_select(ctx, g, g2d_accum, vis_count, grad_threshold, size_threshold, out=None, stream=None):
+    """as_densify_select: (clone_mask u8 [n], is_candidate u8 [n], cand i32 [n] (first n_cand valid), n_cand);
+    out: optional preallocated (clone, is_cand, cand, n_cand) of those shapes."""
     n = g.n
-    clone = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
-    is_cand = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
-    cand = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
-    n_cand = torch.empty(1, dtype=torch.int64, device="cuda")
+    if out is None:
+        clone = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        is_cand = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        cand = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        n_cand = torch.empty(1, dtype=torch.int64, device="cuda")
+    else:
+        clone, is_cand, cand, n_cand = out
     gs = g.struct()
     _check(lib().as_densify_select(ctx.handle, ctypes.byref(gs), _ptr(g2d_accum), _ptr(vis_count),
                                    ctypes.c_double(grad_threshold), ctypes.c_double(size_threshold), _ptr(clone),
@@ -693,23 +709,31 @@ def densify_select(ctx, g, g2d_accum, vis_count, grad_threshold, size_threshold,
     return clone[:n], is_cand[:n], cand, n_cand
 
 
-def split_row_map(ctx, n, cand, mode, capacity, state_in=None, stream=None):
-    """as_split_row_map: row_src i32 [capacity]."""
+def split_row_map(ctx, n, cand, mode, capacity, state_in=None, n_dev=None, n_cand_dev=None, row_src=None,
+                  stream=None):
+    """as_split_row_map: row_src i32 [capacity] (n_dev, n_cand_dev: optional
+    device counts, n and len(cand) then being capacities)."""
     nc = int(cand.shape[0])
-    row_src = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda")
+    if row_src is None:
+        row_src = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda")
     _check(lib().as_split_row_map(ctx.handle, ctypes.c_int64(n), _ptr(cand) if nc else None, ctypes.c_int64(nc),
                                   _ptr(mode) if nc else None, _ptr(state_in), _ptr(row_src), ctypes.c_int64(capacity),
-                                  _stream(stream)))
+                                  _ptr(n_dev), _ptr(n_cand_dev), _stream(stream)))
     return row_src[:capacity]
 
 
-def clone_prune(ctx, g, clone_mask, state_in, min_opacity, max_scale, out=None, stream=None):
-    """as_clone_prune: (out Gaussians with 2 n rows of capacity, state_src i32, n_out device tensor)."""
+def clone_prune(ctx, g, clone_mask, state_in, min_opacity, max_scale, out=None, state_src=None, n_out=None,
+                stream=None):
+    """as_clone_prune: (out Gaussians with 2 n rows of capacity (n without a
+    clone mask), state_src i32, n_out device tensor).  g may carry a device row
+    count (g.counted)."""
     n = g.n
     if out is None:
-        out = Gaussians.empty(max(2 * n, 1), g.sh_degree)
-    state_src = torch.empty(max(out.n, 1), dtype=torch.int32, device="cuda")
-    n_out = torch.empty(1, dtype=torch.int64, device="cuda")
+        out = Gaussians.empty(max(2 * n if clone_mask is not None else n, 1), g.sh_degree)
+    if state_src is None:
+        state_src = torch.empty(max(out.n, 1), dtype=torch.int32, device="cuda")
+    if n_out is None:
+        n_out = torch.empty(1, dtype=torch.int64, device="cuda")
     gs = g.struct()
     om = _GaussiansMut.of(out)
     _check(lib().as_clone_prune(ctx.handle, ctypes.byref(gs), _ptr(clone_mask), _ptr(state_in),
@@ -718,14 +742,15 @@ def clone_prune(ctx, g, clone_mask, state_in, min_opacity, max_scale, out=None, 
     return out, state_src, n_out
 
 
-def gather_rows(ctx, src, row_map, n_rows, dst=None, stream=None):
-    """as_gather_rows: dst row r = src row map[r] (zeros for -1)."""
+def gather_rows(ctx, src, row_map, n_rows, dst=None, n_rows_dev=None, stream=None):
+    """as_gather_rows: dst row r = src row map[r] (zeros for -1); n_rows_dev:
+    optional device count of the rows to write (n_rows then a capacity)."""
     if dst is None:
         dst = Gaussians.empty(max(n_rows, 1), src.sh_degree)
     ss = src.struct()
     dm = _GaussiansMut.of(dst)
     _check(lib().as_gather_rows(ctx.handle, ctypes.byref(ss), _ptr(row_map) if n_rows else None,
-                                ctypes.c_int64(n_rows), ctypes.byref(dm), _stream(stream)))
+                                ctypes.c_int64(n_rows), ctypes.byref(dm), _ptr(n_rows_dev), _stream(stream)))
     return dst
 
 

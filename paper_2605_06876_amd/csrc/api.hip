@@ -59,8 +59,17 @@ bool check_mut(const as_gaussians_mut *g, int64_t rows, int32_t deg, const char 
 GaussPtrs gptrs(const as_gaussians *g) {
     GaussPtrs p;
     p.means = g->means; p.log_scales = g->log_scales; p.quats = g->quats; p.opac = g->opacity_logits; p.sh = g->sh;
-    p.n = g->n; p.deg = g->sh_degree;
+    p.n = g->n; p.deg = g->sh_degree; p.n_dev = g->n_dev;
     return p;
+}
+
+// Calls whose launches follow the host row count refuse a device count.
+bool host_count_only(const as_gaussians *g, const char *what) {
+    if (g && g->n_dev) {
+        as_set_error("%s: takes no device row count (n_dev); only the densification calls do", what);
+        return false;
+    }
+    return true;
 }
 
 GradPtrs mptrs(const as_gaussians_mut *g) {
@@ -564,7 +573,7 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     for (int v = 0; v < n_views; v++) {
         const as_gaussians *g = &scenes[v];
         const as_camera *c = &cams[v];
-        if (!check_gauss(g, "as_render")) return AS_ERR_ARG;
+        if (!check_gauss(g, "as_render") || !host_count_only(g, "as_render")) return AS_ERR_ARG;
         if (g->sh_degree != deg) { as_set_error("as_render: views mix SH degrees %d and %d", deg, g->sh_degree); return AS_ERR_ARG; }
         if (!images[v] || (gt && !gt[v])) { as_set_error("as_render: null image or target of view %d", v); return AS_ERR_ARG; }
         if (c->width < 1 || c->height < 1 || c->width > 32767 || c->height > 32767) {
@@ -684,7 +693,7 @@ static bool same_set(const GaussPtrs &a, const as_gaussians *g) {
 as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame *f, const float *const *dL_dimages,
                                    as_gaussians_mut *grads, float *g2d_norm, int32_t *vis_count, void *stream) {
     if (!ctx || !f || !dL_dimages) { as_set_error("as_render_backward: null argument"); return AS_ERR_ARG; }
-    if (!check_gauss(g, "as_render_backward")) return AS_ERR_ARG;
+    if (!check_gauss(g, "as_render_backward") || !host_count_only(g, "as_render_backward")) return AS_ERR_ARG;
     if (!f->has_render) { as_set_error("as_render_backward: the frame holds no render"); return AS_ERR_STATE; }
     const ViewTable &vt = f->vt;
     for (int v = 0; v < vt.n_views; v++) {
@@ -801,7 +810,7 @@ as_status as_densify_select(as_ctx *ctx, const as_gaussians *g, const float *g2d
                             int32_t *cand, int64_t *n_cand, void *stream) {
     const char *what = "as_densify_select";
     if (!ctx) { as_set_error("%s: null context", what); return AS_ERR_ARG; }
-    if (!check_gauss(g, what)) return AS_ERR_ARG;
+    if (!check_gauss(g, what) || !host_count_only(g, what)) return AS_ERR_ARG;
     if (!n_cand || (g->n > 0 && (!g2d_accum || !vis_count || !clone_mask || !is_candidate || !cand))) {
         as_set_error("%s: null argument", what);
         return AS_ERR_ARG;
@@ -821,7 +830,8 @@ as_status as_densify_select(as_ctx *ctx, const as_gaussians *g, const float *g2d
 }
 
 as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t n_cand, const uint8_t *mode,
-                           const int32_t *state_in, int32_t *row_src, int64_t capacity, void *stream) {
+                           const int32_t *state_in, int32_t *row_src, int64_t capacity, const int64_t *n_dev,
+                           const int64_t *n_cand_dev, void *stream) {
     const char *what = "as_split_row_map";
     if (!ctx || n < 0 || n_cand < 0 || capacity < n || (n_cand > 0 && (!cand || !mode)) || (capacity > 0 && !row_src)) {
         as_set_error("%s: bad argument (n %lld, candidates %lld, capacity %lld)", what, (long long)n, (long long)n_cand,
@@ -835,8 +845,8 @@ as_status as_split_row_map(as_ctx *ctx, int64_t n, const int32_t *cand, int64_t 
     if (n == 0) return launch_status(what);
     uint8_t *keep = (uint8_t *)ctx->tr[TR_FLAG].p;
     int64_t *pos = (int64_t *)ctx->tr[TR_SCAN].p;
-    launch_fill_u8(keep, 1, n, s);
-    launch_mark_kept(cand, n_cand, mode, n, keep, s);
+    launch_keep_init(n, n_dev, keep, s);
+    launch_mark_kept(cand, n_cand, n_cand_dev, mode, n, keep, s);
     scan_u8_to_i64(keep, pos, n, (int64_t *)ctx->tr[TR_TOT].p, ctx->tr[TR_TMP].p, s);
     launch_row_map(n, keep, pos, state_in, capacity, row_src, s);
     return launch_status(what);
@@ -849,12 +859,12 @@ as_status as_clone_prune(as_ctx *ctx, const as_gaussians *g, const uint8_t *clon
     if (!ctx) { as_set_error("%s: null context", what); return AS_ERR_ARG; }
     if (!check_gauss(g, what)) return AS_ERR_ARG;
     if (!out || !state_src || !n_out) { as_set_error("%s: null output", what); return AS_ERR_ARG; }
-    if (out->n < 2 * g->n) {
-        as_set_error("%s: output capacity %lld < 2 x %lld rows (every row may be cloned)", what, (long long)out->n,
-                     (long long)g->n);
+    const int64_t need = clone_mask ? 2 * g->n : g->n;   // every row may be cloned
+    if (out->n < need) {
+        as_set_error("%s: output capacity %lld < %lld rows", what, (long long)out->n, (long long)need);
         return AS_ERR_CAPACITY;
     }
-    if (!check_mut(out, 2 * g->n, g->sh_degree, what)) return AS_ERR_ARG;
+    if (!check_mut(out, need, g->sh_degree, what)) return AS_ERR_ARG;
     if (g->n > 0 && (out->means == g->means || out->sh == g->sh)) { as_set_error("%s: output aliases the input", what); return AS_ERR_ARG; }
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = g->n, m = n > 0 ? n : 1;
@@ -874,11 +884,11 @@ as_status as_clone_prune(as_ctx *ctx, const as_gaussians *g, const uint8_t *clon
 }
 
 as_status as_gather_rows(as_ctx *ctx, const as_gaussians *src, const int32_t *map, int64_t n_rows,
-                         as_gaussians_mut *dst, void *stream) {
+                         as_gaussians_mut *dst, const int64_t *n_rows_dev, void *stream) {
     const char *what = "as_gather_rows";
     if (!ctx || n_rows < 0 || !check_gauss(src, what) || (n_rows > 0 && !map)) { as_set_error("%s: bad argument", what); return AS_ERR_ARG; }
     if (!check_mut(dst, n_rows, src->sh_degree, what)) return AS_ERR_ARG;
-    launch_gather_rows(*src, map, n_rows, *dst, (hipStream_t)stream);
+    launch_gather_rows(*src, map, n_rows, n_rows_dev, *dst, (hipStream_t)stream);
     return launch_status(what);
 }
 
@@ -939,7 +949,7 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
                             const as_region_buf *regions, const as_camera *views, int32_t n_views,
                             const int32_t *attr_count, const as_split_params *params, const float *noise,
                             as_gaussians_mut *out, uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out,
-                            void *stream) {
+                            const int64_t *n_cand_dev, void *stream) {
     if (!ctx || !regions || !regions->records || !regions->count || !attr_count || !n_out || n_cand < 0 ||
         n_views < 0 || (n_views > 0 && !views)) {
         as_set_error("as_adaptive_split: bad argument");
@@ -971,7 +981,8 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
     as_status st;
     {
         StageTimer t(ctx, AS_STAGE_SPLIT, (hipStream_t)stream);
-        st = run_adaptive_split(ctx, gptrs(g), cand, n_cand, *regions, views, n_views, attr_count, *params, noise,
+        st = run_adaptive_split(ctx, gptrs(g), cand, n_cand, n_cand_dev, *regions, views, n_views, attr_count, *params,
+                                noise,
                                 mptrs(out), out->n, mode, count, offset, n_out, (hipStream_t)stream);
     }
     if (st != AS_OK) return st;

@@ -42,8 +42,9 @@ static inline DevCam to_devcam(const as_camera &c) {
 
 struct GaussPtrs {
     const float *means, *log_scales, *quats, *opac, *sh;
-    int64_t n;
+    int64_t n;               // row stride (and capacity when n_dev is set)
     int32_t deg;
+    const int64_t *n_dev;    // NULL, or device [1]: the rows in use (<= n)
 };
 
 struct GradPtrs {
@@ -260,7 +261,9 @@ void launch_l1(int W, int H, const float *img, const float *gt, float *dL, doubl
 void launch_select(const as_gaussians &g, const float *accum, const int32_t *vis, double thr, double size_thr,
                    uint8_t *clone, uint8_t *cand_flag, hipStream_t s);
 void launch_compact_ids(int64_t n, const uint8_t *flag, const int64_t *scan, int32_t *out, hipStream_t s);
-void launch_mark_kept(const int32_t *cand, int64_t n_cand, const uint8_t *mode, int64_t n, uint8_t *keep, hipStream_t s);
+void launch_keep_init(int64_t n, const int64_t *n_dev, uint8_t *keep, hipStream_t s);
+void launch_mark_kept(const int32_t *cand, int64_t n_cand, const int64_t *n_cand_dev, const uint8_t *mode, int64_t n,
+                      uint8_t *keep, hipStream_t s);
 void launch_row_map(int64_t n, const uint8_t *keep, const int64_t *pos, const int32_t *state_in, int64_t capacity,
                     int32_t *row_src, hipStream_t s);
 void launch_prune_flags(const as_gaussians &g, const uint8_t *clone_mask, double min_op, double max_scale,
@@ -269,8 +272,8 @@ void launch_clone_prune_write(const as_gaussians &g, const as_gaussians_mut &out
                               const uint8_t *dup, const int64_t *kpos, const int64_t *dpos, const int64_t *n_keep,
                               const int64_t *n_dup, const int32_t *state_in, int32_t *state_src, int64_t *n_out,
                               hipStream_t s);
-void launch_gather_rows(const as_gaussians &src, const int32_t *map, int64_t n_rows, const as_gaussians_mut &dst,
-                        hipStream_t s);
+void launch_gather_rows(const as_gaussians &src, const int32_t *map, int64_t n_rows, const int64_t *n_rows_dev,
+                        const as_gaussians_mut &dst, hipStream_t s);
 void launch_reset_opacity(const as_gaussians_mut &g, float cap, float *m, float *v, hipStream_t s);
 
 // error statistics (errstats.hip)
@@ -303,6 +306,7 @@ static inline int split_noise_need(const as_split_params &p) {
 size_t split_reserve_bytes(const as_reserve &r);
 hipError_t split_reserve(as_ctx *ctx, const as_reserve &r);
 as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *cand, int64_t n_cand,
+                             const int64_t *n_cand_dev,
                              const as_region_buf &rb, const as_camera *views, int n_views, const int32_t *attr,
                              const as_split_params &p, const float *noise, GradPtrs out, int64_t out_cap,
                              uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out, hipStream_t s);
@@ -333,6 +337,15 @@ void as_set_error(const char *fmt, ...);
 // ---- device helpers -----------------------------------------------------------------
 
 #ifdef __HIPCC__
+// Rows of a Gaussian set in use, and the entries of a capacity-sized list in
+// use: the device count when one is given (at most the capacity), else the
+// host size.
+__device__ __forceinline__ int64_t count_in_use(int64_t cap, const int64_t *dev) {
+    if (!dev) return cap;
+    const int64_t c = *dev;
+    return c < 0 ? 0 : (c < cap ? c : cap);
+}
+__device__ __forceinline__ int64_t rows_in_use(const GaussPtrs &g) { return count_in_use(g.n, g.n_dev); }
 __device__ __forceinline__ float wave_sum(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;

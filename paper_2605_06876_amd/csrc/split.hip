@@ -245,12 +245,13 @@ __global__ void k_reg_keys(const as_region *__restrict__ recs, const uint32_t *_
 
 __global__ void k_cand_ranges(const as_region *__restrict__ recs, const uint32_t *__restrict__ order,
                               const uint32_t *__restrict__ n32, int64_t cap, const int32_t *__restrict__ cand,
-                              int64_t n_cand, int64_t *__restrict__ rs, int64_t *__restrict__ re) {
+                              int64_t n_cand, const int64_t *__restrict__ n_cand_dev, int64_t *__restrict__ rs,
+                              int64_t *__restrict__ re) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t R = *n32;
     if (i >= cap || i >= R) return;
     const int32_t c = recs[order[i]].cand;
-    const int64_t ci = find_cand(cand, n_cand, c);
+    const int64_t ci = find_cand(cand, count_in_use(n_cand, n_cand_dev), c);
     if (ci < 0) return;
     if (i == 0 || recs[order[i - 1]].cand != c) rs[ci] = i;
     if (i == R - 1 || recs[order[i + 1]].cand != c) re[ci] = i + 1;
@@ -258,15 +259,16 @@ __global__ void k_cand_ranges(const as_region *__restrict__ recs, const uint32_t
 
 __global__ void k_propose(GaussPtrs g, const as_region *__restrict__ recs, const uint32_t *__restrict__ order,
                           const uint32_t *__restrict__ n32, int64_t cap, const int32_t *__restrict__ cand,
-                          int64_t n_cand, const DevCam *__restrict__ cams, int n_views, double eps,
-                          Prop *__restrict__ props) {
+                          int64_t n_cand, const int64_t *__restrict__ n_cand_dev, const DevCam *__restrict__ cams,
+                          int n_views, double eps, Prop *__restrict__ props) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cap || i >= (int64_t)*n32) return;
     const as_region r = recs[order[i]];
     Prop p;
     p.ok = 0;
     p.view = r.view;
-    if (find_cand(cand, n_cand, r.cand) >= 0 && r.view >= 0 && r.view < n_views && r.cand < g.n) {
+    if (find_cand(cand, count_in_use(n_cand, n_cand_dev), r.cand) >= 0 && r.view >= 0 && r.view < n_views &&
+        r.cand < rows_in_use(g)) {
         Parent par;
         load_parent(g, r.cand, par);
         make_proposal(par, r, cams[r.view], eps, p);
@@ -303,6 +305,7 @@ __device__ __forceinline__ void uf_unite(int32_t *L, int32_t a, int32_t b) {
 
 // One wave per candidate.
 __global__ void __launch_bounds__(256) k_merge(GaussPtrs g, const int32_t *__restrict__ cand, int64_t n_cand,
+                                               const int64_t *__restrict__ n_cand_dev,
                                                const int32_t *__restrict__ attr, const int64_t *__restrict__ rs_a,
                                                const int64_t *__restrict__ re_a, const Prop *__restrict__ props,
                                                int32_t *__restrict__ uf_all, int32_t *__restrict__ root_all,
@@ -313,6 +316,14 @@ __global__ void __launch_bounds__(256) k_merge(GaussPtrs g, const int32_t *__res
     const int lane = threadIdx.x & 63;
     const int64_t ci = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ci >= n_cand) return;
+    if (ci >= count_in_use(n_cand, n_cand_dev)) {   // capacity past the candidates in use: no rows
+        if (lane == 0) {
+            mode[ci] = 0;
+            count[ci] = 0;
+            nkept[ci] = 0;
+        }
+        return;
+    }
     if (variant == AS_VARIANT_FIXED_N) {   // the random split with a fixed N, whatever the regions say
         if (lane == 0) {
             mode[ci] = 3;
@@ -439,17 +450,17 @@ __global__ void __launch_bounds__(256) k_merge(GaussPtrs g, const int32_t *__res
     }
 }
 
-__global__ void k_mark_removed(const int32_t *__restrict__ cand, int64_t n_cand, const uint8_t *__restrict__ mode,
-                               uint8_t *__restrict__ removed) {
+__global__ void k_mark_removed(const int32_t *__restrict__ cand, int64_t n_cand, const int64_t *__restrict__ n_cand_dev,
+                               const uint8_t *__restrict__ mode, uint8_t *__restrict__ removed) {
     const int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ci >= n_cand) return;
+    if (ci >= count_in_use(n_cand, n_cand_dev)) return;
     if (mode[ci] != 1) removed[cand[ci]] = 1;
 }
 
 __global__ void k_copy_survivors(GaussPtrs g, const uint8_t *__restrict__ removed,
                                  const int64_t *__restrict__ rem_prefix, GradPtrs out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.n || removed[i]) return;
+    if (i >= rows_in_use(g) || removed[i]) return;
     const int64_t n = g.n, os = out.stride;
     const int64_t d = i - rem_prefix[i];
     const int nk = (g.deg + 1) * (g.deg + 1);
@@ -471,16 +482,16 @@ __device__ __forceinline__ void copy_row(const GaussPtrs &g, int64_t src, GradPt
 }
 
 __global__ void k_write_children(GaussPtrs g, const int32_t *__restrict__ cand, int64_t n_cand,
-                                 const uint8_t *__restrict__ mode, const int64_t *__restrict__ offset,
+                                 const int64_t *__restrict__ n_cand_dev, const uint8_t *__restrict__ mode, const int64_t *__restrict__ offset,
                                  const int64_t *__restrict__ tot, const int64_t *__restrict__ rs_a,
                                  const Group *__restrict__ grp_all, const int32_t *__restrict__ kept_all,
                                  const int32_t *__restrict__ nkept, const int32_t *__restrict__ count,
                                  const float *__restrict__ noise, int noise_n, double eta, uint32_t flags,
                                  GradPtrs out, int64_t *__restrict__ n_out) {
     const int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n_surv = g.n - tot[0];
+    const int64_t n_surv = rows_in_use(g) - tot[0];
     if (ci == 0) *n_out = n_surv + tot[1];
-    if (ci >= n_cand) return;
+    if (ci >= count_in_use(n_cand, n_cand_dev)) return;
     const int64_t base = n_surv + offset[ci];
     const int32_t id = cand[ci];
     const uint8_t md = mode[ci];
@@ -579,7 +590,7 @@ hipError_t split_reserve(as_ctx *ctx, const as_reserve &r) {
 }
 
 as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *cand, int64_t n_cand,
-                             const as_region_buf &rb, const as_camera *views, int n_views, const int32_t *attr,
+                             const int64_t *n_cand_dev, const as_region_buf &rb, const as_camera *views, int n_views, const int32_t *attr,
                              const as_split_params &p, const float *noise, GradPtrs out, int64_t out_cap,
                              uint8_t *mode, int32_t *count, int64_t *offset, int64_t *n_out, hipStream_t s) {
     (void)out_cap;
@@ -631,23 +642,28 @@ as_status run_adaptive_split(as_ctx *ctx, const GaussPtrs &g, const int32_t *can
     const uint32_t *order = vals[sel];
     launch_fill_i64(rs, 0, nc1, s);
     launch_fill_i64(re, 0, nc1, s);
-    hipLaunchKernelGGL(k_cand_ranges, dim3(gcap), dim3(256), 0, s, rb.records, order, n32, cap, cand, n_cand, rs, re);
-    hipLaunchKernelGGL(k_propose, dim3(gcap), dim3(256), 0, s, g, rb.records, order, n32, cap, cand, n_cand, dcams,
+    hipLaunchKernelGGL(k_cand_ranges, dim3(gcap), dim3(256), 0, s, rb.records, order, n32, cap, cand, n_cand,
+                       n_cand_dev, rs, re);
+    hipLaunchKernelGGL(k_propose, dim3(gcap), dim3(256), 0, s, g, rb.records, order, n32, cap, cand, n_cand,
+                       n_cand_dev, dcams,
                        n_views, p.eps, props);
     if (n_cand > 0)
-        hipLaunchKernelGGL(k_merge, dim3((unsigned)((n_cand + 3) / 4)), dim3(256), 0, s, g, cand, n_cand, attr, rs,
+        hipLaunchKernelGGL(k_merge, dim3((unsigned)((n_cand + 3) / 4)), dim3(256), 0, s, g, cand, n_cand, n_cand_dev,
+                           attr, rs,
                            re, props, uf, rootof, grp, kept, nkept, p.gamma_d, p.gamma_c, p.n_max, p.variant, p.flags,
                            p.fixed_n, mode, count);
     scan_i32_to_i64(count, offset, n_cand, tot + 1, sp[SP_SCAN].p, s);
     launch_fill_u8(removed, 0, g.n > 0 ? g.n : 1, s);
     if (n_cand > 0)
         hipLaunchKernelGGL(k_mark_removed, dim3((unsigned)((n_cand + 255) / 256)), dim3(256), 0, s, cand, n_cand,
+                           n_cand_dev,
                            mode, removed);
     scan_u8_to_i64(removed, remscan, g.n, tot, sp[SP_SCAN].p, s);
     if (g.n > 0)
         hipLaunchKernelGGL(k_copy_survivors, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g, removed,
                            remscan, out);
-    hipLaunchKernelGGL(k_write_children, dim3((unsigned)((nc1 + 255) / 256)), dim3(256), 0, s, g, cand, n_cand, mode,
+    hipLaunchKernelGGL(k_write_children, dim3((unsigned)((nc1 + 255) / 256)), dim3(256), 0, s, g, cand, n_cand,
+                       n_cand_dev, mode,
                        offset, tot, rs, grp, kept, nkept, count, noise, p.noise_n ? p.noise_n : 2, p.eta, p.flags, out,
                        n_out);
     return AS_OK;

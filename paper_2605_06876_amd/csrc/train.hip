@@ -146,11 +146,19 @@ __global__ void __launch_bounds__(TB) k_compact_ids(int64_t n, const uint8_t *__
 
 // a candidate's parent stays unless its mode is RESET (1)
 __global__ void __launch_bounds__(TB) k_mark_kept(const int32_t *__restrict__ cand, int64_t n_cand,
+                                                  const int64_t *__restrict__ n_cand_dev,
                                                   const uint8_t *__restrict__ mode, int64_t n, uint8_t *__restrict__ keep) {
     const int64_t c = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (c >= n_cand) return;
+    if (c >= count_in_use(n_cand, n_cand_dev)) return;
     const int32_t id = cand[c];
     if (id >= 0 && id < n && mode[c] != 1) keep[id] = 0;
+}
+
+// keep[i] = 1 for the rows in use, 0 for the rest of the capacity
+__global__ void __launch_bounds__(TB) k_keep_init(int64_t n, const int64_t *__restrict__ n_dev,
+                                                  uint8_t *__restrict__ keep) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i < n) keep[i] = i < count_in_use(n, n_dev) ? 1 : 0;
 }
 
 __global__ void __launch_bounds__(TB) k_row_map(int64_t n, const uint8_t *__restrict__ keep,
@@ -160,13 +168,18 @@ __global__ void __launch_bounds__(TB) k_row_map(int64_t n, const uint8_t *__rest
     if (i < n && keep[i] && pos[i] < capacity) row_src[pos[i]] = state_in ? state_in[i] : (int32_t)i;
 }
 
-__global__ void __launch_bounds__(TB) k_prune_flags(int64_t n, const float *__restrict__ op,
-                                                    const float *__restrict__ ls, int64_t stride,
-                                                    const uint8_t *__restrict__ clone_mask, double min_op,
-                                                    double max_scale, uint8_t *__restrict__ keep,
+__global__ void __launch_bounds__(TB) k_prune_flags(int64_t n, const int64_t *__restrict__ n_dev,
+                                                    const float *__restrict__ op, const float *__restrict__ ls,
+                                                    int64_t stride, const uint8_t *__restrict__ clone_mask,
+                                                    double min_op, double max_scale, uint8_t *__restrict__ keep,
                                                     uint8_t *__restrict__ dup) {
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i >= n) return;
+    if (i >= count_in_use(n, n_dev)) {   // past the rows in use: neither kept nor cloned
+        keep[i] = 0;
+        dup[i] = 0;
+        return;
+    }
     const double o = 1.0 / (1.0 + exp(-(double)op[i]));
     bool k = o >= min_op;
     if (max_scale > 0.0) k = k && exp((double)max_log_scale(ls, stride, i)) <= max_scale;
@@ -202,11 +215,13 @@ __global__ void k_add_totals(const int64_t *__restrict__ a, const int64_t *__res
 }
 
 __global__ void __launch_bounds__(TB) k_gather_rows(RowSet src, int64_t src_n, const int32_t *__restrict__ map,
-                                                    int64_t n_rows, RowSet dst) {
+                                                    int64_t n_rows, const int64_t *__restrict__ n_rows_dev,
+                                                    RowSet dst) {
     const int r = blockIdx.y;
     const float *S = row_ptr(src, r);
     float *D = row_ptr(dst, r);
-    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n_rows; i += (int64_t)gridDim.x * TB) {
+    const int64_t m = count_in_use(n_rows, n_rows_dev);
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < m; i += (int64_t)gridDim.x * TB) {
         const int32_t s = map[i];
         D[i] = s >= 0 && s < src_n ? S[s] : 0.0f;
     }
@@ -265,9 +280,16 @@ void launch_compact_ids(int64_t n, const uint8_t *flag, const int64_t *scan, int
     hipLaunchKernelGGL(k_compact_ids, dim3(blocks_for(n, 1ll << 30)), dim3(TB), 0, s, n, flag, scan, out);
 }
 
-void launch_mark_kept(const int32_t *cand, int64_t n_cand, const uint8_t *mode, int64_t n, uint8_t *keep, hipStream_t s) {
+void launch_keep_init(int64_t n, const int64_t *n_dev, uint8_t *keep, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_keep_init, dim3(blocks_for(n, 1ll << 30)), dim3(TB), 0, s, n, n_dev, keep);
+}
+
+void launch_mark_kept(const int32_t *cand, int64_t n_cand, const int64_t *n_cand_dev, const uint8_t *mode, int64_t n,
+                      uint8_t *keep, hipStream_t s) {
     if (n_cand == 0) return;
-    hipLaunchKernelGGL(k_mark_kept, dim3(blocks_for(n_cand, 1ll << 30)), dim3(TB), 0, s, cand, n_cand, mode, n, keep);
+    hipLaunchKernelGGL(k_mark_kept, dim3(blocks_for(n_cand, 1ll << 30)), dim3(TB), 0, s, cand, n_cand, n_cand_dev,
+                       mode, n, keep);
 }
 
 void launch_row_map(int64_t n, const uint8_t *keep, const int64_t *pos, const int32_t *state_in, int64_t capacity,
@@ -280,8 +302,8 @@ void launch_row_map(int64_t n, const uint8_t *keep, const int64_t *pos, const in
 void launch_prune_flags(const as_gaussians &g, const uint8_t *clone_mask, double min_op, double max_scale,
                         uint8_t *keep, uint8_t *dup, hipStream_t s) {
     if (g.n == 0) return;
-    hipLaunchKernelGGL(k_prune_flags, dim3(blocks_for(g.n, 1ll << 30)), dim3(TB), 0, s, g.n, g.opacity_logits,
-                       g.log_scales, g.n, clone_mask, min_op, max_scale, keep, dup);
+    hipLaunchKernelGGL(k_prune_flags, dim3(blocks_for(g.n, 1ll << 30)), dim3(TB), 0, s, g.n, g.n_dev,
+                       g.opacity_logits, g.log_scales, g.n, clone_mask, min_op, max_scale, keep, dup);
 }
 
 void launch_clone_prune_write(const as_gaussians &g, const as_gaussians_mut &out, const uint8_t *keep,
@@ -294,11 +316,12 @@ void launch_clone_prune_write(const as_gaussians &g, const as_gaussians_mut &out
     hipLaunchKernelGGL(k_add_totals, dim3(1), dim3(64), 0, s, n_keep, n_dup, n_out);
 }
 
-void launch_gather_rows(const as_gaussians &src, const int32_t *map, int64_t n_rows, const as_gaussians_mut &dst,
-                        hipStream_t s) {
+void launch_gather_rows(const as_gaussians &src, const int32_t *map, int64_t n_rows, const int64_t *n_rows_dev,
+                        const as_gaussians_mut &dst, hipStream_t s) {
     if (n_rows == 0) return;
     const dim3 grid(blocks_for(n_rows, 1024), (unsigned)set_rows(src.sh_degree));
-    hipLaunchKernelGGL(k_gather_rows, grid, dim3(TB), 0, s, rows_of(src), src.n, map, n_rows, rows_of(dst));
+    hipLaunchKernelGGL(k_gather_rows, grid, dim3(TB), 0, s, rows_of(src), src.n, map, n_rows, n_rows_dev,
+                       rows_of(dst));
 }
 
 void launch_reset_opacity(const as_gaussians_mut &g, float cap, float *m, float *v, hipStream_t s) {

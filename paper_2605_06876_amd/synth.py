@@ -207,9 +207,9 @@ def error_map_fixture(H, W, n, seed, n_sites=400, cand_frac=0.5, empty_frac=0.05
     return img, gt, dom, is_cand
 
 
-def vanilla_noise(n_cand, seed):
-    """Standard normals for the fixed-N fallback split, [n_cand, 2, 3]."""
-    return np.random.default_rng(seed).normal(size=(n_cand, 2, 3)).astype(np.float32)
+def vanilla_noise(n_cand, seed, per=2):
+    """Standard normals for the random children of the split, [n_cand, per, 3]."""
+    return np.random.default_rng(seed).normal(size=(n_cand, per, 3)).astype(np.float32)
 
 
 def c1_inputs(seed=1001):

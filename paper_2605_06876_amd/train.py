@@ -25,7 +25,7 @@ import time
 import numpy as np
 import torch
 
-from . import api, synth
+from . import api, densify, synth
 
 
 class TrainConfig:
@@ -98,6 +98,7 @@ class Trainer:
         self._reset_state(self.g.n, fresh_moments=True)
         self.regions = api.RegionBuffer(cfg.views_per_split * W * H // cfg.split_params.m_min // 4 + 1024)
         self.history, self.densify_ms, self.split_counts = [], [], []
+        self.dstep = None
         self.train_s, self.reset_done = 0.0, False
 
     def _reset_state(self, n, fresh_moments=False):
@@ -116,20 +117,6 @@ class Trainer:
             self.frame = api.Frame(self.ctx, max(2 * n, 1), self.pb.W, self.pb.H, key_cap=32 * max(2 * n, 1))
             self.dm = self.frame.device_maps()
 
-    def _batch_frame(self, n, views):
-        """A batch frame for `views` views of n Gaussians (grown on demand)."""
-        need = n * api.MAX_VIEWS
-        if getattr(self, "bframe", None) is None or self.bframe_entries < need:
-            if getattr(self, "bframe", None) is not None:
-                self.bframe.close()
-            ent = 2 * need
-            cams = [self.pb.train_cams[0]] * api.MAX_VIEWS
-            self.bframe = api.BatchFrame.for_views(self.ctx, 2 * n, cams, key_cap=16 * ent)
-            self.bframe_entries = ent
-            self.bimages = [torch.empty(3, self.pb.H, self.pb.W, dtype=torch.float32, device="cuda")
-                            for _ in range(api.MAX_VIEWS)]
-        return self.bframe
-
     def lr_means(self, it):
         t = min(max(it / self.cfg.iters, 0.0), 1.0)
         a = 1.6e-4 * self.pb.extent
@@ -146,66 +133,36 @@ class Trainer:
         api.adam_step(ctx, self.g, self.grads, self.m, self.v, self.hp, it)
 
     def densify(self, it):
+        """One density-control step (densify.DensifyStep: every count stays on
+        the device until the step ends), then the new set's row count is read."""
         cfg, pb, ctx = self.cfg, self.pb, self.ctx
         g, n = self.g, self.g.n
-        # the densification's scratch, reserved ahead of its calls (a set-up
-        # step between iterations: the calls themselves never allocate)
-        ctx.reserve(max_gaussians=2 * n, max_candidates=max(n, 1), max_pixels=pb.W * pb.H,
-                    max_regions=self.regions.capacity, max_views=max(cfg.views_per_split, 1))
-        clone, is_cand, cand, n_cand = api.densify_select(ctx, g, self.accum, self.vis, self.thr,
-                                                          cfg.percent_dense * pb.extent)
-        nc = int(n_cand.item())
-        # 1. clones appended after the originals (no pruning yet): candidate ids stay valid
-        g1, st1, n1 = api.clone_prune(ctx, g, clone, None, 0.0, 0.0)
-        n1 = int(n1.item())
-        g1, st1 = g1.rows(n1), st1[:n1].contiguous()
-        # 2. split of the candidates
-        cand = cand[:nc].contiguous()
-        if nc > 0:
-            self._ensure_frame(n1)
-            noise = torch.from_numpy(synth.vanilla_noise(nc, int(self.rng.integers(1 << 30)))).cuda()
-            attr = torch.zeros(n1, dtype=torch.int32, device="cuda")
-            self.regions.count.zero_()
+        step = self.dstep
+        if step is None or step.n < n:   # buffers for twice the rows, kept for later steps
+            if step is not None:
+                step.close()
             if cfg.method == "adpsplit":
-                params = cfg.split_params
-                is_cand1 = torch.zeros(n1, dtype=torch.uint8, device="cuda")
-                is_cand1[:n] = is_cand
-                views = self.rng.choice(len(pb.train_cams), min(cfg.views_per_split, len(pb.train_cams)),
-                                        replace=False)
-                cams = [pb.train_cams[vi] for vi in views]
-                # the sampled views in batched launches of up to 16 views each
-                for c0 in range(0, len(views), api.MAX_VIEWS):
-                    chunk = views[c0:c0 + api.MAX_VIEWS]
-                    bf = self._batch_frame(n1, len(chunk))
-                    api.render_batch(ctx, g1, [pb.train_cams[vi] for vi in chunk], bf,
-                                     gts=[pb.train_gt[vi] for vi in chunk], images=self.bimages[:len(chunk)])
-                    for j, vi in enumerate(chunk):
-                        m = bf.device_maps(j)
-                        api.accumulate_error_stats(ctx, pb.W, pb.H, m["err"], m["err_minmax"], m["dom"],
-                                                   pb.train_gt[vi], c0 + j, is_cand1, params, self.regions, attr)
+                k = min(cfg.views_per_split, len(pb.train_cams))
+                step = densify.DensifyStep(ctx, 2 * n, self.deg, "adpsplit", cfg.split_params, pb.train_cams[:k],
+                                           pb.train_gt[:k], self.regions)
             else:
-                params = api.SplitParams(variant=api.VARIANT_FIXED_N, fixed_n=2)
-                cams = [pb.train_cams[0]]
-            out, mode, count, _, n2 = api.adaptive_split(ctx, g1, cand, self.regions, cams, attr, params, noise)
-            n2 = int(n2.item())
-            st2 = api.split_row_map(ctx, n1, cand, mode, out.n, state_in=st1)[:n2].contiguous()
-            g2 = out.rows(n2)
-            self.split_counts.append(int(count.sum().item()))
-        else:
-            g2, st2 = g1, st1
-        # 3. prune (the world-size test from the first opacity reset on)
+                step = densify.DensifyStep(ctx, 2 * n, self.deg, "vanilla")
+            self.dstep = step
+        if cfg.method == "adpsplit":
+            vi = self.rng.choice(len(pb.train_cams), len(step.views), replace=False)
+            step.set_views([pb.train_cams[k] for k in vi], [pb.train_gt[k] for k in vi])
+        step.noise.copy_(torch.from_numpy(synth.vanilla_noise(step.cc, int(self.rng.integers(1 << 30)),
+                                                              step.noise_n)).view_as(step.noise))
+        # the world-size prune from the first opacity reset on
         max_scale = cfg.max_world_scale * pb.extent if self.reset_done else 0.0
-        ctx.reserve(max_gaussians=g2.n)
-        g3, st3, n3 = api.clone_prune(ctx, g2, None, st2, cfg.min_opacity, max_scale)
-        n3 = int(n3.item())
-        self.g = g3.rows(n3)
-        st3 = st3[:n3].contiguous()
-        self.last_state_map = st3
-        # 4. Adam moments follow their rows; new rows start from zero
-        self.m = api.gather_rows(ctx, self.m, st3, n3)
-        self.v = api.gather_rows(ctx, self.v, st3, n3)
-        self._reset_state(n3)
-        return dict(it=it, n_before=n, clones=n1 - n, candidates=nc, n_after=n3)
+        step.run(g, self.m, self.v, self.accum, self.vis, self.thr, cfg.percent_dense * pb.extent, cfg.min_opacity,
+                 max_scale)
+        self.g, self.m, self.v, self.last_state_map = step.result()
+        n_cand, n_after = int(step.sel[3].item()), self.g.n
+        clones = int(step.sel[0][:n].sum().item())
+        self.split_counts.append(int(step.count[:n_cand].sum().item()) if n_cand else 0)
+        self._reset_state(n_after)
+        return dict(it=it, n_before=n, clones=clones, candidates=n_cand, n_after=n_after)
 
     def evaluate(self):
         pb, ctx = self.pb, self.ctx
@@ -257,6 +214,6 @@ def compare(ctx, problem=None, iters=3000, seed=0, n_init=10_000, log=None, **kw
         tr = Trainer(ctx, pb, TrainConfig(method=method, iters=iters, seed=seed, **kw), n_init=n_init)
         out[method] = tr.run(log=log)
         tr.frame.close()
-        if getattr(tr, "bframe", None) is not None:
-            tr.bframe.close()
+        if tr.dstep is not None:
+            tr.dstep.close()
     return out

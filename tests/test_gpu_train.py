@@ -215,9 +215,15 @@ def test_clone_prune_capacity_and_aliasing(ctx):
     rng = np.random.default_rng(2)
     g = to_dev(rand_set(100, 0, rng), 0)
     small = api.Gaussians.empty(150, 0)
+    clone = torch.ones(100, dtype=torch.uint8, device="cuda")
+    # with a clone mask every row may be cloned: 2 n rows; without, n
     with pytest.raises(api.AdpSplitError) as e:
-        api.clone_prune(ctx, g, None, None, 0.005, 0.0, out=small)
+        api.clone_prune(ctx, g, clone, None, 0.005, 0.0, out=small)
     assert e.value.status == api.AS_ERR_CAPACITY
+    with pytest.raises(api.AdpSplitError) as e:
+        api.clone_prune(ctx, g, None, None, 0.005, 0.0, out=api.Gaussians.empty(99, 0))
+    assert e.value.status == api.AS_ERR_CAPACITY
+    api.clone_prune(ctx, g, None, None, 0.005, 0.0, out=small)
 
 
 @pytest.mark.parametrize("n_src,n_rows", [(100, 130), (60001, 60001)])
