@@ -63,7 +63,7 @@ def _args():
     ap.add_argument("--no-training", action="store_true", help="skip the end-to-end densification training leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-view leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="Poisson arrivals of the serving leg (seconds)")
     ap.add_argument("--json", default="", help="also write the JSON line to this file")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tuning)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -186,7 +186,7 @@ def densify_bench(ctx):
     params = api.SplitParams()
     regions = api.RegionBuffer(V * W * H // params.m_min // 4)
     attr = torch.zeros(n, dtype=torch.int32, device="cuda")
-    out = api.Gaussians.empty(n + len(cand) * (params.n_max + 1), 3)
+    out = api.Gaussians.empty(n + len(cand) * api.split_rows_per_candidate(params), 3)
     dm = frame.device_maps()
     ctx.reserve(max_pixels=W * H, max_gaussians=n, max_candidates=len(cand), max_regions=regions.capacity,
                 max_views=V)
@@ -250,7 +250,7 @@ def densify_bench(ctx):
         vp = api.SplitParams(**kw)
         nz = noise if vp.noise_n <= 2 else torch.from_numpy(
             np.random.default_rng(5).standard_normal((len(cand), vp.noise_n, 3)).astype(np.float32)).cuda()
-        vout = api.Gaussians.empty(n + len(cand) * max(2, vp.n_max + 1, vp.fixed_n), 3)
+        vout = api.Gaussians.empty(n + len(cand) * api.split_rows_per_candidate(vp), 3)
         r = api.adaptive_split(ctx, g, cand_t, regions, views, attr, vp, nz, out=vout)
         torch.cuda.synchronize()
         tv = time.perf_counter()
@@ -307,20 +307,24 @@ def densify_bench(ctx):
 
 def training_bench(ctx):
     """Synthetic end-to-end densification training (3DGS's loop with adaptive
-    density control, shortened schedule): a 200,000-Gaussian teacher rendered
-    from 48 training and 8 held-out cameras at 640x480; a student initialised
-    from 20,000 noisy teacher centres; 3000 iterations, densification every
-    100 from 300 to 2100 with the vanilla N = 2 split or AdpSplit (20 sampled
-    views).  Held-out PSNR against training time (evaluation excluded) and
-    the number of Gaussians, every 250 iterations."""
+    density control): a 200,000-Gaussian teacher rendered from 48 training and
+    8 held-out cameras at 640x480; a student initialised from 20,000 noisy
+    teacher centres; densification every 100 iterations from 300.  The arms
+    of Table 1 and Fig. 2 (train.compare_arms): the vanilla N = 2 split on the
+    full schedule (3750 iterations, densification until 3500), and on the
+    shortened one (3000, until 2100) the vanilla split, five random children,
+    the vanilla split with its threshold lowered to AdpSplit's final count,
+    and AdpSplit (20 sampled views).  Held-out PSNR against training time
+    (evaluation excluded) and the number of Gaussians, every 250 iterations."""
     from paper_2605_06876_amd import train
 
     pb = train.Problem(ctx, n_teacher=200_000, n_train=48, n_eval=8, size=(640, 480), seed=7)
-    res = train.compare(ctx, pb, iters=3000, seed=0, n_init=20_000)
-    out = dict(teacher=200_000, size="640x480", train_views=48, eval_views=8, init=20_000, iters=3000)
-    for method, r in res.items():
-        out[method] = {k: v for k, v in r.items() if k != "history"}
-        out[method]["curve"] = [[h["it"], h["train_s"], h["psnr"], h["n"]] for h in r["history"]]
+    res = train.compare_arms(ctx, pb, iters=3000, densify_until=2100, seed=0, n_init=20_000)
+    out = dict(teacher=200_000, size="640x480", train_views=48, eval_views=8, init=20_000,
+               schedules=res.pop("schedules"))
+    for arm, r in res.items():
+        out[arm] = {k: v for k, v in r.items() if k != "history"}
+        out[arm]["curve"] = [[h["it"], h["train_s"], h["psnr"], h["n"]] for h in r["history"]]
     out["curve_columns"] = ["iteration", "train_s", "psnr_db", "gaussians"]
     return out
 
@@ -399,13 +403,23 @@ def batched_bench(reps=10):
                 speedup_batched_graph_vs_loop=round(ms_loop / ms_graph, 3))
 
 
-def serving_bench(seconds=5.0, rate=200.0, burst=400):
+def serving_bench(seconds=30.0, rate=200.0, sweep_rates=(400.0, 1000.0, 1600.0, 2200.0, 3000.0), sweep_seconds=3.0,
+                  tight_gib=8, tight_rate=2200.0, burst=400):
     """Four resident scenes (300k, 600k, 1.2M, 2M clustered Gaussians, SH 3);
     render requests with random poses on a radius-4 sphere and resolutions
-    drawn from {640x480, 1280x720, 1920x1080}.  (a) Poisson arrivals at
-    `rate`/s for `seconds`: continuous batching over 3 slots vs the plain
-    sequential loop on the same request list; (b) a burst of `burst`
-    requests arriving at once (throughput bound)."""
+    drawn from {640x480, 1280x720, 1920x1080} (mean 1.10 Mpx).  Continuous
+    batching over 3 slots of up to 8 views vs the plain sequential loop, on
+    the same request lists:
+      poisson  Poisson arrivals at `rate`/s for `seconds`, slots sized from
+               the free HBM after the scenes less 10% (each slot capped at
+               serve.MAX_SLOT_PAIRS pairs);
+      sweep    `sweep_seconds` of arrivals at each rate of `sweep_rates`, up
+               to past the sequential loop's saturation;
+      tight    a `tight_gib` GiB budget over the 3 slots (admission binds: the
+               estimated pairs close batches early), at `tight_rate`/s;
+      burst    `burst` requests arriving at once.
+    Latency = completion event minus arrival; Mpix/s = pixels served over
+    the wall time from the first arrival to the last completion."""
     import torch
 
     from paper_2605_06876_amd import api, serve, synth
@@ -415,37 +429,57 @@ def serving_bench(seconds=5.0, rate=200.0, burst=400):
     scenes = [api.Gaussians.from_scene(synth.scene_clusters(n, 2001 + k, 3)) for k, n in enumerate(ns)]
     ctx = api.Context(0)
     n_slots, max_views = 3, 8
-    spec = serve.default_spec(ns, sizes, max_views, 24 << 30, n_slots)
-    ex = serve.GpuExecutor(ctx, scenes, spec, n_slots)
+    torch.cuda.synchronize()
+    budget = int(0.9 * torch.cuda.mem_get_info()[0])
     cam_fn = lambda rng, w, h: synth.random_pose_camera(rng, 4.0, w, h)
 
     def fresh(reqs):
         return [serve.Request(r.rid, r.scene, r.cam, r.arrival) for r in reqs]
 
-    warm = serve.poisson_requests(24, 0.0, len(ns), sizes, cam_fn, seed=1)
-    sched = serve.Scheduler(ex, spec, ns)
-    serve.serve_open_loop(sched, warm)
-    serve.serve_sequential(ex, fresh(warm))
-    torch.cuda.synchronize()
+    def both(ex, spec, reqs):
+        sched = serve.Scheduler(ex, spec, ns, keep_images=False)
+        wall = serve.serve_open_loop(sched, reqs)
+        res = dict(batched=serve.latency_stats(sched.completed, wall), batches=sched.batches,
+                   mean_batch=round(len(reqs) / max(sched.batches, 1), 2), pair_bound=sched.pair_bound)
+        seq = fresh(reqs)
+        wall = serve.serve_sequential(ex, seq, keep_images=False)
+        res["sequential"] = serve.latency_stats(seq, wall)
+        return res
+
+    def executor(budget_bytes):
+        spec = serve.default_spec(ns, sizes, max_views, budget_bytes, n_slots)
+        ex = serve.GpuExecutor(ctx, scenes, spec, n_slots)
+        warm = serve.poisson_requests(24, 0.0, len(ns), sizes, cam_fn, seed=1)
+        serve.serve_open_loop(serve.Scheduler(ex, spec, ns, keep_images=False), warm)
+        serve.serve_sequential(ex, fresh(warm), keep_images=False)
+        torch.cuda.synchronize()
+        return spec, ex
+
+    spec, ex = executor(budget)
     out = dict(scenes=ns, sizes=["%dx%d" % s for s in sizes], slots=n_slots, max_views=max_views,
-               hbm=serve.hbm_footprint(scenes, spec, n_slots), slot_pairs=spec.pairs)
-    n = int(seconds * rate)
-    reqs = serve.poisson_requests(n, rate, len(ns), sizes, cam_fn, seed=2005)
-    sched = serve.Scheduler(ex, spec, ns)
-    wall = serve.serve_open_loop(sched, reqs)
-    out["poisson"] = dict(rate_per_s=rate, batched=serve.latency_stats(sched.completed, wall),
-                          batches=sched.batches, overflows=ex.overflows)
-    seq = fresh(reqs)
-    wall = serve.serve_sequential(ex, seq)
-    out["poisson"]["sequential"] = serve.latency_stats(seq, wall)
+               budget_bytes=budget, hbm=serve.hbm_footprint(scenes, spec, n_slots), slot_pairs=spec.pairs)
+    reqs = serve.poisson_requests(int(seconds * rate), rate, len(ns), sizes, cam_fn, seed=2005)
+    ov = ex.overflows
+    out["poisson"] = dict(rate_per_s=rate, seconds=seconds, **both(ex, spec, reqs), overflows=ex.overflows - ov)
+    out["sweep"] = []
+    for k, rt in enumerate(sweep_rates):
+        reqs = serve.poisson_requests(int(sweep_seconds * rt), rt, len(ns), sizes, cam_fn, seed=2100 + k)
+        ov = ex.overflows
+        out["sweep"].append(dict(rate_per_s=rt, seconds=sweep_seconds, **both(ex, spec, reqs),
+                                 overflows=ex.overflows - ov))
     reqs = serve.poisson_requests(burst, 0.0, len(ns), sizes, cam_fn, seed=2006)
-    sched = serve.Scheduler(ex, spec, ns)
-    wall = serve.serve_open_loop(sched, reqs)
-    out["burst"] = dict(requests=burst, batched=serve.latency_stats(sched.completed, wall), batches=sched.batches)
-    seq = fresh(reqs)
-    wall = serve.serve_sequential(ex, seq)
-    out["burst"]["sequential"] = serve.latency_stats(seq, wall)
+    out["burst"] = dict(requests=burst, **both(ex, spec, reqs))
     ex.close()
+    del ex
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    spec_t, ex_t = executor(tight_gib << 30)
+    reqs = serve.poisson_requests(int(sweep_seconds * tight_rate), tight_rate, len(ns), sizes, cam_fn, seed=2200)
+    ov, so = ex_t.overflows, ex_t.single_overflows
+    out["tight"] = dict(budget_gib=tight_gib, slot_pairs=spec_t.pairs, rate_per_s=tight_rate, seconds=sweep_seconds,
+                        hbm=serve.hbm_footprint(scenes, spec_t, n_slots), **both(ex_t, spec_t, reqs),
+                        overflows=ex_t.overflows - ov, single_overflows=ex_t.single_overflows - so)
+    ex_t.close()
     return out
 
 
@@ -619,7 +653,7 @@ def main():
         log("bench: densification step (500k Gaussians, 16 views)")
         out["densify"] = densify_bench(res["ctx"])
     if not args.no_training:
-        log("bench: end-to-end densification training (vanilla split vs AdpSplit)")
+        log("bench: end-to-end densification training (full-schedule, shortened, five-child, equal-count and AdpSplit arms)")
         out["training"] = training_bench(res["ctx"])
     if not args.no_batched:
         log("bench: batched training render (8 uneven views, 1.5M Gaussians)")

@@ -368,7 +368,8 @@ as_status as_accumulate_error_stats_noalloc(as_ctx *ctx, int32_t width, int32_t 
  *   views      : host array [n_views]; a region's view id indexes it
  *   attr_count : [n]
  *   noise      : [n_cand][noise_n][3] standard normals for the random children
- *   out        : rows = capacity (>= n + n_cand * max(2, n_max + 1, fixed_n) always suffices)
+ *   out        : rows = capacity >= n + n_cand * per, per = fixed_n for AS_VARIANT_FIXED_N, else
+ *                max(2, n_max + 1) (AS_ERR_CAPACITY below it)
  *   mode, count: out [n_cand]; offset: out [n_cand] exclusive scan of count
  *   n_out      : out [1] device; the new set is the non-removed Gaussians in
  *                order, then one block per candidate in ascending id order
@@ -489,11 +490,15 @@ typedef struct {
                                 tile unless its alpha >= 1/255 ellipse (with a margin above the
                                 FP32 evaluation error) meets the block; zero: the pixel box alone
                                 decides.  The contributor sets, and so every output, are the same */
+    int32_t single_pass_sort; /* bit 0: the depth sort, bit 1: the pair sort takes one launch per digit
+                                (decoupled look-back across blocks) instead of three (reduce, scan,
+                                scatter); the same order either way */
 } as_tuning;
 
 /* Set / read the context's tuning (defaults: lds_batch 256, longest_first 1,
- * persistent 0, radix_bits 8, block_cull 1).  AS_ERR_ARG for an lds_batch other than 256,
- * 512 or 1024 or a radix_bits outside 4..8. */
+ * persistent 0, radix_bits 8, block_cull 1, single_pass_sort 0).  AS_ERR_ARG for an
+ * lds_batch other than 256, 512 or 1024, a radix_bits outside 4..8 or a
+ * single_pass_sort outside 0..3. */
 as_status as_set_tuning(as_ctx *ctx, const as_tuning *t);
 as_status as_get_tuning(const as_ctx *ctx, as_tuning *t);
 
@@ -549,6 +554,17 @@ void as_graph_destroy(as_graph *graph);
  * test hook: it grows its own scratch on demand (it allocates).
  * keys [n], vals [n]; bits at and above key_bits are ignored. */
 as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64_t n, int32_t key_bits, void *stream);
+
+/* The binning's 32-bit sorter: stable sort of n (key, value) pairs on key bits
+ * [lo_bit, hi_bit) with digits of radix_bits (4..8) bits, in place, by one
+ * launch per digit (single_pass nonzero) or three.  gather_src / gather_dst
+ * (both NULL, or device arrays: gather_src indexed by values, gather_dst [n]):
+ * the last digit pass also writes gather_dst[r] = gather_src[value at r].  A
+ * test hook: it grows its own scratch on demand (it allocates).  Returns
+ * AS_ERR_HIP if a single-pass wait hit its limit. */
+as_status as_debug_sort_u32(as_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int32_t lo_bit, int32_t hi_bit,
+                            int32_t radix_bits, int32_t single_pass, const uint32_t *gather_src, uint32_t *gather_dst,
+                            void *stream);
 
 /* Element-wise FP64 sqrt(a), a / b, exp(b) and log(a) on the device, used to
  * check that the decision arithmetic rounds like the host's.  out[4][n]. */

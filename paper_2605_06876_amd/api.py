@@ -99,7 +99,7 @@ EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "a
             "as_render_backward", "as_render_batch", "as_render_backward_batch", "as_error_map",
             "as_accumulate_error_stats", "as_accumulate_error_stats_noalloc", "as_adaptive_split", "as_set_tuning", "as_get_tuning", "as_timing_enable",
             "as_timing_read", "as_graph_begin", "as_graph_end", "as_graph_launch", "as_graph_destroy",
-            "as_debug_sort_pairs", "as_debug_fp64_ops", "as_debug_blend_alpha", "as_adam_step", "as_l1_loss", "as_densify_select",
+            "as_debug_sort_pairs", "as_debug_sort_u32", "as_debug_fp64_ops", "as_debug_blend_alpha", "as_adam_step", "as_l1_loss", "as_densify_select",
             "as_split_row_map", "as_clone_prune", "as_gather_rows", "as_reset_opacity")
 _NO_STATUS = ("as_last_error", "as_version", "as_ctx_destroy", "as_frame_destroy", "as_graph_destroy")
 
@@ -617,6 +617,13 @@ def accumulate_error_stats_noalloc(ctx, width, height, err, err_minmax, dom, gt,
                                                    _ptr(attr_count), _stream(stream)))
 
 
+def split_rows_per_candidate(params):
+    """Rows the split appends per candidate at most (the output bound is
+    n + n_cand times this): fixed_n for the fixed-N split, else
+    max(2, N_max + 1)."""
+    return params.fixed_n if params.variant == VARIANT_FIXED_N else max(2, params.n_max + 1)
+
+
 def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=None, mode=None, count=None,
                    offset=None, n_out=None, n_cand_dev=None, stream=None):
     """as_adaptive_split.  Returns (out Gaussians with capacity rows, mode,
@@ -625,7 +632,7 @@ def adaptive_split(ctx, g, cand, regions, views, attr_count, params, noise, out=
     is then a capacity)."""
     nc = int(cand.shape[0])
     if out is None:
-        cap = g.n + nc * max(2, params.n_max + 1, params.fixed_n if params.variant == VARIANT_FIXED_N else 0)
+        cap = g.n + nc * split_rows_per_candidate(params)
         out = Gaussians.empty(max(cap, 1), g.sh_degree)
     if mode is None:
         mode = torch.zeros(max(nc, 1), dtype=torch.uint8, device="cuda")
@@ -763,11 +770,15 @@ def reset_opacity(ctx, g, max_opacity, m_op=None, v_op=None, stream=None):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("lds_batch", ctypes.c_int32), ("longest_first", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("radix_bits", ctypes.c_int32), ("block_cull", ctypes.c_int32)]
+                ("radix_bits", ctypes.c_int32), ("block_cull", ctypes.c_int32), ("single_pass_sort", ctypes.c_int32)]
 
 
-def set_tuning(ctx, lds_batch=256, longest_first=True, persistent=False, radix_bits=8, block_cull=True):
-    t = _Tuning(lds_batch, 1 if longest_first else 0, 1 if persistent else 0, radix_bits, 1 if block_cull else 0)
+def set_tuning(ctx, lds_batch=256, longest_first=True, persistent=False, radix_bits=8, block_cull=True,
+               single_pass_sort=0):
+    """as_set_tuning (single_pass_sort: bit 0 the depth sort, bit 1 the pair
+    sort take one launch per digit)."""
+    t = _Tuning(lds_batch, 1 if longest_first else 0, 1 if persistent else 0, radix_bits, 1 if block_cull else 0,
+                int(single_pass_sort))
     _check(lib().as_set_tuning(ctx.handle, ctypes.byref(t)))
 
 
@@ -775,7 +786,7 @@ def get_tuning(ctx):
     t = _Tuning()
     _check(lib().as_get_tuning(ctx.handle, ctypes.byref(t)))
     return dict(lds_batch=t.lds_batch, longest_first=bool(t.longest_first), persistent=bool(t.persistent),
-                radix_bits=t.radix_bits, block_cull=bool(t.block_cull))
+                radix_bits=t.radix_bits, block_cull=bool(t.block_cull), single_pass_sort=t.single_pass_sort)
 
 
 def timing_enable(ctx, on=True):
@@ -793,6 +804,15 @@ def timing_read(ctx):
 def debug_sort_pairs(ctx, keys, vals, key_bits, stream=None):
     _check(lib().as_debug_sort_pairs(ctx.handle, _ptr(keys), _ptr(vals), ctypes.c_int64(keys.shape[0]),
                                      ctypes.c_int32(key_bits), _stream(stream)))
+
+
+def debug_sort_u32(ctx, keys, vals, lo_bit, hi_bit, radix_bits=8, single_pass=True, gather_src=None,
+                   gather_dst=None, stream=None):
+    """as_debug_sort_u32 (in place; int32 tensors holding the u32 bits)."""
+    _check(lib().as_debug_sort_u32(ctx.handle, _ptr(keys), _ptr(vals), ctypes.c_int64(keys.numel()),
+                                   ctypes.c_int32(lo_bit), ctypes.c_int32(hi_bit), ctypes.c_int32(radix_bits),
+                                   ctypes.c_int32(1 if single_pass else 0), _ptr(gather_src), _ptr(gather_dst),
+                                   _stream(stream)))
 
 
 def debug_fp64_ops(ctx, a, b, stream=None):

@@ -6,7 +6,9 @@ same order, and every radix width gives the same stable order), and the
 backward differs only in the order of its float atomics.  For a workload the
 tuner times the caller's own step (a render + backward by default) for every
 blend configuration (LDS depth x tile order x persistent grid), then for every
-radix digit width with the best blend configuration, and keeps the fastest
+radix digit width with the best blend configuration, then for the sorts'
+launch structure (one launch per digit or three, for the depth and the pair
+sort), and keeps the fastest
 (the better of two interleaved rounds per candidate, after a warm-up).
 Results are cached in a JSON file keyed by the workload.
 """
@@ -30,9 +32,13 @@ def workload_key(width, height, n, sh_degree, views=1, arch="gfx950"):
     return "%s|%.2fMpx|n2^%d|sh%d|v%d" % (arch, mp_bucket, n_bucket, sh_degree, views)
 
 
+SORT_CANDIDATES = (0, 1, 2, 3)   # single-pass sorts: neither, depth only, pairs only, both
+
+
 def name_of(t):
-    return "batch%d_%s_%s_r%d" % (t["lds_batch"], "lpt" if t["longest_first"] else "grid",
-                                  "persistent" if t["persistent"] else "blocks", t["radix_bits"])
+    return "batch%d_%s_%s_r%d_sp%d" % (t["lds_batch"], "lpt" if t["longest_first"] else "grid",
+                                       "persistent" if t["persistent"] else "blocks", t["radix_bits"],
+                                       t.get("single_pass_sort", 0))
 
 
 def time_step(run, reps):
@@ -82,8 +88,9 @@ def autotune_step(ctx, run, key, reps=5, cache_path=DEFAULT_CACHE, use_cache=Tru
                 times[name_of(t)] = min(times.get(name_of(t), float("inf")), ms)
         return min(cands, key=lambda t: times[name_of(t)])
 
-    best = rounds([dict(c, radix_bits=8) for c in BLEND_CANDIDATES])
+    best = rounds([dict(c, radix_bits=8, single_pass_sort=0) for c in BLEND_CANDIDATES])
     best = rounds([dict(best, radix_bits=rb) for rb in RADIX_CANDIDATES])
+    best = rounds([dict(best, single_pass_sort=sp) for sp in SORT_CANDIDATES])
     api.set_tuning(ctx, **best)
     if cache_path:
         cache[key] = dict(tuning=best, ms=times)

@@ -625,7 +625,7 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
         // 32-bit keys: 8-bit digits give the fewest passes (four); the last
         // pass also gathers each entry's tile count into depth order
         const int dsel = radix_sort_u32(f->dkeys, f->dvals, f->n_ent, f->ent_cap, n, 0, 32, 8,
-                                        f->dsort_hist.p, s, f->ntiles, f->nt_sorted);
+                                        f->dsort_hist.p, s, f->ntiles, f->nt_sorted, ctx->single_pass_sort & 1);
         order = f->dvals[dsel];
     }
     {
@@ -646,7 +646,7 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
         StageTimer t(ctx, AS_STAGE_SORT, s);
         // only the pairs written (a render over the capacity writes a prefix)
         sel = radix_sort_u32(f->keys, f->vals, f->n_keys + 1, f->key_cap, n_hint, 0, tile_bits(tiles),
-                             ctx->radix_bits, f->sort_hist.p, s);
+                             ctx->radix_bits, f->sort_hist.p, s, nullptr, nullptr, (ctx->single_pass_sort & 2) != 0);
     }
     f->sorted_sel = sel;
     {
@@ -965,8 +965,7 @@ as_status as_adaptive_split(as_ctx *ctx, const as_gaussians *g, const int32_t *c
                      params->noise_n, split_noise_need(*params));
         return AS_ERR_ARG;
     }
-    int64_t per = params->n_max + 1 > 2 ? params->n_max + 1 : 2;
-    if (params->variant == AS_VARIANT_FIXED_N && params->fixed_n > per) per = params->fixed_n;
+    const int64_t per = split_rows_per_candidate(*params);
     const int64_t bound = g->n + n_cand * per;
     if (!check_mut(out, 0, g->sh_degree, "as_adaptive_split")) return AS_ERR_ARG;
     if (out->n < bound) {
@@ -999,11 +998,16 @@ as_status as_set_tuning(as_ctx *ctx, const as_tuning *t) {
         as_set_error("as_set_tuning: radix_bits %d not in 4..8", t->radix_bits);
         return AS_ERR_ARG;
     }
+    if (t->single_pass_sort < 0 || t->single_pass_sort > 3) {
+        as_set_error("as_set_tuning: single_pass_sort %d not in 0..3", t->single_pass_sort);
+        return AS_ERR_ARG;
+    }
     ctx->lds_batch = t->lds_batch;
     ctx->longest_first = t->longest_first != 0;
     ctx->persistent = t->persistent != 0;
     ctx->radix_bits = t->radix_bits;
     ctx->block_cull = t->block_cull != 0;
+    ctx->single_pass_sort = t->single_pass_sort;
     return AS_OK;
 }
 
@@ -1014,6 +1018,7 @@ as_status as_get_tuning(const as_ctx *ctx, as_tuning *t) {
     t->persistent = ctx->persistent;
     t->radix_bits = ctx->radix_bits;
     t->block_cull = ctx->block_cull;
+    t->single_pass_sort = ctx->single_pass_sort;
     return AS_OK;
 }
 
@@ -1115,6 +1120,45 @@ as_status as_debug_sort_pairs(as_ctx *ctx, uint64_t *keys, uint32_t *vals, int64
             return AS_ERR_HIP;
     }
     return launch_status("as_debug_sort_pairs");
+}
+
+as_status as_debug_sort_u32(as_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t n, int32_t lo_bit, int32_t hi_bit,
+                            int32_t radix_bits, int32_t single_pass, const uint32_t *gather_src, uint32_t *gather_dst,
+                            void *stream) {
+    if (!ctx || n < 0 || n > 0x3FFFFFFEll || (n > 0 && (!keys || !vals)) || lo_bit < 0 || hi_bit > 32 ||
+        lo_bit > hi_bit || radix_bits < 4 || radix_bits > 8 || (!gather_src) != (!gather_dst)) {
+        as_set_error("as_debug_sort_u32: bad argument");
+        return AS_ERR_ARG;
+    }
+    if (n == 0 || hi_bit == lo_bit) return AS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (bad(devbuf_ensure(ctx->dbg[4], n * 4), "sort scratch") || bad(devbuf_ensure(ctx->dbg[5], n * 4), "sort scratch") ||
+        bad(devbuf_ensure(ctx->dbg[2], sort_hist_bytes(n)), "sort scratch") || bad(devbuf_ensure(ctx->dbg[3], 64), "sort scratch"))
+        return AS_ERR_HIP;
+    uint32_t *kk[2] = {keys, (uint32_t *)ctx->dbg[4].p};
+    uint32_t *vv[2] = {vals, (uint32_t *)ctx->dbg[5].p};
+    uint32_t *n_dev = (uint32_t *)ctx->dbg[3].p;
+    launch_fill_u32(n_dev, (uint32_t)n, 1, s);
+    uint32_t *flag = (uint32_t *)((char *)ctx->dbg[2].p + sort_wait_flag_offset());
+    launch_fill_u32(flag, 0u, 1, s);
+    const int sel = radix_sort_u32(kk, vv, n_dev, n, n, lo_bit, hi_bit, radix_bits, ctx->dbg[2].p, s, gather_src,
+                                   gather_dst, single_pass != 0);
+    if (sel == 1) {
+        if (bad(hipMemcpyAsync(keys, kk[1], n * 4, hipMemcpyDeviceToDevice, s), "sort copy-back") ||
+            bad(hipMemcpyAsync(vals, vv[1], n * 4, hipMemcpyDeviceToDevice, s), "sort copy-back"))
+            return AS_ERR_HIP;
+    }
+    if (single_pass) {
+        uint32_t hflag = 0;
+        if (bad(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "sort flag") ||
+            bad(hipStreamSynchronize(s), "sort flag"))
+            return AS_ERR_HIP;
+        if (hflag) {
+            as_set_error("as_debug_sort_u32: a look-back wait hit its limit");
+            return AS_ERR_HIP;
+        }
+    }
+    return launch_status("as_debug_sort_u32");
 }
 
 as_status as_debug_fp64_ops(as_ctx *ctx, const double *a, const double *b, int64_t n, double *out, void *stream) {

@@ -157,7 +157,7 @@ struct as_ctx {
     int device;
     DevBuf es[16];    // error-statistics scratch (errstats.hip names the slots)
     DevBuf sp[24];    // adaptive-split scratch (split.hip names the slots)
-    DevBuf dbg[4];    // test hooks
+    DevBuf dbg[6];    // test hooks
     DevBuf tr[8];     // optimisation-loop scratch (train.hip kernels; slots named in api.hip)
     as_reserve res{};             // what es, sp and tr hold (as_ctx_reserve)
     int lds_batch = 256;          // launch tuning (as_set_tuning)
@@ -165,6 +165,7 @@ struct as_ctx {
     int persistent = 0;
     int radix_bits = 8;
     int block_cull = 1;
+    int single_pass_sort = 0;   // bit 0 depth sort, bit 1 pair sort
     int n_cu = 0;                 // compute units of the device
     int timing = 0;
     StageRec *recs = nullptr;     // recorded stage event pairs
@@ -210,9 +211,15 @@ void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *total,
 size_t sort_hist_bytes(int64_t cap);
 // gather_src/gather_dst (optional): the last pass also writes
 // gather_dst[r] = gather_src[sorted value r].
+// single_pass: one launch per digit with decoupled look-back (used when
+// sort_single_pass_ok(cap)); otherwise three launches per digit.  Both give
+// the same order.  The single-pass sort raises a flag in the workspace at
+// byte sort_wait_flag_offset() if a look-back wait hit its limit.
 int radix_sort_u32(uint32_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
                    int hi_bit, int radix_bits, void *hist, hipStream_t s, const uint32_t *gather_src = nullptr,
-                   uint32_t *gather_dst = nullptr);
+                   uint32_t *gather_dst = nullptr, bool single_pass = false);
+bool sort_single_pass_ok(int64_t cap);
+uint32_t sort_wait_flag_offset();
 int radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *n_dev, int64_t cap, int64_t n_hint, int lo_bit,
                    int hi_bit, int radix_bits, void *hist, hipStream_t s);
 // Depth-first binning: keys emitted in the depth order a stable depth sort
@@ -301,6 +308,14 @@ static inline int split_noise_need(const as_split_params &p) {
     if (p.variant == AS_VARIANT_FIXED_N && p.fixed_n > need) need = p.fixed_n;
     if (p.variant == AS_VARIANT_ADAPTIVE_N && p.n_max > need) need = p.n_max;
     return need;
+}
+
+// Rows the split appends per candidate at most: fixed_n for the fixed-N
+// split (the parent is removed), else N_max children plus the parent copy
+// of the adaptive mode (at least 2: the vanilla fallback).
+inline int64_t split_rows_per_candidate(const as_split_params &p) {
+    if (p.variant == AS_VARIANT_FIXED_N) return p.fixed_n;
+    return p.n_max + 1 > 2 ? p.n_max + 1 : 2;
 }
 // Scratch of the split for the region, candidate, view and Gaussian maxima of r.
 size_t split_reserve_bytes(const as_reserve &r);

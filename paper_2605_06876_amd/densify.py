@@ -36,8 +36,9 @@ class DensifyStep:
 
     ctx      : context (reserved here for the step's sizes)
     n, deg   : largest input row count and the SH degree
-    method   : "adpsplit" or "vanilla" (3DGS's N = 2 random split)
-    params   : api.SplitParams of the split (AdpSplit) or None
+    method   : "adpsplit" or "vanilla" (3DGS's random split)
+    params   : api.SplitParams of the split (a fixed-N variant for "vanilla";
+               None gives the defaults: AdpSplit's, or N = 2)
     views    : cameras of the sampled views (AdpSplit), gts their targets
     regions  : api.RegionBuffer for the sampled views' regions
     cand_cap : candidates the split takes at most (default n)
@@ -53,15 +54,19 @@ class DensifyStep:
             self.params = params if params is not None else api.SplitParams()
             self.views, self.gts = list(views), list(gts)
             assert self.views and regions is not None
-        else:
-            self.params = api.SplitParams(variant=api.VARIANT_FIXED_N, fixed_n=2)
+        else:   # 3DGS's random split (N = 2 unless the params say otherwise)
+            self.params = params if params is not None else api.SplitParams(variant=api.VARIANT_FIXED_N, fixed_n=2)
+            assert self.params.variant == api.VARIANT_FIXED_N
             self.views, self.gts = [], []
         # the fixed-N split reads no region: an empty one-record buffer
         self.regions = regions if regions is not None else api.RegionBuffer(1)
         p = self.params
-        per = max(2, p.n_max + 1, p.fixed_n if p.variant == api.VARIANT_FIXED_N else 0)
+        per = api.split_rows_per_candidate(p)
         self.noise_n = max(2, p.n_max if p.variant == api.VARIANT_ADAPTIVE_N else 0,
                            p.fixed_n if p.variant == api.VARIANT_FIXED_N else 0)
+        if p.noise_n < self.noise_n:   # the noise input holds noise_n normals per candidate
+            self.params = p = api.SplitParams(p.tau_l1, p.r_erode, p.m_min, p.L, p.n_max, p.gamma_d, p.gamma_c, p.eps,
+                                              p.eta, p.variant, p.flags, p.fixed_n, self.noise_n)
         self.cc = n if cand_cap is None else max(1, min(int(cand_cap), n))
         self.cap1 = 2 * n
         self.cap2 = self.cap1 + self.cc * per

@@ -9,9 +9,16 @@ One knob varies at a time from the defaults (tau_l1 0.1, r_erode 2, m_min 5,
 L 3, N_max 19, V 16 here: the workload has 16 views).  Reported per setting:
 the time of the step (error statistics of V views + the split; renders
 included), regions, new rows (children and parent copies), the output count,
-and the device memory in use after the step (hipMemGetInfo, relative to the
-start of the sweep; the library's scratch only grows, so this tracks the
-peak).
+and the step's own peak device memory.  Each setting runs on a fresh context
+with its own frame, region buffer and outputs, after torch's cache is
+emptied, so no setting inherits another's allocations: the peak is the
+library's memory for the setting (context reservation + frame, from the
+library's size queries, which walk the same tables as its allocations) plus
+the peak of the step's tensors (regions, attribution counts, noise, split
+outputs; torch's peak counter, reset per setting).  The scene, views and
+targets the settings share are reported once.  (hipMemGetInfo across the
+creation is also recorded; the runtime reuses memory freed by the previous
+setting's context, so it can read below the allocation.)
 
     python -m paper_2605_06876_amd.sweep --out profiles/knob_sweep_densify.md
 """
@@ -55,23 +62,38 @@ class DensifyWorkload:
         self.dm = self.frame.device_maps()
 
     def step(self, params, V, reps=3):
-        ctx, W, H = self.ctx, self.W, self.H
+        """The step for one setting on a fresh context; returns its figures."""
+        W, H, n = self.W, self.H, self.n
         nc = len(self.cand)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        alloc0 = torch.cuda.memory_allocated()
+        free0 = torch.cuda.mem_get_info()[0]
+        cap = V * W * H // max(params.m_min, 1) // 4 + 1024
+        reserve = dict(max_pixels=W * H, max_gaussians=n, max_candidates=nc, max_regions=cap, max_views=V)
+        ctx = api.Context(0, **reserve)
+        frame = api.Frame(ctx, n, W, H, key_cap=16 * n, auto_grow=False, forward_only=True)
+        torch.cuda.synchronize()
+        lib_bytes = free0 - torch.cuda.mem_get_info()[0]
+        lib_query = api.reserve_bytes(**reserve) + api.frame_bytes(1, n, W * H, ((W + 15) // 16) * ((H + 15) // 16),
+                                                                   16 * n, forward_only=True)
+        dm = frame.device_maps()
+        image = torch.empty(3, H, W, dtype=torch.float32, device="cuda")
         noise = torch.from_numpy(synth.vanilla_noise(nc, 5)).cuda()
-        regions = api.RegionBuffer(V * W * H // max(params.m_min, 1) // 4 + 1024)
-        attr = torch.zeros(self.n, dtype=torch.int32, device="cuda")
-        out = api.Gaussians.empty(self.n + nc * max(2, params.n_max + 1), 3)
-        ctx.reserve(max_pixels=W * H, max_gaussians=self.n, max_candidates=nc, max_regions=regions.capacity,
-                    max_views=V)
+        regions = api.RegionBuffer(cap)
+        attr = torch.zeros(n, dtype=torch.int32, device="cuda")
+        out = api.Gaussians.empty(n + nc * api.split_rows_per_candidate(params), 3)
 
         def once():
             regions.count.zero_()
             attr.zero_()
             for v in range(V):
-                api.render(ctx, self.g, self.views[v], self.frame, gt=self.gts[v], image=self.image)
-                api.accumulate_error_stats(ctx, W, H, self.dm["err"], self.dm["err_minmax"], self.dm["dom"],
-                                           self.gts[v], v, self.is_cand, params, regions, attr)
-            return api.adaptive_split(ctx, self.g, self.cand_t, regions, self.views[:V], attr, params, noise, out=out)
+                api.render(ctx, self.g, self.views[v], frame, gt=self.gts[v], image=image)
+                api.accumulate_error_stats(ctx, W, H, dm["err"], dm["err_minmax"], dm["dom"], self.gts[v], v,
+                                           self.is_cand, params, regions, attr)
+            return api.adaptive_split(ctx, self.g, self.cand_t, regions, self.views[:V], attr, params, noise,
+                                      out=out)
 
         once()
         torch.cuda.synchronize()
@@ -80,18 +102,31 @@ class DensifyWorkload:
             r = once()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / reps
+        n_reg = int(regions.count.item())
+        assert n_reg <= cap, "region buffer too small for this setting"
         mode = r[1].cpu().numpy()
-        res = dict(ms=round(ms, 3), regions=int(regions.count.item()), new_rows=int(r[2].sum().item()),
-                   n_out=int(r[4].item()), adaptive=int((mode == 2).sum()), vanilla=int((mode == 0).sum()),
-                   reset=int((mode == 1).sum()))
-        del regions, attr, out, r
+        tensors_peak = torch.cuda.max_memory_allocated() - alloc0
+        res = dict(ms=round(ms, 3), regions=n_reg, new_rows=int(r[2].sum().item()), n_out=int(r[4].item()),
+                   adaptive=int((mode == 2).sum()), vanilla=int((mode == 0).sum()), reset=int((mode == 1).sum()),
+                   lib_gib=round(lib_bytes / 2 ** 30, 3), lib_query_gib=round(lib_query / 2 ** 30, 3),
+                   tensors_gib=round(tensors_peak / 2 ** 30, 3),
+                   peak_gib=round((lib_query + tensors_peak) / 2 ** 30, 3))
+        del regions, attr, out, r, noise, image, dm
+        frame.close()
+        ctx.close()
         return res
+
+    def base_gib(self):
+        """Device memory of what every setting shares: scene, targets, candidates."""
+        b = sum(t.numel() * t.element_size() for t in self.g.tensors())
+        b += sum(t.numel() * t.element_size() for t in self.gts)
+        b += self.is_cand.numel() + self.cand_t.numel() * 4
+        return round(b / 2 ** 30, 3)
 
 
 def run(ctx, out_md=None, log=print):
     wl = DensifyWorkload(ctx)
-    torch.cuda.synchronize()
-    free0, total = torch.cuda.mem_get_info()
+    wl.frame.close()
     rows = []
     for knob, values in GRID.items():
         for val in values:
@@ -99,9 +134,6 @@ def run(ctx, out_md=None, log=print):
             s[knob] = val
             p = api.SplitParams(r_erode=s["r_erode"], L=s["L"], n_max=s["n_max"], m_min=s["m_min"])
             r = wl.step(p, s["V"])
-            torch.cuda.synchronize()
-            free, _ = torch.cuda.mem_get_info()
-            r["mem_gib"] = round((free0 - free) / 2 ** 30, 3)
             r.update(knob=knob, value=val)
             rows.append(r)
             log(json.dumps(r))
@@ -117,14 +149,18 @@ def write_md(path, rows, wl):
              "Workload: %d clustered Gaussians (SH 3), 16 views of %dx%d on a radius-4 sphere, smooth synthetic "
              "targets, %d split candidates (top 5%% by view-averaged screen-space gradient).  One knob varies from "
              "the defaults (r_erode 2, L 3, N_max 19, m_min 5, V 16).  Time = error statistics of V views (renders "
-             "included) + the split, mean of 3.  Memory = device memory in use after the step relative to the start "
-             "(the library's scratch only grows, so it tracks the peak)." % (wl.n, wl.W, wl.H, len(wl.cand)), "",
+             "included) + the split, mean of 3.  Each setting runs on a fresh context after torch's cache is "
+             "emptied.  Library = context reservation + frame, from the library's size queries "
+             "(as_ctx_reserve_bytes + as_frame_bytes); tensors = peak of the step's own tensors (region buffer "
+             "sized V W H / (4 m_min) + 1024 records, attribution counts, noise, split outputs; torch's peak "
+             "counter); peak = their sum.  Shared by every setting and not included: scene, targets and "
+             "candidates, %.3f GiB." % (wl.n, wl.W, wl.H, len(wl.cand), wl.base_gib()), "",
              "| Knob | Value | Step (ms) | Regions | New rows | Adaptive / vanilla / reset | Gaussians after | "
-             "Memory (GiB) |", "|---|---:|---:|---:|---:|---|---:|---:|"]
+             "Library (GiB) | Tensors (GiB) | Peak (GiB) |", "|---|---:|---:|---:|---:|---|---:|---:|---:|---:|"]
     for r in rows:
-        lines.append("| %s | %s | %.2f | %d | %d | %d / %d / %d | %d | %.3f |" % (
+        lines.append("| %s | %s | %.2f | %d | %d | %d / %d / %d | %d | %.3f | %.3f | %.3f |" % (
             r["knob"], r["value"], r["ms"], r["regions"], r["new_rows"], r["adaptive"], r["vanilla"], r["reset"],
-            r["n_out"], r["mem_gib"]))
+            r["n_out"], r["lib_query_gib"], r["tensors_gib"], r["peak_gib"]))
     open(path, "w").write("\n".join(lines) + "\n")
 
 

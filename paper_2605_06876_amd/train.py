@@ -32,8 +32,9 @@ class TrainConfig:
     def __init__(self, method="adpsplit", iters=3000, densify_from=300, densify_until=2100, densify_every=100,
                  opacity_reset_every=1200, grad_threshold_ndc=2e-4, percent_dense=0.01, min_opacity=0.005,
                  max_world_scale=0.1, views_per_split=20, split_params=None, eval_every=250, max_gaussians=2_000_000,
-                 lr_means_final=0.01, seed=0):
+                 lr_means_final=0.01, seed=0, vanilla_n=2):
         assert method in ("adpsplit", "vanilla")
+        self.vanilla_n = vanilla_n   # children of the random split (3DGS: 2; Fig. 2's pilot: 5)
         self.method, self.iters = method, iters
         self.densify_from, self.densify_until, self.densify_every = densify_from, densify_until, densify_every
         self.opacity_reset_every, self.grad_threshold_ndc = opacity_reset_every, grad_threshold_ndc
@@ -146,7 +147,8 @@ class Trainer:
                 step = densify.DensifyStep(ctx, 2 * n, self.deg, "adpsplit", cfg.split_params, pb.train_cams[:k],
                                            pb.train_gt[:k], self.regions)
             else:
-                step = densify.DensifyStep(ctx, 2 * n, self.deg, "vanilla")
+                step = densify.DensifyStep(ctx, 2 * n, self.deg, "vanilla",
+                                           api.SplitParams(variant=api.VARIANT_FIXED_N, fixed_n=cfg.vanilla_n))
             self.dstep = step
         if cfg.method == "adpsplit":
             vi = self.rng.choice(len(pb.train_cams), len(step.views), replace=False)
@@ -206,14 +208,64 @@ class Trainer:
                     split_rows=int(sum(self.split_counts)), history=self.history)
 
 
-def compare(ctx, problem=None, iters=3000, seed=0, n_init=10_000, log=None, **kw):
-    """Vanilla split vs AdpSplit on the same problem and initialisation."""
-    pb = problem if problem is not None else Problem(ctx)
-    out = {}
-    for method in ("vanilla", "adpsplit"):
-        tr = Trainer(ctx, pb, TrainConfig(method=method, iters=iters, seed=seed, **kw), n_init=n_init)
-        out[method] = tr.run(log=log)
+def train_one(ctx, pb, cfg, n_init, log=None):
+    tr = Trainer(ctx, pb, cfg, n_init=n_init)
+    try:
+        return tr.run(log=log)
+    finally:
         tr.frame.close()
         if tr.dstep is not None:
             tr.dstep.close()
+
+
+def compare(ctx, problem=None, iters=3000, seed=0, n_init=10_000, log=None, **kw):
+    """Vanilla split vs AdpSplit on the same problem and initialisation."""
+    pb = problem if problem is not None else Problem(ctx)
+    return {m: train_one(ctx, pb, TrainConfig(method=m, iters=iters, seed=seed, **kw), n_init, log)
+            for m in ("vanilla", "adpsplit")}
+
+
+def compare_arms(ctx, pb, iters=3000, densify_until=2100, seed=0, n_init=10_000, full_scale=1.25,
+                 full_densify_scale=5.0 / 3.0, match_tries=5, log=None):
+    """The arms of Table 1 and Fig. 2 on one problem and initialisation.
+
+    Table 1 trains each baseline with its full schedule, with a shortened
+    densification schedule (-S: densification stops at 9k instead of 15k
+    iterations, training at 24k instead of 30k) and with AdpSplit on the
+    shortened schedule.  Here the shortened schedule is (iters,
+    densify_until) and the full one stretches both by the paper's ratios
+    (15k/9k for densification, 30k/24k for training).  Arms:
+      vanilla_full   3DGS's N = 2 split, full schedule
+      vanilla        N = 2 split, shortened schedule (-S)
+      vanilla_n5     five random children per split, shortened (Fig. 2's pilot)
+      vanilla_equal  N = 2 split, shortened, with the gradient threshold
+                     lowered until the final Gaussian count is that of the
+                     AdpSplit arm (a control for the count: Fig. 2 shows that
+                     more Gaussians alone do not give better reconstructions)
+      adpsplit       AdpSplit, shortened schedule."""
+    kw = dict(seed=seed)
+    short = dict(iters=iters, densify_until=densify_until)
+    full = dict(iters=int(round(iters * full_scale)), densify_until=int(round(densify_until * full_densify_scale)))
+    out = dict(schedules=dict(short=short, full=full))
+    out["vanilla_full"] = train_one(ctx, pb, TrainConfig(method="vanilla", **full, **kw), n_init, log)
+    out["vanilla"] = train_one(ctx, pb, TrainConfig(method="vanilla", **short, **kw), n_init, log)
+    out["vanilla_n5"] = train_one(ctx, pb, TrainConfig(method="vanilla", vanilla_n=5, **short, **kw), n_init, log)
+    out["adpsplit"] = train_one(ctx, pb, TrainConfig(method="adpsplit", **short, **kw), n_init, log)
+    # equal count: bisect the threshold's scale in log space towards AdpSplit's final count
+    target = out["adpsplit"]["final_n"]
+    thr0 = TrainConfig().grad_threshold_ndc
+    lo, hi = math.log(0.05), 0.0       # the final count falls as the threshold grows
+    best = None
+    for _ in range(match_tries):
+        mid = 0.5 * (lo + hi)
+        r = train_one(ctx, pb, TrainConfig(method="vanilla", grad_threshold_ndc=thr0 * math.exp(mid), **short, **kw),
+                      n_init, log)
+        r["threshold_scale"] = round(math.exp(mid), 4)
+        if best is None or abs(r["final_n"] - target) < abs(best["final_n"] - target):
+            best = r
+        if r["final_n"] > target:
+            lo = mid
+        else:
+            hi = mid
+    out["vanilla_equal"] = best
     return out

@@ -54,6 +54,8 @@ def make_step(ctx, st, method):
     if method == "adpsplit":
         regions = api.RegionBuffer(6 * 192 * 144 // 5)
         step = densify.DensifyStep(ctx, st["n"], 3, "adpsplit", api.SplitParams(), st["views"], st["gts"], regions)
+    elif method == "vanilla5":   # five random children per candidate (Fig. 2's pilot)
+        step = densify.DensifyStep(ctx, st["n"], 3, "vanilla", api.SplitParams(variant=api.VARIANT_FIXED_N, fixed_n=5))
     else:
         step = densify.DensifyStep(ctx, st["n"], 3, "vanilla")
     step.noise.copy_(torch.from_numpy(synth.vanilla_noise(step.cc, 5, step.noise_n)).view_as(step.noise))
@@ -68,7 +70,7 @@ def snapshot(step):
     return k, host(step.out, k), host(step.m_out, k), host(step.v_out, k), step.st3[:k].cpu().numpy()
 
 
-@pytest.mark.parametrize("method", ["adpsplit", "vanilla"])
+@pytest.mark.parametrize("method", ["adpsplit", "vanilla", "vanilla5"])
 def test_graph_replays_equal_the_eager_step(state, method):
     ctx = api.Context(0)
     st = state

@@ -129,6 +129,49 @@ def test_radix_sort_digit_widths(n, bits, radix_bits):
     np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[o])
 
 
+@pytest.mark.parametrize("n,lo,hi,rb", [(1, 0, 32, 8), (1000, 0, 13, 7), (8191, 0, 32, 8), (8192, 0, 32, 8),
+                                        (8193, 3, 20, 5), (300_001, 0, 32, 8), (2_097_151, 0, 32, 8),
+                                        (2_097_152, 0, 13, 7), (2_500_003, 0, 32, 4), (8_549_852, 0, 13, 7),
+                                        (8_549_852, 0, 13, 6), (777_777, 0, 32, 6)])
+@pytest.mark.parametrize("single", [True, False])
+def test_u32_sort_is_a_stable_sort(ctx, n, lo, hi, rb, single):
+    """The binning's 32-bit sorter, one launch per digit (decoupled
+    look-back) or three: stable on bits [lo, hi), both tile sizes of the
+    single-pass sort (8192 keys below 2^21 keys, 4096 above), partial last
+    tiles, runs of equal digits across tiles, digits of 4 to 8 bits, and the
+    gather of the last pass."""
+    rng = np.random.default_rng(n + lo * 7 + hi + rb)
+    keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    keys[::3] &= np.uint32(0x1FFF)          # equal low digits across tiles
+    keys[n // 2: n // 2 + n // 8] = np.uint32(12345)
+    vals = rng.permutation(n).astype(np.uint32)
+    src = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    kt = torch.from_numpy(keys.view(np.int32)).cuda()
+    vt = torch.from_numpy(vals.view(np.int32)).cuda()
+    st = torch.from_numpy(src.view(np.int32)).cuda()
+    dt = torch.zeros(n, dtype=torch.int32, device="cuda")
+    api.debug_sort_u32(ctx, kt, vt, lo, hi, rb, single, gather_src=st, gather_dst=dt)
+    sub = (keys.astype(np.uint64) >> np.uint64(lo)) & np.uint64((1 << (hi - lo)) - 1)
+    o = np.argsort(sub, kind="stable")
+    np.testing.assert_array_equal(kt.cpu().numpy().view(np.uint32), keys[o])
+    np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[o])
+    np.testing.assert_array_equal(dt.cpu().numpy().view(np.uint32), src[vals[o]])
+
+
+def test_u32_sort_repeated_calls_reuse_the_workspace(ctx):
+    """Consecutive single-pass sorts of decreasing sizes on one workspace
+    (the counters and look-back words are cleared per sort)."""
+    for k, n in enumerate((3_000_000, 1_000_000, 40_000, 5)):
+        rng = np.random.default_rng(k)
+        keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+        vals = np.arange(n, dtype=np.uint32)
+        kt = torch.from_numpy(keys.view(np.int32)).cuda()
+        vt = torch.from_numpy(vals.view(np.int32)).cuda()
+        api.debug_sort_u32(ctx, kt, vt, 0, 32, 8, True)
+        o = np.argsort(keys, kind="stable")
+        np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[o])
+
+
 # ---- C1: 2,000 Gaussians, 128x128, SH 0 ----------------------------------------------
 
 @pytest.fixture(scope="module")
@@ -496,26 +539,28 @@ def test_autograd_function_matches_oracle_gradients(c1):
     assert (r.vis_count.cpu().numpy() == (pr.valid == 1)).all()
 
 
-@pytest.mark.parametrize("batch,lpt,persistent,radix,cull", [(256, False, False, 8, True), (256, True, True, 8, True),
-                                                            (512, True, False, 6, True), (1024, True, True, 5, True),
-                                                            (1024, False, False, 4, True), (512, False, True, 7, True),
-                                                            (256, True, False, 7, False)])
-def test_tuning_never_changes_results(ctx, c2, batch, lpt, persistent, radix, cull):
+@pytest.mark.parametrize("batch,lpt,persistent,radix,cull,sp", [
+    (256, False, False, 8, True, 3), (256, True, True, 8, True, 3), (512, True, False, 6, True, 1),
+    (1024, True, True, 5, True, 2), (1024, False, False, 4, True, 3), (512, False, True, 7, True, 3),
+    (256, True, False, 7, False, 0)])
+def test_tuning_never_changes_results(ctx, c2, batch, lpt, persistent, radix, cull, sp):
     """Every launch tuning gives a bit-identical forward (same per-pixel
     operations in the same order) and gradients equal up to atomic order.
     The reference culls by the pixel box alone, so the ellipse block culling
-    is shown to drop no contributor on all 1,039,968 pixels."""
+    is shown to drop no contributor on all 1,039,968 pixels, and sorts with
+    three launches per digit, so the single-pass sorts are shown to give the
+    same keys, values and ranges."""
     cam = c2["cam"]
     ctx2 = api.Context(0)
     api.set_tuning(ctx2, lds_batch=batch, longest_first=lpt, persistent=persistent, radix_bits=radix,
-                   block_cull=cull)
+                   block_cull=cull, single_pass_sort=sp)
     g = c2["g"]
     frame = api.Frame(ctx2, g.n, cam.width, cam.height)
     img = api.render(ctx2, g, cam, frame, gt=torch.from_numpy(c2["gt"]).cuda())
     G = torch.from_numpy(np.random.default_rng(9).normal(size=(3, cam.height, cam.width)).astype(np.float32)).cuda()
     grads = api.render_backward(ctx2, g, cam, frame, G)
     ref_ctx = api.Context(0)
-    api.set_tuning(ref_ctx, lds_batch=256, longest_first=False, block_cull=False)
+    api.set_tuning(ref_ctx, lds_batch=256, longest_first=False, block_cull=False, single_pass_sort=0)
     ref_frame = api.Frame(ref_ctx, g.n, cam.width, cam.height)
     ref = api.render(ref_ctx, g, cam, ref_frame, gt=torch.from_numpy(c2["gt"]).cuda())
     ref_grads = api.render_backward(ref_ctx, g, cam, ref_frame, G)

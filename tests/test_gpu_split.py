@@ -149,11 +149,12 @@ def views_for(k, W, H, seed):
     return synth.sphere_cameras(k, 4.0, [(W, H)], seed=seed)
 
 
-def run_both_split(ctx, scene, views, maps_per_view, is_cand, prm, seed):
+def run_both_split(ctx, scene, views, maps_per_view, is_cand, prm, seed, regions_out=None):
     n = scene.n
     attr_o = np.zeros(n, np.int32)
     regs_o = []
-    regions = api.RegionBuffer(sum(m[2].size for m in maps_per_view) // 5 + 16)
+    # a kept region holds at least m_min pixels (one, before the area filter)
+    regions = api.RegionBuffer(sum(m[2].size for m in maps_per_view) // max(1, min(prm.m_min, 5)) + 16)
     attr_g = torch.zeros(n, dtype=torch.int32, device="cuda")
     for v, (img, gt, dom) in enumerate(maps_per_view):
         r, _ = oracle.error_stats(img, gt, dom, is_cand, v, prm, attr_o)
@@ -169,6 +170,8 @@ def run_both_split(ctx, scene, views, maps_per_view, is_cand, prm, seed):
     out, mode, count, offset, n_out = api.adaptive_split(ctx, g, torch.from_numpy(cand).cuda(), regions, views, attr_g,
                                                          gparams(prm), torch.from_numpy(noise).cuda())
     torch.cuda.synchronize()
+    if regions_out is not None:
+        regions_out.update(want=regs_o, got=regions.host(), attr_g=attr_g.cpu().numpy())
     return want, (out, mode.cpu().numpy(), count.cpu().numpy(), offset.cpu().numpy(), int(n_out.item())), attr_o
 
 
@@ -240,6 +243,32 @@ def test_split_variants_and_readings(ctx, variant, flags, fixed_n):
     want, got, attr = run_both_split(ctx, scene, views, maps, is_cand, prm, seed)
     say("variant %d flags %d: modes %s, new rows %d" % (variant, flags, np.bincount(want["mode"], minlength=4),
                                                        want["count"].sum()))
+    compare_split(want, got)
+
+
+@pytest.mark.parametrize("knob,value", [("L", 1), ("L", 2), ("L", 5), ("L", 8), ("m_min", 1), ("m_min", 20),
+                                        ("m_min", 80), ("n_max", 2), ("n_max", 5), ("n_max", 39), ("r_erode", 0),
+                                        ("r_erode", 4), ("r_erode", 8)])
+def test_split_at_swept_knob_settings(ctx, knob, value):
+    """Every value the knob sweep takes (Sec. 5 and the appendix's
+    sensitivity study: L, m_min, N_max, r_erode; one knob off the defaults at
+    a time): region records, attribution counts, modes, counts, offsets and
+    output order bit-exact, children to the float bars."""
+    H, W, n, V = 120, 160, 60, 4
+    seed = 300 + sum(map(ord, knob)) + value
+    scene = synth.scene_uniform_sh0(n, seed=seed)
+    views = views_for(V, W, H, seed)
+    rng = np.random.default_rng(seed)
+    is_cand = (rng.uniform(size=n) < 0.5).astype(np.uint8)
+    maps = [synth.error_map_fixture(H, W, n, seed=seed * 100 + v, n_sites=60, n_blobs=80)[:3] for v in range(V)]
+    prm = oracle.SplitParams(**{knob: value})
+    regs = {}
+    want, got, attr = run_both_split(ctx, scene, views, maps, is_cand, prm, seed, regions_out=regs)
+    say("%s=%d: %d regions, modes %s, new rows %d" % (knob, value, len(regs["want"]),
+                                                      np.bincount(want["mode"], minlength=3), want["count"].sum()))
+    assert len(regs["want"]) > 0
+    compare_regions(regs["got"], regs["want"])
+    np.testing.assert_array_equal(regs["attr_g"], attr)
     compare_split(want, got)
 
 

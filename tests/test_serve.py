@@ -153,6 +153,64 @@ def test_admission_by_footprint():
         sched.admit(big)
 
 
+class PairExecutor(FakeExecutor):
+    """Reports each batch's pair count (per request a fixed function of its
+    scene and resolution); a batch over the slot's pair capacity is rendered
+    again one view at a time (the slot stays busy) before it completes."""
+
+    def __init__(self, clock, n_slots, pairs_of, cap):
+        super().__init__(clock, n_slots)
+        self.pairs_of, self.cap = pairs_of, cap
+        self.again, self.overflows, self.batch_pairs = set(), 0, []
+
+    def retire(self, slot, batch):
+        pairs = sum(self.pairs_of(r) for r in batch)
+        if slot in self.again:
+            self.again.discard(slot)
+            del self.end[slot]
+            for r in batch:
+                r.image = ("image", r.rid)
+            return True, None
+        self.batch_pairs.append((pairs, [r.rid for r in batch]))
+        if pairs > self.cap:
+            self.again.add(slot)
+            self.overflows += 1
+            self.end[slot] = self.clock() + self.overhead * len(batch)
+            return False, pairs
+        del self.end[slot]
+        for r in batch:
+            r.image = ("image", r.rid)
+        return True, pairs
+
+
+def test_admission_learns_pairs_and_overflows_retry_on_the_slot():
+    reqs = make(600, 3000.0, seed=21)
+    pairs_of = lambda r: SCENES[r.scene] * r.pixels // 100_000     # up to 41M pairs per view
+    sp = spec()
+    sp.pairs = 60_000_000
+    clock = FakeClock()
+    ex = PairExecutor(clock, 2, pairs_of, sp.pairs)
+    sched = serve.Scheduler(ex, sp, SCENES, keep_images=False)
+
+    def spin():
+        clock.t += 1e-4
+    serve.serve_open_loop(sched, reqs, clock=clock, spin=spin)
+    assert sorted(r.rid for r in sched.completed) == list(range(600))
+    assert all(r.image is None for r in reqs)
+    # estimates are exact once a (scene, resolution) has been seen, since
+    # the first shares follow Gaussians x pixels, which the pairs do here
+    for (sc, w, h), est in sched.pair_est.items():
+        assert est == pytest.approx(SCENES[sc] * w * h // 100_000, rel=1e-6)
+    assert sched.pair_bound > 0, "the pair estimate must limit some batches"
+    seen = set()
+    for pairs, rids in ex.batch_pairs:
+        keys = {(reqs[i].scene, reqs[i].cam.width, reqs[i].cam.height) for i in rids}
+        if keys <= seen:
+            assert pairs <= 0.9 * sp.pairs or len(rids) == 1
+        seen |= keys
+    assert 0 < ex.overflows <= 12     # only batches holding a resolution/scene not seen before
+
+
 def test_latency_stats():
     reqs = [serve.Request(k, 0, Cam(100, 100), 0.0) for k in range(100)]
     for k, r in enumerate(reqs):
