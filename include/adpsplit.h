@@ -145,12 +145,12 @@ typedef struct {
     uint32_t *n_keys;         /* [2] (tile, entry) pairs of the last render, all views: [0] the
                                  number it needed, [1] the number written to keys / vals
                                  (fewer when [0] > key_cap) */
-    uint32_t *keys;           /* [key_cap] sorted global tile ids */
+    uint32_t *keys;           /* [key_cap] sorted global bin ids (tile ids when bin_size = 16) */
     uint32_t *vals;           /* [key_cap] entry id of each sorted pair (entry = ent_base of its view + Gaussian id) */
     uint32_t *ranges;         /* [tiles][2] start, end into keys/vals of the view's tiles */
     uint32_t *depth_key;      /* [n] float bits of view-space depth */
     int16_t *box;             /* [n][4] inclusive pixel box x0, y0, x1, y1 (valid if ntiles > 0) */
-    uint32_t *ntiles;         /* [n] tiles touched (0 = culled) */
+    uint32_t *ntiles;         /* [n] bins touched (0 = culled) */
     float *rec;               /* [n][12] blend record: mean hi (2), mean lo (2), conic (3), opacity, rgb (3), pad */
     float *t_final;           /* [H][W] final transmittance */
     uint32_t *last;           /* [H][W] index into vals of the last contributor (valid if n_contrib > 0) */
@@ -162,6 +162,11 @@ typedef struct {
                                  entry e (mean x, y; conic a, b, c; opacity; colour r, g, b) at
                                  grad2d[e * grad2d_stride + k], grad2d_stride = 9 */
     int64_t grad2d_stride;
+    int32_t bin_size;         /* pixels per side of the squares the pairs were binned by (16 or 32):
+                                 keys hold global bin ids, ntiles counts bins, and each 16 x 16
+                                 tile's range is that of the bin holding it */
+    int32_t bin_base;         /* global id of the view's first bin */
+    int32_t bins_x, bins_y;
 } as_frame_view;
 
 /* ---- context and state ------------------------------------------------------ */
@@ -493,12 +498,17 @@ typedef struct {
     int32_t single_pass_sort; /* bit 0: the depth sort, bit 1: the pair sort takes one launch per digit
                                 (decoupled look-back across blocks) instead of three (reduce, scan,
                                 scatter); the same order either way */
+    int32_t bin_tile;         /* pixels per side of the squares (tile, Gaussian) pairs are binned by:
+                                16 (one blend tile) or 32 (2 x 2 blend tiles of 16 x 16 share one
+                                list, so fewer pairs are emitted and sorted; each tile skips the
+                                records its box masks exclude).  The blend tiles stay 16 x 16 and
+                                every output is the same */
 } as_tuning;
 
 /* Set / read the context's tuning (defaults: lds_batch 256, longest_first 1,
- * persistent 0, radix_bits 8, block_cull 1, single_pass_sort 0).  AS_ERR_ARG for an
- * lds_batch other than 256, 512 or 1024, a radix_bits outside 4..8 or a
- * single_pass_sort outside 0..3. */
+ * persistent 0, radix_bits 8, block_cull 1, single_pass_sort 0, bin_tile 16).
+ * AS_ERR_ARG for an lds_batch other than 256, 512 or 1024, a radix_bits outside
+ * 4..8, a single_pass_sort outside 0..3 or a bin_tile other than 16 or 32. */
 as_status as_set_tuning(as_ctx *ctx, const as_tuning *t);
 as_status as_get_tuning(const as_ctx *ctx, as_tuning *t);
 

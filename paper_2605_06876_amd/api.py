@@ -74,7 +74,8 @@ class _FrameView(ctypes.Structure):
                 ("ent_base", ctypes.c_uint32)] + [
         (nm, ctypes.c_void_p) for nm in ("n_keys", "keys", "vals", "ranges", "depth_key", "box", "ntiles", "rec",
                                          "t_final", "last", "n_contrib", "dom", "err", "err_minmax", "grad2d")] + [
-        ("grad2d_stride", ctypes.c_int64)]
+        ("grad2d_stride", ctypes.c_int64), ("bin_size", ctypes.c_int32), ("bin_base", ctypes.c_int32),
+        ("bins_x", ctypes.c_int32), ("bins_y", ctypes.c_int32)]
 
 
 REGION_DTYPE = np.dtype([
@@ -380,9 +381,11 @@ class Frame:
     def host_state(self, n, view=0):
         """Keys, values, ranges, per-Gaussian and per-pixel state of one view
         as numpy arrays.  `tile_keys`/`vals` are the sorted pairs of all views
-        (global tile ids, entry ids); `keys` restates each pair as
-        (tile of the view) << 32 | depth bits, the form of a (tile | depth)
-        sort, and `gauss` its Gaussian id (meaningful for this view's pairs)."""
+        (global bin ids, entry ids; bins are the 16 x 16 tiles unless the
+        tuning bins by 32, `bin_size`); `keys` restates each pair as
+        (bin of the view) << 32 | depth bits, the form of a (bin | depth)
+        sort, and `gauss` its Gaussian id (meaningful for this view's pairs);
+        `ranges` are per 16 x 16 tile (a tile's range is its bin's)."""
         v = self.view(view)
         K = self.n_emitted()
         H, W = v.height, v.width
@@ -392,7 +395,7 @@ class Frame:
         vals = self._dev(v.vals, 4 * K).view(np.uint32)
         ne = int(vals.max()) + 1 if K else 0
         dk_all = self._dev(v.depth_key - 4 * v.ent_base, 4 * ne).view(np.uint32)
-        keys = ((tk.astype(np.int64) - v.tile_base).astype(np.uint64) << np.uint64(32)) | \
+        keys = ((tk.astype(np.int64) - v.bin_base).astype(np.uint64) << np.uint64(32)) | \
             (dk_all[vals].astype(np.uint64) if K else np.zeros(0, np.uint64))
         return dict(
             n_keys=self.n_keys(), tile_keys=tk, keys=keys, vals=vals,
@@ -406,7 +409,8 @@ class Frame:
             dom=self._dev(v.dom, 4 * P).view(np.int32).reshape(H, W),
             err=self._dev(v.err, 8 * P).view(np.float64).reshape(H, W),
             err_minmax=self._dev(v.err_minmax, 16).view(np.uint64),
-            tiles_x=v.tiles_x, tiles_y=v.tiles_y, tile_base=v.tile_base, ent_base=v.ent_base)
+            tiles_x=v.tiles_x, tiles_y=v.tiles_y, tile_base=v.tile_base, ent_base=v.ent_base, bin_size=v.bin_size,
+            bin_base=v.bin_base, bins_x=v.bins_x, bins_y=v.bins_y)
 
     def device_maps(self, view=0):
         """Device addresses of one view's per-pixel maps (for accumulate_error_stats)."""
@@ -770,15 +774,17 @@ def reset_opacity(ctx, g, max_opacity, m_op=None, v_op=None, stream=None):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("lds_batch", ctypes.c_int32), ("longest_first", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("radix_bits", ctypes.c_int32), ("block_cull", ctypes.c_int32), ("single_pass_sort", ctypes.c_int32)]
+                ("radix_bits", ctypes.c_int32), ("block_cull", ctypes.c_int32), ("single_pass_sort", ctypes.c_int32),
+                ("bin_tile", ctypes.c_int32)]
 
 
 def set_tuning(ctx, lds_batch=256, longest_first=True, persistent=False, radix_bits=8, block_cull=True,
-               single_pass_sort=0):
+               single_pass_sort=0, bin_tile=16):
     """as_set_tuning (single_pass_sort: bit 0 the depth sort, bit 1 the pair
-    sort take one launch per digit)."""
+    sort take one launch per digit; bin_tile: 16 or 32 pixel squares for
+    the pair binning)."""
     t = _Tuning(lds_batch, 1 if longest_first else 0, 1 if persistent else 0, radix_bits, 1 if block_cull else 0,
-                int(single_pass_sort))
+                int(single_pass_sort), int(bin_tile))
     _check(lib().as_set_tuning(ctx.handle, ctypes.byref(t)))
 
 
@@ -786,7 +792,8 @@ def get_tuning(ctx):
     t = _Tuning()
     _check(lib().as_get_tuning(ctx.handle, ctypes.byref(t)))
     return dict(lds_batch=t.lds_batch, longest_first=bool(t.longest_first), persistent=bool(t.persistent),
-                radix_bits=t.radix_bits, block_cull=bool(t.block_cull), single_pass_sort=t.single_pass_sort)
+                radix_bits=t.radix_bits, block_cull=bool(t.block_cull), single_pass_sort=t.single_pass_sort,
+                bin_tile=t.bin_tile)
 
 
 def timing_enable(ctx, on=True):

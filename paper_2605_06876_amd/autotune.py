@@ -5,10 +5,11 @@ are bit-identical across tunings (each pixel runs the same operations in the
 same order, and every radix width gives the same stable order), and the
 backward differs only in the order of its float atomics.  For a workload the
 tuner times the caller's own step (a render + backward by default) for every
-blend configuration (LDS depth x tile order x persistent grid), then for every
-radix digit width with the best blend configuration, then for the sorts'
+blend configuration (LDS depth x tile order x persistent grid), then for the
+binning square (16 or 32 pixels: the tile size of the pair lists; the blend
+tiles stay 16 x 16), then for every radix digit width, then for the sorts'
 launch structure (one launch per digit or three, for the depth and the pair
-sort), and keeps the fastest
+sort), each with the best choices so far, and keeps the fastest
 (the better of two interleaved rounds per candidate, after a warm-up).
 Results are cached in a JSON file keyed by the workload.
 """
@@ -33,12 +34,13 @@ def workload_key(width, height, n, sh_degree, views=1, arch="gfx950"):
 
 
 SORT_CANDIDATES = (0, 1, 2, 3)   # single-pass sorts: neither, depth only, pairs only, both
+BIN_CANDIDATES = (16, 32)        # pixels per side of the pair binning squares
 
 
 def name_of(t):
-    return "batch%d_%s_%s_r%d_sp%d" % (t["lds_batch"], "lpt" if t["longest_first"] else "grid",
-                                       "persistent" if t["persistent"] else "blocks", t["radix_bits"],
-                                       t.get("single_pass_sort", 0))
+    return "batch%d_%s_%s_bin%d_r%d_sp%d" % (t["lds_batch"], "lpt" if t["longest_first"] else "grid",
+                                             "persistent" if t["persistent"] else "blocks", t.get("bin_tile", 16),
+                                             t["radix_bits"], t.get("single_pass_sort", 0))
 
 
 def time_step(run, reps):
@@ -88,7 +90,8 @@ def autotune_step(ctx, run, key, reps=5, cache_path=DEFAULT_CACHE, use_cache=Tru
                 times[name_of(t)] = min(times.get(name_of(t), float("inf")), ms)
         return min(cands, key=lambda t: times[name_of(t)])
 
-    best = rounds([dict(c, radix_bits=8, single_pass_sort=0) for c in BLEND_CANDIDATES])
+    best = rounds([dict(c, radix_bits=8, single_pass_sort=0, bin_tile=16) for c in BLEND_CANDIDATES])
+    best = rounds([dict(best, bin_tile=bt) for bt in BIN_CANDIDATES])
     best = rounds([dict(best, radix_bits=rb) for rb in RADIX_CANDIDATES])
     best = rounds([dict(best, single_pass_sort=sp) for sp in SORT_CANDIDATES])
     api.set_tuning(ctx, **best)

@@ -138,7 +138,8 @@ void frame_buffers(as_frame *f, bool keys_only, V &&visit) {
         arr(&f->vals[k], key);
     }
     dbuf(f->sort_hist, sort_hist_bytes(key));
-    if (!(f->flags & AS_FRAME_FORWARD_ONLY)) arr(&f->bmask, key);
+    // block masks: one per sorted pair and blend tile of its bin (four for bins of 32)
+    if (!(f->flags & AS_FRAME_FORWARD_ONLY)) arr(&f->bmask, key * 4);
     if (keys_only) return;
     arr(&f->rec, ent); arr(&f->depth_key, ent); arr(&f->box, ent * 4); arr(&f->ntiles, ent); arr(&f->offsets, ent);
     arr(&f->grad2d, ent * 9);
@@ -534,6 +535,10 @@ as_status as_frame_get_view_of(const as_frame *f, int32_t view, as_frame_view *v
     v->err_minmax = f->err_minmax + 2 * (have ? view : 0);
     v->grad2d = f->grad2d + 9 * eb;
     v->grad2d_stride = 9;
+    v->bin_size = have ? 1 << vt.bin_shift : AS_TILE_W;
+    v->bin_base = have ? vt.bin_base[view] : 0;
+    v->bins_x = (W + v->bin_size - 1) / v->bin_size;
+    v->bins_y = (H + v->bin_size - 1) / v->bin_size;
     return AS_OK;
 }
 
@@ -568,7 +573,8 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     memset(&im, 0, sizeof(im));
     memset(&gi, 0, sizeof(gi));
     vt.n_views = n_views;
-    int64_t ents = 0, pix = 0, tiles = 0, max_n = 0;
+    vt.bin_shift = ctx->bin_tile == 32 ? 5 : 4;
+    int64_t ents = 0, pix = 0, tiles = 0, bins = 0, max_n = 0;
     const int deg = scenes[0].sh_degree;
     for (int v = 0; v < n_views; v++) {
         const as_gaussians *g = &scenes[v];
@@ -589,6 +595,11 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
         const int tx = (c->width + AS_TILE_W - 1) / AS_TILE_W, ty = (c->height + AS_TILE_H - 1) / AS_TILE_H;
         vt.tile_base[v] = (int32_t)tiles;
         vt.tiles_x[v] = tx;
+        const int bt = 1 << vt.bin_shift;
+        const int bx = (c->width + bt - 1) / bt, by = (c->height + bt - 1) / bt;
+        vt.bin_base[v] = (int32_t)bins;
+        vt.bins_x[v] = bx;
+        bins += (int64_t)bx * by;
         vt.ent_base[v] = (uint32_t)ents;
         vt.pix_base[v] = pix;
         vt.cam[v] = to_devcam(*c);
@@ -607,6 +618,7 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
         }
     }
     vt.tile_base[n_views] = (int32_t)tiles;
+    vt.bin_base[n_views] = (int32_t)bins;
     vt.ent_base[n_views] = (uint32_t)ents;
     vt.pix_base[n_views] = pix;
     const int64_t n = ents;
@@ -645,13 +657,13 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     {
         StageTimer t(ctx, AS_STAGE_SORT, s);
         // only the pairs written (a render over the capacity writes a prefix)
-        sel = radix_sort_u32(f->keys, f->vals, f->n_keys + 1, f->key_cap, n_hint, 0, tile_bits(tiles),
+        sel = radix_sort_u32(f->keys, f->vals, f->n_keys + 1, f->key_cap, n_hint, 0, tile_bits(bins),
                              ctx->radix_bits, f->sort_hist.p, s, nullptr, nullptr, (ctx->single_pass_sort & 2) != 0);
     }
     f->sorted_sel = sel;
     {
         StageTimer t(ctx, AS_STAGE_RANGES, s);
-        launch_ranges(f->keys[sel], f->n_keys + 1, f->key_cap, tiles, f->ranges, s);
+        launch_ranges(f->keys[sel], f->n_keys + 1, f->key_cap, bins, vt, f->ranges, s);
         f->use_order = ctx->longest_first;
         if (f->use_order) launch_tile_order(f->ranges, (int)tiles, f->tile_order, s);
     }
@@ -1002,12 +1014,17 @@ as_status as_set_tuning(as_ctx *ctx, const as_tuning *t) {
         as_set_error("as_set_tuning: single_pass_sort %d not in 0..3", t->single_pass_sort);
         return AS_ERR_ARG;
     }
+    if (t->bin_tile != 16 && t->bin_tile != 32) {
+        as_set_error("as_set_tuning: bin_tile %d not 16 or 32", t->bin_tile);
+        return AS_ERR_ARG;
+    }
     ctx->lds_batch = t->lds_batch;
     ctx->longest_first = t->longest_first != 0;
     ctx->persistent = t->persistent != 0;
     ctx->radix_bits = t->radix_bits;
     ctx->block_cull = t->block_cull != 0;
     ctx->single_pass_sort = t->single_pass_sort;
+    ctx->bin_tile = t->bin_tile;
     return AS_OK;
 }
 
@@ -1019,6 +1036,7 @@ as_status as_get_tuning(const as_ctx *ctx, as_tuning *t) {
     t->radix_bits = ctx->radix_bits;
     t->block_cull = ctx->block_cull;
     t->single_pass_sort = ctx->single_pass_sort;
+    t->bin_tile = ctx->bin_tile;
     return AS_OK;
 }
 

@@ -118,9 +118,9 @@ void scan_impl(const Tin *in, Tout *out, int64_t n, Tout *total, void *tmp, hipS
 
 // ---- key emission -------------------------------------------------------------------
 
-// Tile keys in depth order: rank r holds entry order[r] and owns key positions
-// [offsets[r], offsets[r] + ntiles) (the scan of ntiles in that order), its
-// tiles row-major over its tile rectangle, as global tile ids of its view.
+// Bin keys in depth order: rank r holds entry order[r] and owns key positions
+// [offsets[r], offsets[r] + ntiles) (the scan of its bin counts in that
+// order), its bins row-major over its bin rectangle, as global bin ids.
 // Consecutive ranks own consecutive positions, so a wave writes one contiguous
 // run of keys: each lane takes positions lane, lane + 64, ... of the run and
 // finds its owner among the wave's 64 ranks by binary search over their
@@ -158,10 +158,11 @@ __global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *
         if (nt) {
             const int v = view_of_entry(vt, e);
             const short4 b = box[e];
-            const int tx0 = b.x / AS_TILE_W, ty0 = b.y / AS_TILE_H;
-            s_t0[w][lane] = vt.tile_base[v] + ty0 * vt.tiles_x[v] + tx0;
-            s_bw[w][lane] = b.z / AS_TILE_W - tx0 + 1;
-            s_tx[w][lane] = vt.tiles_x[v];
+            const int bs = vt.bin_shift;
+            const int tx0 = b.x >> bs, ty0 = b.y >> bs;
+            s_t0[w][lane] = vt.bin_base[v] + ty0 * vt.bins_x[v] + tx0;
+            s_bw[w][lane] = (b.z >> bs) - tx0 + 1;
+            s_tx[w][lane] = vt.bins_x[v];
         }
     }
     s_off[w][lane] = off;   // non-decreasing over the valid ranks; the sentinel sorts last
@@ -189,11 +190,28 @@ __global__ void __launch_bounds__(256) k_emit_sorted(int64_t n, const uint32_t *
     }
 }
 
-// (depth key, entry) pairs of every entry for the depth sort.
-// [start, end) of every tile in the sorted tile keys (tiles without keys keep
-// the [0, 0) the caller filled).
-__global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles,
-                         uint32_t *__restrict__ ranges) {
+// [start, end) of every bin in the sorted bin keys, written as the range of
+// each blend tile of the bin (tiles without keys keep the [0, 0) the caller
+// filled).
+__device__ __forceinline__ void set_bin_range(const ViewTable &vt, uint32_t bin, int end, uint32_t val,
+                                              uint32_t *__restrict__ ranges) {
+    if (vt.bin_shift == 4) {   // bins are the tiles
+        ranges[2 * bin + end] = val;
+        return;
+    }
+    const int v = view_of_bin(vt, (int)bin);
+    const int lb = (int)bin - vt.bin_base[v], bx = lb % vt.bins_x[v], by = lb / vt.bins_x[v];
+    const int tx_n = vt.tiles_x[v], ty_n = (vt.tile_base[v + 1] - vt.tile_base[v]) / tx_n;
+    const int f = 1 << (vt.bin_shift - 4);
+    for (int dy = 0; dy < f; dy++)
+        for (int dx = 0; dx < f; dx++) {
+            const int tx = bx * f + dx, ty = by * f + dy;
+            if (tx < tx_n && ty < ty_n) ranges[2 * (vt.tile_base[v] + ty * tx_n + tx) + end] = val;
+        }
+}
+
+__global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *n_dev, int64_t cap, int64_t n_bins,
+                         const ViewTable vt, uint32_t *__restrict__ ranges) {
     int64_t n = *n_dev;
     if (n > cap) n = cap;
     // four consecutive keys per thread from one 16-byte load (the buffers are
@@ -213,9 +231,9 @@ __global__ void k_ranges(const uint32_t *__restrict__ keys, const uint32_t *n_de
             if (i >= n) break;
             const uint32_t t = k[j];
             const uint32_t nx = j < 3 ? (i + 1 < n ? k[j + 1] : NONE) : after;
-            if (t < (uint64_t)n_tiles) {
-                if (prev != t) ranges[2 * t] = (uint32_t)i;
-                if (nx != t) ranges[2 * t + 1] = (uint32_t)(i + 1);
+            if (t < (uint64_t)n_bins) {
+                if (prev != t) set_bin_range(vt, t, 0, (uint32_t)i, ranges);
+                if (nx != t) set_bin_range(vt, t, 1, (uint32_t)(i + 1), ranges);
             }
             prev = t;
         }
@@ -277,10 +295,10 @@ void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, c
                        2 * n_tiles);
 }
 
-void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
-                   hipStream_t s) {
+void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_bins, const ViewTable &vt,
+                   uint32_t *ranges, hipStream_t s) {
     // the key emission has zeroed the ranges
-    hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, s, keys, n_dev, cap, n_tiles, ranges);
+    hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, s, keys, n_dev, cap, n_bins, vt, ranges);
 }
 
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) { fill_impl<uint8_t>(p, v, n, s); }

@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                     const uint32_t bm = block_mask(sr, ellipse != 0);
                     sh.rec[t] = sr;
                     sh.bm[t] = (uint16_t)bm;
-                    if (bm_out) bm_out[b0 + t] = (uint16_t)bm;   // the reverse pass reuses it
+                    if (bm_out) bm_out[mask_slot(vt, b0 + t, tx, ty)] = (uint16_t)bm;   // the reverse pass reuses it
                 }
                 if (b0 + BATCH + t < end) fetch(vals, rec, box, b0 + BATCH + t, nf[k]);
             }
@@ -619,7 +619,7 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
             for (int k = 0; k < R; k++)
                 if (b0 + k * BWD_BLOCK + tid < s1) {
                     fetch(vals, rec, box, b0 + k * BWD_BLOCK + tid, nf[k]);
-                    if (bm_in) nbm[k] = bm_in[b0 + k * BWD_BLOCK + tid];
+                    if (bm_in) nbm[k] = bm_in[mask_slot(vt, b0 + k * BWD_BLOCK + tid, tx, ty)];
                 }
         }
         for (uint32_t b1 = s1; b1 > s0;) {
@@ -635,7 +635,7 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
                 }
                 if (n0 + t < n1) {
                     fetch(vals, rec, box, n0 + t, nf[k]);
-                    if (bm_in) nbm[k] = bm_in[n0 + t];
+                    if (bm_in) nbm[k] = bm_in[mask_slot(vt, n0 + t, tx, ty)];
                 }
             }
             __syncthreads();

@@ -72,6 +72,12 @@ struct ViewTable {
     int32_t n_views;
     int32_t tile_base[AS_MAX_VIEWS + 1];
     int32_t tiles_x[AS_MAX_VIEWS];
+    // Pairs are binned by square bins of 2^bin_shift pixels (16 or 32): a bin
+    // of 32 holds the 2 x 2 blend tiles of 16 x 16 pixels it covers, which
+    // share its pair list.
+    int32_t bin_shift;
+    int32_t bin_base[AS_MAX_VIEWS + 1];
+    int32_t bins_x[AS_MAX_VIEWS];
     uint32_t ent_base[AS_MAX_VIEWS + 1];
     int64_t pix_base[AS_MAX_VIEWS + 1];
     DevCam cam[AS_MAX_VIEWS];
@@ -120,8 +126,9 @@ struct as_frame {
     uint32_t *tile_hi;     // [tiles] one past the tile's last contributor (0: none), from the forward blend
     float *ckpt;           // [tile_cap][AS_CK_MAX][256][4] per pixel (T, colour behind) at the forward's batch
                            // boundaries; NULL in forward-only frames
-    uint16_t *bmask;       // [key_cap] per sorted pair: the 4x4 pixel blocks of its tile it may contribute to,
-                           // from the forward blend for the reverse blend; NULL in forward-only frames
+    uint16_t *bmask;       // [key_cap][4] per sorted pair and blend tile of its bin (mask_slot): the 4x4 pixel
+                           // blocks of the tile it may contribute to, from the forward blend for the reverse
+                           // blend; NULL in forward-only frames
     int bm_written;        // the last render wrote bmask for every pair the reverse pass walks
     uint32_t *bwd_items;   // [tile_cap * (AS_CK_MAX + 1)][2] (tile, segment) work items of the reverse blend
     uint32_t *n_items;     // [1] device count of bwd_items
@@ -166,6 +173,7 @@ struct as_ctx {
     int radix_bits = 8;
     int block_cull = 1;
     int single_pass_sort = 0;   // bit 0 depth sort, bit 1 pair sort
+    int bin_tile = 16;          // pixels per side of the binning squares (16 or 32)
     int n_cu = 0;                 // compute units of the device
     int timing = 0;
     StageRec *recs = nullptr;     // recorded stage event pairs
@@ -230,8 +238,8 @@ void launch_emit_sorted(int64_t n, const uint32_t *order, const ViewTable &vt, c
                         const uint32_t *nt_sorted, const uint32_t *offsets, int64_t key_cap, uint32_t *keys,
                         uint32_t *vals, uint32_t *n_emit, uint32_t *ranges, int64_t n_tiles, hipStream_t s);
 // [start, end) of each tile with keys (ranges emptied by launch_emit_sorted).
-void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_tiles, uint32_t *ranges,
-                   hipStream_t s);
+void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, int64_t cap, int64_t n_bins, const ViewTable &vt,
+                   uint32_t *ranges, hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
@@ -379,6 +387,17 @@ __device__ __forceinline__ int view_of_tile(const ViewTable &vt, int tile) {
     int v = 0;
     for (int k = 1; k < vt.n_views; k++) v += tile >= vt.tile_base[k] ? 1 : 0;
     return v;
+}
+__device__ __forceinline__ int view_of_bin(const ViewTable &vt, int bin) {
+    int v = 0;
+    for (int k = 1; k < vt.n_views; k++) v += bin >= vt.bin_base[k] ? 1 : 0;
+    return v;
+}
+// Index of a blend tile's block mask for sorted pair i: bins of 32 keep the
+// masks of their four tiles side by side.
+__device__ __forceinline__ size_t mask_slot(const ViewTable &vt, uint32_t i, int tx, int ty) {
+    const int q = vt.bin_shift - 4;
+    return ((size_t)i << (2 * q)) + (size_t)(((ty & q) << q) | (tx & q));
 }
 __device__ __forceinline__ int view_of_entry(const ViewTable &vt, uint32_t e) {
     int v = 0;

@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const View
         rr.rgb = make_float4((float)col[0], (float)col[1], (float)col[2], 0.f);
         const int ix0 = (int)x0, iy0 = (int)y0, ix1 = (int)x1, iy1 = (int)y1;
         bx = make_short4((short)ix0, (short)iy0, (short)ix1, (short)iy1);
-        nt = (uint32_t)((ix1 / AS_TILE_W - ix0 / AS_TILE_W + 1) * (iy1 / AS_TILE_H - iy0 / AS_TILE_H + 1));
+        const int bs = vt.bin_shift;   // bins touched (the box lies in the image: no negative coordinates)
+        nt = (uint32_t)(((ix1 >> bs) - (ix0 >> bs) + 1) * ((iy1 >> bs) - (iy0 >> bs) + 1));
     } while (0);
 
     rec[e] = rr;

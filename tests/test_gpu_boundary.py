@@ -42,7 +42,7 @@ def test_size_queries_match_set_up():
     assert q_frame == api.frame_bytes(1, n, W * H, tiles, key_cap)
     # a forward-only frame holds neither the checkpoints nor the per-pair block masks
     assert (api.frame_bytes(1, n, W * H, tiles, key_cap, forward_only=True) ==
-            q_frame - (tiles * 3 * 256 * 16 + 256) - (key_cap * 2 + 256))
+            q_frame - (tiles * 3 * 256 * 16 + 256) - (key_cap * 8 + 256))
     f0 = free_bytes()
     frame = api.Frame(ctx, n, W, H, key_cap=key_cap, auto_grow=False)
     f1 = free_bytes()
