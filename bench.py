@@ -66,6 +66,9 @@ def _args():
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="Poisson arrivals of the serving leg (seconds)")
     ap.add_argument("--json", default="", help="also write the JSON line to this file")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tuning)")
+    ap.add_argument("--tuning", default="",
+                    help="skip the autotuner and set this tuning, e.g. lds_batch=256,longest_first=1,bin_tile=32 "
+                         "(fields of api.set_tuning; the profiles replay the bench's choice with it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -110,7 +113,11 @@ def training_step_bench(args):
     grads = api.Gaussians.empty(n, scene.sh_degree)
     dm = frame.device_maps()
     from paper_2605_06876_amd import autotune
-    if args.no_tune:
+    if args.tuning:
+        kv = dict(item.split("=") for item in args.tuning.split(",") if item)
+        api.set_tuning(ctx, **{k: int(v) for k, v in kv.items()})
+        best, tune_ms = api.get_tuning(ctx), {}
+    elif args.no_tune:
         best, tune_ms = api.get_tuning(ctx), {}
     else:
         log("bench: autotuning the blend launch (untimed)")

@@ -107,10 +107,49 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(const Tin *in, int64
     }
 }
 
+// Up to SCAN_DIRECT_BLOCKS blocks, the downsweep takes each block's offset
+// by summing the block sums before it itself (at most a few loads per
+// thread), so the scan is two launches instead of three; the last block also
+// writes the total.
+constexpr int64_t SCAN_DIRECT_BLOCKS = 1024;
+
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down_direct(const Tin *in, int64_t n,
+                                                                   const Tout *__restrict__ partials, Tout *out,
+                                                                   Tout *__restrict__ total) {
+    __shared__ Tout s_wave[4];
+    Tout pre = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_THREADS) pre += partials[b];
+    Tout ptot;
+    block_excl_scan<Tout>(pre, s_wave, &ptot);   // ptot: the sum of the block sums before this block
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    Tout v[SCAN_ITEMS];
+    Tout sum = 0;
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        const int64_t idx = base + k;
+        v[k] = idx < n ? (Tout)in[idx] : (Tout)0;
+        sum += v[k];
+    }
+    Tout tot;
+    Tout run = block_excl_scan<Tout>(sum, s_wave, &tot) + ptot;
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        const int64_t idx = base + k;
+        if (idx < n) out[idx] = run;
+        run += v[k];
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = ptot + tot;
+}
+
 template <typename Tin, typename Tout>
 void scan_impl(const Tin *in, Tout *out, int64_t n, Tout *total, void *tmp, hipStream_t s) {
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     Tout *partials = reinterpret_cast<Tout *>(tmp);
+    if (n > 0 && nb <= SCAN_DIRECT_BLOCKS) {
+        hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, n, partials);
+        hipLaunchKernelGGL((k_scan_down_direct<Tin, Tout>), dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, n,
+                           partials, out, total);
+        return;
+    }
     if (n > 0) hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, n, partials);
     hipLaunchKernelGGL((k_scan_partials<Tout>), dim3(1), dim3(SCAN_THREADS), 0, s, partials, nb, total);
     if (n > 0) hipLaunchKernelGGL((k_scan_down<Tin, Tout>), dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, n, partials, out);

@@ -157,7 +157,8 @@ __global__ void __launch_bounds__(ET * ET) k_erode_ccl_local(int W, int H, int t
                                                              uint8_t *__restrict__ B,
                                                              const uint8_t *__restrict__ is_cand,
                                                              int32_t *__restrict__ attr,
-                                                             int32_t *__restrict__ label) {
+                                                             int32_t *__restrict__ label,
+                                                             unsigned long long *__restrict__ mom) {
     __shared__ uint8_t s_m[ES * ES];
     __shared__ uint8_t s_row[ES * ET];
     __shared__ int32_t s_par[ET * ET];
@@ -249,23 +250,37 @@ __global__ void __launch_bounds__(ET * ET) k_erode_ccl_local(int W, int H, int t
         if (active) {
             const int rt = lds_find(s_par, tid);
             lab = (int32_t)((int64_t)(oy + rt / ET) * W + ox + rt % ET);
+            // every component's final root (its smallest index) is the local
+            // root of its part in that tile: the moments are cleared there
+            if (rt == tid)
+                for (int k = 0; k < 6; k++) mom[u * 6 + k] = 0ull;
         }
         label[u] = lab;
     }
 }
 
 // Join the tile-local components across tile borders: only pixels whose W,
-// NW, N or NE neighbour lies in another tile link, with the global
+// NW, N or NE neighbour lies in another tile link (a tile's top row, left
+// and right columns: 3 ET - 2 pixels, one thread each), with the global
 // union-find (roots are the smallest image index).
-__global__ void k_ccl_border(int W, int H, const int32_t *__restrict__ dom, const uint8_t *__restrict__ B,
-                             int32_t *label) {
-    const int64_t P = (int64_t)W * H;
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= P) return;
-    const int x = (int)(u % W), y = (int)(u / W);
-    const int lx = x % ET, ly = y % ET;
-    if (lx != 0 && ly != 0 && lx != ET - 1) return;
-    if (uf_load(label, (int32_t)u) < 0) return;
+constexpr int ES_BORDER = 3 * ET - 2;
+__global__ void k_ccl_border(int W, int H, int tiles_x, int64_t n_tiles, const int32_t *__restrict__ dom,
+                             const uint8_t *__restrict__ B, int32_t *label) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tiles * ES_BORDER) return;
+    const int64_t t = i / ES_BORDER;
+    const int j = (int)(i - t * ES_BORDER);
+    // j < ET: top row; then the left and the right column below it
+    const int lx = j < ET ? j : (j < 2 * ET - 1 ? 0 : ET - 1);
+    const int ly = j < ET ? 0 : (j < 2 * ET - 1 ? j - ET + 1 : j - 2 * ET + 2);
+    const int x = (int)(t % tiles_x) * ET + lx, y = (int)(t / tiles_x) * ET + ly;
+    if (x >= W || y >= H) return;
+    const int64_t u = (int64_t)y * W + x;
+    // a label's sign (active or not) never changes in this pass, only the
+    // values of roots do: plain loads decide activity, the union-find reads
+    // coherently
+    const volatile int32_t *lv = label;
+    if (lv[u] < 0) return;
     const int32_t d = dom[u];
     const uint8_t b = B[u];
     const int nx[4] = {-1, -1, 0, 1};
@@ -275,33 +290,23 @@ __global__ void k_ccl_border(int W, int H, const int32_t *__restrict__ dom, cons
         if (xx < 0 || yy < 0 || xx >= W) continue;
         if (xx / ET == x / ET && yy / ET == y / ET) continue;   // joined by the local pass
         const int64_t q = (int64_t)yy * W + xx;
-        if (uf_load(label, (int32_t)q) < 0) continue;
-        if (dom[q] != d || B[q] != b) continue;
+        if (dom[q] != d || B[q] != b || lv[q] < 0) continue;
         uf_unite(label, (int32_t)u, (int32_t)q);
     }
 }
 
-// Every active pixel's label becomes its root; each root clears its moments.
-__global__ void k_ccl_flatten(int64_t P, int32_t *label, unsigned long long *__restrict__ mom) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= P) return;
-    if (label[u] < 0) return;
-    const int32_t r = uf_find(label, (int32_t)u);
-    label[u] = r;
-    if (r == (int32_t)u)
-        for (int k = 0; k < 6; k++) mom[u * 6 + k] = 0ull;
-}
-
 // Exact integer moments A, Sx, Sy, Sxx, Sxy, Syy per component, stored at the
-// component's root pixel.
+// component's root pixel (the end of the pixel's parent chain: the labels no
+// longer change, so plain loads follow it).
 __global__ void k_moments(int W, int H, const int32_t *__restrict__ label, unsigned long long *__restrict__ mom) {
     const int64_t P = (int64_t)W * H;
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t s = -1;
     int64_t v[6] = {0, 0, 0, 0, 0, 0};
     if (u < P) {
-        const int32_t l = label[u];
+        int32_t l = label[u];
         if (l >= 0) {
+            for (int32_t p = label[l]; p != l; p = label[l]) l = p;
             s = l;
             const int64_t x = u % W, y = u / W;
             v[0] = 1; v[1] = x; v[2] = y; v[3] = x * x; v[4] = x * y; v[5] = y * y;
@@ -600,9 +605,10 @@ void es_launch(const EsScratch &sc, int W, int H, const double *err, const uint6
     // classification, attribution, erosion and the tile-local components in one pass
     hipLaunchKernelGGL(k_erode_ccl_local, dim3(tiles), dim3(ET * ET), 0, s, W, H, tiles_x, p.r_erode, lo, hi, err,
                        reinterpret_cast<const unsigned long long *>(minmax), p.tau_l1, p.L, dom, B, is_cand, attr,
+                       label, mom);
+    const int64_t nb = ((int64_t)tiles * ES_BORDER + 255) / 256;
+    hipLaunchKernelGGL(k_ccl_border, dim3((unsigned)nb), dim3(256), 0, s, W, H, tiles_x, (int64_t)tiles, dom, B,
                        label);
-    hipLaunchKernelGGL(k_ccl_border, dim3(grid), dim3(256), 0, s, W, H, dom, B, label);
-    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid), dim3(256), 0, s, P, label, mom);
     hipLaunchKernelGGL(k_moments, dim3(grid), dim3(256), 0, s, W, H, label, mom);
     // kept roots, one record slot per block (advancing the buffer's count), records
     hipLaunchKernelGGL(k_region_keep, dim3(grid), dim3(256), 0, s, P, label, mom, p.m_min, keep, kidx);
