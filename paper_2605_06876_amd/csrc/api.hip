@@ -147,7 +147,8 @@ void frame_buffers(as_frame *f, bool keys_only, V &&visit) {
     arr(&f->nt_sorted, ent); arr(&f->n_ent, 4); arr(&f->n_keys, 4);
     dbuf(f->dsort_hist, sort_hist_bytes(ent));
     dbuf(f->scan_tmp, scan_tmp_bytes(ent));
-    arr(&f->ranges, tile * 2); arr(&f->tile_order, tile); arr(&f->queue, 2); arr(&f->tile_work, tile);
+    // forward dispatch slots: the tiles, or 32 per 8 bins of 32 (at most 2 tile + 64)
+    arr(&f->ranges, tile * 2); arr(&f->tile_order, 2 * tile + 64); arr(&f->queue, 2); arr(&f->tile_work, tile);
     arr(&f->tile_order_bwd, tile); arr(&f->tile_hi, tile); arr(&f->n_items, 1);
     arr(&f->bwd_items, tile * (AS_CK_MAX + 1) * 2);
     arr(&f->tile_err, tile * 2);
@@ -665,7 +666,7 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
         StageTimer t(ctx, AS_STAGE_RANGES, s);
         launch_ranges(f->keys[sel], f->n_keys + 1, f->key_cap, bins, vt, f->ranges, s);
         f->use_order = ctx->longest_first;
-        if (f->use_order) launch_tile_order(f->ranges, (int)tiles, f->tile_order, s);
+        if (f->use_order) launch_tile_order(f->ranges, vt, f->tile_order, s);
     }
     const BlendLaunch bl{ctx->lds_batch, ctx->persistent, ctx->n_cu, ctx->block_cull};
     {

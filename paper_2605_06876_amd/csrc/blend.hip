@@ -69,13 +69,45 @@ struct Fetched {
     BlendRec r;
     short4 b;
     uint32_t id;
+    bool live;   // the record may touch the tile: only then are its box and blend record staged
 };
 
+__device__ __forceinline__ bool box_meets_tile(short4 b, int ox, int oy) {
+    return b.x < ox + AS_TILE_W && b.z >= ox && b.y < oy + AS_TILE_H && b.w >= oy;
+}
+
+// Forward: the pixel box decides whether the 48-byte blend record is loaded
+// (a list of a bin of 32 also holds the records of the bin's other tiles).
 __device__ __forceinline__ void fetch(const uint32_t *__restrict__ vals, const BlendRec *__restrict__ rec,
-                                      const short4 *__restrict__ box, uint32_t idx, Fetched &f) {
+                                      const short4 *__restrict__ box, uint32_t idx, int ox, int oy, Fetched &f) {
     f.id = vals[idx];
-    f.r = rec[f.id];
     f.b = box[f.id];
+    f.live = box_meets_tile(f.b, ox, oy);
+    if (f.live) f.r = rec[f.id];
+}
+
+// Reverse: the forward's block mask for this tile decides when it is stored
+// (zero: no block can hold a contributor), else the pixel box.  `force`
+// loads the record whatever they say: the first slot of every batch is
+// always staged, because the lanes of a row past its own hits evaluate slot
+// 0 and multiply its values by zero, which must stay finite.
+__device__ __forceinline__ void fetch_masked(const uint32_t *__restrict__ vals, const BlendRec *__restrict__ rec,
+                                             const short4 *__restrict__ box, const uint16_t *__restrict__ bm_in,
+                                             uint32_t idx, size_t slot, int ox, int oy, bool force, Fetched &f,
+                                             uint16_t &m) {
+    f.id = vals[idx];
+    if (bm_in) {
+        m = bm_in[slot];
+        f.live = m != 0;
+        if (f.live || force) {
+            f.b = box[f.id];
+            f.r = rec[f.id];
+        }
+    } else {
+        f.b = box[f.id];
+        f.live = box_meets_tile(f.b, ox, oy);
+        if (f.live || force) f.r = rec[f.id];
+    }
 }
 
 __device__ __forceinline__ StagedRec make_staged(const Fetched &f, int ox, int oy) {
@@ -255,6 +287,15 @@ __device__ __forceinline__ bool next_tile(uint32_t *queue, int n_tiles, int iter
     return idx < (uint32_t)n_tiles;
 }
 
+// Forward dispatch slots (k_tile_order): a tile id, or ORDER_NONE for a slot
+// without a tile (slots grouped by bin of 32 past the image edge).
+constexpr uint32_t ORDER_NONE = 0xFFFFFFFFu;
+
+__host__ __device__ inline int order_slots(const ViewTable &vt) {
+    if (vt.bin_shift == 4) return vt.tile_base[vt.n_views];
+    return 32 * ((vt.bin_base[vt.n_views] + 7) / 8);
+}
+
 template <int BATCH, bool PERSIST>
 __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restrict__ ranges,
                                                         const uint32_t *__restrict__ tile_order,
@@ -281,7 +322,9 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
     const float px = (float)lg.lx + 0.5f, py = (float)lg.ly + 0.5f;
     uint32_t idx;
     for (int iter = 0; next_tile<PERSIST>(queue, n_tiles, iter, idx, &s_next); iter++) {
-        const int tile = tile_order ? (int)tile_order[idx] : (int)idx;
+        const uint32_t slot = tile_order ? tile_order[idx] : idx;
+        if (slot == ORDER_NONE) continue;   // a dispatch slot past the image edge (block-uniform)
+        const int tile = (int)slot;
         const int v = view_of_tile(vt, tile);
         const int lt = tile - vt.tile_base[v], tiles_x = vt.tiles_x[v];
         const int W = vt.cam[v].W, H = vt.cam[v].H;
@@ -304,7 +347,7 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
         Fetched nf[R];
 #pragma unroll
         for (int k = 0; k < R; k++)
-            if (start + k * AS_BLOCK + tid < end) fetch(vals, rec, box, start + k * AS_BLOCK + tid, nf[k]);
+            if (start + k * AS_BLOCK + tid < end) fetch(vals, rec, box, start + k * AS_BLOCK + tid, ox, oy, nf[k]);
         for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
             if (__syncthreads_count(done) == AS_BLOCK) break;   // also: the previous batch is consumed
             if (ck && b0 > start && nck < AS_CK_MAX) {
@@ -315,13 +358,16 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
             for (int k = 0; k < R; k++) {
                 const int t = k * AS_BLOCK + tid;
                 if (b0 + t < end) {
-                    const StagedRec sr = make_staged(nf[k], ox, oy);
-                    const uint32_t bm = block_mask(sr, ellipse != 0);
-                    sh.rec[t] = sr;
+                    uint32_t bm = 0u;   // a record whose box misses the tile is not staged
+                    if (nf[k].live) {
+                        const StagedRec sr = make_staged(nf[k], ox, oy);
+                        bm = block_mask(sr, ellipse != 0);
+                        sh.rec[t] = sr;
+                    }
                     sh.bm[t] = (uint16_t)bm;
                     if (bm_out) bm_out[mask_slot(vt, b0 + t, tx, ty)] = (uint16_t)bm;   // the reverse pass reuses it
                 }
-                if (b0 + BATCH + t < end) fetch(vals, rec, box, b0 + BATCH + t, nf[k]);
+                if (b0 + BATCH + t < end) fetch(vals, rec, box, b0 + BATCH + t, ox, oy, nf[k]);
             }
             __syncthreads();
             if (__ballot(!done) == 0) continue;                 // the whole wave has saturated
@@ -618,8 +664,9 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
 #pragma unroll
             for (int k = 0; k < R; k++)
                 if (b0 + k * BWD_BLOCK + tid < s1) {
-                    fetch(vals, rec, box, b0 + k * BWD_BLOCK + tid, nf[k]);
-                    if (bm_in) nbm[k] = bm_in[mask_slot(vt, b0 + k * BWD_BLOCK + tid, tx, ty)];
+                    const uint32_t i = b0 + k * BWD_BLOCK + tid;
+                    fetch_masked(vals, rec, box, bm_in, i, mask_slot(vt, i, tx, ty), ox, oy, k == 0 && tid == 0, nf[k],
+                                 nbm[k]);
                 }
         }
         for (uint32_t b1 = s1; b1 > s0;) {
@@ -629,14 +676,17 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
             for (int k = 0; k < R; k++) {
                 const int t = k * BWD_BLOCK + tid;
                 if (b0 + t < b1) {
-                    const StagedRec sr = make_staged(nf[k], ox, oy);
-                    sh.rec[t] = sr;
-                    sh.bm[t] = bm_in ? nbm[k] : (uint16_t)block_mask(sr, false);
+                    uint16_t bm = 0;   // records that cannot touch the tile are not staged (slot 0 always is)
+                    if (nf[k].live || t == 0) {
+                        const StagedRec sr = make_staged(nf[k], ox, oy);
+                        sh.rec[t] = sr;
+                        if (nf[k].live) bm = bm_in ? nbm[k] : (uint16_t)block_mask(sr, false);
+                    }
+                    sh.bm[t] = bm;
                 }
-                if (n0 + t < n1) {
-                    fetch(vals, rec, box, n0 + t, nf[k]);
-                    if (bm_in) nbm[k] = bm_in[mask_slot(vt, n0 + t, tx, ty)];
-                }
+                if (n0 + t < n1)
+                    fetch_masked(vals, rec, box, bm_in, n0 + t, mask_slot(vt, n0 + t, tx, ty), ox, oy, t == 0, nf[k],
+                                 nbm[k]);
             }
             __syncthreads();
             const int nh = compact_rows<BATCH>(sh.bm, (int)(b1 - b0), sh.hits[w], sel0, row,
@@ -744,17 +794,39 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
 // Tiles ordered by descending list length (33 length classes with power-of-two
 // boundaries), so the longest lists are dispatched first.  The order within a
 // class is irrelevant: every tile's outputs are independent of the others.
-__global__ void __launch_bounds__(1024) k_tile_order(const uint32_t *__restrict__ ranges, int tiles,
+//
+// With bins of 32 the four tiles of a bin read the same list: bins are
+// ordered instead, and the tiles of the bin at rank q take the dispatch slots
+// 32 (q / 8) + q % 8 + 8 i (i = 0..3), which the hardware hands to one XCD
+// (workgroups go to the eight XCDs round robin), so the bin's records are
+// fetched from HBM once into that XCD's L2.  Slots of tiles past the image
+// edge hold ORDER_NONE and their blocks do nothing.
+__global__ void __launch_bounds__(1024) k_tile_order(const uint32_t *__restrict__ ranges, const ViewTable vt,
                                                      uint32_t *__restrict__ order) {
     __shared__ uint32_t s_cnt[33], s_off[33];
     const int tid = threadIdx.x;
-    if (tid < 33) s_cnt[tid] = 0;
-    __syncthreads();
-    for (int t = tid; t < tiles; t += blockDim.x) {
+    const bool bins = vt.bin_shift != 4;
+    const int n = bins ? vt.bin_base[vt.n_views] : vt.tile_base[vt.n_views];
+    // the first tile of unit u (a tile, or the top-left tile of a bin) and
+    // the tile of quadrant i of bin u (-1 past the image edge)
+    auto quad = [&](int u, int i) -> int {
+        if (!bins) return i == 0 ? u : -1;
+        const int v = view_of_bin(vt, u);
+        const int lb = u - vt.bin_base[v], bx = lb % vt.bins_x[v], by = lb / vt.bins_x[v];
+        const int tx_n = vt.tiles_x[v], ty_n = (vt.tile_base[v + 1] - vt.tile_base[v]) / tx_n;
+        const int tx = 2 * bx + (i & 1), ty = 2 * by + (i >> 1);
+        return tx < tx_n && ty < ty_n ? vt.tile_base[v] + ty * tx_n + tx : -1;
+    };
+    auto cls_of = [&](int u) {
+        const int t = quad(u, 0);
         const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-        const int cls = len ? 32 - __clz(len) : 0;   // 0..32, larger = longer
-        atomicAdd(&s_cnt[32 - cls], 1u);
-    }
+        return len ? 32 - __clz(len) : 0;   // 0..32, larger = longer
+    };
+    if (tid < 33) s_cnt[tid] = 0;
+    if (bins)
+        for (int i = tid; i < order_slots(vt); i += blockDim.x) order[i] = ORDER_NONE;
+    __syncthreads();
+    for (int u = tid; u < n; u += blockDim.x) atomicAdd(&s_cnt[32 - cls_of(u)], 1u);
     __syncthreads();
     if (tid == 0) {
         uint32_t run = 0;
@@ -764,10 +836,16 @@ __global__ void __launch_bounds__(1024) k_tile_order(const uint32_t *__restrict_
         }
     }
     __syncthreads();
-    for (int t = tid; t < tiles; t += blockDim.x) {
-        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-        const int cls = len ? 32 - __clz(len) : 0;
-        order[atomicAdd(&s_off[32 - cls], 1u)] = (uint32_t)t;
+    for (int u = tid; u < n; u += blockDim.x) {
+        const uint32_t q = atomicAdd(&s_off[32 - cls_of(u)], 1u);
+        if (!bins) {
+            order[q] = (uint32_t)u;
+            continue;
+        }
+        for (int i = 0; i < 4; i++) {
+            const int t = quad(u, i);
+            if (t >= 0) order[32 * (q >> 3) + (q & 7) + 8 * i] = (uint32_t)t;
+        }
     }
 }
 
@@ -934,8 +1012,8 @@ void launch_debug_alpha(const as_frame *f, int64_t n, const int32_t *pix, const 
                        reinterpret_cast<const short4 *>(f->box), n, pix, ent, out);
 }
 
-void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipStream_t s) {
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, tiles, order);
+void launch_tile_order(const uint32_t *ranges, const ViewTable &vt, uint32_t *order, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, vt, order);
 }
 
 void launch_after_fwd(const as_frame *f, const ViewTable &vt, const ViewImagesC &gt, int order_on, hipStream_t s) {
@@ -961,8 +1039,9 @@ int blend_fwd_batch(const BlendLaunch &bl) { return bl.batch >= 1024 ? 1024 : bl
 
 void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
                       const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s) {
-    const int tiles = vt.tile_base[vt.n_views];
-    if (tiles == 0) return;
+    if (vt.tile_base[vt.n_views] == 0) return;
+    // dispatch slots: the tiles, or with an order over bins of 32 its slots
+    const int tiles = tile_order ? order_slots(vt) : vt.tile_base[vt.n_views];
     const short4 *b4 = reinterpret_cast<const short4 *>(f->box);
     unsigned long long *te = reinterpret_cast<unsigned long long *>(f->tile_err);
     if (bl.persistent) launch_fill_u32(f->queue, 0u, 1, s);

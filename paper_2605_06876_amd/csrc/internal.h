@@ -120,7 +120,8 @@ struct as_frame {
     uint32_t *vals[2];
     int sorted_sel;
     uint32_t *ranges;      // [tiles][2]
-    uint32_t *tile_order;  // [tiles] dispatch order of the forward blend (longest list first)
+    uint32_t *tile_order;  // [2 tiles + 64] dispatch order of the forward blend (longest list first; with bins
+                           // of 32, slots grouped by XCD with empty slots past the image edge)
     uint32_t *tile_work;   // [tiles] contributors summed over the tile's pixels, from the forward blend
     uint32_t *tile_order_bwd;  // [tiles] dispatch order of the reverse blend (most contributors first)
     uint32_t *tile_hi;     // [tiles] one past the tile's last contributor (0: none), from the forward blend
@@ -255,7 +256,7 @@ struct BlendLaunch {
 };
 // The forward blend's LDS depth for a launch (256, 512 or 1024 records).
 int blend_fwd_batch(const BlendLaunch &bl);
-void launch_tile_order(const uint32_t *ranges, int tiles, uint32_t *order, hipStream_t s);
+void launch_tile_order(const uint32_t *ranges, const ViewTable &vt, uint32_t *order, hipStream_t s);
 // After the forward blend: per-view error ranges, the reverse pass's dispatch
 // order (when order_on) and its work items, from the render's checkpoint state.
 void launch_after_fwd(const as_frame *f, const ViewTable &vt, const ViewImagesC &gt, int order_on, hipStream_t s);

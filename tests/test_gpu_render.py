@@ -501,9 +501,13 @@ def test_bins_of_32_match_the_oracle_and_bins_of_16(ctx, c1, c2, case):
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
     has = a["n_contrib"] > 0
     np.testing.assert_array_equal(a["vals"][a["last"][has]], b["vals"][b["last"][has]])
+    rel = {}
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         x, y = getattr(g32, name), getattr(g16, name)
-        assert (torch.linalg.norm(x - y) <= 1e-5 * torch.linalg.norm(y)).item(), name
+        rel[name] = (torch.linalg.norm(x - y) / torch.linalg.norm(y)).item()
+    say("%s: gradient differences (relative norm) %s" % (case, {k: "%.2e" % v for k, v in rel.items()}))
+    # the same bar as for the other launch tunings: the order of float atomics
+    assert all(v <= 1e-4 for v in rel.values()), rel
     fr32.close()
     fr16.close()
 
@@ -592,7 +596,7 @@ def test_autograd_function_matches_oracle_gradients(c1):
     (256, False, False, 8, True, 3, 16), (256, True, True, 8, True, 3, 16), (512, True, False, 6, True, 1, 16),
     (1024, True, True, 5, True, 2, 16), (1024, False, False, 4, True, 3, 16), (512, False, True, 7, True, 3, 16),
     (256, True, False, 7, False, 0, 16), (256, True, False, 7, True, 0, 32), (512, False, True, 6, True, 0, 32),
-    (256, True, False, 7, False, 3, 32)])
+    (256, True, False, 7, False, 3, 32), (256, True, True, 7, True, 0, 32), (1024, True, False, 8, True, 0, 32)])
 def test_tuning_never_changes_results(ctx, c2, batch, lpt, persistent, radix, cull, sp, bt):
     """Every launch tuning gives a bit-identical forward (same per-pixel
     operations in the same order) and gradients equal up to atomic order.
