@@ -822,22 +822,31 @@ __global__ void __launch_bounds__(1024) k_tile_order(const uint32_t *__restrict_
         const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
         return len ? 32 - __clz(len) : 0;   // 0..32, larger = longer
     };
+    constexpr int TO_LDS_UNITS = 16384;   // classes of up to this many units are kept for the scatter pass
+    __shared__ uint8_t s_cls[TO_LDS_UNITS];
+    const bool keep = n <= TO_LDS_UNITS;
     if (tid < 33) s_cnt[tid] = 0;
     if (bins)
         for (int i = tid; i < order_slots(vt); i += blockDim.x) order[i] = ORDER_NONE;
     __syncthreads();
-    for (int u = tid; u < n; u += blockDim.x) atomicAdd(&s_cnt[32 - cls_of(u)], 1u);
+    for (int u = tid; u < n; u += blockDim.x) {
+        const int c = cls_of(u);
+        if (keep) s_cls[u] = (uint8_t)c;
+        atomicAdd(&s_cnt[32 - c], 1u);
+    }
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int c = 0; c < 33; c++) {
-            s_off[c] = run;
-            run += s_cnt[c];
+    if (tid < 64) {   // exclusive prefix over the 33 classes, one wave
+        const uint32_t v = tid < 33 ? s_cnt[tid] : 0u;
+        uint32_t inc = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)inc, o, 64);
+            if (tid >= o) inc += t;
         }
+        if (tid < 33) s_off[tid] = inc - v;
     }
     __syncthreads();
     for (int u = tid; u < n; u += blockDim.x) {
-        const uint32_t q = atomicAdd(&s_off[32 - cls_of(u)], 1u);
+        const uint32_t q = atomicAdd(&s_off[32 - (keep ? (int)s_cls[u] : cls_of(u))], 1u);
         if (!bins) {
             order[q] = (uint32_t)u;
             continue;
@@ -924,11 +933,23 @@ __global__ void __launch_bounds__(1024) k_after_fwd(const ViewTable vt, const Vi
         __syncthreads();
         for (int t = tid; t < tiles; t += 1024) atomicAdd(&s_cnt[128 - work_class(work[t])], 1u);
         __syncthreads();
-        if (tid == 0) {
-            uint32_t run = 0;
-            for (int c = 0; c < 129; c++) {
-                s_off[c] = run;
-                run += s_cnt[c];
+        if (tid < 64) {   // exclusive prefix over the 129 classes: one wave, three per lane
+            uint32_t v[3], sum = 0;
+            for (int k = 0; k < 3; k++) {
+                const int c = 3 * tid + k;
+                v[k] = c < 129 ? s_cnt[c] : 0u;
+                sum += v[k];
+            }
+            uint32_t inc = sum;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)inc, o, 64);
+                if (tid >= o) inc += t;
+            }
+            uint32_t run = inc - sum;
+            for (int k = 0; k < 3; k++) {
+                const int c = 3 * tid + k;
+                if (c < 129) s_off[c] = run;
+                run += v[k];
             }
         }
         __syncthreads();
