@@ -69,7 +69,8 @@ typedef struct {
 
 typedef struct {
     float *means, *log_scales, *quats, *opacity_logits, *sh;
-    int64_t n;           /* row stride of every array (gradients: n; split output: capacity) */
+    int64_t n;           /* row stride of every array (gradients: n; split output: capacity);
+                            0 <= n < 2^30, else the calls return AS_ERR_ARG */
     int32_t sh_degree;
 } as_gaussians_mut;
 

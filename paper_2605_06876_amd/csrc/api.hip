@@ -36,7 +36,8 @@ int tile_bits(int64_t tiles) {
 
 bool check_gauss(const as_gaussians *g, const char *what) {
     if (!g) { as_set_error("%s: null Gaussians", what); return false; }
-    if (g->n < 0 || g->n > 0xFFFFFFFFll) { as_set_error("%s: n = %lld out of range", what, (long long)g->n); return false; }
+    // rows are addressed with 32-bit byte offsets (4 n < 2^32)
+    if (g->n < 0 || g->n >= (1ll << 30)) { as_set_error("%s: n = %lld not in [0, 2^30)", what, (long long)g->n); return false; }
     if (g->sh_degree < 0 || g->sh_degree > 3) { as_set_error("%s: sh_degree %d not in 0..3", what, g->sh_degree); return false; }
     if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh)) {
         as_set_error("%s: null parameter pointer", what);

@@ -405,6 +405,19 @@ __device__ __forceinline__ int view_of_entry(const ViewTable &vt, uint32_t e) {
     for (int k = 1; k < vt.n_views; k++) v += e >= vt.ent_base[k] ? 1 : 0;
     return v;
 }
+// Element of row `row` of a struct-of-arrays tensor with row stride `n`, for
+// the lane whose byte offset in a row is `boff` (Gaussian i: 4 i; sets hold fewer than 2^30 rows).
+// The row base is wave-uniform and the lane part one 32-bit offset shared by
+// every row, so each access is a load or store with a scalar base and the
+// same vector offset, rather than a 64-bit address per row held in vector
+// registers (the 48 SH rows alone would take 96 register pairs).
+__device__ __forceinline__ const float &at_row(const float *a, int64_t row, int64_t n, uint32_t boff) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(a + row * n) + boff);
+}
+__device__ __forceinline__ float &at_row(float *a, int64_t row, int64_t n, uint32_t boff) {
+    return *reinterpret_cast<float *>(reinterpret_cast<char *>(a + row * n) + boff);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const unsigned lane = __lane_id();
     return lane ? (~0ull >> (64 - lane)) : 0ull;

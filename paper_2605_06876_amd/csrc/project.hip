@@ -32,11 +32,12 @@ __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const View
     if (blockIdx.x == 0 && threadIdx.x == 0) *n_ent = (uint32_t)vt.ent_base[vt.n_views];
     if (i >= g.n) return;
     const int64_t n = g.n;
+    const uint32_t bo = (uint32_t)i * 4u;   // the lane's byte offset in every parameter row
     const int64_t e = (int64_t)vt.ent_base[v] + i;
     double mu[3], s[3], q[4];
-    for (int k = 0; k < 3; k++) mu[k] = (double)g.means[k * n + i];
-    for (int k = 0; k < 3; k++) s[k] = exp((double)g.log_scales[k * n + i]);
-    for (int k = 0; k < 4; k++) q[k] = (double)g.quats[k * n + i];
+    for (int k = 0; k < 3; k++) mu[k] = (double)at_row(g.means, k, n, bo);
+    for (int k = 0; k < 3; k++) s[k] = exp((double)at_row(g.log_scales, k, n, bo));
+    for (int k = 0; k < 4; k++) q[k] = (double)at_row(g.quats, k, n, bo);
     const double ologit = (double)g.opac[i];
 
     double Rc[9], tc[3];
@@ -120,7 +121,7 @@ __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const View
         for (int ch = 0; ch < 3; ch++) {
             double acc = 0.0;
 #pragma unroll
-            for (int k = 0; k < nk; k++) acc += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
+            for (int k = 0; k < nk; k++) acc += Y[k] * (double)at_row(g.sh, k * 3 + ch, n, bo);
             acc += 0.5;
             col[ch] = acc < 0.0 ? 0.0 : acc;
         }

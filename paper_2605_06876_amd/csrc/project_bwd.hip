@@ -30,14 +30,15 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
     const int64_t n = g.n, os = out.stride;
+    const uint32_t bo = (uint32_t)i * 4u;   // the lane's byte offset in every row (n < 2^30)
     constexpr int nk = (DEG + 1) * (DEG + 1);
     if (ntiles[i] == 0) {
         if (accum) return;
-        for (int k = 0; k < 3; k++) { out.means[k * os + i] = 0.f; out.log_scales[k * os + i] = 0.f; }
-        for (int k = 0; k < 4; k++) out.quats[k * os + i] = 0.f;
+        for (int k = 0; k < 3; k++) { at_row(out.means, k, os, bo) = 0.f; at_row(out.log_scales, k, os, bo) = 0.f; }
+        for (int k = 0; k < 4; k++) at_row(out.quats, k, os, bo) = 0.f;
         out.opac[i] = 0.f;
 #pragma unroll
-        for (int k = 0; k < nk * 3; k++) out.sh[(int64_t)k * os + i] = 0.f;
+        for (int k = 0; k < nk * 3; k++) at_row(out.sh, k, os, bo) = 0.f;
         return;
     }
     const double gm0 = g2d[i * 9 + 0], gm1 = g2d[i * 9 + 1];
@@ -48,9 +49,9 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
     if (vis_count) vis_count[i] += 1;
 
     double mu[3], s[3], q[4];
-    for (int k = 0; k < 3; k++) mu[k] = (double)g.means[k * n + i];
-    for (int k = 0; k < 3; k++) s[k] = exp((double)g.log_scales[k * n + i]);
-    for (int k = 0; k < 4; k++) q[k] = (double)g.quats[k * n + i];
+    for (int k = 0; k < 3; k++) mu[k] = (double)at_row(g.means, k, n, bo);
+    for (int k = 0; k < 3; k++) s[k] = exp((double)at_row(g.log_scales, k, n, bo));
+    for (int k = 0; k < 4; k++) q[k] = (double)at_row(g.quats, k, n, bo);
     const double o = 1.0 / (1.0 + exp(-(double)g.opac[i]));
     double Rc[9], tc[3];
     for (int k = 0; k < 9; k++) Rc[k] = (double)cam.R[k];
@@ -74,24 +75,31 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
     const double v[3] = {mu[0] - oc[0], mu[1] - oc[1], mu[2] - oc[2]};
     const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     const double d[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
-    double Y[16], dY[16][3];
+    double Y[16];
     sh_eval_basis(d[0], d[1], d[2], DEG, Y);
-    sh_eval_basis_grad(d[0], d[1], d[2], DEG, dY);
-    double gd[3] = {0.0, 0.0, 0.0};
+    // the clamp of each channel first, then per basis function the weight
+    // w_k = sum over channels of sh_k dL/dc, and the direction gradient as
+    // the gradient of sum_k w_k Y_k (no table of the 48 partials is kept)
+    double gc[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ch++) {
         double raw = 0.0;
 #pragma unroll
-        for (int k = 0; k < nk; k++) raw += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
-        const bool clamped = raw + 0.5 < 0.0;
-        const double gc = clamped ? 0.0 : grgb[ch];
+        for (int k = 0; k < nk; k++) raw += Y[k] * (double)at_row(g.sh, k * 3 + ch, n, bo);
+        gc[ch] = raw + 0.5 < 0.0 ? 0.0 : grgb[ch];
+    }
+    double wk[16];
 #pragma unroll
-        for (int k = 0; k < nk; k++) {
-            put(&out.sh[((int64_t)k * 3 + ch) * os + i], (float)(Y[k] * gc), accum != 0);
-            const double shv = (double)g.sh[((int64_t)k * 3 + ch) * n + i];
-            for (int a = 0; a < 3; a++) gd[a] += dY[k][a] * shv * gc;
+    for (int k = 0; k < nk; k++) {
+        wk[k] = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            put(&at_row(out.sh, k * 3 + ch, os, bo), (float)(Y[k] * gc[ch]), accum != 0);
+            wk[k] += (double)at_row(g.sh, k * 3 + ch, n, bo) * gc[ch];
         }
     }
+    double gd[3];
+    sh_weighted_grad(d[0], d[1], d[2], DEG, wk, gd);
     const double ddot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
     for (int a = 0; a < 3; a++) dmu[a] += (gd[a] - d[a] * ddot) / vn;
 
@@ -170,13 +178,13 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
         dt[2] += dJ[5] * (fy * (cy_ / tz) / (tz * tz));
     }
     for (int a = 0; a < 3; a++) dmu[a] += Rc[0 * 3 + a] * dt[0] + Rc[1 * 3 + a] * dt[1] + Rc[2 * 3 + a] * dt[2];
-    for (int a = 0; a < 3; a++) put(&out.means[a * os + i], (float)dmu[a], accum != 0);
+    for (int a = 0; a < 3; a++) put(&at_row(out.means, a, os, bo), (float)dmu[a], accum != 0);
     // scales
     for (int k = 0; k < 3; k++) {
         double acc = 0.0;
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) acc += Rg[a * 3 + k] * dS[a * 3 + b] * Rg[b * 3 + k];
-        put(&out.log_scales[k * os + i], (float)(2.0 * s[k] * s[k] * acc), accum != 0);
+        put(&at_row(out.log_scales, k, os, bo), (float)(2.0 * s[k] * s[k] * acc), accum != 0);
     }
     // rotation -> quaternion
     double dR[9];
@@ -196,7 +204,7 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
                    y * dR[7]);
     const double qn[4] = {w, x, y, z};
     const double qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-    for (int k = 0; k < 4; k++) put(&out.quats[k * os + i], (float)((dq[k] - qn[k] * qd) / qnorm), accum != 0);
+    for (int k = 0; k < 4; k++) put(&at_row(out.quats, k, os, bo), (float)((dq[k] - qn[k] * qd) / qnorm), accum != 0);
 }
 
 
@@ -212,13 +220,14 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTabl
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
     if (i >= g.n) return;
     const int64_t n = g.n, os = out.stride;
+    const uint32_t bo = (uint32_t)i * 4u;   // the lane's byte offset in every row
 #pragma unroll
     for (int k = 0; k < nk * 3; k++) s_dsh[k][tid] = 0.f;
 
     double mu[3], s[3], q[4];
-    for (int k = 0; k < 3; k++) mu[k] = (double)g.means[k * n + i];
-    for (int k = 0; k < 3; k++) s[k] = exp((double)g.log_scales[k * n + i]);
-    for (int k = 0; k < 4; k++) q[k] = (double)g.quats[k * n + i];
+    for (int k = 0; k < 3; k++) mu[k] = (double)at_row(g.means, k, n, bo);
+    for (int k = 0; k < 3; k++) s[k] = exp((double)at_row(g.log_scales, k, n, bo));
+    for (int k = 0; k < 4; k++) q[k] = (double)at_row(g.quats, k, n, bo);
     const double o = 1.0 / (1.0 + exp(-(double)g.opac[i]));
     const double qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     const double w = q[0] / qnorm, x = q[1] / qnorm, y = q[2] / qnorm, z = q[3] / qnorm;
@@ -260,24 +269,28 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTabl
         const double vv[3] = {mu[0] - oc[0], mu[1] - oc[1], mu[2] - oc[2]};
         const double vn = sqrt(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
         const double d[3] = {vv[0] / vn, vv[1] / vn, vv[2] / vn};
-        double Y[16], dY[16][3];
+        double Y[16];
         sh_eval_basis(d[0], d[1], d[2], DEG, Y);
-        sh_eval_basis_grad(d[0], d[1], d[2], DEG, dY);
-        double gd[3] = {0.0, 0.0, 0.0};
+        double gc[3];   // as in the single-view kernel: clamps, weights, then the direction gradient
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) {
             double raw = 0.0;
 #pragma unroll
-            for (int k = 0; k < nk; k++) raw += Y[k] * (double)g.sh[((int64_t)k * 3 + ch) * n + i];
-            const bool clamped = raw + 0.5 < 0.0;
-            const double gc = clamped ? 0.0 : grgb[ch];
+            for (int k = 0; k < nk; k++) raw += Y[k] * (double)at_row(g.sh, k * 3 + ch, n, bo);
+            gc[ch] = raw + 0.5 < 0.0 ? 0.0 : grgb[ch];
+        }
+        double wk[16];
 #pragma unroll
-            for (int k = 0; k < nk; k++) {
-                s_dsh[k * 3 + ch][tid] += (float)(Y[k] * gc);
-                const double shv = (double)g.sh[((int64_t)k * 3 + ch) * n + i];
-                for (int a = 0; a < 3; a++) gd[a] += dY[k][a] * shv * gc;
+        for (int k = 0; k < nk; k++) {
+            wk[k] = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                s_dsh[k * 3 + ch][tid] += (float)(Y[k] * gc[ch]);
+                wk[k] += (double)at_row(g.sh, k * 3 + ch, n, bo) * gc[ch];
             }
         }
+        double gd[3];
+        sh_weighted_grad(d[0], d[1], d[2], DEG, wk, gd);
         const double ddot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
         for (int a = 0; a < 3; a++) dmu[a] += (gd[a] - d[a] * ddot) / vn;
 
@@ -362,23 +375,23 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTabl
     if (vis && g2d_norm) g2d_norm[i] += nrm;
     if (vis && vis_count) vis_count[i] += vis;
     if (!vis) {   // no view saw it: zero gradients
-        for (int k = 0; k < 3; k++) { out.means[k * os + i] = 0.f; out.log_scales[k * os + i] = 0.f; }
-        for (int k = 0; k < 4; k++) out.quats[k * os + i] = 0.f;
+        for (int k = 0; k < 3; k++) { at_row(out.means, k, os, bo) = 0.f; at_row(out.log_scales, k, os, bo) = 0.f; }
+        for (int k = 0; k < 4; k++) at_row(out.quats, k, os, bo) = 0.f;
         out.opac[i] = 0.f;
 #pragma unroll
-        for (int k = 0; k < nk * 3; k++) out.sh[(int64_t)k * os + i] = 0.f;
+        for (int k = 0; k < nk * 3; k++) at_row(out.sh, k, os, bo) = 0.f;
         return;
     }
     out.opac[i] = (float)(gop * o * (1.0 - o));
 #pragma unroll
-    for (int k = 0; k < nk * 3; k++) out.sh[(int64_t)k * os + i] = s_dsh[k][tid];
-    for (int a = 0; a < 3; a++) out.means[a * os + i] = (float)dmu[a];
+    for (int k = 0; k < nk * 3; k++) at_row(out.sh, k, os, bo) = s_dsh[k][tid];
+    for (int a = 0; a < 3; a++) at_row(out.means, a, os, bo) = (float)dmu[a];
     // scales
     for (int k = 0; k < 3; k++) {
         double acc = 0.0;
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) acc += Rg[a * 3 + k] * dS[a * 3 + b] * Rg[b * 3 + k];
-        out.log_scales[k * os + i] = (float)(2.0 * s[k] * s[k] * acc);
+        at_row(out.log_scales, k, os, bo) = (float)(2.0 * s[k] * s[k] * acc);
     }
     // rotation -> quaternion
     double dR[9];
@@ -398,7 +411,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTabl
                    y * dR[7]);
     const double qn[4] = {w, x, y, z};
     const double qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-    for (int k = 0; k < 4; k++) out.quats[k * os + i] = (float)((dq[k] - qn[k] * qd) / qnorm);
+    for (int k = 0; k < 4; k++) at_row(out.quats, k, os, bo) = (float)((dq[k] - qn[k] * qd) / qnorm);
 }
 
 }  // namespace

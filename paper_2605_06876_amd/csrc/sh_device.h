@@ -71,3 +71,39 @@ __device__ __forceinline__ void sh_eval_basis_grad(double x, double y, double z,
     dY[15][0] = -SH_K33 * (3.0 * xx - 3.0 * yy);
     dY[15][1] = SH_K33 * 6.0 * x * y;
 }
+
+// g[a] = sum_k w[k] dY_k / d(x, y, z)[a], the gradient of sum_k w_k Y_k
+// accumulated term by term (the terms of sh_eval_basis_grad), so no table of
+// the 48 partial derivatives is held.
+__device__ __forceinline__ void sh_weighted_grad(double x, double y, double z, int deg, const double w[16],
+                                                 double g[3]) {
+    g[0] = g[1] = g[2] = 0.0;
+    if (deg < 1) return;
+    g[1] += -SH_K1 * w[1];
+    g[2] += SH_K1 * w[2];
+    g[0] += -SH_K1 * w[3];
+    if (deg < 2) return;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    g[0] += SH_K2A * y * w[4];        g[1] += SH_K2A * x * w[4];
+    g[1] += -SH_K2A * z * w[5];       g[2] += -SH_K2A * y * w[5];
+    g[0] += -2.0 * SH_K20 * x * w[6]; g[1] += -2.0 * SH_K20 * y * w[6]; g[2] += 4.0 * SH_K20 * z * w[6];
+    g[0] += -SH_K2A * z * w[7];       g[2] += -SH_K2A * x * w[7];
+    g[0] += 2.0 * SH_K22 * x * w[8];  g[1] += -2.0 * SH_K22 * y * w[8];
+    if (deg < 3) return;
+    g[0] += -SH_K33 * 6.0 * x * y * w[9];
+    g[1] += -SH_K33 * (3.0 * xx - 3.0 * yy) * w[9];
+    g[0] += SH_K32 * y * z * w[10]; g[1] += SH_K32 * x * z * w[10]; g[2] += SH_K32 * x * y * w[10];
+    g[0] += SH_K31 * 2.0 * x * y * w[11];
+    g[1] += -SH_K31 * (4.0 * zz - xx - 3.0 * yy) * w[11];
+    g[2] += -SH_K31 * 8.0 * y * z * w[11];
+    g[0] += -SH_K30 * 6.0 * x * z * w[12];
+    g[1] += -SH_K30 * 6.0 * y * z * w[12];
+    g[2] += SH_K30 * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12];
+    g[0] += -SH_K31 * (4.0 * zz - 3.0 * xx - yy) * w[13];
+    g[1] += SH_K31 * 2.0 * x * y * w[13];
+    g[2] += -SH_K31 * 8.0 * x * z * w[13];
+    g[0] += SH_K32B * 2.0 * x * z * w[14]; g[1] += -SH_K32B * 2.0 * y * z * w[14]; g[2] += SH_K32B * (xx - yy) * w[14];
+    g[0] += -SH_K33 * (3.0 * xx - 3.0 * yy) * w[15];
+    g[1] += SH_K33 * 6.0 * x * y * w[15];
+}
+
