@@ -6,12 +6,16 @@ degree 3, FP32, one 1256x828 view.  One step = forward render with the fused
 L1 error map, the error-region statistics of the view (5% of the Gaussians
 are split candidates), and the backward pass for a fixed synthetic upstream
 gradient.  All inputs are seeded, synthetic and resident in HBM before the
-timed region.  Also reported: the densification step (500,000 Gaussians, 16
+timed region.  The error statistics and the backward pass both read only
+the render's outputs: the timed step runs the statistics on a second stream
+beside the reverse pass (--no-overlap: everything on one stream; both times
+are reported).  Also reported: the densification step (500,000 Gaussians, 16
 views, top-5% candidates, adaptive split) and the CPU oracle on a bounded
 sample of the same workload.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only),
---no-cpu-baseline, --no-densify, --no-training, --no-batched, --no-serve.
+--no-cpu-baseline, --no-densify, --no-training, --no-batched, --no-serve,
+--no-overlap, --tuning (replay a tuning without the autotuner).
 """
 import argparse
 import json
@@ -66,6 +70,9 @@ def _args():
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="Poisson arrivals of the serving leg (seconds)")
     ap.add_argument("--json", default="", help="also write the JSON line to this file")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tuning)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="time the step with every stage on one stream (the value; by default the error statistics "
+                         "run on a second stream beside the reverse pass)")
     ap.add_argument("--tuning", default="",
                     help="skip the autotuner and set this tuning, e.g. lds_batch=256,longest_first=1,bin_tile=32 "
                          "(fields of api.set_tuning; the profiles replay the bench's choice with it)")
@@ -123,23 +130,49 @@ def training_step_bench(args):
         log("bench: autotuning the blend launch (untimed)")
         best, tune_ms = autotune.autotune(ctx, g, cam, frame, gt=gtt, dL=G, reps=3, use_cache=False, cache_path=None)
 
-    def step():
+    # The error statistics and the reverse pass both only read the render's
+    # outputs, so the statistics run on a second stream (default priority)
+    # forked after the render and joined before the step ends.
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    ev_fork, ev_join = torch.cuda.Event(), torch.cuda.Event()
+
+    def step_overlapped():
+        api.render(ctx, g, cam, frame, gt=gtt, image=image)
+        ev_fork.record(main)
+        side.wait_event(ev_fork)
+        with torch.cuda.stream(side):
+            regions.count.zero_()
+            api.accumulate_error_stats(ctx, W, H, dm["err"], dm["err_minmax"], dm["dom"], gtt, 0, is_cand, params,
+                                       regions, attr)
+            ev_join.record(side)
+        api.render_backward(ctx, g, cam, frame, G, grads=grads, g2d_norm=g2d, vis_count=vis)
+        main.wait_event(ev_join)
+
+    def step_sequential():
         regions.count.zero_()
         api.render(ctx, g, cam, frame, gt=gtt, image=image)
         api.accumulate_error_stats(ctx, W, H, dm["err"], dm["err_minmax"], dm["dom"], gtt, 0, is_cand, params,
                                    regions, attr)
         api.render_backward(ctx, g, cam, frame, G, grads=grads, g2d_norm=g2d, vis_count=vis)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("bench: timing %d steps" % args.steps)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    log("bench: timing %d steps (statistics on a second stream, then all on one)" % args.steps)
+    ms_seq = timed(step_sequential)
+    ms_ovl = timed(step_overlapped)
+    ms = ms_seq if args.no_overlap else ms_ovl
+    # stage times come from one-stream steps: each stage's events then time
+    # that stage alone, not its share of a device it splits with another
+    step = step_sequential
     # per-stage times in separate steps: the stage events add a gap at every
     # stage boundary, so they stay out of the timed loop above
     stage_steps = max(1, min(args.steps, 10))
@@ -154,7 +187,8 @@ def training_step_bench(args):
     if K > key_cap:
         raise RuntimeError("bench: %d pairs exceed the frame's capacity of %d" % (K, key_cap))
     n_regions = int(regions.count.item())
-    return dict(ms=ms, stages=stages, K=K, n=n, W=W, H=H, n_regions=n_regions, steps=args.steps,
+    return dict(ms=ms, ms_sequential=ms_seq, ms_overlapped=ms_ovl, stages=stages, K=K, n=n, W=W, H=H,
+                n_regions=n_regions, steps=args.steps,
                 stage_steps=stage_steps, ctx=ctx,
                 tuning=best, tuning_ms={k: round(v, 4) for k, v in tune_ms.items()})
 
@@ -655,6 +689,9 @@ def main():
         "stage_roofline": all_roofs,
         "blend_roofline": blend_roof,
         "fwd_bwd_kernels_ms": round(fb_ms, 4),
+        "step_streams": {"ms_statistics_beside_reverse_pass": round(res["ms_overlapped"], 4),
+                         "ms_one_stream": round(res["ms_sequential"], 4),
+                         "value_from": "one stream" if args.no_overlap else "statistics beside the reverse pass"},
     }
     if not args.no_densify:
         log("bench: densification step (500k Gaussians, 16 views)")
