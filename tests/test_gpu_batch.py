@@ -55,10 +55,14 @@ def rel(x, y):
     return (torch.linalg.norm(x - y) / torch.linalg.norm(y).clamp_min(1e-30)).item()
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batch_equals_single_views(ctx, persistent):
+@pytest.mark.parametrize("persistent,bin_tile,lpt", [(False, 16, True), (True, 16, True), (False, 32, True),
+                                                     (True, 32, True), (False, 32, False)])
+def test_batch_equals_single_views(ctx, persistent, bin_tile, lpt):
+    """Each view of a batch (uneven sizes, ragged last bins) against a render
+    of that view alone with the same tuning, including pairs binned by 32 x 32
+    squares with the dispatch order that groups a bin's tiles by XCD."""
     c = api.Context(0)
-    api.set_tuning(c, persistent=persistent)
+    api.set_tuning(c, persistent=persistent, bin_tile=bin_tile, longest_first=lpt)
     scene = synth.scene_clusters(6000, seed=71, sh_degree=3, log_scale_mu=-3.8, log_scale_sd=0.5)
     g = api.Gaussians.from_scene(scene)
     cams = cams_for(SIZES, seed=3)

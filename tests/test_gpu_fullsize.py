@@ -40,8 +40,9 @@ if not torch.cuda.is_available():
 from paper_2605_06876_amd import api  # noqa: E402
 
 # the benchmark's tuned launch on C2 and C4 (LDS depth 256, longest-first /
-# work-ordered dispatch, one block per tile, 7-bit pair digits)
-TUNING = dict(lds_batch=256, longest_first=True, persistent=False, radix_bits=7)
+# work-ordered dispatch, one block per tile, pairs binned by 32 x 32 squares,
+# 6-bit pair digits)
+TUNING = dict(lds_batch=256, longest_first=True, persistent=False, radix_bits=6, bin_tile=32)
 C4_SIZES = [(640, 480), (800, 600), (960, 640), (1024, 768), (1256, 828), (1280, 720), (1440, 960), (1600, 1064)]
 GRAD_FIELDS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
