@@ -249,20 +249,51 @@ __device__ __forceinline__ int compact_rows(const uint16_t *s_bm, int cnt, HitT<
     return row == 0 ? n[0] : row == 1 ? n[1] : row == 2 ? n[2] : n[3];
 }
 
-template <int CTRL, int ROW_MASK, int BANK_MASK>
-__device__ __forceinline__ float dpp_f(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, true));
-}
-
-// Sum over the 16 lanes of each DPP row, every lane gets the total: butterfly
-// over lane distance 1, 2 (quad permutations), 4 (half-row mirror) and 8 (row
-// mirror), four DPP adds (every lane of the wave must be active).
-__device__ __forceinline__ float row_sum(float v) {
-    v += dpp_f<0xB1, 0xf, 0xf>(v);    // quad_perm [1,0,3,2]
-    v += dpp_f<0x4E, 0xf, 0xf>(v);    // quad_perm [2,3,0,1]
-    v += dpp_f<0x141, 0xf, 0xf>(v);   // row_half_mirror: quads 0<->1, 2<->3 (each quad holds one value)
-    v += dpp_f<0x140, 0xf, 0xf>(v);   // row_mirror: halves 0<->1
-    return v;
+// Row sums of nine values over the 16 lanes of each DPP row, scattered over
+// the row's four banks (bank b = lanes 4b .. 4b + 3 of the row).  On return
+// every lane of bank b holds in g[0] the row total of value {0, 2, 1, 3}[b],
+// in g[4] that of value 4 + {0, 2, 1, 3}[b], and every lane holds in g[8] the
+// total of value 8; the other entries are spent.  The first two levels halve
+// the row (lanes l and l + 8, then l and l + 4): a DPP add whose bank mask
+// leaves half the banks unwritten carries one value there and another value in
+// the other half, so two values cost one add per level.  The two levels inside
+// a bank are plain quad-permutation butterflies on the three remaining
+// registers: 20 DPP adds instead of 36 for nine separate row sums.
+//
+// Written as one block so the DPP hazard is handled here: a DPP source must
+// be written by a VALU instruction at least two instructions earlier, which
+// the opening s_nop covers for the inputs and the instruction order covers
+// inside (every register is read two or more instructions after its last
+// write).  Every lane of the wave must be active.
+__device__ __forceinline__ void row_sums9(float (&g)[9]) {
+    asm volatile(
+        "s_nop 1\n\t"
+        // lanes l <-> l + 8: banks 0,1 keep value 2i, banks 2,3 take value 2i+1
+        "v_add_f32_dpp %0, %0, %0 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %0, %1, %1 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %2, %3, %3 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %4, %4, %4 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %4, %5, %5 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %6, %6, %6 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %6, %7, %7 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %8, %8, %8 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        // lanes l <-> l + 4 (row_ror:n reads lane l - n of the row): banks 0,2
+        // keep the first register, banks 1,3 take the second
+        "v_add_f32_dpp %0, %0, %0 row_ror:12 row_mask:0xf bank_mask:0x5\n\t"
+        "v_add_f32_dpp %0, %2, %2 row_ror:4 row_mask:0xf bank_mask:0xa\n\t"
+        "v_add_f32_dpp %4, %4, %4 row_ror:12 row_mask:0xf bank_mask:0x5\n\t"
+        "v_add_f32_dpp %4, %6, %6 row_ror:4 row_mask:0xf bank_mask:0xa\n\t"
+        "v_add_f32_dpp %8, %8, %8 row_ror:4 row_mask:0xf bank_mask:0xf\n\t"
+        // the four lanes of a bank
+        "v_add_f32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %4, %4, %4 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %8, %8, %8 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %4, %4, %4 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %8, %8, %8 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+        : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]), "+v"(g[3]), "+v"(g[4]), "+v"(g[5]), "+v"(g[6]), "+v"(g[7]),
+          "+v"(g[8]));
 }
 
 template <int BATCH>
@@ -522,10 +553,12 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
 // read, index, reduction and LDS update serves two pixels.  Per step the row
 // sums over its pixels, with DPP, the colour gradients and the moments
 // dp, dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2 of dp = dL/dp (p the
-// Gaussian's exponent, dx, dy the offsets mean - pixel; A and B share dx);
-// lane 15 adds them into the batch slot of that Gaussian in LDS, and after the
-// batch one pass turns the moments into mean, conic and opacity gradients and
-// issues the global atomics: one set per (Gaussian, tile).
+// Gaussian's exponent, dx, dy the offsets mean - pixel; A and B share dx),
+// reduced and scattered over the row's four lane banks so that one lane per
+// bank adds two or three of the nine sums into the batch slot of that
+// Gaussian in LDS; after the batch one pass turns the moments into mean,
+// conic and opacity gradients and issues the global atomics: one set per
+// (Gaussian, tile).
 constexpr int BWD_BLOCK = 128;
 
 template <int BATCH>
@@ -533,7 +566,7 @@ struct BwdShared {
     StagedRec rec[BATCH];
     uint16_t bm[BATCH];
     HitT<BATCH> hits[BWD_BLOCK / 64][4][BATCH + 4];   // +4: the loop reads one index ahead
-    float gacc[9][BATCH];
+    float gacc[9][BATCH + 1];   // +1: the four banks' adds of one step fall in four LDS banks
     uint8_t gflag[BATCH];
 };
 
@@ -740,17 +773,17 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
                               wA * dA0 + wB * dB0,
                               wA * dA1 + wB * dB1,
                               wA * dA2 + wB * dB2};
-#pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    g[k] = row_sum(g[k]);
-                    // keeps each sum's last DPP add in this block: sunk into
-                    // the branch below it would split into a move and an add
-                    asm volatile("" : "+v"(g[k]));
-                }
-                if (c == 15 && ((cb >> (row * 16)) & 0xFFFFull)) {
-#pragma unroll
-                    for (int k = 0; k < 9; k++) atomicAdd(&sh.gacc[k][j], g[k]);
-                    sh.gflag[j] = 1;
+                row_sums9(g);
+                // the first lane of each bank adds its two sums (bank 0 also
+                // the ninth) into the batch slot of the row's Gaussian
+                if ((c & 3) == 0 && ((cb >> (row * 16)) & 0xFFFFull)) {
+                    const int bank = c >> 2, k0 = ((bank & 1) << 1) | (bank >> 1);
+                    atomicAdd(&sh.gacc[k0][j], g[0]);
+                    atomicAdd(&sh.gacc[4 + k0][j], g[4]);
+                    if (bank == 0) {
+                        atomicAdd(&sh.gacc[8][j], g[8]);
+                        sh.gflag[j] = 1;
+                    }
                 }
             }
             __syncthreads();
