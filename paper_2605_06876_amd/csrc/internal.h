@@ -418,6 +418,10 @@ __device__ __forceinline__ float &at_row(float *a, int64_t row, int64_t n, uint3
     return *reinterpret_cast<float *>(reinterpret_cast<char *>(a + row * n) + boff);
 }
 
+// Fourth word of a gfx9 buffer resource for raw 32-bit accesses: data format
+// 32 (bits 15..18 = 4), no swizzle, no index stride.
+#define AS_BUFFER_RSRC_WORD3 0x00020000
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const unsigned lane = __lane_id();
     return lane ? (~0ull >> (64 - lane)) : 0ull;

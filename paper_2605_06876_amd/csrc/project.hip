@@ -20,7 +20,7 @@ __device__ __forceinline__ void quat_to_rot_d(double w, double x, double y, doub
     R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-template <int DEG>
+template <int DEG, bool BUF>
 __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const ViewTable vt, BlendRec *__restrict__ rec,
                                                  uint32_t *__restrict__ depth_key, short4 *__restrict__ box,
                                                  uint32_t *__restrict__ ntiles, uint32_t *__restrict__ sort_keys,
@@ -63,6 +63,25 @@ __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const View
 
     do {
         if (!(tz > AS_NEAR)) break;
+        // The SH coefficients are loaded here, so their latency overlaps the
+        // covariance and box arithmetic below (an entry culled after this
+        // point has read them for nothing; in front of the camera few are).
+        // One buffer resource over the array with the row's byte offset a
+        // scalar, when every row offset fits 32 bits, else 64-bit row addresses.
+        constexpr int nk = (DEG + 1) * (DEG + 1);
+        float shv[nk * 3];
+        if constexpr (BUF) {
+            const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(g.sh), (short)0, -1,
+                                                                                AS_BUFFER_RSRC_WORD3);
+#pragma unroll
+            for (int k = 0; k < nk * 3; k++)
+                shv[k] = __uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(r, (int)bo, (int)((uint32_t)k * (uint32_t)n * 4u), 0));
+        } else {
+#pragma unroll
+            for (int k = 0; k < nk * 3; k++) shv[k] = at_row(g.sh, k, n, bo);
+        }
+        __asm__ __volatile__("" ::: "memory");   // the loads are issued here, not next to their use
         const double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
         const double qnorm = sqrt(qn2);
         double Rg[9];
@@ -95,18 +114,20 @@ __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const View
             }
         const double A = C2[0] + AS_LOWPASS, B = C2[1], Cc = C2[3] + AS_LOWPASS;
         const double det = A * Cc - B * B;
-        if (!(det > 0.0)) break;
+        // The culling tests below are taken together after the colour, so
+        // the code from the SH loads to the end is one block: the compiler
+        // neither sinks the loads to their use nor splits the arithmetic
+        // around them (a culled entry computes NaNs or values it discards).
         const double mx = fx * tx / tz + cx;
         const double my = fy * ty / tz + cy;
         const double o = 1.0 / (1.0 + exp(-ologit));
-        if (!(o >= (1.0 / 255.0))) break;
         const double kk = 2.0 * log(255.0 * o);
         const double hx = sqrt(kk * A), hy = sqrt(kk * Cc);
         double x0 = ceil(mx - hx - 0.5), x1 = floor(mx + hx - 0.5);
         double y0 = ceil(my - hy - 0.5), y1 = floor(my + hy - 0.5);
         x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
         x1 = fmin(x1, (double)(cam.W - 1)); y1 = fmin(y1, (double)(cam.H - 1));
-        if (!(x0 <= x1 && y0 <= y1)) break;
+        const bool keep = det > 0.0 && o >= (1.0 / 255.0) && x0 <= x1 && y0 <= y1;
 
         // colour along the unit view direction
         double oc[3];
@@ -115,21 +136,29 @@ __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const View
         const double vn = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
         double Y[16];
         sh_eval_basis(v0 / vn, v1 / vn, v2 / vn, DEG, Y);
-        constexpr int nk = (DEG + 1) * (DEG + 1);
         double col[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) {
             double acc = 0.0;
 #pragma unroll
-            for (int k = 0; k < nk; k++) acc += Y[k] * (double)at_row(g.sh, k * 3 + ch, n, bo);
+            for (int k = 0; k < nk; k++) acc += Y[k] * (double)shv[k * 3 + ch];
             acc += 0.5;
             col[ch] = acc < 0.0 ? 0.0 : acc;
         }
+        // The colour is masked with a lane mask the compiler cannot see
+        // through (a select would be turned back into a branch around the
+        // colour), so its loads and arithmetic stay in this block; a culled
+        // entry keeps exact zeros.
+        uint32_t km = keep ? 0xFFFFFFFFu : 0u;
+        __asm__ __volatile__("" : "+v"(km));
+        rr.rgb = make_float4(__uint_as_float(__float_as_uint((float)col[0]) & km),
+                             __uint_as_float(__float_as_uint((float)col[1]) & km),
+                             __uint_as_float(__float_as_uint((float)col[2]) & km), 0.f);
+        if (!keep) break;
 
         const float mxh = (float)mx, myh = (float)my;
         rr.m = make_float4(mxh, myh, (float)(mx - (double)mxh), (float)(my - (double)myh));
         rr.c = make_float4((float)(Cc / det), (float)(-B / det), (float)(A / det), (float)o);
-        rr.rgb = make_float4((float)col[0], (float)col[1], (float)col[2], 0.f);
         const int ix0 = (int)x0, iy0 = (int)y0, ix1 = (int)x1, iy1 = (int)y1;
         bx = make_short4((short)ix0, (short)iy0, (short)ix1, (short)iy1);
         const int bs = vt.bin_shift;   // bins touched (the box lies in the image: no negative coordinates)
@@ -152,16 +181,22 @@ void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, in
     }
     const int64_t blocks = (max_n + 255) / 256 * vt.n_views;
     short4 *b4 = reinterpret_cast<short4 *>(box);
+    // buffer addressing of the SH rows when the last row's byte offset fits 32 bits
+    const bool buf = 3 * (int64_t)(deg + 1) * (deg + 1) * max_n * 4 <= (int64_t)UINT32_MAX;
+#define AS_PRJ(D)                                                                                                  \
+    do {                                                                                                           \
+        if (buf) hipLaunchKernelGGL((k_project<D, true>), dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec,    \
+                                    depth_key, b4, ntiles, sort_keys, sort_vals, n_ent);                          \
+        else hipLaunchKernelGGL((k_project<D, false>), dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec,       \
+                                depth_key, b4, ntiles, sort_keys, sort_vals, n_ent);                              \
+    } while (0)
     switch (deg) {
-    case 0: hipLaunchKernelGGL(k_project<0>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles, sort_keys,
-                                  sort_vals, n_ent); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles, sort_keys,
-                                  sort_vals, n_ent); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles, sort_keys,
-                                  sort_vals, n_ent); break;
-    default: hipLaunchKernelGGL(k_project<3>, dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec, depth_key, b4, ntiles, sort_keys,
-                                  sort_vals, n_ent); break;
+    case 0: AS_PRJ(0); break;
+    case 1: AS_PRJ(1); break;
+    case 2: AS_PRJ(2); break;
+    default: AS_PRJ(3); break;
     }
+#undef AS_PRJ
 }
 
 AS_WARM_KERNEL(project)

@@ -18,44 +18,112 @@
 
 namespace {
 
-// One view, or one view of several added to the output (accum): the form
-// that keeps the fewest values live, used when a render has one view.
-__device__ __forceinline__ void put(float *p, float v, bool acc) { *p = acc ? *p + v : v; }
+// SH rows of the single-view kernel.  With BUF (every row offset of the
+// array below 2^32 bytes: 48 rows of fewer than 22M Gaussians) a row is read
+// and written through one buffer resource over the array, the row's byte
+// offset a scalar and the lane's offset the one vector operand shared by all
+// rows; otherwise through at_row.  A 64-bit address per row would be held in
+// vector registers otherwise: the 48 rows' reads and writes took the kernel
+// to 239 VGPRs, two waves per SIMD.
+template <bool BUF>
+__device__ __forceinline__ float sh_ld(const float *a, int row, int64_t n, uint32_t bo) {
+    if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(a), (short)0, -1,
+                                                                            AS_BUFFER_RSRC_WORD3);
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)bo, (int)((uint32_t)row * (uint32_t)n * 4u), 0));
+    } else {
+        return at_row(a, row, n, bo);
+    }
+}
+template <bool BUF>
+__device__ __forceinline__ void sh_st(float *a, int row, int64_t n, uint32_t bo, float v) {
+    if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(a, (short)0, -1, AS_BUFFER_RSRC_WORD3);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)bo, (int)((uint32_t)row * (uint32_t)n * 4u), 0);
+    } else {
+        at_row(a, row, n, bo) = v;
+    }
+}
 
-template <int DEG>
+// One view: the form that keeps the fewest values live, used when a render
+// has one view.
+template <int DEG, bool BUF>
 __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam cam, const uint32_t *__restrict__ ntiles,
                                                      const float *__restrict__ g2d, GradPtrs out,
-                                                     float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count,
-                                                     int accum) {
+                                                     float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
     const int64_t n = g.n, os = out.stride;
     const uint32_t bo = (uint32_t)i * 4u;   // the lane's byte offset in every row (n < 2^30)
     constexpr int nk = (DEG + 1) * (DEG + 1);
     if (ntiles[i] == 0) {
-        if (accum) return;
         for (int k = 0; k < 3; k++) { at_row(out.means, k, os, bo) = 0.f; at_row(out.log_scales, k, os, bo) = 0.f; }
         for (int k = 0; k < 4; k++) at_row(out.quats, k, os, bo) = 0.f;
         out.opac[i] = 0.f;
 #pragma unroll
-        for (int k = 0; k < nk * 3; k++) at_row(out.sh, k, os, bo) = 0.f;
+        for (int k = 0; k < nk * 3; k++) sh_st<BUF>(out.sh, k, os, bo, 0.f);
         return;
     }
-    const double gm0 = g2d[i * 9 + 0], gm1 = g2d[i * 9 + 1];
-    const double gca = g2d[i * 9 + 2], gcb = g2d[i * 9 + 3], gcc = g2d[i * 9 + 4];
-    const double gop = g2d[i * 9 + 5];
-    const double grgb[3] = {g2d[i * 9 + 6], g2d[i * 9 + 7], g2d[i * 9 + 8]};
-    if (g2d_norm) g2d_norm[i] += (float)sqrt(gm0 * gm0 + gm1 * gm1);
-    if (vis_count) vis_count[i] += 1;
-
-    double mu[3], s[3], q[4];
+    // The colour part first, from the mean and the colour gradient alone, and
+    // a compiler barrier before the rest is loaded: the geometry's inputs and
+    // intermediates are not held in registers across the SH loops (together
+    // they needed 236 VGPRs, two waves per SIMD).
+    double mu[3];
     for (int k = 0; k < 3; k++) mu[k] = (double)at_row(g.means, k, n, bo);
-    for (int k = 0; k < 3; k++) s[k] = exp((double)at_row(g.log_scales, k, n, bo));
-    for (int k = 0; k < 4; k++) q[k] = (double)at_row(g.quats, k, n, bo);
-    const double o = 1.0 / (1.0 + exp(-(double)g.opac[i]));
     double Rc[9], tc[3];
     for (int k = 0; k < 9; k++) Rc[k] = (double)cam.R[k];
     for (int k = 0; k < 3; k++) tc[k] = (double)cam.t[k];
+    double dmu[3];
+    {
+        const double grgb[3] = {g2d[i * 9 + 6], g2d[i * 9 + 7], g2d[i * 9 + 8]};
+        // colour and view direction
+        double oc[3];
+        for (int j = 0; j < 3; j++) oc[j] = -(Rc[0 * 3 + j] * tc[0] + Rc[1 * 3 + j] * tc[1] + Rc[2 * 3 + j] * tc[2]);
+        const double v[3] = {mu[0] - oc[0], mu[1] - oc[1], mu[2] - oc[2]};
+        const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const double d[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
+        double Y[16];
+        sh_eval_basis(d[0], d[1], d[2], DEG, Y);
+        // the clamp of each channel first, then per basis function the weight
+        // w_k = sum over channels of sh_k dL/dc, and the direction gradient as
+        // the gradient of sum_k w_k Y_k (no table of the 48 partials is kept)
+        double gc[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            double raw = 0.0;
+#pragma unroll
+            for (int k = 0; k < nk; k++) raw += Y[k] * (double)sh_ld<BUF>(g.sh, k * 3 + ch, n, bo);
+            gc[ch] = raw + 0.5 < 0.0 ? 0.0 : grgb[ch];
+        }
+        __asm__ __volatile__("" ::: "memory");   // the coefficients are read again (from cache) below
+        double wk[16];
+#pragma unroll
+        for (int k = 0; k < nk; k++) {
+            wk[k] = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                sh_st<BUF>(out.sh, k * 3 + ch, os, bo, (float)(Y[k] * gc[ch]));
+                wk[k] += (double)sh_ld<BUF>(g.sh, k * 3 + ch, n, bo) * gc[ch];
+            }
+        }
+        double gd[3];
+        sh_weighted_grad(d[0], d[1], d[2], DEG, wk, gd);
+        const double ddot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+        for (int a = 0; a < 3; a++) dmu[a] = (gd[a] - d[a] * ddot) / vn;
+    }
+    // the colour part's result is an operand of the barrier, so its arithmetic
+    // finishes before the geometry's loads, which the barrier holds after it
+    __asm__ __volatile__("" : "+v"(dmu[0]), "+v"(dmu[1]), "+v"(dmu[2]) : : "memory");
+
+    const double gm0 = g2d[i * 9 + 0], gm1 = g2d[i * 9 + 1];
+    const double gca = g2d[i * 9 + 2], gcb = g2d[i * 9 + 3], gcc = g2d[i * 9 + 4];
+    const double gop = g2d[i * 9 + 5];
+    if (g2d_norm) g2d_norm[i] += (float)sqrt(gm0 * gm0 + gm1 * gm1);
+    if (vis_count) vis_count[i] += 1;
+    double s[3], q[4];
+    for (int k = 0; k < 3; k++) s[k] = exp((double)at_row(g.log_scales, k, n, bo));
+    for (int k = 0; k < 4; k++) q[k] = (double)at_row(g.quats, k, n, bo);
+    const double o = 1.0 / (1.0 + exp(-(double)g.opac[i]));
     const double fx = cam.fx, fy = cam.fy;
     double tv[3];
     for (int r = 0; r < 3; r++) tv[r] = Rc[r * 3 + 0] * mu[0] + Rc[r * 3 + 1] * mu[1] + Rc[r * 3 + 2] * mu[2] + tc[r];
@@ -65,43 +133,8 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
     const double Rg[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
                           2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
                           2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
-
-    double dmu[3] = {0.0, 0.0, 0.0};
     // opacity
-    put(&out.opac[i], (float)(gop * o * (1.0 - o)), accum != 0);
-    // colour and view direction
-    double oc[3];
-    for (int j = 0; j < 3; j++) oc[j] = -(Rc[0 * 3 + j] * tc[0] + Rc[1 * 3 + j] * tc[1] + Rc[2 * 3 + j] * tc[2]);
-    const double v[3] = {mu[0] - oc[0], mu[1] - oc[1], mu[2] - oc[2]};
-    const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    const double d[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
-    double Y[16];
-    sh_eval_basis(d[0], d[1], d[2], DEG, Y);
-    // the clamp of each channel first, then per basis function the weight
-    // w_k = sum over channels of sh_k dL/dc, and the direction gradient as
-    // the gradient of sum_k w_k Y_k (no table of the 48 partials is kept)
-    double gc[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ch++) {
-        double raw = 0.0;
-#pragma unroll
-        for (int k = 0; k < nk; k++) raw += Y[k] * (double)at_row(g.sh, k * 3 + ch, n, bo);
-        gc[ch] = raw + 0.5 < 0.0 ? 0.0 : grgb[ch];
-    }
-    double wk[16];
-#pragma unroll
-    for (int k = 0; k < nk; k++) {
-        wk[k] = 0.0;
-#pragma unroll
-        for (int ch = 0; ch < 3; ch++) {
-            put(&at_row(out.sh, k * 3 + ch, os, bo), (float)(Y[k] * gc[ch]), accum != 0);
-            wk[k] += (double)at_row(g.sh, k * 3 + ch, n, bo) * gc[ch];
-        }
-    }
-    double gd[3];
-    sh_weighted_grad(d[0], d[1], d[2], DEG, wk, gd);
-    const double ddot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
-    for (int a = 0; a < 3; a++) dmu[a] += (gd[a] - d[a] * ddot) / vn;
+    out.opac[i] = (float)(gop * o * (1.0 - o));
 
     // mean2d
     double dt[3] = {0.0, 0.0, 0.0};
@@ -178,13 +211,13 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
         dt[2] += dJ[5] * (fy * (cy_ / tz) / (tz * tz));
     }
     for (int a = 0; a < 3; a++) dmu[a] += Rc[0 * 3 + a] * dt[0] + Rc[1 * 3 + a] * dt[1] + Rc[2 * 3 + a] * dt[2];
-    for (int a = 0; a < 3; a++) put(&at_row(out.means, a, os, bo), (float)dmu[a], accum != 0);
+    for (int a = 0; a < 3; a++) at_row(out.means, a, os, bo) = (float)dmu[a];
     // scales
     for (int k = 0; k < 3; k++) {
         double acc = 0.0;
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) acc += Rg[a * 3 + k] * dS[a * 3 + b] * Rg[b * 3 + k];
-        put(&at_row(out.log_scales, k, os, bo), (float)(2.0 * s[k] * s[k] * acc), accum != 0);
+        at_row(out.log_scales, k, os, bo) = (float)(2.0 * s[k] * s[k] * acc);
     }
     // rotation -> quaternion
     double dR[9];
@@ -204,7 +237,7 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
                    y * dR[7]);
     const double qn[4] = {w, x, y, z};
     const double qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-    for (int k = 0; k < 4; k++) put(&at_row(out.quats, k, os, bo), (float)((dq[k] - qn[k] * qd) / qnorm), accum != 0);
+    for (int k = 0; k < 4; k++) at_row(out.quats, k, os, bo) = (float)((dq[k] - qn[k] * qd) / qnorm);
 }
 
 
@@ -422,12 +455,23 @@ void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t 
     const dim3 grid((unsigned)((g.n + 255) / 256));
     if (vt.n_views == 1) {
         const DevCam &cam = vt.cam[0];
+        // buffer addressing when the last SH row's byte offset fits 32 bits
+        const int64_t rows = 3 * (int64_t)(g.deg + 1) * (g.deg + 1);
+        const bool buf = rows * (g.n > out.stride ? g.n : out.stride) * 4 <= (int64_t)UINT32_MAX;
+#define AS_PBV(D)                                                                                                  \
+    do {                                                                                                           \
+        if (buf) hipLaunchKernelGGL((k_project_bwd_view<D, true>), grid, dim3(256), 0, s, g, cam, ntiles, grad2d,  \
+                                    out, g2d_norm, vis_count);                                                     \
+        else hipLaunchKernelGGL((k_project_bwd_view<D, false>), grid, dim3(256), 0, s, g, cam, ntiles, grad2d, out, \
+                                g2d_norm, vis_count);                                                              \
+    } while (0)
         switch (g.deg) {
-        case 0: hipLaunchKernelGGL(k_project_bwd_view<0>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, out, g2d_norm, vis_count, 0); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd_view<1>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, out, g2d_norm, vis_count, 0); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd_view<2>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, out, g2d_norm, vis_count, 0); break;
-        default: hipLaunchKernelGGL(k_project_bwd_view<3>, grid, dim3(256), 0, s, g, cam, ntiles, grad2d, out, g2d_norm, vis_count, 0); break;
+        case 0: AS_PBV(0); break;
+        case 1: AS_PBV(1); break;
+        case 2: AS_PBV(2); break;
+        default: AS_PBV(3); break;
         }
+#undef AS_PBV
         return;
     }
     switch (g.deg) {
