@@ -581,6 +581,15 @@ as_status as_debug_sort_u32(as_ctx *ctx, uint32_t *keys, uint32_t *vals, int64_t
  * check that the decision arithmetic rounds like the host's.  out[4][n]. */
 as_status as_debug_fp64_ops(as_ctx *ctx, const double *a, const double *b, int64_t n, double *out, void *stream);
 
+/* Test hook: with force_64bit nonzero, the projection and the single-view
+ * projection backward of this context address the SH coefficient rows by
+ * 64-bit row addresses, the form they take when 48 rows of n floats exceed
+ * 32-bit byte offsets (n of 22M and more), instead of one buffer resource with
+ * 32-bit row offsets.  The results do not depend on it; it lets the wide form
+ * be tested at small n.  Zero restores the default.  AS_ERR_ARG on a null
+ * context. */
+as_status as_debug_row_addressing(as_ctx *ctx, int32_t force_64bit);
+
 /* The forward and reverse blends' unclamped alpha o G of Eq. (rendering),
  * evaluated in FP32 from the staged record of the last render exactly as the
  * blend kernels evaluate it, for n (pixel, Gaussian) pairs of view 0 of the

@@ -100,7 +100,7 @@ EXPORTED = ("as_ctx_create", "as_ctx_destroy", "as_last_error", "as_version", "a
             "as_render_backward", "as_render_batch", "as_render_backward_batch", "as_error_map",
             "as_accumulate_error_stats", "as_accumulate_error_stats_noalloc", "as_adaptive_split", "as_set_tuning", "as_get_tuning", "as_timing_enable",
             "as_timing_read", "as_graph_begin", "as_graph_end", "as_graph_launch", "as_graph_destroy",
-            "as_debug_sort_pairs", "as_debug_sort_u32", "as_debug_fp64_ops", "as_debug_blend_alpha", "as_adam_step", "as_l1_loss", "as_densify_select",
+            "as_debug_sort_pairs", "as_debug_sort_u32", "as_debug_fp64_ops", "as_debug_blend_alpha", "as_debug_row_addressing", "as_adam_step", "as_l1_loss", "as_densify_select",
             "as_split_row_map", "as_clone_prune", "as_gather_rows", "as_reset_opacity")
 _NO_STATUS = ("as_last_error", "as_version", "as_ctx_destroy", "as_frame_destroy", "as_graph_destroy")
 
@@ -827,6 +827,12 @@ def debug_fp64_ops(ctx, a, b, stream=None):
     _check(lib().as_debug_fp64_ops(ctx.handle, _ptr(a), _ptr(b), ctypes.c_int64(a.shape[0]), _ptr(out),
                                    _stream(stream)))
     return out
+
+
+def debug_row_addressing(ctx, force_64bit):
+    """as_debug_row_addressing: SH rows by 64-bit addresses (True) or the
+    default buffer addressing (False) in the context's projection kernels."""
+    _check(lib().as_debug_row_addressing(ctx.handle, ctypes.c_int32(1 if force_64bit else 0)))
 
 
 def debug_blend_alpha(frame, pix, gauss, stream=None):

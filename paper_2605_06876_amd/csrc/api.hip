@@ -628,7 +628,7 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
     {
         StageTimer t(ctx, AS_STAGE_PROJECT, s);
         launch_project(sc, vt, max_n, deg, f->rec, f->depth_key, f->box, f->ntiles, f->dkeys[0], f->dvals[0], f->n_ent,
-                       s);
+                       s, ctx->row_addr64 != 0);
     }
     // Depth-first binning: a stable sort of the entries by depth, keys
     // emitted in that order, then a stable sort on the tile ids alone, gives
@@ -735,7 +735,8 @@ as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame 
     }
     {
         StageTimer t(ctx, AS_STAGE_PROJECT_BWD, s);
-        launch_project_bwd(gptrs(g), vt, f->ntiles, f->grad2d, mptrs(grads), g2d_norm, vis_count, s);
+        launch_project_bwd(gptrs(g), vt, f->ntiles, f->grad2d, mptrs(grads), g2d_norm, vis_count, s,
+                           ctx->row_addr64 != 0);
     }
     return launch_status("as_render_backward");
 }
@@ -1185,6 +1186,12 @@ as_status as_debug_fp64_ops(as_ctx *ctx, const double *a, const double *b, int64
     if (!ctx || n < 0 || (n > 0 && (!a || !b || !out))) { as_set_error("as_debug_fp64_ops: bad argument"); return AS_ERR_ARG; }
     launch_fp64_ops(a, b, n, out, (hipStream_t)stream);
     return launch_status("as_debug_fp64_ops");
+}
+
+as_status as_debug_row_addressing(as_ctx *ctx, int32_t force_64bit) {
+    if (!ctx) { as_set_error("as_debug_row_addressing: null context"); return AS_ERR_ARG; }
+    ctx->row_addr64 = force_64bit != 0;
+    return AS_OK;
 }
 
 as_status as_debug_blend_alpha(const as_frame *f, int32_t view, int64_t n, const int32_t *pix,

@@ -175,6 +175,7 @@ struct as_ctx {
     int block_cull = 1;
     int single_pass_sort = 0;   // bit 0 depth sort, bit 1 pair sort
     int bin_tile = 16;          // pixels per side of the binning squares (16 or 32)
+    int row_addr64 = 0;         // test hook: SH rows by 64-bit addresses even where buffer offsets fit
     int n_cu = 0;                 // compute units of the device
     int timing = 0;
     StageRec *recs = nullptr;     // recorded stage event pairs
@@ -200,11 +201,11 @@ struct StageTimer {
 // (depth key, entry id) and the device entry count.
 void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, int deg, BlendRec *rec,
                     uint32_t *depth_key, int16_t *box, uint32_t *ntiles, uint32_t *sort_keys, uint32_t *sort_vals,
-                    uint32_t *n_ent, hipStream_t s);
+                    uint32_t *n_ent, hipStream_t s, bool force_addr64 = false);
 // projection backward (project_bwd.hip): one Gaussian set seen in every view
 // of vt; gradients summed over the views in view order
 void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t *ntiles, const float *grad2d,
-                        GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s);
+                        GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s, bool force_addr64 = false);
 
 // scans (binning.hip): exclusive scans with the total written to *total
 size_t scan_tmp_bytes(int64_t n);

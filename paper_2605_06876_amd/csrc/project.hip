@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_project(const SceneTable sc, const View
 
 void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, int deg, BlendRec *rec,
                     uint32_t *depth_key, int16_t *box, uint32_t *ntiles, uint32_t *sort_keys, uint32_t *sort_vals,
-                    uint32_t *n_ent, hipStream_t s) {
+                    uint32_t *n_ent, hipStream_t s, bool force_addr64) {
     if (max_n == 0 || vt.n_views == 0) {
         launch_fill_u32(n_ent, 0u, 1, s);
         return;
@@ -182,7 +182,7 @@ void launch_project(const SceneTable &sc, const ViewTable &vt, int64_t max_n, in
     const int64_t blocks = (max_n + 255) / 256 * vt.n_views;
     short4 *b4 = reinterpret_cast<short4 *>(box);
     // buffer addressing of the SH rows when the last row's byte offset fits 32 bits
-    const bool buf = 3 * (int64_t)(deg + 1) * (deg + 1) * max_n * 4 <= (int64_t)UINT32_MAX;
+    const bool buf = !force_addr64 && 3 * (int64_t)(deg + 1) * (deg + 1) * max_n * 4 <= (int64_t)UINT32_MAX;
 #define AS_PRJ(D)                                                                                                  \
     do {                                                                                                           \
         if (buf) hipLaunchKernelGGL((k_project<D, true>), dim3((unsigned)blocks), dim3(256), 0, s, sc, vt, rec,    \

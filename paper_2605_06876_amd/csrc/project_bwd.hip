@@ -450,14 +450,14 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTabl
 }  // namespace
 
 void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t *ntiles, const float *grad2d,
-                        GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s) {
+                        GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s, bool force_addr64) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
     if (vt.n_views == 1) {
         const DevCam &cam = vt.cam[0];
         // buffer addressing when the last SH row's byte offset fits 32 bits
         const int64_t rows = 3 * (int64_t)(g.deg + 1) * (g.deg + 1);
-        const bool buf = rows * (g.n > out.stride ? g.n : out.stride) * 4 <= (int64_t)UINT32_MAX;
+        const bool buf = !force_addr64 && rows * (g.n > out.stride ? g.n : out.stride) * 4 <= (int64_t)UINT32_MAX;
 #define AS_PBV(D)                                                                                                  \
     do {                                                                                                           \
         if (buf) hipLaunchKernelGGL((k_project_bwd_view<D, true>), grid, dim3(256), 0, s, g, cam, ntiles, grad2d,  \

@@ -261,6 +261,39 @@ def test_c1_backward_matches_oracle(ctx, c1):
     say("c1 gradients: " + ", ".join("%s %.2e" % (k, v[0]) for k, v in res.items()))
 
 
+def test_64bit_row_addresses_match_the_buffer_path(ctx, c1):
+    # The projection kernels read (and the backward writes) the SH rows through
+    # a buffer resource with 32-bit row offsets below 22M Gaussians and by 64-bit
+    # row addresses above; the hook forces the wide form on C1, whose outputs
+    # must equal the default form's (the forward bit for bit: FP64 with fixed
+    # expression order; the backward to FP32 rounding), which the C1 tests pin
+    # against the oracle.
+    cam, g, fr = c1["cam"], c1["g"], c1["frame"]
+    G = torch.from_numpy(np.random.default_rng(8).normal(size=(3, cam.height, cam.width)).astype(np.float32)).cuda()
+
+    def run():
+        im = api.render(ctx, g, cam, fr)
+        st = fr.host_state(g.n)
+        gr = api.render_backward(ctx, g, cam, fr, G)
+        torch.cuda.synchronize()
+        return im.cpu().numpy(), st, {k: getattr(gr, k).cpu().numpy() for k in
+                                      ("means", "log_scales", "quats", "opacity_logits", "sh")}
+
+    im_a, st_a, gr_a = run()
+    api.debug_row_addressing(ctx, True)
+    try:
+        im_b, st_b, gr_b = run()
+    finally:
+        api.debug_row_addressing(ctx, False)
+    np.testing.assert_array_equal(im_a, im_b)
+    for k in st_a:
+        if isinstance(st_a[k], np.ndarray):
+            np.testing.assert_array_equal(st_a[k], st_b[k], err_msg=k)
+    for k in gr_a:
+        scale = np.abs(gr_a[k]).max() + 1e-30
+        assert np.abs(gr_a[k] - gr_b[k]).max() <= 1e-6 * scale, k
+
+
 def test_backward_accumulates_adc_statistic(ctx, c1):
     cam = c1["cam"]
     G = np.random.default_rng(6).normal(size=(3, cam.height, cam.width)).astype(np.float32)
