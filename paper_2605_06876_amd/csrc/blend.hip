@@ -901,6 +901,29 @@ __device__ __forceinline__ int work_class(uint32_t wk) {
     return 1 + 4 * lg + frac;   // 1..128
 }
 
+// Exclusive prefix over the 129 work classes (s_cnt -> s_off), by the
+// block's first wave, three classes per lane.
+__device__ __forceinline__ void class_prefix129(const uint32_t *s_cnt, uint32_t *s_off, int tid) {
+    if (tid >= 64) return;
+    uint32_t v[3], sum = 0;
+    for (int k = 0; k < 3; k++) {
+        const int c = 3 * tid + k;
+        v[k] = c < 129 ? s_cnt[c] : 0u;
+        sum += v[k];
+    }
+    uint32_t inc = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)inc, o, 64);
+        if (tid >= o) inc += t;
+    }
+    uint32_t run = inc - sum;
+    for (int k = 0; k < 3; k++) {
+        const int c = 3 * tid + k;
+        if (c < 129) s_off[c] = run;
+        run += v[k];
+    }
+}
+
 // After the forward blend, in one block: the error range of each view with a
 // target (minimum and maximum over its tiles' ranges; device-wide atomics on
 // one word per view would serialise at the memory side), the reverse pass's
@@ -928,71 +951,128 @@ __global__ void __launch_bounds__(1024) k_after_fwd(const ViewTable vt, const Vi
     const int tiles = vt.tile_base[vt.n_views];
     const bool in_lds = order_on && tiles <= AF_LDS_TILES;
     // segments of a tile: one per checkpointed batch boundary it crosses, plus one
-    auto nseg_of = [&](uint32_t tile) -> uint32_t {
-        const uint32_t start = ranges[2 * tile], hi = tile_hi[tile];
+    auto nseg_from = [&](uint32_t start, uint32_t hi) -> uint32_t {
         if (hi <= start) return 0u;
         return ck ? min((hi - start + seg_len - 1) / seg_len, (uint32_t)AS_CK_MAX + 1u) : 1u;
     };
-    for (int v = 0; v < vt.n_views; v++) {
-        if (!gts.p[v]) continue;
-        unsigned long long mn = 0x7ff0000000000000ull, mx = 0ull;
-        for (int t = vt.tile_base[v] + tid; t < vt.tile_base[v + 1]; t += 1024) {
-            const unsigned long long a = tile_err[2 * t], b = tile_err[2 * t + 1];
-            mn = a < mn ? a : mn;
-            mx = b > mx ? b : mx;
+    auto nseg_of = [&](uint32_t tile) -> uint32_t { return nseg_from(ranges[2 * tile], tile_hi[tile]); };
+    // Up to AF_K tiles per thread (8192 tiles) every per-tile input (error
+    // range, work, range and end of list) is loaded once, all loads issued
+    // before the first use, and the passes below work from registers; the
+    // loops over memory that larger counts take wait for one load round trip
+    // per iteration in each pass.
+    constexpr int AF_K = 8;
+    constexpr unsigned long long ERR_HI = 0x7ff0000000000000ull;
+    if (tiles <= AF_K * 1024) {
+        unsigned long long ea[AF_K], eb[AF_K];
+        uint32_t wk[AF_K], r0[AF_K], rh[AF_K];
+#pragma unroll
+        for (int k = 0; k < AF_K; k++) {
+            const int t = tid + 1024 * k;
+            const bool in = t < tiles;
+            ea[k] = in ? tile_err[2 * t] : ERR_HI;
+            eb[k] = in ? tile_err[2 * t + 1] : 0ull;
+            wk[k] = in && order_on ? work[t] : 0u;
+            r0[k] = in && in_lds ? ranges[2 * t] : 0u;
+            rh[k] = in && in_lds ? tile_hi[t] : 0u;
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
-            mn = a < mn ? a : mn;
-            mx = b > mx ? b : mx;
-        }
-        if (lane == 0) {
-            s_mn[w] = mn;
-            s_mx[w] = mx;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int k = 1; k < 16; k++) {
-                mn = s_mn[k] < mn ? s_mn[k] : mn;
-                mx = s_mx[k] > mx ? s_mx[k] : mx;
+        for (int v = 0; v < vt.n_views; v++) {
+            if (!gts.p[v]) continue;
+            unsigned long long mn = ERR_HI, mx = 0ull;
+#pragma unroll
+            for (int k = 0; k < AF_K; k++) {
+                const int t = tid + 1024 * k;
+                if (t >= vt.tile_base[v] && t < vt.tile_base[v + 1]) {
+                    mn = ea[k] < mn ? ea[k] : mn;
+                    mx = eb[k] > mx ? eb[k] : mx;
+                }
             }
-            minmax[2 * v] = mn;
-            minmax[2 * v + 1] = mx;
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+                mn = a < mn ? a : mn;
+                mx = b > mx ? b : mx;
+            }
+            if (lane == 0) {
+                s_mn[w] = mn;
+                s_mx[w] = mx;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                for (int k = 1; k < 16; k++) {
+                    mn = s_mn[k] < mn ? s_mn[k] : mn;
+                    mx = s_mx[k] > mx ? s_mx[k] : mx;
+                }
+                minmax[2 * v] = mn;
+                minmax[2 * v + 1] = mx;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    if (order_on) {
-        if (tid < 129) s_cnt[tid] = 0;
-        __syncthreads();
-        for (int t = tid; t < tiles; t += 1024) atomicAdd(&s_cnt[128 - work_class(work[t])], 1u);
-        __syncthreads();
-        if (tid < 64) {   // exclusive prefix over the 129 classes: one wave, three per lane
-            uint32_t v[3], sum = 0;
-            for (int k = 0; k < 3; k++) {
-                const int c = 3 * tid + k;
-                v[k] = c < 129 ? s_cnt[c] : 0u;
-                sum += v[k];
-            }
-            uint32_t inc = sum;
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t t = (uint32_t)__shfl_up((int)inc, o, 64);
-                if (tid >= o) inc += t;
-            }
-            uint32_t run = inc - sum;
-            for (int k = 0; k < 3; k++) {
-                const int c = 3 * tid + k;
-                if (c < 129) s_off[c] = run;
-                run += v[k];
+        if (order_on) {
+            if (tid < 129) s_cnt[tid] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < AF_K; k++)
+                if (tid + 1024 * k < tiles) atomicAdd(&s_cnt[128 - work_class(wk[k])], 1u);
+            __syncthreads();
+            class_prefix129(s_cnt, s_off, tid);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < AF_K; k++) {
+                const int t = tid + 1024 * k;
+                if (t < tiles) {
+                    const uint32_t slot = atomicAdd(&s_off[128 - work_class(wk[k])], 1u);
+                    order[slot] = (uint32_t)t;
+                    if (in_lds) {
+                        s_tile[slot] = (uint16_t)t;
+                        s_nseg[slot] = (uint8_t)nseg_from(r0[k], rh[k]);
+                    }
+                }
             }
         }
-        __syncthreads();
-        for (int t = tid; t < tiles; t += 1024) {
-            const uint32_t ns = in_lds ? nseg_of((uint32_t)t) : 0u;
-            const uint32_t slot = atomicAdd(&s_off[128 - work_class(work[t])], 1u);
-            order[slot] = (uint32_t)t;
-            if (in_lds) {
-                s_tile[slot] = (uint16_t)t;
-                s_nseg[slot] = (uint8_t)ns;
+    } else {
+        for (int v = 0; v < vt.n_views; v++) {
+            if (!gts.p[v]) continue;
+            unsigned long long mn = 0x7ff0000000000000ull, mx = 0ull;
+            for (int t = vt.tile_base[v] + tid; t < vt.tile_base[v + 1]; t += 1024) {
+                const unsigned long long a = tile_err[2 * t], b = tile_err[2 * t + 1];
+                mn = a < mn ? a : mn;
+                mx = b > mx ? b : mx;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+                mn = a < mn ? a : mn;
+                mx = b > mx ? b : mx;
+            }
+            if (lane == 0) {
+                s_mn[w] = mn;
+                s_mx[w] = mx;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                for (int k = 1; k < 16; k++) {
+                    mn = s_mn[k] < mn ? s_mn[k] : mn;
+                    mx = s_mx[k] > mx ? s_mx[k] : mx;
+                }
+                minmax[2 * v] = mn;
+                minmax[2 * v + 1] = mx;
+            }
+            __syncthreads();
+        }
+        if (order_on) {
+            if (tid < 129) s_cnt[tid] = 0;
+            __syncthreads();
+            for (int t = tid; t < tiles; t += 1024) atomicAdd(&s_cnt[128 - work_class(work[t])], 1u);
+            __syncthreads();
+            class_prefix129(s_cnt, s_off, tid);
+            __syncthreads();
+            for (int t = tid; t < tiles; t += 1024) {
+                const uint32_t ns = in_lds ? nseg_of((uint32_t)t) : 0u;
+                const uint32_t slot = atomicAdd(&s_off[128 - work_class(work[t])], 1u);
+                order[slot] = (uint32_t)t;
+                if (in_lds) {
+                    s_tile[slot] = (uint16_t)t;
+                    s_nseg[slot] = (uint8_t)ns;
+                }
             }
         }
     }
