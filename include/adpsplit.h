@@ -159,7 +159,8 @@ typedef struct {
     int32_t *dom;             /* [H][W] dominant Gaussian id, -1 if none */
     double *err;              /* [H][W] L1 error (written when the render gets a target) */
     uint64_t *err_minmax;     /* [2] bit patterns of the error map's min and max */
-    float *grad2d;            /* per-entry 2D gradients of the last backward, entry-major: the nine of
+    float *grad2d;            /* per-entry 2D gradients of the last backward (a later render of the
+                                 frame clears them), entry-major: the nine of
                                  entry e (mean x, y; conic a, b, c; opacity; colour r, g, b) at
                                  grad2d[e * grad2d_stride + k], grad2d_stride = 9 */
     int64_t grad2d_stride;

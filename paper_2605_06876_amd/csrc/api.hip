@@ -12,6 +12,8 @@
 namespace {
 thread_local char g_err[1024] = "";
 thread_local int g_capturing = 0;   // inside as_graph_begin / as_graph_end on this thread
+thread_local int g_capture_id = 0;  // the open capture's number (0: none open)
+thread_local int g_captures = 0;    // captures begun on this thread
 
 bool bad(hipError_t e, const char *what) {
     if (e == hipSuccess) return false;
@@ -675,7 +677,12 @@ as_status as_render_batch(as_ctx *ctx, const as_gaussians *scenes, const as_came
         f->ck_written = f->ckpt != nullptr;
         f->bm_written = f->bmask != nullptr;
         f->ck_seg = blend_fwd_batch(bl);
-        launch_blend_fwd(f, f->vals[sel], f->use_order ? f->tile_order : nullptr, bl, vt, gi, im, s);
+        // frames that can take a reverse pass have the forward clear the 2D
+        // gradient rows it will add into
+        const bool zg = !(f->flags & AS_FRAME_FORWARD_ONLY);
+        f->g2d_zero = launch_blend_fwd(f, f->vals[sel], f->use_order ? f->tile_order : nullptr, bl, vt, gi, im, s,
+                                       zg ? f->grad2d : nullptr, 9 * n) && zg;
+        f->g2d_zero_capture = g_capture_id;
         // the reverse pass's cost per tile follows its contributors, which only
         // the forward pass knows: order the reverse dispatch by them
         launch_after_fwd(f, vt, gi, f->use_order, s);
@@ -729,7 +736,13 @@ as_status as_render_backward_batch(as_ctx *ctx, const as_gaussians *g, as_frame 
     // boundaries and this pass splits long tile lists at them.
     {
         StageTimer t(ctx, AS_STAGE_BLEND_BWD, s);
-        launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9 * ents, s);
+        // The render's forward cleared the rows, unless this is a second
+        // reverse pass of one render, or the render was not recorded in the
+        // graph being captured now (or was, and this pass runs eagerly): then
+        // the pass clears them itself.
+        if (!f->g2d_zero || f->g2d_zero_capture != g_capture_id)
+            launch_fill_u32(reinterpret_cast<uint32_t *>(f->grad2d), 0u, 9 * ents, s);
+        f->g2d_zero = 0;
         launch_blend_bwd(f, f->vals[f->sorted_sel], f->use_order ? f->tile_order_bwd : nullptr, bl, vt, dl,
                          f->grad2d, s);
     }
@@ -1081,6 +1094,7 @@ as_status as_graph_begin(as_ctx *ctx, void *stream) {
     if (bad(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal), "as_graph_begin"))
         return AS_ERR_HIP;
     g_capturing = 1;
+    g_capture_id = ++g_captures;
     return AS_OK;
 }
 
@@ -1089,6 +1103,7 @@ as_status as_graph_end(as_ctx *ctx, void *stream, as_graph **out) {
     *out = nullptr;
     if (!g_capturing) { as_set_error("as_graph_end: no capture open on this thread"); return AS_ERR_STATE; }
     g_capturing = 0;
+    g_capture_id = 0;
     hipGraph_t g = nullptr;
     if (bad(hipStreamEndCapture((hipStream_t)stream, &g), "as_graph_end")) return AS_ERR_HIP;
     as_graph *gr = new (std::nothrow) as_graph();

@@ -341,8 +341,13 @@ __global__ void __launch_bounds__(AS_BLOCK) k_blend_fwd(const uint32_t *__restri
                                                         uint32_t *__restrict__ tile_work,
                                                         uint32_t *__restrict__ tile_hi, float4 *__restrict__ ckpt,
                                                         uint16_t *__restrict__ bm_out, int ellipse,
-                                                        uint32_t *queue, int n_tiles) {
+                                                        uint32_t *queue, int n_tiles, uint4 *__restrict__ zero4,
+                                                        int64_t zero_n4) {
     constexpr int R = BATCH / AS_BLOCK;
+    // Side job: clear the 2D gradient rows the reverse pass adds into, spread
+    // over every block of the grid, so the reverse pass needs no fill launch.
+    for (int64_t i = (int64_t)blockIdx.x * AS_BLOCK + threadIdx.x; i < zero_n4; i += (int64_t)gridDim.x * AS_BLOCK)
+        zero4[i] = make_uint4(0u, 0u, 0u, 0u);
     __shared__ BlendShared<BATCH> sh;
     __shared__ uint32_t s_next;
     __shared__ unsigned long long s_emin[AS_BLOCK / 64], s_emax[AS_BLOCK / 64];
@@ -1171,9 +1176,13 @@ int resident_blocks(Kern k, int n_cu, int block = AS_BLOCK) {
 
 int blend_fwd_batch(const BlendLaunch &bl) { return bl.batch >= 1024 ? 1024 : bl.batch >= 512 ? 512 : 256; }
 
-void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
-                      const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s) {
-    if (vt.tile_base[vt.n_views] == 0) return;
+bool launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
+                      const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s,
+                      float *zero_g2d, int64_t zero_floats) {
+    if (vt.tile_base[vt.n_views] == 0) return false;
+    // whole 16-byte groups covering the floats (the buffer has slack past its count)
+    uint4 *z4 = reinterpret_cast<uint4 *>(zero_g2d);
+    const int64_t zn4 = zero_g2d ? (zero_floats + 3) / 4 : 0;
     // dispatch slots: the tiles, or with an order over bins of 32 its slots
     const int tiles = tile_order ? order_slots(vt) : vt.tile_base[vt.n_views];
     const short4 *b4 = reinterpret_cast<const short4 *>(f->box);
@@ -1190,7 +1199,7 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         hipLaunchKernelGGL((k_blend_fwd<B, PER>), dim3(grid), dim3(AS_BLOCK), 0, s, f->ranges, tile_order, vals,  \
                            f->rec, b4, vt, gt, image, f->t_final, f->last, f->n_contrib, f->dom, f->err, te,      \
                            f->tile_work, f->tile_hi, reinterpret_cast<float4 *>(f->ckpt), f->bmask,               \
-                           bl.ellipse, f->queue, tiles);                                                           \
+                           bl.ellipse, f->queue, tiles, z4, zn4);                                                  \
     } while (0)
     if (bl.persistent) {
         if (bl.batch >= 1024) AS_FWD(1024, true);
@@ -1202,6 +1211,7 @@ void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *t
         else AS_FWD(256, false);
     }
 #undef AS_FWD
+    return true;
 }
 
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,

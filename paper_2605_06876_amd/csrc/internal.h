@@ -109,6 +109,8 @@ struct as_frame {
     uint32_t *ntiles;
     uint32_t *offsets;     // key offsets, in depth order
     float *grad2d;         // [ent_cap][9] entry-major: the 2D gradients of entry e at 9 e .. 9 e + 8
+    int g2d_zero = 0;      // grad2d is all zeros over the last render's entries (its forward cleared it)
+    int g2d_zero_capture = 0;   // the graph capture that render was recorded in (0: run eagerly)
     // depth-first binning: entries sorted by depth, then keys by tile
     uint32_t *dkeys[2];
     uint32_t *dvals[2];
@@ -261,8 +263,12 @@ void launch_tile_order(const uint32_t *ranges, const ViewTable &vt, uint32_t *or
 // After the forward blend: per-view error ranges, the reverse pass's dispatch
 // order (when order_on) and its work items, from the render's checkpoint state.
 void launch_after_fwd(const as_frame *f, const ViewTable &vt, const ViewImagesC &gt, int order_on, hipStream_t s);
-void launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
-                      const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s);
+// Forward blend; with zero_g2d it also clears zero_floats floats there (rounded
+// up to a multiple of four: the buffer needs that slack) and returns whether
+// it ran (no tiles: nothing launched, nothing cleared).
+bool launch_blend_fwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,
+                      const ViewTable &vt, const ViewImagesC &gt, const ViewImages &image, hipStream_t s,
+                      float *zero_g2d = nullptr, int64_t zero_floats = 0);
 void launch_debug_alpha(const as_frame *f, int64_t n, const int32_t *pix, const uint32_t *ent, float *out,
                         hipStream_t s);
 void launch_blend_bwd(const as_frame *f, const uint32_t *vals, const uint32_t *tile_order, const BlendLaunch &bl,

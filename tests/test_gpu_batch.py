@@ -8,6 +8,7 @@ single-view gradients up to float-atomic order (relative 1e-5).  The single
 view path itself is held to the oracle in test_gpu_render.py; one batched
 view is also compared with the oracle here directly.  Graph replays must equal
 eager calls on the inputs present at replay time."""
+import gc
 import sys
 
 import numpy as np
@@ -243,6 +244,44 @@ def test_first_backward_inside_a_capture(ctx):
         for i, f in enumerate(FIELDS):
             assert rel(got_g[i], want_g[i]) <= 1e-5, "replay %d %s" % (rep, f)
     graph.close()
+
+
+def test_reverse_pass_clears_its_gradient_rows(ctx):
+    """The forward of a render clears the per-entry 2D gradient rows that the
+    reverse pass adds into.  A second reverse pass of the same render, and a
+    reverse pass captured in a graph without its render, clear them
+    themselves: repeated passes and replays give the first pass's gradients
+    instead of sums of them."""
+    scene = synth.scene_clusters(3000, seed=21, sh_degree=1, log_scale_mu=-3.8, log_scale_sd=0.5)
+    g = api.Gaussians.from_scene(scene)
+    cams = cams_for([(96, 64), (64, 80)], seed=12)
+    dLs = [torch.from_numpy(np.random.default_rng(40 + k).normal(size=(3, c.height, c.width)).astype(np.float32)).cuda()
+           for k, c in enumerate(cams)]
+    s = torch.cuda.Stream()
+    frame = api.BatchFrame.for_views(ctx, g.n, cams, key_cap=1 << 20, auto_grow=False)
+    grads = api.Gaussians.empty(g.n, 1)
+    with torch.cuda.stream(s):
+        api.render_batch(ctx, g, cams, frame)
+        api.render_backward_batch(ctx, g, frame, dLs, grads=grads)
+        first = [getattr(grads, f).clone() for f in FIELDS]
+        api.render_backward_batch(ctx, g, frame, dLs, grads=grads)   # no render in between
+    s.synchronize()
+    for i, f in enumerate(FIELDS):
+        assert rel(getattr(grads, f), first[i]) <= 1e-5, "second pass %s" % f
+    with torch.cuda.stream(s):
+        api.render_batch(ctx, g, cams, frame)   # eager render; the capture holds the reverse pass alone
+    s.synchronize()
+    graph = api.Graph.capture(ctx, lambda: api.render_backward_batch(ctx, g, frame, dLs, grads=grads), s)
+    for rep in range(3):
+        _ = torch.randn(500, 500, device="cuda") @ torch.randn(500, 500, device="cuda")   # eager work between
+        torch.cuda.synchronize()
+        graph.launch(s)
+        s.synchronize()
+        for i, f in enumerate(FIELDS):
+            assert rel(getattr(grads, f), first[i]) <= 1e-5, "replay %d %s" % (rep, f)
+    graph.close()
+    del graph, grads, first
+    gc.collect()
 
 
 def test_capture_refuses_a_growing_frame(ctx):

@@ -4,6 +4,7 @@ set-up as_render, as_render_backward, as_accumulate_error_stats and
 as_adaptive_split allocate nothing (the device's free memory and torch's
 allocator are unchanged across each call), and the size queries report what
 set-up actually takes."""
+import gc
 import sys
 
 import numpy as np
@@ -90,6 +91,10 @@ def test_the_four_calls_allocate_nothing():
     offset = torch.zeros(nc, dtype=torch.int64, device="cuda")
     n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
     dm = frame.device_maps()
+    # objects of earlier tests held in reference cycles must not be freed
+    # between the measurements below
+    gc.collect()
+    torch.cuda.synchronize()
     before = free_bytes()
     alloc = torch.cuda.memory_allocated()
 
