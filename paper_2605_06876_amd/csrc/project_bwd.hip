@@ -84,30 +84,32 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
         const double d[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
         double Y[16];
         sh_eval_basis(d[0], d[1], d[2], DEG, Y);
-        // the clamp of each channel first, then per basis function the weight
-        // w_k = sum over channels of sh_k dL/dc, and the direction gradient as
-        // the gradient of sum_k w_k Y_k (no table of the 48 partials is kept)
-        double gc[3];
+        // One pass over the coefficients: per channel the raw colour
+        // sum_k Y_k sh_k (its clamp decides whether the channel's gradient
+        // passes) and the gradient of that sum with respect to the direction,
+        // G_ch = sum_k sh_k dY_k (the terms of sh_weighted_grad).  The
+        // direction gradient is then sum_ch gc_ch G_ch, the same sum as
+        // sum_k (sum_ch sh_k gc_ch) dY_k regrouped, so the coefficients are not
+        // read a second time (a second read missed L2 and cost about 100 MB of
+        // HBM traffic per C2 launch).
+        double gc[3], gd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) {
-            double raw = 0.0;
+            double shc[16], raw = 0.0;
 #pragma unroll
-            for (int k = 0; k < nk; k++) raw += Y[k] * (double)sh_ld<BUF>(g.sh, k * 3 + ch, n, bo);
-            gc[ch] = raw + 0.5 < 0.0 ? 0.0 : grgb[ch];
-        }
-        __asm__ __volatile__("" ::: "memory");   // the coefficients are read again (from cache) below
-        double wk[16];
-#pragma unroll
-        for (int k = 0; k < nk; k++) {
-            wk[k] = 0.0;
-#pragma unroll
-            for (int ch = 0; ch < 3; ch++) {
-                sh_st<BUF>(out.sh, k * 3 + ch, os, bo, (float)(Y[k] * gc[ch]));
-                wk[k] += (double)sh_ld<BUF>(g.sh, k * 3 + ch, n, bo) * gc[ch];
+            for (int k = 0; k < nk; k++) {
+                shc[k] = (double)sh_ld<BUF>(g.sh, k * 3 + ch, n, bo);
+                raw += Y[k] * shc[k];
             }
+            double gch[3];
+            sh_weighted_grad(d[0], d[1], d[2], DEG, shc, gch);
+            gc[ch] = raw + 0.5 < 0.0 ? 0.0 : grgb[ch];
+            for (int a = 0; a < 3; a++) gd[a] += gc[ch] * gch[a];
         }
-        double gd[3];
-        sh_weighted_grad(d[0], d[1], d[2], DEG, wk, gd);
+#pragma unroll
+        for (int k = 0; k < nk; k++)
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) sh_st<BUF>(out.sh, k * 3 + ch, os, bo, (float)(Y[k] * gc[ch]));
         const double ddot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
         for (int a = 0; a < 3; a++) dmu[a] = (gd[a] - d[a] * ddot) / vn;
     }
