@@ -243,8 +243,9 @@ __global__ void __launch_bounds__(256) k_project_bwd_view(GaussPtrs g, DevCam ca
 }
 
 
-// All views of a batch in one pass per Gaussian.
-template <int DEG>
+// All views of a batch in one pass per Gaussian (SH rows addressed as in the
+// single-view kernel, BUF).
+template <int DEG, bool BUF>
 __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTable vt, const uint32_t *__restrict__ ntiles,
                                                      const float *__restrict__ g2d, GradPtrs out,
                                                      float *__restrict__ g2d_norm, int32_t *__restrict__ vis_count) {
@@ -306,26 +307,26 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTabl
         const double d[3] = {vv[0] / vn, vv[1] / vn, vv[2] / vn};
         double Y[16];
         sh_eval_basis(d[0], d[1], d[2], DEG, Y);
-        double gc[3];   // as in the single-view kernel: clamps, weights, then the direction gradient
+        // as in the single-view kernel: one pass over the coefficients gives
+        // each channel's raw colour (its clamp) and direction gradient
+        double gc[3], gd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) {
-            double raw = 0.0;
+            double shc[16], raw = 0.0;
 #pragma unroll
-            for (int k = 0; k < nk; k++) raw += Y[k] * (double)at_row(g.sh, k * 3 + ch, n, bo);
-            gc[ch] = raw + 0.5 < 0.0 ? 0.0 : grgb[ch];
-        }
-        double wk[16];
-#pragma unroll
-        for (int k = 0; k < nk; k++) {
-            wk[k] = 0.0;
-#pragma unroll
-            for (int ch = 0; ch < 3; ch++) {
-                s_dsh[k * 3 + ch][tid] += (float)(Y[k] * gc[ch]);
-                wk[k] += (double)at_row(g.sh, k * 3 + ch, n, bo) * gc[ch];
+            for (int k = 0; k < nk; k++) {
+                shc[k] = (double)sh_ld<BUF>(g.sh, k * 3 + ch, n, bo);
+                raw += Y[k] * shc[k];
             }
+            double gch[3];
+            sh_weighted_grad(d[0], d[1], d[2], DEG, shc, gch);
+            gc[ch] = raw + 0.5 < 0.0 ? 0.0 : grgb[ch];
+            for (int a = 0; a < 3; a++) gd[a] += gc[ch] * gch[a];
         }
-        double gd[3];
-        sh_weighted_grad(d[0], d[1], d[2], DEG, wk, gd);
+#pragma unroll
+        for (int k = 0; k < nk; k++)
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) s_dsh[k * 3 + ch][tid] += (float)(Y[k] * gc[ch]);
         const double ddot = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
         for (int a = 0; a < 3; a++) dmu[a] += (gd[a] - d[a] * ddot) / vn;
 
@@ -414,12 +415,12 @@ __global__ void __launch_bounds__(256) k_project_bwd(GaussPtrs g, const ViewTabl
         for (int k = 0; k < 4; k++) at_row(out.quats, k, os, bo) = 0.f;
         out.opac[i] = 0.f;
 #pragma unroll
-        for (int k = 0; k < nk * 3; k++) at_row(out.sh, k, os, bo) = 0.f;
+        for (int k = 0; k < nk * 3; k++) sh_st<BUF>(out.sh, k, os, bo, 0.f);
         return;
     }
     out.opac[i] = (float)(gop * o * (1.0 - o));
 #pragma unroll
-    for (int k = 0; k < nk * 3; k++) at_row(out.sh, k, os, bo) = s_dsh[k][tid];
+    for (int k = 0; k < nk * 3; k++) sh_st<BUF>(out.sh, k, os, bo, s_dsh[k][tid]);
     for (int a = 0; a < 3; a++) at_row(out.means, a, os, bo) = (float)dmu[a];
     // scales
     for (int k = 0; k < 3; k++) {
@@ -455,11 +456,11 @@ void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t 
                         GradPtrs out, float *g2d_norm, int32_t *vis_count, hipStream_t s, bool force_addr64) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
+    // buffer addressing when the last SH row's byte offset fits 32 bits
+    const int64_t rows = 3 * (int64_t)(g.deg + 1) * (g.deg + 1);
+    const bool buf = !force_addr64 && rows * (g.n > out.stride ? g.n : out.stride) * 4 <= (int64_t)UINT32_MAX;
     if (vt.n_views == 1) {
         const DevCam &cam = vt.cam[0];
-        // buffer addressing when the last SH row's byte offset fits 32 bits
-        const int64_t rows = 3 * (int64_t)(g.deg + 1) * (g.deg + 1);
-        const bool buf = !force_addr64 && rows * (g.n > out.stride ? g.n : out.stride) * 4 <= (int64_t)UINT32_MAX;
 #define AS_PBV(D)                                                                                                  \
     do {                                                                                                           \
         if (buf) hipLaunchKernelGGL((k_project_bwd_view<D, true>), grid, dim3(256), 0, s, g, cam, ntiles, grad2d,  \
@@ -476,12 +477,20 @@ void launch_project_bwd(const GaussPtrs &g, const ViewTable &vt, const uint32_t 
 #undef AS_PBV
         return;
     }
+#define AS_PBB(D)                                                                                                  \
+    do {                                                                                                           \
+        if (buf) hipLaunchKernelGGL((k_project_bwd<D, true>), grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out,   \
+                                    g2d_norm, vis_count);                                                          \
+        else hipLaunchKernelGGL((k_project_bwd<D, false>), grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out,      \
+                                g2d_norm, vis_count);                                                              \
+    } while (0)
     switch (g.deg) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out, g2d_norm, vis_count); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out, g2d_norm, vis_count); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out, g2d_norm, vis_count); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(256), 0, s, g, vt, ntiles, grad2d, out, g2d_norm, vis_count); break;
+    case 0: AS_PBB(0); break;
+    case 1: AS_PBB(1); break;
+    case 2: AS_PBB(2); break;
+    default: AS_PBB(3); break;
     }
+#undef AS_PBB
 }
 
 AS_WARM_KERNEL(project_bwd)

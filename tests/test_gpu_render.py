@@ -292,6 +292,25 @@ def test_64bit_row_addresses_match_the_buffer_path(ctx, c1):
     for k in gr_a:
         scale = np.abs(gr_a[k]).max() + 1e-30
         assert np.abs(gr_a[k] - gr_b[k]).max() <= 1e-6 * scale, k
+    # the multi-view backward (two views of one set in one launch)
+    cams = [cam, synth.sphere_cameras(1, 3.0, [(cam.width, cam.height)], seed=31)[0]]
+    bf = api.BatchFrame.for_views(ctx, g.n, cams)
+
+    def run_batch():
+        api.render_batch(ctx, g, cams, bf)
+        gr = api.render_backward_batch(ctx, g, bf, [G, G])
+        torch.cuda.synchronize()
+        return {k: getattr(gr, k).cpu().numpy() for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+
+    ba = run_batch()
+    api.debug_row_addressing(ctx, True)
+    try:
+        bb = run_batch()
+    finally:
+        api.debug_row_addressing(ctx, False)
+    for k in ba:
+        scale = np.abs(ba[k]).max() + 1e-30
+        assert np.abs(ba[k] - bb[k]).max() <= 1e-5 * scale, "batch " + k   # float atomics of the blend in another order
 
 
 def test_backward_accumulates_adc_statistic(ctx, c1):
