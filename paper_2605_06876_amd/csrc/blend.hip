@@ -739,22 +739,21 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
             // the record index two steps ahead.
             int jcur = nmax > 0 && nmax - 1 < nh ? hits[nmax - 1] : 0;
             float4 pq0 = sh.rec[jcur].mc;
-            float2 pq1 = make_float2(sh.rec[jcur].cc.x, sh.rec[jcur].cc.y);
-            uint32_t pm = __float_as_uint(sh.rec[jcur].ex.y);
+            float4 pq1 = sh.rec[jcur].cc;
+            float2 pq2 = make_float2(sh.rec[jcur].ex.x, sh.rec[jcur].ex.y);
             int jn = hits[nmax > 1 ? nmax - 2 : 0];
             for (int h = nmax - 1; h >= 0; h--) {
                 const bool valid = h < nh;
                 const int j = jcur;
-                const float4 q0 = pq0;
-                const float2 q1xy = pq1;
-                const uint32_t m = pm;
+                const float4 q0 = pq0, q1 = pq1;
+                const float2 q2xy = pq2;
+                const uint32_t m = __float_as_uint(q2xy.y);
                 // the next step's record
                 jcur = h > 0 && h - 1 < nh ? jn : 0;
                 jn = hits[h > 1 ? h - 2 : 0];
                 pq0 = sh.rec[jcur].mc;
-                pq1 = make_float2(sh.rec[jcur].cc.x, sh.rec[jcur].cc.y);
-                pm = __float_as_uint(sh.rec[jcur].ex.y);
-                const float4 q1 = make_float4(q1xy.x, q1xy.y, 0.f, 0.f);
+                pq1 = sh.rec[jcur].cc;
+                pq2 = make_float2(sh.rec[jcur].ex.x, sh.rec[jcur].ex.y);
                 const uint32_t gidx = b0 + (uint32_t)j;
                 const float dx = q0.x - px, dyA = q0.y - pyA, dyB = q0.y - pyB;
                 const float arA = __builtin_amdgcn_exp2f(blend_exponent(dx, dyA, q0, q1));
@@ -764,13 +763,11 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
                 const bool cB = valid && gidx < lB && (m & pbB) == pbB && alB >= ALPHA_MIN;
                 const uint64_t cb = __ballot(cA || cB);
                 if (!cb) continue;
-                const float4 q1c = sh.rec[j].cc;   // colour (z, w) and
-                const float4 q2 = sh.rec[j].ex;    // colour (x) for the body
                 // Every lane evaluates the step for both pixels; a
                 // non-contributor's weight and dp are zero, so its sums and
                 // state stay unchanged.
-                const float cdlA = q1c.z * dA0 + q1c.w * dA1 + q2.x * dA2;
-                const float cdlB = q1c.z * dB0 + q1c.w * dB1 + q2.x * dB2;
+                const float cdlA = q1.z * dA0 + q1.w * dA1 + q2xy.x * dA2;
+                const float cdlB = q1.z * dB0 + q1.w * dB1 + q2xy.x * dB2;
                 const float romA = __builtin_amdgcn_rcpf(1.0f - alA), romB = __builtin_amdgcn_rcpf(1.0f - alB);
                 const float TkA = TA * romA, TkB = TB * romB;
                 TA = cA ? TkA : TA;
