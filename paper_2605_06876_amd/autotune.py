@@ -7,7 +7,8 @@ backward differs only in the order of its float atomics.  For a workload the
 tuner times the caller's own step (a render + backward by default) for every
 blend configuration (LDS depth x tile order x persistent grid), then for the
 binning square (16 or 32 pixels: the tile size of the pair lists; the blend
-tiles stay 16 x 16), then for every radix digit width, then for the sorts'
+tiles stay 16 x 16), then for the tile order and persistent grid again with
+that binning, then for every radix digit width, then for the sorts'
 launch structure (one launch per digit or three, for the depth and the pair
 sort), each with the best choices so far, and keeps the fastest
 (the better of two interleaved rounds per candidate, after a warm-up).
@@ -92,6 +93,10 @@ def autotune_step(ctx, run, key, reps=5, cache_path=DEFAULT_CACHE, use_cache=Tru
 
     best = rounds([dict(c, radix_bits=8, single_pass_sort=0, bin_tile=16) for c in BLEND_CANDIDATES])
     best = rounds([dict(best, bin_tile=bt) for bt in BIN_CANDIDATES])
+    # the dispatch again, with the chosen binning: with bins of 32 the
+    # longest-first order also groups a bin's four tiles on one XCD, which the
+    # first round (bins of 16) cannot see
+    best = rounds([dict(best, longest_first=l, persistent=p) for l in (True, False) for p in (False, True)])
     best = rounds([dict(best, radix_bits=rb) for rb in RADIX_CANDIDATES])
     best = rounds([dict(best, single_pass_sort=sp) for sp in SORT_CANDIDATES])
     api.set_tuning(ctx, **best)
