@@ -809,31 +809,38 @@ __global__ void __launch_bounds__(BWD_BLOCK) k_blend_bwd(const uint32_t *__restr
             // gradients.  With p = -(a dx^2 + c dy^2)/2 - b dx dy (unscaled
             // conic a, b, c): dp/dmean = -(a dx + b dy, c dy + b dx),
             // dp/d(a, b, c) = -(dx^2/2, dx dy, dy^2/2) and dalpha/do = alpha/o.
-            // Lanes take (entry, value) pairs, so the nine atomics of an entry
-            // go to the nine consecutive words of its entry-major row from
-            // neighbouring lanes of one instruction.
-            for (int f = tid; f < 9 * (int)(b1 - b0); f += BWD_BLOCK) {
-                const int i = f / 9, k = f - 9 * i;
+            // First a thread per entry turns its sums into the nine
+            // gradients, in place; then lanes take (entry, value) pairs, so
+            // the nine atomics of an entry go to the nine consecutive words of
+            // its entry-major row from neighbouring lanes of one instruction.
+            // A lane clears the word it read and skips an exact zero (adding
+            // it changes nothing), which also passes over the entries that
+            // received nothing.
+            for (int i = tid; i < (int)(b1 - b0); i += BWD_BLOCK) {
                 if (sh.gflag[i]) {
-                    const float4 q0 = sh.rec[i].mc, q1 = sh.rec[i].cc, q2 = sh.rec[i].ex;
-                    const int64_t id = (int64_t)__float_as_uint(q2.z);
-                    const float a = -2.0f * LN2 * q0.z, b = -LN2 * q0.w, cc = -2.0f * LN2 * q1.x;
-                    float gv = sh.gacc[k][i];   // colour gradients (k = 6, 7, 8) as summed
-                    if (k == 0) gv = -(a * sh.gacc[1][i] + b * sh.gacc[2][i]);
-                    else if (k == 1) gv = -(cc * sh.gacc[2][i] + b * sh.gacc[1][i]);
-                    else if (k == 2) gv = -0.5f * sh.gacc[3][i];
-                    else if (k == 3) gv = -sh.gacc[4][i];
-                    else if (k == 4) gv = -0.5f * sh.gacc[5][i];
-                    else if (k == 5) gv = sh.gacc[0][i] * q2.w;
-                    atomicAdd(&grad2d[id * 9 + k], gv);
+                    sh.gflag[i] = 0;
+                    const float4 q0 = sh.rec[i].mc;
+                    const float q1x = sh.rec[i].cc.x, inv_o = sh.rec[i].ex.w;
+                    const float a = -2.0f * LN2 * q0.z, b = -LN2 * q0.w, cc = -2.0f * LN2 * q1x;
+                    float g[6];
+#pragma unroll
+                    for (int k = 0; k < 6; k++) g[k] = sh.gacc[k][i];
+                    sh.gacc[0][i] = -(a * g[1] + b * g[2]);
+                    sh.gacc[1][i] = -(cc * g[2] + b * g[1]);
+                    sh.gacc[2][i] = -0.5f * g[3];
+                    sh.gacc[3][i] = -g[4];
+                    sh.gacc[4][i] = -0.5f * g[5];
+                    sh.gacc[5][i] = g[0] * inv_o;   // colour gradients (k = 6, 7, 8) as summed
                 }
             }
             __syncthreads();
-            for (int i = tid; i < (int)(b1 - b0); i += BWD_BLOCK) {
-                if (sh.gflag[i]) {
-#pragma unroll
-                    for (int k = 0; k < 9; k++) sh.gacc[k][i] = 0.f;
-                    sh.gflag[i] = 0;
+            for (int f = tid; f < 9 * (int)(b1 - b0); f += BWD_BLOCK) {
+                const int i = f / 9, k = f - 9 * i;
+                const float gv = sh.gacc[k][i];
+                if (gv != 0.0f) {
+                    sh.gacc[k][i] = 0.f;
+                    const int64_t id = (int64_t)__float_as_uint(sh.rec[i].ex.z);
+                    atomicAdd(&grad2d[id * 9 + k], gv);
                 }
             }
             __syncthreads();
